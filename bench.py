@@ -1,0 +1,190 @@
+"""Benchmark of the k-hop Fruchterman-Reingold layout on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+Workload (one "step" = the whole hot path over one graph): build the k-hop
+lists of an R-MAT graph with 2^18 vertices and edge factor 4 (a, b, c = 0.57,
+0.19, 0.19; ~1.0M undirected edges after dedup), k = 2, then 500 layout
+iterations in FP32 with Kahan-compensated force sums (FP64 reductions), paper
+cap schedule, d = 20 + sqrt(800), initial placement uniform in [0, 1200)^2.
+Inputs are generated and resident in HBM before timing starts.
+
+Prints one JSON line.  value = (P + 2m) * H * steps / time, where P is the
+total number of ordered k-hop pairs and 2m the adjacency entries (one force
+term each per iteration).  The roofline object reports the force kernel's
+achieved algorithmic bandwidth against the 8 TB/s HBM peak; cpu_baseline
+times the FP64 CPU oracle on a bounded sample of the same job.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def algorithmic_bytes_per_iter(P: int, nnz: int, n_active: int) -> int:
+    """Compulsory HBM bytes of one FP32 force iteration: 4 B per k-hop id,
+    4 B per adjacency id, and per non-isolated vertex its two row offsets
+    (8 + 8 B), one position read (8 B) and one position write (8 B)."""
+    return 4 * P + 4 * nnz + 32 * n_active
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--iterations", type=int, default=500)
+    ap.add_argument("--scale", type=int, default=18)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=8)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        return 2
+
+    import torch
+
+    from paper_1606_02162_amd import gila, inputs
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+
+    scale, H, k = args.scale, args.iterations, 2
+    g = inputs.rmat(scale, 4, 0.57, 0.19, 0.19, seed=3)
+    n_active = int((np.diff(g.row_ptr) > 0).sum())
+    d = inputs.PAPER_IDEAL_LENGTH
+    temps = gila.paper_schedule(n_active, 1.0, d, H)
+    params = gila.LayoutParams(temperature=temps, ideal_length=d, precision=gila.FP32_KAHAN)
+    rp, ci = gila.to_device_csr(g, dev)
+    pos0 = torch.empty((g.n, 2), dtype=torch.float32, device=dev)
+    gila.init_positions(g.n, 0, inputs.PAPER_FRAME, inputs.PAPER_FRAME, gila.FP32, pos0)
+    pos = torch.empty_like(pos0)
+    torch.cuda.synchronize()
+
+    def one_step():
+        pos.copy_(pos0)
+        kh = gila.build_khop(rp, ci, k)
+        st = gila.run(kh, params, pos)
+        return kh, st
+
+    for _ in range(args.warmup):
+        kh, _ = one_step()
+        kh.free()
+    torch.cuda.synchronize()
+
+    t0 = time.perf_counter()
+    P = None
+    for _ in range(args.steps):
+        kh, st = one_step()
+        if P is None:
+            info = kh.info()
+            P = info["total_pairs"]
+        kh.free()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    total_s = t1 - t0
+    assert st.iterations_run == H
+
+    # --- build time and iteration time, HIP events on the launch stream
+    kh = gila.build_khop(rp, ci, k)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    pos.copy_(pos0)
+    gila.run(kh, params, pos)                  # instantiate the graph for this buffer
+    pos.copy_(pos0)
+    ev[0].record(stream)
+    gila.run(kh, params, pos, 0, 0)            # reset + permute only
+    ev[1].record(stream)
+    ev[2].record(stream)
+    gila.run(kh, params, pos)
+    ev[3].record(stream)
+    torch.cuda.synchronize()
+    overhead_ms = ev[0].elapsed_time(ev[1])
+    loop_ms = ev[2].elapsed_time(ev[3])
+    iter_ms = max(loop_ms - overhead_ms, 1e-9) / H
+    tb0 = time.perf_counter()
+    kh2 = gila.build_khop(rp, ci, k)
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - tb0) * 1e3
+    kh2.free()
+
+    inter_per_iter = P + g.nnz
+    value = inter_per_iter * H * args.steps / total_s
+    alg_bytes = algorithmic_bytes_per_iter(P, g.nnz, n_active)
+    achieved = alg_bytes / (iter_ms * 1e-3) / 1e9
+    out = {
+        "metric": "k-hop force interactions/s (P + 2m per iteration) at ~1M edges",
+        "value": value,
+        "unit": "interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": total_s / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (Kahan lane sums, f64 combine and reductions)",
+        "data": "synthetic",
+        "config": {"workload": f"rmat{scale}_ef4_k{k}_fp32kahan_{H}iters", "n": g.n,
+                   "m": g.m, "k": k, "iterations": H, "total_pairs": P,
+                   "n_active": n_active},
+        "ms_per_iter": iter_ms,
+        "build_ms": build_ms,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "fr_step_kernel<FP32_KAHAN>",
+                     "algorithmic_bytes_per_launch": alg_bytes},
+    }
+
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = oracle.num_threads()
+        tc0 = time.perf_counter()
+        optr, oidx = oracle.khop(g.n, g.row_ptr, g.col_idx, k)
+        tc1 = time.perf_counter()
+        x = pos0.double().cpu().numpy()
+        for h in range(args.cpu_iters):
+            x, _, _, _ = oracle.step(g.n, g.row_ptr, g.col_idx, optr, oidx, d, temps[h], x)
+        tc2 = time.perf_counter()
+        cpu_build, cpu_iter = tc1 - tc0, (tc2 - tc1) / args.cpu_iters
+        cpu_job = cpu_build + H * cpu_iter
+        out["cpu_baseline"] = {
+            "value": inter_per_iter * H / cpu_job, "unit": "interactions/s", "cores": threads,
+            "kind": "oracle",
+            "sample": (f"FP64 oracle on this host ({_cpu_model()}, {threads} threads): k-hop "
+                       f"build once ({cpu_build:.2f} s) + {args.cpu_iters} iterations "
+                       f"({cpu_iter * 1e3:.0f} ms each) of the same graph, extrapolated to "
+                       f"the {H}-iteration job"),
+        }
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

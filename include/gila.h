@@ -1,0 +1,240 @@
+/*
+ * gila.h -- C ABI of an MI355X (gfx950) implementation of the layout step of
+ * GiLA, the vertex-centric Fruchterman-Reingold algorithm of Arleo, Didimo,
+ * Liotta and Montecchiani ("A Distributed Force-Directed Algorithm on Giraph:
+ * Design and Experiments").
+ *
+ * Every iteration each vertex v sums
+ *   - attraction from each adjacent u:  (x_u - x_v) * delta / d
+ *     (magnitude delta^2 / d, Section 3.1 with p = 2), and
+ *   - repulsion from each u in its k-neighbourhood N_v(k):
+ *     (x_v - x_u) * d^2 / delta^2  (magnitude d^2 / delta, q = 1),
+ * where N_v(k) is every vertex at graph distance <= k from v, v excluded
+ * (Section 4.5; the TTL flooding there delivers exactly this set).  Then every
+ * vertex moves at once by Delta_v = F_v * min(|F_v|, t_h) / |F_v| (the
+ * temperature cap of Section 3.1; synchronous update of Section 4.5), and the
+ * temperature cools along a schedule (Section 5.1).
+ *
+ * Conventions for every entry point
+ *   - Return value: GILA_OK (0) or a negative status.  No exception or signal
+ *     crosses the ABI.  gila_last_error() gives a thread-local message for the
+ *     last failing call on the calling thread.
+ *   - "_dev" pointers are device (HBM) pointers on the current HIP device;
+ *     "_host" pointers are host memory.  The caller owns every buffer it
+ *     passes; the library never frees them and keeps no reference after the
+ *     call returns (handles copy what they need).
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream).  Device work
+ *     is ordered on it.  Calls that return statistics synchronise the stream
+ *     before returning.
+ *   - Argument and graph validation happens before any compute kernel runs and
+ *     returns GILA_EINVAL.  Device allocation failure returns GILA_ENOMEM; a
+ *     failing HIP call returns GILA_EDEVICE.
+ *   - Positions are interleaved (x, y) pairs: float[2n] for GILA_FP32 and
+ *     GILA_FP32_KAHAN, double[2n] for GILA_FP64.
+ *   - Calls that share a handle, or the stream a handle's work is on, must not
+ *     overlap; distinct handles may be used from distinct threads.
+ */
+#ifndef GILA_H
+#define GILA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ */
+/* Status codes and precisions                                        */
+/* ------------------------------------------------------------------ */
+enum {
+    GILA_OK = 0,
+    GILA_EINVAL = -1,       /* bad argument or malformed graph */
+    GILA_ENOMEM = -2,       /* device or host allocation failed / over budget */
+    GILA_EDEVICE = -3,      /* a HIP call failed (fault, launch error) */
+    GILA_EAGAIN = -4,       /* result not ready yet (gila_poll) */
+    GILA_ECANCELED = -5,    /* job was cancelled */
+    GILA_EUNSUPPORTED = -6  /* valid request this build does not support */
+};
+
+enum {
+    GILA_FP64 = 0,          /* double positions, double per-pair terms and sums */
+    GILA_FP32 = 1,          /* float positions and per-pair terms, plain float lane sums */
+    GILA_FP32_KAHAN = 2     /* float positions and terms, Kahan-compensated lane sums */
+};
+/* In every precision the per-vertex combine of lane sums, the cap, and the
+ * global reductions (energy, max displacement, moved count) are done in
+ * double (64-bit) arithmetic. */
+
+const char* gila_strerror(int status);
+/* Message of the last failing call on this thread ("" if none). */
+const char* gila_last_error(void);
+/* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
+int gila_version(void);
+
+/* ------------------------------------------------------------------ */
+/* Graph                                                                */
+/* ------------------------------------------------------------------ */
+/* Simple undirected graph G = (V, E) (Section 3.1) in symmetric CSR form:
+ * row_ptr[n+1] (row_ptr[0] = 0, row_ptr[n] = nnz = 2|E|), col_idx[nnz] with
+ * each row strictly ascending, no self-loop, and u in row v iff v in row u.
+ * Isolated vertices are allowed: they feel no force and never move. */
+typedef struct gila_csr {
+    int32_t n;
+    int64_t nnz;
+    const int64_t* row_ptr;
+    const int32_t* col_idx;
+} gila_csr;
+
+/* ------------------------------------------------------------------ */
+/* k-neighbourhood lists N_v(k) (Section 4.5)                          */
+/* ------------------------------------------------------------------ */
+typedef struct gila_khop gila_khop;
+
+/* Build N_v(k) for every vertex of g_dev (device CSR) with k >= 1.
+ * The graph is validated (EINVAL on any CSR rule above, or k < 1), copied into
+ * the handle, relabelled internally by decreasing degree, and its k-hop lists
+ * are built by CSR frontier expansion on the device.  The handle owns all of
+ * its device memory (lists, internal graph copy, iteration workspace) until
+ * gila_khop_free.  Synchronises `stream`. */
+int gila_build_khop(const gila_csr* g_dev, int32_t k, void* stream, gila_khop** out);
+
+/* Sizes of a handle: vertex count, k, total ordered pairs P = sum |N_v(k)|,
+ * non-isolated vertex count, and device bytes the handle holds.  Any output
+ * pointer may be NULL. */
+int gila_khop_info(const gila_khop* kh, int32_t* n, int32_t* k, int64_t* total_pairs,
+                   int32_t* n_active, int64_t* device_bytes);
+
+/* Canonical lists in the caller's vertex ids: ptr_host[n+1] and
+ * idx_host[total_pairs], each row ascending and without v.  Either may be
+ * NULL to skip it.  Synchronises the handle's internal work. */
+int gila_khop_export(const gila_khop* kh, int64_t* ptr_host, int32_t* idx_host);
+
+/* Rows of selected vertices only: for i < count, row verts_host[i] goes to
+ * idx_host[ptr_host[i] .. ptr_host[i+1]) in caller ids, ascending.  With
+ * idx_host == NULL only ptr_host[count+1] is written (to size the buffer). */
+int gila_khop_export_rows(const gila_khop* kh, int64_t count, const int32_t* verts_host,
+                          int64_t* ptr_host, int32_t* idx_host);
+
+void gila_khop_free(gila_khop* kh);
+
+/* ------------------------------------------------------------------ */
+/* Layout parameters                                                    */
+/* ------------------------------------------------------------------ */
+typedef struct gila_params {
+    int32_t precision;          /* GILA_FP64 | GILA_FP32 | GILA_FP32_KAHAN */
+    double ideal_length;        /* d > 0 (Section 3.1; the paper uses 20 + sqrt(800)) */
+    int32_t iterations;         /* H >= 0: length of temperature[] */
+    const double* temperature;  /* host [H]: cap t_h >= 0 of iteration h */
+    double stop_fraction;       /* > 0 enables the halting rule of Section 5.1: stop after
+                                   an iteration in which fewer than stop_fraction * n_active
+                                   vertices moved more than stop_displacement; 0 = off */
+    double stop_displacement;   /* threshold of that rule (the paper: 0.01) */
+} gila_params;
+
+typedef struct gila_stats {
+    int32_t iterations_run;     /* iterations executed by the call */
+    int32_t stopped;            /* 1 if the halting rule ended the run */
+    int64_t moved;              /* last iteration: #{v : |Delta_v| > stop_displacement} */
+    double max_disp;            /* last iteration: max_v |Delta_v| */
+    double energy;              /* last iteration: sum_v |F_v|^2 */
+    int64_t coincident;         /* last iteration: ordered pairs at distance 0 (no force) */
+} gila_stats;
+
+/* Seeded uniform placement in [0, width) x [0, height) (Section 5.1 places the
+ * vertices at random in a 1200 x 1200 frame).  Coordinate c in {0: x, 1: y}
+ * of vertex v is u * width (or height) with u = (s >> 11) * 2^-53 and s the
+ * (2v + c)-th output of SplitMix64 seeded with `seed` (Steele, Lea, Flood
+ * 2014).  Written to pos_dev in the precision's layout. */
+int gila_init_positions(int32_t n, uint64_t seed, double width, double height,
+                        int32_t precision, void* pos_dev, void* stream);
+
+/* One iteration h (cap params->temperature[h]) on pos_dev (caller ids,
+ * in/out).  If force_dev / disp_dev are not NULL they receive F_v and Delta_v
+ * (double[2n], caller ids).  `out` (may be NULL) receives the iteration's
+ * statistics; the call synchronises when out != NULL.  The halting rule is
+ * not applied by a single step. */
+int gila_step(const gila_khop* kh, const gila_params* params, int32_t h, void* pos_dev,
+              double* force_dev, double* disp_dev, void* stream, gila_stats* out);
+
+/* Iterations h = start_h .. end_h-1 (end_h <= params->iterations) on a built
+ * handle, positions in/out at pos_dev (caller ids).  The loop runs on the
+ * device (captured as a HIP graph), the halting rule included; a run split at
+ * any h gives the same bits as one run.  Synchronises `stream`. */
+int gila_run(const gila_khop* kh, const gila_params* params, int32_t start_h, int32_t end_h,
+             void* pos_dev, void* stream, gila_stats* out);
+
+/* Whole layout of one graph: gila_build_khop, gila_run over all
+ * params->iterations, free.  Synchronises `stream`. */
+int gila_layout(const gila_csr* g_dev, int32_t k, const gila_params* params, void* pos_dev,
+                void* stream, gila_stats* out);
+
+/* ------------------------------------------------------------------ */
+/* Many graphs in one launch                                            */
+/* ------------------------------------------------------------------ */
+typedef struct gila_batch gila_batch;
+
+/* Build the k-hop lists of `count` independent graphs (graphs_dev[i] is a
+ * device CSR, k[i] >= 1) into one segmented handle.  Each graph's plan
+ * (threads per vertex, resident or streamed) depends only on that graph, so a
+ * graph's result is the same bits alone or in any batch.  Synchronises. */
+int gila_batch_build(const gila_csr* graphs_dev, int32_t count, const int32_t* k,
+                     void* stream, gila_batch** out);
+
+/* All iterations of every graph of the batch in one persistent segmented
+ * launch.  params[i] and pos_dev[i] belong to graph i; all graphs must use
+ * the same precision.  out (may be NULL) is [count].  Synchronises. */
+int gila_batch_run(gila_batch* b, const gila_params* params, void* const* pos_dev,
+                   void* stream, gila_stats* out);
+
+int gila_batch_info(const gila_batch* b, int32_t* count, int64_t* total_pairs,
+                    int64_t* device_bytes);
+void gila_batch_free(gila_batch* b);
+
+/* gila_batch_build + gila_batch_run + gila_batch_free. */
+int gila_layout_batch(const gila_csr* graphs_dev, int32_t count, const int32_t* k,
+                      const gila_params* params, void* const* pos_dev, void* stream,
+                      gila_stats* out);
+
+/* ------------------------------------------------------------------ */
+/* Serving: continuous batching of layout jobs                          */
+/* ------------------------------------------------------------------ */
+typedef struct gila_server gila_server;
+
+/* A server owns a scheduler thread and its own streams on `device`.  Jobs are
+ * admitted while their device footprint fits in hbm_budget_bytes (0 = 90% of
+ * free HBM) and fewer than max_slots jobs are resident.  Resident jobs advance
+ * together, a few iterations per tick; a job arriving while others run is
+ * admitted at the next tick. */
+int gila_server_create(int32_t device, int64_t hbm_budget_bytes, int32_t max_slots,
+                       gila_server** out);
+
+/* Queue a job.  g_host is a host CSR, init_pos_host double[2n]; both and the
+ * temperature array are copied before return.  All jobs of one server use
+ * the precision of the first job submitted.  ticket receives the job id.
+ * EINVAL for a malformed graph or parameters; ENOMEM if the job alone can
+ * never fit the budget. */
+int gila_submit(gila_server* s, const gila_csr* g_host, int32_t k, const gila_params* params,
+                const double* init_pos_host, uint64_t* ticket);
+
+/* GILA_EAGAIN while the job is queued or running; GILA_OK once done, after
+ * writing out_pos_host double[2n] (may be NULL) and out (may be NULL) and
+ * releasing the job; GILA_ECANCELED / other status if it ended otherwise. */
+int gila_poll(gila_server* s, uint64_t ticket, double* out_pos_host, gila_stats* out);
+
+/* Block until the job is done (or failed); then as gila_poll. */
+int gila_wait(gila_server* s, uint64_t ticket, double* out_pos_host, gila_stats* out);
+
+/* Cancel a queued or running job; its memory is released at the next tick. */
+int gila_cancel(gila_server* s, uint64_t ticket);
+
+/* Counters: jobs done, ticks run, peak resident jobs, device bytes in use. */
+int gila_server_info(gila_server* s, int64_t* jobs_done, int64_t* ticks, int32_t* peak_resident,
+                     int64_t* bytes_in_use);
+
+void gila_server_destroy(gila_server* s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GILA_H */

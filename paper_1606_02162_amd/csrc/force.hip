@@ -1,0 +1,391 @@
+// One layout iteration: forces, capped synchronous move, statistics.
+//
+// For every non-isolated vertex v (Section 3.1 force law, p = 2, q = 1, with
+// the repulsion restricted to N_v(k) as in Section 4.5):
+//   F_v = sum_{u in N_v(k)} (x_v - x_u) d^2 / |x_v - x_u|^2
+//       + sum_{u in adj(v)} (x_u - x_v) |x_u - x_v| / d
+//   Delta_v = F_v min(|F_v|, t) / |F_v|   (0 if F_v = 0)
+//   x_v <- x_v + Delta_v                  (written to the other buffer: all
+//                                          vertices move at once)
+// A pair at distance 0 contributes nothing and is counted.
+//
+// Mapping: a group of LPV lanes of a 64-wide wavefront owns one vertex and
+// strides its k-hop row with unit-stride (coalesced) loads of neighbour ids,
+// gathering each neighbour position as one 8-byte (FP32) or 16-byte (FP64)
+// load.  Lane sums are combined in double precision with a fixed butterfly
+// of cross-lane shuffles, so every result is deterministic.  The longest rows
+// ("hubs", which come first in the internal order) get a whole 256-thread
+// workgroup.  Workgroups of ordinary vertices cover contiguous vertex ranges
+// balanced by pair count, planned once per graph.  Per-workgroup statistics
+// are reduced in a fixed order by whichever workgroup finishes last.
+#include <algorithm>
+#include <cmath>
+
+#include "device_util.h"
+#include "gila_internal.h"
+
+namespace gila {
+
+template <int PREC>
+struct Prec;
+
+template <>
+struct Prec<GILA_FP64> {
+    using real = double;
+    using vec2 = double2;
+    static constexpr bool kahan = false;
+};
+template <>
+struct Prec<GILA_FP32> {
+    using real = float;
+    using vec2 = float2;
+    static constexpr bool kahan = false;
+};
+template <>
+struct Prec<GILA_FP32_KAHAN> {
+    using real = float;
+    using vec2 = float2;
+    static constexpr bool kahan = true;
+};
+
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// Lane accumulator: plain or Kahan-compensated sum of 2-vectors.
+template <class R, bool KAHAN>
+struct Acc {
+    R sx = 0, sy = 0, cx = 0, cy = 0;
+    __device__ __forceinline__ void add(R tx, R ty) {
+        if constexpr (KAHAN) {
+            const R yx = tx - cx;
+            const R ux = sx + yx;
+            cx = (ux - sx) - yx;
+            sx = ux;
+            const R yy = ty - cy;
+            const R uy = sy + yy;
+            cy = (uy - sy) - yy;
+            sy = uy;
+        } else {
+            sx += tx;
+            sy += ty;
+        }
+    }
+    __device__ __forceinline__ double x() const {
+        return KAHAN ? (double)sx - (double)cx : (double)sx;
+    }
+    __device__ __forceinline__ double y() const {
+        return KAHAN ? (double)sy - (double)cy : (double)sy;
+    }
+};
+
+// Repulsion term of neighbour position p on v at (xv, yv): (x_v - x_u) d^2 / delta^2.
+template <class P>
+__device__ __forceinline__ void repulse(typename P::real xv, typename P::real yv,
+                                        typename P::vec2 p, typename P::real d2,
+                                        Acc<typename P::real, P::kahan>& acc, int& coinc) {
+    using R = typename P::real;
+    const R dx = xv - p.x;
+    const R dy = yv - p.y;
+    const R dd = dx * dx + dy * dy;
+    R s;
+    if constexpr (sizeof(R) == 4) {
+        s = dd > R(0) ? d2 * fast_rcp(dd) : R(0);
+    } else {
+        s = dd > R(0) ? d2 / dd : R(0);
+    }
+    coinc += (dd == R(0));
+    acc.add(dx * s, dy * s);
+}
+
+// Attraction term: (x_u - x_v) delta / d.
+template <class P>
+__device__ __forceinline__ void attract(typename P::real xv, typename P::real yv,
+                                        typename P::vec2 p, typename P::real inv_d,
+                                        Acc<typename P::real, P::kahan>& acc) {
+    using R = typename P::real;
+    const R dx = p.x - xv;
+    const R dy = p.y - yv;
+    R s;
+    if constexpr (sizeof(R) == 4) {
+        s = sqrt(dx * dx + dy * dy) * inv_d;
+    } else {
+        s = sqrt(dx * dx + dy * dy) / inv_d;  // inv_d carries d itself in double
+    }
+    acc.add(dx * s, dy * s);
+}
+
+// Partial force of one vertex over lanes lane0, lane0+STRIDE, ... of its rows.
+template <class P, int STRIDE>
+__device__ __forceinline__ void vertex_partial(const StepArgs& a, int32_t v, int lane0,
+                                               Acc<typename P::real, P::kahan>& acc, int& coinc,
+                                               typename P::vec2& xv_out) {
+    using R = typename P::real;
+    using V = typename P::vec2;
+    const V* __restrict__ pos = reinterpret_cast<const V*>(a.pos_cur);
+    const V xv = pos[v];
+    xv_out = xv;
+    const R d2 = (R)(a.d * a.d);
+    const R inv_d = sizeof(R) == 4 ? (R)(1.0 / a.d) : (R)a.d;
+    const int64_t kb = a.kptr[v], ke = a.kptr[v + 1];
+    int64_t e = kb + lane0;
+    // four independent gathers in flight per lane
+    for (; e + 3 * STRIDE < ke; e += 4 * STRIDE) {
+        const int32_t u0 = a.kidx[e];
+        const int32_t u1 = a.kidx[e + STRIDE];
+        const int32_t u2 = a.kidx[e + 2 * STRIDE];
+        const int32_t u3 = a.kidx[e + 3 * STRIDE];
+        const V p0 = pos[u0], p1 = pos[u1], p2 = pos[u2], p3 = pos[u3];
+        repulse<P>(xv.x, xv.y, p0, d2, acc, coinc);
+        repulse<P>(xv.x, xv.y, p1, d2, acc, coinc);
+        repulse<P>(xv.x, xv.y, p2, d2, acc, coinc);
+        repulse<P>(xv.x, xv.y, p3, d2, acc, coinc);
+    }
+    for (; e < ke; e += STRIDE) repulse<P>(xv.x, xv.y, pos[a.kidx[e]], d2, acc, coinc);
+    const int64_t rb = a.rp[v], re = a.rp[v + 1];
+    for (int64_t j = rb + lane0; j < re; j += STRIDE)
+        attract<P>(xv.x, xv.y, pos[a.ci[j]], inv_d, acc);
+}
+
+// Cap, move and record one vertex; returns the vertex's statistics.
+template <class P>
+__device__ __forceinline__ void finish_vertex(const StepArgs& a, int32_t v, typename P::vec2 xv,
+                                              double fx, double fy, double& energy, double& maxd,
+                                              int64_t& moved) {
+    using V = typename P::vec2;
+    using R = typename P::real;
+    const double norm = sqrt(fx * fx + fy * fy);
+    double dx = 0.0, dy = 0.0;
+    if (norm > 0.0) {
+        const double len = norm < a.t ? norm : a.t;
+        dx = fx * (len / norm);
+        dy = fy * (len / norm);
+    }
+    V nx;
+    nx.x = (R)((double)xv.x + dx);
+    nx.y = (R)((double)xv.y + dy);
+    reinterpret_cast<V*>(a.pos_next)[v] = nx;
+    if (a.F_out) {
+        const int32_t o = a.perm[v];
+        a.F_out[2 * (int64_t)o] = fx;
+        a.F_out[2 * (int64_t)o + 1] = fy;
+        a.D_out[2 * (int64_t)o] = dx;
+        a.D_out[2 * (int64_t)o + 1] = dy;
+    }
+    const double dl = sqrt(dx * dx + dy * dy);
+    energy += fx * fx + fy * fy;
+    maxd = dl > maxd ? dl : maxd;
+    moved += dl > a.stop_displacement ? 1 : 0;
+}
+
+template <int PREC, int LPV>
+__global__ __launch_bounds__(kBlock) void fr_step_kernel(StepArgs a) {
+    using P = Prec<PREC>;
+    using V = typename P::vec2;
+    __shared__ double s_fx[kWaves], s_fy[kWaves];
+    __shared__ double s_e[kWaves], s_m[kWaves];
+    __shared__ int64_t s_mv[kWaves], s_c[kWaves];
+    __shared__ int s_last;
+
+    if (a.ctl->stopped) return;  // the halting rule fired in an earlier iteration
+
+    const int lane = lane64();
+    const int w = wave_id();
+    double energy = 0.0, maxd = 0.0;
+    int64_t moved = 0;
+    int coinc = 0;
+
+    if ((int32_t)blockIdx.x < a.nhub) {
+        // one hub vertex per workgroup
+        const int32_t v = blockIdx.x;
+        Acc<typename P::real, P::kahan> acc;
+        V xv;
+        vertex_partial<P, kBlock>(a, v, threadIdx.x, acc, coinc, xv);
+        double fx = wave_sum(acc.x()), fy = wave_sum(acc.y());
+        if (lane == 0) {
+            s_fx[w] = fx;
+            s_fy[w] = fy;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            fx = s_fx[0];
+            fy = s_fy[0];
+            for (int i = 1; i < kWaves; ++i) {
+                fx += s_fx[i];
+                fy += s_fy[i];
+            }
+            finish_vertex<P>(a, v, xv, fx, fy, energy, maxd, moved);
+        }
+    } else {
+        constexpr int G = 64 / LPV;                 // vertices in flight per wavefront
+        const int b = blockIdx.x - a.nhub;
+        const int32_t vb = a.block_start[b], ve = a.block_start[b + 1];
+        const int grp = w * G + lane / LPV;         // group index in the workgroup
+        const int gl = lane % LPV;                  // lane within the group
+        for (int32_t base = vb; base < ve; base += kWaves * G) {
+            const int32_t v = base + grp;
+            const bool live = v < ve;
+            Acc<typename P::real, P::kahan> acc;
+            V xv;
+            xv.x = 0;
+            xv.y = 0;
+            if (live) vertex_partial<P, LPV>(a, v, gl, acc, coinc, xv);
+            const double fx = group_sum<LPV>(acc.x());
+            const double fy = group_sum<LPV>(acc.y());
+            if (live && gl == 0) finish_vertex<P>(a, v, xv, fx, fy, energy, maxd, moved);
+        }
+    }
+
+    // workgroup statistics in a fixed order
+    const double we = wave_sum(energy);
+    const double wm = wave_max(maxd);
+    const int64_t wmv = wave_sum(moved);
+    const int64_t wc = wave_sum((int64_t)coinc);
+    if (lane == 0) {
+        s_e[w] = we;
+        s_m[w] = wm;
+        s_mv[w] = wmv;
+        s_c[w] = wc;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        Partial p;
+        p.energy = s_e[0];
+        p.max_disp = s_m[0];
+        p.moved = s_mv[0];
+        p.coincident = s_c[0];
+        for (int i = 1; i < kWaves; ++i) {
+            p.energy += s_e[i];
+            p.max_disp = s_m[i] > p.max_disp ? s_m[i] : p.max_disp;
+            p.moved += s_mv[i];
+            p.coincident += s_c[i];
+        }
+        a.partials[blockIdx.x] = p;
+        __threadfence();
+        const unsigned ticket = atomicAdd(&a.ctl->done_blocks, 1u);
+        s_last = (ticket == (unsigned)gridDim.x - 1u);
+    }
+    __syncthreads();
+    if (!s_last) return;
+
+    // last workgroup: reduce every partial in index order
+    __threadfence();
+    const volatile Partial* vp = a.partials;
+    double e = 0.0, m = 0.0;
+    int64_t mv = 0, c = 0;
+    for (int i = threadIdx.x; i < a.nblocks; i += kBlock) {
+        e += vp[i].energy;
+        const double x = vp[i].max_disp;
+        m = x > m ? x : m;
+        mv += vp[i].moved;
+        c += vp[i].coincident;
+    }
+    e = wave_sum(e);
+    m = wave_max(m);
+    mv = wave_sum(mv);
+    c = wave_sum(c);
+    if (lane == 0) {
+        s_e[w] = e;
+        s_m[w] = m;
+        s_mv[w] = mv;
+        s_c[w] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        e = s_e[0];
+        m = s_m[0];
+        mv = s_mv[0];
+        c = s_c[0];
+        for (int i = 1; i < kWaves; ++i) {
+            e += s_e[i];
+            m = s_m[i] > m ? s_m[i] : m;
+            mv += s_mv[i];
+            c += s_c[i];
+        }
+        Ctl* ctl = a.ctl;
+        ctl->energy = e;
+        ctl->max_disp = m;
+        ctl->moved = mv;
+        ctl->coincident = c;
+        ctl->iters_run += 1;
+        if (a.check_stop && (double)mv < a.stop_fraction * (double)a.n_active) ctl->stopped = 1;
+        if (a.hist_slot >= 0) {
+            double* hrow = a.hist + 4 * (int64_t)a.hist_slot;
+            hrow[0] = e;
+            hrow[1] = m;
+            hrow[2] = (double)mv;
+            hrow[3] = (double)c;
+        }
+        ctl->done_blocks = 0u;
+        __threadfence();
+    }
+}
+
+// ------------------------------------------------------------------ launch
+template <int PREC>
+static void launch_prec(int lpv, const StepArgs& a, hipStream_t s) {
+    const dim3 grid(a.nblocks), block(kBlock);
+    switch (lpv) {
+        case 4: hipLaunchKernelGGL((fr_step_kernel<PREC, 4>), grid, block, 0, s, a); break;
+        case 8: hipLaunchKernelGGL((fr_step_kernel<PREC, 8>), grid, block, 0, s, a); break;
+        case 16: hipLaunchKernelGGL((fr_step_kernel<PREC, 16>), grid, block, 0, s, a); break;
+        case 32: hipLaunchKernelGGL((fr_step_kernel<PREC, 32>), grid, block, 0, s, a); break;
+        default: hipLaunchKernelGGL((fr_step_kernel<PREC, 64>), grid, block, 0, s, a); break;
+    }
+}
+
+int launch_step(const gila_khop* kh, int precision, const StepArgs& a, hipStream_t s) {
+    if (a.nblocks <= 0) return GILA_OK;
+    switch (precision) {
+        case GILA_FP64: launch_prec<GILA_FP64>(kh->lpv, a, s); break;
+        case GILA_FP32: launch_prec<GILA_FP32>(kh->lpv, a, s); break;
+        case GILA_FP32_KAHAN: launch_prec<GILA_FP32_KAHAN>(kh->lpv, a, s); break;
+        default: return fail(GILA_EINVAL, "unknown precision %d", precision);
+    }
+    GILA_HIP(hipGetLastError());
+    return GILA_OK;
+}
+
+// ------------------------------------------------------------------ plan
+// Rows are sorted by length, longest first.  Rows of at least kHubMin pairs
+// get a workgroup each; the rest are packed into contiguous ranges of about
+// kPairsPerBlock pairs (plus a per-vertex overhead) and at most
+// kMaxVertsPerBlock vertices.
+static constexpr int64_t kHubMin = 8192;
+static constexpr int64_t kVertexCost = 32;
+
+int plan_iteration(gila_khop* kh, const std::vector<int64_t>& counts,
+                   const std::vector<int64_t>& rp_internal) {
+    const int32_t na = kh->n_active;
+    int32_t nhub = 0;
+    while (nhub < na && counts[nhub] >= kHubMin) ++nhub;
+    // lanes per vertex from the median row length of the non-hub vertices
+    int64_t med = 0;
+    if (na > nhub) med = counts[nhub + (na - nhub) / 2];
+    int lpv = 4;
+    while (lpv < 64 && lpv * 8 < med) lpv *= 2;
+    const int64_t pairs_per_block = std::max<int64_t>(2048, 64ll * lpv);
+    const int32_t max_verts = kWaves * (64 / lpv) * 16;
+    std::vector<int32_t> starts;
+    starts.push_back(nhub);
+    int64_t acc = 0;
+    int32_t cnt = 0;
+    for (int32_t v = nhub; v < na; ++v) {
+        acc += counts[v] + (rp_internal[v + 1] - rp_internal[v]) + kVertexCost;
+        ++cnt;
+        if (acc >= pairs_per_block || cnt >= max_verts) {
+            starts.push_back(v + 1);
+            acc = 0;
+            cnt = 0;
+        }
+    }
+    if (starts.back() != na) starts.push_back(na);
+    kh->lpv = lpv;
+    kh->nhub = nhub;
+    const int32_t nnormal = (int32_t)starts.size() - 1;
+    kh->nblocks = nhub + nnormal;
+    GILA_TRY(dalloc_t(&kh->block_start, starts.size()));
+    GILA_HIP(hipMemcpy(kh->block_start, starts.data(), sizeof(int32_t) * starts.size(),
+                       hipMemcpyHostToDevice));
+    return GILA_OK;
+}
+
+}  // namespace gila

@@ -1,0 +1,155 @@
+// Internal declarations of libgila (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/gila.h"
+
+namespace gila {
+
+// ------------------------------------------------------------------ errors
+int fail(int code, const char* fmt, ...);  // records a thread-local message, returns code
+void clear_error();
+
+#define GILA_HIP(call)                                                                  \
+    do {                                                                                \
+        hipError_t gila_e_ = (call);                                                    \
+        if (gila_e_ != hipSuccess)                                                      \
+            return ::gila::fail(gila_e_ == hipErrorOutOfMemory ? GILA_ENOMEM : GILA_EDEVICE, \
+                                "%s failed: %s (%s:%d)", #call,                        \
+                                hipGetErrorString(gila_e_), __FILE__, __LINE__);        \
+    } while (0)
+
+#define GILA_TRY(expr)            \
+    do {                          \
+        int gila_rc_ = (expr);    \
+        if (gila_rc_ != GILA_OK)  \
+            return gila_rc_;      \
+    } while (0)
+
+// Device allocation that maps failure to GILA_ENOMEM.
+int dalloc(void** p, size_t bytes);
+template <class T>
+int dalloc_t(T** p, size_t count) {
+    return dalloc(reinterpret_cast<void**>(p), count * sizeof(T) + (count == 0 ? 16 : 0));
+}
+void dfree(void* p);
+
+// Restores the caller's current device on scope exit.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceGuard(int dev);
+    ~DeviceGuard();
+};
+
+// A library-owned, default-priority stream per device for graph capture.
+hipStream_t capture_stream(int device);
+
+struct DeviceInfo {
+    int cus = 256;
+    size_t max_lds_per_block = 65536;
+    int warp = 64;
+};
+const DeviceInfo& device_info(int device);
+
+constexpr int kBlock = 256;       // threads per workgroup in every kernel
+constexpr int kWaves = kBlock / 64;
+
+// ------------------------------------------------------------------ device control block
+// Written by the last workgroup of each iteration kernel; read by the host at
+// the end of a call and by the next iteration kernel (stopped flag).
+struct Ctl {
+    int32_t stopped;
+    int32_t iters_run;
+    uint32_t done_blocks;  // "last block" ticket, reset to 0 by the last block
+    int32_t pad;
+    int64_t moved;
+    double max_disp;
+    double energy;
+    int64_t coincident;
+};
+
+// Per-workgroup partial statistics of one iteration.
+struct Partial {
+    double energy;
+    double max_disp;
+    int64_t moved;
+    int64_t coincident;
+};
+
+// ------------------------------------------------------------------ iteration kernel arguments
+struct StepArgs {
+    int32_t n_active;
+    int32_t nhub;               // vertices [0, nhub) are hubs: one workgroup each
+    int32_t nblocks;            // total workgroups of the launch
+    const int32_t* block_start; // normal workgroup b - nhub covers [block_start[b-nhub], block_start[b-nhub+1])
+    const int64_t* rp;
+    const int32_t* ci;
+    const int64_t* kptr;
+    const int32_t* kidx;
+    const void* pos_cur;
+    void* pos_next;
+    double d;
+    double t;
+    double stop_fraction;
+    double stop_displacement;
+    int32_t check_stop;
+    int32_t hist_slot;          // < 0: no history
+    const int32_t* perm;        // internal -> caller ids (for F/D outputs)
+    double* F_out;              // caller ids, may be null
+    double* D_out;
+    Partial* partials;          // [nblocks]
+    Ctl* ctl;
+    double* hist;               // [slots][4]: energy, max_disp, moved, coincident
+};
+
+}  // namespace gila
+
+// ------------------------------------------------------------------ handles
+struct gila_khop {
+    int device = 0;
+    int32_t n = 0, k = 0, n_active = 0;
+    int64_t nnz = 0, P = 0;
+    int64_t device_bytes = 0;
+    // internal vertex ids: sorted by |N_v(k)| descending (ties: caller id ascending)
+    int32_t* perm = nullptr;   // [n] internal -> caller
+    int32_t* iperm = nullptr;  // [n] caller -> internal
+    int64_t* rp = nullptr;     // internal CSR
+    int32_t* ci = nullptr;
+    int64_t* kptr = nullptr;   // internal k-hop CSR, rows ascending in internal ids
+    int32_t* kidx = nullptr;
+    // plan of the iteration kernel
+    int32_t lpv = 64;          // lanes per vertex for non-hub vertices
+    int32_t nhub = 0;
+    int32_t nblocks = 0;       // hub + normal workgroups
+    int32_t* block_start = nullptr;
+    // workspace
+    void* pos[2] = {nullptr, nullptr};  // 16 B per vertex each
+    gila::Partial* partials = nullptr;
+    gila::Ctl* ctl = nullptr;
+    double* hist = nullptr;
+    int32_t hist_cap = 0;
+    // cached HIP graph of the last gila_run call
+    hipGraphExec_t gexec = nullptr;
+    std::vector<uint64_t> gkey;
+    std::mutex mu;
+};
+
+namespace gila {
+// implemented in force.hip
+int launch_step(const gila_khop* kh, int precision, const StepArgs& a, hipStream_t s);
+int plan_iteration(gila_khop* kh, const std::vector<int64_t>& counts_internal,
+                   const std::vector<int64_t>& rp_internal);
+// implemented in layout.hip
+int run_iterations(gila_khop* kh, const gila_params* p, int32_t start_h, int32_t end_h,
+                   void* pos_dev, hipStream_t stream, gila_stats* out, bool use_graph);
+int check_params(const gila_params* p, bool need_temps);
+}  // namespace gila

@@ -1,0 +1,553 @@
+// k-neighbourhood lists N_v(k) (Section 4.5) by CSR frontier expansion.
+//
+// The paper delivers N_v(k) to v every iteration by flooding messages with a
+// time-to-live of k and deduplicating senders in a per-vertex hash set.  The
+// graph does not change between iterations, so here the set is built once:
+// one workgroup expands the frontier of one source vertex level by level,
+// deduplicating with a bitmap over all vertex ids held in LDS (global memory
+// when n is too large for LDS).  A count pass gives |N_v(k)|; after the
+// prefix sum a fill pass writes each row by scanning the bitmap, which yields
+// the row in ascending id order with no sort.
+#include <algorithm>
+#include <numeric>
+
+#include "device_util.h"
+#include "gila_internal.h"
+
+namespace gila {
+
+// ------------------------------------------------------------------ validation
+// flag bits: 1 column out of range, 2 self-loop, 4 row not strictly ascending,
+// 8 asymmetric (u in row v but v not in row u)
+__global__ __launch_bounds__(kBlock) void validate_csr_kernel(int32_t n, int64_t nnz,
+                                                              const int64_t* __restrict__ rp,
+                                                              const int32_t* __restrict__ ci,
+                                                              int32_t* __restrict__ flag) {
+    int32_t bad = 0;
+    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < nnz;
+         e += (int64_t)gridDim.x * kBlock) {
+        // owner row: largest v with rp[v] <= e
+        int32_t lo = 0, hi = n - 1;
+        while (lo < hi) {
+            int32_t mid = lo + (hi - lo + 1) / 2;
+            if (rp[mid] <= e) lo = mid;
+            else hi = mid - 1;
+        }
+        const int32_t v = lo;
+        const int32_t u = ci[e];
+        if (u < 0 || u >= n) {
+            bad |= 1;
+            continue;
+        }
+        if (u == v) bad |= 2;
+        if (e > rp[v] && ci[e - 1] >= u) bad |= 4;
+        // binary search v in row u
+        int64_t a = rp[u], b = rp[u + 1] - 1;
+        bool found = false;
+        while (a <= b) {
+            int64_t mid = a + (b - a) / 2;
+            int32_t x = ci[mid];
+            if (x == v) {
+                found = true;
+                break;
+            }
+            if (x < v) a = mid + 1;
+            else b = mid - 1;
+        }
+        if (!found) bad |= 8;
+    }
+    if (bad) atomicOr(flag, bad);
+}
+
+// ------------------------------------------------------------------ BFS count / fill
+struct BfsArgs {
+    int32_t n;
+    int32_t k;
+    int32_t nverts;            // sources are ids [0, nverts)
+    int32_t nwords;            // bitmap words = ceil(n / 32)
+    const int64_t* rp;
+    const int32_t* ci;
+    int64_t* counts;           // count pass: |N_v(k)| per source
+    const int64_t* kptr;       // fill pass: row offsets
+    int32_t* kidx;             // fill pass: rows
+    int32_t* queue;            // [grid][qcap] frontier storage (k >= 3)
+    int64_t qcap;
+    uint32_t* gbitmap;         // [grid][nwords] when the bitmap is not in LDS
+    int32_t* work;             // next source (atomic)
+};
+
+template <bool FILL, bool LDS_BITMAP>
+__global__ __launch_bounds__(kBlock) void khop_bfs_kernel(BfsArgs a) {
+    extern __shared__ uint32_t s_dyn[];
+    __shared__ int32_t s_v;
+    __shared__ int32_t s_qtail;
+    __shared__ int64_t s_incl[kBlock];   // inclusive prefix of frontier-chunk degrees
+    __shared__ int64_t s_start[kBlock];  // row start of each frontier-chunk vertex
+    __shared__ int64_t s_red[4];
+
+    uint32_t* bm = LDS_BITMAP ? s_dyn : a.gbitmap + (size_t)blockIdx.x * a.nwords;
+    int32_t* queue = a.queue ? a.queue + (size_t)blockIdx.x * a.qcap : nullptr;
+
+    for (int i = threadIdx.x; i < a.nwords; i += kBlock) bm[i] = 0u;
+    __syncthreads();
+
+    for (;;) {
+        if (threadIdx.x == 0) s_v = atomicAdd(a.work, 1);
+        __syncthreads();
+        const int32_t v = s_v;
+        if (v >= a.nverts) break;
+        const int64_t rb = a.rp[v], re = a.rp[v + 1];
+        int64_t mycount = 0;
+        if (re > rb) {
+            if (threadIdx.x == 0) {
+                bm[v >> 5] |= 1u << (v & 31);
+                s_qtail = 0;
+            }
+            __syncthreads();
+            // level 1: the adjacency row (distinct, never v in a simple graph)
+            for (int64_t e = rb + threadIdx.x; e < re; e += kBlock) {
+                const int32_t u = a.ci[e];
+                const uint32_t bit = 1u << (u & 31);
+                const uint32_t old = atomicOr(&bm[u >> 5], bit);
+                if (!(old & bit)) {
+                    ++mycount;
+                }
+            }
+            __syncthreads();
+            // levels 2..k: expand the previous level's new vertices
+            int64_t fb = rb, fe = re;
+            bool from_queue = false;
+            for (int level = 2; level <= a.k; ++level) {
+                const bool record = level < a.k;
+                const int32_t qstart = s_qtail;
+                for (int64_t c = fb; c < fe; c += kBlock) {
+                    const int64_t i = c + threadIdx.x;
+                    int64_t deg = 0, start = 0;
+                    if (i < fe) {
+                        const int32_t w = from_queue ? queue[i] : a.ci[i];
+                        start = a.rp[w];
+                        deg = a.rp[w + 1] - start;
+                    }
+                    int64_t total;
+                    const int64_t ex = block_exclusive_scan<int64_t>(deg, s_red, total);
+                    s_incl[threadIdx.x] = ex + deg;
+                    s_start[threadIdx.x] = start;
+                    __syncthreads();
+                    for (int64_t j = threadIdx.x; j < total; j += kBlock) {
+                        int lo = 0, hi = kBlock - 1;
+                        while (lo < hi) {
+                            const int mid = (lo + hi) >> 1;
+                            if (s_incl[mid] > j) hi = mid;
+                            else lo = mid + 1;
+                        }
+                        const int64_t off = j - (lo ? s_incl[lo - 1] : 0);
+                        const int32_t u = a.ci[s_start[lo] + off];
+                        const uint32_t bit = 1u << (u & 31);
+                        const uint32_t old = atomicOr(&bm[u >> 5], bit);
+                        if (!(old & bit)) {
+                            ++mycount;
+                            if (record) {
+                                const int32_t q = atomicAdd(&s_qtail, 1);
+                                queue[q] = u;
+                            }
+                        }
+                    }
+                    __syncthreads();
+                }
+                fb = qstart;
+                fe = s_qtail;
+                from_queue = true;
+                __syncthreads();
+            }
+        }
+        if constexpr (!FILL) {
+            const int64_t cnt = block_sum<int64_t>(mycount, s_red);
+            if (threadIdx.x == 0) a.counts[v] = cnt;
+            if (re > rb) {
+                for (int i = threadIdx.x; i < a.nwords; i += kBlock) bm[i] = 0u;
+            }
+        } else {
+            if (re > rb) {
+                if (threadIdx.x == 0) bm[v >> 5] &= ~(1u << (v & 31));
+                __syncthreads();
+                int64_t base = a.kptr[v];
+                const int64_t end = a.kptr[v + 1];
+                for (int w0 = 0; w0 < a.nwords; w0 += kBlock) {
+                    const int wi = w0 + threadIdx.x;
+                    uint32_t word = wi < a.nwords ? bm[wi] : 0u;
+                    int64_t total;
+                    const int64_t ex =
+                        block_exclusive_scan<int64_t>((int64_t)__popc(word), s_red, total);
+                    int64_t o = base + ex;
+                    while (word) {
+                        const int b = __ffs(word) - 1;
+                        if (o < end) a.kidx[o] = wi * 32 + b;
+                        ++o;
+                        word &= word - 1u;
+                    }
+                    if (wi < a.nwords) bm[wi] = 0u;
+                    base += total;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------ relabelling
+// Internal row i is caller row perm[i] with every id mapped through iperm.
+__global__ __launch_bounds__(kBlock) void relabel_csr_kernel(
+    int32_t n, const int32_t* __restrict__ perm, const int32_t* __restrict__ iperm,
+    const int64_t* __restrict__ rp_in, const int32_t* __restrict__ ci_in,
+    const int64_t* __restrict__ rp_out, int32_t* __restrict__ ci_out) {
+    // one wavefront per row
+    const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
+    const int64_t nw = ((int64_t)gridDim.x * kBlock) >> 6;
+    for (int64_t i = wave; i < n; i += nw) {
+        const int32_t src = perm[i];
+        const int64_t b = rp_in[src], e = rp_in[src + 1], o = rp_out[i];
+        for (int64_t j = b + lane64(); j < e; j += 64) ci_out[o + (j - b)] = iperm[ci_in[j]];
+    }
+}
+
+__global__ void reset_counter_kernel(int32_t* c) { *c = 0; }
+
+static int run_bfs(bool fill, int device, hipStream_t s, BfsArgs a) {
+    const DeviceInfo& di = device_info(device);
+    const size_t bm_bytes = (size_t)a.nwords * 4;
+    const bool lds = bm_bytes + 8 * 1024 * 2 + 1024 <= di.max_lds_per_block;
+    // workgroups resident per CU limited by LDS (160 KB per CU on gfx950)
+    int per_cu = 8;
+    if (lds) {
+        size_t per = bm_bytes + 4096;
+        per_cu = (int)std::max<size_t>(1, std::min<size_t>(8, (160u * 1024u) / per));
+    }
+    int grid = di.cus * per_cu;
+    if (a.nverts < grid) grid = std::max(1, a.nverts);
+    if (a.k >= 3) {
+        // frontier queues: n ids per workgroup, capped at ~1 GiB in total
+        const int64_t cap_grid = std::max<int64_t>(64, (1ll << 30) / std::max<int64_t>(1, 4ll * a.n));
+        grid = (int)std::min<int64_t>(grid, cap_grid);
+        a.qcap = std::max<int32_t>(1, a.n);
+        GILA_TRY(dalloc_t(&a.queue, (size_t)grid * a.qcap));
+    } else {
+        a.queue = nullptr;
+        a.qcap = 0;
+    }
+    a.gbitmap = nullptr;
+    if (!lds) {
+        int rc = dalloc_t(&a.gbitmap, (size_t)grid * a.nwords);
+        if (rc) {
+            dfree(a.queue);
+            return rc;
+        }
+    }
+    int rc = GILA_OK;
+    hipError_t e = hipSuccess;
+    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, a.work);
+    const size_t shm = lds ? bm_bytes : 0;
+    if (fill) {
+        if (lds) {
+            if (shm > 65536)
+                (void)hipFuncSetAttribute((const void*)khop_bfs_kernel<true, true>,
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+            hipLaunchKernelGGL((khop_bfs_kernel<true, true>), dim3(grid), dim3(kBlock), shm, s, a);
+        } else {
+            hipLaunchKernelGGL((khop_bfs_kernel<true, false>), dim3(grid), dim3(kBlock), 0, s, a);
+        }
+    } else {
+        if (lds) {
+            if (shm > 65536)
+                (void)hipFuncSetAttribute((const void*)khop_bfs_kernel<false, true>,
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+            hipLaunchKernelGGL((khop_bfs_kernel<false, true>), dim3(grid), dim3(kBlock), shm, s,
+                               a);
+        } else {
+            hipLaunchKernelGGL((khop_bfs_kernel<false, false>), dim3(grid), dim3(kBlock), 0, s,
+                               a);
+        }
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) rc = fail(GILA_EDEVICE, "k-hop kernel launch: %s", hipGetErrorString(e));
+    // scratch is freed after the work on the stream is done
+    hipError_t se = hipStreamSynchronize(s);
+    if (rc == GILA_OK && se != hipSuccess)
+        rc = fail(GILA_EDEVICE, "k-hop kernel: %s", hipGetErrorString(se));
+    dfree(a.queue);
+    dfree(a.gbitmap);
+    return rc;
+}
+
+static void free_khop(gila_khop* kh) {
+    if (!kh) return;
+    DeviceGuard g(kh->device);
+    if (kh->gexec) (void)hipGraphExecDestroy(kh->gexec);
+    dfree(kh->perm);
+    dfree(kh->iperm);
+    dfree(kh->rp);
+    dfree(kh->ci);
+    dfree(kh->kptr);
+    dfree(kh->kidx);
+    dfree(kh->block_start);
+    dfree(kh->pos[0]);
+    dfree(kh->pos[1]);
+    dfree(kh->partials);
+    dfree(kh->ctl);
+    dfree(kh->hist);
+    delete kh;
+}
+
+struct KhopHolder {
+    gila_khop* p;
+    ~KhopHolder() { free_khop(p); }
+};
+
+static int build_khop(const gila_csr* g, int32_t k, hipStream_t s, gila_khop** out) {
+    if (!out) return fail(GILA_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!g) return fail(GILA_EINVAL, "graph is NULL");
+    if (k < 1) return fail(GILA_EINVAL, "k must be >= 1 (got %d)", k);
+    if (g->n < 0 || g->nnz < 0) return fail(GILA_EINVAL, "negative n or nnz");
+    if (g->n > 0 && !g->row_ptr) return fail(GILA_EINVAL, "row_ptr is NULL");
+    if (g->nnz > 0 && !g->col_idx) return fail(GILA_EINVAL, "col_idx is NULL");
+    if (g->nnz > (int64_t)g->n * (int64_t)(g->n > 0 ? g->n - 1 : 0))
+        return fail(GILA_EINVAL, "nnz exceeds n(n-1)");
+    int dev = 0;
+    GILA_HIP(hipGetDevice(&dev));
+    const int32_t n = g->n;
+    const int64_t nnz = g->nnz;
+
+    KhopHolder h{new gila_khop()};
+    gila_khop* kh = h.p;
+    kh->device = dev;
+    kh->n = n;
+    kh->k = k;
+    kh->nnz = nnz;
+
+    // --- row pointers on the host: monotone, 0 .. nnz
+    std::vector<int64_t> rp_host((size_t)n + 1, 0);
+    if (n > 0) {
+        GILA_HIP(hipMemcpyAsync(rp_host.data(), g->row_ptr, sizeof(int64_t) * (n + 1),
+                                hipMemcpyDeviceToHost, s));
+        GILA_HIP(hipStreamSynchronize(s));
+        if (rp_host[0] != 0 || rp_host[n] != nnz)
+            return fail(GILA_EINVAL, "row_ptr[0] must be 0 and row_ptr[n] must equal nnz");
+        for (int32_t v = 0; v < n; ++v)
+            if (rp_host[v + 1] < rp_host[v]) return fail(GILA_EINVAL, "row_ptr not monotone");
+        if (nnz % 2) return fail(GILA_EINVAL, "nnz must be even for a symmetric CSR");
+    }
+
+    // --- device validation of every entry
+    int32_t* d_flag = nullptr;
+    int32_t* d_work = nullptr;
+    GILA_TRY(dalloc_t(&d_flag, 2));
+    struct F {
+        int32_t* p;
+        int32_t* w;
+        ~F() {
+            dfree(p);
+        }
+    } fguard{d_flag, nullptr};
+    d_work = d_flag + 1;
+    GILA_HIP(hipMemsetAsync(d_flag, 0, 2 * sizeof(int32_t), s));
+    if (nnz > 0) {
+        const int grid = (int)std::min<int64_t>(4096, (nnz + kBlock - 1) / kBlock);
+        hipLaunchKernelGGL(validate_csr_kernel, dim3(grid), dim3(kBlock), 0, s, n, nnz,
+                           g->row_ptr, g->col_idx, d_flag);
+        GILA_HIP(hipGetLastError());
+    }
+    int32_t flag = 0;
+    GILA_HIP(hipMemcpyAsync(&flag, d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    GILA_HIP(hipStreamSynchronize(s));
+    if (flag) {
+        return fail(GILA_EINVAL, "malformed CSR:%s%s%s%s", (flag & 1) ? " column out of range" : "",
+                    (flag & 2) ? " self-loop" : "", (flag & 4) ? " row not strictly ascending" : "",
+                    (flag & 8) ? " not symmetric" : "");
+    }
+
+    // --- count pass on the caller's graph
+    const int32_t nwords = (n + 31) / 32;
+    std::vector<int64_t> counts((size_t)n, 0);
+    int64_t* d_counts = nullptr;
+    if (n > 0) {
+        GILA_TRY(dalloc_t(&d_counts, (size_t)n));
+        BfsArgs a{};
+        a.n = n;
+        a.k = k;
+        a.nverts = n;
+        a.nwords = nwords;
+        a.rp = g->row_ptr;
+        a.ci = g->col_idx;
+        a.counts = d_counts;
+        a.work = d_work;
+        int rc = run_bfs(false, dev, s, a);
+        if (rc == GILA_OK) {
+            hipError_t e = hipMemcpy(counts.data(), d_counts, sizeof(int64_t) * n,
+                                     hipMemcpyDeviceToHost);
+            if (e != hipSuccess) rc = fail(GILA_EDEVICE, "copy counts: %s", hipGetErrorString(e));
+        }
+        dfree(d_counts);
+        if (rc) return rc;
+    }
+
+    // --- internal order: |N_v(k)| descending, ties by caller id
+    std::vector<int32_t> perm((size_t)n), iperm((size_t)n);
+    std::iota(perm.begin(), perm.end(), 0);
+    std::stable_sort(perm.begin(), perm.end(),
+                     [&](int32_t x, int32_t y) { return counts[x] > counts[y]; });
+    for (int32_t i = 0; i < n; ++i) iperm[perm[i]] = i;
+    int64_t P = 0;
+    int32_t n_active = 0;
+    std::vector<int64_t> rp_int((size_t)n + 1, 0), kptr((size_t)n + 1, 0), cnt_int((size_t)n);
+    for (int32_t i = 0; i < n; ++i) {
+        const int32_t v = perm[i];
+        cnt_int[i] = counts[v];
+        rp_int[i + 1] = rp_int[i] + (rp_host[v + 1] - rp_host[v]);
+        kptr[i + 1] = kptr[i] + counts[v];
+        if (rp_host[v + 1] > rp_host[v]) ++n_active;
+    }
+    P = kptr[n];
+    kh->P = P;
+    kh->n_active = n_active;
+
+    // --- internal graph copy
+    GILA_TRY(dalloc_t(&kh->perm, (size_t)n));
+    GILA_TRY(dalloc_t(&kh->iperm, (size_t)n));
+    GILA_TRY(dalloc_t(&kh->rp, (size_t)n + 1));
+    GILA_TRY(dalloc_t(&kh->ci, (size_t)nnz));
+    GILA_TRY(dalloc_t(&kh->kptr, (size_t)n + 1));
+    GILA_TRY(dalloc_t(&kh->kidx, (size_t)P));
+    GILA_HIP(hipMemcpyAsync(kh->perm, perm.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
+    GILA_HIP(hipMemcpyAsync(kh->iperm, iperm.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice,
+                            s));
+    GILA_HIP(hipMemcpyAsync(kh->rp, rp_int.data(), sizeof(int64_t) * (n + 1),
+                            hipMemcpyHostToDevice, s));
+    GILA_HIP(hipMemcpyAsync(kh->kptr, kptr.data(), sizeof(int64_t) * (n + 1),
+                            hipMemcpyHostToDevice, s));
+    if (n > 0 && nnz > 0) {
+        const int grid = (int)std::min<int64_t>(8192, ((int64_t)n * 64 + kBlock - 1) / kBlock);
+        hipLaunchKernelGGL(relabel_csr_kernel, dim3(grid), dim3(kBlock), 0, s, n, kh->perm,
+                           kh->iperm, g->row_ptr, g->col_idx, kh->rp, kh->ci);
+        GILA_HIP(hipGetLastError());
+    }
+
+    // --- fill pass on the internal graph (rows come out ascending)
+    if (n_active > 0 && P > 0) {
+        BfsArgs a{};
+        a.n = n;
+        a.k = k;
+        a.nverts = n_active;
+        a.nwords = nwords;
+        a.rp = kh->rp;
+        a.ci = kh->ci;
+        a.kptr = kh->kptr;
+        a.kidx = kh->kidx;
+        a.work = d_work;
+        GILA_TRY(run_bfs(true, dev, s, a));
+    }
+
+    // --- plan of the iteration kernel and its workspace
+    GILA_TRY(plan_iteration(kh, cnt_int, rp_int));
+    GILA_TRY(dalloc_t(reinterpret_cast<double**>(&kh->pos[0]), 2 * (size_t)std::max(n, 1)));
+    GILA_TRY(dalloc_t(reinterpret_cast<double**>(&kh->pos[1]), 2 * (size_t)std::max(n, 1)));
+    GILA_TRY(dalloc_t(&kh->partials, (size_t)std::max(kh->nblocks, 1)));
+    GILA_TRY(dalloc_t(&kh->ctl, 1));
+    GILA_HIP(hipMemsetAsync(kh->ctl, 0, sizeof(Ctl), s));
+    GILA_HIP(hipStreamSynchronize(s));
+    kh->device_bytes = (int64_t)sizeof(int32_t) * 2 * n + sizeof(int64_t) * 2 * (n + 1) +
+                       sizeof(int32_t) * (nnz + P) + 32 * (int64_t)n +
+                       (int64_t)sizeof(Partial) * kh->nblocks + sizeof(int32_t) * (kh->nblocks + 1);
+    *out = kh;
+    h.p = nullptr;
+    return GILA_OK;
+}
+
+}  // namespace gila
+
+using namespace gila;
+
+extern "C" {
+
+int gila_build_khop(const gila_csr* g_dev, int32_t k, void* stream, gila_khop** out) {
+    clear_error();
+    return build_khop(g_dev, k, (hipStream_t)stream, out);
+}
+
+int gila_khop_info(const gila_khop* kh, int32_t* n, int32_t* k, int64_t* total_pairs,
+                   int32_t* n_active, int64_t* device_bytes) {
+    if (!kh) return fail(GILA_EINVAL, "handle is NULL");
+    if (n) *n = kh->n;
+    if (k) *k = kh->k;
+    if (total_pairs) *total_pairs = kh->P;
+    if (n_active) *n_active = kh->n_active;
+    if (device_bytes) *device_bytes = kh->device_bytes;
+    return GILA_OK;
+}
+
+int gila_khop_export_rows(const gila_khop* kh, int64_t count, const int32_t* verts_host,
+                          int64_t* ptr_host, int32_t* idx_host) {
+    clear_error();
+    if (!kh) return fail(GILA_EINVAL, "handle is NULL");
+    if (count < 0 || (count > 0 && !verts_host)) return fail(GILA_EINVAL, "bad vertex list");
+    if (!ptr_host) return fail(GILA_EINVAL, "ptr_host is NULL");
+    DeviceGuard dg(kh->device);
+    const int32_t n = kh->n;
+    std::vector<int64_t> kptr((size_t)n + 1);
+    std::vector<int32_t> perm((size_t)n), iperm((size_t)n);
+    GILA_HIP(hipMemcpy(kptr.data(), kh->kptr, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost));
+    GILA_HIP(hipMemcpy(perm.data(), kh->perm, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+    GILA_HIP(hipMemcpy(iperm.data(), kh->iperm, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+    ptr_host[0] = 0;
+    for (int64_t i = 0; i < count; ++i) {
+        const int32_t v = verts_host[i];
+        if (v < 0 || v >= n) return fail(GILA_EINVAL, "vertex %d out of range", v);
+        const int32_t r = iperm[v];
+        ptr_host[i + 1] = ptr_host[i] + (kptr[r + 1] - kptr[r]);
+    }
+    if (!idx_host) return GILA_OK;
+    for (int64_t i = 0; i < count; ++i) {
+        const int32_t r = iperm[verts_host[i]];
+        const int64_t len = kptr[r + 1] - kptr[r];
+        int32_t* dst = idx_host + ptr_host[i];
+        if (len > 0)
+            GILA_HIP(hipMemcpy(dst, kh->kidx + kptr[r], sizeof(int32_t) * len,
+                               hipMemcpyDeviceToHost));
+        for (int64_t j = 0; j < len; ++j) dst[j] = perm[dst[j]];
+        std::sort(dst, dst + len);
+    }
+    return GILA_OK;
+}
+
+int gila_khop_export(const gila_khop* kh, int64_t* ptr_host, int32_t* idx_host) {
+    clear_error();
+    if (!kh) return fail(GILA_EINVAL, "handle is NULL");
+    DeviceGuard dg(kh->device);
+    const int32_t n = kh->n;
+    std::vector<int64_t> kptr((size_t)n + 1);
+    std::vector<int32_t> perm((size_t)n), iperm((size_t)n);
+    GILA_HIP(hipMemcpy(kptr.data(), kh->kptr, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost));
+    GILA_HIP(hipMemcpy(perm.data(), kh->perm, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+    GILA_HIP(hipMemcpy(iperm.data(), kh->iperm, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+    std::vector<int64_t> ptr((size_t)n + 1, 0);
+    for (int32_t v = 0; v < n; ++v) {
+        const int32_t r = iperm[v];
+        ptr[v + 1] = ptr[v] + (kptr[r + 1] - kptr[r]);
+    }
+    if (ptr_host) std::memcpy(ptr_host, ptr.data(), sizeof(int64_t) * (n + 1));
+    if (!idx_host) return GILA_OK;
+    std::vector<int32_t> all((size_t)kh->P);
+    if (kh->P > 0)
+        GILA_HIP(hipMemcpy(all.data(), kh->kidx, sizeof(int32_t) * kh->P, hipMemcpyDeviceToHost));
+    for (int32_t v = 0; v < n; ++v) {
+        const int32_t r = iperm[v];
+        int32_t* dst = idx_host + ptr[v];
+        const int64_t len = kptr[r + 1] - kptr[r];
+        for (int64_t j = 0; j < len; ++j) dst[j] = perm[all[kptr[r] + j]];
+        std::sort(dst, dst + len);
+    }
+    return GILA_OK;
+}
+
+void gila_khop_free(gila_khop* kh) { free_khop(kh); }
+
+}  // extern "C"

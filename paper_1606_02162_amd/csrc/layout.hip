@@ -1,0 +1,339 @@
+// Iteration drivers: seeded placement, one step, a device-resident loop of
+// steps captured as a HIP graph, and the whole-layout entry point.
+#include <cmath>
+
+#include "device_util.h"
+#include "gila_internal.h"
+
+namespace gila {
+
+// ------------------------------------------------------------------ placement
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t c) {
+    // output number c (0-based) of SplitMix64 seeded with `seed`
+    uint64_t z = seed + (c + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+template <class V>
+__global__ __launch_bounds__(kBlock) void init_positions_kernel(int32_t n, uint64_t seed,
+                                                                double width, double height,
+                                                                V* __restrict__ pos) {
+    for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * kBlock) {
+        const double ux = (double)(splitmix64_at(seed, 2ull * v) >> 11) * 0x1.0p-53;
+        const double uy = (double)(splitmix64_at(seed, 2ull * v + 1ull) >> 11) * 0x1.0p-53;
+        V p;
+        p.x = (decltype(p.x))(ux * width);
+        p.y = (decltype(p.y))(uy * height);
+        pos[v] = p;
+    }
+}
+
+// ------------------------------------------------------------------ small kernels
+__global__ void reset_ctl_kernel(Ctl* ctl) {
+    ctl->stopped = 0;
+    ctl->iters_run = 0;
+    ctl->done_blocks = 0u;
+    ctl->moved = 0;
+    ctl->max_disp = 0.0;
+    ctl->energy = 0.0;
+    ctl->coincident = 0;
+}
+
+// Caller positions -> internal buffer 0; isolated vertices (the tail of the
+// internal order) never move, so they are written to buffer 1 as well.
+template <class V>
+__global__ __launch_bounds__(kBlock) void permute_in_kernel(int32_t n, int32_t n_active,
+                                                            const int32_t* __restrict__ perm,
+                                                            const V* __restrict__ src,
+                                                            V* __restrict__ b0,
+                                                            V* __restrict__ b1) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock) {
+        const V p = src[perm[i]];
+        b0[i] = p;
+        if (i >= n_active) b1[i] = p;
+    }
+}
+
+// Internal buffer holding the result (iteration parity) -> caller positions.
+template <class V>
+__global__ __launch_bounds__(kBlock) void permute_out_kernel(int32_t n,
+                                                             const int32_t* __restrict__ perm,
+                                                             const V* __restrict__ b0,
+                                                             const V* __restrict__ b1,
+                                                             const Ctl* __restrict__ ctl,
+                                                             V* __restrict__ dst) {
+    const V* src = (ctl->iters_run & 1) ? b1 : b0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock)
+        dst[perm[i]] = src[i];
+}
+
+static int grid_for(int64_t items) {
+    return (int)std::max<int64_t>(1, std::min<int64_t>(4096, (items + kBlock - 1) / kBlock));
+}
+
+static int launch_permute_in(const gila_khop* kh, int precision, const void* pos, hipStream_t s) {
+    if (kh->n == 0) return GILA_OK;
+    const int g = grid_for(kh->n);
+    if (precision == GILA_FP64)
+        hipLaunchKernelGGL(permute_in_kernel<double2>, dim3(g), dim3(kBlock), 0, s, kh->n,
+                           kh->n_active, kh->perm, (const double2*)pos, (double2*)kh->pos[0],
+                           (double2*)kh->pos[1]);
+    else
+        hipLaunchKernelGGL(permute_in_kernel<float2>, dim3(g), dim3(kBlock), 0, s, kh->n,
+                           kh->n_active, kh->perm, (const float2*)pos, (float2*)kh->pos[0],
+                           (float2*)kh->pos[1]);
+    GILA_HIP(hipGetLastError());
+    return GILA_OK;
+}
+
+static int launch_permute_out(const gila_khop* kh, int precision, void* pos, hipStream_t s) {
+    if (kh->n == 0) return GILA_OK;
+    const int g = grid_for(kh->n);
+    if (precision == GILA_FP64)
+        hipLaunchKernelGGL(permute_out_kernel<double2>, dim3(g), dim3(kBlock), 0, s, kh->n,
+                           kh->perm, (const double2*)kh->pos[0], (const double2*)kh->pos[1],
+                           kh->ctl, (double2*)pos);
+    else
+        hipLaunchKernelGGL(permute_out_kernel<float2>, dim3(g), dim3(kBlock), 0, s, kh->n,
+                           kh->perm, (const float2*)kh->pos[0], (const float2*)kh->pos[1],
+                           kh->ctl, (float2*)pos);
+    GILA_HIP(hipGetLastError());
+    return GILA_OK;
+}
+
+int check_params(const gila_params* p, bool need_temps) {
+    if (!p) return fail(GILA_EINVAL, "params is NULL");
+    if (p->precision != GILA_FP64 && p->precision != GILA_FP32 &&
+        p->precision != GILA_FP32_KAHAN)
+        return fail(GILA_EINVAL, "unknown precision %d", p->precision);
+    if (!(p->ideal_length > 0.0) || !std::isfinite(p->ideal_length))
+        return fail(GILA_EINVAL, "ideal_length must be finite and > 0");
+    if (p->iterations < 0) return fail(GILA_EINVAL, "iterations must be >= 0");
+    if (need_temps && p->iterations > 0 && !p->temperature)
+        return fail(GILA_EINVAL, "temperature is NULL");
+    if (p->temperature)
+        for (int32_t h = 0; h < p->iterations; ++h)
+            if (!(p->temperature[h] >= 0.0) || !std::isfinite(p->temperature[h]))
+                return fail(GILA_EINVAL, "temperature[%d] must be finite and >= 0", h);
+    if (!(p->stop_fraction >= 0.0) || !(p->stop_displacement >= 0.0))
+        return fail(GILA_EINVAL, "stop parameters must be >= 0");
+    return GILA_OK;
+}
+
+static StepArgs base_args(const gila_khop* kh, const gila_params* p) {
+    StepArgs a{};
+    a.n_active = kh->n_active;
+    a.nhub = kh->nhub;
+    a.nblocks = kh->nblocks;
+    a.block_start = kh->block_start;
+    a.rp = kh->rp;
+    a.ci = kh->ci;
+    a.kptr = kh->kptr;
+    a.kidx = kh->kidx;
+    a.d = p->ideal_length;
+    a.stop_fraction = p->stop_fraction;
+    a.stop_displacement = p->stop_displacement;
+    a.perm = kh->perm;
+    a.partials = kh->partials;
+    a.ctl = kh->ctl;
+    a.hist = kh->hist;
+    a.hist_slot = -1;
+    return a;
+}
+
+static void to_stats(const Ctl& c, gila_stats* out) {
+    out->iterations_run = c.iters_run;
+    out->stopped = c.stopped;
+    out->moved = c.moved;
+    out->max_disp = c.max_disp;
+    out->energy = c.energy;
+    out->coincident = c.coincident;
+}
+
+// Enqueue: reset, permute in, iterations, permute out.
+static int enqueue_run(gila_khop* kh, const gila_params* p, int32_t start_h, int32_t end_h,
+                       void* pos_dev, hipStream_t s) {
+    hipLaunchKernelGGL(reset_ctl_kernel, dim3(1), dim3(1), 0, s, kh->ctl);
+    GILA_HIP(hipGetLastError());
+    GILA_TRY(launch_permute_in(kh, p->precision, pos_dev, s));
+    StepArgs a = base_args(kh, p);
+    a.check_stop = p->stop_fraction > 0.0 ? 1 : 0;
+    for (int32_t h = start_h; h < end_h; ++h) {
+        const int j = h - start_h;
+        a.pos_cur = kh->pos[j & 1];
+        a.pos_next = kh->pos[(j + 1) & 1];
+        a.t = p->temperature[h];
+        GILA_TRY(launch_step(kh, p->precision, a, s));
+    }
+    GILA_TRY(launch_permute_out(kh, p->precision, pos_dev, s));
+    return GILA_OK;
+}
+
+static std::vector<uint64_t> graph_key(const gila_params* p, int32_t start_h, int32_t end_h,
+                                       void* pos_dev) {
+    auto bits = [](double x) {
+        uint64_t u;
+        std::memcpy(&u, &x, 8);
+        return u;
+    };
+    std::vector<uint64_t> key = {(uint64_t)(uintptr_t)pos_dev, (uint64_t)start_h, (uint64_t)end_h,
+                                 (uint64_t)p->precision, bits(p->ideal_length),
+                                 bits(p->stop_fraction), bits(p->stop_displacement)};
+    for (int32_t h = start_h; h < end_h; ++h) key.push_back(bits(p->temperature[h]));
+    return key;
+}
+
+int run_iterations(gila_khop* kh, const gila_params* p, int32_t start_h, int32_t end_h,
+                   void* pos_dev, hipStream_t stream, gila_stats* out, bool use_graph) {
+    if (kh->n > 0 && !pos_dev) return fail(GILA_EINVAL, "pos_dev is NULL");
+    if (start_h < 0 || end_h < start_h || end_h > p->iterations)
+        return fail(GILA_EINVAL, "iteration range [%d, %d) outside [0, %d]", start_h, end_h,
+                    p->iterations);
+    if (use_graph && end_h > start_h) {
+        std::vector<uint64_t> key = graph_key(p, start_h, end_h, pos_dev);
+        if (!kh->gexec || key != kh->gkey) {
+            if (kh->gexec) {
+                (void)hipGraphExecDestroy(kh->gexec);
+                kh->gexec = nullptr;
+            }
+            hipStream_t cs = capture_stream(kh->device);
+            if (!cs) return fail(GILA_EDEVICE, "cannot create capture stream");
+            GILA_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+            const int rc = enqueue_run(kh, p, start_h, end_h, pos_dev, cs);
+            hipGraph_t graph = nullptr;
+            const hipError_t ee = hipStreamEndCapture(cs, &graph);
+            if (rc != GILA_OK) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return rc;
+            }
+            if (ee != hipSuccess)
+                return fail(GILA_EDEVICE, "graph capture: %s", hipGetErrorString(ee));
+            const hipError_t ie = hipGraphInstantiate(&kh->gexec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (ie != hipSuccess) {
+                kh->gexec = nullptr;
+                return fail(GILA_EDEVICE, "graph instantiate: %s", hipGetErrorString(ie));
+            }
+            kh->gkey = key;
+        }
+        GILA_HIP(hipGraphLaunch(kh->gexec, stream));
+    } else {
+        GILA_TRY(enqueue_run(kh, p, start_h, end_h, pos_dev, stream));
+    }
+    Ctl c{};
+    GILA_HIP(hipMemcpyAsync(&c, kh->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
+    GILA_HIP(hipStreamSynchronize(stream));
+    if (kh->nblocks == 0) c.iters_run = end_h - start_h;  // nothing can move
+    if (out) to_stats(c, out);
+    return GILA_OK;
+}
+
+}  // namespace gila
+
+using namespace gila;
+
+extern "C" {
+
+int gila_init_positions(int32_t n, uint64_t seed, double width, double height, int32_t precision,
+                        void* pos_dev, void* stream) {
+    clear_error();
+    if (n < 0) return fail(GILA_EINVAL, "n must be >= 0");
+    if (n > 0 && !pos_dev) return fail(GILA_EINVAL, "pos_dev is NULL");
+    if (!(width >= 0.0) || !(height >= 0.0) || !std::isfinite(width) || !std::isfinite(height))
+        return fail(GILA_EINVAL, "frame must be finite and >= 0");
+    if (n == 0) return GILA_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const int g = grid_for(n);
+    switch (precision) {
+        case GILA_FP64:
+            hipLaunchKernelGGL(init_positions_kernel<double2>, dim3(g), dim3(kBlock), 0, s, n,
+                               seed, width, height, (double2*)pos_dev);
+            break;
+        case GILA_FP32:
+        case GILA_FP32_KAHAN:
+            hipLaunchKernelGGL(init_positions_kernel<float2>, dim3(g), dim3(kBlock), 0, s, n,
+                               seed, width, height, (float2*)pos_dev);
+            break;
+        default: return fail(GILA_EINVAL, "unknown precision %d", precision);
+    }
+    GILA_HIP(hipGetLastError());
+    return GILA_OK;
+}
+
+int gila_step(const gila_khop* kh_c, const gila_params* params, int32_t h, void* pos_dev,
+              double* force_dev, double* disp_dev, void* stream, gila_stats* out) {
+    clear_error();
+    gila_khop* kh = const_cast<gila_khop*>(kh_c);
+    if (!kh) return fail(GILA_EINVAL, "handle is NULL");
+    GILA_TRY(check_params(params, true));
+    if (h < 0 || h >= params->iterations)
+        return fail(GILA_EINVAL, "h = %d outside [0, %d)", h, params->iterations);
+    if (kh->n > 0 && !pos_dev) return fail(GILA_EINVAL, "pos_dev is NULL");
+    if ((force_dev == nullptr) != (disp_dev == nullptr))
+        return fail(GILA_EINVAL, "force_dev and disp_dev must both be set or both NULL");
+    std::lock_guard<std::mutex> lk(kh->mu);
+    DeviceGuard dg(kh->device);
+    hipStream_t s = (hipStream_t)stream;
+    if (force_dev && kh->n > 0) {
+        // isolated vertices feel no force and do not move
+        GILA_HIP(hipMemsetAsync(force_dev, 0, sizeof(double) * 2 * kh->n, s));
+        GILA_HIP(hipMemsetAsync(disp_dev, 0, sizeof(double) * 2 * kh->n, s));
+    }
+    hipLaunchKernelGGL(reset_ctl_kernel, dim3(1), dim3(1), 0, s, kh->ctl);
+    GILA_HIP(hipGetLastError());
+    GILA_TRY(launch_permute_in(kh, params->precision, pos_dev, s));
+    StepArgs a = base_args(kh, params);
+    a.check_stop = 0;
+    a.pos_cur = kh->pos[0];
+    a.pos_next = kh->pos[1];
+    a.t = params->temperature[h];
+    a.F_out = force_dev;
+    a.D_out = disp_dev;
+    GILA_TRY(launch_step(kh, params->precision, a, s));
+    GILA_TRY(launch_permute_out(kh, params->precision, pos_dev, s));
+    if (out) {
+        Ctl c{};
+        GILA_HIP(hipMemcpyAsync(&c, kh->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+        GILA_HIP(hipStreamSynchronize(s));
+        if (kh->nblocks == 0) c.iters_run = 1;
+        to_stats(c, out);
+    }
+    return GILA_OK;
+}
+
+int gila_run(const gila_khop* kh_c, const gila_params* params, int32_t start_h, int32_t end_h,
+             void* pos_dev, void* stream, gila_stats* out) {
+    clear_error();
+    gila_khop* kh = const_cast<gila_khop*>(kh_c);
+    if (!kh) return fail(GILA_EINVAL, "handle is NULL");
+    GILA_TRY(check_params(params, true));
+    std::lock_guard<std::mutex> lk(kh->mu);
+    DeviceGuard dg(kh->device);
+    const char* env = getenv("GILA_NO_GRAPH");
+    const bool use_graph = !(env && env[0] == '1');
+    return run_iterations(kh, params, start_h, end_h, pos_dev, (hipStream_t)stream, out,
+                          use_graph);
+}
+
+int gila_layout(const gila_csr* g_dev, int32_t k, const gila_params* params, void* pos_dev,
+                void* stream, gila_stats* out) {
+    clear_error();
+    GILA_TRY(check_params(params, true));
+    gila_khop* kh = nullptr;
+    GILA_TRY(gila_build_khop(g_dev, k, stream, &kh));
+    int rc;
+    {
+        std::lock_guard<std::mutex> lk(kh->mu);
+        rc = run_iterations(kh, params, 0, params->iterations, pos_dev, (hipStream_t)stream, out,
+                            false);
+    }
+    gila_khop_free(kh);
+    return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,289 @@
+"""Thin ctypes binding of libgila (``include/gila.h``).
+
+Argument marshalling only: every step of the layout runs in the library's HIP
+kernels.  Device buffers are torch tensors on a ROCm device (torch is used for
+device memory and the current stream only); host buffers are numpy arrays.
+Importing this module loads ``libgila.so`` and raises if it has not been
+built -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgila.so")
+
+GILA_OK = 0
+GILA_EINVAL = -1
+GILA_ENOMEM = -2
+GILA_EDEVICE = -3
+GILA_EAGAIN = -4
+GILA_ECANCELED = -5
+GILA_EUNSUPPORTED = -6
+
+FP64 = 0
+FP32 = 1
+FP32_KAHAN = 2
+
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp32_kahan": FP32_KAHAN}
+
+
+class GilaError(RuntimeError):
+    def __init__(self, code: int, where: str, message: str):
+        super().__init__(f"{where}: {message} (status {code})")
+        self.code = code
+
+
+class Csr(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int64),
+                ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p)]
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("ideal_length", ctypes.c_double),
+                ("iterations", ctypes.c_int32), ("temperature", ctypes.POINTER(ctypes.c_double)),
+                ("stop_fraction", ctypes.c_double), ("stop_displacement", ctypes.c_double)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("iterations_run", ctypes.c_int32), ("stopped", ctypes.c_int32),
+                ("moved", ctypes.c_int64), ("max_disp", ctypes.c_double),
+                ("energy", ctypes.c_double), ("coincident", ctypes.c_int64)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(f"libgila.so not built at {path}: run `python -m paper_1606_02162_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64, u64, dbl = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64,
+                              ctypes.c_double)
+    P = ctypes.POINTER
+    sig = {
+        "gila_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+        "gila_last_error": (ctypes.c_char_p, []),
+        "gila_version": (ctypes.c_int, []),
+        "gila_build_khop": (ctypes.c_int, [P(Csr), i32, vp, P(vp)]),
+        "gila_khop_info": (ctypes.c_int, [vp, P(i32), P(i32), P(i64), P(i32), P(i64)]),
+        "gila_khop_export": (ctypes.c_int, [vp, vp, vp]),
+        "gila_khop_export_rows": (ctypes.c_int, [vp, i64, vp, vp, vp]),
+        "gila_khop_free": (None, [vp]),
+        "gila_init_positions": (ctypes.c_int, [i32, u64, dbl, dbl, i32, vp, vp]),
+        "gila_step": (ctypes.c_int, [vp, P(_Params), i32, vp, vp, vp, vp, P(Stats)]),
+        "gila_run": (ctypes.c_int, [vp, P(_Params), i32, i32, vp, vp, P(Stats)]),
+        "gila_layout": (ctypes.c_int, [P(Csr), i32, P(_Params), vp, vp, P(Stats)]),
+        "gila_batch_build": (ctypes.c_int, [P(Csr), i32, P(i32), vp, P(vp)]),
+        "gila_batch_run": (ctypes.c_int, [vp, P(_Params), P(vp), vp, P(Stats)]),
+        "gila_batch_info": (ctypes.c_int, [vp, P(i32), P(i64), P(i64)]),
+        "gila_batch_free": (None, [vp]),
+        "gila_layout_batch": (ctypes.c_int, [P(Csr), i32, P(i32), P(_Params), P(vp), vp,
+                                             P(Stats)]),
+        "gila_server_create": (ctypes.c_int, [i32, i64, i32, P(vp)]),
+        "gila_submit": (ctypes.c_int, [vp, P(Csr), i32, P(_Params), vp, P(u64)]),
+        "gila_poll": (ctypes.c_int, [vp, u64, vp, P(Stats)]),
+        "gila_wait": (ctypes.c_int, [vp, u64, vp, P(Stats)]),
+        "gila_cancel": (ctypes.c_int, [vp, u64]),
+        "gila_server_info": (ctypes.c_int, [vp, P(i64), P(i64), P(i32), P(i64)]),
+        "gila_server_destroy": (None, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = load_library()
+
+
+def lib() -> ctypes.CDLL:
+    return _lib
+
+
+def _check(rc: int, where: str):
+    if rc != GILA_OK:
+        msg = _lib.gila_last_error().decode(errors="replace") or _lib.gila_strerror(rc).decode()
+        raise GilaError(rc, where, msg)
+
+
+def _stream(stream=None) -> int:
+    if stream is not None:
+        return int(getattr(stream, "cuda_stream", stream))
+    import torch
+    return int(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t) -> int:
+    if t is None:
+        return 0
+    return int(t.data_ptr())
+
+
+# ---------------------------------------------------------------- schedules
+def paper_schedule(n_vertices: float, aspect: float, ideal_length: float,
+                   iterations: int) -> np.ndarray:
+    """Cap of Section 5.1: sqrt((n / a) d) 0.93^h, h = 0 .. iterations-1."""
+    base = math.sqrt(n_vertices / aspect * ideal_length)
+    return base * np.power(0.93, np.arange(iterations, dtype=np.float64))
+
+
+def linear_schedule(t0: float, iterations: int) -> np.ndarray:
+    """t0 - t0 h / iterations, h = 0 .. iterations-1 (t0 down to t0/iterations)."""
+    h = np.arange(iterations, dtype=np.float64)
+    return t0 - (t0 * h) / iterations
+
+
+# ---------------------------------------------------------------- params
+@dataclass
+class LayoutParams:
+    temperature: np.ndarray
+    ideal_length: float = 20.0 + math.sqrt(800.0)
+    precision: int = FP32_KAHAN
+    stop_fraction: float = 0.0
+    stop_displacement: float = 0.01
+    _keep: list = field(default_factory=list, repr=False)
+
+    @property
+    def iterations(self) -> int:
+        return int(np.asarray(self.temperature).size)
+
+    def as_struct(self) -> _Params:
+        t = np.ascontiguousarray(self.temperature, dtype=np.float64)
+        self._keep = [t]
+        p = _Params()
+        p.precision = int(self.precision)
+        p.ideal_length = float(self.ideal_length)
+        p.iterations = int(t.size)
+        p.temperature = t.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if t.size else None
+        p.stop_fraction = float(self.stop_fraction)
+        p.stop_displacement = float(self.stop_displacement)
+        return p
+
+
+def position_dtype(precision: int):
+    import torch
+    return torch.float64 if precision == FP64 else torch.float32
+
+
+def make_csr(row_ptr, col_idx, n: int | None = None) -> Csr:
+    """CSR descriptor over torch device tensors (or numpy host arrays)."""
+    if n is None:
+        n = int(row_ptr.shape[0]) - 1
+    c = Csr()
+    c.n = n
+    c.nnz = int(col_idx.shape[0])
+    if isinstance(row_ptr, np.ndarray):
+        c.row_ptr = row_ptr.ctypes.data
+        c.col_idx = col_idx.ctypes.data
+    else:
+        c.row_ptr = _ptr(row_ptr)
+        c.col_idx = _ptr(col_idx)
+    return c
+
+
+def to_device_csr(graph, device="cuda"):
+    """Upload an ``inputs.Graph`` to device tensors (row_ptr int64, col_idx int32)."""
+    import torch
+    rp = torch.from_numpy(np.ascontiguousarray(graph.row_ptr, dtype=np.int64)).to(device)
+    ci = torch.from_numpy(np.ascontiguousarray(graph.col_idx, dtype=np.int32)).to(device)
+    return rp, ci
+
+
+# ---------------------------------------------------------------- k-hop handle
+class KHop:
+    """Device k-neighbourhood lists of one graph (gila_build_khop)."""
+
+    def __init__(self, row_ptr, col_idx, k: int, stream=None):
+        self._h = ctypes.c_void_p()
+        self._csr = make_csr(row_ptr, col_idx)
+        _check(_lib.gila_build_khop(ctypes.byref(self._csr), int(k), _stream(stream),
+                                    ctypes.byref(self._h)), "gila_build_khop")
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> dict:
+        n, k, na = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        P, b = ctypes.c_int64(), ctypes.c_int64()
+        _check(_lib.gila_khop_info(self._h, ctypes.byref(n), ctypes.byref(k), ctypes.byref(P),
+                                   ctypes.byref(na), ctypes.byref(b)), "gila_khop_info")
+        return {"n": n.value, "k": k.value, "total_pairs": P.value, "n_active": na.value,
+                "device_bytes": b.value}
+
+    def export(self):
+        inf = self.info()
+        ptr = np.zeros(inf["n"] + 1, dtype=np.int64)
+        idx = np.zeros(max(inf["total_pairs"], 1), dtype=np.int32)
+        _check(_lib.gila_khop_export(self._h, ptr.ctypes.data, idx.ctypes.data),
+               "gila_khop_export")
+        return ptr, idx[: inf["total_pairs"]]
+
+    def export_rows(self, verts):
+        v = np.ascontiguousarray(verts, dtype=np.int32)
+        ptr = np.zeros(v.size + 1, dtype=np.int64)
+        _check(_lib.gila_khop_export_rows(self._h, v.size, v.ctypes.data, ptr.ctypes.data, None),
+               "gila_khop_export_rows")
+        idx = np.zeros(max(int(ptr[-1]), 1), dtype=np.int32)
+        _check(_lib.gila_khop_export_rows(self._h, v.size, v.ctypes.data, ptr.ctypes.data,
+                                          idx.ctypes.data), "gila_khop_export_rows")
+        return ptr, idx[: int(ptr[-1])]
+
+    def free(self):
+        if self._h:
+            _lib.gila_khop_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def build_khop(row_ptr, col_idx, k: int, stream=None) -> KHop:
+    return KHop(row_ptr, col_idx, k, stream)
+
+
+def init_positions(n: int, seed: int, width: float, height: float, precision: int, out,
+                   stream=None):
+    _check(_lib.gila_init_positions(int(n), int(seed) & 0xFFFFFFFFFFFFFFFF, float(width),
+                                    float(height), int(precision), _ptr(out), _stream(stream)),
+           "gila_init_positions")
+    return out
+
+
+def step(kh: KHop, params: LayoutParams, h: int, pos, force=None, disp=None,
+         stream=None) -> Stats:
+    st = Stats()
+    p = params.as_struct()
+    _check(_lib.gila_step(kh.handle, ctypes.byref(p), int(h), _ptr(pos), _ptr(force), _ptr(disp),
+                          _stream(stream), ctypes.byref(st)), "gila_step")
+    return st
+
+
+def run(kh: KHop, params: LayoutParams, pos, start_h: int = 0, end_h: int | None = None,
+        stream=None) -> Stats:
+    st = Stats()
+    p = params.as_struct()
+    if end_h is None:
+        end_h = params.iterations
+    _check(_lib.gila_run(kh.handle, ctypes.byref(p), int(start_h), int(end_h), _ptr(pos),
+                         _stream(stream), ctypes.byref(st)), "gila_run")
+    return st
+
+
+def layout(row_ptr, col_idx, k: int, params: LayoutParams, pos, stream=None) -> Stats:
+    st = Stats()
+    csr = make_csr(row_ptr, col_idx)
+    p = params.as_struct()
+    _check(_lib.gila_layout(ctypes.byref(csr), int(k), ctypes.byref(p), _ptr(pos),
+                            _stream(stream), ctypes.byref(st)), "gila_layout")
+    return st

@@ -1,0 +1,105 @@
+"""Host-only checks of the C ABI: the built library loads, exports every
+function that include/gila.h declares, and rejects bad arguments before any
+device work (these calls never reach the GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gila.h")
+LIB = os.path.join(ROOT, "paper_1606_02162_amd", "libgila.so")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gila_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libgila.so is not built; run `python -m paper_1606_02162_amd.build`")
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for required in ("gila_build_khop", "gila_step", "gila_run", "gila_layout", "gila_submit",
+                     "gila_poll", "gila_layout_batch", "gila_khop_export"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    missing = [n for n in _declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_host_only_calls(lib):
+    lib.gila_strerror.restype = ctypes.c_char_p
+    lib.gila_last_error.restype = ctypes.c_char_p
+    assert lib.gila_version() >= 10000
+    assert lib.gila_strerror(-1) == b"invalid argument or malformed graph"
+    assert lib.gila_strerror(0) == b"ok"
+
+
+def test_argument_validation_before_device_work():
+    from paper_1606_02162_amd import gila
+    L = gila.lib()
+    out = ctypes.c_void_p()
+    csr = gila.Csr()
+    csr.n = 4
+    csr.nnz = 2
+    # k < 1
+    assert L.gila_build_khop(ctypes.byref(csr), 0, None, ctypes.byref(out)) == gila.GILA_EINVAL
+    assert b"k must be" in L.gila_last_error()
+    # null graph / null out
+    assert L.gila_build_khop(None, 2, None, ctypes.byref(out)) == gila.GILA_EINVAL
+    assert L.gila_build_khop(ctypes.byref(csr), 2, None, None) == gila.GILA_EINVAL
+    # null row_ptr with n > 0
+    assert L.gila_build_khop(ctypes.byref(csr), 2, None, ctypes.byref(out)) == gila.GILA_EINVAL
+    # negative n
+    csr.n = -1
+    assert L.gila_build_khop(ctypes.byref(csr), 2, None, ctypes.byref(out)) == gila.GILA_EINVAL
+    # null handles
+    assert L.gila_khop_info(None, None, None, None, None, None) == gila.GILA_EINVAL
+    assert L.gila_run(None, None, 0, 0, None, None, None) == gila.GILA_EINVAL
+    assert L.gila_step(None, None, 0, None, None, None, None, None) == gila.GILA_EINVAL
+    # init positions: negative n, bad precision
+    assert L.gila_init_positions(-1, 0, 1.0, 1.0, 1, None, None) == gila.GILA_EINVAL
+    assert L.gila_init_positions(0, 0, 1.0, 1.0, 1, None, None) == gila.GILA_OK
+
+
+def test_params_validation():
+    import numpy as np
+    from paper_1606_02162_amd import gila
+    L = gila.lib()
+    csr = gila.Csr()
+    csr.n = 2
+    csr.nnz = 2
+    bad = [
+        gila.LayoutParams(temperature=np.ones(3), ideal_length=-1.0),
+        gila.LayoutParams(temperature=np.array([1.0, -2.0])),
+        gila.LayoutParams(temperature=np.ones(2), precision=7),
+        gila.LayoutParams(temperature=np.array([1.0, float("nan")])),
+        gila.LayoutParams(temperature=np.ones(2), stop_fraction=-0.1),
+    ]
+    st = gila.Stats()
+    for p in bad:
+        s = p.as_struct()
+        rc = L.gila_layout(ctypes.byref(csr), 2, ctypes.byref(s), None, None, ctypes.byref(st))
+        assert rc == gila.GILA_EINVAL, p
+
+
+def test_schedules_match_closed_forms():
+    import math
+    import numpy as np
+    from paper_1606_02162_amd import gila
+    t = gila.linear_schedule(100.0, 100)
+    assert np.array_equal(t, 100.0 - np.arange(100))
+    d = 20 + math.sqrt(800)
+    p = gila.paper_schedule(1000, 1.0, d, 10)
+    assert abs(p[0] ** 2 - 1000 * d) < 1e-9
+    assert np.allclose(p[1:] / p[:-1], 0.93, rtol=1e-14, atol=0)

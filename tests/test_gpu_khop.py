@@ -1,0 +1,121 @@
+"""GPU parity of the k-hop lists N_v(k) (Section 4.5): bit-exact against the
+oracle's BFS, on small graphs of every family (every row) and at the full
+benchmark sizes (exact row lengths for every vertex, sampled rows in full)."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from gpu_common import oracle_rows, require_gpu, small_graph_suite
+from paper_1606_02162_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def G():
+    require_gpu()
+    from paper_1606_02162_amd import gila
+    return gila
+
+
+def _build(G, g, k):
+    rp, ci = G.to_device_csr(g)
+    return G.build_khop(rp, ci, k)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4])
+def test_small_graphs_bit_exact(G, k):
+    for g in small_graph_suite():
+        if k == 4 and g.n > 3000:
+            continue
+        print(f"khop {g.name} n={g.n} k={k}", flush=True)
+        kh = _build(G, g, k)
+        ptr, idx = kh.export()
+        optr, oidx = oracle_rows(g, k)
+        assert np.array_equal(ptr, optr), g.name
+        assert np.array_equal(idx, oidx), g.name
+        inf = kh.info()
+        assert inf["total_pairs"] == int(optr[-1])
+        assert inf["n_active"] == int((np.diff(g.row_ptr) > 0).sum())
+        kh.free()
+
+
+def test_grid32_config_total(G):
+    g = inputs.grid_graph(32, 32)
+    kh = _build(G, g, 2)
+    assert kh.info()["total_pairs"] == 11652
+
+
+def test_empty_and_degenerate_graphs(G):
+    for g in (inputs.to_csr(0, [], []), inputs.to_csr(1, [], []), inputs.to_csr(7, [], []),
+              inputs.path_graph(2)):
+        for k in (1, 3):
+            if g.n == 0:
+                import torch
+                rp = torch.zeros(1, dtype=torch.int64, device="cuda")
+                ci = torch.zeros(0, dtype=torch.int32, device="cuda")
+                kh = G.build_khop(rp, ci, k)
+            else:
+                kh = _build(G, g, k)
+            ptr, idx = kh.export()
+            optr, oidx = oracle_rows(g, k)
+            assert np.array_equal(ptr, optr) and np.array_equal(idx, oidx)
+
+
+def _bad_csr(G, rp, ci, k=2):
+    import torch
+    rpd = torch.tensor(rp, dtype=torch.int64, device="cuda")
+    cid = torch.tensor(ci, dtype=torch.int32, device="cuda")
+    with pytest.raises(G.GilaError) as e:
+        G.build_khop(rpd, cid, k)
+    assert e.value.code == G.GILA_EINVAL
+    return str(e.value)
+
+
+def test_malformed_csr_rejected(G):
+    assert "not symmetric" in _bad_csr(G, [0, 1, 2, 2], [1, 2])             # 0->1, 1->2 only
+    assert "self-loop" in _bad_csr(G, [0, 2, 3], [0, 1, 0])
+    assert "ascending" in _bad_csr(G, [0, 2, 3, 4], [2, 1, 0, 0])
+    assert "out of range" in _bad_csr(G, [0, 1, 2], [5, 0])
+    _bad_csr(G, [0, 2, 1], [1, 0])                                           # non-monotone
+    _bad_csr(G, [1, 2, 2], [1, 0])                                           # row_ptr[0] != 0
+    with pytest.raises(G.GilaError):
+        _build(G, inputs.path_graph(4), 0)
+
+
+@pytest.mark.parametrize("which", ["ba100k_k3", "rmat18_k2"])
+def test_full_size_lists(G, which):
+    """Full benchmark graphs: every row length exact, 3000 sampled rows exact."""
+    if which == "ba100k_k3":
+        g, k = inputs.barabasi_albert(100000, 3, seed=2), 3
+    else:
+        g, k = inputs.rmat(18, 4, 0.57, 0.19, 0.19, seed=3), 2
+    print(f"full-size khop {which}", flush=True)
+    kh = _build(G, g, k)
+    all_v = np.arange(g.n, dtype=np.int32)
+    # exact sizes of every row (oracle count pass over all vertices)
+    import oracle
+    sizes = np.zeros(g.n, dtype=np.int64)
+    lib = oracle._load()
+    rc = lib.orc_khop_count(g.n, g.row_ptr, g.col_idx, k, g.n, None, sizes)
+    assert rc == 0
+    gptr = np.zeros(g.n + 1, dtype=np.int64)
+    L = G.lib()
+    assert L.gila_khop_export_rows(kh.handle, g.n, all_v.ctypes.data, gptr.ctypes.data,
+                                   None) == 0
+    assert np.array_equal(np.diff(gptr), sizes)
+    assert kh.info()["total_pairs"] == int(sizes.sum())
+    rng = np.random.default_rng(7)
+    verts = np.concatenate([np.argsort(-sizes)[:20], rng.integers(0, g.n, 3000)]).astype(np.int32)
+    sp, si = kh.export_rows(verts)
+    op, oi = oracle_rows(g, k, verts=verts)
+    assert np.array_equal(sp, op)
+    assert np.array_equal(si, oi)
+
+
+def test_build_is_deterministic(G):
+    g = inputs.barabasi_albert(5000, 3, seed=9)
+    a = _build(G, g, 3).export()
+    b = _build(G, g, 3).export()
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])

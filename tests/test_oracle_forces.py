@@ -298,3 +298,23 @@ def test_linear_schedule_exact():
 def test_paper_ideal_length_constant():
     # d = N_s + sqrt(N_h^2 + N_w^2), all three = 20 (Section 5.1)
     assert abs(inputs.PAPER_IDEAL_LENGTH - 48.284271247461902) < 1e-12
+
+
+def test_oracle_trajectory_sensitivity():
+    """Conditioning of whole trajectories (why GPU/oracle parity is checked
+    per step): perturbing one coordinate of the 32x32 grid's start by one ulp
+    changes the oracle's own layout by ~1e-15 of the extent at h = 20 but by
+    more than 1e-5 at h = 100."""
+    g = inputs.grid_graph(32, 32)
+    kp, ki = _kh(g, 2)
+    temps = oracle.linear_schedule(100.0, 100)
+    x0 = inputs.uniform_positions(g.n, seed=0, width=1000.0)
+    x1 = x0.copy()
+    x1[5, 0] = np.nextafter(x1[5, 0], 2000.0)
+    res = {}
+    for H in (20, 100):
+        a, _, _ = oracle.layout(g.n, g.row_ptr, g.col_idx, kp, ki, 10.0, temps, x0, h_end=H)
+        b, _, _ = oracle.layout(g.n, g.row_ptr, g.col_idx, kp, ki, 10.0, temps, x1, h_end=H)
+        res[H] = np.abs(a - b).max() / np.ptp(a, axis=0).max()
+    assert res[20] < 1e-13
+    assert res[100] > 1e-5
