@@ -21,97 +21,9 @@
 #include <algorithm>
 #include <cmath>
 
-#include "device_util.h"
-#include "gila_internal.h"
+#include "iteration.h"
 
 namespace gila {
-
-template <int PREC>
-struct Prec;
-
-template <>
-struct Prec<GILA_FP64> {
-    using real = double;
-    using vec2 = double2;
-    static constexpr bool kahan = false;
-};
-template <>
-struct Prec<GILA_FP32> {
-    using real = float;
-    using vec2 = float2;
-    static constexpr bool kahan = false;
-};
-template <>
-struct Prec<GILA_FP32_KAHAN> {
-    using real = float;
-    using vec2 = float2;
-    static constexpr bool kahan = true;
-};
-
-__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-
-// Lane accumulator: plain or Kahan-compensated sum of 2-vectors.
-template <class R, bool KAHAN>
-struct Acc {
-    R sx = 0, sy = 0, cx = 0, cy = 0;
-    __device__ __forceinline__ void add(R tx, R ty) {
-        if constexpr (KAHAN) {
-            const R yx = tx - cx;
-            const R ux = sx + yx;
-            cx = (ux - sx) - yx;
-            sx = ux;
-            const R yy = ty - cy;
-            const R uy = sy + yy;
-            cy = (uy - sy) - yy;
-            sy = uy;
-        } else {
-            sx += tx;
-            sy += ty;
-        }
-    }
-    __device__ __forceinline__ double x() const {
-        return KAHAN ? (double)sx - (double)cx : (double)sx;
-    }
-    __device__ __forceinline__ double y() const {
-        return KAHAN ? (double)sy - (double)cy : (double)sy;
-    }
-};
-
-// Repulsion term of neighbour position p on v at (xv, yv): (x_v - x_u) d^2 / delta^2.
-template <class P>
-__device__ __forceinline__ void repulse(typename P::real xv, typename P::real yv,
-                                        typename P::vec2 p, typename P::real d2,
-                                        Acc<typename P::real, P::kahan>& acc, int& coinc) {
-    using R = typename P::real;
-    const R dx = xv - p.x;
-    const R dy = yv - p.y;
-    const R dd = dx * dx + dy * dy;
-    R s;
-    if constexpr (sizeof(R) == 4) {
-        s = dd > R(0) ? d2 * fast_rcp(dd) : R(0);
-    } else {
-        s = dd > R(0) ? d2 / dd : R(0);
-    }
-    coinc += (dd == R(0));
-    acc.add(dx * s, dy * s);
-}
-
-// Attraction term: (x_u - x_v) delta / d.
-template <class P>
-__device__ __forceinline__ void attract(typename P::real xv, typename P::real yv,
-                                        typename P::vec2 p, typename P::real inv_d,
-                                        Acc<typename P::real, P::kahan>& acc) {
-    using R = typename P::real;
-    const R dx = p.x - xv;
-    const R dy = p.y - yv;
-    R s;
-    if constexpr (sizeof(R) == 4) {
-        s = sqrt(dx * dx + dy * dy) * inv_d;
-    } else {
-        s = sqrt(dx * dx + dy * dy) / inv_d;  // inv_d carries d itself in double
-    }
-    acc.add(dx * s, dy * s);
-}
 
 // Partial force of one vertex over lanes lane0, lane0+STRIDE, ... of its rows.
 template <class P, int STRIDE>
@@ -124,7 +36,7 @@ __device__ __forceinline__ void vertex_partial(const StepArgs& a, int32_t v, int
     const V xv = pos[v];
     xv_out = xv;
     const R d2 = (R)(a.d * a.d);
-    const R inv_d = sizeof(R) == 4 ? (R)(1.0 / a.d) : (R)a.d;
+    const R inv_d = attract_param<R>(a.d);
     const int64_t kb = a.kptr[v], ke = a.kptr[v + 1];
     int64_t e = kb + lane0;
     // four independent gathers in flight per lane
@@ -145,45 +57,11 @@ __device__ __forceinline__ void vertex_partial(const StepArgs& a, int32_t v, int
         attract<P>(xv.x, xv.y, pos[a.ci[j]], inv_d, acc);
 }
 
-// Cap, move and record one vertex; returns the vertex's statistics.
-template <class P>
-__device__ __forceinline__ void finish_vertex(const StepArgs& a, int32_t v, typename P::vec2 xv,
-                                              double fx, double fy, double& energy, double& maxd,
-                                              int64_t& moved) {
-    using V = typename P::vec2;
-    using R = typename P::real;
-    const double norm = sqrt(fx * fx + fy * fy);
-    double dx = 0.0, dy = 0.0;
-    if (norm > 0.0) {
-        const double len = norm < a.t ? norm : a.t;
-        dx = fx * (len / norm);
-        dy = fy * (len / norm);
-    }
-    V nx;
-    nx.x = (R)((double)xv.x + dx);
-    nx.y = (R)((double)xv.y + dy);
-    reinterpret_cast<V*>(a.pos_next)[v] = nx;
-    if (a.F_out) {
-        const int32_t o = a.perm[v];
-        a.F_out[2 * (int64_t)o] = fx;
-        a.F_out[2 * (int64_t)o + 1] = fy;
-        a.D_out[2 * (int64_t)o] = dx;
-        a.D_out[2 * (int64_t)o + 1] = dy;
-    }
-    const double dl = sqrt(dx * dx + dy * dy);
-    energy += fx * fx + fy * fy;
-    maxd = dl > maxd ? dl : maxd;
-    moved += dl > a.stop_displacement ? 1 : 0;
-}
-
 template <int PREC, int LPV>
 __global__ __launch_bounds__(kBlock) void fr_step_kernel(StepArgs a) {
     using P = Prec<PREC>;
     using V = typename P::vec2;
     __shared__ double s_fx[kWaves], s_fy[kWaves];
-    __shared__ double s_e[kWaves], s_m[kWaves];
-    __shared__ int64_t s_mv[kWaves], s_c[kWaves];
-    __shared__ int s_last;
 
     if (a.ctl->stopped) return;  // the halting rule fired in an earlier iteration
 
@@ -234,89 +112,7 @@ __global__ __launch_bounds__(kBlock) void fr_step_kernel(StepArgs a) {
         }
     }
 
-    // workgroup statistics in a fixed order
-    const double we = wave_sum(energy);
-    const double wm = wave_max(maxd);
-    const int64_t wmv = wave_sum(moved);
-    const int64_t wc = wave_sum((int64_t)coinc);
-    if (lane == 0) {
-        s_e[w] = we;
-        s_m[w] = wm;
-        s_mv[w] = wmv;
-        s_c[w] = wc;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        Partial p;
-        p.energy = s_e[0];
-        p.max_disp = s_m[0];
-        p.moved = s_mv[0];
-        p.coincident = s_c[0];
-        for (int i = 1; i < kWaves; ++i) {
-            p.energy += s_e[i];
-            p.max_disp = s_m[i] > p.max_disp ? s_m[i] : p.max_disp;
-            p.moved += s_mv[i];
-            p.coincident += s_c[i];
-        }
-        a.partials[blockIdx.x] = p;
-        __threadfence();
-        const unsigned ticket = atomicAdd(&a.ctl->done_blocks, 1u);
-        s_last = (ticket == (unsigned)gridDim.x - 1u);
-    }
-    __syncthreads();
-    if (!s_last) return;
-
-    // last workgroup: reduce every partial in index order
-    __threadfence();
-    const volatile Partial* vp = a.partials;
-    double e = 0.0, m = 0.0;
-    int64_t mv = 0, c = 0;
-    for (int i = threadIdx.x; i < a.nblocks; i += kBlock) {
-        e += vp[i].energy;
-        const double x = vp[i].max_disp;
-        m = x > m ? x : m;
-        mv += vp[i].moved;
-        c += vp[i].coincident;
-    }
-    e = wave_sum(e);
-    m = wave_max(m);
-    mv = wave_sum(mv);
-    c = wave_sum(c);
-    if (lane == 0) {
-        s_e[w] = e;
-        s_m[w] = m;
-        s_mv[w] = mv;
-        s_c[w] = c;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        e = s_e[0];
-        m = s_m[0];
-        mv = s_mv[0];
-        c = s_c[0];
-        for (int i = 1; i < kWaves; ++i) {
-            e += s_e[i];
-            m = s_m[i] > m ? s_m[i] : m;
-            mv += s_mv[i];
-            c += s_c[i];
-        }
-        Ctl* ctl = a.ctl;
-        ctl->energy = e;
-        ctl->max_disp = m;
-        ctl->moved = mv;
-        ctl->coincident = c;
-        ctl->iters_run += 1;
-        if (a.check_stop && (double)mv < a.stop_fraction * (double)a.n_active) ctl->stopped = 1;
-        if (a.hist_slot >= 0) {
-            double* hrow = a.hist + 4 * (int64_t)a.hist_slot;
-            hrow[0] = e;
-            hrow[1] = m;
-            hrow[2] = (double)mv;
-            hrow[3] = (double)c;
-        }
-        ctl->done_blocks = 0u;
-        __threadfence();
-    }
+    end_iteration(a, energy, maxd, moved, (int64_t)coinc);
 }
 
 // ------------------------------------------------------------------ launch

@@ -75,6 +75,7 @@ struct Ctl {
     double max_disp;
     double energy;
     int64_t coincident;
+    int64_t coinc_pending;  // coincident pairs counted by the segment kernel, not yet published
 };
 
 // Per-workgroup partial statistics of one iteration.
@@ -109,6 +110,24 @@ struct StepArgs {
     Partial* partials;          // [nblocks]
     Ctl* ctl;
     double* hist;               // [slots][4]: energy, max_disp, moved, coincident
+    // segment-blocked path
+    int32_t nseg;
+    const double2* part;        // [nseg][n_active] per-segment partial forces
+};
+
+// Arguments of the segment kernel (one workgroup = one id segment x a row range).
+struct SegArgs {
+    int32_t na;                 // non-isolated vertices (rows)
+    int32_t seg;                // segment size S (vertex ids per segment)
+    const int4* wg;             // [grid] (segment, first row, end row, lanes per row)
+    const int64_t* kptr;        // [nseg * na + 1] k-hop slices, segment-major
+    const uint16_t* kidx;       // id - s*S of each k-hop entry
+    const int32_t* aptr;        // [nseg * na + 1] adjacency slices
+    const uint16_t* aidx;
+    const void* pos;            // positions of this iteration (internal ids)
+    double2* part;              // [nseg][na]
+    double d;
+    Ctl* ctl;
 };
 
 }  // namespace gila
@@ -134,9 +153,22 @@ struct gila_khop {
     // workspace
     void* pos[2] = {nullptr, nullptr};  // 16 B per vertex each
     gila::Partial* partials = nullptr;
+    int32_t partials_cap = 0;
     gila::Ctl* ctl = nullptr;
     double* hist = nullptr;
     int32_t hist_cap = 0;
+    // segment-blocked layout of the k-hop and adjacency lists (see segment.hip)
+    bool seg_ready = false;
+    int32_t seg = 0, nseg = 0;      // segment size and count
+    int64_t* sk_ptr = nullptr;      // [nseg * n_active + 1]
+    uint16_t* sk_idx = nullptr;     // [P]
+    int32_t* sa_ptr = nullptr;      // [nseg * n_active + 1]
+    uint16_t* sa_idx = nullptr;     // [nnz]
+    int4* seg_wg = nullptr;         // [seg_grid]
+    int32_t seg_grid = 0;
+    int32_t comb_grid = 0;
+    double2* part = nullptr;        // [nseg * n_active]
+    int32_t seg_precision = -1;     // precision the segment size was chosen for
     // cached HIP graph of the last gila_run call
     hipGraphExec_t gexec = nullptr;
     std::vector<uint64_t> gkey;
@@ -148,6 +180,14 @@ namespace gila {
 int launch_step(const gila_khop* kh, int precision, const StepArgs& a, hipStream_t s);
 int plan_iteration(gila_khop* kh, const std::vector<int64_t>& counts_internal,
                    const std::vector<int64_t>& rp_internal);
+// implemented in segment.hip
+int build_segments(gila_khop* kh, int precision, hipStream_t s);
+int launch_segment_step(const gila_khop* kh, int precision, const StepArgs& a, hipStream_t s);
+bool segment_path_enabled();
+int seg_size_for(int precision, int device);
+// implemented in layout.hip: one iteration on whichever path the handle is ready for
+int launch_iteration(const gila_khop* kh, int precision, const StepArgs& a, hipStream_t s);
+int prepare_precision(gila_khop* kh, int precision, hipStream_t s);
 // implemented in layout.hip
 int run_iterations(gila_khop* kh, const gila_params* p, int32_t start_h, int32_t end_h,
                    void* pos_dev, hipStream_t stream, gila_stats* out, bool use_graph);

@@ -294,6 +294,12 @@ static void free_khop(gila_khop* kh) {
     dfree(kh->partials);
     dfree(kh->ctl);
     dfree(kh->hist);
+    dfree(kh->sk_ptr);
+    dfree(kh->sk_idx);
+    dfree(kh->sa_ptr);
+    dfree(kh->sa_idx);
+    dfree(kh->seg_wg);
+    dfree(kh->part);
     delete kh;
 }
 
@@ -431,6 +437,29 @@ static int build_khop(const gila_csr* g, int32_t k, hipStream_t s, gila_khop** o
         GILA_HIP(hipGetLastError());
     }
 
+    // --- internal adjacency rows in ascending order (a k = 1 fill pass)
+    if (n_active > 0 && nnz > 0) {
+        int32_t* ci_sorted = nullptr;
+        GILA_TRY(dalloc_t(&ci_sorted, (size_t)nnz));
+        BfsArgs a{};
+        a.n = n;
+        a.k = 1;
+        a.nverts = n_active;
+        a.nwords = nwords;
+        a.rp = kh->rp;
+        a.ci = kh->ci;
+        a.kptr = kh->rp;
+        a.kidx = ci_sorted;
+        a.work = d_work;
+        const int rc = run_bfs(true, dev, s, a);
+        if (rc) {
+            dfree(ci_sorted);
+            return rc;
+        }
+        dfree(kh->ci);
+        kh->ci = ci_sorted;
+    }
+
     // --- fill pass on the internal graph (rows come out ascending)
     if (n_active > 0 && P > 0) {
         BfsArgs a{};
@@ -451,9 +480,17 @@ static int build_khop(const gila_csr* g, int32_t k, hipStream_t s, gila_khop** o
     GILA_TRY(dalloc_t(reinterpret_cast<double**>(&kh->pos[0]), 2 * (size_t)std::max(n, 1)));
     GILA_TRY(dalloc_t(reinterpret_cast<double**>(&kh->pos[1]), 2 * (size_t)std::max(n, 1)));
     GILA_TRY(dalloc_t(&kh->partials, (size_t)std::max(kh->nblocks, 1)));
+    kh->partials_cap = std::max(kh->nblocks, 1);
     GILA_TRY(dalloc_t(&kh->ctl, 1));
     GILA_HIP(hipMemsetAsync(kh->ctl, 0, sizeof(Ctl), s));
     GILA_HIP(hipStreamSynchronize(s));
+    // segment-blocked lists for FP32 positions (the common case); FP64 runs
+    // rebuild them for their own segment size on first use
+    if (segment_path_enabled()) {
+        const int src = build_segments(kh, GILA_FP32_KAHAN, s);
+        if (src != GILA_OK && src != GILA_EUNSUPPORTED) return src;
+        clear_error();
+    }
     kh->device_bytes = (int64_t)sizeof(int32_t) * 2 * n + sizeof(int64_t) * 2 * (n + 1) +
                        sizeof(int32_t) * (nnz + P) + 32 * (int64_t)n +
                        (int64_t)sizeof(Partial) * kh->nblocks + sizeof(int32_t) * (kh->nblocks + 1);

@@ -1,6 +1,8 @@
 // Iteration drivers: seeded placement, one step, a device-resident loop of
 // steps captured as a HIP graph, and the whole-layout entry point.
+#include <algorithm>
 #include <cmath>
+#include <cstdlib>
 
 #include "device_util.h"
 #include "gila_internal.h"
@@ -40,6 +42,7 @@ __global__ void reset_ctl_kernel(Ctl* ctl) {
     ctl->max_disp = 0.0;
     ctl->energy = 0.0;
     ctl->coincident = 0;
+    ctl->coinc_pending = 0;
 }
 
 // Caller positions -> internal buffer 0; isolated vertices (the tail of the
@@ -168,10 +171,32 @@ static int enqueue_run(gila_khop* kh, const gila_params* p, int32_t start_h, int
         a.pos_cur = kh->pos[j & 1];
         a.pos_next = kh->pos[(j + 1) & 1];
         a.t = p->temperature[h];
-        GILA_TRY(launch_step(kh, p->precision, a, s));
+        GILA_TRY(launch_iteration(kh, p->precision, a, s));
     }
     GILA_TRY(launch_permute_out(kh, p->precision, pos_dev, s));
     return GILA_OK;
+}
+
+int prepare_precision(gila_khop* kh, int precision, hipStream_t s) {
+    if (!segment_path_enabled()) return GILA_OK;
+    if (kh->seg_ready && kh->seg == seg_size_for(precision, kh->device)) return GILA_OK;
+    if (kh->gexec) {
+        (void)hipGraphExecDestroy(kh->gexec);
+        kh->gexec = nullptr;
+        kh->gkey.clear();
+    }
+    const int rc = build_segments(kh, precision, s);
+    if (rc == GILA_EUNSUPPORTED) {
+        clear_error();
+        return GILA_OK;  // the direct-gather kernel serves this graph
+    }
+    return rc;
+}
+
+int launch_iteration(const gila_khop* kh, int precision, const StepArgs& a, hipStream_t s) {
+    if (kh->seg_ready && segment_path_enabled() && kh->seg == seg_size_for(precision, kh->device))
+        return launch_segment_step(kh, precision, a, s);
+    return launch_step(kh, precision, a, s);
 }
 
 static std::vector<uint64_t> graph_key(const gila_params* p, int32_t start_h, int32_t end_h,
@@ -194,6 +219,7 @@ int run_iterations(gila_khop* kh, const gila_params* p, int32_t start_h, int32_t
     if (start_h < 0 || end_h < start_h || end_h > p->iterations)
         return fail(GILA_EINVAL, "iteration range [%d, %d) outside [0, %d]", start_h, end_h,
                     p->iterations);
+    GILA_TRY(prepare_precision(kh, p->precision, stream));
     if (use_graph && end_h > start_h) {
         std::vector<uint64_t> key = graph_key(p, start_h, end_h, pos_dev);
         if (!kh->gexec || key != kh->gkey) {
@@ -279,6 +305,7 @@ int gila_step(const gila_khop* kh_c, const gila_params* params, int32_t h, void*
     std::lock_guard<std::mutex> lk(kh->mu);
     DeviceGuard dg(kh->device);
     hipStream_t s = (hipStream_t)stream;
+    GILA_TRY(prepare_precision(kh, params->precision, s));
     if (force_dev && kh->n > 0) {
         // isolated vertices feel no force and do not move
         GILA_HIP(hipMemsetAsync(force_dev, 0, sizeof(double) * 2 * kh->n, s));
@@ -294,7 +321,7 @@ int gila_step(const gila_khop* kh_c, const gila_params* params, int32_t h, void*
     a.t = params->temperature[h];
     a.F_out = force_dev;
     a.D_out = disp_dev;
-    GILA_TRY(launch_step(kh, params->precision, a, s));
+    GILA_TRY(launch_iteration(kh, params->precision, a, s));
     GILA_TRY(launch_permute_out(kh, params->precision, pos_dev, s));
     if (out) {
         Ctl c{};

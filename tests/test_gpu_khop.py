@@ -75,7 +75,7 @@ def _bad_csr(G, rp, ci, k=2):
 
 def test_malformed_csr_rejected(G):
     assert "not symmetric" in _bad_csr(G, [0, 1, 2, 2], [1, 2])             # 0->1, 1->2 only
-    assert "self-loop" in _bad_csr(G, [0, 2, 3], [0, 1, 0])
+    assert "self-loop" in _bad_csr(G, [0, 2, 4, 4], [0, 1, 0, 1])
     assert "ascending" in _bad_csr(G, [0, 2, 3, 4], [2, 1, 0, 0])
     assert "out of range" in _bad_csr(G, [0, 1, 2], [5, 0])
     _bad_csr(G, [0, 2, 1], [1, 0])                                           # non-monotone

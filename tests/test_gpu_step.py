@@ -8,6 +8,8 @@ The displacement error e_D is reported, not gated: near equilibrium a capped
 move's direction is ill-conditioned, so FP32 per-term rounding shows up in it
 whatever the summation method.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -40,12 +42,33 @@ def _gpu_step(G, kh, params, h, pos_np):
     return (pos.double().cpu().numpy(), F.cpu().numpy(), D.cpu().numpy(), st)
 
 
+PATHS = {
+    "segment": {},                                   # LDS segments of 64 KB
+    "segment_tiny": {"GILA_SEG_BYTES": "2048"},      # 2 KB segments: many segments per graph
+    "direct": {"GILA_PATH": "direct"},               # direct global gathers
+}
+
+
+@pytest.fixture(params=list(PATHS))
+def path_env(request):
+    old = {k: os.environ.get(k) for k in ("GILA_PATH", "GILA_SEG_BYTES")}
+    for k in old:
+        os.environ.pop(k, None)
+    os.environ.update(PATHS[request.param])
+    yield request.param
+    for k, v in old.items():
+        if v is None:
+            os.environ.pop(k, None)
+        else:
+            os.environ[k] = v
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_kahan"])
-def test_single_step_small_suite(G, precision):
+def test_single_step_small_suite(G, precision, path_env):
     prec = G.PRECISIONS[precision]
     for g in small_graph_suite():
         for k in (1, 2, 3):
-            print(f"step {g.name} k={k} {precision}", flush=True)
+            print(f"step {g.name} k={k} {precision} {path_env}", flush=True)
             rp, ci = _dev(G, g)
             kh = G.build_khop(rp, ci, k)
             pos0 = inputs.uniform_positions(g.n, seed=11, width=1200.0)
@@ -118,14 +141,16 @@ def test_trajectory_sampled_steps_fp32(G, precision):
 
 
 @pytest.mark.parametrize("which", ["rmat18_k2", "ba100k_k3"])
-def test_full_size_step(G, which):
+def test_full_size_step(G, which, path_env):
     """Full benchmark graphs, FP32 + Kahan, first and a later step: whole
     force field against the oracle."""
     if which == "rmat18_k2":
         g, k, frame = inputs.rmat(18, 4, 0.57, 0.19, 0.19, seed=3), 2, 1200.0
     else:
         g, k, frame = inputs.barabasi_albert(100000, 3, seed=2), 3, 1e4
-    print(f"full-size step {which}", flush=True)
+    if path_env == "segment_tiny":
+        pytest.skip("tiny segments are exercised on the small suite")
+    print(f"full-size step {which} {path_env}", flush=True)
     rp, ci = _dev(G, g)
     kh = G.build_khop(rp, ci, k)
     optr, oidx = oracle_rows(g, k)
@@ -137,7 +162,7 @@ def test_full_size_step(G, which):
         x_g, F_g, D_g, st = _gpu_step(G, kh, params, h, x)
         x_o, F_o, D_o, so = oracle.step(g.n, g.row_ptr, g.col_idx, optr, oidx, d, temps[h], x)
         eF, ex, eD = rel_l2(F_g, F_o), pos_err(x_g, x_o), rel_l2(D_g, D_o)
-        print(f"{which} h={h} e_F={eF:.2e} e_x={ex:.2e} e_D={eD:.2e}", flush=True)
+        print(f"{which} {path_env} h={h} e_F={eF:.2e} e_x={ex:.2e} e_D={eD:.2e}", flush=True)
         assert eF <= 1e-5 and ex <= 1e-5
         assert st.coincident == so.coincident
         x = x_g
