@@ -61,6 +61,9 @@ def main() -> int:
     ap.add_argument("--scale", type=int, default=18)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=8)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy (three times) so that HBM "
+                         "traffic counters can be scaled against a known byte count")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -69,6 +72,16 @@ def main() -> int:
         return 2
 
     import torch
+
+    if args.calibrate_copy:
+        x = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "device copy", "bytes_read": x.numel() * 4,
+                          "bytes_written": y.numel() * 4, "launches": 3}))
+        return 0
 
     from paper_1606_02162_amd import gila, inputs
 

@@ -60,6 +60,45 @@ struct Acc {
     }
 };
 
+// Repulsion term (x_v - x_u) d^2 / delta^2 of a neighbour at p on v at (xv, yv)
+// (magnitude d^2 / delta, q = 1), returned in (tx, ty).  A coincident pair
+// (delta = 0) has dx = dy = 0; clamping delta^2 to a tiny positive value keeps
+// its scale finite, so its term is exactly 0.  The clamp changes nothing else:
+// any squared FP32 distance this small already overflows the force.  `mindd`
+// tracks the smallest delta^2 seen, so that rows holding a coincident pair can
+// be recounted exactly (rare) without a per-pair counter.
+template <class P>
+__device__ __forceinline__ void repulse_term(typename P::real xv, typename P::real yv,
+                                             typename P::vec2 p, typename P::real d2,
+                                             typename P::real& tx, typename P::real& ty,
+                                             typename P::real& mindd) {
+    using R = typename P::real;
+    const R dx = xv - p.x;
+    const R dy = yv - p.y;
+    const R dd = dx * dx + dy * dy;
+    mindd = fmin(mindd, dd);
+    R s;
+    if constexpr (sizeof(R) == 4) {
+        s = d2 * fast_rcp(fmaxf(dd, 1e-30f));
+    } else {
+        s = dd > R(0) ? d2 / dd : R(0);
+    }
+    tx = dx * s;
+    ty = dy * s;
+}
+
+// Number of pairs of a strided row walk whose points coincide.
+template <class V, class IDX, int STRIDE>
+__device__ __forceinline__ int count_coincident(V xv, const IDX* __restrict__ row, int len,
+                                                int lane0, const V* __restrict__ pos) {
+    int c = 0;
+    for (int e = lane0; e < len; e += STRIDE) {
+        const V p = pos[row[e]];
+        c += (xv.x == p.x && xv.y == p.y) ? 1 : 0;
+    }
+    return c;
+}
+
 // Repulsion on v (at xv, yv) from a neighbour at p: (x_v - x_u) d^2 / delta^2
 // (magnitude d^2 / delta, q = 1).  A coincident pair adds nothing and is counted.
 template <class P>

@@ -1,10 +1,15 @@
 // Segment-blocked iteration: every neighbour gather comes from LDS.
 //
 // Internal vertex ids are split into segments of S consecutive ids (S
-// positions fill 64 KB of LDS).  Each k-hop row (and adjacency row) of an
-// active vertex v is cut into per-segment slices; slice (s, v) holds the ids
-// of N_v(k) (resp. adj(v)) that fall in segment s, stored as 16-bit offsets
-// id - s*S, segment-major: all slices of segment s, rows in internal order.
+// positions fill 32 KB of LDS by default).  Each k-hop row (and adjacency
+// row) of an active vertex v is cut into per-segment slices; slice (s, v)
+// holds the ids of N_v(k) (resp. adj(v)) that fall in segment s, stored as
+// 16-bit LDS byte offsets (id - s*S) * sizeof(position), segment-major: all
+// slices of segment s, rows in internal order.  k-hop slices are padded to a
+// whole number of 4-id quads with a sentinel offset: LDS slot S holds a
+// position so far away (1e30) that its squared distance overflows to +inf, the
+// reciprocal is exactly 0 and the padding term is exactly zero.  Each lane then
+// loads one aligned 8-byte quad of ids per memory instruction.
 //
 // One iteration is two kernels:
 //   seg_force_kernel   one workgroup = one segment x a pair-balanced range of
@@ -26,6 +31,7 @@
 namespace gila {
 
 constexpr int kSegBlock = 512;   // threads per segment workgroup
+constexpr int kSegTailPad = 1024;  // slack entries after the k-hop index array (>= 3 * 64 quads)
 
 bool segment_path_enabled() {
     const char* e = getenv("GILA_PATH");
@@ -67,47 +73,93 @@ __global__ __launch_bounds__(kBlock) void seg_count_kernel(
     }
 }
 
-// Wave per active row: copy each slice as 16-bit offsets into its place.
+// Wave per active row: write each slice as LDS byte offsets into its place,
+// k-hop slices padded to whole quads with the sentinel offset.
 __global__ __launch_bounds__(kBlock) void seg_fill_kernel(
-    int32_t na, int32_t S, int32_t nseg, const int64_t* __restrict__ kptr,
+    int32_t na, int32_t S, int32_t nseg, int32_t pos_bytes, const int64_t* __restrict__ kptr,
     const int32_t* __restrict__ kidx, const int64_t* __restrict__ rp,
-    const int32_t* __restrict__ ci, const int64_t* __restrict__ sk_ptr,
-    uint16_t* __restrict__ sk_idx, const int32_t* __restrict__ sa_ptr,
-    uint16_t* __restrict__ sa_idx) {
+    const int32_t* __restrict__ ci, const int32_t* __restrict__ kcnt,
+    const int64_t* __restrict__ sk_ptr, uint16_t* __restrict__ sk_idx,
+    const int32_t* __restrict__ sa_ptr, uint16_t* __restrict__ sa_idx) {
     const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * kBlock) >> 6;
     const int lane = lane64();
+    const uint16_t sentinel = (uint16_t)(S * pos_bytes);
     for (int64_t v = wave; v < na; v += nwaves) {
         int64_t kpos = kptr[v];
         int64_t apos = rp[v];
         for (int s = 0; s < nseg; ++s) {
             const int64_t slot = (int64_t)s * na + v;
-            const int64_t kdst = sk_ptr[slot], klen = sk_ptr[slot + 1] - kdst;
+            const int64_t kdst = sk_ptr[slot], kpad = sk_ptr[slot + 1] - kdst;
+            const int32_t klen = kcnt[slot];
             const int32_t base = s * S;
-            for (int64_t j = lane; j < klen; j += 64)
-                sk_idx[kdst + j] = (uint16_t)(kidx[kpos + j] - base);
+            for (int64_t j = lane; j < kpad; j += 64)
+                sk_idx[kdst + j] =
+                    j < klen ? (uint16_t)((kidx[kpos + j] - base) * pos_bytes) : sentinel;
             kpos += klen;
             const int64_t adst = sa_ptr[slot], alen = sa_ptr[slot + 1] - adst;
             for (int64_t j = lane; j < alen; j += 64)
-                sa_idx[adst + j] = (uint16_t)(ci[apos + j] - base);
+                sa_idx[adst + j] = (uint16_t)((ci[apos + j] - base) * pos_bytes);
             apos += alen;
         }
     }
 }
 
 // ------------------------------------------------------------------ iteration: segment kernel
+// Exact number of coincident pairs in a row of quads (only walked for rows in
+// which some lane saw a zero squared distance).
+template <class V, int LPV>
+__device__ __forceinline__ int count_coincident_quads(V xv, const uint2* __restrict__ q4, int nq,
+                                                      int gl, const unsigned char* __restrict__ lds) {
+    int c = 0;
+    for (int q = gl; q < nq; q += LPV) {
+        const uint2 w = q4[q];
+        const uint32_t offs[4] = {w.x & 0xFFFFu, w.x >> 16, w.y & 0xFFFFu, w.y >> 16};
+        for (int i = 0; i < 4; ++i) {
+            const V p = *reinterpret_cast<const V*>(lds + offs[i]);
+            c += (p.x == xv.x && p.y == xv.y) ? 1 : 0;
+        }
+    }
+    return c;
+}
+
+// Repulsion from the four neighbours whose LDS byte offsets are packed in w.
+template <class P>
+__device__ __forceinline__ void quad_terms(uint2 w, const unsigned char* __restrict__ lds,
+                                           typename P::real xv, typename P::real yv,
+                                           typename P::real d2, typename P::real& sx,
+                                           typename P::real& sy, typename P::real& mindd) {
+    using R = typename P::real;
+    using V = typename P::vec2;
+    const V p0 = *reinterpret_cast<const V*>(lds + (w.x & 0xFFFFu));
+    const V p1 = *reinterpret_cast<const V*>(lds + (w.x >> 16));
+    const V p2 = *reinterpret_cast<const V*>(lds + (w.y & 0xFFFFu));
+    const V p3 = *reinterpret_cast<const V*>(lds + (w.y >> 16));
+    R x0, y0, x1, y1, x2, y2, x3, y3;
+    repulse_term<P>(xv, yv, p0, d2, x0, y0, mindd);
+    repulse_term<P>(xv, yv, p1, d2, x1, y1, mindd);
+    repulse_term<P>(xv, yv, p2, d2, x2, y2, mindd);
+    repulse_term<P>(xv, yv, p3, d2, x3, y3, mindd);
+    sx = (x0 + x1) + (x2 + x3);
+    sy = (y0 + y1) + (y2 + y3);
+}
+
 template <class P, int LPV>
 __device__ __forceinline__ void seg_rows(const SegArgs& a, int s, int vb, int ve,
-                                         const typename P::vec2* __restrict__ lp, int& coinc) {
+                                         const typename P::vec2* __restrict__ lp,
+                                         int& coinc) {
     using R = typename P::real;
     using V = typename P::vec2;
     const V* __restrict__ gpos = reinterpret_cast<const V*>(a.pos);
+    const unsigned char* __restrict__ lds = reinterpret_cast<const unsigned char*>(lp);
     const R d2 = (R)(a.d * a.d);
     const R dpar = attract_param<R>(a.d);
     const int ngroups = kSegBlock / LPV;
     const int grp = threadIdx.x / LPV;
     const int gl = threadIdx.x % LPV;
     const int64_t sbase = (int64_t)s * a.na;
+    const uint32_t sq = (uint32_t)a.seg * (uint32_t)sizeof(V);
+    const uint2 sentinel = make_uint2(sq | (sq << 16), sq | (sq << 16));
     for (int v0 = vb; v0 < ve; v0 += ngroups) {
         const int v = v0 + grp;
         Acc<R, P::kahan> acc;
@@ -115,21 +167,32 @@ __device__ __forceinline__ void seg_rows(const SegArgs& a, int s, int vb, int ve
             const V xv = gpos[v];
             const int64_t slot = sbase + v;
             const int64_t kb = a.kptr[slot], ke = a.kptr[slot + 1];
-            int64_t e = kb + gl;
-            for (; e + 3 * LPV < ke; e += 4 * LPV) {
-                const uint32_t u0 = a.kidx[e];
-                const uint32_t u1 = a.kidx[e + LPV];
-                const uint32_t u2 = a.kidx[e + 2 * LPV];
-                const uint32_t u3 = a.kidx[e + 3 * LPV];
-                const V p0 = lp[u0], p1 = lp[u1], p2 = lp[u2], p3 = lp[u3];
-                repulse<P>(xv.x, xv.y, p0, d2, acc, coinc);
-                repulse<P>(xv.x, xv.y, p1, d2, acc, coinc);
-                repulse<P>(xv.x, xv.y, p2, d2, acc, coinc);
-                repulse<P>(xv.x, xv.y, p3, d2, acc, coinc);
+            const uint2* __restrict__ q4 = reinterpret_cast<const uint2*>(a.kidx + kb);
+            const int nq = (int)((ke - kb) >> 2);
+            R mindd = R(1);
+            // two quads per lane per step, the next two already in flight.
+            // Loads run up to 3*LPV quads past the row end (the index array
+            // carries kSegTailPad entries of slack); quads past the end are
+            // replaced by sentinels, whose terms are exactly 0.
+            int q = gl;
+            uint2 n0 = q4[q];
+            uint2 n1 = q4[q + LPV];
+            while (q < nq) {
+                const uint2 w0 = n0;
+                const uint2 w1 = q + LPV < nq ? n1 : sentinel;
+                q += 2 * LPV;
+                n0 = q4[q];
+                n1 = q4[q + LPV];
+                R sx, sy;
+                quad_terms<P>(w0, lds, xv.x, xv.y, d2, sx, sy, mindd);
+                acc.add(sx, sy);
+                quad_terms<P>(w1, lds, xv.x, xv.y, d2, sx, sy, mindd);
+                acc.add(sx, sy);
             }
-            for (; e < ke; e += LPV) repulse<P>(xv.x, xv.y, lp[a.kidx[e]], d2, acc, coinc);
+            if (mindd == R(0)) coinc += count_coincident_quads<V, LPV>(xv, q4, nq, gl, lds);
             const int32_t ab = a.aptr[slot], ae = a.aptr[slot + 1];
-            for (int32_t j = ab + gl; j < ae; j += LPV) attract<P>(xv.x, xv.y, lp[a.aidx[j]], dpar, acc);
+            for (int32_t j = ab + gl; j < ae; j += LPV)
+                attract<P>(xv.x, xv.y, *reinterpret_cast<const V*>(lds + a.aidx[j]), dpar, acc);
         }
         const double fx = group_sum<LPV>(acc.x());
         const double fy = group_sum<LPV>(acc.y());
@@ -153,6 +216,12 @@ __global__ __launch_bounds__(kSegBlock) void seg_force_kernel(SegArgs a) {
     const int64_t left = (int64_t)a.na - base;
     const int cnt = (int)(left < a.seg ? left : a.seg);
     for (int i = threadIdx.x; i < cnt; i += kSegBlock) lp[i] = gpos[base + i];
+    if (threadIdx.x == 0) {
+        V far;
+        far.x = sizeof(far.x) == 4 ? (decltype(far.x))1e30f : (decltype(far.x))1e300;
+        far.y = far.x;
+        lp[a.seg] = far;  // sentinel slot: padding terms vanish exactly
+    }
     __syncthreads();
     int coinc = 0;
     switch (lpv) {
@@ -206,15 +275,18 @@ int seg_size_for(int precision, int device) {
     const int pos_bytes = precision == GILA_FP64 ? 16 : 8;
     // LDS of one workgroup: the segment's positions plus ~1 KB of other state
     const int64_t lds_cap = (int64_t)device_info(device).max_lds_per_block - 1024;
-    const int64_t want = std::min<int64_t>(env_int("GILA_SEG_BYTES", 65536), lds_cap);
-    const int S = (int)(want / pos_bytes);
-    return std::max(256, std::min(S, 65536));
+    const int64_t want = std::min<int64_t>(env_int("GILA_SEG_BYTES", 32768), lds_cap);
+    int S = (int)(want / pos_bytes) - 1;  // one slot for the sentinel
+    S = std::min(S, 65535 / pos_bytes - 1);  // byte offsets, sentinel included, fit in 16 bits
+    return std::max(64, S);
 }
 
 static int lanes_for(int64_t med) {
-    // about 24 entries per lane amortise the per-slice reduction
+    // enough quads per lane (GILA_SEG_QPL, default 8) to amortise the
+    // per-slice reduction
+    const int64_t qpl = env_int("GILA_SEG_QPL", 8);
     int l = 1;
-    while (l < 64 && (int64_t)l * 24 * 2 <= med) l *= 2;
+    while (l < 64 && (int64_t)l * 2 * qpl * 4 <= med) l *= 2;
     return l;
 }
 
@@ -257,8 +329,11 @@ int build_segments(gila_khop* kh, int precision, hipStream_t st) {
     hipError_t e2 = hipMemcpyAsync(kc.data(), d_kc, sizeof(int32_t) * slots, hipMemcpyDeviceToHost, st);
     hipError_t e3 = hipMemcpyAsync(ac.data(), d_ac, sizeof(int32_t) * slots, hipMemcpyDeviceToHost, st);
     hipError_t e4 = hipStreamSynchronize(st);
-    dfree(d_kc);
     dfree(d_ac);
+    struct KcGuard {
+        int32_t* p;
+        ~KcGuard() { dfree(p); }
+    } kc_guard{d_kc};
     if (e1 || e2 || e3 || e4) return fail(GILA_EDEVICE, "segment count failed");
 
     // segment-major offsets
@@ -266,18 +341,21 @@ int build_segments(gila_khop* kh, int precision, hipStream_t st) {
     std::vector<int32_t> sap((size_t)slots + 1);
     skp[0] = 0;
     sap[0] = 0;
+    int64_t ksum = 0;
     for (int64_t i = 0; i < slots; ++i) {
-        skp[i + 1] = skp[i] + kc[i];
+        ksum += kc[i];
+        skp[i + 1] = skp[i] + ((kc[i] + 3) & ~3);
         sap[i + 1] = sap[i] + ac[i];
     }
-    if (skp[slots] != kh->P || sap[slots] != kh->nnz)
+    if (ksum != kh->P || sap[slots] != kh->nnz)
         return fail(GILA_EDEVICE, "segment slices do not cover the lists");
+    const int64_t kstore = skp[slots];
 
     // workgroup plan: per segment, contiguous row ranges of ~equal work
     const int cus = device_info(kh->device).cus;
     const int64_t row_cost = env_int("GILA_SEG_ROW_COST", 24);
     const int64_t total = kh->P + kh->nnz + row_cost * slots;
-    const int64_t target_wgs = (int64_t)cus * env_int("GILA_SEG_WG_PER_CU", 4);
+    const int64_t target_wgs = (int64_t)cus * env_int("GILA_SEG_WG_PER_CU", 16);
     const int64_t per_wg = std::max<int64_t>(4096, total / std::max<int64_t>(1, target_wgs));
     std::vector<int4> plan;
     std::vector<int64_t> lens;
@@ -305,7 +383,7 @@ int build_segments(gila_khop* kh, int precision, hipStream_t st) {
 
     GILA_TRY(dalloc_t(&kh->sk_ptr, (size_t)slots + 1));
     GILA_TRY(dalloc_t(&kh->sa_ptr, (size_t)slots + 1));
-    GILA_TRY(dalloc_t(&kh->sk_idx, (size_t)kh->P + 64));
+    GILA_TRY(dalloc_t(&kh->sk_idx, (size_t)kstore + kSegTailPad));
     GILA_TRY(dalloc_t(&kh->sa_idx, (size_t)kh->nnz + 64));
     GILA_TRY(dalloc_t(&kh->seg_wg, plan.size()));
     GILA_TRY(dalloc_t(&kh->part, (size_t)slots));
@@ -322,10 +400,11 @@ int build_segments(gila_khop* kh, int precision, hipStream_t st) {
                             hipMemcpyHostToDevice, st));
     GILA_HIP(hipMemcpyAsync(kh->seg_wg, plan.data(), sizeof(int4) * plan.size(),
                             hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(seg_fill_kernel, dim3(grid), dim3(kBlock), 0, st, na, S, nseg, kh->kptr,
-                       kh->kidx, kh->rp, kh->ci, kh->sk_ptr, kh->sk_idx, kh->sa_ptr, kh->sa_idx);
+    hipLaunchKernelGGL(seg_fill_kernel, dim3(grid), dim3(kBlock), 0, st, na, S, nseg, pos_bytes,
+                       kh->kptr, kh->kidx, kh->rp, kh->ci, d_kc, kh->sk_ptr, kh->sk_idx,
+                       kh->sa_ptr, kh->sa_idx);
     GILA_HIP(hipGetLastError());
-    const size_t lds = (size_t)S * pos_bytes;
+    const size_t lds = (size_t)(S + 1) * pos_bytes;
     if (lds > 48 * 1024) {
         (void)hipFuncSetAttribute((const void*)seg_force_kernel<GILA_FP64>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -337,7 +416,7 @@ int build_segments(gila_khop* kh, int precision, hipStream_t st) {
     GILA_HIP(hipStreamSynchronize(st));
     kh->seg_precision = precision;
     kh->seg_ready = true;
-    kh->device_bytes += (int64_t)(slots + 1) * 12 + 2 * (kh->P + kh->nnz) + 16 * slots +
+    kh->device_bytes += (int64_t)(slots + 1) * 12 + 2 * (kstore + kh->nnz) + 16 * slots +
                         (int64_t)sizeof(int4) * (int64_t)plan.size();
     return GILA_OK;
 }
@@ -361,7 +440,7 @@ int launch_segment_step(const gila_khop* kh, int precision, const StepArgs& a, h
     c.part = kh->part;
     c.nblocks = kh->comb_grid;
     const int pos_bytes = precision == GILA_FP64 ? 16 : 8;
-    const size_t lds = (size_t)kh->seg * pos_bytes;
+    const size_t lds = (size_t)(kh->seg + 1) * pos_bytes;
     const dim3 sg(kh->seg_grid), sb(kSegBlock), cg(kh->comb_grid), cb(kBlock);
     switch (precision) {
         case GILA_FP64:
