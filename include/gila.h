@@ -163,6 +163,15 @@ int gila_step(const gila_khop* kh, const gila_params* params, int32_t h, void* p
 int gila_run(const gila_khop* kh, const gila_params* params, int32_t start_h, int32_t end_h,
              void* pos_dev, void* stream, gila_stats* out);
 
+/* Measurement: `reps` iterations h, h+1, ... (eager launches, no HIP graph)
+ * on pos_dev with HIP events recorded on `stream` around every kernel.
+ * ms_out[0] receives the average duration of the force kernel (the segment
+ * kernel, or the direct-gather kernel on that path), ms_out[1] that of the
+ * combine kernel (0 on the direct path).  pos_dev is advanced by the
+ * iterations.  Synchronises `stream`. */
+int gila_time_iterations(const gila_khop* kh, const gila_params* params, int32_t h,
+                         int32_t reps, void* pos_dev, void* stream, double* ms_out);
+
 /* Whole layout of one graph: gila_build_khop, gila_run over all
  * params->iterations, free.  Synchronises `stream`. */
 int gila_layout(const gila_csr* g_dev, int32_t k, const gila_params* params, void* pos_dev,

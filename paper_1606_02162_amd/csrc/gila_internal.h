@@ -182,7 +182,8 @@ int plan_iteration(gila_khop* kh, const std::vector<int64_t>& counts_internal,
                    const std::vector<int64_t>& rp_internal);
 // implemented in segment.hip
 int build_segments(gila_khop* kh, int precision, hipStream_t s);
-int launch_segment_step(const gila_khop* kh, int precision, const StepArgs& a, hipStream_t s);
+int launch_segment_step(const gila_khop* kh, int precision, const StepArgs& a, hipStream_t s,
+                        hipEvent_t* ev = nullptr);
 bool segment_path_enabled();
 int seg_size_for(int precision, int device);
 // implemented in layout.hip: one iteration on whichever path the handle is ready for

@@ -347,6 +347,70 @@ int gila_run(const gila_khop* kh_c, const gila_params* params, int32_t start_h, 
                           use_graph);
 }
 
+int gila_time_iterations(const gila_khop* kh_c, const gila_params* params, int32_t h,
+                         int32_t reps, void* pos_dev, void* stream, double* ms_out) {
+    clear_error();
+    gila_khop* kh = const_cast<gila_khop*>(kh_c);
+    if (!kh) return fail(GILA_EINVAL, "handle is NULL");
+    if (!ms_out) return fail(GILA_EINVAL, "ms_out is NULL");
+    GILA_TRY(check_params(params, true));
+    if (reps < 1 || h < 0 || h + reps > params->iterations)
+        return fail(GILA_EINVAL, "iterations [%d, %d) outside the schedule", h, h + reps);
+    if (kh->n > 0 && !pos_dev) return fail(GILA_EINVAL, "pos_dev is NULL");
+    std::lock_guard<std::mutex> lk(kh->mu);
+    DeviceGuard dg(kh->device);
+    hipStream_t s = (hipStream_t)stream;
+    GILA_TRY(prepare_precision(kh, params->precision, s));
+    const bool seg = kh->seg_ready && segment_path_enabled() &&
+                     kh->seg == seg_size_for(params->precision, kh->device);
+    std::vector<hipEvent_t> ev((size_t)reps * 3, nullptr);
+    for (auto& e : ev)
+        if (hipEventCreate(&e) != hipSuccess) e = nullptr;
+    int rc = GILA_OK;
+    for (auto& e : ev)
+        if (!e) rc = fail(GILA_EDEVICE, "hipEventCreate failed");
+    if (rc == GILA_OK) {
+        hipLaunchKernelGGL(reset_ctl_kernel, dim3(1), dim3(1), 0, s, kh->ctl);
+        rc = launch_permute_in(kh, params->precision, pos_dev, s);
+    }
+    StepArgs a = base_args(kh, params);
+    for (int32_t r = 0; r < reps && rc == GILA_OK; ++r) {
+        a.pos_cur = kh->pos[r & 1];
+        a.pos_next = kh->pos[(r + 1) & 1];
+        a.t = params->temperature[h + r];
+        hipEvent_t* e3 = &ev[(size_t)r * 3];
+        if (seg) {
+            rc = launch_segment_step(kh, params->precision, a, s, e3);
+        } else {
+            if (hipEventRecord(e3[0], s) != hipSuccess) rc = fail(GILA_EDEVICE, "event record");
+            if (rc == GILA_OK) rc = launch_step(kh, params->precision, a, s);
+            if (rc == GILA_OK && hipEventRecord(e3[1], s) != hipSuccess)
+                rc = fail(GILA_EDEVICE, "event record");
+            if (rc == GILA_OK && hipEventRecord(e3[2], s) != hipSuccess)
+                rc = fail(GILA_EDEVICE, "event record");
+        }
+    }
+    if (rc == GILA_OK) rc = launch_permute_out(kh, params->precision, pos_dev, s);
+    if (rc == GILA_OK && hipStreamSynchronize(s) != hipSuccess)
+        rc = fail(GILA_EDEVICE, "stream synchronise failed");
+    double f = 0.0, c = 0.0;
+    for (int32_t r = 0; r < reps && rc == GILA_OK; ++r) {
+        float t1 = 0.f, t2 = 0.f;
+        if (hipEventElapsedTime(&t1, ev[(size_t)r * 3], ev[(size_t)r * 3 + 1]) != hipSuccess ||
+            hipEventElapsedTime(&t2, ev[(size_t)r * 3 + 1], ev[(size_t)r * 3 + 2]) != hipSuccess)
+            rc = fail(GILA_EDEVICE, "hipEventElapsedTime failed");
+        f += t1;
+        c += t2;
+    }
+    for (auto& e : ev)
+        if (e) (void)hipEventDestroy(e);
+    if (rc == GILA_OK) {
+        ms_out[0] = f / reps;
+        ms_out[1] = c / reps;
+    }
+    return rc;
+}
+
 int gila_layout(const gila_csr* g_dev, int32_t k, const gila_params* params, void* pos_dev,
                 void* stream, gila_stats* out) {
     clear_error();

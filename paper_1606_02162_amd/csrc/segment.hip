@@ -421,7 +421,8 @@ int build_segments(gila_khop* kh, int precision, hipStream_t st) {
     return GILA_OK;
 }
 
-int launch_segment_step(const gila_khop* kh, int precision, const StepArgs& a, hipStream_t s) {
+int launch_segment_step(const gila_khop* kh, int precision, const StepArgs& a, hipStream_t s,
+                        hipEvent_t* ev) {
     if (kh->n_active == 0) return GILA_OK;
     SegArgs g{};
     g.na = kh->n_active;
@@ -442,21 +443,21 @@ int launch_segment_step(const gila_khop* kh, int precision, const StepArgs& a, h
     const int pos_bytes = precision == GILA_FP64 ? 16 : 8;
     const size_t lds = (size_t)(kh->seg + 1) * pos_bytes;
     const dim3 sg(kh->seg_grid), sb(kSegBlock), cg(kh->comb_grid), cb(kBlock);
+    if (precision != GILA_FP64 && precision != GILA_FP32 && precision != GILA_FP32_KAHAN)
+        return fail(GILA_EINVAL, "unknown precision %d", precision);
+    if (ev) GILA_HIP(hipEventRecord(ev[0], s));
     switch (precision) {
-        case GILA_FP64:
-            hipLaunchKernelGGL(seg_force_kernel<GILA_FP64>, sg, sb, lds, s, g);
-            hipLaunchKernelGGL(seg_combine_kernel<GILA_FP64>, cg, cb, 0, s, c);
-            break;
-        case GILA_FP32:
-            hipLaunchKernelGGL(seg_force_kernel<GILA_FP32>, sg, sb, lds, s, g);
-            hipLaunchKernelGGL(seg_combine_kernel<GILA_FP32>, cg, cb, 0, s, c);
-            break;
-        case GILA_FP32_KAHAN:
-            hipLaunchKernelGGL(seg_force_kernel<GILA_FP32_KAHAN>, sg, sb, lds, s, g);
-            hipLaunchKernelGGL(seg_combine_kernel<GILA_FP32_KAHAN>, cg, cb, 0, s, c);
-            break;
-        default: return fail(GILA_EINVAL, "unknown precision %d", precision);
+        case GILA_FP64: hipLaunchKernelGGL(seg_force_kernel<GILA_FP64>, sg, sb, lds, s, g); break;
+        case GILA_FP32: hipLaunchKernelGGL(seg_force_kernel<GILA_FP32>, sg, sb, lds, s, g); break;
+        default: hipLaunchKernelGGL(seg_force_kernel<GILA_FP32_KAHAN>, sg, sb, lds, s, g); break;
     }
+    if (ev) GILA_HIP(hipEventRecord(ev[1], s));
+    switch (precision) {
+        case GILA_FP64: hipLaunchKernelGGL(seg_combine_kernel<GILA_FP64>, cg, cb, 0, s, c); break;
+        case GILA_FP32: hipLaunchKernelGGL(seg_combine_kernel<GILA_FP32>, cg, cb, 0, s, c); break;
+        default: hipLaunchKernelGGL(seg_combine_kernel<GILA_FP32_KAHAN>, cg, cb, 0, s, c); break;
+    }
+    if (ev) GILA_HIP(hipEventRecord(ev[2], s));
     GILA_HIP(hipGetLastError());
     return GILA_OK;
 }

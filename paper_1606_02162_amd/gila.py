@@ -79,6 +79,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "gila_step": (ctypes.c_int, [vp, P(_Params), i32, vp, vp, vp, vp, P(Stats)]),
         "gila_run": (ctypes.c_int, [vp, P(_Params), i32, i32, vp, vp, P(Stats)]),
         "gila_layout": (ctypes.c_int, [P(Csr), i32, P(_Params), vp, vp, P(Stats)]),
+        "gila_time_iterations": (ctypes.c_int, [vp, P(_Params), i32, i32, vp, vp,
+                                                P(ctypes.c_double)]),
         "gila_batch_build": (ctypes.c_int, [P(Csr), i32, P(i32), vp, P(vp)]),
         "gila_batch_run": (ctypes.c_int, [vp, P(_Params), P(vp), vp, P(Stats)]),
         "gila_batch_info": (ctypes.c_int, [vp, P(i32), P(i64), P(i64)]),
@@ -278,6 +280,17 @@ def run(kh: KHop, params: LayoutParams, pos, start_h: int = 0, end_h: int | None
     _check(_lib.gila_run(kh.handle, ctypes.byref(p), int(start_h), int(end_h), _ptr(pos),
                          _stream(stream), ctypes.byref(st)), "gila_run")
     return st
+
+
+def time_iterations(kh: KHop, params: LayoutParams, pos, h: int = 0, reps: int = 10,
+                    stream=None) -> tuple[float, float]:
+    """Average (force kernel, combine kernel) milliseconds over `reps` eager
+    iterations starting at h, timed with HIP events on the launch stream."""
+    ms = (ctypes.c_double * 2)()
+    p = params.as_struct()
+    _check(_lib.gila_time_iterations(kh.handle, ctypes.byref(p), int(h), int(reps), _ptr(pos),
+                                     _stream(stream), ms), "gila_time_iterations")
+    return float(ms[0]), float(ms[1])
 
 
 def layout(row_ptr, col_idx, k: int, params: LayoutParams, pos, stream=None) -> Stats:
