@@ -1,22 +1,844 @@
-// Many graphs in one persistent segmented launch (placeholder until implemented).
-#include "gila_internal.h"
+// Many independent graphs in one persistent launch.
+//
+// Build: the graphs are laid out one after another as a block-diagonal union
+// (vertex ids offset by each graph's base), validated, and their k-hop lists
+// are built in one batched frontier expansion whose bitmaps cover only the
+// source's own graph.  Lists and adjacency are stored as 16-bit ids local to
+// their graph.
+//
+// Run: one persistent kernel.  A workgroup takes the next graph (largest
+// first), copies its positions into LDS (two buffers), and runs ALL of the
+// graph's iterations there -- forces from LDS gathers, the temperature cap,
+// the synchronous move into the other buffer, the statistics and the halting
+// rule -- with only workgroup barriers between iterations; then it writes the
+// positions back and takes the next graph.  A graph's arithmetic depends only
+// on that graph (its lanes per vertex come from a per-class table fixed for
+// the process), so its result is the same bits alone or in any batch.  The
+// launch is captured as a HIP graph and replayed on later runs.
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <map>
+#include <numeric>
+
+#include "iteration.h"
+
+namespace gila {
+
+struct BatchDesc {
+    int64_t vbase;             // first vertex of the graph in the union
+    int32_t n;
+    int32_t n_active;
+    int32_t lpv;               // lanes per vertex
+    int32_t iters;             // iterations to run
+    int32_t t_off;             // offset of its temperatures
+    int32_t cls;               // row-length class (autotuner key)
+    double d;
+    double stop_fraction;
+    double stop_displacement;
+    void* pos;                 // caller's positions (n, precision layout)
+};
+
+struct BatchArgs {
+    int32_t count;
+    const BatchDesc* graphs;
+    const int32_t* order;      // graphs in decreasing work
+    const int64_t* kptr;       // union k-hop row offsets
+    const uint16_t* kidx;      // local ids
+    const int64_t* rp;         // union adjacency row offsets
+    const uint16_t* ci;        // local ids
+    const double* temps;
+    gila_stats* stats;         // [count], indexed like graphs
+    int32_t* work;             // next graph (atomic)
+};
+
+}  // namespace gila
+
+struct gila_batch {
+    int device = 0;
+    int32_t count = 0;
+    int64_t nv = 0, nnz = 0, P = 0;
+    int64_t device_bytes = 0;
+    int32_t nmax = 0;
+    std::vector<int64_t> vbase, ebase, Pg;
+    std::vector<int32_t> n, n_active, k, cls;
+    int64_t* kptr = nullptr;
+    uint16_t* kidx = nullptr;
+    int64_t* rp = nullptr;
+    uint16_t* ci16 = nullptr;
+    gila::BatchDesc* d_desc = nullptr;
+    int32_t* d_order = nullptr;
+    double* d_temps = nullptr;
+    int64_t temps_cap = 0;
+    gila_stats* d_stats = nullptr;
+    int32_t* d_work = nullptr;
+    std::vector<int32_t> order;
+    hipGraphExec_t gexec = nullptr;
+    std::vector<uint64_t> gkey;
+    std::mutex mu;
+};
+
+namespace gila {
+
+constexpr int kBatchBlock = 512;
+constexpr int kBatchWaves = kBatchBlock / 64;
+constexpr int kClasses = 8;
+
+// ------------------------------------------------------------------ build kernels
+struct GraphSrc {
+    const int64_t* rp;
+    const int32_t* ci;
+    int64_t vbase, ebase, nnz;
+    int32_t n, pad;
+};
+
+// One workgroup per graph: copy its CSR into the union with rebased ids and
+// check the per-graph rules that the union check cannot see.
+__global__ __launch_bounds__(kBlock) void gather_csr_kernel(const GraphSrc* __restrict__ src,
+                                                            int64_t* __restrict__ rp,
+                                                            int32_t* __restrict__ ci,
+                                                            int32_t* __restrict__ flag) {
+    const GraphSrc g = src[blockIdx.x];
+    int32_t bad = 0;
+    for (int64_t i = threadIdx.x; i <= g.n; i += kBlock) {
+        const int64_t r = g.rp ? g.rp[i] : 0;  // an empty graph may pass no row_ptr
+        if ((i == 0 && r != 0) || (i == g.n && r != g.nnz) || r < 0 || r > g.nnz) bad |= 16;
+        if (i > 0 && g.rp[i - 1] > r) bad |= 16;
+        rp[g.vbase + i] = g.ebase + (r < 0 ? 0 : (r > g.nnz ? g.nnz : r));
+    }
+    for (int64_t j = threadIdx.x; j < g.nnz; j += kBlock) {
+        const int32_t u = g.ci[j];
+        if (u < 0 || u >= g.n) {
+            bad |= 1;
+            ci[g.ebase + j] = (int32_t)g.vbase;  // keeps later checks in range
+        } else {
+            ci[g.ebase + j] = (int32_t)(g.vbase + u);
+        }
+    }
+    if (bad) atomicOr(flag, bad);
+}
+
+// One workgroup per graph: local 16-bit adjacency ids and the non-isolated
+// vertex count.
+__global__ __launch_bounds__(kBlock) void localize_kernel(const GraphSrc* __restrict__ src,
+                                                          const int32_t* __restrict__ ci,
+                                                          const int64_t* __restrict__ rp,
+                                                          uint16_t* __restrict__ ci16,
+                                                          int32_t* __restrict__ n_active) {
+    __shared__ int32_t s_red[4];
+    const GraphSrc g = src[blockIdx.x];
+    for (int64_t j = threadIdx.x; j < g.nnz; j += kBlock)
+        ci16[g.ebase + j] = (uint16_t)(ci[g.ebase + j] - g.vbase);
+    int32_t act = 0;
+    for (int64_t i = threadIdx.x; i < g.n; i += kBlock)
+        act += rp[g.vbase + i + 1] > rp[g.vbase + i] ? 1 : 0;
+    const int32_t tot = block_sum<int32_t>(act, s_red);
+    if (threadIdx.x == 0) n_active[blockIdx.x] = tot;
+}
+
+__global__ void gather_bounds_kernel(const int64_t* __restrict__ kptr,
+                                     const int64_t* __restrict__ vb, int32_t count,
+                                     int64_t* __restrict__ out) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i <= count; i += gridDim.x * blockDim.x)
+        out[i] = kptr[vb[i]];
+}
+
+// ------------------------------------------------------------------ the persistent kernel
+template <class P, int LPV>
+__device__ __forceinline__ void batch_graph_iteration(
+    const BatchArgs& a, const BatchDesc& G, const typename P::vec2* __restrict__ cur,
+    typename P::vec2* __restrict__ nxt, double t, double& energy, double& maxd, int64_t& moved,
+    int& coinc) {
+    using R = typename P::real;
+    using V = typename P::vec2;
+    const R d2 = (R)(G.d * G.d);
+    const R dpar = attract_param<R>(G.d);
+    constexpr int ngroups = kBatchBlock / LPV;
+    const int grp = threadIdx.x / LPV;
+    const int gl = threadIdx.x % LPV;
+    for (int v0 = 0; v0 < G.n; v0 += ngroups) {
+        const int v = v0 + grp;
+        Acc<R, P::kahan> acc;
+        V xv;
+        xv.x = 0;
+        xv.y = 0;
+        if (v < G.n) {
+            xv = cur[v];
+            const int64_t kb = a.kptr[G.vbase + v], ke = a.kptr[G.vbase + v + 1];
+            const uint16_t* __restrict__ row = a.kidx + kb;
+            const int len = (int)(ke - kb);
+            R mindd = R(1);
+            int e = gl;
+            for (; e + 3 * LPV < len; e += 4 * LPV) {
+                const V p0 = cur[row[e]], p1 = cur[row[e + LPV]], p2 = cur[row[e + 2 * LPV]],
+                        p3 = cur[row[e + 3 * LPV]];
+                R x0, y0, x1, y1, x2, y2, x3, y3;
+                repulse_term<P>(xv.x, xv.y, p0, d2, x0, y0, mindd);
+                repulse_term<P>(xv.x, xv.y, p1, d2, x1, y1, mindd);
+                repulse_term<P>(xv.x, xv.y, p2, d2, x2, y2, mindd);
+                repulse_term<P>(xv.x, xv.y, p3, d2, x3, y3, mindd);
+                acc.add((x0 + x1) + (x2 + x3), (y0 + y1) + (y2 + y3));
+            }
+            for (; e < len; e += LPV) {
+                R tx, ty;
+                repulse_term<P>(xv.x, xv.y, cur[row[e]], d2, tx, ty, mindd);
+                acc.add(tx, ty);
+            }
+            if (mindd == R(0)) coinc += count_coincident<V, uint16_t, LPV>(xv, row, len, gl, cur);
+            const int64_t ab = a.rp[G.vbase + v], ae = a.rp[G.vbase + v + 1];
+            for (int64_t j = ab + gl; j < ae; j += LPV) attract<P>(xv.x, xv.y, cur[a.ci[j]], dpar, acc);
+        }
+        const double fx = group_sum<LPV>(acc.x());
+        const double fy = group_sum<LPV>(acc.y());
+        if (v < G.n && gl == 0) {
+            // temperature cap and synchronous move (into the other buffer)
+            const double norm = sqrt(fx * fx + fy * fy);
+            double dx = 0.0, dy = 0.0;
+            if (norm > 0.0) {
+                const double l = norm < t ? norm : t;
+                dx = fx * (l / norm);
+                dy = fy * (l / norm);
+            }
+            V nx;
+            nx.x = (R)((double)xv.x + dx);
+            nx.y = (R)((double)xv.y + dy);
+            nxt[v] = nx;
+            const double dl = sqrt(dx * dx + dy * dy);
+            energy += fx * fx + fy * fy;
+            maxd = dl > maxd ? dl : maxd;
+            moved += dl > G.stop_displacement ? 1 : 0;
+        }
+    }
+}
+
+template <int PREC>
+__global__ __launch_bounds__(kBatchBlock) void batch_layout_kernel(BatchArgs a) {
+    using P = Prec<PREC>;
+    using V = typename P::vec2;
+    extern __shared__ __align__(16) unsigned char s_raw[];
+    __shared__ int s_g;
+    __shared__ int s_stop;
+    __shared__ double s_e[kBatchWaves], s_m[kBatchWaves];
+    __shared__ int64_t s_mv[kBatchWaves], s_c[kBatchWaves];
+    const int lane = lane64(), w = wave_id();
+    for (;;) {
+        if (threadIdx.x == 0) s_g = atomicAdd(a.work, 1);
+        __syncthreads();
+        const int gi = s_g;
+        if (gi >= a.count) break;
+        const int gid = a.order[gi];
+        const BatchDesc G = a.graphs[gid];
+        V* cur = reinterpret_cast<V*>(s_raw);
+        V* nxt = cur + G.n;
+        const V* src = reinterpret_cast<const V*>(G.pos);
+        for (int i = threadIdx.x; i < G.n; i += kBatchBlock) cur[i] = src[i];
+        __syncthreads();
+        double E = 0.0, M = 0.0;
+        int64_t MV = 0, C = 0;
+        int run = 0, stopped = 0;
+        for (int h = 0; h < G.iters; ++h) {
+            const double t = a.temps[G.t_off + h];
+            double energy = 0.0, maxd = 0.0;
+            int64_t moved = 0;
+            int coinc = 0;
+            switch (G.lpv) {
+                case 1: batch_graph_iteration<P, 1>(a, G, cur, nxt, t, energy, maxd, moved, coinc); break;
+                case 2: batch_graph_iteration<P, 2>(a, G, cur, nxt, t, energy, maxd, moved, coinc); break;
+                case 4: batch_graph_iteration<P, 4>(a, G, cur, nxt, t, energy, maxd, moved, coinc); break;
+                case 8: batch_graph_iteration<P, 8>(a, G, cur, nxt, t, energy, maxd, moved, coinc); break;
+                case 16: batch_graph_iteration<P, 16>(a, G, cur, nxt, t, energy, maxd, moved, coinc); break;
+                case 32: batch_graph_iteration<P, 32>(a, G, cur, nxt, t, energy, maxd, moved, coinc); break;
+                default: batch_graph_iteration<P, 64>(a, G, cur, nxt, t, energy, maxd, moved, coinc); break;
+            }
+            // iteration statistics in a fixed order
+            const double we = wave_sum(energy);
+            const double wm = wave_max(maxd);
+            const int64_t wmv = wave_sum(moved);
+            const int64_t wc = wave_sum((int64_t)coinc);
+            if (lane == 0) {
+                s_e[w] = we;
+                s_m[w] = wm;
+                s_mv[w] = wmv;
+                s_c[w] = wc;
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                double e = s_e[0], m = s_m[0];
+                int64_t mv = s_mv[0], c = s_c[0];
+                for (int i = 1; i < kBatchWaves; ++i) {
+                    e += s_e[i];
+                    m = s_m[i] > m ? s_m[i] : m;
+                    mv += s_mv[i];
+                    c += s_c[i];
+                }
+                s_e[0] = e;
+                s_m[0] = m;
+                s_mv[0] = mv;
+                s_c[0] = c;
+                s_stop = G.stop_fraction > 0.0 && (double)mv < G.stop_fraction * (double)G.n_active;
+            }
+            __syncthreads();
+            E = s_e[0];
+            M = s_m[0];
+            MV = s_mv[0];
+            C = s_c[0];
+            ++run;
+            V* tmp = cur;
+            cur = nxt;
+            nxt = tmp;
+            const int stop = s_stop;
+            __syncthreads();  // everyone has read the statistics before they are reused
+            if (stop) {
+                stopped = 1;
+                break;
+            }
+        }
+        V* dst = reinterpret_cast<V*>(G.pos);
+        for (int i = threadIdx.x; i < G.n; i += kBatchBlock) dst[i] = cur[i];
+        if (threadIdx.x == 0) {
+            gila_stats st;
+            st.iterations_run = run;
+            st.stopped = stopped;
+            st.moved = MV;
+            st.max_disp = M;
+            st.energy = E;
+            st.coincident = C;
+            a.stats[gid] = st;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void reset_work_kernel(int32_t* w) { *w = 0; }
+
+// ------------------------------------------------------------------ lanes per vertex
+// Row-length class of a graph: floor(log2(mean |N_v(k)|)), clamped to the table.
+static int row_class(int64_t P, int32_t n) {
+    const double mean = n > 0 ? (double)P / n : 0.0;
+    int c = 0;
+    while (c < kClasses - 1 && mean >= (double)(4 << c)) ++c;
+    return c;
+}
+
+// Default lanes per vertex of a class: about eight entries per lane.
+static int default_lpv(int cls) {
+    const int mean_hi = 4 << cls;
+    int l = 1;
+    while (l < 64 && l * 8 < mean_hi) l *= 2;
+    return l;
+}
+
+struct TuneTable {
+    int lpv[3][kClasses];
+    bool tuned[3][kClasses];
+};
+static std::mutex g_tune_mu;
+static std::map<int, TuneTable> g_tune;  // per device
+
+static TuneTable& tune_table(int device) {
+    auto it = g_tune.find(device);
+    if (it == g_tune.end()) {
+        TuneTable t{};
+        for (int p = 0; p < 3; ++p)
+            for (int c = 0; c < kClasses; ++c) {
+                t.lpv[p][c] = default_lpv(c);
+                t.tuned[p][c] = false;
+            }
+        it = g_tune.emplace(device, t).first;
+    }
+    return it->second;
+}
+
+static bool autotune_enabled() {
+    const char* e = getenv("GILA_AUTOTUNE");
+    return !(e && e[0] == '0');
+}
+
+static size_t lds_bytes(int32_t nmax, int precision) {
+    return (size_t)2 * (size_t)std::max(nmax, 1) * (precision == GILA_FP64 ? 16 : 8);
+}
+
+static void launch_batch_kernel(int precision, int grid, size_t lds, hipStream_t s,
+                                const BatchArgs& a) {
+    switch (precision) {
+        case GILA_FP64:
+            hipLaunchKernelGGL(batch_layout_kernel<GILA_FP64>, dim3(grid), dim3(kBatchBlock), lds, s, a);
+            break;
+        case GILA_FP32:
+            hipLaunchKernelGGL(batch_layout_kernel<GILA_FP32>, dim3(grid), dim3(kBatchBlock), lds, s, a);
+            break;
+        default:
+            hipLaunchKernelGGL(batch_layout_kernel<GILA_FP32_KAHAN>, dim3(grid), dim3(kBatchBlock), lds,
+                               s, a);
+            break;
+    }
+}
+
+static void set_lds_attr(size_t lds) {
+    if (lds <= 48 * 1024) return;
+    (void)hipFuncSetAttribute((const void*)batch_layout_kernel<GILA_FP64>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    (void)hipFuncSetAttribute((const void*)batch_layout_kernel<GILA_FP32>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    (void)hipFuncSetAttribute((const void*)batch_layout_kernel<GILA_FP32_KAHAN>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+static int batch_grid(const gila_batch* b, size_t lds) {
+    const DeviceInfo& di = device_info(b->device);
+    const size_t per_cu = std::max<size_t>(1, std::min<size_t>(4, (160u * 1024u) / (lds + 1024)));
+    return (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)di.cus * (int64_t)per_cu, b->count));
+}
+
+// Times every candidate lanes-per-vertex on up to 48 graphs of each class not
+// tuned yet (8 iterations on scratch copies of their positions) and keeps the
+// fastest.  The choice is made once per device, class and precision.
+static int autotune(gila_batch* b, int precision, hipStream_t s,
+                    const std::vector<BatchDesc>& desc) {
+    TuneTable& tt = tune_table(b->device);
+    std::vector<int> todo;
+    for (int c = 0; c < kClasses; ++c) {
+        if (tt.tuned[precision][c]) continue;
+        for (int32_t i = 0; i < b->count; ++i)
+            if (b->cls[i] == c && desc[i].n > 0) {
+                todo.push_back(c);
+                break;
+            }
+    }
+    if (todo.empty()) return GILA_OK;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    GILA_HIP(hipEventCreate(&e0));
+    GILA_HIP(hipEventCreate(&e1));
+    const size_t pb = precision == GILA_FP64 ? 16 : 8;
+    int rc = GILA_OK;
+    for (int c : todo) {
+        std::vector<int32_t> ids;
+        for (int32_t i = 0; i < b->count && ids.size() < 48; ++i)
+            if (b->cls[i] == c && desc[i].n > 0) ids.push_back(i);
+        int64_t vtot = 0;
+        int32_t nmax = 0;
+        for (int32_t i : ids) {
+            vtot += desc[i].n;
+            nmax = std::max(nmax, desc[i].n);
+        }
+        void* scratch = nullptr;
+        BatchDesc* d_desc = nullptr;
+        int32_t* d_order = nullptr;
+        double* d_t = nullptr;
+        gila_stats* d_st = nullptr;
+        rc = dalloc(&scratch, (size_t)vtot * pb);
+        if (!rc) rc = dalloc_t(&d_desc, ids.size());
+        if (!rc) rc = dalloc_t(&d_order, ids.size());
+        if (!rc) rc = dalloc_t(&d_t, 8);
+        if (!rc) rc = dalloc_t(&d_st, ids.size());
+        const std::vector<double> temps(8, 0.0);  // t = 0: nothing moves
+        std::vector<int32_t> ord(ids.size());
+        std::iota(ord.begin(), ord.end(), 0);
+        if (!rc && hipMemcpyAsync(d_t, temps.data(), 8 * sizeof(double), hipMemcpyHostToDevice, s))
+            rc = fail(GILA_EDEVICE, "autotune upload");
+        if (!rc && hipMemcpyAsync(d_order, ord.data(), ord.size() * 4, hipMemcpyHostToDevice, s))
+            rc = fail(GILA_EDEVICE, "autotune upload");
+        float best_ms = 1e30f;
+        int best = tt.lpv[precision][c];
+        const size_t lds = lds_bytes(nmax, precision);
+        set_lds_attr(lds);
+        for (int lpv = 1; lpv <= 64 && !rc; lpv *= 2) {
+            std::vector<BatchDesc> sub;
+            int64_t off = 0;
+            for (int32_t i : ids) {
+                BatchDesc d = desc[i];
+                if (hipMemcpyAsync((char*)scratch + off * pb, d.pos, (size_t)d.n * pb,
+                                   hipMemcpyDeviceToDevice, s) != hipSuccess) {
+                    rc = fail(GILA_EDEVICE, "autotune copy");
+                    break;
+                }
+                d.pos = (char*)scratch + off * pb;
+                d.lpv = lpv;
+                d.iters = 8;
+                d.t_off = 0;
+                d.stop_fraction = 0.0;
+                off += d.n;
+                sub.push_back(d);
+            }
+            if (rc) break;
+            if (hipMemcpyAsync(d_desc, sub.data(), sub.size() * sizeof(BatchDesc),
+                               hipMemcpyHostToDevice, s) != hipSuccess) {
+                rc = fail(GILA_EDEVICE, "autotune upload");
+                break;
+            }
+            BatchArgs a{};
+            a.count = (int32_t)sub.size();
+            a.graphs = d_desc;
+            a.order = d_order;
+            a.kptr = b->kptr;
+            a.kidx = b->kidx;
+            a.rp = b->rp;
+            a.ci = b->ci16;
+            a.temps = d_t;
+            a.stats = d_st;
+            a.work = b->d_work;
+            const int grid = (int)std::min<int64_t>(a.count, device_info(b->device).cus);
+            hipLaunchKernelGGL(reset_work_kernel, dim3(1), dim3(1), 0, s, b->d_work);
+            (void)hipEventRecord(e0, s);
+            launch_batch_kernel(precision, grid, lds, s, a);
+            (void)hipEventRecord(e1, s);
+            if (hipStreamSynchronize(s) != hipSuccess) {
+                rc = fail(GILA_EDEVICE, "autotune run failed");
+                break;
+            }
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = lpv;
+            }
+        }
+        dfree(scratch);
+        dfree(d_desc);
+        dfree(d_order);
+        dfree(d_t);
+        dfree(d_st);
+        if (rc) break;
+        tt.lpv[precision][c] = best;
+        tt.tuned[precision][c] = true;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
+}
+
+static void free_batch(gila_batch* b) {
+    if (!b) return;
+    DeviceGuard g(b->device);
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    dfree(b->kptr);
+    dfree(b->kidx);
+    dfree(b->rp);
+    dfree(b->ci16);
+    dfree(b->d_desc);
+    dfree(b->d_order);
+    dfree(b->d_temps);
+    dfree(b->d_stats);
+    dfree(b->d_work);
+    delete b;
+}
+
+struct BatchHolder {
+    gila_batch* p;
+    ~BatchHolder() { free_batch(p); }
+};
+
+template <class T>
+struct DevTmp {
+    T* p = nullptr;
+    ~DevTmp() { dfree(p); }
+};
+
+static int batch_build(const gila_csr* graphs, int32_t count, const int32_t* k, hipStream_t s,
+                       gila_batch** out) {
+    if (!out) return fail(GILA_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (count < 0) return fail(GILA_EINVAL, "count must be >= 0");
+    if (count > 0 && (!graphs || !k)) return fail(GILA_EINVAL, "graphs or k is NULL");
+    int dev = 0;
+    GILA_HIP(hipGetDevice(&dev));
+    BatchHolder h{new gila_batch()};
+    gila_batch* b = h.p;
+    b->device = dev;
+    b->count = count;
+    b->vbase.assign((size_t)count + 1, 0);
+    b->ebase.assign((size_t)count + 1, 0);
+    b->n.assign(count, 0);
+    b->k.assign(count, 0);
+    std::vector<GraphSrc> src(count);
+    int32_t kmax = 1;
+    for (int32_t i = 0; i < count; ++i) {
+        const gila_csr& g = graphs[i];
+        if (k[i] < 1) return fail(GILA_EINVAL, "graph %d: k must be >= 1", i);
+        if (g.n < 0 || g.nnz < 0) return fail(GILA_EINVAL, "graph %d: negative size", i);
+        if (g.n > 65535) return fail(GILA_EUNSUPPORTED, "graph %d: more than 65535 vertices", i);
+        if (g.nnz % 2 || g.nnz > (int64_t)g.n * (g.n > 0 ? g.n - 1 : 0))
+            return fail(GILA_EINVAL, "graph %d: bad nnz", i);
+        if ((g.n > 0 && !g.row_ptr) || (g.nnz > 0 && !g.col_idx))
+            return fail(GILA_EINVAL, "graph %d: NULL array", i);
+        b->n[i] = g.n;
+        b->k[i] = k[i];
+        kmax = std::max(kmax, k[i]);
+        b->nmax = std::max(b->nmax, g.n);
+        b->vbase[i + 1] = b->vbase[i] + g.n;
+        b->ebase[i + 1] = b->ebase[i] + g.nnz;
+        src[i] = GraphSrc{g.n > 0 ? g.row_ptr : nullptr, g.col_idx, b->vbase[i], b->ebase[i],
+                           g.nnz, g.n, 0};
+    }
+    b->nv = b->vbase[count];
+    b->nnz = b->ebase[count];
+    if (b->nv > INT32_MAX - 1) return fail(GILA_EUNSUPPORTED, "batch too large");
+    if (count == 0) {  // an empty batch holds no device state
+        *out = b;
+        h.p = nullptr;
+        return GILA_OK;
+    }
+
+    DevTmp<GraphSrc> d_src;
+    DevTmp<int32_t> d_flag, d_ci32, d_k, d_nact;
+    DevTmp<int64_t> d_vb, d_counts, d_bounds;
+    GILA_TRY(dalloc_t(&d_src.p, std::max(count, 1)));
+    GILA_TRY(dalloc_t(&d_flag.p, 2));
+    GILA_TRY(dalloc_t(&b->rp, (size_t)b->nv + 1));
+    GILA_TRY(dalloc_t(&d_ci32.p, (size_t)b->nnz));
+    GILA_TRY(dalloc_t(&b->ci16, (size_t)b->nnz));
+    GILA_TRY(dalloc_t(&d_vb.p, (size_t)count + 1));
+    GILA_TRY(dalloc_t(&d_k.p, std::max(count, 1)));
+    GILA_TRY(dalloc_t(&d_nact.p, std::max(count, 1)));
+    GILA_TRY(dalloc_t(&b->d_work, 1));
+    GILA_HIP(hipMemsetAsync(d_flag.p, 0, 2 * sizeof(int32_t), s));
+    GILA_HIP(hipMemsetAsync(b->rp, 0, sizeof(int64_t), s));
+    GILA_HIP(hipMemcpyAsync(d_vb.p, b->vbase.data(), sizeof(int64_t) * (count + 1),
+                            hipMemcpyHostToDevice, s));
+    if (count > 0) {
+        GILA_HIP(hipMemcpyAsync(d_src.p, src.data(), sizeof(GraphSrc) * count,
+                                hipMemcpyHostToDevice, s));
+        GILA_HIP(hipMemcpyAsync(d_k.p, b->k.data(), sizeof(int32_t) * count,
+                                hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(gather_csr_kernel, dim3(count), dim3(kBlock), 0, s, d_src.p, b->rp,
+                           d_ci32.p, d_flag.p);
+        GILA_HIP(hipGetLastError());
+        GILA_TRY(launch_validate_csr((int32_t)b->nv, b->nnz, b->rp, d_ci32.p, d_flag.p, s));
+    }
+    int32_t flag = 0;
+    GILA_HIP(hipMemcpyAsync(&flag, d_flag.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    GILA_HIP(hipStreamSynchronize(s));
+    if (flag)
+        return fail(GILA_EINVAL, "malformed CSR in batch:%s%s%s%s%s",
+                    (flag & 16) ? " bad row_ptr" : "", (flag & 1) ? " column out of range" : "",
+                    (flag & 2) ? " self-loop" : "", (flag & 4) ? " row not strictly ascending" : "",
+                    (flag & 8) ? " not symmetric" : "");
+
+    // k-hop counts, offsets and 16-bit local rows
+    const int32_t nwords = std::max<int32_t>(1, (b->nmax + 31) / 32);
+    GILA_TRY(dalloc_t(&d_counts.p, (size_t)std::max<int64_t>(b->nv, 1)));
+    GILA_TRY(dalloc_t(&b->kptr, (size_t)b->nv + 1));
+    BfsArgs a{};
+    a.n = (int32_t)b->nv;
+    a.k = kmax;
+    a.kmax = kmax;
+    a.nverts = (int32_t)b->nv;
+    a.nwords = nwords;
+    a.rp = b->rp;
+    a.ci = d_ci32.p;
+    a.counts = d_counts.p;
+    a.work = d_flag.p + 1;
+    a.gvbase = d_vb.p;
+    a.gk = d_k.p;
+    a.ngraphs = count;
+    a.qcap = std::max<int32_t>(1, b->nmax);
+    if (b->nv > 0) GILA_TRY(run_bfs(false, dev, s, a));
+    GILA_TRY(exclusive_scan_i64(d_counts.p, b->kptr, b->nv, s));
+    GILA_HIP(hipMemcpy(&b->P, b->kptr + b->nv, sizeof(int64_t), hipMemcpyDeviceToHost));
+    GILA_TRY(dalloc_t(&b->kidx, (size_t)b->P + 64));
+    if (b->nv > 0 && b->P > 0) {
+        a.kptr = b->kptr;
+        a.kidx16 = b->kidx;
+        GILA_TRY(run_bfs(true, dev, s, a));
+    }
+    if (count > 0) {
+        hipLaunchKernelGGL(localize_kernel, dim3(count), dim3(kBlock), 0, s, d_src.p, d_ci32.p,
+                           b->rp, b->ci16, d_nact.p);
+        GILA_HIP(hipGetLastError());
+    }
+    // per-graph pair counts and non-isolated counts
+    GILA_TRY(dalloc_t(&d_bounds.p, (size_t)count + 1));
+    hipLaunchKernelGGL(gather_bounds_kernel, dim3((count + 256) / 256), dim3(256), 0, s, b->kptr,
+                       d_vb.p, count, d_bounds.p);
+    GILA_HIP(hipGetLastError());
+    std::vector<int64_t> bounds((size_t)count + 1, 0);
+    b->n_active.assign(count, 0);
+    GILA_HIP(hipMemcpyAsync(bounds.data(), d_bounds.p, sizeof(int64_t) * (count + 1),
+                            hipMemcpyDeviceToHost, s));
+    if (count > 0)
+        GILA_HIP(hipMemcpyAsync(b->n_active.data(), d_nact.p, sizeof(int32_t) * count,
+                                hipMemcpyDeviceToHost, s));
+    GILA_HIP(hipStreamSynchronize(s));
+    b->Pg.assign(count, 0);
+    b->cls.assign(count, 0);
+    std::vector<int64_t> work(count);
+    for (int32_t i = 0; i < count; ++i) {
+        b->Pg[i] = bounds[i + 1] - bounds[i];
+        b->cls[i] = row_class(b->Pg[i], b->n[i]);
+        work[i] = b->Pg[i] + (b->ebase[i + 1] - b->ebase[i]) + 8ll * b->n[i];
+    }
+    b->order.resize(count);
+    std::iota(b->order.begin(), b->order.end(), 0);
+    std::stable_sort(b->order.begin(), b->order.end(),
+                     [&](int32_t x, int32_t y) { return work[x] > work[y]; });
+    GILA_TRY(dalloc_t(&b->d_order, std::max(count, 1)));
+    GILA_TRY(dalloc_t(&b->d_desc, std::max(count, 1)));
+    GILA_TRY(dalloc_t(&b->d_stats, std::max(count, 1)));
+    if (count > 0)
+        GILA_HIP(hipMemcpyAsync(b->d_order, b->order.data(), sizeof(int32_t) * count,
+                                hipMemcpyHostToDevice, s));
+    GILA_HIP(hipStreamSynchronize(s));
+    b->device_bytes = 8 * (2 * (b->nv + 1)) + 2 * (b->P + b->nnz) +
+                      (int64_t)(sizeof(BatchDesc) + 4 + sizeof(gila_stats)) * count;
+    *out = b;
+    h.p = nullptr;
+    return GILA_OK;
+}
+
+static int batch_run(gila_batch* b, const gila_params* params, void* const* pos, hipStream_t s,
+                     gila_stats* out) {
+    const int32_t count = b->count;
+    if (count == 0) return GILA_OK;
+    if (!params || !pos) return fail(GILA_EINVAL, "params or pos is NULL");
+    const int precision = params[0].precision;
+    int64_t total_t = 0;
+    for (int32_t i = 0; i < count; ++i) {
+        GILA_TRY(check_params(&params[i], true));
+        if (params[i].precision != precision)
+            return fail(GILA_EINVAL, "graph %d: all graphs of a batch share one precision", i);
+        if (b->n[i] > 0 && !pos[i]) return fail(GILA_EINVAL, "graph %d: pos is NULL", i);
+        total_t += params[i].iterations;
+    }
+    const size_t lds = lds_bytes(b->nmax, precision);
+    if (lds > device_info(b->device).max_lds_per_block - 2048)
+        return fail(GILA_EUNSUPPORTED, "largest graph (%d vertices) does not fit in LDS",
+                    b->nmax);
+    std::vector<double> temps((size_t)std::max<int64_t>(total_t, 1));
+    std::vector<BatchDesc> desc(count);
+    int64_t off = 0;
+    for (int32_t i = 0; i < count; ++i) {
+        BatchDesc& d = desc[i];
+        d.vbase = b->vbase[i];
+        d.n = b->n[i];
+        d.n_active = b->n_active[i];
+        d.cls = b->cls[i];
+        d.iters = params[i].iterations;
+        d.t_off = (int32_t)off;
+        d.d = params[i].ideal_length;
+        d.stop_fraction = params[i].stop_fraction;
+        d.stop_displacement = params[i].stop_displacement;
+        d.pos = pos[i];
+        if (params[i].iterations > 0)
+            std::memcpy(&temps[off], params[i].temperature,
+                        sizeof(double) * params[i].iterations);
+        off += params[i].iterations;
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        if (autotune_enabled()) GILA_TRY(autotune(b, precision, s, desc));
+        const TuneTable& tt = tune_table(b->device);
+        for (int32_t i = 0; i < count; ++i) desc[i].lpv = tt.lpv[precision][desc[i].cls];
+    }
+    if ((int64_t)temps.size() > b->temps_cap) {
+        dfree(b->d_temps);
+        b->d_temps = nullptr;
+        b->temps_cap = 0;
+        GILA_TRY(dalloc_t(&b->d_temps, temps.size()));
+        b->temps_cap = (int64_t)temps.size();
+        if (b->gexec) {
+            (void)hipGraphExecDestroy(b->gexec);
+            b->gexec = nullptr;
+        }
+    }
+    GILA_HIP(hipMemcpyAsync(b->d_temps, temps.data(), sizeof(double) * temps.size(),
+                            hipMemcpyHostToDevice, s));
+    GILA_HIP(hipMemcpyAsync(b->d_desc, desc.data(), sizeof(BatchDesc) * count,
+                            hipMemcpyHostToDevice, s));
+    set_lds_attr(lds);
+    BatchArgs a{};
+    a.count = count;
+    a.graphs = b->d_desc;
+    a.order = b->d_order;
+    a.kptr = b->kptr;
+    a.kidx = b->kidx;
+    a.rp = b->rp;
+    a.ci = b->ci16;
+    a.temps = b->d_temps;
+    a.stats = b->d_stats;
+    a.work = b->d_work;
+    const int grid = batch_grid(b, lds);
+    const std::vector<uint64_t> key = {(uint64_t)precision, (uint64_t)lds, (uint64_t)grid,
+                                       (uint64_t)(uintptr_t)b->d_temps};
+    if (!b->gexec || key != b->gkey) {
+        if (b->gexec) {
+            (void)hipGraphExecDestroy(b->gexec);
+            b->gexec = nullptr;
+        }
+        hipStream_t cs = capture_stream(b->device);
+        if (!cs) return fail(GILA_EDEVICE, "cannot create capture stream");
+        GILA_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        hipLaunchKernelGGL(reset_work_kernel, dim3(1), dim3(1), 0, cs, b->d_work);
+        launch_batch_kernel(precision, grid, lds, cs, a);
+        hipGraph_t graph = nullptr;
+        const hipError_t le = hipGetLastError();
+        const hipError_t ee = hipStreamEndCapture(cs, &graph);
+        if (le != hipSuccess || ee != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return fail(GILA_EDEVICE, "batch graph capture: %s",
+                        hipGetErrorString(le != hipSuccess ? le : ee));
+        }
+        const hipError_t ie = hipGraphInstantiate(&b->gexec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ie != hipSuccess) {
+            b->gexec = nullptr;
+            return fail(GILA_EDEVICE, "batch graph instantiate: %s", hipGetErrorString(ie));
+        }
+        b->gkey = key;
+    }
+    GILA_HIP(hipGraphLaunch(b->gexec, s));
+    std::vector<gila_stats> st(count);
+    GILA_HIP(hipMemcpyAsync(st.data(), b->d_stats, sizeof(gila_stats) * count,
+                            hipMemcpyDeviceToHost, s));
+    GILA_HIP(hipStreamSynchronize(s));
+    if (out) std::memcpy(out, st.data(), sizeof(gila_stats) * count);
+    return GILA_OK;
+}
+
+}  // namespace gila
 
 using namespace gila;
 
 extern "C" {
-int gila_batch_build(const gila_csr*, int32_t, const int32_t*, void*, gila_batch** out) {
-    if (out) *out = nullptr;
-    return fail(GILA_EUNSUPPORTED, "batched layout not built yet");
+
+int gila_batch_build(const gila_csr* graphs_dev, int32_t count, const int32_t* k, void* stream,
+                     gila_batch** out) {
+    clear_error();
+    return batch_build(graphs_dev, count, k, (hipStream_t)stream, out);
 }
-int gila_batch_run(gila_batch*, const gila_params*, void* const*, void*, gila_stats*) {
-    return fail(GILA_EUNSUPPORTED, "batched layout not built yet");
+
+int gila_batch_run(gila_batch* b, const gila_params* params, void* const* pos_dev, void* stream,
+                   gila_stats* out) {
+    clear_error();
+    if (!b) return fail(GILA_EINVAL, "batch is NULL");
+    std::lock_guard<std::mutex> lk(b->mu);
+    DeviceGuard dg(b->device);
+    return batch_run(b, params, pos_dev, (hipStream_t)stream, out);
 }
-int gila_batch_info(const gila_batch*, int32_t*, int64_t*, int64_t*) {
-    return fail(GILA_EUNSUPPORTED, "batched layout not built yet");
+
+int gila_batch_info(const gila_batch* b, int32_t* count, int64_t* total_pairs,
+                    int64_t* device_bytes) {
+    if (!b) return fail(GILA_EINVAL, "batch is NULL");
+    if (count) *count = b->count;
+    if (total_pairs) *total_pairs = b->P;
+    if (device_bytes) *device_bytes = b->device_bytes;
+    return GILA_OK;
 }
-void gila_batch_free(gila_batch*) {}
-int gila_layout_batch(const gila_csr*, int32_t, const int32_t*, const gila_params*, void* const*,
-                      void*, gila_stats*) {
-    return fail(GILA_EUNSUPPORTED, "batched layout not built yet");
+
+void gila_batch_free(gila_batch* b) { free_batch(b); }
+
+int gila_layout_batch(const gila_csr* graphs_dev, int32_t count, const int32_t* k,
+                      const gila_params* params, void* const* pos_dev, void* stream,
+                      gila_stats* out) {
+    clear_error();
+    gila_batch* b = nullptr;
+    GILA_TRY(batch_build(graphs_dev, count, k, (hipStream_t)stream, &b));
+    int rc;
+    {
+        std::lock_guard<std::mutex> lk(b->mu);
+        rc = batch_run(b, params, pos_dev, (hipStream_t)stream, out);
+    }
+    free_batch(b);
+    return rc;
 }
-}
+
+}  // extern "C"

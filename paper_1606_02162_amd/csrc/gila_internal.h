@@ -130,6 +130,29 @@ struct SegArgs {
     Ctl* ctl;
 };
 
+// Arguments of the k-hop frontier-expansion kernel (khop.hip).
+struct BfsArgs {
+    int32_t n;
+    int32_t k;
+    int32_t nverts;            // sources are ids [0, nverts)
+    int32_t nwords;            // bitmap words (largest graph)
+    const int64_t* rp;
+    const int32_t* ci;
+    int64_t* counts;           // count pass: |N_v(k)| per source
+    const int64_t* kptr;       // fill pass: row offsets
+    int32_t* kidx;             // fill pass: rows (global ids) ...
+    uint16_t* kidx16;          // ... or rows as ids local to the source's graph
+    int32_t* queue;            // [grid][qcap] frontier storage (k >= 3)
+    int64_t qcap;
+    uint32_t* gbitmap;         // [grid][nwords] when the bitmap is not in LDS
+    int32_t* work;             // next source (atomic)
+    // batch mode (gvbase != nullptr)
+    const int64_t* gvbase;     // [ngraphs + 1] first vertex of each graph
+    const int32_t* gk;         // [ngraphs] k of each graph
+    int32_t ngraphs;
+    int32_t kmax;
+};
+
 }  // namespace gila
 
 // ------------------------------------------------------------------ handles
@@ -180,6 +203,12 @@ namespace gila {
 int launch_step(const gila_khop* kh, int precision, const StepArgs& a, hipStream_t s);
 int plan_iteration(gila_khop* kh, const std::vector<int64_t>& counts_internal,
                    const std::vector<int64_t>& rp_internal);
+// implemented in khop.hip
+int run_bfs(bool fill, int device, hipStream_t s, BfsArgs a);
+int launch_validate_csr(int32_t n, int64_t nnz, const int64_t* rp, const int32_t* ci, int32_t* flag,
+                        hipStream_t s);
+// implemented in util.hip: out[0] = 0, out[i + 1] = in[0] + ... + in[i]
+int exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t s);
 // implemented in segment.hip
 int build_segments(gila_khop* kh, int precision, hipStream_t s);
 int launch_segment_step(const gila_khop* kh, int precision, const StepArgs& a, hipStream_t s,

@@ -60,22 +60,10 @@ __global__ __launch_bounds__(kBlock) void validate_csr_kernel(int32_t n, int64_t
 }
 
 // ------------------------------------------------------------------ BFS count / fill
-struct BfsArgs {
-    int32_t n;
-    int32_t k;
-    int32_t nverts;            // sources are ids [0, nverts)
-    int32_t nwords;            // bitmap words = ceil(n / 32)
-    const int64_t* rp;
-    const int32_t* ci;
-    int64_t* counts;           // count pass: |N_v(k)| per source
-    const int64_t* kptr;       // fill pass: row offsets
-    int32_t* kidx;             // fill pass: rows
-    int32_t* queue;            // [grid][qcap] frontier storage (k >= 3)
-    int64_t qcap;
-    uint32_t* gbitmap;         // [grid][nwords] when the bitmap is not in LDS
-    int32_t* work;             // next source (atomic)
-};
-
+// One workgroup expands one source at a time.  In batch mode the sources
+// belong to many independent graphs laid out one after another (a
+// block-diagonal union): each source's bitmap covers only its own graph's id
+// range and its k is its graph's k.
 template <bool FILL, bool LDS_BITMAP>
 __global__ __launch_bounds__(kBlock) void khop_bfs_kernel(BfsArgs a) {
     extern __shared__ uint32_t s_dyn[];
@@ -96,29 +84,42 @@ __global__ __launch_bounds__(kBlock) void khop_bfs_kernel(BfsArgs a) {
         __syncthreads();
         const int32_t v = s_v;
         if (v >= a.nverts) break;
+        // the source's graph: id base, bitmap words and k
+        int64_t base = 0;
+        int32_t nw = a.nwords, k = a.k;
+        if (a.gvbase) {
+            int32_t lo = 0, hi = a.ngraphs - 1;
+            while (lo < hi) {
+                const int32_t mid = lo + (hi - lo + 1) / 2;
+                if (a.gvbase[mid] <= v) lo = mid;
+                else hi = mid - 1;
+            }
+            base = a.gvbase[lo];
+            nw = (int32_t)((a.gvbase[lo + 1] - base + 31) / 32);
+            k = a.gk[lo];
+        }
         const int64_t rb = a.rp[v], re = a.rp[v + 1];
         int64_t mycount = 0;
         if (re > rb) {
             if (threadIdx.x == 0) {
-                bm[v >> 5] |= 1u << (v & 31);
+                const int64_t lv = v - base;
+                bm[lv >> 5] |= 1u << (lv & 31);
                 s_qtail = 0;
             }
             __syncthreads();
             // level 1: the adjacency row (distinct, never v in a simple graph)
             for (int64_t e = rb + threadIdx.x; e < re; e += kBlock) {
-                const int32_t u = a.ci[e];
+                const int64_t u = a.ci[e] - base;
                 const uint32_t bit = 1u << (u & 31);
                 const uint32_t old = atomicOr(&bm[u >> 5], bit);
-                if (!(old & bit)) {
-                    ++mycount;
-                }
+                if (!(old & bit)) ++mycount;
             }
             __syncthreads();
             // levels 2..k: expand the previous level's new vertices
             int64_t fb = rb, fe = re;
             bool from_queue = false;
-            for (int level = 2; level <= a.k; ++level) {
-                const bool record = level < a.k;
+            for (int level = 2; level <= k; ++level) {
+                const bool record = level < k;
                 const int32_t qstart = s_qtail;
                 for (int64_t c = fb; c < fe; c += kBlock) {
                     const int64_t i = c + threadIdx.x;
@@ -141,14 +142,15 @@ __global__ __launch_bounds__(kBlock) void khop_bfs_kernel(BfsArgs a) {
                             else lo = mid + 1;
                         }
                         const int64_t off = j - (lo ? s_incl[lo - 1] : 0);
-                        const int32_t u = a.ci[s_start[lo] + off];
+                        const int32_t ug = a.ci[s_start[lo] + off];
+                        const int64_t u = ug - base;
                         const uint32_t bit = 1u << (u & 31);
                         const uint32_t old = atomicOr(&bm[u >> 5], bit);
                         if (!(old & bit)) {
                             ++mycount;
                             if (record) {
                                 const int32_t q = atomicAdd(&s_qtail, 1);
-                                queue[q] = u;
+                                queue[q] = ug;
                             }
                         }
                     }
@@ -164,29 +166,36 @@ __global__ __launch_bounds__(kBlock) void khop_bfs_kernel(BfsArgs a) {
             const int64_t cnt = block_sum<int64_t>(mycount, s_red);
             if (threadIdx.x == 0) a.counts[v] = cnt;
             if (re > rb) {
-                for (int i = threadIdx.x; i < a.nwords; i += kBlock) bm[i] = 0u;
+                for (int i = threadIdx.x; i < nw; i += kBlock) bm[i] = 0u;
             }
         } else {
             if (re > rb) {
-                if (threadIdx.x == 0) bm[v >> 5] &= ~(1u << (v & 31));
+                if (threadIdx.x == 0) {
+                    const int64_t lv = v - base;
+                    bm[lv >> 5] &= ~(1u << (lv & 31));
+                }
                 __syncthreads();
-                int64_t base = a.kptr[v];
+                int64_t pos = a.kptr[v];
                 const int64_t end = a.kptr[v + 1];
-                for (int w0 = 0; w0 < a.nwords; w0 += kBlock) {
+                for (int w0 = 0; w0 < nw; w0 += kBlock) {
                     const int wi = w0 + threadIdx.x;
-                    uint32_t word = wi < a.nwords ? bm[wi] : 0u;
+                    uint32_t word = wi < nw ? bm[wi] : 0u;
                     int64_t total;
                     const int64_t ex =
                         block_exclusive_scan<int64_t>((int64_t)__popc(word), s_red, total);
-                    int64_t o = base + ex;
+                    int64_t o = pos + ex;
                     while (word) {
                         const int b = __ffs(word) - 1;
-                        if (o < end) a.kidx[o] = wi * 32 + b;
+                        const int64_t local = (int64_t)wi * 32 + b;
+                        if (o < end) {
+                            if (a.kidx16) a.kidx16[o] = (uint16_t)local;
+                            else a.kidx[o] = (int32_t)(base + local);
+                        }
                         ++o;
                         word &= word - 1u;
                     }
-                    if (wi < a.nwords) bm[wi] = 0u;
-                    base += total;
+                    if (wi < nw) bm[wi] = 0u;
+                    pos += total;
                 }
             }
         }
@@ -212,7 +221,16 @@ __global__ __launch_bounds__(kBlock) void relabel_csr_kernel(
 
 __global__ void reset_counter_kernel(int32_t* c) { *c = 0; }
 
-static int run_bfs(bool fill, int device, hipStream_t s, BfsArgs a) {
+int launch_validate_csr(int32_t n, int64_t nnz, const int64_t* rp, const int32_t* ci, int32_t* flag,
+                        hipStream_t s) {
+    if (nnz <= 0) return GILA_OK;
+    const int grid = (int)std::min<int64_t>(4096, (nnz + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(validate_csr_kernel, dim3(grid), dim3(kBlock), 0, s, n, nnz, rp, ci, flag);
+    GILA_HIP(hipGetLastError());
+    return GILA_OK;
+}
+
+int run_bfs(bool fill, int device, hipStream_t s, BfsArgs a) {
     const DeviceInfo& di = device_info(device);
     const size_t bm_bytes = (size_t)a.nwords * 4;
     const bool lds = bm_bytes + 8 * 1024 * 2 + 1024 <= di.max_lds_per_block;
@@ -224,11 +242,14 @@ static int run_bfs(bool fill, int device, hipStream_t s, BfsArgs a) {
     }
     int grid = di.cus * per_cu;
     if (a.nverts < grid) grid = std::max(1, a.nverts);
-    if (a.k >= 3) {
-        // frontier queues: n ids per workgroup, capped at ~1 GiB in total
-        const int64_t cap_grid = std::max<int64_t>(64, (1ll << 30) / std::max<int64_t>(1, 4ll * a.n));
+    const int32_t kmax = a.gvbase ? a.kmax : a.k;
+    if (kmax >= 3) {
+        // frontier queues: one graph's vertex count per workgroup (the
+        // largest graph in batch mode), capped at ~1 GiB in total
+        const int64_t qn = a.qcap > 0 ? a.qcap : std::max<int32_t>(1, a.n);
+        const int64_t cap_grid = std::max<int64_t>(64, (1ll << 30) / std::max<int64_t>(1, 4ll * qn));
         grid = (int)std::min<int64_t>(grid, cap_grid);
-        a.qcap = std::max<int32_t>(1, a.n);
+        a.qcap = qn;
         GILA_TRY(dalloc_t(&a.queue, (size_t)grid * a.qcap));
     } else {
         a.queue = nullptr;

@@ -2,9 +2,81 @@
 #include <cstdio>
 #include <map>
 
+#include "device_util.h"
 #include "gila_internal.h"
 
 namespace gila {
+
+// ------------------------------------------------------------------ exclusive scan (int64)
+constexpr int kScanItems = 8;                  // items per thread
+constexpr int kScanTile = kBlock * kScanItems;  // items per workgroup
+
+__global__ __launch_bounds__(kBlock) void scan_tiles_kernel(const int64_t* __restrict__ in,
+                                                            int64_t* __restrict__ out, int64_t n,
+                                                            int64_t* __restrict__ tile_sums) {
+    __shared__ int64_t s_red[4];
+    const int64_t t0 = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int64_t v[kScanItems];
+    int64_t sum = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        v[i] = (t0 + i < n) ? in[t0 + i] : 0;
+        sum += v[i];
+    }
+    int64_t total;
+    int64_t run = block_exclusive_scan<int64_t>(sum, s_red, total);
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        run += v[i];
+        if (t0 + i < n) out[t0 + i + 1] = run;
+    }
+    if (threadIdx.x == 0) tile_sums[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kBlock) void scan_sums_kernel(int64_t* __restrict__ sums, int64_t m) {
+    // in place: sums[i] <- sums[0] + ... + sums[i-1] (one workgroup)
+    __shared__ int64_t s_red[4];
+    int64_t carry = 0;
+    for (int64_t b = 0; b < m; b += kBlock) {
+        const int64_t i = b + threadIdx.x;
+        const int64_t x = i < m ? sums[i] : 0;
+        int64_t total;
+        const int64_t ex = block_exclusive_scan<int64_t>(x, s_red, total);
+        if (i < m) sums[i] = carry + ex;
+        carry += total;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void scan_add_kernel(int64_t* __restrict__ out, int64_t n,
+                                                          const int64_t* __restrict__ offs) {
+    const int64_t t0 = (int64_t)blockIdx.x * kScanTile;
+    const int64_t add = offs[blockIdx.x];
+    for (int i = threadIdx.x; i < kScanTile; i += kBlock) {
+        const int64_t j = t0 + i;
+        if (j < n) out[j + 1] += add;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) out[0] = 0;
+}
+
+int exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t s) {
+    if (n <= 0) {
+        GILA_HIP(hipMemsetAsync(out, 0, sizeof(int64_t), s));
+        return GILA_OK;
+    }
+    const int64_t tiles = (n + kScanTile - 1) / kScanTile;
+    int64_t* sums = nullptr;
+    GILA_TRY(dalloc_t(&sums, (size_t)tiles));
+    hipLaunchKernelGGL(scan_tiles_kernel, dim3((unsigned)tiles), dim3(kBlock), 0, s, in, out, n,
+                       sums);
+    hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(kBlock), 0, s, sums, tiles);
+    hipLaunchKernelGGL(scan_add_kernel, dim3((unsigned)tiles), dim3(kBlock), 0, s, out, n, sums);
+    const hipError_t e = hipGetLastError();
+    const hipError_t e2 = hipStreamSynchronize(s);
+    dfree(sums);
+    if (e != hipSuccess || e2 != hipSuccess)
+        return fail(GILA_EDEVICE, "scan failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+    return GILA_OK;
+}
 
 static thread_local std::string t_last_error;
 

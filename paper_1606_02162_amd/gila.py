@@ -81,12 +81,11 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "gila_layout": (ctypes.c_int, [P(Csr), i32, P(_Params), vp, vp, P(Stats)]),
         "gila_time_iterations": (ctypes.c_int, [vp, P(_Params), i32, i32, vp, vp,
                                                 P(ctypes.c_double)]),
-        "gila_batch_build": (ctypes.c_int, [P(Csr), i32, P(i32), vp, P(vp)]),
-        "gila_batch_run": (ctypes.c_int, [vp, P(_Params), P(vp), vp, P(Stats)]),
+        "gila_batch_build": (ctypes.c_int, [vp, i32, vp, vp, P(vp)]),
+        "gila_batch_run": (ctypes.c_int, [vp, vp, vp, vp, vp]),
         "gila_batch_info": (ctypes.c_int, [vp, P(i32), P(i64), P(i64)]),
         "gila_batch_free": (None, [vp]),
-        "gila_layout_batch": (ctypes.c_int, [P(Csr), i32, P(i32), P(_Params), P(vp), vp,
-                                             P(Stats)]),
+        "gila_layout_batch": (ctypes.c_int, [vp, i32, vp, vp, vp, vp, vp]),
         "gila_server_create": (ctypes.c_int, [i32, i64, i32, P(vp)]),
         "gila_submit": (ctypes.c_int, [vp, P(Csr), i32, P(_Params), vp, P(u64)]),
         "gila_poll": (ctypes.c_int, [vp, u64, vp, P(Stats)]),
@@ -120,6 +119,10 @@ def _stream(stream=None) -> int:
         return int(getattr(stream, "cuda_stream", stream))
     import torch
     return int(torch.cuda.current_stream().cuda_stream)
+
+
+def _addr(arr):
+    return ctypes.cast(arr, ctypes.c_void_p)
 
 
 def _ptr(t) -> int:
@@ -300,3 +303,72 @@ def layout(row_ptr, col_idx, k: int, params: LayoutParams, pos, stream=None) -> 
     _check(_lib.gila_layout(ctypes.byref(csr), int(k), ctypes.byref(p), _ptr(pos),
                             _stream(stream), ctypes.byref(st)), "gila_layout")
     return st
+
+
+# ---------------------------------------------------------------- batches
+class Batch:
+    """Many graphs' k-hop lists in one segmented handle (gila_batch_build).
+
+    ``graphs`` is a list of (row_ptr, col_idx) device tensor pairs, ``k`` a
+    list of ints (or one int for all)."""
+
+    def __init__(self, graphs, k, stream=None):
+        count = len(graphs)
+        ks = [int(k)] * count if isinstance(k, int) else [int(x) for x in k]
+        self._csr = (Csr * max(count, 1))()
+        for i, (rp, ci) in enumerate(graphs):
+            self._csr[i] = make_csr(rp, ci)
+        self._k = (ctypes.c_int32 * max(count, 1))(*ks)
+        self.count = count
+        self._h = ctypes.c_void_p()
+        _check(_lib.gila_batch_build(_addr(self._csr), count, _addr(self._k), _stream(stream),
+                                     ctypes.byref(self._h)), "gila_batch_build")
+
+    def info(self) -> dict:
+        c, P, b = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64()
+        _check(_lib.gila_batch_info(self._h, ctypes.byref(c), ctypes.byref(P), ctypes.byref(b)),
+               "gila_batch_info")
+        return {"count": c.value, "total_pairs": P.value, "device_bytes": b.value}
+
+    def run(self, params, pos, stream=None):
+        """params: list of LayoutParams (or one for all); pos: list of device
+        tensors, updated in place.  Returns a list of Stats."""
+        plist = params if isinstance(params, (list, tuple)) else [params] * self.count
+        structs = (_Params * max(self.count, 1))()
+        for i, p in enumerate(plist):
+            structs[i] = p.as_struct()
+        ptrs = (ctypes.c_void_p * max(self.count, 1))(*[_ptr(t) for t in pos])
+        stats = (Stats * max(self.count, 1))()
+        _check(_lib.gila_batch_run(self._h, _addr(structs), _addr(ptrs), _stream(stream),
+                                   _addr(stats)), "gila_batch_run")
+        return [stats[i] for i in range(self.count)]
+
+    def free(self):
+        if self._h:
+            _lib.gila_batch_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def layout_batch(graphs, k, params, pos, stream=None):
+    """Build, run and free a batch in one call (gila_layout_batch)."""
+    count = len(graphs)
+    ks = [int(k)] * count if isinstance(k, int) else [int(x) for x in k]
+    csr = (Csr * max(count, 1))()
+    for i, (rp, ci) in enumerate(graphs):
+        csr[i] = make_csr(rp, ci)
+    kk = (ctypes.c_int32 * max(count, 1))(*ks)
+    plist = params if isinstance(params, (list, tuple)) else [params] * count
+    structs = (_Params * max(count, 1))()
+    for i, p in enumerate(plist):
+        structs[i] = p.as_struct()
+    ptrs = (ctypes.c_void_p * max(count, 1))(*[_ptr(t) for t in pos])
+    stats = (Stats * max(count, 1))()
+    _check(_lib.gila_layout_batch(_addr(csr), count, _addr(kk), _addr(structs), _addr(ptrs),
+                                  _stream(stream), _addr(stats)), "gila_layout_batch")
+    return [stats[i] for i in range(count)]

@@ -1,0 +1,169 @@
+"""GPU parity of the batched form: many graphs of mixed sizes, families and k
+in one persistent launch, each graph's iterations run in LDS.
+
+Checks: one FP64 iteration with an unbounded cap returns x + F exactly, so
+the batch's forces are compared with the oracle's at 1e-12; FP32 + Kahan
+iterations stepped along each graph's own trajectory against the oracle at
+the 1e-5 gates; a graph alone and inside a batch give the same bits; the
+halting rule per graph; malformed inputs are rejected."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_common import oracle_rows, pos_err, rel_l2, require_gpu
+from paper_1606_02162_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def G():
+    require_gpu()
+    from paper_1606_02162_amd import gila
+    return gila
+
+
+def _mixed_graphs(count, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    sizes = inputs.log_uniform_sizes(count, 20, 3000, seed)
+    for i, n in enumerate(sizes.tolist()):
+        fam = i % 4
+        if fam == 0:
+            g = inputs.random_tree_plus_edges(n, n // 2, seed=seed * 100 + i)
+        elif fam == 1:
+            g = inputs.watts_strogatz(max(n, 8), 6, 0.1, seed=seed * 100 + i)
+        elif fam == 2:
+            g = inputs.barabasi_albert(max(n, 5), 2, seed=seed * 100 + i)
+        else:
+            side = max(2, int(np.sqrt(n)))
+            g = inputs.grid_graph(side, side)
+        out.append((g, int(rng.integers(1, 4))))
+    return out
+
+
+def _t(G, x, prec):
+    import torch
+    return torch.from_numpy(np.asarray(x, dtype=np.float64)).to(
+        dtype=G.position_dtype(prec), device="cuda").contiguous()
+
+
+def test_batch_fp64_forces_exact(G):
+    gs = _mixed_graphs(40, 1)
+    dev = [G.to_device_csr(g) for g, _ in gs]
+    b = G.Batch(dev, [k for _, k in gs])
+    x0 = [inputs.uniform_positions(g.n, seed=i, width=500.0) for i, (g, _) in enumerate(gs)]
+    pos = [_t(G, x, G.FP64) for x in x0]
+    params = [G.LayoutParams(temperature=np.array([1e300]), ideal_length=30.0, precision=G.FP64)
+              for _ in gs]
+    st = b.run(params, pos)
+    worst = 0.0
+    for i, (g, k) in enumerate(gs):
+        optr, oidx = oracle_rows(g, k)
+        F, _ = oracle.forces(g.n, g.row_ptr, g.col_idx, optr, oidx, 30.0, x0[i])
+        Fg = pos[i].cpu().numpy() - x0[i]
+        e = rel_l2(Fg, F)
+        worst = max(worst, e)
+        assert e <= 1e-10, (i, g.name, k, e)
+        assert st[i].iterations_run == 1
+    print(f"batch fp64 worst force error {worst:.3e}")
+
+
+@pytest.mark.parametrize("precision", ["fp32_kahan", "fp32"])
+def test_batch_steps_along_trajectory(G, precision):
+    prec = G.PRECISIONS[precision]
+    gs = _mixed_graphs(24, 2)
+    dev = [G.to_device_csr(g) for g, _ in gs]
+    b = G.Batch(dev, [k for _, k in gs])
+    H = 30
+    temps = [G.paper_schedule(g.n, 1.0, 40.0, H) for g, _ in gs]
+    xs = [inputs.uniform_positions(g.n, seed=i, width=800.0).astype(np.float32).astype(np.float64)
+          for i, (g, _) in enumerate(gs)]
+    rows = [oracle_rows(g, k) for g, k in gs]
+    worst = 0.0
+    for h in range(H):
+        pos = [_t(G, x, prec) for x in xs]
+        params = [G.LayoutParams(temperature=temps[i][h:h + 1], ideal_length=40.0, precision=prec)
+                  for i in range(len(gs))]
+        b.run(params, pos)
+        for i, (g, k) in enumerate(gs):
+            xn = pos[i].double().cpu().numpy()
+            if h % 7 == 0 or h == H - 1:
+                xo, _, _, _ = oracle.step(g.n, g.row_ptr, g.col_idx, rows[i][0], rows[i][1], 40.0,
+                                          temps[i][h], xs[i])
+                e = pos_err(xn, xo) if g.n > 1 else 0.0
+                worst = max(worst, e)
+                assert e <= 1e-5, (h, i, g.name, e)
+            xs[i] = xn
+    print(f"batch {precision} worst per-step position error {worst:.3e}")
+
+
+def test_alone_equals_mixed_bitwise(G):
+    gs = _mixed_graphs(32, 3)
+    dev = [G.to_device_csr(g) for g, _ in gs]
+    H = 40
+    params = [G.LayoutParams(temperature=G.paper_schedule(g.n, 1.0, 40.0, H), ideal_length=40.0,
+                             precision=G.FP32_KAHAN) for g, _ in gs]
+    x0 = [inputs.uniform_positions(g.n, seed=i, width=800.0) for i, (g, _) in enumerate(gs)]
+    pos = [_t(G, x, G.FP32_KAHAN) for x in x0]
+    G.Batch(dev, [k for _, k in gs]).run(params, pos)
+    for i in (0, 5, 17, 31):
+        alone = [_t(G, x0[i], G.FP32_KAHAN)]
+        G.Batch([dev[i]], [gs[i][1]]).run([params[i]], alone)
+        assert np.array_equal(alone[0].cpu().numpy(), pos[i].cpu().numpy()), i
+    # and a second mix in another order
+    perm = list(reversed(range(len(gs))))
+    pos2 = [_t(G, x0[i], G.FP32_KAHAN) for i in perm]
+    G.Batch([dev[i] for i in perm], [gs[i][1] for i in perm]).run([params[i] for i in perm], pos2)
+    for j, i in enumerate(perm):
+        assert np.array_equal(pos2[j].cpu().numpy(), pos[i].cpu().numpy()), i
+
+
+def test_batch_halting_and_layout_batch(G):
+    n = 64
+    ring = inputs.cycle_graph(n)
+    th = 2 * np.pi * np.arange(n) / n
+    xr = np.stack([200 * np.cos(th), 200 * np.sin(th)], axis=1)
+    temps = 20.0 * 0.9 ** np.arange(300)
+    optr, oidx = oracle_rows(ring, 2)
+    _, run, _ = oracle.layout(ring.n, ring.row_ptr, ring.col_idx, optr, oidx, 10.0, temps, xr,
+                              stop_fraction=0.15, stop_displacement=0.01)
+    other = inputs.random_tree_plus_edges(500, 250, seed=9)
+    dev = [G.to_device_csr(ring), G.to_device_csr(other)]
+    pos = [_t(G, xr, G.FP64), _t(G, inputs.uniform_positions(500, 1, 300.0), G.FP64)]
+    params = [G.LayoutParams(temperature=temps, ideal_length=10.0, precision=G.FP64,
+                             stop_fraction=0.15, stop_displacement=0.01),
+              G.LayoutParams(temperature=temps[:50], ideal_length=10.0, precision=G.FP64)]
+    st = G.layout_batch(dev, [2, 3], params, pos)
+    assert st[0].stopped == 1 and st[0].iterations_run == run < 300
+    assert st[1].stopped == 0 and st[1].iterations_run == 50
+
+
+def test_batch_edge_cases(G):
+    import torch
+    # empty batch
+    assert G.Batch([], []).run([], []) == []
+    # a batch holding an isolated-only graph and a one-edge graph
+    iso = inputs.to_csr(5, [], [])
+    one = inputs.path_graph(2)
+    dev = [G.to_device_csr(iso), G.to_device_csr(one)]
+    x = [inputs.uniform_positions(5, 1, 10.0), np.array([[0.0, 0.0], [1.0, 0.0]])]
+    pos = [_t(G, xi, G.FP64) for xi in x]
+    p = G.LayoutParams(temperature=np.ones(3), ideal_length=4.0, precision=G.FP64)
+    st = G.Batch(dev, [2, 1]).run([p, p], pos)
+    assert np.array_equal(pos[0].cpu().numpy(), x[0])
+    assert pos[1].cpu().numpy()[1, 0] > 1.0          # the pair repels apart (d = 4)
+    assert st[0].iterations_run == 3
+    # malformed graphs
+    bad = (torch.tensor([0, 1, 1], dtype=torch.int64, device="cuda"),
+           torch.tensor([1], dtype=torch.int32, device="cuda"))
+    with pytest.raises(G.GilaError) as e:
+        G.Batch([dev[1], bad], [1, 1])
+    assert e.value.code == G.GILA_EINVAL
+    with pytest.raises(G.GilaError):
+        G.Batch([dev[1]], [0])
+    # mixed precisions are refused
+    b = G.Batch(dev, [2, 1])
+    with pytest.raises(G.GilaError):
+        b.run([p, G.LayoutParams(temperature=np.ones(3), ideal_length=4.0, precision=G.FP32)],
+              pos)
