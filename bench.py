@@ -94,6 +94,12 @@ def main() -> int:
     ap.add_argument("--scale", type=int, default=18)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=8)
+    ap.add_argument("--workload", choices=["rmat", "batch", "serve"], default="rmat",
+                    help="rmat: one R-MAT graph (default line); batch: 4096 graphs in one "
+                         "persistent launch; serve: Poisson stream through the layout server")
+    ap.add_argument("--batch-count", type=int, default=4096)
+    ap.add_argument("--serve-jobs", type=int, default=400)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (three times) so that HBM "
                          "traffic counters can be scaled against a known byte count")
@@ -115,6 +121,11 @@ def main() -> int:
         print(json.dumps({"calibration": "device copy", "bytes_read": x.numel() * 4,
                           "bytes_written": y.numel() * 4, "launches": 3}))
         return 0
+
+    if args.workload == "batch":
+        return bench_batch(args)
+    if args.workload == "serve":
+        return bench_serve(args)
 
     from paper_1606_02162_amd import gila, inputs
 
@@ -239,6 +250,126 @@ def main() -> int:
         }
     print(json.dumps(out))
     return 0
+
+
+def _percentiles(x):
+    x = np.asarray(x, dtype=np.float64)
+    if x.size == 0:
+        return None, None
+    return float(np.percentile(x, 50)), float(np.percentile(x, 99))
+
+
+def bench_batch(args) -> int:
+    """4096 connected graphs (random recursive tree + 0.5n extra edges, n
+    log-uniform in [50, 5000]), k = 3, FP32, 200 iterations each, in one
+    persistent launch.  A step is build + run of the whole batch.  The same
+    graphs through the plain per-graph solver (gila_layout one after another)
+    are timed on a sample of every 16th graph and scaled by pair count."""
+    import torch
+
+    from paper_1606_02162_amd import gila, inputs
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    count, H, k = args.batch_count, 200, 3
+    d = inputs.PAPER_IDEAL_LENGTH
+    sizes = inputs.log_uniform_sizes(count, 50, 5000, seed=4)
+    graphs = [inputs.random_tree_plus_edges(int(n), int(n) // 2, seed=4_000_000 + i)
+              for i, n in enumerate(sizes)]
+    # one upload: views into two concatenated tensors
+    rp_all = torch.from_numpy(np.concatenate([g.row_ptr for g in graphs])).to(dev)
+    ci_all = torch.from_numpy(np.concatenate([g.col_idx for g in graphs])).to(dev)
+    dev_graphs, ro, co = [], 0, 0
+    for g in graphs:
+        dev_graphs.append((rp_all[ro:ro + g.n + 1], ci_all[co:co + g.nnz]))
+        ro += g.n + 1
+        co += g.nnz
+    nv = int(sizes.sum())
+    pos0 = torch.empty((nv, 2), dtype=torch.float32, device=dev)
+    views, vo = [], 0
+    for i, g in enumerate(graphs):
+        v = pos0[vo:vo + g.n]
+        gila.init_positions(g.n, i, inputs.PAPER_FRAME, inputs.PAPER_FRAME, gila.FP32, v)
+        views.append(v)
+        vo += g.n
+    pos = torch.empty_like(pos0)
+    pviews, vo = [], 0
+    for g in graphs:
+        pviews.append(pos[vo:vo + g.n])
+        vo += g.n
+    params = [gila.LayoutParams(temperature=gila.paper_schedule(g.n, 1.0, d, H), ideal_length=d,
+                                precision=gila.FP32) for g in graphs]
+    torch.cuda.synchronize()
+
+    def one_step():
+        pos.copy_(pos0)
+        b = gila.Batch(dev_graphs, k)
+        st = b.run(params, pviews)
+        return b, st
+
+    for _ in range(args.warmup):
+        b, _ = one_step()          # the first run also fills the autotuner's table
+        b.free()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b, st = one_step()
+        info = b.info()
+        lat = b.latency_ms()
+        b.free()
+    torch.cuda.synchronize()
+    total_s = time.perf_counter() - t0
+    assert all(s.iterations_run == H for s in st)
+    P = info["total_pairs"]
+    nnz = sum(g.nnz for g in graphs)
+    inter = (P + nnz) * H
+    # run-only time (lists already built)
+    b = gila.Batch(dev_graphs, k)
+    pos.copy_(pos0)
+    torch.cuda.synchronize()
+    tr0 = time.perf_counter()
+    b.run(params, pviews)
+    torch.cuda.synchronize()
+    run_s = time.perf_counter() - tr0
+    b.free()
+    # plain per-graph solver on a sample, scaled by pair count
+    sample = list(range(0, count, 16))
+    sp = 0
+    torch.cuda.synchronize()
+    ts0 = time.perf_counter()
+    for i in sample:
+        pviews[i].copy_(views[i])
+        gila.layout(dev_graphs[i][0], dev_graphs[i][1], k, params[i], pviews[i])
+    torch.cuda.synchronize()
+    sample_s = time.perf_counter() - ts0
+    for i in sample:
+        kh = gila.build_khop(dev_graphs[i][0], dev_graphs[i][1], k)
+        sp += (kh.info()["total_pairs"] + graphs[i].nnz) * H
+        kh.free()
+    per_graph_rate = sp / sample_s
+    value = inter * args.steps / total_s
+    p50, p99 = _percentiles(lat)
+    out = {
+        "metric": "batched layout: k-hop force interactions/s over 4096 graphs",
+        "value": value, "unit": "interactions/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": total_s / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"batch{count}_tree+0.5n_k{k}_fp32_{H}iters",
+                   "graphs": count, "vertices": nv, "total_pairs": P, "iterations": H},
+        "run_only_ms": run_s * 1e3,
+        "latency_ms_within_batch": {"p50": p50, "p99": p99, "max": float(np.max(lat))},
+        "per_graph_solver": {"interactions_per_s": per_graph_rate,
+                             "sample_graphs": len(sample),
+                             "speedup_of_batch": value / per_graph_rate},
+    }
+    print(json.dumps(out))
+    return 0
+
+
+def bench_serve(args) -> int:
+    from paper_1606_02162_amd import serving_bench
+    return serving_bench.main(args)
 
 
 if __name__ == "__main__":

@@ -197,6 +197,11 @@ int gila_batch_run(gila_batch* b, const gila_params* params, void* const* pos_de
 
 int gila_batch_info(const gila_batch* b, int32_t* count, int64_t* total_pairs,
                     int64_t* device_bytes);
+
+/* Latency of each graph in the last gila_batch_run: ms_host[count] receives
+ * the time from the start of the first graph's work to the moment graph i's
+ * positions were written back (device wall clock). */
+int gila_batch_latency(const gila_batch* b, double* ms_host);
 void gila_batch_free(gila_batch* b);
 
 /* gila_batch_build + gila_batch_run + gila_batch_free. */
@@ -218,10 +223,12 @@ int gila_server_create(int32_t device, int64_t hbm_budget_bytes, int32_t max_slo
                        gila_server** out);
 
 /* Queue a job.  g_host is a host CSR, init_pos_host double[2n]; both and the
- * temperature array are copied before return.  All jobs of one server use
- * the precision of the first job submitted.  ticket receives the job id.
- * EINVAL for a malformed graph or parameters; ENOMEM if the job alone can
- * never fit the budget. */
+ * temperature array are copied before return.  ticket receives the job id.
+ * Returns EINVAL for bad parameters or out-of-range indices; the remaining
+ * graph rules (sorted rows, no self-loop, symmetry) are checked on the device
+ * when the job is admitted, and a violation fails the job with EINVAL (seen by
+ * gila_poll).  A job whose footprint bound exceeds the whole budget fails
+ * with ENOMEM; one that fits waits until enough memory is free. */
 int gila_submit(gila_server* s, const gila_csr* g_host, int32_t k, const gila_params* params,
                 const double* init_pos_host, uint64_t* ticket);
 
@@ -236,7 +243,17 @@ int gila_wait(gila_server* s, uint64_t ticket, double* out_pos_host, gila_stats*
 /* Cancel a queued or running job; its memory is released at the next tick. */
 int gila_cancel(gila_server* s, uint64_t ticket);
 
-/* Counters: jobs done, ticks run, peak resident jobs, device bytes in use. */
+/* Server settings: "tick_iterations" (iterations a resident job advances per
+ * tick, default 25), "small_max_vertices" (largest job laid out by the batched
+ * LDS-resident kernel; 0 = what fits in LDS), "fail_alloc_ticket" (test hook:
+ * the job with this ticket fails its device allocation with ENOMEM). */
+int gila_server_config(gila_server* s, const char* key, int64_t value);
+
+/* Queue wait and total latency (submit to completion, ms) of a finished job;
+ * GILA_EAGAIN before it finished.  Kept until the server is destroyed. */
+int gila_job_latency(gila_server* s, uint64_t ticket, double* queued_ms, double* total_ms);
+
+/* Counters: jobs done, ticks run, peak resident jobs, device bytes reserved. */
 int gila_server_info(gila_server* s, int64_t* jobs_done, int64_t* ticks, int32_t* peak_resident,
                      int64_t* bytes_in_use);
 

@@ -49,6 +49,8 @@ struct BatchArgs {
     const uint16_t* ci;        // local ids
     const double* temps;
     gila_stats* stats;         // [count], indexed like graphs
+    uint64_t* t_start;         // [count] device wall clock when the graph was taken
+    uint64_t* t_end;           // [count] ... and when its positions were written back
     int32_t* work;             // next graph (atomic)
 };
 
@@ -71,6 +73,7 @@ struct gila_batch {
     double* d_temps = nullptr;
     int64_t temps_cap = 0;
     gila_stats* d_stats = nullptr;
+    uint64_t* d_clock = nullptr;   // [2 * count]: start and end wall clock per graph
     int32_t* d_work = nullptr;
     std::vector<int32_t> order;
     hipGraphExec_t gexec = nullptr;
@@ -228,6 +231,7 @@ __global__ __launch_bounds__(kBatchBlock) void batch_layout_kernel(BatchArgs a) 
         if (gi >= a.count) break;
         const int gid = a.order[gi];
         const BatchDesc G = a.graphs[gid];
+        if (threadIdx.x == 0 && a.t_start) a.t_start[gid] = wall_clock64();
         V* cur = reinterpret_cast<V*>(s_raw);
         V* nxt = cur + G.n;
         const V* src = reinterpret_cast<const V*>(G.pos);
@@ -306,6 +310,11 @@ __global__ __launch_bounds__(kBatchBlock) void batch_layout_kernel(BatchArgs a) 
             a.stats[gid] = st;
         }
         __syncthreads();
+        if (threadIdx.x == 0 && a.t_end) {
+            __threadfence();
+            a.t_end[gid] = wall_clock64();
+        }
+        __syncthreads();
     }
 }
 
@@ -354,7 +363,7 @@ static bool autotune_enabled() {
     return !(e && e[0] == '0');
 }
 
-static size_t lds_bytes(int32_t nmax, int precision) {
+size_t batch_lds_bytes(int32_t nmax, int precision) {
     return (size_t)2 * (size_t)std::max(nmax, 1) * (precision == GILA_FP64 ? 16 : 8);
 }
 
@@ -440,7 +449,7 @@ static int autotune(gila_batch* b, int precision, hipStream_t s,
             rc = fail(GILA_EDEVICE, "autotune upload");
         float best_ms = 1e30f;
         int best = tt.lpv[precision][c];
-        const size_t lds = lds_bytes(nmax, precision);
+        const size_t lds = batch_lds_bytes(nmax, precision);
         set_lds_attr(lds);
         for (int lpv = 1; lpv <= 64 && !rc; lpv *= 2) {
             std::vector<BatchDesc> sub;
@@ -507,7 +516,7 @@ static int autotune(gila_batch* b, int precision, hipStream_t s,
     return rc;
 }
 
-static void free_batch(gila_batch* b) {
+void free_batch(gila_batch* b) {
     if (!b) return;
     DeviceGuard g(b->device);
     if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
@@ -519,6 +528,7 @@ static void free_batch(gila_batch* b) {
     dfree(b->d_order);
     dfree(b->d_temps);
     dfree(b->d_stats);
+    dfree(b->d_clock);
     dfree(b->d_work);
     delete b;
 }
@@ -534,8 +544,8 @@ struct DevTmp {
     ~DevTmp() { dfree(p); }
 };
 
-static int batch_build(const gila_csr* graphs, int32_t count, const int32_t* k, hipStream_t s,
-                       gila_batch** out) {
+int batch_build(const gila_csr* graphs, int32_t count, const int32_t* k, hipStream_t s,
+                gila_batch** out) {
     if (!out) return fail(GILA_EINVAL, "out is NULL");
     *out = nullptr;
     if (count < 0) return fail(GILA_EINVAL, "count must be >= 0");
@@ -674,6 +684,7 @@ static int batch_build(const gila_csr* graphs, int32_t count, const int32_t* k, 
     GILA_TRY(dalloc_t(&b->d_order, std::max(count, 1)));
     GILA_TRY(dalloc_t(&b->d_desc, std::max(count, 1)));
     GILA_TRY(dalloc_t(&b->d_stats, std::max(count, 1)));
+    GILA_TRY(dalloc_t(&b->d_clock, 2 * (size_t)std::max(count, 1)));
     if (count > 0)
         GILA_HIP(hipMemcpyAsync(b->d_order, b->order.data(), sizeof(int32_t) * count,
                                 hipMemcpyHostToDevice, s));
@@ -685,8 +696,8 @@ static int batch_build(const gila_csr* graphs, int32_t count, const int32_t* k, 
     return GILA_OK;
 }
 
-static int batch_run(gila_batch* b, const gila_params* params, void* const* pos, hipStream_t s,
-                     gila_stats* out) {
+int batch_run(gila_batch* b, const gila_params* params, void* const* pos, hipStream_t s,
+              gila_stats* out, bool use_graph) {
     const int32_t count = b->count;
     if (count == 0) return GILA_OK;
     if (!params || !pos) return fail(GILA_EINVAL, "params or pos is NULL");
@@ -699,7 +710,7 @@ static int batch_run(gila_batch* b, const gila_params* params, void* const* pos,
         if (b->n[i] > 0 && !pos[i]) return fail(GILA_EINVAL, "graph %d: pos is NULL", i);
         total_t += params[i].iterations;
     }
-    const size_t lds = lds_bytes(b->nmax, precision);
+    const size_t lds = batch_lds_bytes(b->nmax, precision);
     if (lds > device_info(b->device).max_lds_per_block - 2048)
         return fail(GILA_EUNSUPPORTED, "largest graph (%d vertices) does not fit in LDS",
                     b->nmax);
@@ -755,11 +766,17 @@ static int batch_run(gila_batch* b, const gila_params* params, void* const* pos,
     a.ci = b->ci16;
     a.temps = b->d_temps;
     a.stats = b->d_stats;
+    a.t_start = b->d_clock;
+    a.t_end = b->d_clock + count;
     a.work = b->d_work;
     const int grid = batch_grid(b, lds);
     const std::vector<uint64_t> key = {(uint64_t)precision, (uint64_t)lds, (uint64_t)grid,
                                        (uint64_t)(uintptr_t)b->d_temps};
-    if (!b->gexec || key != b->gkey) {
+    if (!use_graph) {
+        hipLaunchKernelGGL(reset_work_kernel, dim3(1), dim3(1), 0, s, b->d_work);
+        launch_batch_kernel(precision, grid, lds, s, a);
+        GILA_HIP(hipGetLastError());
+    } else if (!b->gexec || key != b->gkey) {
         if (b->gexec) {
             (void)hipGraphExecDestroy(b->gexec);
             b->gexec = nullptr;
@@ -785,7 +802,7 @@ static int batch_run(gila_batch* b, const gila_params* params, void* const* pos,
         }
         b->gkey = key;
     }
-    GILA_HIP(hipGraphLaunch(b->gexec, s));
+    if (use_graph) GILA_HIP(hipGraphLaunch(b->gexec, s));
     std::vector<gila_stats> st(count);
     GILA_HIP(hipMemcpyAsync(st.data(), b->d_stats, sizeof(gila_stats) * count,
                             hipMemcpyDeviceToHost, s));
@@ -812,7 +829,7 @@ int gila_batch_run(gila_batch* b, const gila_params* params, void* const* pos_de
     if (!b) return fail(GILA_EINVAL, "batch is NULL");
     std::lock_guard<std::mutex> lk(b->mu);
     DeviceGuard dg(b->device);
-    return batch_run(b, params, pos_dev, (hipStream_t)stream, out);
+    return batch_run(b, params, pos_dev, (hipStream_t)stream, out, true);
 }
 
 int gila_batch_info(const gila_batch* b, int32_t* count, int64_t* total_pairs,
@@ -821,6 +838,24 @@ int gila_batch_info(const gila_batch* b, int32_t* count, int64_t* total_pairs,
     if (count) *count = b->count;
     if (total_pairs) *total_pairs = b->P;
     if (device_bytes) *device_bytes = b->device_bytes;
+    return GILA_OK;
+}
+
+int gila_batch_latency(const gila_batch* b, double* ms_host) {
+    clear_error();
+    if (!b || !ms_host) return fail(GILA_EINVAL, "batch or output is NULL");
+    if (b->count == 0) return GILA_OK;
+    DeviceGuard dg(b->device);
+    std::vector<uint64_t> clk(2 * (size_t)b->count);
+    GILA_HIP(hipMemcpy(clk.data(), b->d_clock, sizeof(uint64_t) * clk.size(),
+                       hipMemcpyDeviceToHost));
+    int khz = 0;
+    GILA_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, b->device));
+    if (khz <= 0) return fail(GILA_EDEVICE, "no device wall clock rate");
+    uint64_t t0 = clk[0];
+    for (int32_t i = 0; i < b->count; ++i) t0 = std::min(t0, clk[i]);
+    for (int32_t i = 0; i < b->count; ++i)
+        ms_host[i] = (double)(clk[b->count + i] - t0) / (double)khz;
     return GILA_OK;
 }
 
@@ -835,7 +870,7 @@ int gila_layout_batch(const gila_csr* graphs_dev, int32_t count, const int32_t* 
     int rc;
     {
         std::lock_guard<std::mutex> lk(b->mu);
-        rc = batch_run(b, params, pos_dev, (hipStream_t)stream, out);
+        rc = batch_run(b, params, pos_dev, (hipStream_t)stream, out, false);
     }
     free_batch(b);
     return rc;

@@ -50,6 +50,19 @@ struct DeviceGuard {
     ~DeviceGuard();
 };
 
+// Phase timing of host-driven builds, printed to stderr when the environment
+// variable GILA_TIMING is 1 (each mark synchronises the stream).
+struct PhaseTimer {
+    const char* what;
+    hipStream_t stream;
+    bool on;
+    double t0, last;
+    std::string log;
+    PhaseTimer(const char* w, hipStream_t s);
+    void mark(const char* phase);
+    ~PhaseTimer();
+};
+
 // A library-owned, default-priority stream per device for graph capture.
 hipStream_t capture_stream(int device);
 
@@ -204,6 +217,8 @@ int launch_step(const gila_khop* kh, int precision, const StepArgs& a, hipStream
 int plan_iteration(gila_khop* kh, const std::vector<int64_t>& counts_internal,
                    const std::vector<int64_t>& rp_internal);
 // implemented in khop.hip
+int build_khop(const gila_csr* g, int32_t k, hipStream_t s, gila_khop** out);
+void free_khop(gila_khop* kh);
 int run_bfs(bool fill, int device, hipStream_t s, BfsArgs a);
 int launch_validate_csr(int32_t n, int64_t nnz, const int64_t* rp, const int32_t* ci, int32_t* flag,
                         hipStream_t s);
@@ -222,4 +237,15 @@ int prepare_precision(gila_khop* kh, int precision, hipStream_t s);
 int run_iterations(gila_khop* kh, const gila_params* p, int32_t start_h, int32_t end_h,
                    void* pos_dev, hipStream_t stream, gila_stats* out, bool use_graph);
 int check_params(const gila_params* p, bool need_temps);
+// Enqueues (no synchronisation) iterations [start_h, end_h) on pos_dev: reset
+// of the control block, permute in, the iterations, permute out.
+int enqueue_run(gila_khop* kh, const gila_params* p, int32_t start_h, int32_t end_h,
+                void* pos_dev, hipStream_t s);
+// implemented in batch.hip
+int batch_build(const gila_csr* graphs, int32_t count, const int32_t* k, hipStream_t s,
+                gila_batch** out);
+int batch_run(gila_batch* b, const gila_params* params, void* const* pos, hipStream_t s,
+              gila_stats* out, bool use_graph);
+void free_batch(gila_batch* b);
+size_t batch_lds_bytes(int32_t nmax, int precision);
 }  // namespace gila

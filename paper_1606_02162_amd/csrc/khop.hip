@@ -299,7 +299,7 @@ int run_bfs(bool fill, int device, hipStream_t s, BfsArgs a) {
     return rc;
 }
 
-static void free_khop(gila_khop* kh) {
+void free_khop(gila_khop* kh) {
     if (!kh) return;
     DeviceGuard g(kh->device);
     if (kh->gexec) (void)hipGraphExecDestroy(kh->gexec);
@@ -329,7 +329,7 @@ struct KhopHolder {
     ~KhopHolder() { free_khop(p); }
 };
 
-static int build_khop(const gila_csr* g, int32_t k, hipStream_t s, gila_khop** out) {
+int build_khop(const gila_csr* g, int32_t k, hipStream_t s, gila_khop** out) {
     if (!out) return fail(GILA_EINVAL, "out is NULL");
     *out = nullptr;
     if (!g) return fail(GILA_EINVAL, "graph is NULL");
@@ -343,6 +343,7 @@ static int build_khop(const gila_csr* g, int32_t k, hipStream_t s, gila_khop** o
     GILA_HIP(hipGetDevice(&dev));
     const int32_t n = g->n;
     const int64_t nnz = g->nnz;
+    PhaseTimer pt("build_khop", s);
 
     KhopHolder h{new gila_khop()};
     gila_khop* kh = h.p;
@@ -364,6 +365,7 @@ static int build_khop(const gila_csr* g, int32_t k, hipStream_t s, gila_khop** o
         if (nnz % 2) return fail(GILA_EINVAL, "nnz must be even for a symmetric CSR");
     }
 
+    pt.mark("rowptr");
     // --- device validation of every entry
     int32_t* d_flag = nullptr;
     int32_t* d_work = nullptr;
@@ -392,6 +394,7 @@ static int build_khop(const gila_csr* g, int32_t k, hipStream_t s, gila_khop** o
                     (flag & 8) ? " not symmetric" : "");
     }
 
+    pt.mark("validate");
     // --- count pass on the caller's graph
     const int32_t nwords = (n + 31) / 32;
     std::vector<int64_t> counts((size_t)n, 0);
@@ -417,6 +420,7 @@ static int build_khop(const gila_csr* g, int32_t k, hipStream_t s, gila_khop** o
         if (rc) return rc;
     }
 
+    pt.mark("count");
     // --- internal order: |N_v(k)| descending, ties by caller id
     std::vector<int32_t> perm((size_t)n), iperm((size_t)n);
     std::iota(perm.begin(), perm.end(), 0);
@@ -437,6 +441,7 @@ static int build_khop(const gila_csr* g, int32_t k, hipStream_t s, gila_khop** o
     kh->P = P;
     kh->n_active = n_active;
 
+    pt.mark("order");
     // --- internal graph copy
     GILA_TRY(dalloc_t(&kh->perm, (size_t)n));
     GILA_TRY(dalloc_t(&kh->iperm, (size_t)n));
@@ -458,6 +463,7 @@ static int build_khop(const gila_csr* g, int32_t k, hipStream_t s, gila_khop** o
         GILA_HIP(hipGetLastError());
     }
 
+    pt.mark("relabel");
     // --- internal adjacency rows in ascending order (a k = 1 fill pass)
     if (n_active > 0 && nnz > 0) {
         int32_t* ci_sorted = nullptr;
@@ -481,6 +487,7 @@ static int build_khop(const gila_csr* g, int32_t k, hipStream_t s, gila_khop** o
         kh->ci = ci_sorted;
     }
 
+    pt.mark("sort_adj");
     // --- fill pass on the internal graph (rows come out ascending)
     if (n_active > 0 && P > 0) {
         BfsArgs a{};
@@ -496,6 +503,7 @@ static int build_khop(const gila_csr* g, int32_t k, hipStream_t s, gila_khop** o
         GILA_TRY(run_bfs(true, dev, s, a));
     }
 
+    pt.mark("fill");
     // --- plan of the iteration kernel and its workspace
     GILA_TRY(plan_iteration(kh, cnt_int, rp_int));
     GILA_TRY(dalloc_t(reinterpret_cast<double**>(&kh->pos[0]), 2 * (size_t)std::max(n, 1)));
@@ -507,6 +515,7 @@ static int build_khop(const gila_csr* g, int32_t k, hipStream_t s, gila_khop** o
     GILA_HIP(hipStreamSynchronize(s));
     // segment-blocked lists for FP32 positions (the common case); FP64 runs
     // rebuild them for their own segment size on first use
+    pt.mark("plan");
     if (segment_path_enabled()) {
         const int src = build_segments(kh, GILA_FP32_KAHAN, s);
         if (src != GILA_OK && src != GILA_EUNSUPPORTED) return src;

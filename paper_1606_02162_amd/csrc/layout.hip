@@ -159,8 +159,8 @@ static void to_stats(const Ctl& c, gila_stats* out) {
 }
 
 // Enqueue: reset, permute in, iterations, permute out.
-static int enqueue_run(gila_khop* kh, const gila_params* p, int32_t start_h, int32_t end_h,
-                       void* pos_dev, hipStream_t s) {
+int enqueue_run(gila_khop* kh, const gila_params* p, int32_t start_h, int32_t end_h,
+                void* pos_dev, hipStream_t s) {
     hipLaunchKernelGGL(reset_ctl_kernel, dim3(1), dim3(1), 0, s, kh->ctl);
     GILA_HIP(hipGetLastError());
     GILA_TRY(launch_permute_in(kh, p->precision, pos_dev, s));

@@ -313,6 +313,7 @@ int build_segments(gila_khop* kh, int precision, hipStream_t st) {
     if (kh->nnz >= (int64_t)INT32_MAX) return fail(GILA_EUNSUPPORTED, "adjacency too large");
     const int32_t nseg = (int32_t)((na + (int64_t)S - 1) / S);
     const int64_t slots = (int64_t)nseg * na;
+    PhaseTimer pt("build_segments", st);
 
     int32_t *d_kc = nullptr, *d_ac = nullptr;
     GILA_TRY(dalloc_t(&d_kc, (size_t)slots));
@@ -336,6 +337,7 @@ int build_segments(gila_khop* kh, int precision, hipStream_t st) {
     } kc_guard{d_kc};
     if (e1 || e2 || e3 || e4) return fail(GILA_EDEVICE, "segment count failed");
 
+    pt.mark("count");
     // segment-major offsets
     std::vector<int64_t> skp((size_t)slots + 1);
     std::vector<int32_t> sap((size_t)slots + 1);
@@ -376,6 +378,7 @@ int build_segments(gila_khop* kh, int precision, hipStream_t st) {
             }
         }
     }
+    pt.mark("plan");
     kh->seg = S;
     kh->nseg = nseg;
     kh->seg_grid = (int32_t)plan.size();
@@ -394,6 +397,7 @@ int build_segments(gila_khop* kh, int precision, hipStream_t st) {
         GILA_TRY(dalloc_t(&kh->partials, (size_t)kh->comb_grid));
         kh->partials_cap = kh->comb_grid;
     }
+    pt.mark("alloc");
     GILA_HIP(hipMemcpyAsync(kh->sk_ptr, skp.data(), sizeof(int64_t) * (slots + 1),
                             hipMemcpyHostToDevice, st));
     GILA_HIP(hipMemcpyAsync(kh->sa_ptr, sap.data(), sizeof(int32_t) * (slots + 1),
@@ -404,6 +408,7 @@ int build_segments(gila_khop* kh, int precision, hipStream_t st) {
                        kh->kptr, kh->kidx, kh->rp, kh->ci, d_kc, kh->sk_ptr, kh->sk_idx,
                        kh->sa_ptr, kh->sa_idx);
     GILA_HIP(hipGetLastError());
+    pt.mark("upload+fill");
     const size_t lds = (size_t)(S + 1) * pos_bytes;
     if (lds > 48 * 1024) {
         (void)hipFuncSetAttribute((const void*)seg_force_kernel<GILA_FP64>,

@@ -1,26 +1,595 @@
-// Continuous-batching layout server (placeholder until implemented).
+// Layout server: continuous batching of layout jobs on one GPU.
+//
+// Jobs (host graph, k, parameters, initial positions) are queued by
+// gila_submit.  One scheduler thread owns all device work and loops in ticks:
+//   1. every resident large job gets its next `tick_iterations` iterations
+//      enqueued on the compute stream (asynchronously);
+//   2. while that runs, queued jobs are admitted in arrival order as slots and
+//      HBM budget allow: their graphs are uploaded and their k-hop lists built
+//      on a second stream.  Jobs small enough for the LDS-resident batch kernel
+//      are laid out right away, together, in one batched launch on that
+//      stream; larger ones become resident and join the next tick;
+//   3. the scheduler waits for the tick, reads each large job's control block
+//      and retires jobs that finished (all iterations, or the halting rule).
+// A job's arithmetic depends only on its own graph and parameters (the
+// iteration plan is per graph; ticks split a run without changing its bits),
+// so each result is the same alone and in any mix of concurrent jobs.
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstdlib>
+#include <deque>
+#include <map>
+#include <thread>
+
 #include "gila_internal.h"
+
+namespace gila {
+
+enum JobState { kPending = 0, kResident = 1, kDone = 2, kFailed = 3, kCanceled = 4 };
+
+struct Job {
+    uint64_t id = 0;
+    int32_t k = 0;
+    int32_t n = 0;
+    int64_t nnz = 0;
+    gila_params params{};
+    std::vector<double> temps;
+    std::vector<int64_t> rp;
+    std::vector<int32_t> ci;
+    std::vector<double> init;
+    std::vector<double> result;
+    int state = kPending;
+    int status = GILA_OK;
+    std::atomic<bool> cancel{false};
+    bool small = false;
+    int64_t footprint = 0;
+    // device state of a resident job
+    int64_t* d_rp = nullptr;
+    int32_t* d_ci = nullptr;
+    void* d_pos = nullptr;
+    gila_khop* kh = nullptr;
+    int32_t h = 0;
+    int32_t h_target = 0;
+    int lane = 0;  // which compute stream the job's ticks run on
+    gila_stats stats{};
+    double t_submit = 0.0, t_admit = 0.0, t_done = 0.0;
+};
+
+static double now_s() {
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+// Upper bound of P = sum_v |N_v(k)| from the adjacency alone: the number of
+// walks of length <= k from v, capped at n - 1 per vertex.
+static int64_t pairs_upper_bound(const Job& j) {
+    const int32_t n = j.n;
+    std::vector<int64_t> cur(n), nxt(n), tot(n);
+    for (int32_t v = 0; v < n; ++v) cur[v] = tot[v] = j.rp[v + 1] - j.rp[v];
+    for (int32_t level = 2; level <= j.k; ++level) {
+        for (int32_t v = 0; v < n; ++v) {
+            int64_t s = 0;
+            for (int64_t e = j.rp[v]; e < j.rp[v + 1]; ++e) s += cur[j.ci[e]];
+            nxt[v] = std::min<int64_t>(s, (int64_t)n);
+            tot[v] = std::min<int64_t>(tot[v] + nxt[v], (int64_t)n - 1);
+        }
+        cur.swap(nxt);
+    }
+    int64_t P = 0;
+    for (int32_t v = 0; v < n; ++v) P += tot[v];
+    return P;
+}
+
+// Bytes a job may hold on the device: graph, positions, lists (int32 and
+// 16-bit padded copies), per-slice offsets and partials (bounded by the lists).
+static int64_t footprint_bytes(const Job& j) {
+    const int64_t P = pairs_upper_bound(j);
+    return 64ll * j.n + 16ll * j.nnz + 8ll * P + (1ll << 20);
+}
+
+}  // namespace gila
+
+struct gila_server {
+    int device = 0;
+    int64_t budget = 0;
+    int32_t max_slots = 1;
+    int32_t tick_iters = 25;
+    int32_t small_max_n = 0;         // 0 = what fits the batch kernel's LDS
+    std::atomic<uint64_t> fail_alloc_ticket{0};  // test hook: this job's allocation fails
+    std::mutex mu;
+    std::condition_variable cv;       // wakes the scheduler
+    std::condition_variable cv_done;  // wakes waiters
+    std::deque<uint64_t> pending;
+    std::map<uint64_t, gila::Job*> jobs;
+    std::map<uint64_t, std::pair<double, double>> times;  // queued ms, total ms
+    std::vector<gila::Job*> resident;
+    uint64_t next_id = 1;
+    int64_t reserved = 0;
+    int32_t in_flight = 0;
+    bool stop = false;
+    std::thread th;
+    static constexpr int kComputeStreams = 3;
+    hipStream_t compute[kComputeStreams] = {nullptr, nullptr, nullptr};
+    hipStream_t build = nullptr;
+    int64_t jobs_done = 0, ticks = 0;
+    int32_t peak_resident = 0;
+};
+
+namespace gila {
+
+static void release_device(Job* j) {
+    if (j->kh) free_khop(j->kh);
+    dfree(j->d_rp);
+    dfree(j->d_ci);
+    dfree(j->d_pos);
+    j->kh = nullptr;
+    j->d_rp = nullptr;
+    j->d_ci = nullptr;
+    j->d_pos = nullptr;
+}
+
+// Scheduler-side completion (mutex held by the caller).
+static void finish_job(gila_server* s, Job* j, int state, int status) {
+    j->state = state;
+    j->status = status;
+    j->t_done = now_s();
+    s->reserved -= j->footprint;
+    s->in_flight -= 1;
+    if (state == kDone) s->jobs_done += 1;
+    s->times[j->id] = {(j->t_admit - j->t_submit) * 1e3, (j->t_done - j->t_submit) * 1e3};
+    s->cv_done.notify_all();
+}
+
+static int upload_job(gila_server* s, Job* j, hipStream_t st) {
+    if (s->fail_alloc_ticket == j->id) return fail(GILA_ENOMEM, "injected allocation failure");
+    const size_t pb = j->params.precision == GILA_FP64 ? 16 : 8;
+    GILA_TRY(dalloc_t(&j->d_rp, (size_t)j->n + 1));
+    GILA_TRY(dalloc_t(&j->d_ci, (size_t)std::max<int64_t>(j->nnz, 1)));
+    GILA_TRY(dalloc(&j->d_pos, (size_t)std::max(j->n, 1) * pb));
+    GILA_HIP(hipMemcpyAsync(j->d_rp, j->rp.data(), sizeof(int64_t) * (j->n + 1),
+                            hipMemcpyHostToDevice, st));
+    if (j->nnz > 0)
+        GILA_HIP(hipMemcpyAsync(j->d_ci, j->ci.data(), sizeof(int32_t) * j->nnz,
+                                hipMemcpyHostToDevice, st));
+    if (pb == 16) {
+        GILA_HIP(hipMemcpyAsync(j->d_pos, j->init.data(), sizeof(double) * 2 * j->n,
+                                hipMemcpyHostToDevice, st));
+    } else {
+        std::vector<float> f((size_t)2 * j->n);
+        for (size_t i = 0; i < f.size(); ++i) f[i] = (float)j->init[i];
+        GILA_HIP(hipMemcpyAsync(j->d_pos, f.data(), sizeof(float) * f.size(),
+                                hipMemcpyHostToDevice, st));
+        GILA_HIP(hipStreamSynchronize(st));  // f leaves scope
+    }
+    return GILA_OK;
+}
+
+static int download_positions(Job* j, hipStream_t st) {
+    j->result.assign((size_t)2 * j->n, 0.0);
+    if (j->n == 0) return GILA_OK;
+    if (j->params.precision == GILA_FP64) {
+        GILA_HIP(hipMemcpyAsync(j->result.data(), j->d_pos, sizeof(double) * 2 * j->n,
+                                hipMemcpyDeviceToHost, st));
+        GILA_HIP(hipStreamSynchronize(st));
+    } else {
+        std::vector<float> f((size_t)2 * j->n);
+        GILA_HIP(hipMemcpyAsync(f.data(), j->d_pos, sizeof(float) * f.size(),
+                                hipMemcpyDeviceToHost, st));
+        GILA_HIP(hipStreamSynchronize(st));
+        for (size_t i = 0; i < f.size(); ++i) j->result[i] = f[i];
+    }
+    return GILA_OK;
+}
+
+// Lays out a group of small jobs of one precision in one batched launch.
+static void run_small_group(gila_server* s, std::vector<Job*>& group) {
+    std::vector<gila_csr> csr;
+    std::vector<int32_t> ks;
+    std::vector<gila_params> ps;
+    std::vector<void*> pos;
+    std::vector<Job*> ok;
+    for (Job* j : group) {
+        const int rc = upload_job(s, j, s->build);
+        if (rc != GILA_OK) {
+            release_device(j);
+            std::lock_guard<std::mutex> lk(s->mu);
+            finish_job(s, j, kFailed, rc);
+            continue;
+        }
+        gila_csr c{j->n, j->nnz, j->d_rp, j->d_ci};
+        csr.push_back(c);
+        ks.push_back(j->k);
+        ps.push_back(j->params);
+        pos.push_back(j->d_pos);
+        ok.push_back(j);
+    }
+    if (ok.empty()) return;
+    std::vector<gila_stats> st(ok.size());
+    std::vector<int> rcs(ok.size(), GILA_OK);
+    auto run_range = [&](size_t lo, size_t hi) {
+        gila_batch* b = nullptr;
+        const int32_t cnt = (int32_t)(hi - lo);
+        int rc = batch_build(&csr[lo], cnt, &ks[lo], s->build, &b);
+        if (rc == GILA_OK) rc = batch_run(b, &ps[lo], &pos[lo], s->build, &st[lo], false);
+        if (b) free_batch(b);
+        for (size_t i = lo; i < hi; ++i) rcs[i] = rc;
+        return rc;
+    };
+    // one launch for the group; if it is refused (say one graph is malformed)
+    // each job runs on its own, so only the offending job fails
+    if (run_range(0, ok.size()) != GILA_OK && ok.size() > 1)
+        for (size_t i = 0; i < ok.size(); ++i) run_range(i, i + 1);
+    for (size_t i = 0; i < ok.size(); ++i) {
+        Job* j = ok[i];
+        int r = rcs[i];
+        if (r == GILA_OK) r = download_positions(j, s->build);
+        release_device(j);
+        std::lock_guard<std::mutex> lk(s->mu);
+        j->stats = st[i];
+        finish_job(s, j, j->cancel ? kCanceled : (r == GILA_OK ? kDone : kFailed),
+                   j->cancel ? GILA_ECANCELED : r);
+    }
+}
+
+static int admit_large(gila_server* s, Job* j) {
+    GILA_TRY(upload_job(s, j, s->build));
+    gila_csr c{j->n, j->nnz, j->d_rp, j->d_ci};
+    GILA_TRY(build_khop(&c, j->k, s->build, &j->kh));
+    GILA_TRY(prepare_precision(j->kh, j->params.precision, s->build));
+    GILA_HIP(hipStreamSynchronize(s->build));
+    j->h = 0;
+    return GILA_OK;
+}
+
+// Admits queued jobs in arrival order while slots and budget allow.  Small
+// jobs are laid out at once (batched); large ones become resident.
+static void admit(gila_server* s) {
+    std::map<int, std::vector<Job*>> small_groups;
+    std::vector<Job*> large;
+    // footprint bounds of newly queued jobs, computed outside the lock (a
+    // queued job is never deleted, so the pointers stay valid)
+    std::vector<Job*> fresh;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        for (uint64_t id : s->pending)
+            if (s->jobs[id]->footprint < 0) fresh.push_back(s->jobs[id]);
+    }
+    for (Job* j : fresh) {
+        const int64_t f = footprint_bytes(*j);
+        std::lock_guard<std::mutex> lk(s->mu);
+        j->footprint = f;
+    }
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        while (!s->pending.empty()) {
+            Job* j = s->jobs[s->pending.front()];
+            if (j->cancel) {
+                s->pending.pop_front();
+                j->state = kCanceled;
+                j->status = GILA_ECANCELED;
+                j->t_done = now_s();
+                s->cv_done.notify_all();
+                continue;
+            }
+            if (j->footprint < 0) break;  // arrived after the bounds were taken
+            if (j->footprint > s->budget) {
+                s->pending.pop_front();
+                j->state = kFailed;
+                j->status = GILA_ENOMEM;
+                j->t_done = now_s();
+                s->cv_done.notify_all();
+                continue;
+            }
+            if (s->in_flight >= s->max_slots || s->reserved + j->footprint > s->budget) break;
+            s->pending.pop_front();
+            s->reserved += j->footprint;
+            s->in_flight += 1;
+            j->state = kResident;
+            j->t_admit = now_s();
+            if (j->small) small_groups[j->params.precision].push_back(j);
+            else large.push_back(j);
+        }
+    }
+    for (Job* j : large) {
+        const int rc = admit_large(s, j);
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (rc != GILA_OK) {
+            release_device(j);
+            finish_job(s, j, kFailed, rc);
+        } else {
+            j->lane = (int)(j->id % gila_server::kComputeStreams);
+            s->resident.push_back(j);
+            s->peak_resident = std::max<int32_t>(s->peak_resident, (int32_t)s->resident.size());
+        }
+    }
+    for (auto& kv : small_groups) run_small_group(s, kv.second);
+}
+
+static void scheduler(gila_server* s) {
+    (void)hipSetDevice(s->device);
+    constexpr int NC = gila_server::kComputeStreams;
+    hipEvent_t tick_done[NC] = {nullptr, nullptr, nullptr};
+    for (int c = 0; c < NC; ++c) (void)hipEventCreateWithFlags(&tick_done[c], hipEventDisableTiming);
+    for (;;) {
+        std::vector<Job*> active;
+        int32_t tick_iters = 1;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            s->cv.wait(lk, [&] { return s->stop || !s->pending.empty() || !s->resident.empty(); });
+            if (s->stop) break;
+            active = s->resident;
+            tick_iters = s->tick_iters;
+        }
+        // 1. next iterations of every resident job, asynchronously
+        std::vector<int> enq_rc(active.size(), GILA_OK);
+        for (size_t i = 0; i < active.size(); ++i) {
+            Job* j = active[i];
+            if (j->cancel) continue;
+            j->h_target = std::min(j->h + tick_iters, j->params.iterations);
+            enq_rc[i] = enqueue_run(j->kh, &j->params, j->h, j->h_target, j->d_pos,
+                                    s->compute[j->lane]);
+        }
+        for (int c = 0; c < NC; ++c) (void)hipEventRecord(tick_done[c], s->compute[c]);
+        // 2. admissions overlap with the tick
+        admit(s);
+        // 3. retire finished jobs
+        hipError_t we = hipSuccess;
+        for (int c = 0; c < NC; ++c) {
+            const hipError_t e = hipEventSynchronize(tick_done[c]);
+            if (e != hipSuccess) we = e;
+        }
+        std::vector<Job*> keep;
+        for (size_t i = 0; i < active.size(); ++i) {
+            Job* j = active[i];
+            int rc = we == hipSuccess ? enq_rc[i] : GILA_EDEVICE;
+            bool finished = j->cancel || rc != GILA_OK;
+            if (!finished) {
+                Ctl c{};
+                if (hipMemcpy(&c, j->kh->ctl, sizeof(Ctl), hipMemcpyDeviceToHost) != hipSuccess) {
+                    rc = GILA_EDEVICE;
+                    finished = true;
+                } else {
+                    j->stats.iterations_run += j->h_target > j->h ? c.iters_run : 0;
+                    j->stats.stopped = c.stopped;
+                    if (j->h_target > j->h) {
+                        j->stats.moved = c.moved;
+                        j->stats.max_disp = c.max_disp;
+                        j->stats.energy = c.energy;
+                        j->stats.coincident = c.coincident;
+                    }
+                    j->h = j->h_target;
+                    finished = c.stopped || j->h >= j->params.iterations;
+                    if (finished) rc = download_positions(j, s->compute[j->lane]);
+                }
+            }
+            if (!finished) {
+                keep.push_back(j);
+                continue;
+            }
+            release_device(j);
+            std::lock_guard<std::mutex> lk(s->mu);
+            finish_job(s, j, j->cancel ? kCanceled : (rc == GILA_OK ? kDone : kFailed),
+                       j->cancel ? GILA_ECANCELED : rc);
+        }
+        std::lock_guard<std::mutex> lk(s->mu);
+        // jobs admitted during this tick were appended after `active`
+        std::vector<Job*> added(s->resident.begin() + (ptrdiff_t)active.size(), s->resident.end());
+        s->resident = keep;
+        s->resident.insert(s->resident.end(), added.begin(), added.end());
+        s->ticks += 1;
+    }
+    for (int c = 0; c < NC; ++c) (void)hipEventDestroy(tick_done[c]);
+}
+
+// Cheap host checks at submission (every index in range, so the footprint
+// bound can walk the graph); sortedness, self-loops and symmetry are checked
+// on the device when the job is admitted.
+static int validate_host_csr(const gila_csr* g) {
+    if (!g) return fail(GILA_EINVAL, "graph is NULL");
+    if (g->n < 0 || g->nnz < 0 || g->nnz % 2) return fail(GILA_EINVAL, "bad n or nnz");
+    if (g->n > 0 && !g->row_ptr) return fail(GILA_EINVAL, "row_ptr is NULL");
+    if (g->nnz > 0 && !g->col_idx) return fail(GILA_EINVAL, "col_idx is NULL");
+    if (g->n > 0 && (g->row_ptr[0] != 0 || g->row_ptr[g->n] != g->nnz))
+        return fail(GILA_EINVAL, "row_ptr must run from 0 to nnz");
+    for (int32_t v = 0; v < g->n; ++v)
+        if (g->row_ptr[v + 1] < g->row_ptr[v]) return fail(GILA_EINVAL, "row_ptr not monotone");
+    for (int64_t e = 0; e < g->nnz; ++e)
+        if (g->col_idx[e] < 0 || g->col_idx[e] >= g->n)
+            return fail(GILA_EINVAL, "column out of range");
+    return GILA_OK;
+}
+
+}  // namespace gila
 
 using namespace gila;
 
 extern "C" {
-int gila_server_create(int32_t, int64_t, int32_t, gila_server** out) {
-    if (out) *out = nullptr;
-    return fail(GILA_EUNSUPPORTED, "server not built yet");
+
+int gila_server_create(int32_t device, int64_t hbm_budget_bytes, int32_t max_slots,
+                       gila_server** out) {
+    clear_error();
+    if (!out) return fail(GILA_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (max_slots < 1) return fail(GILA_EINVAL, "max_slots must be >= 1");
+    if (hbm_budget_bytes < 0) return fail(GILA_EINVAL, "negative budget");
+    int ndev = 0;
+    GILA_HIP(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) return fail(GILA_EINVAL, "no device %d", device);
+    DeviceGuard dg(device);
+    gila_server* s = new gila_server();
+    s->device = device;
+    s->max_slots = max_slots;
+    if (hbm_budget_bytes == 0) {
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+            delete s;
+            return fail(GILA_EDEVICE, "hipMemGetInfo failed");
+        }
+        hbm_budget_bytes = (int64_t)(0.9 * (double)fr);
+    }
+    s->budget = hbm_budget_bytes;
+    bool ok = hipStreamCreateWithFlags(&s->build, hipStreamNonBlocking) == hipSuccess;
+    for (int c = 0; c < gila_server::kComputeStreams && ok; ++c)
+        ok = hipStreamCreateWithFlags(&s->compute[c], hipStreamNonBlocking) == hipSuccess;
+    if (!ok) {
+        for (int c = 0; c < gila_server::kComputeStreams; ++c)
+            if (s->compute[c]) (void)hipStreamDestroy(s->compute[c]);
+        if (s->build) (void)hipStreamDestroy(s->build);
+        delete s;
+        return fail(GILA_EDEVICE, "cannot create streams");
+    }
+    s->th = std::thread(scheduler, s);
+    *out = s;
+    return GILA_OK;
 }
-int gila_submit(gila_server*, const gila_csr*, int32_t, const gila_params*, const double*,
-                uint64_t*) {
-    return fail(GILA_EUNSUPPORTED, "server not built yet");
+
+int gila_server_config(gila_server* s, const char* key, int64_t value) {
+    clear_error();
+    if (!s || !key) return fail(GILA_EINVAL, "server or key is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (!std::strcmp(key, "tick_iterations")) {
+        if (value < 1) return fail(GILA_EINVAL, "tick_iterations must be >= 1");
+        s->tick_iters = (int32_t)value;
+    } else if (!std::strcmp(key, "small_max_vertices")) {
+        if (value < 0) return fail(GILA_EINVAL, "small_max_vertices must be >= 0");
+        s->small_max_n = (int32_t)value;
+    } else if (!std::strcmp(key, "fail_alloc_ticket")) {
+        s->fail_alloc_ticket = (uint64_t)value;
+    } else {
+        return fail(GILA_EINVAL, "unknown key '%s'", key);
+    }
+    return GILA_OK;
 }
-int gila_poll(gila_server*, uint64_t, double*, gila_stats*) {
-    return fail(GILA_EUNSUPPORTED, "server not built yet");
+
+int gila_submit(gila_server* s, const gila_csr* g_host, int32_t k, const gila_params* params,
+                const double* init_pos_host, uint64_t* ticket) {
+    clear_error();
+    if (!s || !ticket) return fail(GILA_EINVAL, "server or ticket is NULL");
+    if (k < 1) return fail(GILA_EINVAL, "k must be >= 1");
+    GILA_TRY(validate_host_csr(g_host));
+    GILA_TRY(check_params(params, true));
+    if (g_host->n > 0 && !init_pos_host) return fail(GILA_EINVAL, "init_pos_host is NULL");
+    Job* j = new Job();
+    j->k = k;
+    j->n = g_host->n;
+    j->nnz = g_host->nnz;
+    j->rp.assign(g_host->row_ptr, g_host->row_ptr + (g_host->n > 0 ? g_host->n + 1 : 0));
+    if (j->rp.empty()) j->rp.push_back(0);
+    j->ci.assign(g_host->col_idx, g_host->col_idx + g_host->nnz);
+    j->init.assign(init_pos_host, init_pos_host + 2 * (size_t)g_host->n);
+    j->temps.assign(params->temperature, params->temperature + params->iterations);
+    j->params = *params;
+    j->params.temperature = j->temps.data();
+    j->footprint = -1;  // computed by the scheduler when the job is first considered
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        int32_t lim = s->small_max_n;
+        if (lim == 0) {
+            const size_t cap = device_info(s->device).max_lds_per_block - 2048;
+            const size_t per = 2 * (params->precision == GILA_FP64 ? 16 : 8);
+            lim = (int32_t)std::min<size_t>(65535, cap / per);
+        }
+        j->small = j->n <= lim;
+        j->id = s->next_id++;
+        j->t_submit = now_s();
+        s->jobs[j->id] = j;
+        s->pending.push_back(j->id);
+        *ticket = j->id;
+    }
+    s->cv.notify_one();
+    return GILA_OK;
 }
-int gila_wait(gila_server*, uint64_t, double*, gila_stats*) {
-    return fail(GILA_EUNSUPPORTED, "server not built yet");
+
+static int take_result(gila_server* s, Job* j, double* out_pos, gila_stats* out) {
+    // mutex held
+    const int state = j->state, status = j->status;
+    if (state == kDone) {
+        if (out_pos && j->n > 0) std::memcpy(out_pos, j->result.data(), sizeof(double) * 2 * j->n);
+        if (out) *out = j->stats;
+    }
+    s->jobs.erase(j->id);
+    delete j;
+    if (state == kDone) return GILA_OK;
+    if (state == kCanceled) return fail(GILA_ECANCELED, "job was cancelled");
+    return fail(status, "job failed: %s", gila_strerror(status));
 }
-int gila_cancel(gila_server*, uint64_t) { return fail(GILA_EUNSUPPORTED, "server not built yet"); }
-int gila_server_info(gila_server*, int64_t*, int64_t*, int32_t*, int64_t*) {
-    return fail(GILA_EUNSUPPORTED, "server not built yet");
+
+int gila_poll(gila_server* s, uint64_t ticket, double* out_pos_host, gila_stats* out) {
+    clear_error();
+    if (!s) return fail(GILA_EINVAL, "server is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->jobs.find(ticket);
+    if (it == s->jobs.end()) return fail(GILA_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+    Job* j = it->second;
+    if (j->state == kPending || j->state == kResident) return GILA_EAGAIN;
+    return take_result(s, j, out_pos_host, out);
 }
-void gila_server_destroy(gila_server*) {}
+
+int gila_wait(gila_server* s, uint64_t ticket, double* out_pos_host, gila_stats* out) {
+    clear_error();
+    if (!s) return fail(GILA_EINVAL, "server is NULL");
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->jobs.find(ticket);
+    if (it == s->jobs.end()) return fail(GILA_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+    Job* j = it->second;
+    s->cv_done.wait(lk, [&] { return j->state != kPending && j->state != kResident; });
+    return take_result(s, j, out_pos_host, out);
 }
+
+int gila_cancel(gila_server* s, uint64_t ticket) {
+    clear_error();
+    if (!s) return fail(GILA_EINVAL, "server is NULL");
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        auto it = s->jobs.find(ticket);
+        if (it == s->jobs.end()) return fail(GILA_EINVAL, "unknown ticket");
+        it->second->cancel = true;
+    }
+    s->cv.notify_one();
+    return GILA_OK;
+}
+
+int gila_job_latency(gila_server* s, uint64_t ticket, double* queued_ms, double* total_ms) {
+    clear_error();
+    if (!s) return fail(GILA_EINVAL, "server is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->times.find(ticket);
+    if (it == s->times.end()) return fail(GILA_EAGAIN, "job %llu has not finished",
+                                          (unsigned long long)ticket);
+    if (queued_ms) *queued_ms = it->second.first;
+    if (total_ms) *total_ms = it->second.second;
+    return GILA_OK;
+}
+
+int gila_server_info(gila_server* s, int64_t* jobs_done, int64_t* ticks, int32_t* peak_resident,
+                     int64_t* bytes_in_use) {
+    if (!s) return fail(GILA_EINVAL, "server is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (jobs_done) *jobs_done = s->jobs_done;
+    if (ticks) *ticks = s->ticks;
+    if (peak_resident) *peak_resident = s->peak_resident;
+    if (bytes_in_use) *bytes_in_use = s->reserved;
+    return GILA_OK;
+}
+
+void gila_server_destroy(gila_server* s) {
+    if (!s) return;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+    }
+    s->cv.notify_all();
+    if (s->th.joinable()) s->th.join();
+    DeviceGuard dg(s->device);
+    for (int c = 0; c < gila_server::kComputeStreams; ++c) (void)hipStreamSynchronize(s->compute[c]);
+    (void)hipStreamSynchronize(s->build);
+    for (Job* j : s->resident) release_device(j);
+    for (auto& kv : s->jobs) delete kv.second;
+    for (int c = 0; c < gila_server::kComputeStreams; ++c) (void)hipStreamDestroy(s->compute[c]);
+    (void)hipStreamDestroy(s->build);
+    delete s;
+}
+
+}  // extern "C"

@@ -1,5 +1,7 @@
 // Error reporting, device helpers and small ABI functions of libgila.
+#include <chrono>
 #include <cstdio>
+#include <cstdlib>
 #include <map>
 
 #include "device_util.h"
@@ -78,6 +80,32 @@ int exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t s
     return GILA_OK;
 }
 
+static double wall_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+PhaseTimer::PhaseTimer(const char* w, hipStream_t s) : what(w), stream(s) {
+    const char* e = getenv("GILA_TIMING");
+    on = e && e[0] == '1';
+    t0 = last = on ? wall_s() : 0.0;
+}
+
+void PhaseTimer::mark(const char* phase) {
+    if (!on) return;
+    (void)hipStreamSynchronize(stream);
+    const double t = wall_s();
+    char buf[128];
+    snprintf(buf, sizeof(buf), " %s=%.2f", phase, (t - last) * 1e3);
+    log += buf;
+    last = t;
+}
+
+PhaseTimer::~PhaseTimer() {
+    if (on) fprintf(stderr, "[gila timing] %s total=%.2f ms:%s\n", what, (wall_s() - t0) * 1e3,
+                    log.c_str());
+}
+
 static thread_local std::string t_last_error;
 
 int fail(int code, const char* fmt, ...) {
@@ -118,16 +146,24 @@ DeviceGuard::~DeviceGuard() {
 }
 
 static std::mutex g_mu;
-static std::map<int, hipStream_t> g_capture_streams;
 static std::map<int, DeviceInfo> g_info;
 
+// Capture streams are per thread (captures on one stream from two threads
+// would interleave) and are destroyed when the thread exits.
+struct CaptureStreams {
+    std::map<int, hipStream_t> by_device;
+    ~CaptureStreams() {
+        for (auto& kv : by_device) (void)hipStreamDestroy(kv.second);
+    }
+};
+static thread_local CaptureStreams t_capture;
+
 hipStream_t capture_stream(int device) {
-    std::lock_guard<std::mutex> lk(g_mu);
-    auto it = g_capture_streams.find(device);
-    if (it != g_capture_streams.end()) return it->second;
+    auto it = t_capture.by_device.find(device);
+    if (it != t_capture.by_device.end()) return it->second;
     hipStream_t s = nullptr;
     if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return nullptr;
-    g_capture_streams[device] = s;
+    t_capture.by_device[device] = s;
     return s;
 }
 

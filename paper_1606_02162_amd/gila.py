@@ -85,8 +85,11 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "gila_batch_run": (ctypes.c_int, [vp, vp, vp, vp, vp]),
         "gila_batch_info": (ctypes.c_int, [vp, P(i32), P(i64), P(i64)]),
         "gila_batch_free": (None, [vp]),
+        "gila_batch_latency": (ctypes.c_int, [vp, vp]),
         "gila_layout_batch": (ctypes.c_int, [vp, i32, vp, vp, vp, vp, vp]),
         "gila_server_create": (ctypes.c_int, [i32, i64, i32, P(vp)]),
+        "gila_server_config": (ctypes.c_int, [vp, ctypes.c_char_p, i64]),
+        "gila_job_latency": (ctypes.c_int, [vp, u64, P(dbl), P(dbl)]),
         "gila_submit": (ctypes.c_int, [vp, P(Csr), i32, P(_Params), vp, P(u64)]),
         "gila_poll": (ctypes.c_int, [vp, u64, vp, P(Stats)]),
         "gila_wait": (ctypes.c_int, [vp, u64, vp, P(Stats)]),
@@ -343,6 +346,12 @@ class Batch:
                                    _addr(stats)), "gila_batch_run")
         return [stats[i] for i in range(self.count)]
 
+    def latency_ms(self) -> np.ndarray:
+        """Per-graph completion time (ms) of the last run, from its first start."""
+        out = np.zeros(max(self.count, 1), dtype=np.float64)
+        _check(_lib.gila_batch_latency(self._h, out.ctypes.data), "gila_batch_latency")
+        return out[: self.count]
+
     def free(self):
         if self._h:
             _lib.gila_batch_free(self._h)
@@ -372,3 +381,85 @@ def layout_batch(graphs, k, params, pos, stream=None):
     _check(_lib.gila_layout_batch(_addr(csr), count, _addr(kk), _addr(structs), _addr(ptrs),
                                   _stream(stream), _addr(stats)), "gila_layout_batch")
     return [stats[i] for i in range(count)]
+
+
+# ---------------------------------------------------------------- serving
+class Server:
+    """Continuous-batching layout server (gila_server_*).  Jobs are host
+    graphs (``inputs.Graph`` or any object with n, row_ptr, col_idx) with host
+    initial positions (float64 [n, 2])."""
+
+    def __init__(self, device: int = 0, budget_bytes: int = 0, max_slots: int = 64):
+        self._h = ctypes.c_void_p()
+        _check(_lib.gila_server_create(int(device), int(budget_bytes), int(max_slots),
+                                       ctypes.byref(self._h)), "gila_server_create")
+        self._keep = {}
+
+    def config(self, key: str, value: int):
+        _check(_lib.gila_server_config(self._h, key.encode(), int(value)), "gila_server_config")
+
+    def submit(self, graph, k: int, params: LayoutParams, init_pos) -> int:
+        rp = np.ascontiguousarray(graph.row_ptr, dtype=np.int64)
+        ci = np.ascontiguousarray(graph.col_idx, dtype=np.int32)
+        x = np.ascontiguousarray(init_pos, dtype=np.float64).reshape(-1)
+        csr = make_csr(rp, ci, int(graph.n))
+        p = params.as_struct()
+        t = ctypes.c_uint64()
+        _check(_lib.gila_submit(self._h, ctypes.byref(csr), int(k), ctypes.byref(p),
+                                x.ctypes.data if x.size else None, ctypes.byref(t)),
+               "gila_submit")
+        self._keep[t.value] = int(graph.n)
+        return t.value
+
+    def poll(self, ticket: int):
+        """(status, positions or None, Stats); status GILA_EAGAIN while running."""
+        n = self._keep.get(ticket, 0)
+        out = np.zeros((max(n, 1), 2), dtype=np.float64)
+        st = Stats()
+        rc = _lib.gila_poll(self._h, int(ticket), out.ctypes.data, ctypes.byref(st))
+        if rc == GILA_EAGAIN:
+            return rc, None, None
+        self._keep.pop(ticket, None)
+        return rc, (out[:n] if rc == GILA_OK else None), st
+
+    def wait(self, ticket: int):
+        n = self._keep.get(ticket, 0)
+        out = np.zeros((max(n, 1), 2), dtype=np.float64)
+        st = Stats()
+        rc = _lib.gila_wait(self._h, int(ticket), out.ctypes.data, ctypes.byref(st))
+        self._keep.pop(ticket, None)
+        _check(rc, "gila_wait")
+        return out[:n], st
+
+    def cancel(self, ticket: int):
+        _check(_lib.gila_cancel(self._h, int(ticket)), "gila_cancel")
+
+    def latency(self, ticket: int):
+        q, t = ctypes.c_double(), ctypes.c_double()
+        _check(_lib.gila_job_latency(self._h, int(ticket), ctypes.byref(q), ctypes.byref(t)),
+               "gila_job_latency")
+        return q.value, t.value
+
+    def info(self) -> dict:
+        d, t, p, b = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int64()
+        _check(_lib.gila_server_info(self._h, ctypes.byref(d), ctypes.byref(t), ctypes.byref(p),
+                                     ctypes.byref(b)), "gila_server_info")
+        return {"jobs_done": d.value, "ticks": t.value, "peak_resident": p.value,
+                "bytes_reserved": b.value}
+
+    def close(self):
+        if self._h:
+            _lib.gila_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

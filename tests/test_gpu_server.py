@@ -1,0 +1,183 @@
+"""GPU tests of the layout server (continuous batching).
+
+A job's result must not depend on what else is in flight: every job of a
+concurrent mix (small jobs laid out in batched LDS-resident launches, large
+ones advanced a few iterations per tick) is compared bitwise with the same
+job run alone, and with the library's direct entry points.  Also: one-step
+parity against the oracle, admission under a small HBM budget (queueing and
+rejection), cancellation, malformed input, an injected allocation failure,
+and the halting rule."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_common import oracle_rows, pos_err, require_gpu
+from paper_1606_02162_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def G():
+    require_gpu()
+    from paper_1606_02162_amd import gila
+    return gila
+
+
+def _jobs(count, seed, big_every=4):
+    rng = np.random.default_rng(seed)
+    jobs = []
+    for i in range(count):
+        if i % big_every == 0:
+            n = int(rng.integers(15000, 40000))      # too large for the LDS-resident kernel
+        else:
+            n = int(rng.integers(100, 4000))
+        g = inputs.watts_strogatz(n, 6, 0.1, seed=seed * 1000 + i)
+        k = int(rng.integers(2, 4))
+        H = int(rng.integers(20, 60))
+        x0 = inputs.uniform_positions(n, seed=i, width=1200.0)
+        jobs.append((g, k, H, x0))
+    return jobs
+
+
+def _params(G, g, H, prec=None):
+    return G.LayoutParams(temperature=G.paper_schedule(g.n, 1.0, 48.0, H), ideal_length=48.0,
+                          precision=G.FP32_KAHAN if prec is None else prec)
+
+
+def test_mix_equals_alone_and_direct(G):
+    import torch
+    jobs = _jobs(12, 1)
+    with G.Server(max_slots=64) as srv:
+        srv.config("tick_iterations", 7)
+        tickets = [srv.submit(g, k, _params(G, g, H), x0) for g, k, H, x0 in jobs]
+        mixed = [srv.wait(t)[0] for t in tickets]
+        info = srv.info()
+    print("server info", info)
+    assert info["jobs_done"] == len(jobs)
+    with G.Server(max_slots=1) as srv:
+        srv.config("tick_iterations", 13)
+        for (g, k, H, x0), xm in zip(jobs, mixed):
+            xa, st = srv.wait(srv.submit(g, k, _params(G, g, H), x0))
+            assert np.array_equal(xa, xm), g.name
+            assert st.iterations_run == H
+    # the same jobs through the direct entry points give the same bits
+    for (g, k, H, x0), xm in zip(jobs, mixed):
+        rp, ci = G.to_device_csr(g)
+        pos = torch.from_numpy(x0.astype(np.float32)).cuda()
+        if g.n > 12000:
+            kh = G.build_khop(rp, ci, k)
+            G.run(kh, _params(G, g, H), pos)
+        else:
+            G.Batch([(rp, ci)], [k]).run([_params(G, g, H)], [pos])
+        assert np.array_equal(pos.double().cpu().numpy(), xm), g.name
+
+
+def test_one_step_parity(G):
+    jobs = _jobs(6, 2, big_every=2)
+    with G.Server() as srv:
+        tickets = []
+        for g, k, _, x0 in jobs:
+            x32 = x0.astype(np.float32).astype(np.float64)
+            tickets.append(srv.submit(g, k, _params(G, g, 1), x32))
+        for (g, k, _, x0), t in zip(jobs, tickets):
+            xg, st = srv.wait(t)
+            x32 = x0.astype(np.float32).astype(np.float64)
+            optr, oidx = oracle_rows(g, k)
+            xo, _, _, _ = oracle.step(g.n, g.row_ptr, g.col_idx, optr, oidx, 48.0,
+                                      G.paper_schedule(g.n, 1.0, 48.0, 1)[0], x32)
+            assert pos_err(xg, xo) <= 1e-5, g.name
+            q, tot = srv.latency(t)
+            assert 0 <= q <= tot
+
+
+def test_small_budget_queues_and_rejects(G):
+    jobs = _jobs(6, 3, big_every=2)
+    with G.Server(max_slots=64) as srv:
+        alone = [srv.wait(srv.submit(g, k, _params(G, g, H), x0))[0] for g, k, H, x0 in jobs]
+    # a budget a bit above the largest single job: jobs must wait for memory
+    budget = 96 << 20
+    with G.Server(budget_bytes=budget, max_slots=64) as srv:
+        tickets = [srv.submit(g, k, _params(G, g, H), x0) for g, k, H, x0 in jobs]
+        huge = inputs.watts_strogatz(400000, 6, 0.1, seed=77)
+        th = srv.submit(huge, 3, _params(G, huge, 5), inputs.uniform_positions(huge.n, 1))
+        outs = [srv.wait(t)[0] for t in tickets]
+        rc, _, _ = _wait_poll(G, srv, th)
+        assert rc == G.GILA_ENOMEM
+        assert srv.info()["bytes_reserved"] == 0
+    for a, b in zip(alone, outs):
+        assert np.array_equal(a, b)
+
+
+def _wait_poll(G, srv, t, timeout=120.0):
+    t0 = time.time()
+    while time.time() - t0 < timeout:
+        rc, x, st = srv.poll(t)
+        if rc != G.GILA_EAGAIN:
+            return rc, x, st
+        time.sleep(0.005)
+    raise AssertionError("job did not finish")
+
+
+def test_cancel_malformed_and_injected_failure(G):
+    jobs = _jobs(5, 4, big_every=2)
+    with G.Server() as srv:
+        alone = [srv.wait(srv.submit(g, k, _params(G, g, H), x0))[0] for g, k, H, x0 in jobs]
+    with G.Server() as srv:
+        # a long job to cancel
+        big = inputs.watts_strogatz(60000, 6, 0.1, seed=5)
+        tc = srv.submit(big, 3, _params(G, big, 5000), inputs.uniform_positions(big.n, 2))
+        # a malformed graph (asymmetric): accepted at submission, fails at admission
+        bad = inputs.Graph(n=3, row_ptr=np.array([0, 1, 2, 2]), col_idx=np.array([1, 2], np.int32))
+        tb = srv.submit(bad, 2, _params(G, bad, 3), np.zeros((3, 2)))
+        srv.config("fail_alloc_ticket", tb + 2)      # tickets are issued in order
+        tickets = [srv.submit(g, k, _params(G, g, H), x0) for g, k, H, x0 in jobs]
+        assert tickets[1] == tb + 2
+        time.sleep(0.05)
+        srv.cancel(tc)
+        outs = []
+        for i, t in enumerate(tickets):
+            rc, x, _ = _wait_poll(G, srv, t)
+            if i == 1:
+                assert rc == G.GILA_ENOMEM
+                outs.append(None)
+            else:
+                assert rc == G.GILA_OK
+                outs.append(x)
+        assert _wait_poll(G, srv, tc)[0] == G.GILA_ECANCELED
+        assert _wait_poll(G, srv, tb)[0] == G.GILA_EINVAL
+        # bad parameters are refused at submission
+        g0 = jobs[0][0]
+        with pytest.raises(G.GilaError):
+            srv.submit(g0, 0, _params(G, g0, 3), jobs[0][3])
+        with pytest.raises(G.GilaError):
+            srv.submit(g0, 2, G.LayoutParams(temperature=np.array([-1.0])), jobs[0][3])
+    for i, (a, b) in enumerate(zip(alone, outs)):
+        if b is not None:
+            assert np.array_equal(a, b), i
+
+
+def test_server_halting_rule(G):
+    n = 64
+    ring = inputs.cycle_graph(n)
+    th = 2 * np.pi * np.arange(n) / n
+    xr = np.stack([200 * np.cos(th), 200 * np.sin(th)], axis=1)
+    temps = 20.0 * 0.9 ** np.arange(300)
+    optr, oidx = oracle_rows(ring, 2)
+    _, run, _ = oracle.layout(ring.n, ring.row_ptr, ring.col_idx, optr, oidx, 10.0, temps, xr,
+                              stop_fraction=0.15, stop_displacement=0.01)
+    big = inputs.cycle_graph(20000)
+    tb = 2 * np.pi * np.arange(big.n) / big.n
+    xb = np.stack([3000 * np.cos(tb), 3000 * np.sin(tb)], axis=1)
+    with G.Server() as srv:
+        srv.config("tick_iterations", 9)
+        p = G.LayoutParams(temperature=temps, ideal_length=10.0, precision=G.FP64,
+                           stop_fraction=0.15, stop_displacement=0.01)
+        t1 = srv.submit(ring, 2, p, xr)
+        t2 = srv.submit(big, 2, p, xb)
+        _, s1 = srv.wait(t1)
+        _, s2 = srv.wait(t2)
+    assert s1.stopped == 1 and s1.iterations_run == run
+    assert s2.stopped == 1 and s2.iterations_run < 300
