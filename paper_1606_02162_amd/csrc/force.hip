@@ -141,11 +141,10 @@ int launch_step(const gila_khop* kh, int precision, const StepArgs& a, hipStream
 }
 
 // ------------------------------------------------------------------ plan
-// Rows are sorted by length, longest first.  Rows of at least kHubMin pairs
-// get a workgroup each; the rest are packed into contiguous ranges of about
+// Rows of at least kHubMin pairs come first in the internal order and get a
+// workgroup each; the rest are packed into contiguous ranges of about
 // kPairsPerBlock pairs (plus a per-vertex overhead) and at most
 // kMaxVertsPerBlock vertices.
-static constexpr int64_t kHubMin = 8192;
 static constexpr int64_t kVertexCost = 32;
 
 int plan_iteration(gila_khop* kh, const std::vector<int64_t>& counts,
@@ -155,7 +154,11 @@ int plan_iteration(gila_khop* kh, const std::vector<int64_t>& counts,
     while (nhub < na && counts[nhub] >= kHubMin) ++nhub;
     // lanes per vertex from the median row length of the non-hub vertices
     int64_t med = 0;
-    if (na > nhub) med = counts[nhub + (na - nhub) / 2];
+    if (na > nhub) {
+        std::vector<int64_t> rest(counts.begin() + nhub, counts.begin() + na);
+        std::nth_element(rest.begin(), rest.begin() + rest.size() / 2, rest.end());
+        med = rest[rest.size() / 2];
+    }
     int lpv = 4;
     while (lpv < 64 && lpv * 8 < med) lpv *= 2;
     const int64_t pairs_per_block = std::max<int64_t>(2048, 64ll * lpv);

@@ -74,6 +74,7 @@ struct DeviceInfo {
 const DeviceInfo& device_info(int device);
 
 constexpr int kBlock = 256;       // threads per workgroup in every kernel
+constexpr int64_t kHubMin = 8192; // rows at least this long get a workgroup of their own (direct path)
 constexpr int kWaves = kBlock / 64;
 
 // ------------------------------------------------------------------ device control block
@@ -123,22 +124,26 @@ struct StepArgs {
     Partial* partials;          // [nblocks]
     Ctl* ctl;
     double* hist;               // [slots][4]: energy, max_disp, moved, coincident
-    // segment-blocked path
-    int32_t nseg;
-    const double2* part;        // [nseg][n_active] per-segment partial forces
+    // segment-blocked path: the partial forces of vertex v are
+    // part[vsl[v] .. vsl[v + 1]), one per non-empty slice, in segment order
+    const int64_t* vsl;
+    const double2* part;
 };
 
-// Arguments of the segment kernel (one workgroup = one id segment x a row range).
+// Arguments of the segment kernel (one workgroup = one id segment x a range
+// of that segment's slices).
 struct SegArgs {
     int32_t na;                 // non-isolated vertices (rows)
     int32_t seg;                // segment size S (vertex ids per segment)
-    const int4* wg;             // [grid] (segment, first row, end row, lanes per row)
-    const int64_t* kptr;        // [nseg * na + 1] k-hop slices, segment-major
-    const uint16_t* kidx;       // id - s*S of each k-hop entry
-    const int32_t* aptr;        // [nseg * na + 1] adjacency slices
-    const uint16_t* aidx;
+    const int4* wg;             // [grid] (segment, first slice, end slice, lanes per slice)
+    const int32_t* sl_v;        // [T] row of each slice (segment-major order)
+    const int32_t* sl_p;        // [T] index of the slice's partial force
+    const int64_t* sl_k;        // [T + 1] start of each slice in kidx (quad-aligned)
+    const int32_t* sl_a;        // [T + 1] start of each slice in aidx
+    const uint16_t* kidx;       // LDS byte offsets of the k-hop entries
+    const uint16_t* aidx;       // LDS byte offsets of the adjacency entries
     const void* pos;            // positions of this iteration (internal ids)
-    double2* part;              // [nseg][na]
+    double2* part;              // [T]
     double d;
     Ctl* ctl;
 };
@@ -174,7 +179,11 @@ struct gila_khop {
     int32_t n = 0, k = 0, n_active = 0;
     int64_t nnz = 0, P = 0;
     int64_t device_bytes = 0;
-    // internal vertex ids: sorted by |N_v(k)| descending (ties: caller id ascending)
+    // internal vertex ids: non-isolated vertices first.  Either by |N_v(k)|
+    // descending (ties: caller id), or, when the caller's order already keeps
+    // most edges short, rows of at least kHubMin entries first and then the
+    // caller's order (see build_khop).
+    bool caller_order = false;
     int32_t* perm = nullptr;   // [n] internal -> caller
     int32_t* iperm = nullptr;  // [n] caller -> internal
     int64_t* rp = nullptr;     // internal CSR
@@ -196,14 +205,18 @@ struct gila_khop {
     // segment-blocked layout of the k-hop and adjacency lists (see segment.hip)
     bool seg_ready = false;
     int32_t seg = 0, nseg = 0;      // segment size and count
-    int64_t* sk_ptr = nullptr;      // [nseg * n_active + 1]
-    uint16_t* sk_idx = nullptr;     // [P]
-    int32_t* sa_ptr = nullptr;      // [nseg * n_active + 1]
-    uint16_t* sa_idx = nullptr;     // [nnz]
+    int64_t nslices = 0;            // non-empty (segment, row) slices T
+    int64_t* vsl = nullptr;         // [n_active + 1] first partial of each row
+    int32_t* sl_v = nullptr;        // [T] slice records, segment-major
+    int32_t* sl_p = nullptr;        // [T]
+    int64_t* sl_k = nullptr;        // [T + 1]
+    int32_t* sl_a = nullptr;        // [T + 1]
+    uint16_t* sk_idx = nullptr;     // [sl_k[T] + tail pad]
+    uint16_t* sa_idx = nullptr;     // [nnz + pad]
     int4* seg_wg = nullptr;         // [seg_grid]
     int32_t seg_grid = 0;
     int32_t comb_grid = 0;
-    double2* part = nullptr;        // [nseg * n_active]
+    double2* part = nullptr;        // [T] partial force of each slice, row-major
     int32_t seg_precision = -1;     // precision the segment size was chosen for
     // cached HIP graph of the last gila_run call
     hipGraphExec_t gexec = nullptr;
@@ -223,9 +236,15 @@ int run_bfs(bool fill, int device, hipStream_t s, BfsArgs a);
 int launch_validate_csr(int32_t n, int64_t nnz, const int64_t* rp, const int32_t* ci, int32_t* flag,
                         hipStream_t s);
 // implemented in util.hip: out[0] = 0, out[i + 1] = in[0] + ... + in[i]
+// (in != out).  The enqueue variant needs scan_workspace_count(n) int64 of
+// workspace and does not synchronise; the other allocates and synchronises.
 int exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t s);
+int64_t scan_workspace_count(int64_t n);
+int enqueue_exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* ws,
+                               hipStream_t s);
 // implemented in segment.hip
 int build_segments(gila_khop* kh, int precision, hipStream_t s);
+void free_segments(gila_khop* kh);
 int launch_segment_step(const gila_khop* kh, int precision, const StepArgs& a, hipStream_t s,
                         hipEvent_t* ev = nullptr);
 bool segment_path_enabled();

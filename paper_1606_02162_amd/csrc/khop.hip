@@ -9,6 +9,8 @@
 // prefix sum a fill pass writes each row by scanning the bitmap, which yields
 // the row in ascending id order with no sort.
 #include <algorithm>
+#include <cstdlib>
+#include <cstring>
 #include <numeric>
 
 #include "device_util.h"
@@ -18,12 +20,16 @@ namespace gila {
 
 // ------------------------------------------------------------------ validation
 // flag bits: 1 column out of range, 2 self-loop, 4 row not strictly ascending,
-// 8 asymmetric (u in row v but v not in row u)
+// 8 asymmetric (u in row v but v not in row u).  With `near` set, also counts
+// the entries with |u - v| < window (how local the caller's order is).
 __global__ __launch_bounds__(kBlock) void validate_csr_kernel(int32_t n, int64_t nnz,
                                                               const int64_t* __restrict__ rp,
                                                               const int32_t* __restrict__ ci,
-                                                              int32_t* __restrict__ flag) {
+                                                              int32_t* __restrict__ flag,
+                                                              int32_t window,
+                                                              unsigned long long* __restrict__ near) {
     int32_t bad = 0;
+    int64_t close = 0;
     for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < nnz;
          e += (int64_t)gridDim.x * kBlock) {
         // owner row: largest v with rp[v] <= e
@@ -40,6 +46,7 @@ __global__ __launch_bounds__(kBlock) void validate_csr_kernel(int32_t n, int64_t
             continue;
         }
         if (u == v) bad |= 2;
+        close += (u - v < window && v - u < window) ? 1 : 0;
         if (e > rp[v] && ci[e - 1] >= u) bad |= 4;
         // binary search v in row u
         int64_t a = rp[u], b = rp[u + 1] - 1;
@@ -57,6 +64,10 @@ __global__ __launch_bounds__(kBlock) void validate_csr_kernel(int32_t n, int64_t
         if (!found) bad |= 8;
     }
     if (bad) atomicOr(flag, bad);
+    if (near) {
+        const int64_t c = wave_sum(close);
+        if (lane64() == 0 && c) atomicAdd(near, (unsigned long long)c);
+    }
 }
 
 // ------------------------------------------------------------------ BFS count / fill
@@ -225,7 +236,8 @@ int launch_validate_csr(int32_t n, int64_t nnz, const int64_t* rp, const int32_t
                         hipStream_t s) {
     if (nnz <= 0) return GILA_OK;
     const int grid = (int)std::min<int64_t>(4096, (nnz + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(validate_csr_kernel, dim3(grid), dim3(kBlock), 0, s, n, nnz, rp, ci, flag);
+    hipLaunchKernelGGL(validate_csr_kernel, dim3(grid), dim3(kBlock), 0, s, n, nnz, rp, ci, flag,
+                       0, (unsigned long long*)nullptr);
     GILA_HIP(hipGetLastError());
     return GILA_OK;
 }
@@ -315,12 +327,7 @@ void free_khop(gila_khop* kh) {
     dfree(kh->partials);
     dfree(kh->ctl);
     dfree(kh->hist);
-    dfree(kh->sk_ptr);
-    dfree(kh->sk_idx);
-    dfree(kh->sa_ptr);
-    dfree(kh->sa_idx);
-    dfree(kh->seg_wg);
-    dfree(kh->part);
+    free_segments(kh);
     delete kh;
 }
 
@@ -328,6 +335,58 @@ struct KhopHolder {
     gila_khop* p;
     ~KhopHolder() { free_khop(p); }
 };
+
+// ------------------------------------------------------------------ internal vertex order
+// Edges shorter than this in the caller's order count as local.
+static constexpr int32_t kLocalWindow = 1024;
+
+// The caller's order is kept when most edges are local (meshes, rings, road
+// networks numbered along the graph): neighbourhoods then fall into few
+// segments of the iteration kernel.  Otherwise rows are sorted by length.
+// GILA_ORDER=degree|caller overrides the choice.
+static bool use_caller_order(unsigned long long near_edges, int64_t nnz) {
+    const char* e = getenv("GILA_ORDER");
+    if (e && std::strcmp(e, "degree") == 0) return false;
+    if (e && std::strcmp(e, "caller") == 0) return true;
+    return nnz > 0 && (double)near_edges >= 0.7 * (double)nnz;
+}
+
+// perm[i] = caller id of internal vertex i.  Isolated vertices last (caller
+// order).  Degree order: |N_v(k)| descending, ties by caller id.  Caller
+// order: rows of at least kHubMin entries first, then the others, each in
+// the caller's order.  Stable LSD radix sort (11-bit digits) on the key.
+static void order_vertices(const std::vector<int64_t>& counts, const std::vector<int64_t>& rp,
+                           bool caller_order, std::vector<int32_t>& perm) {
+    const int32_t n = (int32_t)counts.size();
+    int64_t maxc = 0;
+    for (int32_t v = 0; v < n; ++v) maxc = std::max(maxc, counts[v]);
+    std::vector<uint64_t> key((size_t)n);
+    for (int32_t v = 0; v < n; ++v) {
+        const bool isolated = rp[v + 1] == rp[v];
+        if (caller_order)
+            key[v] = isolated ? 2 : (counts[v] >= kHubMin ? 0 : 1);
+        else
+            key[v] = isolated ? (uint64_t)maxc + 1 : (uint64_t)(maxc - counts[v]);
+    }
+    const uint64_t kmax = caller_order ? 2 : (uint64_t)maxc + 1;
+    std::vector<int32_t> tmp((size_t)n);
+    for (int32_t v = 0; v < n; ++v) perm[v] = v;
+    constexpr int kBits = 11;
+    std::vector<int64_t> cnt((size_t)1 << kBits);
+    for (int shift = 0; shift < 64 && (kmax >> shift) > 0; shift += kBits) {
+        std::fill(cnt.begin(), cnt.end(), 0);
+        const uint64_t mask = ((uint64_t)1 << kBits) - 1;
+        for (int32_t i = 0; i < n; ++i) ++cnt[(key[perm[i]] >> shift) & mask];
+        int64_t run = 0;
+        for (auto& c : cnt) {
+            const int64_t t = c;
+            c = run;
+            run += t;
+        }
+        for (int32_t i = 0; i < n; ++i) tmp[cnt[(key[perm[i]] >> shift) & mask]++] = perm[i];
+        perm.swap(tmp);
+    }
+}
 
 int build_khop(const gila_csr* g, int32_t k, hipStream_t s, gila_khop** out) {
     if (!out) return fail(GILA_EINVAL, "out is NULL");
@@ -367,9 +426,11 @@ int build_khop(const gila_csr* g, int32_t k, hipStream_t s, gila_khop** out) {
 
     pt.mark("rowptr");
     // --- device validation of every entry
+    // d_flag[0]: validation flags, d_flag[1]: BFS work counter,
+    // d_flag[2..3]: number of short edges (caller's order)
     int32_t* d_flag = nullptr;
     int32_t* d_work = nullptr;
-    GILA_TRY(dalloc_t(&d_flag, 2));
+    GILA_TRY(dalloc_t(&d_flag, 4));
     struct F {
         int32_t* p;
         int32_t* w;
@@ -378,16 +439,20 @@ int build_khop(const gila_csr* g, int32_t k, hipStream_t s, gila_khop** out) {
         }
     } fguard{d_flag, nullptr};
     d_work = d_flag + 1;
-    GILA_HIP(hipMemsetAsync(d_flag, 0, 2 * sizeof(int32_t), s));
+    unsigned long long* d_near = reinterpret_cast<unsigned long long*>(d_flag + 2);
+    GILA_HIP(hipMemsetAsync(d_flag, 0, 4 * sizeof(int32_t), s));
     if (nnz > 0) {
         const int grid = (int)std::min<int64_t>(4096, (nnz + kBlock - 1) / kBlock);
         hipLaunchKernelGGL(validate_csr_kernel, dim3(grid), dim3(kBlock), 0, s, n, nnz,
-                           g->row_ptr, g->col_idx, d_flag);
+                           g->row_ptr, g->col_idx, d_flag, kLocalWindow, d_near);
         GILA_HIP(hipGetLastError());
     }
-    int32_t flag = 0;
-    GILA_HIP(hipMemcpyAsync(&flag, d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    int32_t hflag[4] = {0, 0, 0, 0};
+    GILA_HIP(hipMemcpyAsync(hflag, d_flag, sizeof(hflag), hipMemcpyDeviceToHost, s));
     GILA_HIP(hipStreamSynchronize(s));
+    const int32_t flag = hflag[0];
+    unsigned long long near_edges = 0;
+    std::memcpy(&near_edges, &hflag[2], sizeof(near_edges));
     if (flag) {
         return fail(GILA_EINVAL, "malformed CSR:%s%s%s%s", (flag & 1) ? " column out of range" : "",
                     (flag & 2) ? " self-loop" : "", (flag & 4) ? " row not strictly ascending" : "",
@@ -421,11 +486,10 @@ int build_khop(const gila_csr* g, int32_t k, hipStream_t s, gila_khop** out) {
     }
 
     pt.mark("count");
-    // --- internal order: |N_v(k)| descending, ties by caller id
+    // --- internal order (non-isolated vertices first)
+    kh->caller_order = use_caller_order(near_edges, nnz);
     std::vector<int32_t> perm((size_t)n), iperm((size_t)n);
-    std::iota(perm.begin(), perm.end(), 0);
-    std::stable_sort(perm.begin(), perm.end(),
-                     [&](int32_t x, int32_t y) { return counts[x] > counts[y]; });
+    order_vertices(counts, rp_host, kh->caller_order, perm);
     for (int32_t i = 0; i < n; ++i) iperm[perm[i]] = i;
     int64_t P = 0;
     int32_t n_active = 0;

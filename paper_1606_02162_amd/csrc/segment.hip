@@ -1,108 +1,297 @@
 // Segment-blocked iteration: every neighbour gather comes from LDS.
 //
 // Internal vertex ids are split into segments of S consecutive ids (S
-// positions fill 32 KB of LDS by default).  Each k-hop row (and adjacency
-// row) of an active vertex v is cut into per-segment slices; slice (s, v)
-// holds the ids of N_v(k) (resp. adj(v)) that fall in segment s, stored as
-// 16-bit LDS byte offsets (id - s*S) * sizeof(position), segment-major: all
-// slices of segment s, rows in internal order.  k-hop slices are padded to a
-// whole number of 4-id quads with a sentinel offset: LDS slot S holds a
-// position so far away (1e30) that its squared distance overflows to +inf, the
-// reciprocal is exactly 0 and the padding term is exactly zero.  Each lane then
-// loads one aligned 8-byte quad of ids per memory instruction.
+// positions fill 32 KB of LDS by default).  The k-hop row (and adjacency row)
+// of an active vertex v is cut into slices, one per segment that the row
+// touches; only non-empty slices exist.  A slice holds its ids as 16-bit LDS
+// byte offsets (id - s*S) * sizeof(position).  Slices are stored
+// segment-major (all slices of segment 0 in row order, then segment 1, ...).
+// k-hop slices are padded to a whole number of 4-id quads with a sentinel
+// offset: LDS slot S holds a position so far away (1e30) that its squared
+// distance overflows to +inf, the reciprocal is exactly 0 and the padding term
+// is exactly zero.  Each lane then loads one aligned 8-byte quad of ids per
+// memory instruction.
 //
 // One iteration is two kernels:
-//   seg_force_kernel   one workgroup = one segment x a pair-balanced range of
-//                      rows.  It copies the segment's positions into LDS,
-//                      then sums repulsion (k-hop slice) and attraction
-//                      (adjacency slice) for each row of its range, and
-//                      writes the row's partial force for that segment
-//                      (FP32 / Kahan lane sums, double-precision combine).
+//   seg_force_kernel   one workgroup = one segment x a work-balanced range of
+//                      its slices.  It copies the segment's positions into
+//                      LDS, then sums repulsion (k-hop slice) and attraction
+//                      (adjacency slice) of each slice and writes the slice's
+//                      partial force (FP32 / Kahan lane sums, double-precision
+//                      combine).  Partials are stored row-major: the partials
+//                      of row v are contiguous and in segment order.
 //   seg_combine_kernel one thread per vertex: adds the vertex's partials in
 //                      segment order, applies the temperature cap, writes the
 //                      vertex's next position and the iteration statistics.
-// The result of every row depends only on the graph's plan (lanes per row of
+// The result of every row depends only on the graph's plan (lanes per slice of
 // its workgroup) and on the fixed segment order, never on scheduling.
+//
+// The layout is built on the device (build_segments): count the slices of
+// every row, emit them row-major, reorder them segment-major with a stable
+// counting sort by segment, prefix-sum the padded lengths, fill the offsets,
+// and cut each segment into workgroups of about equal work.
 #include <algorithm>
 #include <cstdlib>
+#include <cstring>
 
 #include "iteration.h"
 
 namespace gila {
 
-constexpr int kSegBlock = 512;   // threads per segment workgroup
-constexpr int kSegTailPad = 1024;  // slack entries after the k-hop index array (>= 3 * 64 quads)
+constexpr int kSegBlock = 512;     // threads per segment workgroup
+constexpr int kSegTailPad = 1024;  // slack entries after the k-hop offsets (>= 3 * 64 quads)
+constexpr int kMaxSegments = 16384;  // segment counters of the build fit in 64 KB of LDS
+constexpr int kLongRow = 16;       // rows longer than kLongRow * nseg: binary search per segment
+constexpr int kFillLanes = 16;     // lanes per slice in the fill pass
 
 bool segment_path_enabled() {
     const char* e = getenv("GILA_PATH");
     return !(e && std::strcmp(e, "direct") == 0);
 }
 
-// ------------------------------------------------------------------ build: counts
-// Wave per active row v: slice lengths of the (sorted) k-hop and adjacency
-// rows for every segment, by binary search of the segment boundaries.
-__device__ __forceinline__ int64_t lower_bound_i32(const int32_t* __restrict__ a, int64_t lo,
-                                                   int64_t hi, int32_t key) {
+// ------------------------------------------------------------------ build kernels
+template <class T>
+__device__ __forceinline__ int64_t lower_bound_ids(const T* __restrict__ a, int64_t lo, int64_t hi,
+                                                   int64_t key) {
     while (lo < hi) {
         const int64_t mid = lo + ((hi - lo) >> 1);
-        if (a[mid] < key) lo = mid + 1;
+        if ((int64_t)a[mid] < key) lo = mid + 1;
         else hi = mid;
     }
     return lo;
 }
 
-__global__ __launch_bounds__(kBlock) void seg_count_kernel(
-    int32_t na, int32_t S, int32_t nseg, const int64_t* __restrict__ kptr,
-    const int32_t* __restrict__ kidx, const int64_t* __restrict__ rp,
-    const int32_t* __restrict__ ci, int32_t* __restrict__ kcnt, int32_t* __restrict__ acnt) {
+struct SliceBuild {
+    int32_t na, S, nseg, pos_bytes;
+    const int64_t* kptr;  // internal k-hop rows (ascending ids)
+    const int32_t* kidx;
+    const int64_t* rp;    // internal adjacency rows (ascending ids)
+    const int32_t* ci;
+    int64_t* rs;          // [na] slices per row (count pass)
+    const int64_t* vsl;   // [na + 1] first slice of each row, row-major
+    // row-major slice descriptors (emit pass)
+    int32_t* d_seg;
+    int64_t* d_k0;
+    int32_t* d_kn;
+    int32_t* d_a0;
+    int32_t* d_an;
+    int32_t* d_row;
+};
+
+__device__ __forceinline__ void emit_slice(const SliceBuild& b, int64_t j, int32_t v, int32_t s,
+                                           int64_t k0, int64_t ke, int64_t ab, int64_t ae) {
+    const int64_t lo = (int64_t)s * b.S, hi = lo + b.S;
+    const int64_t k1 = lower_bound_ids(b.kidx, k0, ke, hi);
+    const int64_t a0 = lower_bound_ids(b.ci, ab, ae, lo);
+    const int64_t a1 = lower_bound_ids(b.ci, a0, ae, hi);
+    b.d_seg[j] = s;
+    b.d_k0[j] = k0;
+    b.d_kn[j] = (int32_t)(k1 - k0);
+    b.d_a0[j] = (int32_t)a0;
+    b.d_an[j] = (int32_t)(a1 - a0);
+    b.d_row[j] = v;
+}
+
+// Wave per row: the segments a sorted k-hop row touches.  Short rows are
+// scanned for segment changes; long rows binary-search each segment.  The
+// count pass writes the number of slices; the emit pass writes them at
+// vsl[v] onward in segment order.  Every adjacency id of v is also a k-hop id
+// of v (k >= 1), so the k-hop slices cover the adjacency slices.
+template <bool EMIT>
+__global__ __launch_bounds__(kBlock) void slice_rows_kernel(SliceBuild b) {
     const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * kBlock) >> 6;
     const int lane = lane64();
-    for (int64_t v = wave; v < na; v += nwaves) {
-        const int64_t kb = kptr[v], ke = kptr[v + 1];
-        const int64_t ab = rp[v], ae = rp[v + 1];
-        for (int s = lane; s < nseg; s += 64) {
-            const int32_t lo_id = s * S, hi_id = (s + 1) * S;
-            const int64_t k0 = lower_bound_i32(kidx, kb, ke, lo_id);
-            const int64_t k1 = lower_bound_i32(kidx, k0, ke, hi_id);
-            const int64_t a0 = lower_bound_i32(ci, ab, ae, lo_id);
-            const int64_t a1 = lower_bound_i32(ci, a0, ae, hi_id);
-            kcnt[(int64_t)s * na + v] = (int32_t)(k1 - k0);
-            acnt[(int64_t)s * na + v] = (int32_t)(a1 - a0);
+    const uint64_t below = (1ull << lane) - 1ull;
+    for (int64_t vv = wave; vv < b.na; vv += nwaves) {
+        const int32_t v = (int32_t)vv;
+        const int64_t kb = b.kptr[v], ke = b.kptr[v + 1];
+        const int64_t ab = b.rp[v], ae = b.rp[v + 1];
+        int64_t t = EMIT ? b.vsl[v] : 0;
+        if (ke - kb > (int64_t)kLongRow * b.nseg) {
+            for (int32_t s0 = 0; s0 < b.nseg; s0 += 64) {
+                const int32_t s = s0 + lane;
+                bool ne = false;
+                int64_t k0 = ke;
+                if (s < b.nseg) {
+                    k0 = lower_bound_ids(b.kidx, kb, ke, (int64_t)s * b.S);
+                    ne = k0 < ke && (int64_t)b.kidx[k0] < (int64_t)(s + 1) * b.S;
+                }
+                const uint64_t m = __ballot(ne);
+                if (EMIT && ne) emit_slice(b, t + __popcll(m & below), v, s, k0, ke, ab, ae);
+                t += __popcll(m);
+            }
+        } else {
+            for (int64_t j0 = kb; j0 < ke; j0 += 64) {
+                const int64_t j = j0 + lane;
+                bool start = false;
+                int32_t s = 0;
+                if (j < ke) {
+                    s = b.kidx[j] / b.S;
+                    start = j == kb || b.kidx[j - 1] / b.S != s;
+                }
+                const uint64_t m = __ballot(start);
+                if (EMIT && start) emit_slice(b, t + __popcll(m & below), v, s, j, ke, ab, ae);
+                t += __popcll(m);
+            }
+        }
+        if (!EMIT && lane == 0) b.rs[v] = t;
+    }
+}
+
+// Stable counting sort of the row-major slices by segment, in tiles of `tj`
+// consecutive slices.  Pass 1: per-tile histogram, stored segment-major
+// (hist[s * ntiles + tile]) so that its exclusive prefix sum is the first
+// segment-major position of each (segment, tile).
+__global__ __launch_bounds__(kBlock) void slice_hist_kernel(int64_t T, int64_t tj, int64_t ntiles,
+                                                            int32_t nseg,
+                                                            const int32_t* __restrict__ d_seg,
+                                                            int64_t* __restrict__ hist) {
+    extern __shared__ int32_t s_cnt[];
+    for (int s = threadIdx.x; s < nseg; s += kBlock) s_cnt[s] = 0;
+    __syncthreads();
+    const int64_t j0 = (int64_t)blockIdx.x * tj;
+    const int64_t j1 = j0 + tj < T ? j0 + tj : T;
+    for (int64_t j = j0 + threadIdx.x; j < j1; j += kBlock) atomicAdd(&s_cnt[d_seg[j]], 1);
+    __syncthreads();
+    for (int s = threadIdx.x; s < nseg; s += kBlock) hist[(int64_t)s * ntiles + blockIdx.x] = s_cnt[s];
+}
+
+// Pass 2 (one wavefront per tile): walk the tile in order, 64 slices at a
+// time; equal segments within a step are ranked by lane, so slices of one
+// segment keep their row-major (= row) order.  order[i] = row-major index of
+// the i-th segment-major slice.
+__global__ __launch_bounds__(64) void slice_scatter_kernel(int64_t T, int64_t tj, int64_t ntiles,
+                                                           int32_t nseg,
+                                                           const int32_t* __restrict__ d_seg,
+                                                           const int64_t* __restrict__ base,
+                                                           int32_t* __restrict__ order) {
+    extern __shared__ int32_t s_next[];
+    const int lane = threadIdx.x;
+    for (int s = lane; s < nseg; s += 64) s_next[s] = (int32_t)base[(int64_t)s * ntiles + blockIdx.x];
+    __syncthreads();
+    const int64_t j0 = (int64_t)blockIdx.x * tj;
+    const int64_t j1 = j0 + tj < T ? j0 + tj : T;
+    for (int64_t c = j0; c < j1; c += 64) {
+        const int64_t j = c + lane;
+        const bool valid = j < j1;
+        const int32_t s = valid ? d_seg[j] : -1;
+        int rank = 0, same = 0;
+        for (int l = 0; l < 64; ++l) {
+            const int32_t sl = __builtin_amdgcn_readlane(s, l);
+            same += sl == s ? 1 : 0;
+            rank += (sl == s && l < lane) ? 1 : 0;
+        }
+        const int32_t at = valid ? s_next[s] : 0;
+        __syncthreads();
+        if (valid) {
+            order[at + rank] = (int32_t)j;
+            if (rank == same - 1) s_next[s] = at + same;
+        }
+        __syncthreads();
+    }
+}
+
+// Padded k-hop and adjacency lengths of each segment-major slice.
+__global__ __launch_bounds__(kBlock) void slice_lengths_kernel(int64_t T,
+                                                               const int32_t* __restrict__ order,
+                                                               const int32_t* __restrict__ d_kn,
+                                                               const int32_t* __restrict__ d_an,
+                                                               int64_t* __restrict__ wk,
+                                                               int64_t* __restrict__ wa) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= T) return;
+    const int32_t j = order[i];
+    wk[i] = (d_kn[j] + 3) & ~3;
+    wa[i] = d_an[j];
+}
+
+// Cumulative work of the slices before i: entries plus a fixed cost per slice.
+__device__ __forceinline__ int64_t slice_work(const int64_t* sl_k, const int64_t* sl_a, int64_t i,
+                                              int64_t slice_cost) {
+    return sl_k[i] + sl_a[i] + slice_cost * i;
+}
+
+// For each segment s (and s = nseg): its first segment-major slice and the
+// cumulative work there; last entry: total padded k-hop length.
+__global__ __launch_bounds__(kBlock) void segment_starts_kernel(
+    int32_t nseg, int64_t T, int64_t ntiles, int64_t slice_cost, const int64_t* __restrict__ base,
+    const int64_t* __restrict__ sl_k, const int64_t* __restrict__ sl_a, int64_t* __restrict__ out) {
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    if (s > nseg) return;
+    const int64_t f = s < nseg ? base[(int64_t)s * ntiles] : T;
+    out[2 * s] = f;
+    out[2 * s + 1] = slice_work(sl_k, sl_a, f, slice_cost);
+    if (s == nseg) out[2 * s + 2] = sl_k[T];
+}
+
+// kFillLanes lanes per segment-major slice: LDS byte offsets of its ids, the
+// k-hop part padded with the sentinel; the slice records.
+__global__ __launch_bounds__(kBlock) void slice_fill_kernel(
+    SliceBuild b, int64_t T, const int32_t* __restrict__ order, const int64_t* __restrict__ sl_k,
+    const int64_t* __restrict__ sl_a64, uint16_t* __restrict__ sk_idx, uint16_t* __restrict__ sa_idx,
+    int32_t* __restrict__ sl_v, int32_t* __restrict__ sl_p, int32_t* __restrict__ sl_a) {
+    const int64_t g = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kFillLanes;
+    const int64_t ng = ((int64_t)gridDim.x * kBlock) / kFillLanes;
+    const int gl = threadIdx.x % kFillLanes;
+    const uint16_t sentinel = (uint16_t)(b.S * b.pos_bytes);
+    for (int64_t i = g; i < T; i += ng) {
+        const int32_t j = order[i];
+        const int32_t s = b.d_seg[j];
+        const int32_t lo = s * b.S;
+        const int64_t k0 = b.d_k0[j];
+        const int32_t kn = b.d_kn[j];
+        const int64_t dst = sl_k[i], kpad = sl_k[i + 1] - dst;
+        for (int64_t t = gl; t < kpad; t += kFillLanes)
+            sk_idx[dst + t] = t < kn ? (uint16_t)((b.kidx[k0 + t] - lo) * b.pos_bytes) : sentinel;
+        const int32_t a0 = b.d_a0[j], an = b.d_an[j];
+        const int64_t adst = sl_a64[i];
+        for (int32_t t = gl; t < an; t += kFillLanes)
+            sa_idx[adst + t] = (uint16_t)((b.ci[a0 + t] - lo) * b.pos_bytes);
+        if (gl == 0) {
+            sl_v[i] = b.d_row[j];
+            sl_p[i] = j;
+            sl_a[i] = (int32_t)adst;
+            if (i == T - 1) sl_a[T] = (int32_t)sl_a64[T];
         }
     }
 }
 
-// Wave per active row: write each slice as LDS byte offsets into its place,
-// k-hop slices padded to whole quads with the sentinel offset.
-__global__ __launch_bounds__(kBlock) void seg_fill_kernel(
-    int32_t na, int32_t S, int32_t nseg, int32_t pos_bytes, const int64_t* __restrict__ kptr,
-    const int32_t* __restrict__ kidx, const int64_t* __restrict__ rp,
-    const int32_t* __restrict__ ci, const int32_t* __restrict__ kcnt,
-    const int64_t* __restrict__ sk_ptr, uint16_t* __restrict__ sk_idx,
-    const int32_t* __restrict__ sa_ptr, uint16_t* __restrict__ sa_idx) {
-    const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
-    const int64_t nwaves = ((int64_t)gridDim.x * kBlock) >> 6;
-    const int lane = lane64();
-    const uint16_t sentinel = (uint16_t)(S * pos_bytes);
-    for (int64_t v = wave; v < na; v += nwaves) {
-        int64_t kpos = kptr[v];
-        int64_t apos = rp[v];
-        for (int s = 0; s < nseg; ++s) {
-            const int64_t slot = (int64_t)s * na + v;
-            const int64_t kdst = sk_ptr[slot], kpad = sk_ptr[slot + 1] - kdst;
-            const int32_t klen = kcnt[slot];
-            const int32_t base = s * S;
-            for (int64_t j = lane; j < kpad; j += 64)
-                sk_idx[kdst + j] =
-                    j < klen ? (uint16_t)((kidx[kpos + j] - base) * pos_bytes) : sentinel;
-            kpos += klen;
-            const int64_t adst = sa_ptr[slot], alen = sa_ptr[slot + 1] - adst;
-            for (int64_t j = lane; j < alen; j += 64)
-                sa_idx[adst + j] = (uint16_t)((ci[apos + j] - base) * pos_bytes);
-            apos += alen;
+// Enough quads per lane (qpl) to amortise the per-slice reduction.
+__host__ __device__ __forceinline__ int lanes_for_length(int64_t len, int64_t qpl) {
+    int l = 1;
+    while (l < 64 && (int64_t)l * 2 * qpl * 4 <= len) l *= 2;
+    return l;
+}
+
+// One thread per workgroup of the force kernel: desc = (segment, index in
+// the segment, workgroups of the segment).  The segment's slices are split
+// where the cumulative work crosses equal fractions; lanes per slice follow
+// the mean slice length of the range.
+__global__ __launch_bounds__(kBlock) void segment_plan_kernel(
+    int32_t nwg, int64_t slice_cost, int64_t qpl, const int64_t* __restrict__ starts,
+    const int64_t* __restrict__ sl_k, const int32_t* __restrict__ sl_a, int4* __restrict__ wg) {
+    const int w = blockIdx.x * kBlock + threadIdx.x;
+    if (w >= nwg) return;
+    const int4 d = wg[w];
+    const int s = d.x, t = d.y, c = d.z;
+    const int64_t f0 = starts[2 * s], f1 = starts[2 * s + 2];
+    const int64_t c0 = starts[2 * s + 1], c1 = starts[2 * s + 3];
+    const int64_t W = c1 - c0;
+    auto work = [&](int64_t i) { return sl_k[i] + (int64_t)sl_a[i] + slice_cost * i; };
+    auto cut = [&](int64_t target) {
+        int64_t lo = f0, hi = f1;
+        while (lo < hi) {
+            const int64_t mid = lo + ((hi - lo) >> 1);
+            if (work(mid) < target) lo = mid + 1;
+            else hi = mid;
         }
-    }
+        return lo;
+    };
+    const int64_t ib = t == 0 ? f0 : cut(c0 + W * t / c);
+    const int64_t ie = t == c - 1 ? f1 : cut(c0 + W * (t + 1) / c);
+    const int64_t len = ie > ib ? ((sl_k[ie] - sl_k[ib]) + (int64_t)(sl_a[ie] - sl_a[ib])) / (ie - ib) : 0;
+    wg[w] = make_int4(s, (int)ib, (int)ie, lanes_for_length(len, qpl));
 }
 
 // ------------------------------------------------------------------ iteration: segment kernel
@@ -145,9 +334,8 @@ __device__ __forceinline__ void quad_terms(uint2 w, const unsigned char* __restr
 }
 
 template <class P, int LPV>
-__device__ __forceinline__ void seg_rows(const SegArgs& a, int s, int vb, int ve,
-                                         const typename P::vec2* __restrict__ lp,
-                                         int& coinc) {
+__device__ __forceinline__ void seg_slices(const SegArgs& a, int ib, int ie,
+                                           const typename P::vec2* __restrict__ lp, int& coinc) {
     using R = typename P::real;
     using V = typename P::vec2;
     const V* __restrict__ gpos = reinterpret_cast<const V*>(a.pos);
@@ -157,21 +345,19 @@ __device__ __forceinline__ void seg_rows(const SegArgs& a, int s, int vb, int ve
     const int ngroups = kSegBlock / LPV;
     const int grp = threadIdx.x / LPV;
     const int gl = threadIdx.x % LPV;
-    const int64_t sbase = (int64_t)s * a.na;
     const uint32_t sq = (uint32_t)a.seg * (uint32_t)sizeof(V);
     const uint2 sentinel = make_uint2(sq | (sq << 16), sq | (sq << 16));
-    for (int v0 = vb; v0 < ve; v0 += ngroups) {
-        const int v = v0 + grp;
+    for (int i0 = ib; i0 < ie; i0 += ngroups) {
+        const int i = i0 + grp;
         Acc<R, P::kahan> acc;
-        if (v < ve) {
-            const V xv = gpos[v];
-            const int64_t slot = sbase + v;
-            const int64_t kb = a.kptr[slot], ke = a.kptr[slot + 1];
+        if (i < ie) {
+            const V xv = gpos[a.sl_v[i]];
+            const int64_t kb = a.sl_k[i], ke = a.sl_k[i + 1];
             const uint2* __restrict__ q4 = reinterpret_cast<const uint2*>(a.kidx + kb);
             const int nq = (int)((ke - kb) >> 2);
             R mindd = R(1);
             // two quads per lane per step, the next two already in flight.
-            // Loads run up to 3*LPV quads past the row end (the index array
+            // Loads run up to 3*LPV quads past the slice end (the offset array
             // carries kSegTailPad entries of slack); quads past the end are
             // replaced by sentinels, whose terms are exactly 0.
             int q = gl;
@@ -190,13 +376,13 @@ __device__ __forceinline__ void seg_rows(const SegArgs& a, int s, int vb, int ve
                 acc.add(sx, sy);
             }
             if (mindd == R(0)) coinc += count_coincident_quads<V, LPV>(xv, q4, nq, gl, lds);
-            const int32_t ab = a.aptr[slot], ae = a.aptr[slot + 1];
+            const int32_t ab = a.sl_a[i], ae = a.sl_a[i + 1];
             for (int32_t j = ab + gl; j < ae; j += LPV)
                 attract<P>(xv.x, xv.y, *reinterpret_cast<const V*>(lds + a.aidx[j]), dpar, acc);
         }
         const double fx = group_sum<LPV>(acc.x());
         const double fy = group_sum<LPV>(acc.y());
-        if (v < ve && gl == 0) a.part[sbase + v] = make_double2(fx, fy);
+        if (i < ie && gl == 0) a.part[a.sl_p[i]] = make_double2(fx, fy);
     }
 }
 
@@ -209,7 +395,7 @@ __global__ __launch_bounds__(kSegBlock) void seg_force_kernel(SegArgs a) {
     __shared__ int64_t s_c[kSegBlock / 64];
     if (a.ctl->stopped) return;
     const int4 w = a.wg[blockIdx.x];
-    const int s = w.x, vb = w.y, ve = w.z, lpv = w.w;
+    const int s = w.x, ib = w.y, ie = w.z, lpv = w.w;
     // stage the segment's positions
     const V* gpos = reinterpret_cast<const V*>(a.pos);
     const int64_t base = (int64_t)s * a.seg;
@@ -225,13 +411,13 @@ __global__ __launch_bounds__(kSegBlock) void seg_force_kernel(SegArgs a) {
     __syncthreads();
     int coinc = 0;
     switch (lpv) {
-        case 1: seg_rows<P, 1>(a, s, vb, ve, lp, coinc); break;
-        case 2: seg_rows<P, 2>(a, s, vb, ve, lp, coinc); break;
-        case 4: seg_rows<P, 4>(a, s, vb, ve, lp, coinc); break;
-        case 8: seg_rows<P, 8>(a, s, vb, ve, lp, coinc); break;
-        case 16: seg_rows<P, 16>(a, s, vb, ve, lp, coinc); break;
-        case 32: seg_rows<P, 32>(a, s, vb, ve, lp, coinc); break;
-        default: seg_rows<P, 64>(a, s, vb, ve, lp, coinc); break;
+        case 1: seg_slices<P, 1>(a, ib, ie, lp, coinc); break;
+        case 2: seg_slices<P, 2>(a, ib, ie, lp, coinc); break;
+        case 4: seg_slices<P, 4>(a, ib, ie, lp, coinc); break;
+        case 8: seg_slices<P, 8>(a, ib, ie, lp, coinc); break;
+        case 16: seg_slices<P, 16>(a, ib, ie, lp, coinc); break;
+        case 32: seg_slices<P, 32>(a, ib, ie, lp, coinc); break;
+        default: seg_slices<P, 64>(a, ib, ie, lp, coinc); break;
     }
     const int64_t wc = wave_sum((int64_t)coinc);
     if (lane64() == 0) s_c[wave_id()] = wc;
@@ -254,8 +440,9 @@ __global__ __launch_bounds__(kBlock) void seg_combine_kernel(StepArgs a) {
     const int32_t v = blockIdx.x * kBlock + threadIdx.x;
     if (v < a.n_active) {
         double fx = 0.0, fy = 0.0;
-        for (int s = 0; s < a.nseg; ++s) {
-            const double2 p = a.part[(int64_t)s * a.n_active + v];
+        const int64_t je = a.vsl[v + 1];
+        for (int64_t j = a.vsl[v]; j < je; ++j) {
+            const double2 p = a.part[j];
             fx += p.x;
             fy += p.y;
         }
@@ -281,115 +468,179 @@ int seg_size_for(int precision, int device) {
     return std::max(64, S);
 }
 
-static int lanes_for(int64_t med) {
-    // enough quads per lane (GILA_SEG_QPL, default 8) to amortise the
-    // per-slice reduction
-    const int64_t qpl = env_int("GILA_SEG_QPL", 8);
-    int l = 1;
-    while (l < 64 && (int64_t)l * 2 * qpl * 4 <= med) l *= 2;
-    return l;
+void free_segments(gila_khop* kh) {
+    dfree(kh->vsl);
+    dfree(kh->sl_v);
+    dfree(kh->sl_p);
+    dfree(kh->sl_k);
+    dfree(kh->sl_a);
+    dfree(kh->sk_idx);
+    dfree(kh->sa_idx);
+    dfree(kh->seg_wg);
+    dfree(kh->part);
+    kh->vsl = nullptr;
+    kh->sl_v = kh->sl_p = kh->sl_a = nullptr;
+    kh->sl_k = nullptr;
+    kh->sk_idx = kh->sa_idx = nullptr;
+    kh->seg_wg = nullptr;
+    kh->part = nullptr;
+    kh->seg_ready = false;
+    kh->nslices = 0;
 }
+
+namespace {
+// One device allocation carved into 256-byte aligned pieces.
+struct Arena {
+    void* base = nullptr;
+    size_t used = 0, cap = 0;
+    ~Arena() { dfree(base); }
+    template <class T>
+    T* take(size_t count) {
+        T* p = reinterpret_cast<T*>(static_cast<char*>(base) + used);
+        used += (count * sizeof(T) + 255) & ~(size_t)255;
+        return p;
+    }
+    template <class T>
+    static size_t size(size_t count) {
+        return (count * sizeof(T) + 255) & ~(size_t)255;
+    }
+};
+}  // namespace
 
 int build_segments(gila_khop* kh, int precision, hipStream_t st) {
     const int32_t na = kh->n_active;
     const int pos_bytes = precision == GILA_FP64 ? 16 : 8;
     const int S = seg_size_for(precision, kh->device);
     if (kh->seg_ready && kh->seg == S) return GILA_OK;
-    // release an older layout
-    dfree(kh->sk_ptr);
-    dfree(kh->sk_idx);
-    dfree(kh->sa_ptr);
-    dfree(kh->sa_idx);
-    dfree(kh->seg_wg);
-    dfree(kh->part);
-    kh->sk_ptr = nullptr;
-    kh->sk_idx = nullptr;
-    kh->sa_ptr = nullptr;
-    kh->sa_idx = nullptr;
-    kh->seg_wg = nullptr;
-    kh->part = nullptr;
-    kh->seg_ready = false;
+    free_segments(kh);
     if (na == 0) return GILA_OK;
     if (kh->nnz >= (int64_t)INT32_MAX) return fail(GILA_EUNSUPPORTED, "adjacency too large");
     const int32_t nseg = (int32_t)((na + (int64_t)S - 1) / S);
-    const int64_t slots = (int64_t)nseg * na;
+    if (nseg > kMaxSegments) return fail(GILA_EUNSUPPORTED, "too many segments (%d)", nseg);
     PhaseTimer pt("build_segments", st);
+    const int grid_rows = (int)std::min<int64_t>(16384, ((int64_t)na * 64 + kBlock - 1) / kBlock);
 
-    int32_t *d_kc = nullptr, *d_ac = nullptr;
-    GILA_TRY(dalloc_t(&d_kc, (size_t)slots));
-    int rc = dalloc_t(&d_ac, (size_t)slots);
-    if (rc) {
-        dfree(d_kc);
-        return rc;
+    // --- slices per row, row-major offsets
+    GILA_TRY(dalloc_t(&kh->vsl, (size_t)na + 1));
+    int64_t T = 0;
+    {
+        Arena ar;
+        const size_t ws = (size_t)scan_workspace_count(na);
+        GILA_TRY(dalloc(&ar.base, Arena::size<int64_t>(na) + Arena::size<int64_t>(ws)));
+        SliceBuild b{};
+        b.na = na;
+        b.S = S;
+        b.nseg = nseg;
+        b.pos_bytes = pos_bytes;
+        b.kptr = kh->kptr;
+        b.kidx = kh->kidx;
+        b.rp = kh->rp;
+        b.ci = kh->ci;
+        b.rs = ar.take<int64_t>(na);
+        hipLaunchKernelGGL(slice_rows_kernel<false>, dim3(grid_rows), dim3(kBlock), 0, st, b);
+        GILA_HIP(hipGetLastError());
+        GILA_TRY(enqueue_exclusive_scan_i64(b.rs, kh->vsl, na, ar.take<int64_t>(ws), st));
+        GILA_HIP(hipMemcpyAsync(&T, kh->vsl + na, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        GILA_HIP(hipStreamSynchronize(st));
     }
-    const int grid = (int)std::min<int64_t>(8192, ((int64_t)na * 64 + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(seg_count_kernel, dim3(grid), dim3(kBlock), 0, st, na, S, nseg, kh->kptr,
-                       kh->kidx, kh->rp, kh->ci, d_kc, d_ac);
-    std::vector<int32_t> kc((size_t)slots), ac((size_t)slots);
-    hipError_t e1 = hipGetLastError();
-    hipError_t e2 = hipMemcpyAsync(kc.data(), d_kc, sizeof(int32_t) * slots, hipMemcpyDeviceToHost, st);
-    hipError_t e3 = hipMemcpyAsync(ac.data(), d_ac, sizeof(int32_t) * slots, hipMemcpyDeviceToHost, st);
-    hipError_t e4 = hipStreamSynchronize(st);
-    dfree(d_ac);
-    struct KcGuard {
-        int32_t* p;
-        ~KcGuard() { dfree(p); }
-    } kc_guard{d_kc};
-    if (e1 || e2 || e3 || e4) return fail(GILA_EDEVICE, "segment count failed");
-
+    if (T <= 0 || T >= (int64_t)INT32_MAX) return fail(GILA_EUNSUPPORTED, "%lld slices", (long long)T);
     pt.mark("count");
-    // segment-major offsets
-    std::vector<int64_t> skp((size_t)slots + 1);
-    std::vector<int32_t> sap((size_t)slots + 1);
-    skp[0] = 0;
-    sap[0] = 0;
-    int64_t ksum = 0;
-    for (int64_t i = 0; i < slots; ++i) {
-        ksum += kc[i];
-        skp[i + 1] = skp[i] + ((kc[i] + 3) & ~3);
-        sap[i + 1] = sap[i] + ac[i];
-    }
-    if (ksum != kh->P || sap[slots] != kh->nnz)
-        return fail(GILA_EDEVICE, "segment slices do not cover the lists");
-    const int64_t kstore = skp[slots];
+    if (pt.on) pt.log += " nseg=" + std::to_string(nseg) + " slices=" + std::to_string(T);
 
-    // workgroup plan: per segment, contiguous row ranges of ~equal work
+    // --- counting sort of the slices by segment (tiles of tj slices)
+    const int64_t tj = std::max<int64_t>(4096, (T * (int64_t)nseg + (1 << 24) - 1) >> 24);
+    const int64_t ntiles = (T + tj - 1) / tj;
+    const int64_t H = ntiles * nseg;
+    const size_t ws = (size_t)std::max(scan_workspace_count(H), scan_workspace_count(T));
+    Arena ar;
+    GILA_TRY(dalloc(&ar.base, Arena::size<int32_t>(T) * 5 + Arena::size<int64_t>(T) +  // d_*
+                                  Arena::size<int64_t>(H) + Arena::size<int64_t>(H + 1) +  // hist, its scan
+                                  Arena::size<int32_t>(T) +                                // order
+                                  Arena::size<int64_t>(T) * 2 + Arena::size<int64_t>(T + 1) +  // wk, wa, sl_a64
+                                  Arena::size<int64_t>(ws) + Arena::size<int64_t>(2 * nseg + 4)));
+    SliceBuild b{};
+    b.na = na;
+    b.S = S;
+    b.nseg = nseg;
+    b.pos_bytes = pos_bytes;
+    b.kptr = kh->kptr;
+    b.kidx = kh->kidx;
+    b.rp = kh->rp;
+    b.ci = kh->ci;
+    b.vsl = kh->vsl;
+    b.d_seg = ar.take<int32_t>(T);
+    b.d_k0 = ar.take<int64_t>(T);
+    b.d_kn = ar.take<int32_t>(T);
+    b.d_a0 = ar.take<int32_t>(T);
+    b.d_an = ar.take<int32_t>(T);
+    b.d_row = ar.take<int32_t>(T);
+    int64_t* hist = ar.take<int64_t>(H);
+    int64_t* hscan = ar.take<int64_t>(H + 1);
+    int32_t* order = ar.take<int32_t>(T);
+    int64_t* wk = ar.take<int64_t>(T);
+    int64_t* wa = ar.take<int64_t>(T);
+    int64_t* sl_a64 = ar.take<int64_t>(T + 1);
+    int64_t* sws = ar.take<int64_t>(ws);
+    int64_t* starts = ar.take<int64_t>(2 * nseg + 4);
+
+    GILA_TRY(dalloc_t(&kh->sl_v, (size_t)T));
+    GILA_TRY(dalloc_t(&kh->sl_p, (size_t)T));
+    GILA_TRY(dalloc_t(&kh->sl_k, (size_t)T + 1));
+    GILA_TRY(dalloc_t(&kh->sl_a, (size_t)T + 1));
+    GILA_TRY(dalloc_t(&kh->part, (size_t)T));
+
+    hipLaunchKernelGGL(slice_rows_kernel<true>, dim3(grid_rows), dim3(kBlock), 0, st, b);
+    const size_t cnt_lds = sizeof(int32_t) * (size_t)nseg;
+    if (cnt_lds > 48 * 1024) {
+        (void)hipFuncSetAttribute((const void*)slice_hist_kernel,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)cnt_lds);
+        (void)hipFuncSetAttribute((const void*)slice_scatter_kernel,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)cnt_lds);
+    }
+    hipLaunchKernelGGL(slice_hist_kernel, dim3((unsigned)ntiles), dim3(kBlock), cnt_lds, st, T, tj,
+                       ntiles, nseg, b.d_seg, hist);
+    GILA_HIP(hipGetLastError());
+    GILA_TRY(enqueue_exclusive_scan_i64(hist, hscan, H, sws, st));
+    hipLaunchKernelGGL(slice_scatter_kernel, dim3((unsigned)ntiles), dim3(64), cnt_lds, st, T, tj,
+                       ntiles, nseg, b.d_seg, hscan, order);
+    hipLaunchKernelGGL(slice_lengths_kernel, dim3((unsigned)((T + kBlock - 1) / kBlock)),
+                       dim3(kBlock), 0, st, T, order, b.d_kn, b.d_an, wk, wa);
+    GILA_HIP(hipGetLastError());
+    GILA_TRY(enqueue_exclusive_scan_i64(wk, kh->sl_k, T, sws, st));
+    GILA_TRY(enqueue_exclusive_scan_i64(wa, sl_a64, T, sws, st));
+    const int64_t slice_cost = env_int("GILA_SEG_ROW_COST", 24);
+    hipLaunchKernelGGL(segment_starts_kernel, dim3((nseg + 1 + kBlock - 1) / kBlock), dim3(kBlock), 0,
+                       st, nseg, T, ntiles, slice_cost, hscan, kh->sl_k, sl_a64, starts);
+    GILA_HIP(hipGetLastError());
+    std::vector<int64_t> hs((size_t)2 * nseg + 3);
+    GILA_HIP(hipMemcpyAsync(hs.data(), starts, sizeof(int64_t) * hs.size(), hipMemcpyDeviceToHost, st));
+    GILA_HIP(hipStreamSynchronize(st));
+    const int64_t kstore = hs[2 * nseg + 2];
+    if (hs[2 * nseg] != T || hs[0] != 0 || kstore < kh->P)
+        return fail(GILA_EDEVICE, "segment slices do not cover the lists");
+    pt.mark("sort");
+
+    // --- workgroups: per segment, ranges of about equal work
     const int cus = device_info(kh->device).cus;
-    const int64_t row_cost = env_int("GILA_SEG_ROW_COST", 24);
-    const int64_t total = kh->P + kh->nnz + row_cost * slots;
+    const int64_t total = hs[2 * nseg + 1] - hs[1];
     const int64_t target_wgs = (int64_t)cus * env_int("GILA_SEG_WG_PER_CU", 16);
     const int64_t per_wg = std::max<int64_t>(4096, total / std::max<int64_t>(1, target_wgs));
     std::vector<int4> plan;
-    std::vector<int64_t> lens;
-    for (int32_t s = 0; s < nseg; ++s) {
-        const int64_t b = (int64_t)s * na;
-        int32_t start = 0;
-        int64_t acc = 0;
-        for (int32_t v = 0; v < na; ++v) {
-            acc += kc[b + v] + ac[b + v] + row_cost;
-            if (acc >= per_wg || v == na - 1) {
-                lens.clear();
-                for (int32_t u = start; u <= v; ++u) lens.push_back(kc[b + u] + ac[b + u]);
-                std::nth_element(lens.begin(), lens.begin() + lens.size() / 2, lens.end());
-                const int lpv = lanes_for(lens[lens.size() / 2]);
-                plan.push_back(make_int4(s, start, v + 1, lpv));
-                start = v + 1;
-                acc = 0;
-            }
-        }
+    for (int32_t sg = 0; sg < nseg; ++sg) {
+        if (hs[2 * sg + 2] == hs[2 * sg]) continue;
+        const int64_t W = hs[2 * sg + 3] - hs[2 * sg + 1];
+        const int c = (int)std::max<int64_t>(1, (W + per_wg - 1) / per_wg);
+        for (int t = 0; t < c; ++t) plan.push_back(make_int4(sg, t, c, 0));
     }
-    pt.mark("plan");
     kh->seg = S;
     kh->nseg = nseg;
+    kh->nslices = T;
     kh->seg_grid = (int32_t)plan.size();
     kh->comb_grid = (na + kBlock - 1) / kBlock;
 
-    GILA_TRY(dalloc_t(&kh->sk_ptr, (size_t)slots + 1));
-    GILA_TRY(dalloc_t(&kh->sa_ptr, (size_t)slots + 1));
     GILA_TRY(dalloc_t(&kh->sk_idx, (size_t)kstore + kSegTailPad));
     GILA_TRY(dalloc_t(&kh->sa_idx, (size_t)kh->nnz + 64));
     GILA_TRY(dalloc_t(&kh->seg_wg, plan.size()));
-    GILA_TRY(dalloc_t(&kh->part, (size_t)slots));
     if (kh->comb_grid > kh->partials_cap) {
         dfree(kh->partials);
         kh->partials = nullptr;
@@ -397,18 +648,16 @@ int build_segments(gila_khop* kh, int precision, hipStream_t st) {
         GILA_TRY(dalloc_t(&kh->partials, (size_t)kh->comb_grid));
         kh->partials_cap = kh->comb_grid;
     }
-    pt.mark("alloc");
-    GILA_HIP(hipMemcpyAsync(kh->sk_ptr, skp.data(), sizeof(int64_t) * (slots + 1),
-                            hipMemcpyHostToDevice, st));
-    GILA_HIP(hipMemcpyAsync(kh->sa_ptr, sap.data(), sizeof(int32_t) * (slots + 1),
-                            hipMemcpyHostToDevice, st));
     GILA_HIP(hipMemcpyAsync(kh->seg_wg, plan.data(), sizeof(int4) * plan.size(),
                             hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(seg_fill_kernel, dim3(grid), dim3(kBlock), 0, st, na, S, nseg, pos_bytes,
-                       kh->kptr, kh->kidx, kh->rp, kh->ci, d_kc, kh->sk_ptr, kh->sk_idx,
-                       kh->sa_ptr, kh->sa_idx);
+    const int fill_grid =
+        (int)std::min<int64_t>(65536, (T * kFillLanes + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(slice_fill_kernel, dim3(fill_grid), dim3(kBlock), 0, st, b, T, order,
+                       kh->sl_k, sl_a64, kh->sk_idx, kh->sa_idx, kh->sl_v, kh->sl_p, kh->sl_a);
+    hipLaunchKernelGGL(segment_plan_kernel, dim3((unsigned)((plan.size() + kBlock - 1) / kBlock)),
+                       dim3(kBlock), 0, st, (int32_t)plan.size(), slice_cost,
+                       (int64_t)env_int("GILA_SEG_QPL", 8), starts, kh->sl_k, kh->sl_a, kh->seg_wg);
     GILA_HIP(hipGetLastError());
-    pt.mark("upload+fill");
     const size_t lds = (size_t)(S + 1) * pos_bytes;
     if (lds > 48 * 1024) {
         (void)hipFuncSetAttribute((const void*)seg_force_kernel<GILA_FP64>,
@@ -419,9 +668,10 @@ int build_segments(gila_khop* kh, int precision, hipStream_t st) {
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     }
     GILA_HIP(hipStreamSynchronize(st));
+    pt.mark("fill+plan");
     kh->seg_precision = precision;
     kh->seg_ready = true;
-    kh->device_bytes += (int64_t)(slots + 1) * 12 + 2 * (kstore + kh->nnz) + 16 * slots +
+    kh->device_bytes += (int64_t)(na + 1) * 8 + T * (4 + 4 + 8 + 4 + 16) + 2 * (kstore + kh->nnz) +
                         (int64_t)sizeof(int4) * (int64_t)plan.size();
     return GILA_OK;
 }
@@ -433,16 +683,18 @@ int launch_segment_step(const gila_khop* kh, int precision, const StepArgs& a, h
     g.na = kh->n_active;
     g.seg = kh->seg;
     g.wg = kh->seg_wg;
-    g.kptr = kh->sk_ptr;
+    g.sl_v = kh->sl_v;
+    g.sl_p = kh->sl_p;
+    g.sl_k = kh->sl_k;
+    g.sl_a = kh->sl_a;
     g.kidx = kh->sk_idx;
-    g.aptr = kh->sa_ptr;
     g.aidx = kh->sa_idx;
     g.pos = a.pos_cur;
     g.part = kh->part;
     g.d = a.d;
     g.ctl = a.ctl;
     StepArgs c = a;
-    c.nseg = kh->nseg;
+    c.vsl = kh->vsl;
     c.part = kh->part;
     c.nblocks = kh->comb_grid;
     const int pos_bytes = precision == GILA_FP64 ? 16 : 8;

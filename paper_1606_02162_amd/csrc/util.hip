@@ -60,23 +60,32 @@ __global__ __launch_bounds__(kBlock) void scan_add_kernel(int64_t* __restrict__ 
     if (blockIdx.x == 0 && threadIdx.x == 0) out[0] = 0;
 }
 
-int exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t s) {
+int64_t scan_workspace_count(int64_t n) { return n <= 0 ? 1 : (n + kScanTile - 1) / kScanTile; }
+
+int enqueue_exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* ws,
+                               hipStream_t s) {
     if (n <= 0) {
-        GILA_HIP(hipMemsetAsync(out, 0, sizeof(int64_t), s));
+        hipLaunchKernelGGL(scan_add_kernel, dim3(1), dim3(kBlock), 0, s, out, (int64_t)0, ws);
+        GILA_HIP(hipGetLastError());
         return GILA_OK;
     }
-    const int64_t tiles = (n + kScanTile - 1) / kScanTile;
-    int64_t* sums = nullptr;
-    GILA_TRY(dalloc_t(&sums, (size_t)tiles));
+    const int64_t tiles = scan_workspace_count(n);
     hipLaunchKernelGGL(scan_tiles_kernel, dim3((unsigned)tiles), dim3(kBlock), 0, s, in, out, n,
-                       sums);
-    hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(kBlock), 0, s, sums, tiles);
-    hipLaunchKernelGGL(scan_add_kernel, dim3((unsigned)tiles), dim3(kBlock), 0, s, out, n, sums);
-    const hipError_t e = hipGetLastError();
+                       ws);
+    hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(kBlock), 0, s, ws, tiles);
+    hipLaunchKernelGGL(scan_add_kernel, dim3((unsigned)tiles), dim3(kBlock), 0, s, out, n, ws);
+    GILA_HIP(hipGetLastError());
+    return GILA_OK;
+}
+
+int exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t s) {
+    int64_t* ws = nullptr;
+    GILA_TRY(dalloc_t(&ws, (size_t)scan_workspace_count(n)));
+    const int rc = enqueue_exclusive_scan_i64(in, out, n, ws, s);
     const hipError_t e2 = hipStreamSynchronize(s);
-    dfree(sums);
-    if (e != hipSuccess || e2 != hipSuccess)
-        return fail(GILA_EDEVICE, "scan failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+    dfree(ws);
+    if (rc) return rc;
+    if (e2 != hipSuccess) return fail(GILA_EDEVICE, "scan failed: %s", hipGetErrorString(e2));
     return GILA_OK;
 }
 
