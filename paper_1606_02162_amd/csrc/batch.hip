@@ -311,7 +311,9 @@ __global__ __launch_bounds__(kBatchBlock) void batch_layout_kernel(BatchArgs a) 
         }
         __syncthreads();
         if (threadIdx.x == 0 && a.t_end) {
-            __threadfence();
+            // the workgroup's position stores have completed (the barrier
+            // above, then a wait for this wave's own stores)
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
             a.t_end[gid] = wall_clock64();
         }
         __syncthreads();

@@ -137,7 +137,7 @@ int launch_step(const gila_khop* kh, int precision, const StepArgs& a, hipStream
         default: return fail(GILA_EINVAL, "unknown precision %d", precision);
     }
     GILA_HIP(hipGetLastError());
-    return GILA_OK;
+    return launch_iteration_stats(a, s);
 }
 
 // ------------------------------------------------------------------ plan

@@ -78,12 +78,12 @@ constexpr int64_t kHubMin = 8192; // rows at least this long get a workgroup of 
 constexpr int kWaves = kBlock / 64;
 
 // ------------------------------------------------------------------ device control block
-// Written by the last workgroup of each iteration kernel; read by the host at
-// the end of a call and by the next iteration kernel (stopped flag).
+// Written by the statistics kernel that ends each iteration; read by the host
+// at the end of a call and by the next iteration's kernels (stopped flag).
 struct Ctl {
     int32_t stopped;
     int32_t iters_run;
-    uint32_t done_blocks;  // "last block" ticket, reset to 0 by the last block
+    uint32_t done_blocks;  // reserved
     int32_t pad;
     int64_t moved;
     double max_disp;
@@ -249,6 +249,9 @@ int launch_segment_step(const gila_khop* kh, int precision, const StepArgs& a, h
                         hipEvent_t* ev = nullptr);
 bool segment_path_enabled();
 int seg_size_for(int precision, int device);
+// implemented in layout.hip: publishes an iteration's statistics from the
+// per-workgroup partials (launched after each per-vertex kernel)
+int launch_iteration_stats(const StepArgs& a, hipStream_t s);
 // implemented in layout.hip: one iteration on whichever path the handle is ready for
 int launch_iteration(const gila_khop* kh, int precision, const StepArgs& a, hipStream_t s);
 int prepare_precision(gila_khop* kh, int precision, hipStream_t s);

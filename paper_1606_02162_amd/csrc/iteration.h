@@ -174,29 +174,27 @@ __device__ __forceinline__ void finish_vertex(const StepArgs& a, int32_t v, type
     moved += dl > a.stop_displacement ? 1 : 0;
 }
 
-// Ends an iteration kernel: workgroup statistics in a fixed order, then the
-// workgroup that finishes last reduces every workgroup's partial in index
-// order and publishes the iteration's statistics (and the halting decision).
-// Every thread of the workgroup must call it.  `extra_coinc` is a pending
-// coincident-pair count accumulated by an earlier kernel of the iteration.
+// Ends the per-vertex part of an iteration kernel: the workgroup's statistics,
+// reduced in a fixed order, go to a.partials[blockIdx.x].  The iteration's
+// totals are published by iteration_stats_kernel, launched next on the same
+// stream (a kernel boundary makes the partials visible to it without a
+// device-wide cache writeback per workgroup).  Every thread of the workgroup
+// must call it.
 __device__ __forceinline__ void end_iteration(const StepArgs& a, double energy, double maxd,
                                               int64_t moved, int64_t coinc) {
     __shared__ double s_e[kWaves], s_m[kWaves];
     __shared__ int64_t s_mv[kWaves], s_c[kWaves];
-    __shared__ int s_last;
     const int lane = lane64();
     const int w = wave_id();
-    {
-        const double we = wave_sum(energy);
-        const double wm = wave_max(maxd);
-        const int64_t wmv = wave_sum(moved);
-        const int64_t wc = wave_sum(coinc);
-        if (lane == 0) {
-            s_e[w] = we;
-            s_m[w] = wm;
-            s_mv[w] = wmv;
-            s_c[w] = wc;
-        }
+    const double we = wave_sum(energy);
+    const double wm = wave_max(maxd);
+    const int64_t wmv = wave_sum(moved);
+    const int64_t wc = wave_sum(coinc);
+    if (lane == 0) {
+        s_e[w] = we;
+        s_m[w] = wm;
+        s_mv[w] = wmv;
+        s_c[w] = wc;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -212,65 +210,6 @@ __device__ __forceinline__ void end_iteration(const StepArgs& a, double energy, 
             p.coincident += s_c[i];
         }
         a.partials[blockIdx.x] = p;
-        __threadfence();
-        const unsigned ticket = atomicAdd(&a.ctl->done_blocks, 1u);
-        s_last = (ticket == (unsigned)gridDim.x - 1u);
-    }
-    __syncthreads();
-    if (!s_last) return;
-
-    __threadfence();
-    const volatile Partial* vp = a.partials;
-    double e = 0.0, m = 0.0;
-    int64_t mv = 0, c = 0;
-    for (int i = threadIdx.x; i < (int)gridDim.x; i += kBlock) {
-        e += vp[i].energy;
-        const double x = vp[i].max_disp;
-        m = x > m ? x : m;
-        mv += vp[i].moved;
-        c += vp[i].coincident;
-    }
-    e = wave_sum(e);
-    m = wave_max(m);
-    mv = wave_sum(mv);
-    c = wave_sum(c);
-    if (lane == 0) {
-        s_e[w] = e;
-        s_m[w] = m;
-        s_mv[w] = mv;
-        s_c[w] = c;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        e = s_e[0];
-        m = s_m[0];
-        mv = s_mv[0];
-        c = s_c[0];
-        for (int i = 1; i < kWaves; ++i) {
-            e += s_e[i];
-            m = s_m[i] > m ? s_m[i] : m;
-            mv += s_mv[i];
-            c += s_c[i];
-        }
-        Ctl* ctl = a.ctl;
-        volatile int64_t* pend = &ctl->coinc_pending;
-        c += *pend;
-        *pend = 0;
-        ctl->energy = e;
-        ctl->max_disp = m;
-        ctl->moved = mv;
-        ctl->coincident = c;
-        ctl->iters_run += 1;
-        if (a.check_stop && (double)mv < a.stop_fraction * (double)a.n_active) ctl->stopped = 1;
-        if (a.hist_slot >= 0) {
-            double* hrow = a.hist + 4 * (int64_t)a.hist_slot;
-            hrow[0] = e;
-            hrow[1] = m;
-            hrow[2] = (double)mv;
-            hrow[3] = (double)c;
-        }
-        ctl->done_blocks = 0u;
-        __threadfence();
     }
 }
 

@@ -9,6 +9,72 @@
 
 namespace gila {
 
+// ------------------------------------------------------------------ iteration statistics
+// One workgroup, after the iteration's per-vertex kernel: reduces the
+// workgroups' partials (a.nblocks of them) in a fixed order and publishes the
+// iteration's statistics (Section 5.1 halting rule included).
+__global__ __launch_bounds__(kBlock) void iteration_stats_kernel(StepArgs a) {
+    __shared__ double s_e[kWaves], s_m[kWaves];
+    __shared__ int64_t s_mv[kWaves], s_c[kWaves];
+    Ctl* ctl = a.ctl;
+    if (ctl->stopped) return;
+    const int lane = lane64();
+    const int w = wave_id();
+    double e = 0.0, m = 0.0;
+    int64_t mv = 0, c = 0;
+    for (int i = threadIdx.x; i < a.nblocks; i += kBlock) {
+        const Partial p = a.partials[i];
+        e += p.energy;
+        m = p.max_disp > m ? p.max_disp : m;
+        mv += p.moved;
+        c += p.coincident;
+    }
+    e = wave_sum(e);
+    m = wave_max(m);
+    mv = wave_sum(mv);
+    c = wave_sum(c);
+    if (lane == 0) {
+        s_e[w] = e;
+        s_m[w] = m;
+        s_mv[w] = mv;
+        s_c[w] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        e = s_e[0];
+        m = s_m[0];
+        mv = s_mv[0];
+        c = s_c[0];
+        for (int i = 1; i < kWaves; ++i) {
+            e += s_e[i];
+            m = s_m[i] > m ? s_m[i] : m;
+            mv += s_mv[i];
+            c += s_c[i];
+        }
+        c += ctl->coinc_pending;
+        ctl->coinc_pending = 0;
+        ctl->energy = e;
+        ctl->max_disp = m;
+        ctl->moved = mv;
+        ctl->coincident = c;
+        ctl->iters_run += 1;
+        if (a.check_stop && (double)mv < a.stop_fraction * (double)a.n_active) ctl->stopped = 1;
+        if (a.hist_slot >= 0) {
+            double* hrow = a.hist + 4 * (int64_t)a.hist_slot;
+            hrow[0] = e;
+            hrow[1] = m;
+            hrow[2] = (double)mv;
+            hrow[3] = (double)c;
+        }
+    }
+}
+
+int launch_iteration_stats(const StepArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(iteration_stats_kernel, dim3(1), dim3(kBlock), 0, s, a);
+    GILA_HIP(hipGetLastError());
+    return GILA_OK;
+}
+
 // ------------------------------------------------------------------ placement
 __device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t c) {
     // output number c (0-based) of SplitMix64 seeded with `seed`

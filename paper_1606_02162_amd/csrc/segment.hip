@@ -39,7 +39,11 @@
 namespace gila {
 
 constexpr int kSegBlock = 512;     // threads per segment workgroup
-constexpr int kSegTailPad = 1024;  // slack entries after the k-hop offsets (>= 3 * 64 quads)
+#ifndef GILA_SEG_WAVES
+#define GILA_SEG_WAVES 8
+#endif
+constexpr int kSegWaves = GILA_SEG_WAVES;  // waves per SIMD the FP32 force kernel is built for
+constexpr int kSegTailPad = 64;    // slack entries after the k-hop offsets
 constexpr int kMaxSegments = 16384;  // segment counters of the build fit in 64 KB of LDS
 constexpr int kLongRow = 16;       // rows longer than kLongRow * nseg: binary search per segment
 constexpr int kFillLanes = 16;     // lanes per slice in the fill pass
@@ -312,25 +316,54 @@ __device__ __forceinline__ int count_coincident_quads(V xv, const uint2* __restr
     return c;
 }
 
-// Repulsion from the four neighbours whose LDS byte offsets are packed in w.
+// Squared distance plus a tiny bias: a coincident pair gets delta^2 = bias
+// instead of 0, so its reciprocal is finite and its term (dx = dy = 0) is
+// exactly 0.  For any two distinct positions of magnitude below ~1e12 the
+// bias is far below the rounding of delta^2 and changes nothing.
+template <class R>
+__device__ __forceinline__ R coincidence_bias() {
+    return sizeof(R) == 4 ? (R)1e-30f : (R)1e-300;
+}
+
+// Repulsion (x_v - x_u) / delta^2 from the four neighbours whose LDS byte
+// offsets are packed in w, summed; the factor d^2 is applied once per slice.
+// A sentinel slot lies so far away that delta^2 = +inf and its term is 0.
 template <class P>
 __device__ __forceinline__ void quad_terms(uint2 w, const unsigned char* __restrict__ lds,
                                            typename P::real xv, typename P::real yv,
-                                           typename P::real d2, typename P::real& sx,
-                                           typename P::real& sy, typename P::real& mindd) {
+                                           typename P::real& sx, typename P::real& sy,
+                                           typename P::real& mindd) {
     using R = typename P::real;
     using V = typename P::vec2;
+    const R bias = coincidence_bias<R>();
     const V p0 = *reinterpret_cast<const V*>(lds + (w.x & 0xFFFFu));
     const V p1 = *reinterpret_cast<const V*>(lds + (w.x >> 16));
     const V p2 = *reinterpret_cast<const V*>(lds + (w.y & 0xFFFFu));
     const V p3 = *reinterpret_cast<const V*>(lds + (w.y >> 16));
-    R x0, y0, x1, y1, x2, y2, x3, y3;
-    repulse_term<P>(xv, yv, p0, d2, x0, y0, mindd);
-    repulse_term<P>(xv, yv, p1, d2, x1, y1, mindd);
-    repulse_term<P>(xv, yv, p2, d2, x2, y2, mindd);
-    repulse_term<P>(xv, yv, p3, d2, x3, y3, mindd);
-    sx = (x0 + x1) + (x2 + x3);
-    sy = (y0 + y1) + (y2 + y3);
+    const R dx0 = xv - p0.x, dy0 = yv - p0.y;
+    const R dx1 = xv - p1.x, dy1 = yv - p1.y;
+    const R dx2 = xv - p2.x, dy2 = yv - p2.y;
+    const R dx3 = xv - p3.x, dy3 = yv - p3.y;
+    const R dd0 = fma(dx0, dx0, fma(dy0, dy0, bias));
+    const R dd1 = fma(dx1, dx1, fma(dy1, dy1, bias));
+    const R dd2 = fma(dx2, dx2, fma(dy2, dy2, bias));
+    const R dd3 = fma(dx3, dx3, fma(dy3, dy3, bias));
+    mindd = fmin(fmin(mindd, dd0), dd1);
+    mindd = fmin(fmin(mindd, dd2), dd3);
+    R r0, r1, r2, r3;
+    if constexpr (sizeof(R) == 4) {
+        r0 = fast_rcp(dd0);
+        r1 = fast_rcp(dd1);
+        r2 = fast_rcp(dd2);
+        r3 = fast_rcp(dd3);
+    } else {
+        r0 = R(1) / dd0;
+        r1 = R(1) / dd1;
+        r2 = R(1) / dd2;
+        r3 = R(1) / dd3;
+    }
+    sx = fma(dx0, r0, dx1 * r1) + fma(dx2, r2, dx3 * r3);
+    sy = fma(dy0, r0, dy1 * r1) + fma(dy2, r2, dy3 * r3);
 }
 
 template <class P, int LPV>
@@ -340,13 +373,12 @@ __device__ __forceinline__ void seg_slices(const SegArgs& a, int ib, int ie,
     using V = typename P::vec2;
     const V* __restrict__ gpos = reinterpret_cast<const V*>(a.pos);
     const unsigned char* __restrict__ lds = reinterpret_cast<const unsigned char*>(lp);
-    const R d2 = (R)(a.d * a.d);
-    const R dpar = attract_param<R>(a.d);
+    const double d2 = a.d * a.d;
+    // attraction (x_u - x_v) delta / d enters the same sum divided by d^2
+    const R dpar = sizeof(R) == 4 ? (R)(1.0 / (a.d * d2)) : (R)(a.d * d2);
     const int ngroups = kSegBlock / LPV;
     const int grp = threadIdx.x / LPV;
     const int gl = threadIdx.x % LPV;
-    const uint32_t sq = (uint32_t)a.seg * (uint32_t)sizeof(V);
-    const uint2 sentinel = make_uint2(sq | (sq << 16), sq | (sq << 16));
     for (int i0 = ib; i0 < ie; i0 += ngroups) {
         const int i = i0 + grp;
         Acc<R, P::kahan> acc;
@@ -356,38 +388,43 @@ __device__ __forceinline__ void seg_slices(const SegArgs& a, int ib, int ie,
             const uint2* __restrict__ q4 = reinterpret_cast<const uint2*>(a.kidx + kb);
             const int nq = (int)((ke - kb) >> 2);
             R mindd = R(1);
-            // two quads per lane per step, the next two already in flight.
-            // Loads run up to 3*LPV quads past the slice end (the offset array
-            // carries kSegTailPad entries of slack); quads past the end are
-            // replaced by sentinels, whose terms are exactly 0.
+            // four quads (16 neighbours) per lane per step, one compensated
+            // add per eight terms; then the remaining quads one by one
             int q = gl;
-            uint2 n0 = q4[q];
-            uint2 n1 = q4[q + LPV];
-            while (q < nq) {
-                const uint2 w0 = n0;
-                const uint2 w1 = q + LPV < nq ? n1 : sentinel;
-                q += 2 * LPV;
-                n0 = q4[q];
-                n1 = q4[q + LPV];
-                R sx, sy;
-                quad_terms<P>(w0, lds, xv.x, xv.y, d2, sx, sy, mindd);
-                acc.add(sx, sy);
-                quad_terms<P>(w1, lds, xv.x, xv.y, d2, sx, sy, mindd);
-                acc.add(sx, sy);
+            for (; q + 3 * LPV < nq; q += 4 * LPV) {
+                const uint2 w0 = q4[q];
+                const uint2 w1 = q4[q + LPV];
+                const uint2 w2 = q4[q + 2 * LPV];
+                const uint2 w3 = q4[q + 3 * LPV];
+                R ax, ay, bx, by;
+                quad_terms<P>(w0, lds, xv.x, xv.y, ax, ay, mindd);
+                quad_terms<P>(w1, lds, xv.x, xv.y, bx, by, mindd);
+                acc.add(ax + bx, ay + by);
+                quad_terms<P>(w2, lds, xv.x, xv.y, ax, ay, mindd);
+                quad_terms<P>(w3, lds, xv.x, xv.y, bx, by, mindd);
+                acc.add(ax + bx, ay + by);
             }
-            if (mindd == R(0)) coinc += count_coincident_quads<V, LPV>(xv, q4, nq, gl, lds);
+            for (; q < nq; q += LPV) {
+                R ax, ay;
+                quad_terms<P>(q4[q], lds, xv.x, xv.y, ax, ay, mindd);
+                acc.add(ax, ay);
+            }
+            if (mindd <= coincidence_bias<R>())
+                coinc += count_coincident_quads<V, LPV>(xv, q4, nq, gl, lds);
             const int32_t ab = a.sl_a[i], ae = a.sl_a[i + 1];
             for (int32_t j = ab + gl; j < ae; j += LPV)
                 attract<P>(xv.x, xv.y, *reinterpret_cast<const V*>(lds + a.aidx[j]), dpar, acc);
         }
-        const double fx = group_sum<LPV>(acc.x());
-        const double fy = group_sum<LPV>(acc.y());
+        const double fx = group_sum<LPV>(acc.x()) * d2;
+        const double fy = group_sum<LPV>(acc.y()) * d2;
         if (i < ie && gl == 0) a.part[a.sl_p[i]] = make_double2(fx, fy);
     }
 }
 
+// FP32: eight waves per SIMD (the LDS of four workgroups per CU allows it);
+// FP64 needs more registers.
 template <int PREC>
-__global__ __launch_bounds__(kSegBlock) void seg_force_kernel(SegArgs a) {
+__global__ __launch_bounds__(kSegBlock, PREC == GILA_FP64 ? 4 : kSegWaves) void seg_force_kernel(SegArgs a) {
     using P = Prec<PREC>;
     using V = typename P::vec2;
     extern __shared__ __align__(16) unsigned char s_raw[];
@@ -439,9 +476,24 @@ __global__ __launch_bounds__(kBlock) void seg_combine_kernel(StepArgs a) {
     int64_t moved = 0;
     const int32_t v = blockIdx.x * kBlock + threadIdx.x;
     if (v < a.n_active) {
+        // partials added one after another in segment order; loads are
+        // issued four at a time
         double fx = 0.0, fy = 0.0;
         const int64_t je = a.vsl[v + 1];
-        for (int64_t j = a.vsl[v]; j < je; ++j) {
+        int64_t j = a.vsl[v];
+        for (; j + 3 < je; j += 4) {
+            const double2 p0 = a.part[j], p1 = a.part[j + 1], p2 = a.part[j + 2],
+                          p3 = a.part[j + 3];
+            fx += p0.x;
+            fy += p0.y;
+            fx += p1.x;
+            fy += p1.y;
+            fx += p2.x;
+            fy += p2.y;
+            fx += p3.x;
+            fy += p3.y;
+        }
+        for (; j < je; ++j) {
             const double2 p = a.part[j];
             fx += p.x;
             fy += p.y;
@@ -714,6 +766,7 @@ int launch_segment_step(const gila_khop* kh, int precision, const StepArgs& a, h
         case GILA_FP32: hipLaunchKernelGGL(seg_combine_kernel<GILA_FP32>, cg, cb, 0, s, c); break;
         default: hipLaunchKernelGGL(seg_combine_kernel<GILA_FP32_KAHAN>, cg, cb, 0, s, c); break;
     }
+    GILA_TRY(launch_iteration_stats(c, s));
     if (ev) GILA_HIP(hipEventRecord(ev[2], s));
     GILA_HIP(hipGetLastError());
     return GILA_OK;

@@ -16,7 +16,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libgila.so")
+LIB_PATH = os.environ.get("GILA_LIBRARY") or os.path.join(_HERE, "libgila.so")
 
 GILA_OK = 0
 GILA_EINVAL = -1
