@@ -5,7 +5,9 @@
 // of an active vertex v is cut into slices, one per segment that the row
 // touches; only non-empty slices exist.  A slice holds its ids as 16-bit LDS
 // byte offsets (id - s*S) * sizeof(position).  Slices are stored
-// segment-major (all slices of segment 0 in row order, then segment 1, ...).
+// segment-major (all slices of segment 0, then segment 1, ...), within a
+// segment longest first, so that the lane groups of one wavefront walk
+// slices of about the same length.
 // k-hop slices are padded to a whole number of 4-id quads with a sentinel
 // offset: LDS slot S holds a position so far away (1e30) that its squared
 // distance overflows to +inf, the reciprocal is exactly 0 and the padding term
@@ -27,9 +29,9 @@
 // its workgroup) and on the fixed segment order, never on scheduling.
 //
 // The layout is built on the device (build_segments): count the slices of
-// every row, emit them row-major, reorder them segment-major with a stable
-// counting sort by segment, prefix-sum the padded lengths, fill the offsets,
-// and cut each segment into workgroups of about equal work.
+// every row, emit them row-major, reorder them by segment and length with two
+// stable counting sorts, prefix-sum the padded lengths, fill the offsets, and
+// cut each segment into workgroups of about equal work.
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
@@ -143,43 +145,51 @@ __global__ __launch_bounds__(kBlock) void slice_rows_kernel(SliceBuild b) {
     }
 }
 
-// Stable counting sort of the row-major slices by segment, in tiles of `tj`
-// consecutive slices.  Pass 1: per-tile histogram, stored segment-major
-// (hist[s * ntiles + tile]) so that its exclusive prefix sum is the first
-// segment-major position of each (segment, tile).
+// Stable counting sort of a sequence of slices by an integer key in
+// [0, nkeys), in tiles of `tj` consecutive elements.  Element i of the input
+// is slice perm[i] (slice i when perm is null); its key is key[perm[i]].
+// Pass 1: per-tile histogram, stored key-major (hist[key * ntiles + tile]) so
+// that its exclusive prefix sum is the first output position of each
+// (key, tile).
+__device__ __forceinline__ int64_t sort_elem(const int32_t* perm, int64_t i) {
+    return perm ? perm[i] : i;
+}
+
 __global__ __launch_bounds__(kBlock) void slice_hist_kernel(int64_t T, int64_t tj, int64_t ntiles,
-                                                            int32_t nseg,
-                                                            const int32_t* __restrict__ d_seg,
+                                                            int32_t nkeys,
+                                                            const int32_t* __restrict__ key,
+                                                            const int32_t* __restrict__ perm,
                                                             int64_t* __restrict__ hist) {
     extern __shared__ int32_t s_cnt[];
-    for (int s = threadIdx.x; s < nseg; s += kBlock) s_cnt[s] = 0;
+    for (int s = threadIdx.x; s < nkeys; s += kBlock) s_cnt[s] = 0;
     __syncthreads();
     const int64_t j0 = (int64_t)blockIdx.x * tj;
     const int64_t j1 = j0 + tj < T ? j0 + tj : T;
-    for (int64_t j = j0 + threadIdx.x; j < j1; j += kBlock) atomicAdd(&s_cnt[d_seg[j]], 1);
+    for (int64_t j = j0 + threadIdx.x; j < j1; j += kBlock) atomicAdd(&s_cnt[key[sort_elem(perm, j)]], 1);
     __syncthreads();
-    for (int s = threadIdx.x; s < nseg; s += kBlock) hist[(int64_t)s * ntiles + blockIdx.x] = s_cnt[s];
+    for (int s = threadIdx.x; s < nkeys; s += kBlock) hist[(int64_t)s * ntiles + blockIdx.x] = s_cnt[s];
 }
 
-// Pass 2 (one wavefront per tile): walk the tile in order, 64 slices at a
-// time; equal segments within a step are ranked by lane, so slices of one
-// segment keep their row-major (= row) order.  order[i] = row-major index of
-// the i-th segment-major slice.
+// Pass 2 (one wavefront per tile): walk the tile in order, 64 elements at a
+// time; equal keys within a step are ranked by lane, so elements with equal
+// keys keep their input order.  out[position] = slice.
 __global__ __launch_bounds__(64) void slice_scatter_kernel(int64_t T, int64_t tj, int64_t ntiles,
-                                                           int32_t nseg,
-                                                           const int32_t* __restrict__ d_seg,
+                                                           int32_t nkeys,
+                                                           const int32_t* __restrict__ key,
+                                                           const int32_t* __restrict__ perm,
                                                            const int64_t* __restrict__ base,
-                                                           int32_t* __restrict__ order) {
+                                                           int32_t* __restrict__ out) {
     extern __shared__ int32_t s_next[];
     const int lane = threadIdx.x;
-    for (int s = lane; s < nseg; s += 64) s_next[s] = (int32_t)base[(int64_t)s * ntiles + blockIdx.x];
+    for (int s = lane; s < nkeys; s += 64) s_next[s] = (int32_t)base[(int64_t)s * ntiles + blockIdx.x];
     __syncthreads();
     const int64_t j0 = (int64_t)blockIdx.x * tj;
     const int64_t j1 = j0 + tj < T ? j0 + tj : T;
     for (int64_t c = j0; c < j1; c += 64) {
         const int64_t j = c + lane;
         const bool valid = j < j1;
-        const int32_t s = valid ? d_seg[j] : -1;
+        const int64_t e = valid ? sort_elem(perm, j) : 0;
+        const int32_t s = valid ? key[e] : -1;
         int rank = 0, same = 0;
         for (int l = 0; l < 64; ++l) {
             const int32_t sl = __builtin_amdgcn_readlane(s, l);
@@ -189,11 +199,22 @@ __global__ __launch_bounds__(64) void slice_scatter_kernel(int64_t T, int64_t tj
         const int32_t at = valid ? s_next[s] : 0;
         __syncthreads();
         if (valid) {
-            order[at + rank] = (int32_t)j;
+            out[at + rank] = (int32_t)e;
             if (rank == same - 1) s_next[s] = at + same;
         }
         __syncthreads();
     }
+}
+
+// Length key of each slice: slices with more quads get smaller keys (longest
+// first), clamped to kLenKeys buckets.
+constexpr int kLenKeys = 1024;
+__global__ __launch_bounds__(kBlock) void slice_lenkey_kernel(int64_t T, const int32_t* __restrict__ d_kn,
+                                                              int32_t* __restrict__ lenkey) {
+    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (j >= T) return;
+    const int32_t nq = (d_kn[j] + 3) >> 2;
+    lenkey[j] = kLenKeys - 1 - (nq < kLenKeys - 1 ? nq : kLenKeys - 1);
 }
 
 // Padded k-hop and adjacency lengths of each segment-major slice.
@@ -368,7 +389,8 @@ __device__ __forceinline__ void quad_terms(uint2 w, const unsigned char* __restr
 
 template <class P, int LPV>
 __device__ __forceinline__ void seg_slices(const SegArgs& a, int ib, int ie,
-                                           const typename P::vec2* __restrict__ lp, int& coinc) {
+                                           const typename P::vec2* __restrict__ lp,
+                                           int* s_next, int& coinc) {
     using R = typename P::real;
     using V = typename P::vec2;
     const V* __restrict__ gpos = reinterpret_cast<const V*>(a.pos);
@@ -376,11 +398,19 @@ __device__ __forceinline__ void seg_slices(const SegArgs& a, int ib, int ie,
     const double d2 = a.d * a.d;
     // attraction (x_u - x_v) delta / d enters the same sum divided by d^2
     const R dpar = sizeof(R) == 4 ? (R)(1.0 / (a.d * d2)) : (R)(a.d * d2);
-    const int ngroups = kSegBlock / LPV;
-    const int grp = threadIdx.x / LPV;
+    // Each wavefront takes the next (64 / LPV) slices of the range when it
+    // is done with its previous ones (slices are sorted longest first, so the
+    // groups of a wavefront get similar work and no wavefront idles while
+    // slices remain).  A slice's result depends only on the slice and LPV.
+    constexpr int kPerWave = 64 / LPV;
     const int gl = threadIdx.x % LPV;
-    for (int i0 = ib; i0 < ie; i0 += ngroups) {
-        const int i = i0 + grp;
+    const int wgrp = lane64() / LPV;
+    for (;;) {
+        int i0 = 0;
+        if (lane64() == 0) i0 = atomicAdd(s_next, kPerWave);
+        i0 = __builtin_amdgcn_readfirstlane(i0);
+        if (i0 >= ie) break;
+        const int i = i0 + wgrp;
         Acc<R, P::kahan> acc;
         if (i < ie) {
             const V xv = gpos[a.sl_v[i]];
@@ -439,7 +469,9 @@ __global__ __launch_bounds__(kSegBlock, PREC == GILA_FP64 ? 4 : kSegWaves) void 
     const int64_t left = (int64_t)a.na - base;
     const int cnt = (int)(left < a.seg ? left : a.seg);
     for (int i = threadIdx.x; i < cnt; i += kSegBlock) lp[i] = gpos[base + i];
+    __shared__ int s_next;
     if (threadIdx.x == 0) {
+        s_next = ib;
         V far;
         far.x = sizeof(far.x) == 4 ? (decltype(far.x))1e30f : (decltype(far.x))1e300;
         far.y = far.x;
@@ -448,13 +480,13 @@ __global__ __launch_bounds__(kSegBlock, PREC == GILA_FP64 ? 4 : kSegWaves) void 
     __syncthreads();
     int coinc = 0;
     switch (lpv) {
-        case 1: seg_slices<P, 1>(a, ib, ie, lp, coinc); break;
-        case 2: seg_slices<P, 2>(a, ib, ie, lp, coinc); break;
-        case 4: seg_slices<P, 4>(a, ib, ie, lp, coinc); break;
-        case 8: seg_slices<P, 8>(a, ib, ie, lp, coinc); break;
-        case 16: seg_slices<P, 16>(a, ib, ie, lp, coinc); break;
-        case 32: seg_slices<P, 32>(a, ib, ie, lp, coinc); break;
-        default: seg_slices<P, 64>(a, ib, ie, lp, coinc); break;
+        case 1: seg_slices<P, 1>(a, ib, ie, lp, &s_next, coinc); break;
+        case 2: seg_slices<P, 2>(a, ib, ie, lp, &s_next, coinc); break;
+        case 4: seg_slices<P, 4>(a, ib, ie, lp, &s_next, coinc); break;
+        case 8: seg_slices<P, 8>(a, ib, ie, lp, &s_next, coinc); break;
+        case 16: seg_slices<P, 16>(a, ib, ie, lp, &s_next, coinc); break;
+        case 32: seg_slices<P, 32>(a, ib, ie, lp, &s_next, coinc); break;
+        default: seg_slices<P, 64>(a, ib, ie, lp, &s_next, coinc); break;
     }
     const int64_t wc = wave_sum((int64_t)coinc);
     if (lane64() == 0) s_c[wave_id()] = wc;
@@ -599,15 +631,22 @@ int build_segments(gila_khop* kh, int precision, hipStream_t st) {
     pt.mark("count");
     if (pt.on) pt.log += " nseg=" + std::to_string(nseg) + " slices=" + std::to_string(T);
 
-    // --- counting sort of the slices by segment (tiles of tj slices)
-    const int64_t tj = std::max<int64_t>(4096, (T * (int64_t)nseg + (1 << 24) - 1) >> 24);
-    const int64_t ntiles = (T + tj - 1) / tj;
-    const int64_t H = ntiles * nseg;
+    // --- slices ordered by segment, then by length (longest first), then
+    // row: two stable counting sorts (length, then segment).  Groups of
+    // lanes in one wavefront then walk slices of about the same length.
+    auto tiling = [&](int32_t nkeys, int64_t& tj, int64_t& ntiles) {
+        tj = std::max<int64_t>(4096, (T * (int64_t)nkeys + (1 << 24) - 1) >> 24);
+        ntiles = (T + tj - 1) / tj;
+    };
+    int64_t tj1, nt1, tj2, nt2;
+    tiling(kLenKeys, tj1, nt1);
+    tiling(nseg, tj2, nt2);
+    const int64_t H = std::max(nt1 * kLenKeys, nt2 * nseg);
     const size_t ws = (size_t)std::max(scan_workspace_count(H), scan_workspace_count(T));
     Arena ar;
     GILA_TRY(dalloc(&ar.base, Arena::size<int32_t>(T) * 5 + Arena::size<int64_t>(T) +  // d_*
                                   Arena::size<int64_t>(H) + Arena::size<int64_t>(H + 1) +  // hist, its scan
-                                  Arena::size<int32_t>(T) +                                // order
+                                  Arena::size<int32_t>(T) * 3 +                            // lenkey, order1, order
                                   Arena::size<int64_t>(T) * 2 + Arena::size<int64_t>(T + 1) +  // wk, wa, sl_a64
                                   Arena::size<int64_t>(ws) + Arena::size<int64_t>(2 * nseg + 4)));
     SliceBuild b{};
@@ -628,6 +667,8 @@ int build_segments(gila_khop* kh, int precision, hipStream_t st) {
     b.d_row = ar.take<int32_t>(T);
     int64_t* hist = ar.take<int64_t>(H);
     int64_t* hscan = ar.take<int64_t>(H + 1);
+    int32_t* lenkey = ar.take<int32_t>(T);
+    int32_t* order1 = ar.take<int32_t>(T);
     int32_t* order = ar.take<int32_t>(T);
     int64_t* wk = ar.take<int64_t>(T);
     int64_t* wa = ar.take<int64_t>(T);
@@ -642,19 +683,30 @@ int build_segments(gila_khop* kh, int precision, hipStream_t st) {
     GILA_TRY(dalloc_t(&kh->part, (size_t)T));
 
     hipLaunchKernelGGL(slice_rows_kernel<true>, dim3(grid_rows), dim3(kBlock), 0, st, b);
-    const size_t cnt_lds = sizeof(int32_t) * (size_t)nseg;
-    if (cnt_lds > 48 * 1024) {
-        (void)hipFuncSetAttribute((const void*)slice_hist_kernel,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)cnt_lds);
-        (void)hipFuncSetAttribute((const void*)slice_scatter_kernel,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)cnt_lds);
-    }
-    hipLaunchKernelGGL(slice_hist_kernel, dim3((unsigned)ntiles), dim3(kBlock), cnt_lds, st, T, tj,
-                       ntiles, nseg, b.d_seg, hist);
+    const unsigned tgrid = (unsigned)((T + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(slice_lenkey_kernel, dim3(tgrid), dim3(kBlock), 0, st, T, b.d_kn, lenkey);
     GILA_HIP(hipGetLastError());
-    GILA_TRY(enqueue_exclusive_scan_i64(hist, hscan, H, sws, st));
-    hipLaunchKernelGGL(slice_scatter_kernel, dim3((unsigned)ntiles), dim3(64), cnt_lds, st, T, tj,
-                       ntiles, nseg, b.d_seg, hscan, order);
+    auto counting_sort = [&](int32_t nkeys, int64_t tj, int64_t ntiles, const int32_t* key,
+                             const int32_t* perm, int32_t* out) -> int {
+        const size_t lds = sizeof(int32_t) * (size_t)nkeys;
+        if (lds > 48 * 1024) {
+            (void)hipFuncSetAttribute((const void*)slice_hist_kernel,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            (void)hipFuncSetAttribute((const void*)slice_scatter_kernel,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        }
+        hipLaunchKernelGGL(slice_hist_kernel, dim3((unsigned)ntiles), dim3(kBlock), lds, st, T, tj,
+                           ntiles, nkeys, key, perm, hist);
+        GILA_HIP(hipGetLastError());
+        GILA_TRY(enqueue_exclusive_scan_i64(hist, hscan, ntiles * nkeys, sws, st));
+        hipLaunchKernelGGL(slice_scatter_kernel, dim3((unsigned)ntiles), dim3(64), lds, st, T, tj,
+                           ntiles, nkeys, key, perm, hscan, out);
+        GILA_HIP(hipGetLastError());
+        return GILA_OK;
+    };
+    GILA_TRY(counting_sort(kLenKeys, tj1, nt1, lenkey, nullptr, order1));
+    GILA_TRY(counting_sort(nseg, tj2, nt2, b.d_seg, order1, order));
+    const int64_t ntiles = nt2;  // hscan now holds the segment sort's offsets
     hipLaunchKernelGGL(slice_lengths_kernel, dim3((unsigned)((T + kBlock - 1) / kBlock)),
                        dim3(kBlock), 0, st, T, order, b.d_kn, b.d_an, wk, wa);
     GILA_HIP(hipGetLastError());
