@@ -92,7 +92,9 @@ typedef struct gila_khop gila_khop;
 
 /* Build N_v(k) for every vertex of g_dev (device CSR) with k >= 1.
  * The graph is validated (EINVAL on any CSR rule above, or k < 1), copied into
- * the handle, relabelled internally by decreasing degree, and its k-hop lists
+ * the handle and relabelled internally (non-isolated vertices first; by
+ * decreasing |N_v(k)|, or in the caller's order when most edges are short in
+ * it -- results are returned in caller ids either way), and its k-hop lists
  * are built by CSR frontier expansion on the device.  The handle owns all of
  * its device memory (lists, internal graph copy, iteration workspace) until
  * gila_khop_free.  Synchronises `stream`. */
@@ -166,8 +168,9 @@ int gila_run(const gila_khop* kh, const gila_params* params, int32_t start_h, in
 /* Measurement: `reps` iterations h, h+1, ... (eager launches, no HIP graph)
  * on pos_dev with HIP events recorded on `stream` around every kernel.
  * ms_out[0] receives the average duration of the force kernel (the segment
- * kernel, or the direct-gather kernel on that path), ms_out[1] that of the
- * combine kernel (0 on the direct path).  pos_dev is advanced by the
+ * kernel, or the direct-gather kernel with the statistics kernel on that
+ * path), ms_out[1] that of the rest of the iteration on the segment path (the
+ * combine and statistics kernels; 0 on the direct path).  pos_dev is advanced by the
  * iterations.  Synchronises `stream`. */
 int gila_time_iterations(const gila_khop* kh, const gila_params* params, int32_t h,
                          int32_t reps, void* pos_dev, void* stream, double* ms_out);
@@ -202,6 +205,12 @@ int gila_batch_info(const gila_batch* b, int32_t* count, int64_t* total_pairs,
  * the time from the start of the first graph's work to the moment graph i's
  * positions were written back (device wall clock). */
 int gila_batch_latency(const gila_batch* b, double* ms_host);
+
+/* The k-hop lists N_v(k) of graph `graph` of a built batch, in that graph's own
+ * vertex ids: ptr_host[n + 1] (ptr_host[0] = 0) and idx_host[ptr_host[n]],
+ * each row ascending.  idx_host may be NULL to size the rows first.  EINVAL
+ * for a NULL batch or ptr_host or a graph index out of range.  Synchronous. */
+int gila_batch_export(const gila_batch* b, int32_t graph, int64_t* ptr_host, int32_t* idx_host);
 void gila_batch_free(gila_batch* b);
 
 /* gila_batch_build + gila_batch_run + gila_batch_free. */

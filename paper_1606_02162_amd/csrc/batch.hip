@@ -16,6 +16,7 @@
 // the process), so its result is the same bits alone or in any batch.  The
 // launch is captured as a HIP graph and replayed on later runs.
 #include <algorithm>
+#include <cstring>
 #include <cmath>
 #include <cstdlib>
 #include <map>
@@ -146,6 +147,149 @@ __global__ void gather_bounds_kernel(const int64_t* __restrict__ kptr,
         out[i] = kptr[vb[i]];
 }
 
+// ------------------------------------------------------------------ k-hop lists of small graphs
+// One workgroup per graph (largest first): the graph's CSR is copied into LDS
+// with local ids, then each wavefront takes one source at a time and runs a
+// level-synchronous BFS to depth k on three bitmaps of its own in LDS
+// (visited, this level, next level), deduplicating with LDS atomic ORs.  The
+// count pass writes |N_v(k)|; the fill pass writes the row ascending by
+// scanning the visited bitmap.  Used when every graph of the batch fits.
+constexpr int kBfsBlock = 512;
+constexpr int kBfsWaves = kBfsBlock / 64;
+
+struct BatchBfsArgs {
+    int32_t count;
+    const int32_t* gorder;   // graphs, largest first
+    const int64_t* vbase;    // [count + 1]
+    const int64_t* rp;       // union CSR (global ids)
+    const int32_t* ci;
+    const int32_t* gk;       // k of each graph
+    int64_t* counts;         // count pass: [nv]
+    const int64_t* kptr;     // fill pass: [nv + 1]
+    uint16_t* kidx;          // fill pass: local ids
+    int32_t* work;           // next graph (atomic)
+    int32_t nmax;            // largest graph: vertices ...
+    int64_t nnzmax;          // ... and adjacency entries
+};
+
+size_t batch_bfs_lds_bytes(int32_t nmax, int64_t nnzmax) {
+    const size_t nwords = (size_t)(nmax + 31) / 32;
+    return 4 * ((size_t)nmax + 1) + 2 * (((size_t)nnzmax + 1) & ~(size_t)1) +
+           4 * nwords * 3 * kBfsWaves;
+}
+
+template <bool FILL>
+__global__ __launch_bounds__(kBfsBlock) void batch_khop_kernel(BatchBfsArgs a) {
+    extern __shared__ __align__(16) unsigned char s_raw[];
+    __shared__ int s_g;
+    const int nwords_max = (a.nmax + 31) / 32;
+    int32_t* s_rp = reinterpret_cast<int32_t*>(s_raw);
+    uint16_t* s_ci = reinterpret_cast<uint16_t*>(s_rp + a.nmax + 1);
+    uint32_t* s_bm = reinterpret_cast<uint32_t*>(s_ci + ((a.nnzmax + 1) & ~(int64_t)1));
+    const int lane = lane64(), w = wave_id();
+    uint32_t* vis = s_bm + (size_t)w * 3 * nwords_max;
+    for (;;) {
+        if (threadIdx.x == 0) s_g = atomicAdd(a.work, 1);
+        __syncthreads();
+        const int gi = s_g;
+        __syncthreads();
+        if (gi >= a.count) return;
+        const int g = a.gorder[gi];
+        const int64_t vb = a.vbase[g];
+        const int n = (int)(a.vbase[g + 1] - vb);
+        const int k = a.gk[g];
+        const int64_t eb = a.rp[vb];
+        const int64_t ne = a.rp[vb + n] - eb;
+        for (int i = threadIdx.x; i <= n; i += kBfsBlock) s_rp[i] = (int32_t)(a.rp[vb + i] - eb);
+        for (int64_t j = threadIdx.x; j < ne; j += kBfsBlock) s_ci[j] = (uint16_t)(a.ci[eb + j] - vb);
+        __syncthreads();
+        const int nw = (n + 31) >> 5;
+        for (int src = w; src < n; src += kBfsWaves) {
+            uint32_t* cur = vis + nwords_max;
+            uint32_t* nxt = cur + nwords_max;
+            for (int i = lane; i < nw; i += 64) {
+                vis[i] = 0u;
+                cur[i] = 0u;
+            }
+            __builtin_amdgcn_wave_barrier();
+            if (lane == 0) {
+                vis[src >> 5] = 1u << (src & 31);
+                cur[src >> 5] = 1u << (src & 31);
+            }
+            __builtin_amdgcn_wave_barrier();
+            int found = 0;
+            for (int level = 0; level < k; ++level) {
+                for (int i = lane; i < nw; i += 64) nxt[i] = 0u;
+                __builtin_amdgcn_wave_barrier();
+                int added = 0;
+                for (int i = lane; i < nw; i += 64) {
+                    uint32_t bits = cur[i];
+                    while (bits) {
+                        const int u = i * 32 + __builtin_ctz(bits);
+                        bits &= bits - 1u;
+                        const int e1 = s_rp[u + 1];
+                        for (int e = s_rp[u]; e < e1; ++e) {
+                            const int x = s_ci[e];
+                            const uint32_t m = 1u << (x & 31);
+                            if (!(atomicOr(&vis[x >> 5], m) & m)) {
+                                atomicOr(&nxt[x >> 5], m);
+                                ++added;
+                            }
+                        }
+                    }
+                }
+                __builtin_amdgcn_wave_barrier();
+                found += added;
+                uint32_t* t = cur;
+                cur = nxt;
+                nxt = t;
+                if (__ballot(added > 0) == 0ull) break;
+            }
+            if constexpr (!FILL) {
+                const int total = wave_sum(found);
+                if (lane == 0) a.counts[vb + src] = total;
+            } else {
+                // the row: visited ids except src, ascending
+                int64_t out = a.kptr[vb + src];
+                for (int i0 = 0; i0 < nw; i0 += 64) {
+                    const int i = i0 + lane;
+                    uint32_t bits = i < nw ? vis[i] : 0u;
+                    if (i == (src >> 5)) bits &= ~(1u << (src & 31));
+                    const int c = __popc(bits);
+                    const int incl = wave_inclusive_scan(c);
+                    int64_t at = out + incl - c;
+                    while (bits) {
+                        a.kidx[at++] = (uint16_t)(i * 32 + __builtin_ctz(bits));
+                        bits &= bits - 1u;
+                    }
+                    out += __shfl(incl, 63, 64);
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        __syncthreads();
+    }
+}
+
+static int run_batch_bfs(bool fill, const BatchBfsArgs& a, size_t lds, int device, hipStream_t s) {
+    if (lds > 48 * 1024) {
+        (void)hipFuncSetAttribute((const void*)batch_khop_kernel<false>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        (void)hipFuncSetAttribute((const void*)batch_khop_kernel<true>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    }
+    const DeviceInfo& di = device_info(device);
+    const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(4, (160u * 1024u) / (lds + 1024)));
+    const int grid = std::min(a.count, di.cus * per_cu);
+    GILA_HIP(hipMemsetAsync(a.work, 0, sizeof(int32_t), s));
+    if (fill)
+        hipLaunchKernelGGL(batch_khop_kernel<true>, dim3(grid), dim3(kBfsBlock), lds, s, a);
+    else
+        hipLaunchKernelGGL(batch_khop_kernel<false>, dim3(grid), dim3(kBfsBlock), lds, s, a);
+    GILA_HIP(hipGetLastError());
+    return GILA_OK;
+}
+
 // ------------------------------------------------------------------ the persistent kernel
 template <class P, int LPV>
 __device__ __forceinline__ void batch_graph_iteration(
@@ -154,8 +298,10 @@ __device__ __forceinline__ void batch_graph_iteration(
     int& coinc) {
     using R = typename P::real;
     using V = typename P::vec2;
-    const R d2 = (R)(G.d * G.d);
-    const R dpar = attract_param<R>(G.d);
+    const double d2 = G.d * G.d;
+    // repulsion is summed without its factor d^2 (applied once per row), so
+    // attraction (x_u - x_v) delta / d enters the same sum divided by d^2
+    const R dpar = sizeof(R) == 4 ? (R)(1.0 / (G.d * d2)) : (R)(G.d * d2);
     constexpr int ngroups = kBatchBlock / LPV;
     const int grp = threadIdx.x / LPV;
     const int gl = threadIdx.x % LPV;
@@ -173,26 +319,23 @@ __device__ __forceinline__ void batch_graph_iteration(
             R mindd = R(1);
             int e = gl;
             for (; e + 3 * LPV < len; e += 4 * LPV) {
-                const V p0 = cur[row[e]], p1 = cur[row[e + LPV]], p2 = cur[row[e + 2 * LPV]],
-                        p3 = cur[row[e + 3 * LPV]];
-                R x0, y0, x1, y1, x2, y2, x3, y3;
-                repulse_term<P>(xv.x, xv.y, p0, d2, x0, y0, mindd);
-                repulse_term<P>(xv.x, xv.y, p1, d2, x1, y1, mindd);
-                repulse_term<P>(xv.x, xv.y, p2, d2, x2, y2, mindd);
-                repulse_term<P>(xv.x, xv.y, p3, d2, x3, y3, mindd);
-                acc.add((x0 + x1) + (x2 + x3), (y0 + y1) + (y2 + y3));
+                R sx, sy;
+                repulse4<P>(cur[row[e]], cur[row[e + LPV]], cur[row[e + 2 * LPV]],
+                            cur[row[e + 3 * LPV]], xv.x, xv.y, sx, sy, mindd);
+                acc.add(sx, sy);
             }
             for (; e < len; e += LPV) {
                 R tx, ty;
-                repulse_term<P>(xv.x, xv.y, cur[row[e]], d2, tx, ty, mindd);
+                repulse1<P>(cur[row[e]], xv.x, xv.y, tx, ty, mindd);
                 acc.add(tx, ty);
             }
-            if (mindd == R(0)) coinc += count_coincident<V, uint16_t, LPV>(xv, row, len, gl, cur);
+            if (mindd <= coincidence_bias<R>())
+                coinc += count_coincident<V, uint16_t, LPV>(xv, row, len, gl, cur);
             const int64_t ab = a.rp[G.vbase + v], ae = a.rp[G.vbase + v + 1];
             for (int64_t j = ab + gl; j < ae; j += LPV) attract<P>(xv.x, xv.y, cur[a.ci[j]], dpar, acc);
         }
-        const double fx = group_sum<LPV>(acc.x());
-        const double fy = group_sum<LPV>(acc.y());
+        const double fx = group_sum<LPV>(acc.x()) * d2;
+        const double fy = group_sum<LPV>(acc.y()) * d2;
         if (v < G.n && gl == 0) {
             // temperature cap and synchronous move (into the other buffer)
             const double norm = sqrt(fx * fx + fy * fy);
@@ -591,6 +734,7 @@ int batch_build(const gila_csr* graphs, int32_t count, const int32_t* k, hipStre
         return GILA_OK;
     }
 
+    PhaseTimer pt("batch_build", s);
     DevTmp<GraphSrc> d_src;
     DevTmp<int32_t> d_flag, d_ci32, d_k, d_nact;
     DevTmp<int64_t> d_vb, d_counts, d_bounds;
@@ -626,6 +770,7 @@ int batch_build(const gila_csr* graphs, int32_t count, const int32_t* k, hipStre
                     (flag & 2) ? " self-loop" : "", (flag & 4) ? " row not strictly ascending" : "",
                     (flag & 8) ? " not symmetric" : "");
 
+    pt.mark("gather+validate");
     // k-hop counts, offsets and 16-bit local rows
     const int32_t nwords = std::max<int32_t>(1, (b->nmax + 31) / 32);
     GILA_TRY(dalloc_t(&d_counts.p, (size_t)std::max<int64_t>(b->nv, 1)));
@@ -644,15 +789,53 @@ int batch_build(const gila_csr* graphs, int32_t count, const int32_t* k, hipStre
     a.gk = d_k.p;
     a.ngraphs = count;
     a.qcap = std::max<int32_t>(1, b->nmax);
-    if (b->nv > 0) GILA_TRY(run_bfs(false, dev, s, a));
+    // graphs whose CSR and three bitmaps per wavefront fit in LDS: one
+    // workgroup per graph; otherwise one workgroup per source
+    int64_t nnzmax = 0;
+    for (int32_t i = 0; i < count; ++i) nnzmax = std::max(nnzmax, b->ebase[i + 1] - b->ebase[i]);
+    const size_t bfs_lds = batch_bfs_lds_bytes(b->nmax, nnzmax);
+    const bool per_graph = bfs_lds + 1024 <= device_info(dev).max_lds_per_block &&
+                           !(getenv("GILA_BATCH_BFS") && std::strcmp(getenv("GILA_BATCH_BFS"), "source") == 0);
+    BatchBfsArgs ga{};
+    DevTmp<int32_t> d_gorder;
+    if (per_graph) {
+        std::vector<int32_t> gorder((size_t)count);
+        std::iota(gorder.begin(), gorder.end(), 0);
+        std::stable_sort(gorder.begin(), gorder.end(),
+                         [&](int32_t x, int32_t y) { return b->n[x] > b->n[y]; });
+        GILA_TRY(dalloc_t(&d_gorder.p, (size_t)count));
+        GILA_HIP(hipMemcpyAsync(d_gorder.p, gorder.data(), sizeof(int32_t) * count,
+                                hipMemcpyHostToDevice, s));
+        ga.count = count;
+        ga.gorder = d_gorder.p;
+        ga.vbase = d_vb.p;
+        ga.rp = b->rp;
+        ga.ci = d_ci32.p;
+        ga.gk = d_k.p;
+        ga.counts = d_counts.p;
+        ga.work = d_flag.p + 1;
+        ga.nmax = b->nmax;
+        ga.nnzmax = nnzmax;
+        GILA_TRY(run_batch_bfs(false, ga, bfs_lds, dev, s));
+    } else if (b->nv > 0) {
+        GILA_TRY(run_bfs(false, dev, s, a));
+    }
+    pt.mark("count");
     GILA_TRY(exclusive_scan_i64(d_counts.p, b->kptr, b->nv, s));
     GILA_HIP(hipMemcpy(&b->P, b->kptr + b->nv, sizeof(int64_t), hipMemcpyDeviceToHost));
     GILA_TRY(dalloc_t(&b->kidx, (size_t)b->P + 64));
     if (b->nv > 0 && b->P > 0) {
-        a.kptr = b->kptr;
-        a.kidx16 = b->kidx;
-        GILA_TRY(run_bfs(true, dev, s, a));
+        if (per_graph) {
+            ga.kptr = b->kptr;
+            ga.kidx = b->kidx;
+            GILA_TRY(run_batch_bfs(true, ga, bfs_lds, dev, s));
+        } else {
+            a.kptr = b->kptr;
+            a.kidx16 = b->kidx;
+            GILA_TRY(run_bfs(true, dev, s, a));
+        }
     }
+    pt.mark("fill");
     if (count > 0) {
         hipLaunchKernelGGL(localize_kernel, dim3(count), dim3(kBlock), 0, s, d_src.p, d_ci32.p,
                            b->rp, b->ci16, d_nact.p);
@@ -671,6 +854,7 @@ int batch_build(const gila_csr* graphs, int32_t count, const int32_t* k, hipStre
         GILA_HIP(hipMemcpyAsync(b->n_active.data(), d_nact.p, sizeof(int32_t) * count,
                                 hipMemcpyDeviceToHost, s));
     GILA_HIP(hipStreamSynchronize(s));
+    pt.mark("localize+bounds");
     b->Pg.assign(count, 0);
     b->cls.assign(count, 0);
     std::vector<int64_t> work(count);
@@ -691,6 +875,7 @@ int batch_build(const gila_csr* graphs, int32_t count, const int32_t* k, hipStre
         GILA_HIP(hipMemcpyAsync(b->d_order, b->order.data(), sizeof(int32_t) * count,
                                 hipMemcpyHostToDevice, s));
     GILA_HIP(hipStreamSynchronize(s));
+    pt.mark("order");
     b->device_bytes = 8 * (2 * (b->nv + 1)) + 2 * (b->P + b->nnz) +
                       (int64_t)(sizeof(BatchDesc) + 4 + sizeof(gila_stats)) * count;
     *out = b;
@@ -840,6 +1025,24 @@ int gila_batch_info(const gila_batch* b, int32_t* count, int64_t* total_pairs,
     if (count) *count = b->count;
     if (total_pairs) *total_pairs = b->P;
     if (device_bytes) *device_bytes = b->device_bytes;
+    return GILA_OK;
+}
+
+int gila_batch_export(const gila_batch* b, int32_t graph, int64_t* ptr_host, int32_t* idx_host) {
+    clear_error();
+    if (!b || !ptr_host) return fail(GILA_EINVAL, "batch or ptr_host is NULL");
+    if (graph < 0 || graph >= b->count) return fail(GILA_EINVAL, "graph %d out of range", graph);
+    DeviceGuard dg(b->device);
+    const int32_t n = b->n[graph];
+    std::vector<int64_t> kp((size_t)n + 1);
+    GILA_HIP(hipMemcpy(kp.data(), b->kptr + b->vbase[graph], sizeof(int64_t) * (n + 1),
+                       hipMemcpyDeviceToHost));
+    for (int32_t v = 0; v <= n; ++v) ptr_host[v] = kp[v] - kp[0];
+    if (!idx_host || ptr_host[n] == 0) return GILA_OK;
+    std::vector<uint16_t> rows((size_t)ptr_host[n]);
+    GILA_HIP(hipMemcpy(rows.data(), b->kidx + kp[0], sizeof(uint16_t) * rows.size(),
+                       hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < rows.size(); ++i) idx_host[i] = rows[i];
     return GILA_OK;
 }
 

@@ -87,6 +87,70 @@ __device__ __forceinline__ void repulse_term(typename P::real xv, typename P::re
     ty = dy * s;
 }
 
+// Squared distance plus a tiny bias: a coincident pair gets delta^2 = bias
+// instead of 0, so its reciprocal is finite and its term (dx = dy = 0) is
+// exactly 0.  For any two distinct positions of magnitude below ~1e12 the
+// bias is far below the rounding of delta^2 and changes nothing.
+template <class R>
+__device__ __forceinline__ R coincidence_bias() {
+    return sizeof(R) == 4 ? (R)1e-30f : (R)1e-300;
+}
+
+// Repulsion (x_v - x_u) / delta^2 from four neighbours at p0..p3, summed into
+// (sx, sy); the factor d^2 of the force (magnitude d^2 / delta, q = 1) is
+// applied by the caller once per row.  A sentinel far away (delta^2 = +inf)
+// contributes exactly 0.  `mindd` tracks the smallest biased delta^2, so rows
+// holding a coincident pair can be recounted exactly (rare).
+template <class P>
+__device__ __forceinline__ void repulse4(typename P::vec2 p0, typename P::vec2 p1,
+                                         typename P::vec2 p2, typename P::vec2 p3,
+                                         typename P::real xv, typename P::real yv,
+                                         typename P::real& sx, typename P::real& sy,
+                                         typename P::real& mindd) {
+    using R = typename P::real;
+    const R bias = coincidence_bias<R>();
+    const R dx0 = xv - p0.x, dy0 = yv - p0.y;
+    const R dx1 = xv - p1.x, dy1 = yv - p1.y;
+    const R dx2 = xv - p2.x, dy2 = yv - p2.y;
+    const R dx3 = xv - p3.x, dy3 = yv - p3.y;
+    const R dd0 = fma(dx0, dx0, fma(dy0, dy0, bias));
+    const R dd1 = fma(dx1, dx1, fma(dy1, dy1, bias));
+    const R dd2 = fma(dx2, dx2, fma(dy2, dy2, bias));
+    const R dd3 = fma(dx3, dx3, fma(dy3, dy3, bias));
+    mindd = fmin(fmin(mindd, dd0), dd1);
+    mindd = fmin(fmin(mindd, dd2), dd3);
+    R r0, r1, r2, r3;
+    if constexpr (sizeof(R) == 4) {
+        r0 = fast_rcp(dd0);
+        r1 = fast_rcp(dd1);
+        r2 = fast_rcp(dd2);
+        r3 = fast_rcp(dd3);
+    } else {
+        r0 = R(1) / dd0;
+        r1 = R(1) / dd1;
+        r2 = R(1) / dd2;
+        r3 = R(1) / dd3;
+    }
+    sx = fma(dx0, r0, dx1 * r1) + fma(dx2, r2, dx3 * r3);
+    sy = fma(dy0, r0, dy1 * r1) + fma(dy2, r2, dy3 * r3);
+}
+
+// One neighbour (the remainder of a row walk), same conventions as repulse4.
+template <class P>
+__device__ __forceinline__ void repulse1(typename P::vec2 p, typename P::real xv,
+                                         typename P::real yv, typename P::real& sx,
+                                         typename P::real& sy, typename P::real& mindd) {
+    using R = typename P::real;
+    const R dx = xv - p.x, dy = yv - p.y;
+    const R dd = fma(dx, dx, fma(dy, dy, coincidence_bias<R>()));
+    mindd = fmin(mindd, dd);
+    R r;
+    if constexpr (sizeof(R) == 4) r = fast_rcp(dd);
+    else r = R(1) / dd;
+    sx = dx * r;
+    sy = dy * r;
+}
+
 // Number of pairs of a strided row walk whose points coincide.
 template <class V, class IDX, int STRIDE>
 __device__ __forceinline__ int count_coincident(V xv, const IDX* __restrict__ row, int len,

@@ -337,54 +337,18 @@ __device__ __forceinline__ int count_coincident_quads(V xv, const uint2* __restr
     return c;
 }
 
-// Squared distance plus a tiny bias: a coincident pair gets delta^2 = bias
-// instead of 0, so its reciprocal is finite and its term (dx = dy = 0) is
-// exactly 0.  For any two distinct positions of magnitude below ~1e12 the
-// bias is far below the rounding of delta^2 and changes nothing.
-template <class R>
-__device__ __forceinline__ R coincidence_bias() {
-    return sizeof(R) == 4 ? (R)1e-30f : (R)1e-300;
-}
-
-// Repulsion (x_v - x_u) / delta^2 from the four neighbours whose LDS byte
-// offsets are packed in w, summed; the factor d^2 is applied once per slice.
-// A sentinel slot lies so far away that delta^2 = +inf and its term is 0.
+// Repulsion from the four neighbours whose LDS byte offsets are packed in w.
 template <class P>
 __device__ __forceinline__ void quad_terms(uint2 w, const unsigned char* __restrict__ lds,
                                            typename P::real xv, typename P::real yv,
                                            typename P::real& sx, typename P::real& sy,
                                            typename P::real& mindd) {
-    using R = typename P::real;
     using V = typename P::vec2;
-    const R bias = coincidence_bias<R>();
     const V p0 = *reinterpret_cast<const V*>(lds + (w.x & 0xFFFFu));
     const V p1 = *reinterpret_cast<const V*>(lds + (w.x >> 16));
     const V p2 = *reinterpret_cast<const V*>(lds + (w.y & 0xFFFFu));
     const V p3 = *reinterpret_cast<const V*>(lds + (w.y >> 16));
-    const R dx0 = xv - p0.x, dy0 = yv - p0.y;
-    const R dx1 = xv - p1.x, dy1 = yv - p1.y;
-    const R dx2 = xv - p2.x, dy2 = yv - p2.y;
-    const R dx3 = xv - p3.x, dy3 = yv - p3.y;
-    const R dd0 = fma(dx0, dx0, fma(dy0, dy0, bias));
-    const R dd1 = fma(dx1, dx1, fma(dy1, dy1, bias));
-    const R dd2 = fma(dx2, dx2, fma(dy2, dy2, bias));
-    const R dd3 = fma(dx3, dx3, fma(dy3, dy3, bias));
-    mindd = fmin(fmin(mindd, dd0), dd1);
-    mindd = fmin(fmin(mindd, dd2), dd3);
-    R r0, r1, r2, r3;
-    if constexpr (sizeof(R) == 4) {
-        r0 = fast_rcp(dd0);
-        r1 = fast_rcp(dd1);
-        r2 = fast_rcp(dd2);
-        r3 = fast_rcp(dd3);
-    } else {
-        r0 = R(1) / dd0;
-        r1 = R(1) / dd1;
-        r2 = R(1) / dd2;
-        r3 = R(1) / dd3;
-    }
-    sx = fma(dx0, r0, dx1 * r1) + fma(dx2, r2, dx3 * r3);
-    sy = fma(dy0, r0, dy1 * r1) + fma(dy2, r2, dy3 * r3);
+    repulse4<P>(p0, p1, p2, p3, xv, yv, sx, sy, mindd);
 }
 
 template <class P, int LPV>

@@ -86,6 +86,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "gila_batch_info": (ctypes.c_int, [vp, P(i32), P(i64), P(i64)]),
         "gila_batch_free": (None, [vp]),
         "gila_batch_latency": (ctypes.c_int, [vp, vp]),
+        "gila_batch_export": (ctypes.c_int, [vp, i32, vp, vp]),
         "gila_layout_batch": (ctypes.c_int, [vp, i32, vp, vp, vp, vp, vp]),
         "gila_server_create": (ctypes.c_int, [i32, i64, i32, P(vp)]),
         "gila_server_config": (ctypes.c_int, [vp, ctypes.c_char_p, i64]),
@@ -345,6 +346,15 @@ class Batch:
         _check(_lib.gila_batch_run(self._h, _addr(structs), _addr(ptrs), _stream(stream),
                                    _addr(stats)), "gila_batch_run")
         return [stats[i] for i in range(self.count)]
+
+    def export(self, graph: int, n: int):
+        """k-hop lists of graph `graph` (n vertices) in its own ids: (ptr, idx)."""
+        ptr = np.zeros(n + 1, dtype=np.int64)
+        _check(_lib.gila_batch_export(self._h, graph, ptr.ctypes.data, None), "gila_batch_export")
+        idx = np.zeros(max(int(ptr[-1]), 1), dtype=np.int32)
+        _check(_lib.gila_batch_export(self._h, graph, ptr.ctypes.data, idx.ctypes.data),
+               "gila_batch_export")
+        return ptr, idx[: int(ptr[-1])]
 
     def latency_ms(self) -> np.ndarray:
         """Per-graph completion time (ms) of the last run, from its first start."""

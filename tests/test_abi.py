@@ -55,6 +55,9 @@ def test_argument_validation_before_device_work():
     # k < 1
     assert L.gila_build_khop(ctypes.byref(csr), 0, None, ctypes.byref(out)) == gila.GILA_EINVAL
     assert b"k must be" in L.gila_last_error()
+    # batch export without a batch
+    ptr = (ctypes.c_int64 * 4)()
+    assert L.gila_batch_export(None, 0, ptr, None) == gila.GILA_EINVAL
     # null graph / null out
     assert L.gila_build_khop(None, 2, None, ctypes.byref(out)) == gila.GILA_EINVAL
     assert L.gila_build_khop(ctypes.byref(csr), 2, None, None) == gila.GILA_EINVAL

@@ -48,6 +48,26 @@ def _t(G, x, prec):
         dtype=G.position_dtype(prec), device="cuda").contiguous()
 
 
+@pytest.mark.parametrize("bfs", ["graph", "source"])
+def test_batch_khop_lists_bit_exact(G, bfs, monkeypatch):
+    """Every graph's k-hop lists equal the oracle's BFS, on the per-graph LDS
+    path and on the per-source path (GILA_BATCH_BFS=source)."""
+    if bfs == "source":
+        monkeypatch.setenv("GILA_BATCH_BFS", "source")
+    gs = _mixed_graphs(60, 7)
+    gs.append((inputs.path_graph(2), 5))        # k beyond the diameter
+    gs.append((inputs.complete_graph(40), 2))   # dense rows
+    gs.append((inputs.Graph(n=3, row_ptr=np.zeros(4, np.int64), col_idx=np.zeros(0, np.int32)), 2))
+    dev = [G.to_device_csr(g) for g, _ in gs]
+    b = G.Batch(dev, [k for _, k in gs])
+    for i, (g, k) in enumerate(gs):
+        ptr, idx = b.export(i, g.n)
+        optr, oidx = oracle_rows(g, k)
+        assert np.array_equal(ptr, optr), (i, g.name, k)
+        assert np.array_equal(idx, oidx), (i, g.name, k)
+    b.free()
+
+
 def test_batch_fp64_forces_exact(G):
     gs = _mixed_graphs(40, 1)
     dev = [G.to_device_csr(g) for g, _ in gs]
