@@ -60,7 +60,7 @@ struct BatchArgs {
 struct gila_batch {
     int device = 0;
     int32_t count = 0;
-    int64_t nv = 0, nnz = 0, P = 0;
+    int64_t nv = 0, nnz = 0, P = 0, P_padded = 0;  // pairs; entries of the quad-padded rows
     int64_t device_bytes = 0;
     int32_t nmax = 0;
     std::vector<int64_t> vbase, ebase, Pg;
@@ -290,6 +290,28 @@ static int run_batch_bfs(bool fill, const BatchBfsArgs& a, size_t lds, int devic
     return GILA_OK;
 }
 
+// Rows of the layout kernel are padded to whole quads of ids: padded counts,
+// and the padding entries set to the graph's sentinel id n (an LDS slot that
+// holds a position far away, whose terms are exactly 0).
+__global__ void pad_counts_kernel(int64_t nv, const int64_t* __restrict__ counts,
+                                  int64_t* __restrict__ padded) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv;
+         i += (int64_t)gridDim.x * blockDim.x)
+        padded[i] = (counts[i] + 3) & ~(int64_t)3;
+}
+
+__global__ __launch_bounds__(kBlock) void pad_rows_kernel(const int64_t* __restrict__ vbase,
+                                                          const int64_t* __restrict__ kptr,
+                                                          const int64_t* __restrict__ counts,
+                                                          uint16_t* __restrict__ kidx) {
+    const int64_t vb = vbase[blockIdx.x];
+    const int n = (int)(vbase[blockIdx.x + 1] - vb);
+    for (int v = threadIdx.x; v < n; v += kBlock) {
+        const int64_t e1 = kptr[vb + v + 1];
+        for (int64_t e = kptr[vb + v] + counts[vb + v]; e < e1; ++e) kidx[e] = (uint16_t)n;
+    }
+}
+
 // ------------------------------------------------------------------ the persistent kernel
 template <class P, int LPV>
 __device__ __forceinline__ void batch_graph_iteration(
@@ -313,24 +335,37 @@ __device__ __forceinline__ void batch_graph_iteration(
         xv.y = 0;
         if (v < G.n) {
             xv = cur[v];
+            // the row as quads of 16-bit local ids (padded with the sentinel id n)
             const int64_t kb = a.kptr[G.vbase + v], ke = a.kptr[G.vbase + v + 1];
-            const uint16_t* __restrict__ row = a.kidx + kb;
-            const int len = (int)(ke - kb);
+            const uint2* __restrict__ q4 = reinterpret_cast<const uint2*>(a.kidx + kb);
+            const int nq = (int)((ke - kb) >> 2);
             R mindd = R(1);
-            int e = gl;
-            for (; e + 3 * LPV < len; e += 4 * LPV) {
-                R sx, sy;
-                repulse4<P>(cur[row[e]], cur[row[e + LPV]], cur[row[e + 2 * LPV]],
-                            cur[row[e + 3 * LPV]], xv.x, xv.y, sx, sy, mindd);
-                acc.add(sx, sy);
+            int q = gl;
+            for (; q + LPV < nq; q += 2 * LPV) {
+                const uint2 w0 = q4[q];
+                const uint2 w1 = q4[q + LPV];
+                R ax, ay, bx, by;
+                repulse4<P>(cur[w0.x & 0xFFFFu], cur[w0.x >> 16], cur[w0.y & 0xFFFFu],
+                            cur[w0.y >> 16], xv.x, xv.y, ax, ay, mindd);
+                repulse4<P>(cur[w1.x & 0xFFFFu], cur[w1.x >> 16], cur[w1.y & 0xFFFFu],
+                            cur[w1.y >> 16], xv.x, xv.y, bx, by, mindd);
+                acc.add(ax + bx, ay + by);
             }
-            for (; e < len; e += LPV) {
-                R tx, ty;
-                repulse1<P>(cur[row[e]], xv.x, xv.y, tx, ty, mindd);
-                acc.add(tx, ty);
+            for (; q < nq; q += LPV) {
+                const uint2 w0 = q4[q];
+                R ax, ay;
+                repulse4<P>(cur[w0.x & 0xFFFFu], cur[w0.x >> 16], cur[w0.y & 0xFFFFu],
+                            cur[w0.y >> 16], xv.x, xv.y, ax, ay, mindd);
+                acc.add(ax, ay);
             }
-            if (mindd <= coincidence_bias<R>())
-                coinc += count_coincident<V, uint16_t, LPV>(xv, row, len, gl, cur);
+            if (mindd <= coincidence_bias<R>()) {
+                const uint16_t* row = a.kidx + kb;
+                const int len = (int)(ke - kb);
+                for (int e = gl; e < len; e += LPV) {
+                    const V p = cur[row[e]];
+                    coinc += (row[e] != G.n && p.x == xv.x && p.y == xv.y) ? 1 : 0;
+                }
+            }
             const int64_t ab = a.rp[G.vbase + v], ae = a.rp[G.vbase + v + 1];
             for (int64_t j = ab + gl; j < ae; j += LPV) attract<P>(xv.x, xv.y, cur[a.ci[j]], dpar, acc);
         }
@@ -375,10 +410,18 @@ __global__ __launch_bounds__(kBatchBlock) void batch_layout_kernel(BatchArgs a) 
         const int gid = a.order[gi];
         const BatchDesc G = a.graphs[gid];
         if (threadIdx.x == 0 && a.t_start) a.t_start[gid] = wall_clock64();
+        // two position buffers of n + 1 slots; slot n holds the far sentinel
         V* cur = reinterpret_cast<V*>(s_raw);
-        V* nxt = cur + G.n;
+        V* nxt = cur + G.n + 1;
         const V* src = reinterpret_cast<const V*>(G.pos);
         for (int i = threadIdx.x; i < G.n; i += kBatchBlock) cur[i] = src[i];
+        if (threadIdx.x == 0) {
+            V far;
+            far.x = sizeof(far.x) == 4 ? (decltype(far.x))1e30f : (decltype(far.x))1e300;
+            far.y = far.x;
+            cur[G.n] = far;
+            nxt[G.n] = far;
+        }
         __syncthreads();
         double E = 0.0, M = 0.0;
         int64_t MV = 0, C = 0;
@@ -509,7 +552,7 @@ static bool autotune_enabled() {
 }
 
 size_t batch_lds_bytes(int32_t nmax, int precision) {
-    return (size_t)2 * (size_t)std::max(nmax, 1) * (precision == GILA_FP64 ? 16 : 8);
+    return (size_t)2 * ((size_t)std::max(nmax, 1) + 1) * (precision == GILA_FP64 ? 16 : 8);
 }
 
 static void launch_batch_kernel(int precision, int grid, size_t lds, hipStream_t s,
@@ -821,9 +864,21 @@ int batch_build(const gila_csr* graphs, int32_t count, const int32_t* k, hipStre
         GILA_TRY(run_bfs(false, dev, s, a));
     }
     pt.mark("count");
-    GILA_TRY(exclusive_scan_i64(d_counts.p, b->kptr, b->nv, s));
-    GILA_HIP(hipMemcpy(&b->P, b->kptr + b->nv, sizeof(int64_t), hipMemcpyDeviceToHost));
-    GILA_TRY(dalloc_t(&b->kidx, (size_t)b->P + 64));
+    // true row offsets (pair counts) and quad-padded offsets (layout rows)
+    DevTmp<int64_t> d_ktrue, d_padded;
+    GILA_TRY(dalloc_t(&d_ktrue.p, (size_t)b->nv + 1));
+    GILA_TRY(dalloc_t(&d_padded.p, (size_t)std::max<int64_t>(b->nv, 1)));
+    GILA_TRY(exclusive_scan_i64(d_counts.p, d_ktrue.p, b->nv, s));
+    if (b->nv > 0) {
+        const int pg = (int)std::min<int64_t>(4096, (b->nv + kBlock - 1) / kBlock);
+        hipLaunchKernelGGL(pad_counts_kernel, dim3(pg), dim3(kBlock), 0, s, b->nv, d_counts.p,
+                           d_padded.p);
+        GILA_HIP(hipGetLastError());
+    }
+    GILA_TRY(exclusive_scan_i64(d_padded.p, b->kptr, b->nv, s));
+    GILA_HIP(hipMemcpy(&b->P, d_ktrue.p + b->nv, sizeof(int64_t), hipMemcpyDeviceToHost));
+    GILA_HIP(hipMemcpy(&b->P_padded, b->kptr + b->nv, sizeof(int64_t), hipMemcpyDeviceToHost));
+    GILA_TRY(dalloc_t(&b->kidx, (size_t)b->P_padded + 64));
     if (b->nv > 0 && b->P > 0) {
         if (per_graph) {
             ga.kptr = b->kptr;
@@ -835,6 +890,11 @@ int batch_build(const gila_csr* graphs, int32_t count, const int32_t* k, hipStre
             GILA_TRY(run_bfs(true, dev, s, a));
         }
     }
+    if (b->P_padded > b->P) {
+        hipLaunchKernelGGL(pad_rows_kernel, dim3(count), dim3(kBlock), 0, s, d_vb.p, b->kptr,
+                           d_counts.p, b->kidx);
+        GILA_HIP(hipGetLastError());
+    }
     pt.mark("fill");
     if (count > 0) {
         hipLaunchKernelGGL(localize_kernel, dim3(count), dim3(kBlock), 0, s, d_src.p, d_ci32.p,
@@ -843,7 +903,7 @@ int batch_build(const gila_csr* graphs, int32_t count, const int32_t* k, hipStre
     }
     // per-graph pair counts and non-isolated counts
     GILA_TRY(dalloc_t(&d_bounds.p, (size_t)count + 1));
-    hipLaunchKernelGGL(gather_bounds_kernel, dim3((count + 256) / 256), dim3(256), 0, s, b->kptr,
+    hipLaunchKernelGGL(gather_bounds_kernel, dim3((count + 256) / 256), dim3(256), 0, s, d_ktrue.p,
                        d_vb.p, count, d_bounds.p);
     GILA_HIP(hipGetLastError());
     std::vector<int64_t> bounds((size_t)count + 1, 0);
@@ -876,7 +936,7 @@ int batch_build(const gila_csr* graphs, int32_t count, const int32_t* k, hipStre
                                 hipMemcpyHostToDevice, s));
     GILA_HIP(hipStreamSynchronize(s));
     pt.mark("order");
-    b->device_bytes = 8 * (2 * (b->nv + 1)) + 2 * (b->P + b->nnz) +
+    b->device_bytes = 8 * (2 * (b->nv + 1)) + 2 * (b->P_padded + b->nnz) +
                       (int64_t)(sizeof(BatchDesc) + 4 + sizeof(gila_stats)) * count;
     *out = b;
     h.p = nullptr;
@@ -1037,12 +1097,21 @@ int gila_batch_export(const gila_batch* b, int32_t graph, int64_t* ptr_host, int
     std::vector<int64_t> kp((size_t)n + 1);
     GILA_HIP(hipMemcpy(kp.data(), b->kptr + b->vbase[graph], sizeof(int64_t) * (n + 1),
                        hipMemcpyDeviceToHost));
-    for (int32_t v = 0; v <= n; ++v) ptr_host[v] = kp[v] - kp[0];
-    if (!idx_host || ptr_host[n] == 0) return GILA_OK;
-    std::vector<uint16_t> rows((size_t)ptr_host[n]);
-    GILA_HIP(hipMemcpy(rows.data(), b->kidx + kp[0], sizeof(uint16_t) * rows.size(),
-                       hipMemcpyDeviceToHost));
-    for (size_t i = 0; i < rows.size(); ++i) idx_host[i] = rows[i];
+    // rows are stored padded to quads with the sentinel id n: strip it
+    std::vector<uint16_t> rows((size_t)(kp[n] - kp[0]));
+    if (!rows.empty())
+        GILA_HIP(hipMemcpy(rows.data(), b->kidx + kp[0], sizeof(uint16_t) * rows.size(),
+                           hipMemcpyDeviceToHost));
+    ptr_host[0] = 0;
+    for (int32_t v = 0; v < n; ++v) {
+        int64_t e = kp[v + 1] - kp[0];
+        while (e > kp[v] - kp[0] && rows[(size_t)e - 1] == (uint16_t)n) --e;
+        const int64_t len = e - (kp[v] - kp[0]);
+        if (idx_host)
+            for (int64_t j = 0; j < len; ++j)
+                idx_host[ptr_host[v] + j] = rows[(size_t)(kp[v] - kp[0] + j)];
+        ptr_host[v + 1] = ptr_host[v] + len;
+    }
     return GILA_OK;
 }
 
