@@ -223,11 +223,14 @@ int gila_layout_batch(const gila_csr* graphs_dev, int32_t count, const int32_t* 
 /* ------------------------------------------------------------------ */
 typedef struct gila_server gila_server;
 
-/* A server owns a scheduler thread and its own streams on `device`.  Jobs are
- * admitted while their device footprint fits in hbm_budget_bytes (0 = 90% of
- * free HBM) and fewer than max_slots jobs are resident.  Resident jobs advance
- * together, a few iterations per tick; a job arriving while others run is
- * admitted at the next tick. */
+/* A server owns four threads (admission, k-hop builds, batched small jobs,
+ * ticks) and its own streams on `device`.  Jobs are admitted in arrival order
+ * while their device footprint bound fits in hbm_budget_bytes (0 = 90% of free
+ * HBM) and fewer than max_slots jobs are in flight.  Small jobs are laid out
+ * together in batched launches; larger ones are built, then advance together
+ * a few iterations per tick; builds, batched launches and ticks overlap.
+ * Device memory released by the server goes to the library's block cache
+ * (reused without device-wide synchronisation). */
 int gila_server_create(int32_t device, int64_t hbm_budget_bytes, int32_t max_slots,
                        gila_server** out);
 
@@ -253,9 +256,11 @@ int gila_wait(gila_server* s, uint64_t ticket, double* out_pos_host, gila_stats*
 int gila_cancel(gila_server* s, uint64_t ticket);
 
 /* Server settings: "tick_iterations" (iterations a resident job advances per
- * tick, default 25), "small_max_vertices" (largest job laid out by the batched
- * LDS-resident kernel; 0 = what fits in LDS), "fail_alloc_ticket" (test hook:
- * the job with this ticket fails its device allocation with ENOMEM). */
+ * tick, default 50), "small_max_vertices" (largest job laid out by the batched
+ * LDS-resident kernel, default 2048 -- one workgroup per graph, so larger jobs
+ * finish sooner on the whole-GPU path; 0 = the most that fits in LDS),
+ * "fail_alloc_ticket" (test hook: the job with this ticket fails its device
+ * allocation with ENOMEM). */
 int gila_server_config(gila_server* s, const char* key, int64_t value);
 
 /* Queue wait and total latency (submit to completion, ms) of a finished job;

@@ -690,11 +690,11 @@ static int autotune(gila_batch* b, int precision, hipStream_t s,
                 best = lpv;
             }
         }
-        dfree(scratch);
-        dfree(d_desc);
-        dfree(d_order);
-        dfree(d_t);
-        dfree(d_st);
+        dfree_on(scratch, s);
+        dfree_on(d_desc, s);
+        dfree_on(d_order, s);
+        dfree_on(d_t, s);
+        dfree_on(d_st, s);
         if (rc) break;
         tt.lpv[precision][c] = best;
         tt.tuned[precision][c] = true;
@@ -704,20 +704,20 @@ static int autotune(gila_batch* b, int precision, hipStream_t s,
     return rc;
 }
 
-void free_batch(gila_batch* b) {
+void free_batch(gila_batch* b, Release rel) {
     if (!b) return;
     DeviceGuard g(b->device);
     if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
-    dfree(b->kptr);
-    dfree(b->kidx);
-    dfree(b->rp);
-    dfree(b->ci16);
-    dfree(b->d_desc);
-    dfree(b->d_order);
-    dfree(b->d_temps);
-    dfree(b->d_stats);
-    dfree(b->d_clock);
-    dfree(b->d_work);
+    rel(b->kptr);
+    rel(b->kidx);
+    rel(b->rp);
+    rel(b->ci16);
+    rel(b->d_desc);
+    rel(b->d_order);
+    rel(b->d_temps);
+    rel(b->d_stats);
+    rel(b->d_clock);
+    rel(b->d_work);
     delete b;
 }
 
@@ -726,10 +726,13 @@ struct BatchHolder {
     ~BatchHolder() { free_batch(p); }
 };
 
+// A build temporary, released into the cache after the work on its stream.
 template <class T>
 struct DevTmp {
+    hipStream_t s;
     T* p = nullptr;
-    ~DevTmp() { dfree(p); }
+    explicit DevTmp(hipStream_t st) : s(st) {}
+    ~DevTmp() { dfree_on(p, s); }
 };
 
 int batch_build(const gila_csr* graphs, int32_t count, const int32_t* k, hipStream_t s,
@@ -778,9 +781,9 @@ int batch_build(const gila_csr* graphs, int32_t count, const int32_t* k, hipStre
     }
 
     PhaseTimer pt("batch_build", s);
-    DevTmp<GraphSrc> d_src;
-    DevTmp<int32_t> d_flag, d_ci32, d_k, d_nact;
-    DevTmp<int64_t> d_vb, d_counts, d_bounds;
+    DevTmp<GraphSrc> d_src(s);
+    DevTmp<int32_t> d_flag(s), d_ci32(s), d_k(s), d_nact(s);
+    DevTmp<int64_t> d_vb(s), d_counts(s), d_bounds(s);
     GILA_TRY(dalloc_t(&d_src.p, std::max(count, 1)));
     GILA_TRY(dalloc_t(&d_flag.p, 2));
     GILA_TRY(dalloc_t(&b->rp, (size_t)b->nv + 1));
@@ -840,7 +843,7 @@ int batch_build(const gila_csr* graphs, int32_t count, const int32_t* k, hipStre
     const bool per_graph = bfs_lds + 1024 <= device_info(dev).max_lds_per_block &&
                            !(getenv("GILA_BATCH_BFS") && std::strcmp(getenv("GILA_BATCH_BFS"), "source") == 0);
     BatchBfsArgs ga{};
-    DevTmp<int32_t> d_gorder;
+    DevTmp<int32_t> d_gorder(s);
     if (per_graph) {
         std::vector<int32_t> gorder((size_t)count);
         std::iota(gorder.begin(), gorder.end(), 0);
@@ -865,7 +868,7 @@ int batch_build(const gila_csr* graphs, int32_t count, const int32_t* k, hipStre
     }
     pt.mark("count");
     // true row offsets (pair counts) and quad-padded offsets (layout rows)
-    DevTmp<int64_t> d_ktrue, d_padded;
+    DevTmp<int64_t> d_ktrue(s), d_padded(s);
     GILA_TRY(dalloc_t(&d_ktrue.p, (size_t)b->nv + 1));
     GILA_TRY(dalloc_t(&d_padded.p, (size_t)std::max<int64_t>(b->nv, 1)));
     GILA_TRY(exclusive_scan_i64(d_counts.p, d_ktrue.p, b->nv, s));

@@ -40,7 +40,23 @@ template <class T>
 int dalloc_t(T** p, size_t count) {
     return dalloc(reinterpret_cast<void**>(p), count * sizeof(T) + (count == 0 ? 16 : 0));
 }
+// hipFree semantics (synchronises the device)
 void dfree(void* p);
+// Releases a dalloc() block into the library's cache: it is reused once the
+// work enqueued on `s` so far has completed (at once when `idle`: the caller
+// knows no work uses it).  No device-wide synchronisation.
+void dfree_on(void* p, hipStream_t s, bool idle = false);
+
+// How a handle's device memory is released: hipFree (the default, safe for
+// work on any stream), or into the cache once the work on `stream` is done.
+struct Release {
+    bool cached = false;
+    hipStream_t stream = nullptr;
+    void operator()(void* p) const {
+        if (cached) dfree_on(p, stream);
+        else dfree(p);
+    }
+};
 
 // Restores the caller's current device on scope exit.
 struct DeviceGuard {
@@ -231,7 +247,7 @@ int plan_iteration(gila_khop* kh, const std::vector<int64_t>& counts_internal,
                    const std::vector<int64_t>& rp_internal);
 // implemented in khop.hip
 int build_khop(const gila_csr* g, int32_t k, hipStream_t s, gila_khop** out);
-void free_khop(gila_khop* kh);
+void free_khop(gila_khop* kh, Release rel = Release{});
 int run_bfs(bool fill, int device, hipStream_t s, BfsArgs a);
 int launch_validate_csr(int32_t n, int64_t nnz, const int64_t* rp, const int32_t* ci, int32_t* flag,
                         hipStream_t s);
@@ -244,7 +260,7 @@ int enqueue_exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, int64
                                hipStream_t s);
 // implemented in segment.hip
 int build_segments(gila_khop* kh, int precision, hipStream_t s);
-void free_segments(gila_khop* kh);
+void free_segments(gila_khop* kh, Release rel = Release{});
 int launch_segment_step(const gila_khop* kh, int precision, const StepArgs& a, hipStream_t s,
                         hipEvent_t* ev = nullptr);
 bool segment_path_enabled();
@@ -268,6 +284,6 @@ int batch_build(const gila_csr* graphs, int32_t count, const int32_t* k, hipStre
                 gila_batch** out);
 int batch_run(gila_batch* b, const gila_params* params, void* const* pos, hipStream_t s,
               gila_stats* out, bool use_graph);
-void free_batch(gila_batch* b);
+void free_batch(gila_batch* b, Release rel = Release{});
 size_t batch_lds_bytes(int32_t nmax, int precision);
 }  // namespace gila

@@ -75,9 +75,13 @@ __global__ __launch_bounds__(kBlock) void validate_csr_kernel(int32_t n, int64_t
 // belong to many independent graphs laid out one after another (a
 // block-diagonal union): each source's bitmap covers only its own graph's id
 // range and its k is its graph's k.
+// With the bitmap in LDS, a summary bitmap (one bit per bitmap word) records
+// the words a source touched, so clearing and scanning cost O(n/1024 + |row|)
+// per source instead of O(n/32).
 template <bool FILL, bool LDS_BITMAP>
 __global__ __launch_bounds__(kBlock) void khop_bfs_kernel(BfsArgs a) {
     extern __shared__ uint32_t s_dyn[];
+    constexpr bool SUMMARY = LDS_BITMAP;
     __shared__ int32_t s_v;
     __shared__ int32_t s_qtail;
     __shared__ int64_t s_incl[kBlock];   // inclusive prefix of frontier-chunk degrees
@@ -85,10 +89,21 @@ __global__ __launch_bounds__(kBlock) void khop_bfs_kernel(BfsArgs a) {
     __shared__ int64_t s_red[4];
 
     uint32_t* bm = LDS_BITMAP ? s_dyn : a.gbitmap + (size_t)blockIdx.x * a.nwords;
+    uint32_t* sm = s_dyn + a.nwords;  // summary (LDS bitmap only)
     int32_t* queue = a.queue ? a.queue + (size_t)blockIdx.x * a.qcap : nullptr;
 
     for (int i = threadIdx.x; i < a.nwords; i += kBlock) bm[i] = 0u;
+    if constexpr (SUMMARY)
+        for (int i = threadIdx.x; i < (a.nwords + 31) / 32; i += kBlock) sm[i] = 0u;
     __syncthreads();
+    // sets bit u; true if it was clear
+    auto visit = [&](int64_t u) -> bool {
+        const uint32_t bit = 1u << (u & 31);
+        const uint32_t old = atomicOr(&bm[u >> 5], bit);
+        if constexpr (SUMMARY)
+            if (old == 0u) atomicOr(&sm[u >> 10], 1u << ((u >> 5) & 31));
+        return !(old & bit);
+    };
 
     for (;;) {
         if (threadIdx.x == 0) s_v = atomicAdd(a.work, 1);
@@ -113,18 +128,13 @@ __global__ __launch_bounds__(kBlock) void khop_bfs_kernel(BfsArgs a) {
         int64_t mycount = 0;
         if (re > rb) {
             if (threadIdx.x == 0) {
-                const int64_t lv = v - base;
-                bm[lv >> 5] |= 1u << (lv & 31);
+                visit(v - base);
                 s_qtail = 0;
             }
             __syncthreads();
             // level 1: the adjacency row (distinct, never v in a simple graph)
-            for (int64_t e = rb + threadIdx.x; e < re; e += kBlock) {
-                const int64_t u = a.ci[e] - base;
-                const uint32_t bit = 1u << (u & 31);
-                const uint32_t old = atomicOr(&bm[u >> 5], bit);
-                if (!(old & bit)) ++mycount;
-            }
+            for (int64_t e = rb + threadIdx.x; e < re; e += kBlock)
+                if (visit(a.ci[e] - base)) ++mycount;
             __syncthreads();
             // levels 2..k: expand the previous level's new vertices
             int64_t fb = rb, fe = re;
@@ -154,10 +164,7 @@ __global__ __launch_bounds__(kBlock) void khop_bfs_kernel(BfsArgs a) {
                         }
                         const int64_t off = j - (lo ? s_incl[lo - 1] : 0);
                         const int32_t ug = a.ci[s_start[lo] + off];
-                        const int64_t u = ug - base;
-                        const uint32_t bit = 1u << (u & 31);
-                        const uint32_t old = atomicOr(&bm[u >> 5], bit);
-                        if (!(old & bit)) {
+                        if (visit(ug - base)) {
                             ++mycount;
                             if (record) {
                                 const int32_t q = atomicAdd(&s_qtail, 1);
@@ -177,7 +184,18 @@ __global__ __launch_bounds__(kBlock) void khop_bfs_kernel(BfsArgs a) {
             const int64_t cnt = block_sum<int64_t>(mycount, s_red);
             if (threadIdx.x == 0) a.counts[v] = cnt;
             if (re > rb) {
-                for (int i = threadIdx.x; i < nw; i += kBlock) bm[i] = 0u;
+                if constexpr (SUMMARY) {
+                    for (int i = threadIdx.x; i < (nw + 31) / 32; i += kBlock) {
+                        uint32_t t = sm[i];
+                        while (t) {
+                            bm[i * 32 + __builtin_ctz(t)] = 0u;
+                            t &= t - 1u;
+                        }
+                        sm[i] = 0u;
+                    }
+                } else {
+                    for (int i = threadIdx.x; i < nw; i += kBlock) bm[i] = 0u;
+                }
             }
         } else {
             if (re > rb) {
@@ -188,13 +206,7 @@ __global__ __launch_bounds__(kBlock) void khop_bfs_kernel(BfsArgs a) {
                 __syncthreads();
                 int64_t pos = a.kptr[v];
                 const int64_t end = a.kptr[v + 1];
-                for (int w0 = 0; w0 < nw; w0 += kBlock) {
-                    const int wi = w0 + threadIdx.x;
-                    uint32_t word = wi < nw ? bm[wi] : 0u;
-                    int64_t total;
-                    const int64_t ex =
-                        block_exclusive_scan<int64_t>((int64_t)__popc(word), s_red, total);
-                    int64_t o = pos + ex;
+                auto emit = [&](int wi, uint32_t word, int64_t& o) {
                     while (word) {
                         const int b = __ffs(word) - 1;
                         const int64_t local = (int64_t)wi * 32 + b;
@@ -205,8 +217,39 @@ __global__ __launch_bounds__(kBlock) void khop_bfs_kernel(BfsArgs a) {
                         ++o;
                         word &= word - 1u;
                     }
-                    if (wi < nw) bm[wi] = 0u;
-                    pos += total;
+                };
+                if constexpr (SUMMARY) {
+                    // thread t owns summary word i: the 32 bitmap words of ids
+                    // [1024 i, 1024 (i + 1)), emitted in order after a scan
+                    const int ns = (nw + 31) / 32;
+                    for (int s0 = 0; s0 < ns; s0 += kBlock) {
+                        const int si = s0 + threadIdx.x;
+                        const uint32_t t0 = si < ns ? sm[si] : 0u;
+                        int64_t c = 0;
+                        for (uint32_t t = t0; t; t &= t - 1u) c += __popc(bm[si * 32 + __builtin_ctz(t)]);
+                        int64_t total;
+                        const int64_t ex = block_exclusive_scan<int64_t>(c, s_red, total);
+                        int64_t o = pos + ex;
+                        for (uint32_t t = t0; t; t &= t - 1u) {
+                            const int wi = si * 32 + __builtin_ctz(t);
+                            emit(wi, bm[wi], o);
+                            bm[wi] = 0u;
+                        }
+                        if (si < ns) sm[si] = 0u;
+                        pos += total;
+                    }
+                } else {
+                    for (int w0 = 0; w0 < nw; w0 += kBlock) {
+                        const int wi = w0 + threadIdx.x;
+                        const uint32_t word = wi < nw ? bm[wi] : 0u;
+                        int64_t total;
+                        const int64_t ex =
+                            block_exclusive_scan<int64_t>((int64_t)__popc(word), s_red, total);
+                        int64_t o = pos + ex;
+                        emit(wi, word, o);
+                        if (wi < nw) bm[wi] = 0u;
+                        pos += total;
+                    }
                 }
             }
         }
@@ -244,7 +287,8 @@ int launch_validate_csr(int32_t n, int64_t nnz, const int64_t* rp, const int32_t
 
 int run_bfs(bool fill, int device, hipStream_t s, BfsArgs a) {
     const DeviceInfo& di = device_info(device);
-    const size_t bm_bytes = (size_t)a.nwords * 4;
+    // LDS bitmap: one bit per vertex id plus the summary (one bit per word)
+    const size_t bm_bytes = ((size_t)a.nwords + ((size_t)a.nwords + 31) / 32) * 4;
     const bool lds = bm_bytes + 8 * 1024 * 2 + 1024 <= di.max_lds_per_block;
     // workgroups resident per CU limited by LDS (160 KB per CU on gfx950)
     int per_cu = 8;
@@ -271,7 +315,7 @@ int run_bfs(bool fill, int device, hipStream_t s, BfsArgs a) {
     if (!lds) {
         int rc = dalloc_t(&a.gbitmap, (size_t)grid * a.nwords);
         if (rc) {
-            dfree(a.queue);
+            dfree_on(a.queue, s);
             return rc;
         }
     }
@@ -306,28 +350,28 @@ int run_bfs(bool fill, int device, hipStream_t s, BfsArgs a) {
     hipError_t se = hipStreamSynchronize(s);
     if (rc == GILA_OK && se != hipSuccess)
         rc = fail(GILA_EDEVICE, "k-hop kernel: %s", hipGetErrorString(se));
-    dfree(a.queue);
-    dfree(a.gbitmap);
+    dfree_on(a.queue, s);
+    dfree_on(a.gbitmap, s);
     return rc;
 }
 
-void free_khop(gila_khop* kh) {
+void free_khop(gila_khop* kh, Release rel) {
     if (!kh) return;
     DeviceGuard g(kh->device);
     if (kh->gexec) (void)hipGraphExecDestroy(kh->gexec);
-    dfree(kh->perm);
-    dfree(kh->iperm);
-    dfree(kh->rp);
-    dfree(kh->ci);
-    dfree(kh->kptr);
-    dfree(kh->kidx);
-    dfree(kh->block_start);
-    dfree(kh->pos[0]);
-    dfree(kh->pos[1]);
-    dfree(kh->partials);
-    dfree(kh->ctl);
-    dfree(kh->hist);
-    free_segments(kh);
+    rel(kh->perm);
+    rel(kh->iperm);
+    rel(kh->rp);
+    rel(kh->ci);
+    rel(kh->kptr);
+    rel(kh->kidx);
+    rel(kh->block_start);
+    rel(kh->pos[0]);
+    rel(kh->pos[1]);
+    rel(kh->partials);
+    rel(kh->ctl);
+    rel(kh->hist);
+    free_segments(kh, rel);
     delete kh;
 }
 
@@ -433,11 +477,9 @@ int build_khop(const gila_csr* g, int32_t k, hipStream_t s, gila_khop** out) {
     GILA_TRY(dalloc_t(&d_flag, 4));
     struct F {
         int32_t* p;
-        int32_t* w;
-        ~F() {
-            dfree(p);
-        }
-    } fguard{d_flag, nullptr};
+        hipStream_t s;
+        ~F() { dfree_on(p, s); }
+    } fguard{d_flag, s};
     d_work = d_flag + 1;
     unsigned long long* d_near = reinterpret_cast<unsigned long long*>(d_flag + 2);
     GILA_HIP(hipMemsetAsync(d_flag, 0, 4 * sizeof(int32_t), s));
@@ -481,7 +523,7 @@ int build_khop(const gila_csr* g, int32_t k, hipStream_t s, gila_khop** out) {
                                      hipMemcpyDeviceToHost);
             if (e != hipSuccess) rc = fail(GILA_EDEVICE, "copy counts: %s", hipGetErrorString(e));
         }
-        dfree(d_counts);
+        dfree_on(d_counts, s);
         if (rc) return rc;
     }
 
@@ -544,10 +586,10 @@ int build_khop(const gila_csr* g, int32_t k, hipStream_t s, gila_khop** out) {
         a.work = d_work;
         const int rc = run_bfs(true, dev, s, a);
         if (rc) {
-            dfree(ci_sorted);
+            dfree_on(ci_sorted, s);
             return rc;
         }
-        dfree(kh->ci);
+        dfree_on(kh->ci, s);
         kh->ci = ci_sorted;
     }
 

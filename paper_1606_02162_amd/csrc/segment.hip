@@ -516,16 +516,16 @@ int seg_size_for(int precision, int device) {
     return std::max(64, S);
 }
 
-void free_segments(gila_khop* kh) {
-    dfree(kh->vsl);
-    dfree(kh->sl_v);
-    dfree(kh->sl_p);
-    dfree(kh->sl_k);
-    dfree(kh->sl_a);
-    dfree(kh->sk_idx);
-    dfree(kh->sa_idx);
-    dfree(kh->seg_wg);
-    dfree(kh->part);
+void free_segments(gila_khop* kh, Release rel) {
+    rel(kh->vsl);
+    rel(kh->sl_v);
+    rel(kh->sl_p);
+    rel(kh->sl_k);
+    rel(kh->sl_a);
+    rel(kh->sk_idx);
+    rel(kh->sa_idx);
+    rel(kh->seg_wg);
+    rel(kh->part);
     kh->vsl = nullptr;
     kh->sl_v = kh->sl_p = kh->sl_a = nullptr;
     kh->sl_k = nullptr;
@@ -539,9 +539,11 @@ void free_segments(gila_khop* kh) {
 namespace {
 // One device allocation carved into 256-byte aligned pieces.
 struct Arena {
+    hipStream_t st;  // the stream that uses it
     void* base = nullptr;
-    size_t used = 0, cap = 0;
-    ~Arena() { dfree(base); }
+    size_t used = 0;
+    explicit Arena(hipStream_t s) : st(s) {}
+    ~Arena() { dfree_on(base, st); }
     template <class T>
     T* take(size_t count) {
         T* p = reinterpret_cast<T*>(static_cast<char*>(base) + used);
@@ -572,7 +574,7 @@ int build_segments(gila_khop* kh, int precision, hipStream_t st) {
     GILA_TRY(dalloc_t(&kh->vsl, (size_t)na + 1));
     int64_t T = 0;
     {
-        Arena ar;
+        Arena ar(st);
         const size_t ws = (size_t)scan_workspace_count(na);
         GILA_TRY(dalloc(&ar.base, Arena::size<int64_t>(na) + Arena::size<int64_t>(ws)));
         SliceBuild b{};
@@ -607,7 +609,7 @@ int build_segments(gila_khop* kh, int precision, hipStream_t st) {
     tiling(nseg, tj2, nt2);
     const int64_t H = std::max(nt1 * kLenKeys, nt2 * nseg);
     const size_t ws = (size_t)std::max(scan_workspace_count(H), scan_workspace_count(T));
-    Arena ar;
+    Arena ar(st);
     GILA_TRY(dalloc(&ar.base, Arena::size<int32_t>(T) * 5 + Arena::size<int64_t>(T) +  // d_*
                                   Arena::size<int64_t>(H) + Arena::size<int64_t>(H + 1) +  // hist, its scan
                                   Arena::size<int32_t>(T) * 3 +                            // lenkey, order1, order
@@ -710,7 +712,7 @@ int build_segments(gila_khop* kh, int precision, hipStream_t st) {
     GILA_TRY(dalloc_t(&kh->sa_idx, (size_t)kh->nnz + 64));
     GILA_TRY(dalloc_t(&kh->seg_wg, plan.size()));
     if (kh->comb_grid > kh->partials_cap) {
-        dfree(kh->partials);
+        dfree_on(kh->partials, st);
         kh->partials = nullptr;
         kh->partials_cap = 0;
         GILA_TRY(dalloc_t(&kh->partials, (size_t)kh->comb_grid));

@@ -1,16 +1,18 @@
 // Layout server: continuous batching of layout jobs on one GPU.
 //
 // Jobs (host graph, k, parameters, initial positions) are queued by
-// gila_submit.  One scheduler thread owns all device work and loops in ticks:
-//   1. every resident large job gets its next `tick_iterations` iterations
-//      enqueued on the compute stream (asynchronously);
-//   2. while that runs, queued jobs are admitted in arrival order as slots and
-//      HBM budget allow: their graphs are uploaded and their k-hop lists built
-//      on a second stream.  Jobs small enough for the LDS-resident batch kernel
-//      are laid out right away, together, in one batched launch on that
-//      stream; larger ones become resident and join the next tick;
-//   3. the scheduler waits for the tick, reads each large job's control block
-//      and retires jobs that finished (all iterations, or the halting rule).
+// gila_submit.  Three threads own the device work, each on streams of its own:
+//   admitter  admits queued jobs in arrival order as slots and the HBM budget
+//             allow (footprint bound from the graph).  Jobs small enough for
+//             the LDS-resident batch kernel go to the small-job worker, larger
+//             ones to the builder.
+//   small     lays out all waiting small jobs together in one batched launch.
+//   builder   uploads a large job's graph and builds its k-hop lists on its
+//             build stream, then hands the job to the ticker.
+//   ticker    advances every resident large job by `tick_iterations`
+//             iterations per tick on the compute streams, waits for the tick,
+//             and retires jobs that finished (all iterations, or the halting
+//             rule).  Builds and batched launches overlap with the ticks.
 // A job's arithmetic depends only on its own graph and parameters (the
 // iteration plan is per graph; ticks split a run without changing its bits),
 // so each result is the same alone and in any mix of concurrent jobs.
@@ -19,6 +21,7 @@
 #include <chrono>
 #include <condition_variable>
 #include <cstdlib>
+#include <cstring>
 #include <deque>
 #include <map>
 #include <thread>
@@ -95,35 +98,45 @@ struct gila_server {
     int device = 0;
     int64_t budget = 0;
     int32_t max_slots = 1;
-    int32_t tick_iters = 25;
-    int32_t small_max_n = 0;         // 0 = what fits the batch kernel's LDS
+    int32_t tick_iters = 50;
+    int32_t small_max_n = 2048;      // 0 = the most that fits the batch kernel's LDS
     std::atomic<uint64_t> fail_alloc_ticket{0};  // test hook: this job's allocation fails
     std::mutex mu;
-    std::condition_variable cv;       // wakes the scheduler
-    std::condition_variable cv_done;  // wakes waiters
+    std::condition_variable cv;        // wakes the admitter
+    std::condition_variable cv_small;  // wakes the small-job worker
+    std::condition_variable cv_build;  // wakes the builder
+    std::condition_variable cv_tick;   // wakes the ticker
+    std::condition_variable cv_done;   // wakes waiters
     std::deque<uint64_t> pending;
     std::map<uint64_t, gila::Job*> jobs;
     std::map<uint64_t, std::pair<double, double>> times;  // queued ms, total ms
-    std::vector<gila::Job*> resident;
+    std::vector<gila::Job*> small_queue;  // admitted small jobs
+    std::deque<gila::Job*> build_queue;   // admitted large jobs, not yet built
+    std::vector<gila::Job*> ready;        // built large jobs, not yet ticked
+    std::vector<gila::Job*> resident;     // large jobs owned by the ticker
     uint64_t next_id = 1;
     int64_t reserved = 0;
     int32_t in_flight = 0;
     bool stop = false;
-    std::thread th;
+    std::thread th_admit, th_small, th_build, th_tick;
     static constexpr int kComputeStreams = 3;
     hipStream_t compute[kComputeStreams] = {nullptr, nullptr, nullptr};
     hipStream_t build = nullptr;
+    hipStream_t small = nullptr;
     int64_t jobs_done = 0, ticks = 0;
     int32_t peak_resident = 0;
 };
 
 namespace gila {
 
-static void release_device(Job* j) {
-    if (j->kh) free_khop(j->kh);
-    dfree(j->d_rp);
-    dfree(j->d_ci);
-    dfree(j->d_pos);
+// Releases a job's device memory into the library's cache once the work on
+// `st` (the last stream that used it) is done: no device-wide synchronisation.
+static void release_device(Job* j, hipStream_t st) {
+    const Release rel{true, st};
+    if (j->kh) free_khop(j->kh, rel);
+    rel(j->d_rp);
+    rel(j->d_ci);
+    rel(j->d_pos);
     j->kh = nullptr;
     j->d_rp = nullptr;
     j->d_ci = nullptr;
@@ -140,6 +153,7 @@ static void finish_job(gila_server* s, Job* j, int state, int status) {
     if (state == kDone) s->jobs_done += 1;
     s->times[j->id] = {(j->t_admit - j->t_submit) * 1e3, (j->t_done - j->t_submit) * 1e3};
     s->cv_done.notify_all();
+    s->cv.notify_one();  // slots and budget were released
 }
 
 static int upload_job(gila_server* s, Job* j, hipStream_t st) {
@@ -184,48 +198,107 @@ static int download_positions(Job* j, hipStream_t st) {
 }
 
 // Lays out a group of small jobs of one precision in one batched launch.
+// The group's graphs and positions travel in one device allocation and one
+// copy each way.
 static void run_small_group(gila_server* s, std::vector<Job*>& group) {
-    std::vector<gila_csr> csr;
-    std::vector<int32_t> ks;
-    std::vector<gila_params> ps;
-    std::vector<void*> pos;
     std::vector<Job*> ok;
     for (Job* j : group) {
-        const int rc = upload_job(s, j, s->build);
-        if (rc != GILA_OK) {
-            release_device(j);
+        if (s->fail_alloc_ticket == j->id) {
             std::lock_guard<std::mutex> lk(s->mu);
-            finish_job(s, j, kFailed, rc);
+            finish_job(s, j, kFailed, fail(GILA_ENOMEM, "injected allocation failure"));
             continue;
         }
-        gila_csr c{j->n, j->nnz, j->d_rp, j->d_ci};
-        csr.push_back(c);
-        ks.push_back(j->k);
-        ps.push_back(j->params);
-        pos.push_back(j->d_pos);
         ok.push_back(j);
     }
     if (ok.empty()) return;
+    const bool fp64 = ok[0]->params.precision == GILA_FP64;
+    const size_t pb = fp64 ? 16 : 8;
+    // offsets of each job's arrays in the staging buffers
+    std::vector<size_t> orp(ok.size()), oci(ok.size()), opos(ok.size());
+    size_t nrp = 0, nci = 0, npos = 0;
+    for (size_t i = 0; i < ok.size(); ++i) {
+        orp[i] = nrp;
+        oci[i] = nci;
+        opos[i] = npos;
+        nrp += (size_t)ok[i]->n + 1;
+        nci += (size_t)ok[i]->nnz;
+        npos += (size_t)ok[i]->n;
+    }
+    std::vector<int64_t> h_rp(nrp);
+    std::vector<int32_t> h_ci(std::max<size_t>(nci, 1));
+    std::vector<unsigned char> h_pos(std::max<size_t>(npos, 1) * pb);
+    for (size_t i = 0; i < ok.size(); ++i) {
+        const Job* j = ok[i];
+        std::copy(j->rp.begin(), j->rp.begin() + j->n + 1, h_rp.begin() + orp[i]);
+        std::copy(j->ci.begin(), j->ci.end(), h_ci.begin() + oci[i]);
+        if (fp64) {
+            std::memcpy(h_pos.data() + opos[i] * pb, j->init.data(), sizeof(double) * 2 * j->n);
+        } else {
+            float* f = reinterpret_cast<float*>(h_pos.data() + opos[i] * pb);
+            for (size_t e = 0; e < (size_t)2 * j->n; ++e) f[e] = (float)j->init[e];
+        }
+    }
+    const size_t brp = (nrp * 8 + 255) & ~(size_t)255, bci = (nci * 4 + 255) & ~(size_t)255;
+    const size_t bytes = brp + bci + std::max<size_t>(npos, 1) * pb;
+    void* arena = nullptr;
+    int rc = dalloc(&arena, bytes);
+    char* base = static_cast<char*>(arena);
+    if (rc == GILA_OK && hipMemcpyAsync(base, h_rp.data(), nrp * 8, hipMemcpyHostToDevice,
+                                        s->small) != hipSuccess)
+        rc = fail(GILA_EDEVICE, "upload");
+    if (rc == GILA_OK && nci > 0 &&
+        hipMemcpyAsync(base + brp, h_ci.data(), nci * 4, hipMemcpyHostToDevice, s->small) !=
+            hipSuccess)
+        rc = fail(GILA_EDEVICE, "upload");
+    if (rc == GILA_OK && npos > 0 &&
+        hipMemcpyAsync(base + brp + bci, h_pos.data(), npos * pb, hipMemcpyHostToDevice,
+                       s->small) != hipSuccess)
+        rc = fail(GILA_EDEVICE, "upload");
+    std::vector<gila_csr> csr(ok.size());
+    std::vector<int32_t> ks(ok.size());
+    std::vector<gila_params> ps(ok.size());
+    std::vector<void*> pos(ok.size());
+    for (size_t i = 0; i < ok.size(); ++i) {
+        const Job* j = ok[i];
+        csr[i] = gila_csr{j->n, j->nnz, reinterpret_cast<const int64_t*>(base) + orp[i],
+                          reinterpret_cast<const int32_t*>(base + brp) + oci[i]};
+        ks[i] = j->k;
+        ps[i] = j->params;
+        pos[i] = base + brp + bci + opos[i] * pb;
+    }
     std::vector<gila_stats> st(ok.size());
-    std::vector<int> rcs(ok.size(), GILA_OK);
+    std::vector<int> rcs(ok.size(), rc);
     auto run_range = [&](size_t lo, size_t hi) {
         gila_batch* b = nullptr;
         const int32_t cnt = (int32_t)(hi - lo);
-        int rc = batch_build(&csr[lo], cnt, &ks[lo], s->build, &b);
-        if (rc == GILA_OK) rc = batch_run(b, &ps[lo], &pos[lo], s->build, &st[lo], false);
-        if (b) free_batch(b);
-        for (size_t i = lo; i < hi; ++i) rcs[i] = rc;
-        return rc;
+        int r = batch_build(&csr[lo], cnt, &ks[lo], s->small, &b);
+        if (r == GILA_OK) r = batch_run(b, &ps[lo], &pos[lo], s->small, &st[lo], false);
+        if (b) free_batch(b, Release{true, s->small});
+        for (size_t i = lo; i < hi; ++i) rcs[i] = r;
+        return r;
     };
     // one launch for the group; if it is refused (say one graph is malformed)
     // each job runs on its own, so only the offending job fails
-    if (run_range(0, ok.size()) != GILA_OK && ok.size() > 1)
+    if (rc == GILA_OK && run_range(0, ok.size()) != GILA_OK && ok.size() > 1)
         for (size_t i = 0; i < ok.size(); ++i) run_range(i, i + 1);
+    if (rc == GILA_OK && npos > 0 &&
+        (hipMemcpyAsync(h_pos.data(), base + brp + bci, npos * pb, hipMemcpyDeviceToHost,
+                        s->small) != hipSuccess ||
+         hipStreamSynchronize(s->small) != hipSuccess))
+        for (auto& r : rcs) r = GILA_EDEVICE;
+    dfree_on(arena, s->small);
     for (size_t i = 0; i < ok.size(); ++i) {
         Job* j = ok[i];
-        int r = rcs[i];
-        if (r == GILA_OK) r = download_positions(j, s->build);
-        release_device(j);
+        const int r = rcs[i];
+        if (r == GILA_OK) {
+            j->result.assign((size_t)2 * j->n, 0.0);
+            if (fp64) {
+                std::memcpy(j->result.data(), h_pos.data() + opos[i] * pb, sizeof(double) * 2 * j->n);
+            } else {
+                const float* f = reinterpret_cast<const float*>(h_pos.data() + opos[i] * pb);
+                for (size_t e = 0; e < (size_t)2 * j->n; ++e) j->result[e] = f[e];
+            }
+        }
         std::lock_guard<std::mutex> lk(s->mu);
         j->stats = st[i];
         finish_job(s, j, j->cancel ? kCanceled : (r == GILA_OK ? kDone : kFailed),
@@ -243,26 +316,35 @@ static int admit_large(gila_server* s, Job* j) {
     return GILA_OK;
 }
 
-// Admits queued jobs in arrival order while slots and budget allow.  Small
-// jobs are laid out at once (batched); large ones become resident.
-static void admit(gila_server* s) {
-    std::map<int, std::vector<Job*>> small_groups;
-    std::vector<Job*> large;
-    // footprint bounds of newly queued jobs, computed outside the lock (a
-    // queued job is never deleted, so the pointers stay valid)
-    std::vector<Job*> fresh;
-    {
+// Admitter thread: admits queued jobs in arrival order while slots and budget
+// allow; small jobs go to the small-job worker, large ones are built here and
+// handed to the ticker.
+static void admitter(gila_server* s) {
+    (void)hipSetDevice(s->device);
+    for (;;) {
+        std::vector<Job*> fresh;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            s->cv.wait(lk, [&] {
+                if (s->stop) return true;
+                if (s->pending.empty()) return false;
+                const Job* j = s->jobs[s->pending.front()];
+                return j->footprint < 0 || j->cancel || j->footprint > s->budget ||
+                       (s->in_flight < s->max_slots && s->reserved + j->footprint <= s->budget);
+            });
+            if (s->stop) break;
+            for (uint64_t id : s->pending)
+                if (s->jobs[id]->footprint < 0) fresh.push_back(s->jobs[id]);
+        }
+        // footprint bounds of newly queued jobs, outside the lock (a queued
+        // job is never deleted, so the pointers stay valid)
+        for (Job* j : fresh) {
+            const int64_t f = footprint_bytes(*j);
+            std::lock_guard<std::mutex> lk(s->mu);
+            j->footprint = f;
+        }
         std::lock_guard<std::mutex> lk(s->mu);
-        for (uint64_t id : s->pending)
-            if (s->jobs[id]->footprint < 0) fresh.push_back(s->jobs[id]);
-    }
-    for (Job* j : fresh) {
-        const int64_t f = footprint_bytes(*j);
-        std::lock_guard<std::mutex> lk(s->mu);
-        j->footprint = f;
-    }
-    {
-        std::lock_guard<std::mutex> lk(s->mu);
+        bool small_added = false, large_added = false;
         while (!s->pending.empty()) {
             Job* j = s->jobs[s->pending.front()];
             if (j->cancel) {
@@ -288,26 +370,65 @@ static void admit(gila_server* s) {
             s->in_flight += 1;
             j->state = kResident;
             j->t_admit = now_s();
-            if (j->small) small_groups[j->params.precision].push_back(j);
-            else large.push_back(j);
+            if (j->small) {
+                s->small_queue.push_back(j);
+                small_added = true;
+            } else {
+                s->build_queue.push_back(j);
+                large_added = true;
+            }
         }
+        if (small_added) s->cv_small.notify_one();
+        if (large_added) s->cv_build.notify_one();
     }
-    for (Job* j : large) {
-        const int rc = admit_large(s, j);
-        std::lock_guard<std::mutex> lk(s->mu);
-        if (rc != GILA_OK) {
-            release_device(j);
-            finish_job(s, j, kFailed, rc);
-        } else {
-            j->lane = (int)(j->id % gila_server::kComputeStreams);
-            s->resident.push_back(j);
-            s->peak_resident = std::max<int32_t>(s->peak_resident, (int32_t)s->resident.size());
-        }
-    }
-    for (auto& kv : small_groups) run_small_group(s, kv.second);
 }
 
-static void scheduler(gila_server* s) {
+// Builder: graph upload and k-hop lists of admitted large jobs, one at a time
+// in admission order, then the job joins the ticker's resident set.
+static void builder(gila_server* s) {
+    (void)hipSetDevice(s->device);
+    for (;;) {
+        Job* j = nullptr;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            s->cv_build.wait(lk, [&] { return s->stop || !s->build_queue.empty(); });
+            if (s->stop) break;
+            j = s->build_queue.front();
+            s->build_queue.pop_front();
+        }
+        const int rc = j->cancel ? GILA_ECANCELED : admit_large(s, j);
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (rc != GILA_OK) {
+            release_device(j, s->build);
+            finish_job(s, j, j->cancel ? kCanceled : kFailed, rc);
+        } else {
+            j->lane = (int)(j->id % gila_server::kComputeStreams);
+            s->ready.push_back(j);
+            s->cv_tick.notify_one();
+        }
+    }
+}
+
+// Small-job worker: lays out everything admitted so far in batched launches
+// (one per precision).
+static void small_worker(gila_server* s) {
+    (void)hipSetDevice(s->device);
+    for (;;) {
+        std::vector<Job*> take;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            s->cv_small.wait(lk, [&] { return s->stop || !s->small_queue.empty(); });
+            if (s->stop) break;
+            take.swap(s->small_queue);
+        }
+        std::map<int, std::vector<Job*>> groups;
+        for (Job* j : take) groups[j->params.precision].push_back(j);
+        for (auto& kv : groups) run_small_group(s, kv.second);
+    }
+}
+
+// Ticker: advances every resident large job by one tick per loop.
+static void ticker(gila_server* s) {
     (void)hipSetDevice(s->device);
     constexpr int NC = gila_server::kComputeStreams;
     hipEvent_t tick_done[NC] = {nullptr, nullptr, nullptr};
@@ -317,12 +438,15 @@ static void scheduler(gila_server* s) {
         int32_t tick_iters = 1;
         {
             std::unique_lock<std::mutex> lk(s->mu);
-            s->cv.wait(lk, [&] { return s->stop || !s->pending.empty() || !s->resident.empty(); });
+            s->cv_tick.wait(lk, [&] { return s->stop || !s->ready.empty() || !s->resident.empty(); });
             if (s->stop) break;
+            s->resident.insert(s->resident.end(), s->ready.begin(), s->ready.end());
+            s->ready.clear();
+            s->peak_resident = std::max<int32_t>(s->peak_resident, (int32_t)s->resident.size());
             active = s->resident;
             tick_iters = s->tick_iters;
         }
-        // 1. next iterations of every resident job, asynchronously
+        // the next iterations of every resident job, asynchronously
         std::vector<int> enq_rc(active.size(), GILA_OK);
         for (size_t i = 0; i < active.size(); ++i) {
             Job* j = active[i];
@@ -332,14 +456,12 @@ static void scheduler(gila_server* s) {
                                     s->compute[j->lane]);
         }
         for (int c = 0; c < NC; ++c) (void)hipEventRecord(tick_done[c], s->compute[c]);
-        // 2. admissions overlap with the tick
-        admit(s);
-        // 3. retire finished jobs
         hipError_t we = hipSuccess;
         for (int c = 0; c < NC; ++c) {
             const hipError_t e = hipEventSynchronize(tick_done[c]);
             if (e != hipSuccess) we = e;
         }
+        // retire finished jobs
         std::vector<Job*> keep;
         for (size_t i = 0; i < active.size(); ++i) {
             Job* j = active[i];
@@ -368,16 +490,13 @@ static void scheduler(gila_server* s) {
                 keep.push_back(j);
                 continue;
             }
-            release_device(j);
+            release_device(j, s->compute[j->lane]);
             std::lock_guard<std::mutex> lk(s->mu);
             finish_job(s, j, j->cancel ? kCanceled : (rc == GILA_OK ? kDone : kFailed),
                        j->cancel ? GILA_ECANCELED : rc);
         }
         std::lock_guard<std::mutex> lk(s->mu);
-        // jobs admitted during this tick were appended after `active`
-        std::vector<Job*> added(s->resident.begin() + (ptrdiff_t)active.size(), s->resident.end());
         s->resident = keep;
-        s->resident.insert(s->resident.end(), added.begin(), added.end());
         s->ticks += 1;
     }
     for (int c = 0; c < NC; ++c) (void)hipEventDestroy(tick_done[c]);
@@ -430,17 +549,22 @@ int gila_server_create(int32_t device, int64_t hbm_budget_bytes, int32_t max_slo
         hbm_budget_bytes = (int64_t)(0.9 * (double)fr);
     }
     s->budget = hbm_budget_bytes;
-    bool ok = hipStreamCreateWithFlags(&s->build, hipStreamNonBlocking) == hipSuccess;
+    bool ok = hipStreamCreateWithFlags(&s->build, hipStreamNonBlocking) == hipSuccess &&
+              hipStreamCreateWithFlags(&s->small, hipStreamNonBlocking) == hipSuccess;
     for (int c = 0; c < gila_server::kComputeStreams && ok; ++c)
         ok = hipStreamCreateWithFlags(&s->compute[c], hipStreamNonBlocking) == hipSuccess;
     if (!ok) {
         for (int c = 0; c < gila_server::kComputeStreams; ++c)
             if (s->compute[c]) (void)hipStreamDestroy(s->compute[c]);
         if (s->build) (void)hipStreamDestroy(s->build);
+        if (s->small) (void)hipStreamDestroy(s->small);
         delete s;
         return fail(GILA_EDEVICE, "cannot create streams");
     }
-    s->th = std::thread(scheduler, s);
+    s->th_admit = std::thread(admitter, s);
+    s->th_small = std::thread(small_worker, s);
+    s->th_build = std::thread(builder, s);
+    s->th_tick = std::thread(ticker, s);
     *out = s;
     return GILA_OK;
 }
@@ -482,15 +606,14 @@ int gila_submit(gila_server* s, const gila_csr* g_host, int32_t k, const gila_pa
     j->temps.assign(params->temperature, params->temperature + params->iterations);
     j->params = *params;
     j->params.temperature = j->temps.data();
-    j->footprint = -1;  // computed by the scheduler when the job is first considered
+    j->footprint = -1;  // computed by the admitter when the job is first considered
     {
         std::lock_guard<std::mutex> lk(s->mu);
-        int32_t lim = s->small_max_n;
-        if (lim == 0) {
-            const size_t cap = device_info(s->device).max_lds_per_block - 2048;
-            const size_t per = 2 * (params->precision == GILA_FP64 ? 16 : 8);
-            lim = (int32_t)std::min<size_t>(65535, cap / per);
-        }
+        // the batch kernel holds both position buffers (n + 1 slots) in LDS
+        const size_t cap = device_info(s->device).max_lds_per_block - 2048;
+        const size_t per = 2 * (params->precision == GILA_FP64 ? 16 : 8);
+        const int32_t fits = (int32_t)std::min<size_t>(65535, cap / per - 1);
+        const int32_t lim = s->small_max_n == 0 ? fits : std::min(s->small_max_n, fits);
         j->small = j->n <= lim;
         j->id = s->next_id++;
         j->t_submit = now_s();
@@ -548,6 +671,7 @@ int gila_cancel(gila_server* s, uint64_t ticket) {
         it->second->cancel = true;
     }
     s->cv.notify_one();
+    s->cv_tick.notify_one();
     return GILA_OK;
 }
 
@@ -581,14 +705,23 @@ void gila_server_destroy(gila_server* s) {
         s->stop = true;
     }
     s->cv.notify_all();
-    if (s->th.joinable()) s->th.join();
+    s->cv_small.notify_all();
+    s->cv_build.notify_all();
+    s->cv_tick.notify_all();
+    if (s->th_admit.joinable()) s->th_admit.join();
+    if (s->th_small.joinable()) s->th_small.join();
+    if (s->th_build.joinable()) s->th_build.join();
+    if (s->th_tick.joinable()) s->th_tick.join();
     DeviceGuard dg(s->device);
     for (int c = 0; c < gila_server::kComputeStreams; ++c) (void)hipStreamSynchronize(s->compute[c]);
     (void)hipStreamSynchronize(s->build);
-    for (Job* j : s->resident) release_device(j);
+    (void)hipStreamSynchronize(s->small);
+    for (Job* j : s->resident) release_device(j, s->build);
+    for (Job* j : s->ready) release_device(j, s->build);
     for (auto& kv : s->jobs) delete kv.second;
     for (int c = 0; c < gila_server::kComputeStreams; ++c) (void)hipStreamDestroy(s->compute[c]);
     (void)hipStreamDestroy(s->build);
+    (void)hipStreamDestroy(s->small);
     delete s;
 }
 

@@ -3,6 +3,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <map>
+#include <mutex>
+#include <vector>
+#include <algorithm>
 
 #include "device_util.h"
 #include "gila_internal.h"
@@ -83,7 +86,7 @@ int exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t s
     GILA_TRY(dalloc_t(&ws, (size_t)scan_workspace_count(n)));
     const int rc = enqueue_exclusive_scan_i64(in, out, n, ws, s);
     const hipError_t e2 = hipStreamSynchronize(s);
-    dfree(ws);
+    dfree_on(ws, s);
     if (rc) return rc;
     if (e2 != hipSuccess) return fail(GILA_EDEVICE, "scan failed: %s", hipGetErrorString(e2));
     return GILA_OK;
@@ -129,20 +132,130 @@ int fail(int code, const char* fmt, ...) {
 
 void clear_error() { t_last_error.clear(); }
 
+// ------------------------------------------------------------------ device memory cache
+// hipFree synchronises the whole device.  Blocks released with dfree_on() go to
+// a cache instead and are reused by a later dalloc() of the same size class
+// once the work on the releasing stream has completed (an event marks it), so
+// code that runs beside other streams (the layout server's builder, batched
+// launches, ticks) never waits for the whole device.  dfree() keeps
+// hipFree's semantics.  Cached blocks beyond kCacheLimit are returned to the
+// device (oldest first), and all of them when an allocation fails.
+namespace {
+struct CachedBlock {
+    void* p;
+    size_t bytes;
+    hipEvent_t ev;  // null: reusable at once
+    uint64_t seq;
+};
+struct LiveBlock {
+    int device;
+    size_t bytes;
+};
+std::mutex g_mem_mu;
+std::multimap<std::pair<int, size_t>, CachedBlock> g_cache;
+std::map<void*, LiveBlock> g_live;
+size_t g_cached_bytes = 0;
+uint64_t g_seq = 0;
+constexpr size_t kCacheLimit = (size_t)16 << 30;
+
+size_t size_class(size_t b) {
+    constexpr size_t kBig = (size_t)64 << 20;
+    if (b > kBig) return (b + kBig - 1) / kBig * kBig;
+    size_t r = 512;
+    while (r < b) r <<= 1;
+    return r;
+}
+
+bool block_ready(const CachedBlock& c) { return !c.ev || hipEventQuery(c.ev) == hipSuccess; }
+
+// Returns ready cached blocks to the device until at most `keep` bytes stay
+// cached (all ready blocks for keep = 0).  Lock held.
+void trim_locked(size_t keep) {
+    std::vector<std::multimap<std::pair<int, size_t>, CachedBlock>::iterator> order;
+    for (auto it = g_cache.begin(); it != g_cache.end(); ++it) order.push_back(it);
+    std::sort(order.begin(), order.end(),
+              [](const auto& a, const auto& b) { return a->second.seq < b->second.seq; });
+    for (auto it : order) {
+        if (g_cached_bytes <= keep) break;
+        if (!block_ready(it->second)) continue;
+        DeviceGuard dg(it->first.first);
+        if (it->second.ev) (void)hipEventDestroy(it->second.ev);
+        (void)hipFree(it->second.p);
+        g_cached_bytes -= it->second.bytes;
+        g_cache.erase(it);
+    }
+}
+}  // namespace
+
 int dalloc(void** p, size_t bytes) {
     *p = nullptr;
-    hipError_t e = hipMalloc(p, bytes ? bytes : 16);
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(GILA_EDEVICE, "no current device");
+    const size_t rb = size_class(bytes ? bytes : 16);
+    {
+        std::lock_guard<std::mutex> lk(g_mem_mu);
+        auto range = g_cache.equal_range({dev, rb});
+        for (auto it = range.first; it != range.second; ++it) {
+            if (!block_ready(it->second)) continue;
+            *p = it->second.p;
+            if (it->second.ev) (void)hipEventDestroy(it->second.ev);
+            g_cached_bytes -= rb;
+            g_cache.erase(it);
+            g_live[*p] = LiveBlock{dev, rb};
+            return GILA_OK;
+        }
+    }
+    hipError_t e = hipMalloc(p, rb);
+    if (e == hipErrorOutOfMemory) {
+        (void)hipGetLastError();
+        {
+            std::lock_guard<std::mutex> lk(g_mem_mu);
+            trim_locked(0);
+        }
+        e = hipMalloc(p, rb);
+    }
     if (e != hipSuccess) {
         *p = nullptr;
         (void)hipGetLastError();
         return fail(e == hipErrorOutOfMemory ? GILA_ENOMEM : GILA_EDEVICE,
                     "hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
     }
+    std::lock_guard<std::mutex> lk(g_mem_mu);
+    g_live[*p] = LiveBlock{dev, rb};
     return GILA_OK;
 }
 
 void dfree(void* p) {
-    if (p) (void)hipFree(p);
+    if (!p) return;
+    {
+        std::lock_guard<std::mutex> lk(g_mem_mu);
+        g_live.erase(p);
+    }
+    (void)hipFree(p);
+}
+
+void dfree_on(void* p, hipStream_t s, bool idle) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(g_mem_mu);
+    auto it = g_live.find(p);
+    if (it == g_live.end()) {  // not from dalloc: plain free
+        (void)hipFree(p);
+        return;
+    }
+    CachedBlock c{p, it->second.bytes, nullptr, ++g_seq};
+    if (!idle) {
+        if (hipEventCreateWithFlags(&c.ev, hipEventDisableTiming) != hipSuccess ||
+            hipEventRecord(c.ev, s) != hipSuccess) {
+            // cannot mark the stream: wait for it instead
+            if (c.ev) (void)hipEventDestroy(c.ev);
+            c.ev = nullptr;
+            (void)hipStreamSynchronize(s);
+        }
+    }
+    g_cache.insert({{it->second.device, c.bytes}, c});
+    g_cached_bytes += c.bytes;
+    g_live.erase(it);
+    if (g_cached_bytes > kCacheLimit) trim_locked(kCacheLimit / 2);
 }
 
 DeviceGuard::DeviceGuard(int dev) {

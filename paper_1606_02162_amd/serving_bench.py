@@ -22,6 +22,10 @@ import numpy as np
 from . import gila, inputs
 
 
+# the server's default limit for small (batched) jobs
+SMALL_MAX_N = 2048
+
+
 def make_jobs(count: int, seed: int = 5):
     sizes = inputs.log_uniform_sizes(count, 100, 200000, seed)
     rng = np.random.default_rng(seed)
@@ -40,8 +44,10 @@ def params_for(g, H=200):
                              precision=gila.FP32_KAHAN)
 
 
-def run_server(jobs, arrivals, max_slots=256):
+def run_server(jobs, arrivals, max_slots=256, config=None):
     srv = gila.Server(max_slots=max_slots)
+    for key, value in (config or {}).items():
+        srv.config(key, value)
     tickets = [None] * len(jobs)
     t0 = time.perf_counter()
 
@@ -115,6 +121,14 @@ def main(args) -> int:
         free_at = start + service[i]
         finish[i] = free_at
     base_lat = (finish - arrivals) * 1e3
+    # latency by job class: small jobs go through batched LDS-resident launches
+    small = np.array([g.n <= SMALL_MAX_N for g, _, _ in jobs])
+    by_class = {}
+    for name, mask in (("small", small), ("large", ~small)):
+        if mask.any():
+            by_class[name] = {"jobs": int(mask.sum()),
+                              "p50": float(np.percentile(lat[mask], 50)),
+                              "p99": float(np.percentile(lat[mask], 99))}
     out = {
         "metric": "served layouts: k-hop force interactions/s and p50/p99 latency",
         "value": inter / wall, "unit": "interactions/s", "n_gpus": 1, "steps": 1,
@@ -123,7 +137,8 @@ def main(args) -> int:
         "config": {"workload": f"serve_ws_poisson{rate:g}_{count}jobs_k2or3_200iters",
                    "jobs": count, "rate_per_s": rate},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                       "max": float(lat.max()), "queued_p50": float(np.percentile(queued, 50))},
+                       "max": float(lat.max()), "queued_p50": float(np.percentile(queued, 50)),
+                       "by_class": by_class},
         "server": info,
         "per_graph_solver": {
             "interactions_per_s": inter / base_busy,

@@ -18,6 +18,8 @@ from paper_1606_02162_amd import inputs
 
 pytestmark = pytest.mark.gpu
 
+SMALL_MAX = 2048   # jobs up to this many vertices go through batched launches
+
 
 @pytest.fixture(scope="module")
 def G():
@@ -52,6 +54,7 @@ def test_mix_equals_alone_and_direct(G):
     jobs = _jobs(12, 1)
     with G.Server(max_slots=64) as srv:
         srv.config("tick_iterations", 7)
+        srv.config("small_max_vertices", SMALL_MAX)
         tickets = [srv.submit(g, k, _params(G, g, H), x0) for g, k, H, x0 in jobs]
         mixed = [srv.wait(t)[0] for t in tickets]
         info = srv.info()
@@ -59,6 +62,7 @@ def test_mix_equals_alone_and_direct(G):
     assert info["jobs_done"] == len(jobs)
     with G.Server(max_slots=1) as srv:
         srv.config("tick_iterations", 13)
+        srv.config("small_max_vertices", SMALL_MAX)
         for (g, k, H, x0), xm in zip(jobs, mixed):
             xa, st = srv.wait(srv.submit(g, k, _params(G, g, H), x0))
             assert np.array_equal(xa, xm), g.name
@@ -67,7 +71,7 @@ def test_mix_equals_alone_and_direct(G):
     for (g, k, H, x0), xm in zip(jobs, mixed):
         rp, ci = G.to_device_csr(g)
         pos = torch.from_numpy(x0.astype(np.float32)).cuda()
-        if g.n > 12000:
+        if g.n > SMALL_MAX:
             kh = G.build_khop(rp, ci, k)
             G.run(kh, _params(G, g, H), pos)
         else:
