@@ -50,17 +50,17 @@ KERNEL_SOURCES = ["paper_1606_02162_amd/csrc/segment.hip", "paper_1606_02162_amd
                   "paper_1606_02162_amd/csrc/gila_internal.h"]
 
 
-def algorithmic_bytes_per_iter(P: int, nnz: int, n_active: int) -> int:
-    """Compulsory HBM bytes of one FP32 iteration: 4 B per k-hop id, 4 B per
+def algorithmic_bytes_per_iter(P: int, nnz: int, n_active: int, pos_bytes: int = 8) -> int:
+    """Compulsory HBM bytes of one iteration: 4 B per k-hop id, 4 B per
     adjacency id, and per non-isolated vertex its two row offsets (8 + 8 B),
-    one position read (8 B) and one position write (8 B)."""
-    return 4 * P + 4 * nnz + 32 * n_active
+    one position read and one position write (8 B each in FP32, 16 B in FP64)."""
+    return 4 * P + 4 * nnz + (16 + 2 * pos_bytes) * n_active
 
 
-def force_kernel_bytes(P: int, nnz: int, n_active: int) -> int:
+def force_kernel_bytes(P: int, nnz: int, n_active: int, pos_bytes: int = 8) -> int:
     """The share of those bytes the force kernel moves: everything but the
     position write, which the combine kernel does."""
-    return 4 * P + 4 * nnz + 24 * n_active
+    return 4 * P + 4 * nnz + (16 + pos_bytes) * n_active
 
 
 def kernel_source_hash() -> str:
@@ -85,18 +85,50 @@ def measured_traffic():
     return t.get("bytes_per_launch")
 
 
+def single_graph_workloads(args):
+    """The single-graph workloads: graph, k, iterations, precision, frame,
+    ideal length and cap schedule of each."""
+    from paper_1606_02162_amd import gila, inputs
+    d = inputs.PAPER_IDEAL_LENGTH
+
+    def paper_caps(g, H):
+        n_active = int((np.diff(g.row_ptr) > 0).sum())
+        return gila.paper_schedule(n_active, 1.0, d, H)
+
+    return {
+        # R-MAT scale 18, edge factor 4, k = 2, FP32 + Kahan, 500 iterations
+        "rmat": dict(make=lambda: inputs.rmat(args.scale, 4, 0.57, 0.19, 0.19, seed=3), k=2,
+                     H=args.iterations, precision=gila.FP32_KAHAN, frame=inputs.PAPER_FRAME,
+                     d=d, caps=paper_caps, seed=0,
+                     name=lambda H: f"rmat{args.scale}_ef4_k2_fp32kahan_{H}iters",
+                     dtype="f32 (Kahan lane sums, f64 combine and reductions)",
+                     metric="k-hop force interactions/s (P + 2m per iteration) at ~1M edges"),
+        # Barabasi-Albert n = 100,000, m = 3, k = 3, FP32, [0, 1e4)^2, 300 iterations
+        "ba": dict(make=lambda: inputs.barabasi_albert(100_000, 3, seed=2), k=3, H=300,
+                   precision=gila.FP32, frame=1e4, d=d, caps=paper_caps, seed=0,
+                   name=lambda H: f"ba100k_m3_k3_fp32_{H}iters", dtype="f32",
+                   metric="k-hop force interactions/s (P + 2m per iteration), Barabasi-Albert 100k"),
+        # 32 x 32 grid, k = 2, FP64, [0, 1000)^2, d = 10, cap 100 cooled linearly, 100 iterations
+        "grid": dict(make=lambda: inputs.grid_graph(32, 32), k=2, H=100, precision=gila.FP64,
+                     frame=1000.0, d=10.0, caps=lambda g, H: gila.linear_schedule(100.0, H),
+                     seed=0, name=lambda H: f"grid32x32_k2_fp64_{H}iters", dtype="f64",
+                     metric="k-hop force interactions/s (P + 2m per iteration), 32x32 grid"),
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--iterations", type=int, default=500)
+    ap.add_argument("--iterations", type=int, default=500, help="iterations of the rmat workload")
     ap.add_argument("--scale", type=int, default=18)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=8)
-    ap.add_argument("--workload", choices=["rmat", "batch", "serve"], default="rmat",
-                    help="rmat: one R-MAT graph (default line); batch: 4096 graphs in one "
-                         "persistent launch; serve: Poisson stream through the layout server")
+    ap.add_argument("--workload", choices=["rmat", "ba", "grid", "batch", "serve"], default="rmat",
+                    help="rmat: one R-MAT graph (default line); ba: Barabasi-Albert 100k; "
+                         "grid: 32x32 grid in FP64; batch: 4096 graphs in one persistent "
+                         "launch; serve: Poisson stream through the layout server")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--serve-jobs", type=int, default=400)
     ap.add_argument("--serve-rate", type=float, default=200.0)
@@ -127,22 +159,29 @@ def main() -> int:
     if args.workload == "serve":
         return bench_serve(args)
 
-    from paper_1606_02162_amd import gila, inputs
+    return bench_single(args, single_graph_workloads(args)[args.workload])
+
+
+def bench_single(args, wl) -> int:
+    """One graph: a step is gila_build_khop + all iterations."""
+    import torch
+
+    from paper_1606_02162_amd import gila
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
 
-    scale, H, k = args.scale, args.iterations, 2
-    g = inputs.rmat(scale, 4, 0.57, 0.19, 0.19, seed=3)
+    g = wl["make"]()
+    H, k, prec, d = wl["H"], wl["k"], wl["precision"], wl["d"]
     n_active = int((np.diff(g.row_ptr) > 0).sum())
-    d = inputs.PAPER_IDEAL_LENGTH
-    temps = gila.paper_schedule(n_active, 1.0, d, H)
-    params = gila.LayoutParams(temperature=temps, ideal_length=d, precision=gila.FP32_KAHAN)
+    temps = wl["caps"](g, H)
+    params = gila.LayoutParams(temperature=temps, ideal_length=d, precision=prec)
     rp, ci = gila.to_device_csr(g, dev)
-    pos0 = torch.empty((g.n, 2), dtype=torch.float32, device=dev)
-    gila.init_positions(g.n, 0, inputs.PAPER_FRAME, inputs.PAPER_FRAME, gila.FP32, pos0)
+    pos0 = torch.empty((g.n, 2), dtype=gila.position_dtype(prec), device=dev)
+    gila.init_positions(g.n, wl["seed"], wl["frame"], wl["frame"], prec, pos0)
     pos = torch.empty_like(pos0)
+    pos_bytes = 16 if prec == gila.FP64 else 8
     torch.cuda.synchronize()
 
     def one_step():
@@ -195,11 +234,12 @@ def main() -> int:
 
     inter_per_iter = P + g.nnz
     value = inter_per_iter * H * args.steps / total_s
-    alg_bytes = algorithmic_bytes_per_iter(P, g.nnz, n_active)
-    kern_bytes = force_kernel_bytes(P, g.nnz, n_active)
+    alg_bytes = algorithmic_bytes_per_iter(P, g.nnz, n_active, pos_bytes)
+    kern_bytes = force_kernel_bytes(P, g.nnz, n_active, pos_bytes)
     achieved = kern_bytes / (force_ms * 1e-3) / 1e9
+    prec_name = {gila.FP64: "FP64", gila.FP32: "FP32", gila.FP32_KAHAN: "FP32_KAHAN"}[prec]
     out = {
-        "metric": "k-hop force interactions/s (P + 2m per iteration) at ~1M edges",
+        "metric": wl["metric"],
         "value": value,
         "unit": "interactions/s",
         "n_gpus": 1,
@@ -209,17 +249,17 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 (Kahan lane sums, f64 combine and reductions)",
+        "dtype": wl["dtype"],
         "data": "synthetic",
-        "config": {"workload": f"rmat{scale}_ef4_k{k}_fp32kahan_{H}iters", "n": g.n,
+        "config": {"workload": wl["name"](H), "n": g.n,
                    "m": g.m, "k": k, "iterations": H, "total_pairs": P,
                    "n_active": n_active},
         "ms_per_iter": iter_ms,
         "build_ms": build_ms,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(),
-                     "kernel": "seg_force_kernel<FP32_KAHAN>",
+                     "traffic": measured_traffic() if args.workload == "rmat" else None,
+                     "kernel": f"seg_force_kernel<{prec_name}>",
                      "kernel_ms": force_ms,
                      "algorithmic_bytes_per_launch": kern_bytes},
         "iteration": {"ms": iter_ms, "force_kernel_ms": force_ms,
