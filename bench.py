@@ -316,35 +316,35 @@ def bench_batch(args) -> int:
     sizes = inputs.log_uniform_sizes(count, 50, 5000, seed=4)
     graphs = [inputs.random_tree_plus_edges(int(n), int(n) // 2, seed=4_000_000 + i)
               for i, n in enumerate(sizes)]
-    # one upload: views into two concatenated tensors
+    # one upload: the graphs and the positions concatenated into single tensors
     rp_all = torch.from_numpy(np.concatenate([g.row_ptr for g in graphs])).to(dev)
     ci_all = torch.from_numpy(np.concatenate([g.col_idx for g in graphs])).to(dev)
+    n_arr = np.array([g.n for g in graphs], dtype=np.int64)
+    nnz_arr = np.array([g.nnz for g in graphs], dtype=np.int64)
     dev_graphs, ro, co = [], 0, 0
     for g in graphs:
         dev_graphs.append((rp_all[ro:ro + g.n + 1], ci_all[co:co + g.nnz]))
         ro += g.n + 1
         co += g.nnz
     nv = int(sizes.sum())
+    voff = np.concatenate([[0], np.cumsum(n_arr)[:-1]]).astype(np.int64)
     pos0 = torch.empty((nv, 2), dtype=torch.float32, device=dev)
-    views, vo = [], 0
+    views = []
     for i, g in enumerate(graphs):
-        v = pos0[vo:vo + g.n]
+        v = pos0[voff[i]:voff[i] + g.n]
         gila.init_positions(g.n, i, inputs.PAPER_FRAME, inputs.PAPER_FRAME, gila.FP32, v)
         views.append(v)
-        vo += g.n
     pos = torch.empty_like(pos0)
-    pviews, vo = [], 0
-    for g in graphs:
-        pviews.append(pos[vo:vo + g.n])
-        vo += g.n
+    pviews = [pos[voff[i]:voff[i] + g.n] for i, g in enumerate(graphs)]
     params = [gila.LayoutParams(temperature=gila.paper_schedule(g.n, 1.0, d, H), ideal_length=d,
                                 precision=gila.FP32) for g in graphs]
+    bparams = gila.BatchParams([p.temperature for p in params], d, gila.FP32)
     torch.cuda.synchronize()
 
     def one_step():
         pos.copy_(pos0)
-        b = gila.Batch(dev_graphs, k)
-        st = b.run(params, pviews)
+        b = gila.Batch.concatenated(rp_all, ci_all, n_arr, nnz_arr, k)
+        st = b.run(bparams, (pos, voff))
         return b, st
 
     for _ in range(args.warmup):
@@ -364,11 +364,11 @@ def bench_batch(args) -> int:
     nnz = sum(g.nnz for g in graphs)
     inter = (P + nnz) * H
     # run-only time (lists already built)
-    b = gila.Batch(dev_graphs, k)
+    b = gila.Batch.concatenated(rp_all, ci_all, n_arr, nnz_arr, k)
     pos.copy_(pos0)
     torch.cuda.synchronize()
     tr0 = time.perf_counter()
-    b.run(params, pviews)
+    b.run(bparams, (pos, voff))
     torch.cuda.synchronize()
     run_s = time.perf_counter() - tr0
     b.free()

@@ -50,6 +50,23 @@ class _Params(ctypes.Structure):
                 ("stop_fraction", ctypes.c_double), ("stop_displacement", ctypes.c_double)]
 
 
+# numpy mirrors of gila_csr and gila_params, for marshalling thousands at once
+CSR_DTYPE = np.dtype({"names": ["n", "nnz", "row_ptr", "col_idx"],
+                      "formats": [np.int32, np.int64, np.uint64, np.uint64],
+                      "offsets": [Csr.n.offset, Csr.nnz.offset, Csr.row_ptr.offset,
+                                  Csr.col_idx.offset],
+                      "itemsize": ctypes.sizeof(Csr)})
+PARAMS_DTYPE = np.dtype({"names": ["precision", "ideal_length", "iterations", "temperature",
+                                   "stop_fraction", "stop_displacement"],
+                         "formats": [np.int32, np.float64, np.int32, np.uint64, np.float64,
+                                     np.float64],
+                         "offsets": [_Params.precision.offset, _Params.ideal_length.offset,
+                                     _Params.iterations.offset, _Params.temperature.offset,
+                                     _Params.stop_fraction.offset,
+                                     _Params.stop_displacement.offset],
+                         "itemsize": ctypes.sizeof(_Params)})
+
+
 class Stats(ctypes.Structure):
     _fields_ = [("iterations_run", ctypes.c_int32), ("stopped", ctypes.c_int32),
                 ("moved", ctypes.c_int64), ("max_disp", ctypes.c_double),
@@ -316,17 +333,39 @@ class Batch:
     ``graphs`` is a list of (row_ptr, col_idx) device tensor pairs, ``k`` a
     list of ints (or one int for all)."""
 
-    def __init__(self, graphs, k, stream=None):
-        count = len(graphs)
-        ks = [int(k)] * count if isinstance(k, int) else [int(x) for x in k]
-        self._csr = (Csr * max(count, 1))()
-        for i, (rp, ci) in enumerate(graphs):
-            self._csr[i] = make_csr(rp, ci)
-        self._k = (ctypes.c_int32 * max(count, 1))(*ks)
-        self.count = count
+    def __init__(self, graphs, k, stream=None, _csr=None):
+        if _csr is None:
+            count = len(graphs)
+            csr = np.zeros(max(count, 1), dtype=CSR_DTYPE)
+            for i, (rp, ci) in enumerate(graphs):
+                c = make_csr(rp, ci)
+                csr[i] = (c.n, c.nnz, c.row_ptr or 0, c.col_idx or 0)
+        else:
+            csr, count = _csr, int(_csr.size)
+        ks = np.full(max(count, 1), int(k), dtype=np.int32) if isinstance(k, int) else \
+            np.ascontiguousarray(k, dtype=np.int32)
+        self._csr, self._k, self.count = csr, ks, count
         self._h = ctypes.c_void_p()
-        _check(_lib.gila_batch_build(_addr(self._csr), count, _addr(self._k), _stream(stream),
+        _check(_lib.gila_batch_build(csr.ctypes.data, count, ks.ctypes.data, _stream(stream),
                                      ctypes.byref(self._h)), "gila_batch_build")
+
+    @classmethod
+    def concatenated(cls, row_ptr_all, col_idx_all, n, nnz, k, stream=None):
+        """Graphs given as one concatenation: graph i has n[i] vertices and
+        nnz[i] adjacency entries; its row_ptr (n[i] + 1 entries, values from 0)
+        and col_idx (its own ids) follow the previous graph's in the two
+        device tensors."""
+        n = np.ascontiguousarray(n, dtype=np.int64)
+        nnz = np.ascontiguousarray(nnz, dtype=np.int64)
+        rp_off = np.concatenate([[0], np.cumsum(n + 1)[:-1]]).astype(np.int64)
+        ci_off = np.concatenate([[0], np.cumsum(nnz)[:-1]]).astype(np.int64)
+        csr = np.zeros(max(n.size, 1), dtype=CSR_DTYPE)
+        csr["n"][: n.size] = n
+        csr["nnz"][: n.size] = nnz
+        csr["row_ptr"][: n.size] = _ptr(row_ptr_all) + 8 * rp_off
+        csr["col_idx"][: n.size] = _ptr(col_idx_all) + 4 * ci_off
+        csr = csr[: n.size] if n.size else csr[:0]
+        return cls(None, k, stream=stream, _csr=np.ascontiguousarray(csr))
 
     def info(self) -> dict:
         c, P, b = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64()
@@ -335,16 +374,29 @@ class Batch:
         return {"count": c.value, "total_pairs": P.value, "device_bytes": b.value}
 
     def run(self, params, pos, stream=None):
-        """params: list of LayoutParams (or one for all); pos: list of device
-        tensors, updated in place.  Returns a list of Stats."""
-        plist = params if isinstance(params, (list, tuple)) else [params] * self.count
-        structs = (_Params * max(self.count, 1))()
-        for i, p in enumerate(plist):
-            structs[i] = p.as_struct()
-        ptrs = (ctypes.c_void_p * max(self.count, 1))(*[_ptr(t) for t in pos])
+        """params: list of LayoutParams (or one for all), or a BatchParams;
+        pos: list of device tensors, or (one tensor, vertex offset of each
+        graph) for graphs laid out one after another in it; updated in place.
+        Returns a list of Stats."""
+        if isinstance(params, BatchParams):
+            structs = params.structs
+        else:
+            plist = params if isinstance(params, (list, tuple)) else [params] * self.count
+            structs = (_Params * max(self.count, 1))()
+            for i, p in enumerate(plist):
+                structs[i] = p.as_struct()
+        if isinstance(pos, tuple):
+            t, voff = pos
+            ptrs = np.ascontiguousarray(_ptr(t) + 2 * t.element_size() *
+                                        np.asarray(voff, dtype=np.int64), dtype=np.uint64)
+            paddr = ptrs.ctypes.data
+        else:
+            ptrs = (ctypes.c_void_p * max(self.count, 1))(*[_ptr(t) for t in pos])
+            paddr = _addr(ptrs)
+        saddr = structs.ctypes.data if isinstance(structs, np.ndarray) else _addr(structs)
         stats = (Stats * max(self.count, 1))()
-        _check(_lib.gila_batch_run(self._h, _addr(structs), _addr(ptrs), _stream(stream),
-                                   _addr(stats)), "gila_batch_run")
+        _check(_lib.gila_batch_run(self._h, saddr, paddr, _stream(stream), _addr(stats)),
+               "gila_batch_run")
         return [stats[i] for i in range(self.count)]
 
     def export(self, graph: int, n: int):
@@ -372,6 +424,27 @@ class Batch:
             self.free()
         except Exception:
             pass
+
+
+class BatchParams:
+    """Parameters of every graph of a batch marshalled once: temperatures is a
+    list of per-graph schedules; ideal_length, precision and the halting
+    settings are shared."""
+
+    def __init__(self, temperatures, ideal_length=20.0 + math.sqrt(800.0),
+                 precision=FP32_KAHAN, stop_fraction=0.0, stop_displacement=0.01):
+        lens = np.array([len(t) for t in temperatures], dtype=np.int64)
+        self._t = np.ascontiguousarray(np.concatenate(temperatures) if len(temperatures) else
+                                       np.zeros(1), dtype=np.float64)
+        off = np.concatenate([[0], np.cumsum(lens)[:-1]]).astype(np.int64)
+        st = np.zeros(max(lens.size, 1), dtype=PARAMS_DTYPE)
+        st["precision"] = int(precision)
+        st["ideal_length"] = float(ideal_length)
+        st["iterations"][: lens.size] = lens
+        st["temperature"][: lens.size] = np.where(lens > 0, self._t.ctypes.data + 8 * off, 0)
+        st["stop_fraction"] = float(stop_fraction)
+        st["stop_displacement"] = float(stop_displacement)
+        self.structs = st
 
 
 def layout_batch(graphs, k, params, pos, stream=None):

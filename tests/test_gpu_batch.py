@@ -68,6 +68,39 @@ def test_batch_khop_lists_bit_exact(G, bfs, monkeypatch):
     b.free()
 
 
+def test_concatenated_marshalling_same_bits(G):
+    """Batch.concatenated + BatchParams + (positions, offsets) give the same
+    bits as the per-graph list form."""
+    import torch
+    gs = _mixed_graphs(30, 9)
+    ks = [k for _, k in gs]
+    H = 25
+    temps = [G.paper_schedule(max(g.n, 1), 1.0, 40.0, H) for g, _ in gs]
+    x0 = [inputs.uniform_positions(g.n, seed=i, width=800.0) for i, (g, _) in enumerate(gs)]
+    # list form
+    dev = [G.to_device_csr(g) for g, _ in gs]
+    pos_list = [_t(G, x, G.FP32) for x in x0]
+    params = [G.LayoutParams(temperature=t, ideal_length=40.0, precision=G.FP32) for t in temps]
+    b1 = G.Batch(dev, ks)
+    st1 = b1.run(params, pos_list)
+    # concatenated form
+    rp_all = torch.from_numpy(np.concatenate([g.row_ptr for g, _ in gs])).cuda()
+    ci_all = torch.from_numpy(np.concatenate([g.col_idx for g, _ in gs])).cuda()
+    n = np.array([g.n for g, _ in gs])
+    nnz = np.array([g.nnz for g, _ in gs])
+    voff = np.concatenate([[0], np.cumsum(n)[:-1]])
+    pos_all = _t(G, np.concatenate(x0), G.FP32)
+    b2 = G.Batch.concatenated(rp_all, ci_all, n, nnz, ks)
+    st2 = b2.run(G.BatchParams(temps, 40.0, G.FP32), (pos_all, voff))
+    for i in range(len(gs)):
+        assert np.array_equal(pos_list[i].cpu().numpy(),
+                              pos_all[voff[i]:voff[i] + n[i]].cpu().numpy()), i
+        assert st1[i].iterations_run == st2[i].iterations_run == H
+        assert st1[i].energy == st2[i].energy
+    b1.free()
+    b2.free()
+
+
 def test_batch_fp64_forces_exact(G):
     gs = _mixed_graphs(40, 1)
     dev = [G.to_device_csr(g) for g, _ in gs]
