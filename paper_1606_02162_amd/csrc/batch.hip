@@ -373,21 +373,40 @@ __device__ __forceinline__ void batch_graph_iteration(
         const double fy = group_sum<LPV>(acc.y()) * d2;
         if (v < G.n && gl == 0) {
             // temperature cap and synchronous move (into the other buffer)
-            const double norm = sqrt(fx * fx + fy * fy);
-            double dx = 0.0, dy = 0.0;
-            if (norm > 0.0) {
-                const double l = norm < t ? norm : t;
-                dx = fx * (l / norm);
-                dy = fy * (l / norm);
-            }
-            V nx;
-            nx.x = (R)((double)xv.x + dx);
-            nx.y = (R)((double)xv.y + dy);
-            nxt[v] = nx;
-            const double dl = sqrt(dx * dx + dy * dy);
             energy += fx * fx + fy * fy;
-            maxd = dl > maxd ? dl : maxd;
-            moved += dl > G.stop_displacement ? 1 : 0;
+            V nx;
+            if constexpr (sizeof(R) == 4) {
+                // FP32 positions: the move in FP32 (one lane per vertex does
+                // this part, so its instruction count matters); |Delta| = the
+                // capped length
+                const float fxf = (float)fx, fyf = (float)fy;
+                const float norm = sqrtf(fmaf(fxf, fxf, fyf * fyf));
+                float l = 0.f, dx = 0.f, dy = 0.f;
+                if (norm > 0.f) {
+                    l = fminf(norm, (float)t);
+                    const float sc = l * fast_rcp(norm);
+                    dx = fxf * sc;
+                    dy = fyf * sc;
+                }
+                nx.x = xv.x + dx;
+                nx.y = xv.y + dy;
+                maxd = (double)l > maxd ? (double)l : maxd;
+                moved += (double)l > G.stop_displacement ? 1 : 0;
+            } else {
+                const double norm = sqrt(fx * fx + fy * fy);
+                double dx = 0.0, dy = 0.0;
+                if (norm > 0.0) {
+                    const double l = norm < t ? norm : t;
+                    dx = fx * (l / norm);
+                    dy = fy * (l / norm);
+                }
+                nx.x = (R)((double)xv.x + dx);
+                nx.y = (R)((double)xv.y + dy);
+                const double dl = sqrt(dx * dx + dy * dy);
+                maxd = dl > maxd ? dl : maxd;
+                moved += dl > G.stop_displacement ? 1 : 0;
+            }
+            nxt[v] = nx;
         }
     }
 }
