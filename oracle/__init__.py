@@ -15,7 +15,9 @@ Force-Directed Algorithm on Giraph: Design and Experiments"):
     ||f^r|| = d^2/delta^q with p = 2, q = 1;
   * Section 4.5, the k-neighbourhood N_v(k), adjacent vertices receiving both
     forces, and the synchronous coordinate update;
-  * Section 5.1, the cap schedule sqrt((n/a) d) 0.93^h and the halting rule.
+  * Section 5.1, the cap schedule sqrt((n/a) d) 0.93^h and the halting rule;
+  * Sections 4.3 and 4.6, pruning of degree-one vertices, repulsion weighted
+    by the pruned leaves, and reinsertion of the leaves on a small circle.
 """
 from __future__ import annotations
 
@@ -64,20 +66,25 @@ def _load():
     lib.orc_khop_fill.argtypes = [ctypes.c_int32, _i64p, _i32p, ctypes.c_int32, ctypes.c_int64,
                                   vp, _i64p, _i32p]
     lib.orc_forces.argtypes = [ctypes.c_int32, _i64p, _i32p, ctypes.c_int64, vp, _i64p, _i32p,
-                               ctypes.c_double, _f64p, _f64p, ctypes.POINTER(ctypes.c_int64)]
+                               ctypes.c_double, vp, _f64p, _f64p, ctypes.POINTER(ctypes.c_int64)]
     lib.orc_cap.argtypes = [ctypes.c_int64, _f64p, ctypes.c_double, _f64p]
-    lib.orc_step.argtypes = [ctypes.c_int32, _i64p, _i32p, _i64p, _i32p, ctypes.c_double,
+    lib.orc_step.argtypes = [ctypes.c_int32, _i64p, _i32p, _i64p, _i32p, ctypes.c_double, vp,
                              ctypes.c_double, ctypes.c_double, _f64p, _f64p, _f64p,
                              ctypes.POINTER(_IterStats)]
     lib.orc_layout.argtypes = [ctypes.c_int32, _i64p, _i32p, _i64p, _i32p, ctypes.c_double,
-                               _f64p, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                               vp, _f64p, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                                ctypes.c_double, _f64p, ctypes.POINTER(ctypes.c_int32),
                                ctypes.POINTER(_IterStats)]
     lib.orc_paper_schedule.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                        ctypes.c_int32, _f64p]
     lib.orc_linear_schedule.argtypes = [ctypes.c_double, ctypes.c_int32, _f64p]
+    lib.orc_prune.argtypes = [ctypes.c_int32, _i64p, _i32p, _i32p, _i32p, _i32p,
+                              ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)]
+    lib.orc_pruned_graph.argtypes = [ctypes.c_int32, _i64p, _i32p, _i32p, _i64p, _i32p]
+    lib.orc_reinsert.argtypes = [ctypes.c_int32, _i32p, _i32p, _i32p, ctypes.c_int32, _i64p,
+                                 _i32p, ctypes.c_double, _f64p, _f64p]
     for f in ("orc_khop_count", "orc_khop_fill", "orc_forces", "orc_cap", "orc_step",
-              "orc_layout"):
+              "orc_layout", "orc_prune", "orc_pruned_graph", "orc_reinsert"):
         getattr(lib, f).restype = ctypes.c_int
     lib.orc_paper_schedule.restype = None
     lib.orc_linear_schedule.restype = None
@@ -94,6 +101,16 @@ def _check(rc: int, what: str):
 def _csr(row_ptr, col_idx):
     return (np.ascontiguousarray(row_ptr, dtype=np.int64),
             np.ascontiguousarray(col_idx, dtype=np.int32))
+
+
+def _mass(mass, n):
+    """(array, pointer) for an optional float64[n] weight vector (None = unit)."""
+    if mass is None:
+        return None, None
+    arr = np.ascontiguousarray(mass, dtype=np.float64)
+    if arr.size != n:
+        raise ValueError("mass must hold one weight per vertex")
+    return arr, arr.ctypes.data_as(ctypes.c_void_p)
 
 
 def _verts(verts):
@@ -126,15 +143,18 @@ def khop(n: int, row_ptr, col_idx, k: int, verts=None):
     return ptr, idx[: int(ptr[-1])]
 
 
-def forces(n: int, row_ptr, col_idx, kptr, kidx, d: float, pos, verts=None):
+def forces(n: int, row_ptr, col_idx, kptr, kidx, d: float, pos, verts=None, mass=None):
     """F_v for verts (Section 3.1 with N_v(k) repulsion, Section 4.5).
 
     ``kptr``/``kidx`` hold the rows of exactly the vertices in ``verts``
-    (all vertices when verts is None).  ``pos`` is float64[n, 2].
+    (all vertices when verts is None).  ``pos`` is float64[n, 2].  ``mass``
+    (float64[n], optional) scales the repulsion each vertex exerts
+    (Section 4.6: 1 + its pruned leaves).
     Returns (F float64[count, 2], coincident pair count).
     """
     lib = _load()
     rp, ci = _csr(row_ptr, col_idx)
+    marr, mptr = _mass(mass, n)
     varr, vptr = _verts(verts)
     count = n if varr is None else varr.size
     p = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1)
@@ -144,8 +164,8 @@ def forces(n: int, row_ptr, col_idx, kptr, kidx, d: float, pos, verts=None):
         ki = np.zeros(1, dtype=np.int32)
     F = np.zeros(2 * max(count, 1), dtype=np.float64)
     coinc = ctypes.c_int64(0)
-    _check(lib.orc_forces(n, rp, ci, count, vptr, kp, ki, float(d), p, F, ctypes.byref(coinc)),
-           "forces")
+    _check(lib.orc_forces(n, rp, ci, count, vptr, kp, ki, float(d), mptr, p, F,
+                          ctypes.byref(coinc)), "forces")
     return F[: 2 * count].reshape(count, 2), int(coinc.value)
 
 
@@ -167,10 +187,11 @@ class StepStats:
 
 
 def step(n: int, row_ptr, col_idx, kptr, kidx, d: float, t: float, pos,
-         stop_displacement: float = 0.01):
+         stop_displacement: float = 0.01, mass=None):
     """One synchronous iteration.  Returns (new_pos, F, Delta, StepStats)."""
     lib = _load()
     rp, ci = _csr(row_ptr, col_idx)
+    marr, mptr = _mass(mass, n)
     p = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1).copy()
     kp = np.ascontiguousarray(kptr, dtype=np.int64)
     ki = np.ascontiguousarray(kidx, dtype=np.int32)
@@ -179,18 +200,19 @@ def step(n: int, row_ptr, col_idx, kptr, kidx, d: float, t: float, pos,
     F = np.zeros(2 * max(n, 1), dtype=np.float64)
     D = np.zeros(2 * max(n, 1), dtype=np.float64)
     st = _IterStats()
-    _check(lib.orc_step(n, rp, ci, kp, ki, float(d), float(t), float(stop_displacement), p, F, D,
-                        ctypes.byref(st)), "step")
+    _check(lib.orc_step(n, rp, ci, kp, ki, float(d), mptr, float(t), float(stop_displacement),
+                        p, F, D, ctypes.byref(st)), "step")
     return (p.reshape(-1, 2), F[: 2 * n].reshape(-1, 2), D[: 2 * n].reshape(-1, 2),
             StepStats(int(st.moved), float(st.max_disp), float(st.energy), int(st.coincident)))
 
 
 def layout(n: int, row_ptr, col_idx, kptr, kidx, d: float, temperature, pos,
            h0: int = 0, h_end: int | None = None, stop_fraction: float = 0.0,
-           stop_displacement: float = 0.01):
+           stop_displacement: float = 0.01, mass=None):
     """Iterations h0 .. h_end-1.  Returns (pos, iterations_run, StepStats)."""
     lib = _load()
     rp, ci = _csr(row_ptr, col_idx)
+    marr, mptr = _mass(mass, n)
     temps = np.ascontiguousarray(temperature, dtype=np.float64)
     if h_end is None:
         h_end = temps.size
@@ -205,7 +227,7 @@ def layout(n: int, row_ptr, col_idx, kptr, kidx, d: float, temperature, pos,
         temps = np.zeros(1)
     run = ctypes.c_int32(0)
     st = _IterStats()
-    _check(lib.orc_layout(n, rp, ci, kp, ki, float(d), temps, int(h0), int(h_end),
+    _check(lib.orc_layout(n, rp, ci, kp, ki, float(d), mptr, temps, int(h0), int(h_end),
                           float(stop_fraction), float(stop_displacement), p, ctypes.byref(run),
                           ctypes.byref(st)), "layout")
     return (p.reshape(-1, 2), int(run.value),
@@ -224,3 +246,70 @@ def linear_schedule(t0: float, iterations: int) -> np.ndarray:
     t = np.zeros(max(iterations, 1))
     _load().orc_linear_schedule(float(t0), int(iterations), t)
     return t[:iterations]
+
+
+@dataclass
+class Pruned:
+    """Result of pruning the degree-one vertices (Section 4.3).
+
+    anchor[v]: the neighbour v was pruned from, -1 for kept vertices;
+    leaves[v]: the number of vertices pruned from v;
+    new_id[v]: v's id in the pruned graph (ascending original order), -1 if
+    pruned; row_ptr/col_idx: the pruned graph; n: its vertex count.
+    """
+    anchor: np.ndarray
+    leaves: np.ndarray
+    new_id: np.ndarray
+    n: int
+    row_ptr: np.ndarray
+    col_idx: np.ndarray
+
+    def mass(self) -> np.ndarray:
+        """Weight of the repulsion exerted by each kept vertex (Section 4.6):
+        1 + its pruned leaves, indexed by the pruned graph's ids."""
+        kept = self.new_id >= 0
+        m = np.zeros(self.n, dtype=np.float64)
+        m[self.new_id[kept]] = 1.0 + self.leaves[kept]
+        return m
+
+
+def prune(n: int, row_ptr, col_idx) -> Pruned:
+    """Remove the degree-one vertices (Section 4.3)."""
+    lib = _load()
+    rp, ci = _csr(row_ptr, col_idx)
+    if ci.size == 0:
+        ci = np.zeros(1, dtype=np.int32)
+    anchor = np.zeros(max(n, 1), dtype=np.int32)
+    leaves = np.zeros(max(n, 1), dtype=np.int32)
+    new_id = np.zeros(max(n, 1), dtype=np.int32)
+    nk = ctypes.c_int32(0)
+    nnz = ctypes.c_int64(0)
+    _check(lib.orc_prune(n, rp, ci, anchor, leaves, new_id, ctypes.byref(nk), ctypes.byref(nnz)),
+           "prune")
+    rpk = np.zeros(nk.value + 1, dtype=np.int64)
+    cik = np.zeros(max(nnz.value, 1), dtype=np.int32)
+    _check(lib.orc_pruned_graph(n, rp, ci, new_id, rpk, cik), "pruned_graph")
+    return Pruned(anchor[:n], leaves[:n], new_id[:n], int(nk.value), rpk, cik[: nnz.value])
+
+
+def reinsert(pr: Pruned, d: float, pos_kept) -> np.ndarray:
+    """Place the pruned leaves around their neighbours (Section 4.6).
+
+    pos_kept: float64[pr.n, 2], the pruned graph's drawing.  Returns
+    float64[n, 2] for the original graph.
+    """
+    lib = _load()
+    n = pr.anchor.size
+    pk = np.ascontiguousarray(pos_kept, dtype=np.float64).reshape(-1)
+    if pk.size != 2 * pr.n:
+        raise ValueError("pos_kept must be [n_kept, 2]")
+    if pk.size == 0:
+        pk = np.zeros(2)
+    out = np.zeros(2 * max(n, 1), dtype=np.float64)
+    ci = pr.col_idx if pr.col_idx.size else np.zeros(1, dtype=np.int32)
+    anchor = np.ascontiguousarray(pr.anchor if n else np.zeros(1, np.int32), dtype=np.int32)
+    leaves = np.ascontiguousarray(pr.leaves if n else np.zeros(1, np.int32), dtype=np.int32)
+    new_id = np.ascontiguousarray(pr.new_id if n else np.zeros(1, np.int32), dtype=np.int32)
+    _check(lib.orc_reinsert(n, anchor, leaves, new_id, pr.n, pr.row_ptr, ci, float(d), pk, out),
+           "reinsert")
+    return out[: 2 * n].reshape(-1, 2)

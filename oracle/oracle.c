@@ -25,9 +25,21 @@
  *   - Halting statistic: number of vertices displaced by more than a
  *     threshold (Section 5.1: stop when fewer than 15% moved more than 0.01).
  *
+ *   - Pruning of degree-one vertices before the layout (Section 4.3), the
+ *     repulsion exerted by a vertex weighted by its pruned leaves
+ *     (Section 4.6), and reinsertion of the leaves on a circle around their
+ *     neighbour after the layout (Section 4.6).
+ *
  * Readings where the paper is silent: a pair of distinct vertices at the same
  * point (delta = 0) contributes no force and is counted; F_v = 0 gives no
- * move; coordinates are not clamped to any frame.
+ * move; coordinates are not clamped to any frame.  Pruning: a degree-one
+ * vertex is removed unless its only neighbour also has degree one and a
+ * larger id (so one vertex of an isolated edge stays); one pass only.  The
+ * weight of the repulsion exerted by u is 1 + (number of leaves pruned from
+ * u).  Reinsertion: radius 0.2 times the shortest edge incident to the
+ * vertex in the pruned drawing (0.2 d when it has none); its L leaves, in
+ * ascending id, at angles phi + 2 pi j / L, with phi chosen so that the
+ * leaves are as far as possible (in angle) from the incident edges.
  *
  * Sums are plain sequential double sums in ascending neighbour id.  OpenMP
  * splits the *vertices* across threads (never a sum), so results do not
@@ -153,7 +165,7 @@ int orc_khop_fill(int32_t n, const int64_t* row_ptr, const int32_t* col_idx, int
 /* One vertex: F_v = attraction over adj(v) + repulsion over N_v(k).
  * pos is interleaved (x, y).  Returns the number of coincident pairs. */
 static int64_t force_one(int32_t v, const int64_t* row_ptr, const int32_t* col_idx,
-                         const int32_t* krow, int64_t klen, double d,
+                         const int32_t* krow, int64_t klen, double d, const double* mass,
                          const double* pos, double* fx_out, double* fy_out) {
     const double xv = pos[2 * (int64_t)v], yv = pos[2 * (int64_t)v + 1];
     double ax = 0.0, ay = 0.0, rx = 0.0, ry = 0.0;
@@ -178,9 +190,11 @@ static int64_t force_one(int32_t v, const int64_t* row_ptr, const int32_t* col_i
             ++coincident;
             continue;
         }
-        /* unit vector (dx, dy) / delta times d^2 / delta */
-        rx += dx * (d * d / dd);
-        ry += dy * (d * d / dd);
+        /* unit vector (dx, dy) / delta times d^2 / delta, weighted by the
+         * leaves pruned from u (Section 4.6) when masses are given */
+        const double w = mass ? mass[u] : 1.0;
+        rx += dx * (w * (d * d / dd));
+        ry += dy * (w * (d * d / dd));
     }
     *fx_out = ax + rx;
     *fy_out = ay + ry;
@@ -192,7 +206,7 @@ static int64_t force_one(int32_t v, const int64_t* row_ptr, const int32_t* col_i
  * verts, so a sampled subset carries only its own rows.  F is [count][2]. */
 int orc_forces(int32_t n, const int64_t* row_ptr, const int32_t* col_idx,
                int64_t count, const int32_t* verts, const int64_t* kptr,
-               const int32_t* kidx, double d, const double* pos, double* F,
+               const int32_t* kidx, double d, const double* mass, const double* pos, double* F,
                int64_t* coincident_out) {
     if (n < 0 || !(d > 0.0)) return ORC_EINVAL;
     if (verts == NULL) count = n;
@@ -201,7 +215,7 @@ int orc_forces(int32_t n, const int64_t* row_ptr, const int32_t* col_idx,
     for (int64_t i = 0; i < count; ++i) {
         int32_t v = verts ? verts[i] : (int32_t)i;
         coincident += force_one(v, row_ptr, col_idx, kidx + kptr[i], kptr[i + 1] - kptr[i],
-                                d, pos, &F[2 * i], &F[2 * i + 1]);
+                                d, mass, pos, &F[2 * i], &F[2 * i + 1]);
     }
     if (coincident_out) *coincident_out = coincident;
     return ORC_OK;
@@ -241,11 +255,11 @@ typedef struct {
  * place only after all forces are known.  F and D (both [n][2]) receive the
  * forces and displacements. */
 int orc_step(int32_t n, const int64_t* row_ptr, const int32_t* col_idx,
-             const int64_t* kptr, const int32_t* kidx, double d, double t,
+             const int64_t* kptr, const int32_t* kidx, double d, const double* mass, double t,
              double stop_displacement, double* pos, double* F, double* D,
              orc_iter_stats* st) {
     int64_t coincident = 0;
-    int rc = orc_forces(n, row_ptr, col_idx, n, NULL, kptr, kidx, d, pos, F, &coincident);
+    int rc = orc_forces(n, row_ptr, col_idx, n, NULL, kptr, kidx, d, mass, pos, F, &coincident);
     if (rc) return rc;
     rc = orc_cap(n, F, t, D);
     if (rc) return rc;
@@ -274,7 +288,7 @@ int orc_step(int32_t n, const int64_t* row_ptr, const int32_t* col_idx,
  * (Section 5.1); n_active counts the vertices with at least one edge.
  * Returns the number of iterations run in *iters_run. */
 int orc_layout(int32_t n, const int64_t* row_ptr, const int32_t* col_idx,
-               const int64_t* kptr, const int32_t* kidx, double d,
+               const int64_t* kptr, const int32_t* kidx, double d, const double* mass,
                const double* temperature, int32_t h0, int32_t h_end,
                double stop_fraction, double stop_displacement, double* pos,
                int32_t* iters_run, orc_iter_stats* last) {
@@ -292,8 +306,8 @@ int orc_layout(int32_t n, const int64_t* row_ptr, const int32_t* col_idx,
     int32_t run = 0;
     int rc = ORC_OK;
     for (int32_t h = h0; h < h_end; ++h) {
-        rc = orc_step(n, row_ptr, col_idx, kptr, kidx, d, temperature[h], stop_displacement,
-                      pos, F, D, &st);
+        rc = orc_step(n, row_ptr, col_idx, kptr, kidx, d, mass, temperature[h],
+                      stop_displacement, pos, F, D, &st);
         if (rc) break;
         ++run;
         if (stop_fraction > 0.0 && (double)st.moved < stop_fraction * (double)n_active) break;
@@ -303,6 +317,160 @@ int orc_layout(int32_t n, const int64_t* row_ptr, const int32_t* col_idx,
     if (iters_run) *iters_run = run;
     if (last) *last = st;
     return rc;
+}
+
+/* ------------------------------------------------------------------ */
+/* Pruning and reinsertion of degree-one vertices (Sections 4.3, 4.6)  */
+/* ------------------------------------------------------------------ */
+
+/* Marks the pruned vertices: a degree-one vertex v with neighbour w is
+ * pruned unless w has degree one too and w > v.  anchor[v] = w for a pruned
+ * v (else -1); leaves[w] counts the vertices pruned from w.  new_id[v] is v's
+ * id in the pruned graph (kept vertices in ascending original id; -1 for
+ * pruned ones).  Returns the number of kept vertices in *n_kept and the
+ * pruned graph's adjacency entries in *nnz_kept. */
+int orc_prune(int32_t n, const int64_t* row_ptr, const int32_t* col_idx, int32_t* anchor,
+              int32_t* leaves, int32_t* new_id, int32_t* n_kept, int64_t* nnz_kept) {
+    if (n < 0) return ORC_EINVAL;
+    for (int32_t v = 0; v < n; ++v) {
+        anchor[v] = -1;
+        leaves[v] = 0;
+    }
+    for (int32_t v = 0; v < n; ++v) {
+        if (row_ptr[v + 1] - row_ptr[v] != 1) continue;
+        const int32_t w = col_idx[row_ptr[v]];
+        const int64_t degw = row_ptr[w + 1] - row_ptr[w];
+        if (degw > 1 || w < v) anchor[v] = w;
+    }
+    int32_t kept = 0;
+    int64_t nnz = 0;
+    for (int32_t v = 0; v < n; ++v) {
+        if (anchor[v] >= 0) {
+            leaves[anchor[v]] += 1;
+            new_id[v] = -1;
+        } else {
+            new_id[v] = kept++;
+        }
+    }
+    for (int32_t v = 0; v < n; ++v) {
+        if (anchor[v] >= 0) continue;
+        for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) nnz += anchor[col_idx[e]] < 0;
+    }
+    *n_kept = kept;
+    *nnz_kept = nnz;
+    return ORC_OK;
+}
+
+/* The pruned graph's CSR (kept vertices renumbered by new_id; rows stay
+ * ascending because the renumbering keeps the order). */
+int orc_pruned_graph(int32_t n, const int64_t* row_ptr, const int32_t* col_idx,
+                     const int32_t* new_id, int64_t* rp_out, int32_t* ci_out) {
+    int64_t o = 0;
+    int32_t r = 0;
+    rp_out[0] = 0;
+    for (int32_t v = 0; v < n; ++v) {
+        if (new_id[v] < 0) continue;
+        for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+            const int32_t u = new_id[col_idx[e]];
+            if (u >= 0) ci_out[o++] = u;
+        }
+        rp_out[++r] = o;
+    }
+    return ORC_OK;
+}
+
+static int cmp_f64(const void* a, const void* b) {
+    const double x = *(const double*)a, y = *(const double*)b;
+    return (x > y) - (x < y);
+}
+
+/* Reinsertion (Section 4.6).  pos_kept [n_kept][2] is the drawing of the
+ * pruned graph (rp_k, ci_k); pos_all [n][2] receives every vertex: kept ones
+ * copied, the leaves of kept vertex v (original ids in ascending order) on
+ * the circle of radius rho = 0.2 * (shortest edge incident to v in the pruned
+ * drawing; d if it has none) at angles phi + 2 pi j / L.  phi is the middle
+ * of the widest gap between the incident edges' angles taken modulo 2 pi / L
+ * (the first widest gap in ascending order; phi = 0 without incident edges),
+ * so every leaf is as far as possible in angle from the incident edges. */
+int orc_reinsert(int32_t n, const int32_t* anchor, const int32_t* leaves, const int32_t* new_id,
+                 int32_t n_kept, const int64_t* rp_k, const int32_t* ci_k, double d,
+                 const double* pos_kept, double* pos_all) {
+    const double two_pi = 6.283185307179586476925286766559;
+    int32_t* kept_of = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n_kept > 0 ? n_kept : 1));
+    int32_t* next_j = (int32_t*)calloc((size_t)(n > 0 ? n : 1), sizeof(int32_t));
+    double* phi = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double* rho = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    if (!kept_of || !next_j || !phi || !rho) {
+        free(kept_of);
+        free(next_j);
+        free(phi);
+        free(rho);
+        return ORC_ENOMEM;
+    }
+    for (int32_t v = 0; v < n; ++v)
+        if (new_id[v] >= 0) kept_of[new_id[v]] = v;
+    for (int32_t i = 0; i < n_kept; ++i) {
+        const int32_t v = kept_of[i];
+        pos_all[2 * (int64_t)v] = pos_kept[2 * (int64_t)i];
+        pos_all[2 * (int64_t)v + 1] = pos_kept[2 * (int64_t)i + 1];
+        const int32_t L = leaves[v];
+        if (L == 0) continue;
+        const double xv = pos_kept[2 * (int64_t)i], yv = pos_kept[2 * (int64_t)i + 1];
+        const int64_t deg = rp_k[i + 1] - rp_k[i];
+        const double period = two_pi / (double)L;
+        double shortest = -1.0;
+        double* res = (double*)malloc(sizeof(double) * (size_t)(deg > 0 ? deg : 1));
+        if (!res) {
+            free(kept_of);
+            free(next_j);
+            free(phi);
+            free(rho);
+            return ORC_ENOMEM;
+        }
+        for (int64_t e = 0; e < deg; ++e) {
+            const int32_t u = ci_k[rp_k[i] + e];
+            const double dx = pos_kept[2 * (int64_t)u] - xv, dy = pos_kept[2 * (int64_t)u + 1] - yv;
+            const double len = sqrt(dx * dx + dy * dy);
+            if (shortest < 0.0 || len < shortest) shortest = len;
+            double a = atan2(dy, dx);
+            if (a < 0.0) a += two_pi;
+            double r = fmod(a, period);
+            if (r < 0.0) r += period;
+            if (r >= period) r -= period;
+            res[e] = r;
+        }
+        double best = 0.0;
+        if (deg > 0) {
+            qsort(res, (size_t)deg, sizeof(double), cmp_f64);
+            double widest = -1.0;
+            for (int64_t e = 0; e < deg; ++e) {
+                const double lo = res[e];
+                const double hi = e + 1 < deg ? res[e + 1] : res[0] + period;
+                if (hi - lo > widest) {
+                    widest = hi - lo;
+                    best = lo + 0.5 * (hi - lo);
+                }
+            }
+            if (best >= period) best -= period;
+        }
+        free(res);
+        phi[v] = best;
+        rho[v] = 0.2 * (deg > 0 ? shortest : d);
+    }
+    for (int32_t u = 0; u < n; ++u) {
+        const int32_t v = anchor[u];
+        if (v < 0) continue;
+        const int32_t j = next_j[v]++;
+        const double theta = phi[v] + two_pi * (double)j / (double)leaves[v];
+        const int32_t i = new_id[v];
+        pos_all[2 * (int64_t)u] = pos_kept[2 * (int64_t)i] + rho[v] * cos(theta);
+        pos_all[2 * (int64_t)u + 1] = pos_kept[2 * (int64_t)i + 1] + rho[v] * sin(theta);
+    }
+    free(kept_of);
+    free(next_j);
+    free(phi);
+    free(rho);
+    return ORC_OK;
 }
 
 /* ------------------------------------------------------------------ */
