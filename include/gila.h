@@ -119,6 +119,17 @@ int gila_khop_export_rows(const gila_khop* kh, int64_t count, const int32_t* ver
 
 void gila_khop_free(gila_khop* kh);
 
+/* Weights of the repulsion each vertex exerts (Section 4.6: a vertex from
+ * which L degree-one neighbours were pruned repels with weight 1 + L, so the
+ * disc its leaves are put back on stays clear).  The repulsion on v from u
+ * becomes w_u (x_v - x_u) d^2 / delta^2; attraction is unchanged.  mass_dev
+ * is double[n] on the device, caller ids, every weight in [0, 1e30]; it is
+ * copied into the handle (EINVAL, and the previous weights kept, if any is
+ * out of range).  NULL restores unit weights.  The next iteration call
+ * rebuilds the segment layout for the weighted kernels (a weight is staged in
+ * LDS beside each position).  Synchronises `stream`. */
+int gila_khop_set_mass(gila_khop* kh, const double* mass_dev, void* stream);
+
 /* ------------------------------------------------------------------ */
 /* Layout parameters                                                    */
 /* ------------------------------------------------------------------ */
@@ -179,6 +190,68 @@ int gila_time_iterations(const gila_khop* kh, const gila_params* params, int32_t
  * params->iterations, free.  Synchronises `stream`. */
 int gila_layout(const gila_csr* g_dev, int32_t k, const gila_params* params, void* pos_dev,
                 void* stream, gila_stats* out);
+
+/* ------------------------------------------------------------------ */
+/* Degree-one vertices: pruning and reinsertion (Sections 4.3, 4.6)     */
+/* ------------------------------------------------------------------ */
+typedef struct gila_pruned gila_pruned;
+
+/* Prune the degree-one vertices of g_dev (device CSR, validated as for
+ * gila_build_khop).  A vertex of degree one is removed unless its only
+ * neighbour also has degree one and a larger id (one end of each isolated
+ * edge stays); one pass, so every removed vertex hangs from a kept one.  The
+ * kept vertices, renumbered in ascending original id, and the edges among
+ * them form the pruned graph.  The handle owns its device memory until
+ * gila_pruned_free.  Synchronises `stream`. */
+int gila_prune(const gila_csr* g_dev, void* stream, gila_pruned** out);
+
+/* Sizes: kept vertices, adjacency entries of the pruned graph, pruned
+ * vertices, kept vertices with at least one pruned neighbour, device bytes
+ * held.  Any output may be NULL. */
+int gila_pruned_info(const gila_pruned* p, int32_t* n_kept, int64_t* nnz_kept, int32_t* n_pruned,
+                     int32_t* n_with_leaves, int64_t* device_bytes);
+
+/* The pruned graph as a device CSR and the repulsion weights of its vertices
+ * (double[n_kept], 1 + pruned neighbours; for gila_khop_set_mass).  Both
+ * point into the handle: valid until gila_pruned_free.  Either output may be
+ * NULL. */
+int gila_pruned_graph(const gila_pruned* p, gila_csr* g_dev_out, const double** mass_dev_out);
+
+/* Host copies, each int32[n] in original ids (any may be NULL): the kept
+ * vertex a pruned vertex hung from (-1 for kept vertices), the number of
+ * vertices pruned from each vertex, and each vertex's id in the pruned graph
+ * (-1 for pruned vertices).  Synchronous. */
+int gila_pruned_export(const gila_pruned* p, int32_t* anchor_host, int32_t* leaves_host,
+                       int32_t* new_id_host);
+
+/* pos_kept_dev[new_id[v]] = pos_all_dev[v] for every kept v (positions in
+ * the precision's layout).  Enqueued on `stream`. */
+int gila_pruned_gather(const gila_pruned* p, int32_t precision, const void* pos_all_dev,
+                       void* pos_kept_dev, void* stream);
+
+/* Reinsertion (Section 4.6): pos_all_dev receives every vertex of the
+ * original graph.  Kept vertices take their position in pos_kept_dev (the
+ * drawing of the pruned graph).  The L vertices pruned from kept vertex v go,
+ * in ascending id, to v + rho (cos a_j, sin a_j) with a_j = phi + 2 pi j / L,
+ * rho = 0.2 x the length of v's shortest edge in the pruned drawing
+ * (0.2 x ideal_length if v has none), and phi the middle of the widest gap
+ * between the angles of v's edges taken modulo 2 pi / L (the first widest
+ * in ascending order; 0 without edges): the leaves are spread evenly and as
+ * far as possible in angle from the edges.  Computed in double; enqueued on
+ * `stream`. */
+int gila_reinsert(const gila_pruned* p, double ideal_length, int32_t precision,
+                  const void* pos_kept_dev, void* pos_all_dev, void* stream);
+
+void gila_pruned_free(gila_pruned* p);
+
+/* The pipeline of Sections 4.3 - 4.6 on one graph: prune, build N_v(k) of the
+ * pruned graph, weight each kept vertex's repulsion by 1 + its pruned
+ * neighbours, run all params->iterations from the kept vertices' positions in
+ * pos_dev (the pruned vertices' entries are ignored), then reinsert, writing
+ * every vertex to pos_dev.  `out` describes the iterations on the pruned
+ * graph (n_active and the halting rule count its vertices).  Synchronises. */
+int gila_layout_pruned(const gila_csr* g_dev, int32_t k, const gila_params* params, void* pos_dev,
+                       void* stream, gila_stats* out);
 
 /* ------------------------------------------------------------------ */
 /* Many graphs in one launch                                            */

@@ -26,7 +26,8 @@
 namespace gila {
 
 // Partial force of one vertex over lanes lane0, lane0+STRIDE, ... of its rows.
-template <class P, int STRIDE>
+// WEIGHTED scales the repulsion from u by u's weight (Section 4.6).
+template <class P, int STRIDE, bool WEIGHTED>
 __device__ __forceinline__ void vertex_partial(const StepArgs& a, int32_t v, int lane0,
                                                Acc<typename P::real, P::kahan>& acc, int& coinc,
                                                typename P::vec2& xv_out) {
@@ -37,6 +38,11 @@ __device__ __forceinline__ void vertex_partial(const StepArgs& a, int32_t v, int
     xv_out = xv;
     const R d2 = (R)(a.d * a.d);
     const R inv_d = attract_param<R>(a.d);
+    const R* __restrict__ wt = reinterpret_cast<const R*>(a.mass);
+    auto scale = [&](int32_t u) -> R {
+        if constexpr (WEIGHTED) return d2 * wt[u];
+        else return d2;
+    };
     const int64_t kb = a.kptr[v], ke = a.kptr[v + 1];
     int64_t e = kb + lane0;
     // four independent gathers in flight per lane
@@ -46,18 +52,21 @@ __device__ __forceinline__ void vertex_partial(const StepArgs& a, int32_t v, int
         const int32_t u2 = a.kidx[e + 2 * STRIDE];
         const int32_t u3 = a.kidx[e + 3 * STRIDE];
         const V p0 = pos[u0], p1 = pos[u1], p2 = pos[u2], p3 = pos[u3];
-        repulse<P>(xv.x, xv.y, p0, d2, acc, coinc);
-        repulse<P>(xv.x, xv.y, p1, d2, acc, coinc);
-        repulse<P>(xv.x, xv.y, p2, d2, acc, coinc);
-        repulse<P>(xv.x, xv.y, p3, d2, acc, coinc);
+        repulse<P>(xv.x, xv.y, p0, scale(u0), acc, coinc);
+        repulse<P>(xv.x, xv.y, p1, scale(u1), acc, coinc);
+        repulse<P>(xv.x, xv.y, p2, scale(u2), acc, coinc);
+        repulse<P>(xv.x, xv.y, p3, scale(u3), acc, coinc);
     }
-    for (; e < ke; e += STRIDE) repulse<P>(xv.x, xv.y, pos[a.kidx[e]], d2, acc, coinc);
+    for (; e < ke; e += STRIDE) {
+        const int32_t u = a.kidx[e];
+        repulse<P>(xv.x, xv.y, pos[u], scale(u), acc, coinc);
+    }
     const int64_t rb = a.rp[v], re = a.rp[v + 1];
     for (int64_t j = rb + lane0; j < re; j += STRIDE)
         attract<P>(xv.x, xv.y, pos[a.ci[j]], inv_d, acc);
 }
 
-template <int PREC, int LPV>
+template <int PREC, int LPV, bool WEIGHTED>
 __global__ __launch_bounds__(kBlock) void fr_step_kernel(StepArgs a) {
     using P = Prec<PREC>;
     using V = typename P::vec2;
@@ -76,7 +85,7 @@ __global__ __launch_bounds__(kBlock) void fr_step_kernel(StepArgs a) {
         const int32_t v = blockIdx.x;
         Acc<typename P::real, P::kahan> acc;
         V xv;
-        vertex_partial<P, kBlock>(a, v, threadIdx.x, acc, coinc, xv);
+        vertex_partial<P, kBlock, WEIGHTED>(a, v, threadIdx.x, acc, coinc, xv);
         double fx = wave_sum(acc.x()), fy = wave_sum(acc.y());
         if (lane == 0) {
             s_fx[w] = fx;
@@ -105,7 +114,7 @@ __global__ __launch_bounds__(kBlock) void fr_step_kernel(StepArgs a) {
             V xv;
             xv.x = 0;
             xv.y = 0;
-            if (live) vertex_partial<P, LPV>(a, v, gl, acc, coinc, xv);
+            if (live) vertex_partial<P, LPV, WEIGHTED>(a, v, gl, acc, coinc, xv);
             const double fx = group_sum<LPV>(acc.x());
             const double fy = group_sum<LPV>(acc.y());
             if (live && gl == 0) finish_vertex<P>(a, v, xv, fx, fy, energy, maxd, moved);
@@ -116,16 +125,22 @@ __global__ __launch_bounds__(kBlock) void fr_step_kernel(StepArgs a) {
 }
 
 // ------------------------------------------------------------------ launch
-template <int PREC>
-static void launch_prec(int lpv, const StepArgs& a, hipStream_t s) {
+template <int PREC, bool WEIGHTED>
+static void launch_lpv(int lpv, const StepArgs& a, hipStream_t s) {
     const dim3 grid(a.nblocks), block(kBlock);
     switch (lpv) {
-        case 4: hipLaunchKernelGGL((fr_step_kernel<PREC, 4>), grid, block, 0, s, a); break;
-        case 8: hipLaunchKernelGGL((fr_step_kernel<PREC, 8>), grid, block, 0, s, a); break;
-        case 16: hipLaunchKernelGGL((fr_step_kernel<PREC, 16>), grid, block, 0, s, a); break;
-        case 32: hipLaunchKernelGGL((fr_step_kernel<PREC, 32>), grid, block, 0, s, a); break;
-        default: hipLaunchKernelGGL((fr_step_kernel<PREC, 64>), grid, block, 0, s, a); break;
+        case 4: hipLaunchKernelGGL((fr_step_kernel<PREC, 4, WEIGHTED>), grid, block, 0, s, a); break;
+        case 8: hipLaunchKernelGGL((fr_step_kernel<PREC, 8, WEIGHTED>), grid, block, 0, s, a); break;
+        case 16: hipLaunchKernelGGL((fr_step_kernel<PREC, 16, WEIGHTED>), grid, block, 0, s, a); break;
+        case 32: hipLaunchKernelGGL((fr_step_kernel<PREC, 32, WEIGHTED>), grid, block, 0, s, a); break;
+        default: hipLaunchKernelGGL((fr_step_kernel<PREC, 64, WEIGHTED>), grid, block, 0, s, a); break;
     }
+}
+
+template <int PREC>
+static void launch_prec(int lpv, const StepArgs& a, hipStream_t s) {
+    if (a.mass) launch_lpv<PREC, true>(lpv, a, s);
+    else launch_lpv<PREC, false>(lpv, a, s);
 }
 
 int launch_step(const gila_khop* kh, int precision, const StepArgs& a, hipStream_t s) {

@@ -144,6 +144,9 @@ struct StepArgs {
     // part[vsl[v] .. vsl[v + 1]), one per non-empty slice, in segment order
     const int64_t* vsl;
     const double2* part;
+    // weight of the repulsion each vertex exerts (internal ids; float for the
+    // FP32 precisions, double for FP64); null = every weight 1
+    const void* mass;
 };
 
 // Arguments of the segment kernel (one workgroup = one id segment x a range
@@ -162,6 +165,7 @@ struct SegArgs {
     double2* part;              // [T]
     double d;
     Ctl* ctl;
+    const void* mass;           // repulsion weights (internal ids), null = unit
 };
 
 // Arguments of the k-hop frontier-expansion kernel (khop.hip).
@@ -234,6 +238,10 @@ struct gila_khop {
     int32_t comb_grid = 0;
     double2* part = nullptr;        // [T] partial force of each slice, row-major
     int32_t seg_precision = -1;     // precision the segment size was chosen for
+    bool seg_weighted = false;      // segment size chosen with a weight per staged vertex
+    // weights of the repulsion each vertex exerts (internal ids), null = unit
+    double* mass64 = nullptr;
+    float* mass32 = nullptr;
     // cached HIP graph of the last gila_run call
     hipGraphExec_t gexec = nullptr;
     std::vector<uint64_t> gkey;
@@ -251,6 +259,7 @@ void free_khop(gila_khop* kh, Release rel = Release{});
 int run_bfs(bool fill, int device, hipStream_t s, BfsArgs a);
 int launch_validate_csr(int32_t n, int64_t nnz, const int64_t* rp, const int32_t* ci, int32_t* flag,
                         hipStream_t s);
+int validate_graph(const gila_csr* g, hipStream_t s);
 // implemented in util.hip: out[0] = 0, out[i + 1] = in[0] + ... + in[i]
 // (in != out).  The enqueue variant needs scan_workspace_count(n) int64 of
 // workspace and does not synchronise; the other allocates and synchronises.
@@ -264,7 +273,11 @@ void free_segments(gila_khop* kh, Release rel = Release{});
 int launch_segment_step(const gila_khop* kh, int precision, const StepArgs& a, hipStream_t s,
                         hipEvent_t* ev = nullptr);
 bool segment_path_enabled();
-int seg_size_for(int precision, int device);
+// segment size S for the handle's graph in `precision` (weighted repulsion
+// stores a weight beside each staged position)
+int seg_size_for(const gila_khop* kh, int precision);
+// the segment layout is built for `precision` and the iteration uses it
+bool segment_ready_for(const gila_khop* kh, int precision);
 // implemented in layout.hip: publishes an iteration's statistics from the
 // per-workgroup partials (launched after each per-vertex kernel)
 int launch_iteration_stats(const StepArgs& a, hipStream_t s);

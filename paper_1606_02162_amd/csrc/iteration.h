@@ -100,13 +100,16 @@ __device__ __forceinline__ R coincidence_bias() {
 // (sx, sy); the factor d^2 of the force (magnitude d^2 / delta, q = 1) is
 // applied by the caller once per row.  A sentinel far away (delta^2 = +inf)
 // contributes exactly 0.  `mindd` tracks the smallest biased delta^2, so rows
-// holding a coincident pair can be recounted exactly (rare).
-template <class P>
+// holding a coincident pair can be recounted exactly (rare).  With WEIGHTED,
+// the term of neighbour i is scaled by w[i], the weight of the repulsion that
+// neighbour exerts (1 + its pruned degree-one neighbours, Section 4.6).
+template <class P, bool WEIGHTED = false>
 __device__ __forceinline__ void repulse4(typename P::vec2 p0, typename P::vec2 p1,
                                          typename P::vec2 p2, typename P::vec2 p3,
                                          typename P::real xv, typename P::real yv,
                                          typename P::real& sx, typename P::real& sy,
-                                         typename P::real& mindd) {
+                                         typename P::real& mindd,
+                                         const typename P::real* w = nullptr) {
     using R = typename P::real;
     const R bias = coincidence_bias<R>();
     const R dx0 = xv - p0.x, dy0 = yv - p0.y;
@@ -130,6 +133,12 @@ __device__ __forceinline__ void repulse4(typename P::vec2 p0, typename P::vec2 p
         r1 = R(1) / dd1;
         r2 = R(1) / dd2;
         r3 = R(1) / dd3;
+    }
+    if constexpr (WEIGHTED) {
+        r0 *= w[0];
+        r1 *= w[1];
+        r2 *= w[2];
+        r3 *= w[3];
     }
     sx = fma(dx0, r0, dx1 * r1) + fma(dx2, r2, dx3 * r3);
     sy = fma(dy0, r0, dy1 * r1) + fma(dy2, r2, dy3 * r3);

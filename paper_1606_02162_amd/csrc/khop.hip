@@ -285,6 +285,48 @@ int launch_validate_csr(int32_t n, int64_t nnz, const int64_t* rp, const int32_t
     return GILA_OK;
 }
 
+// Host checks of the row pointers and the device check of every entry of a
+// caller's CSR (the rules of gila_csr).  Synchronises `s`.
+int validate_graph(const gila_csr* g, hipStream_t s) {
+    if (!g) return fail(GILA_EINVAL, "graph is NULL");
+    if (g->n < 0 || g->nnz < 0) return fail(GILA_EINVAL, "negative n or nnz");
+    if (g->n > 0 && !g->row_ptr) return fail(GILA_EINVAL, "row_ptr is NULL");
+    if (g->nnz > 0 && !g->col_idx) return fail(GILA_EINVAL, "col_idx is NULL");
+    if (g->nnz > (int64_t)g->n * (int64_t)(g->n > 0 ? g->n - 1 : 0))
+        return fail(GILA_EINVAL, "nnz exceeds n(n-1)");
+    if (g->n == 0) return GILA_OK;
+    std::vector<int64_t> rp((size_t)g->n + 1);
+    GILA_HIP(hipMemcpyAsync(rp.data(), g->row_ptr, sizeof(int64_t) * rp.size(),
+                            hipMemcpyDeviceToHost, s));
+    GILA_HIP(hipStreamSynchronize(s));
+    if (rp[0] != 0 || rp[g->n] != g->nnz)
+        return fail(GILA_EINVAL, "row_ptr[0] must be 0 and row_ptr[n] must equal nnz");
+    for (int32_t v = 0; v < g->n; ++v)
+        if (rp[v + 1] < rp[v]) return fail(GILA_EINVAL, "row_ptr not monotone");
+    if (g->nnz % 2) return fail(GILA_EINVAL, "nnz must be even for a symmetric CSR");
+    if (g->nnz == 0) return GILA_OK;
+    int32_t* d_flag = nullptr;
+    GILA_TRY(dalloc_t(&d_flag, 1));
+    int rc = GILA_OK;
+    int32_t flag = 0;
+    hipError_t e = hipMemsetAsync(d_flag, 0, sizeof(int32_t), s);
+    if (e == hipSuccess) {
+        rc = launch_validate_csr(g->n, g->nnz, g->row_ptr, g->col_idx, d_flag, s);
+        if (rc == GILA_OK) {
+            e = hipMemcpyAsync(&flag, d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+        }
+    }
+    dfree_on(d_flag, s);
+    if (rc != GILA_OK) return rc;
+    if (e != hipSuccess) return fail(GILA_EDEVICE, "validation: %s", hipGetErrorString(e));
+    if (flag)
+        return fail(GILA_EINVAL, "malformed CSR:%s%s%s%s", (flag & 1) ? " column out of range" : "",
+                    (flag & 2) ? " self-loop" : "", (flag & 4) ? " row not strictly ascending" : "",
+                    (flag & 8) ? " not symmetric" : "");
+    return GILA_OK;
+}
+
 int run_bfs(bool fill, int device, hipStream_t s, BfsArgs a) {
     const DeviceInfo& di = device_info(device);
     // LDS bitmap: one bit per vertex id plus the summary (one bit per word)
@@ -371,6 +413,8 @@ void free_khop(gila_khop* kh, Release rel) {
     rel(kh->partials);
     rel(kh->ctl);
     rel(kh->hist);
+    rel(kh->mass64);
+    rel(kh->mass32);
     free_segments(kh, rel);
     delete kh;
 }
@@ -379,6 +423,27 @@ struct KhopHolder {
     gila_khop* p;
     ~KhopHolder() { free_khop(p); }
 };
+
+// ------------------------------------------------------------------ repulsion weights
+// Caller-order weights -> internal order, in double and float; flags any
+// weight outside [0, kMaxWeight] (NaN included).
+static constexpr double kMaxWeight = 1e30;
+
+__global__ __launch_bounds__(kBlock) void weights_in_kernel(int32_t n, const int32_t* __restrict__ perm,
+                                                            const double* __restrict__ src,
+                                                            double* __restrict__ w64,
+                                                            float* __restrict__ w32,
+                                                            int32_t* __restrict__ flag) {
+    int32_t bad = 0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock) {
+        const double w = src[perm[i]];
+        if (!(w >= 0.0 && w <= kMaxWeight)) bad = 1;
+        w64[i] = w;
+        w32[i] = (float)w;
+    }
+    if (bad) atomicOr(flag, 1);
+}
 
 // ------------------------------------------------------------------ internal vertex order
 // Edges shorter than this in the caller's order count as local.
@@ -717,6 +782,61 @@ int gila_khop_export(const gila_khop* kh, int64_t* ptr_host, int32_t* idx_host) 
         const int64_t len = kptr[r + 1] - kptr[r];
         for (int64_t j = 0; j < len; ++j) dst[j] = perm[all[kptr[r] + j]];
         std::sort(dst, dst + len);
+    }
+    return GILA_OK;
+}
+
+int gila_khop_set_mass(gila_khop* kh, const double* mass_dev, void* stream) {
+    clear_error();
+    if (!kh) return fail(GILA_EINVAL, "handle is NULL");
+    std::lock_guard<std::mutex> lk(kh->mu);
+    DeviceGuard dg(kh->device);
+    hipStream_t s = (hipStream_t)stream;
+    if (mass_dev && kh->n > 0) {
+        const int32_t n = kh->n;
+        double* w64 = nullptr;
+        float* w32 = nullptr;
+        int32_t* d_flag = nullptr;
+        int rc = dalloc_t(&w64, (size_t)n);
+        if (rc == GILA_OK) rc = dalloc_t(&w32, (size_t)n);
+        if (rc == GILA_OK) rc = dalloc_t(&d_flag, 1);
+        int32_t flag = 0;
+        if (rc == GILA_OK) {
+            hipError_t e = hipMemsetAsync(d_flag, 0, sizeof(int32_t), s);
+            if (e == hipSuccess) {
+                const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(4096, (n + kBlock - 1) / kBlock));
+                hipLaunchKernelGGL(weights_in_kernel, dim3(grid), dim3(kBlock), 0, s, n, kh->perm,
+                                   mass_dev, w64, w32, d_flag);
+                e = hipGetLastError();
+            }
+            if (e == hipSuccess) e = hipMemcpyAsync(&flag, d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e != hipSuccess) rc = fail(GILA_EDEVICE, "weights: %s", hipGetErrorString(e));
+            else if (flag) rc = fail(GILA_EINVAL, "every weight must lie in [0, 1e30]");
+        }
+        dfree_on(d_flag, s);
+        if (rc != GILA_OK) {
+            dfree_on(w64, s);
+            dfree_on(w32, s);
+            return rc;
+        }
+        if (!kh->mass64) kh->device_bytes += 12 * (int64_t)n;
+        dfree_on(kh->mass64, s);
+        dfree_on(kh->mass32, s);
+        kh->mass64 = w64;
+        kh->mass32 = w32;
+    } else if (kh->mass64) {
+        dfree_on(kh->mass64, s);
+        dfree_on(kh->mass32, s);
+        kh->mass64 = nullptr;
+        kh->mass32 = nullptr;
+        kh->device_bytes -= 12 * (int64_t)kh->n;
+    }
+    // the captured loop holds the previous kernels and arguments
+    if (kh->gexec) {
+        (void)hipGraphExecDestroy(kh->gexec);
+        kh->gexec = nullptr;
+        kh->gkey.clear();
     }
     return GILA_OK;
 }

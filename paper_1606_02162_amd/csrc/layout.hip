@@ -212,6 +212,8 @@ static StepArgs base_args(const gila_khop* kh, const gila_params* p) {
     a.ctl = kh->ctl;
     a.hist = kh->hist;
     a.hist_slot = -1;
+    if (kh->mass64)
+        a.mass = p->precision == GILA_FP64 ? (const void*)kh->mass64 : (const void*)kh->mass32;
     return a;
 }
 
@@ -245,7 +247,7 @@ int enqueue_run(gila_khop* kh, const gila_params* p, int32_t start_h, int32_t en
 
 int prepare_precision(gila_khop* kh, int precision, hipStream_t s) {
     if (!segment_path_enabled()) return GILA_OK;
-    if (kh->seg_ready && kh->seg == seg_size_for(precision, kh->device)) return GILA_OK;
+    if (segment_ready_for(kh, precision)) return GILA_OK;
     if (kh->gexec) {
         (void)hipGraphExecDestroy(kh->gexec);
         kh->gexec = nullptr;
@@ -260,8 +262,7 @@ int prepare_precision(gila_khop* kh, int precision, hipStream_t s) {
 }
 
 int launch_iteration(const gila_khop* kh, int precision, const StepArgs& a, hipStream_t s) {
-    if (kh->seg_ready && segment_path_enabled() && kh->seg == seg_size_for(precision, kh->device))
-        return launch_segment_step(kh, precision, a, s);
+    if (segment_ready_for(kh, precision)) return launch_segment_step(kh, precision, a, s);
     return launch_step(kh, precision, a, s);
 }
 
@@ -427,8 +428,7 @@ int gila_time_iterations(const gila_khop* kh_c, const gila_params* params, int32
     DeviceGuard dg(kh->device);
     hipStream_t s = (hipStream_t)stream;
     GILA_TRY(prepare_precision(kh, params->precision, s));
-    const bool seg = kh->seg_ready && segment_path_enabled() &&
-                     kh->seg == seg_size_for(params->precision, kh->device);
+    const bool seg = segment_ready_for(kh, params->precision);
     std::vector<hipEvent_t> ev((size_t)reps * 3, nullptr);
     for (auto& e : ev)
         if (hipEventCreate(&e) != hipSuccess) e = nullptr;

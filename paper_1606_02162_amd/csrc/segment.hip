@@ -338,20 +338,33 @@ __device__ __forceinline__ int count_coincident_quads(V xv, const uint2* __restr
 }
 
 // Repulsion from the four neighbours whose LDS byte offsets are packed in w.
-template <class P>
+// With WEIGHTED, the weight of the vertex staged at byte offset o of the
+// positions is at byte offset o / 2 of `lw` (a weight is half a position).
+template <class P, bool WEIGHTED>
 __device__ __forceinline__ void quad_terms(uint2 w, const unsigned char* __restrict__ lds,
+                                           const unsigned char* __restrict__ lw,
                                            typename P::real xv, typename P::real yv,
                                            typename P::real& sx, typename P::real& sy,
                                            typename P::real& mindd) {
+    using R = typename P::real;
     using V = typename P::vec2;
-    const V p0 = *reinterpret_cast<const V*>(lds + (w.x & 0xFFFFu));
-    const V p1 = *reinterpret_cast<const V*>(lds + (w.x >> 16));
-    const V p2 = *reinterpret_cast<const V*>(lds + (w.y & 0xFFFFu));
-    const V p3 = *reinterpret_cast<const V*>(lds + (w.y >> 16));
-    repulse4<P>(p0, p1, p2, p3, xv, yv, sx, sy, mindd);
+    const uint32_t o0 = w.x & 0xFFFFu, o1 = w.x >> 16, o2 = w.y & 0xFFFFu, o3 = w.y >> 16;
+    const V p0 = *reinterpret_cast<const V*>(lds + o0);
+    const V p1 = *reinterpret_cast<const V*>(lds + o1);
+    const V p2 = *reinterpret_cast<const V*>(lds + o2);
+    const V p3 = *reinterpret_cast<const V*>(lds + o3);
+    if constexpr (WEIGHTED) {
+        const R m[4] = {*reinterpret_cast<const R*>(lw + (o0 >> 1)),
+                        *reinterpret_cast<const R*>(lw + (o1 >> 1)),
+                        *reinterpret_cast<const R*>(lw + (o2 >> 1)),
+                        *reinterpret_cast<const R*>(lw + (o3 >> 1))};
+        repulse4<P, true>(p0, p1, p2, p3, xv, yv, sx, sy, mindd, m);
+    } else {
+        repulse4<P>(p0, p1, p2, p3, xv, yv, sx, sy, mindd);
+    }
 }
 
-template <class P, int LPV>
+template <class P, int LPV, bool WEIGHTED>
 __device__ __forceinline__ void seg_slices(const SegArgs& a, int ib, int ie,
                                            const typename P::vec2* __restrict__ lp,
                                            int* s_next, int& coinc) {
@@ -359,6 +372,7 @@ __device__ __forceinline__ void seg_slices(const SegArgs& a, int ib, int ie,
     using V = typename P::vec2;
     const V* __restrict__ gpos = reinterpret_cast<const V*>(a.pos);
     const unsigned char* __restrict__ lds = reinterpret_cast<const unsigned char*>(lp);
+    const unsigned char* __restrict__ lw = lds + (size_t)(a.seg + 1) * sizeof(V);
     const double d2 = a.d * a.d;
     // attraction (x_u - x_v) delta / d enters the same sum divided by d^2
     const R dpar = sizeof(R) == 4 ? (R)(1.0 / (a.d * d2)) : (R)(a.d * d2);
@@ -391,16 +405,16 @@ __device__ __forceinline__ void seg_slices(const SegArgs& a, int ib, int ie,
                 const uint2 w2 = q4[q + 2 * LPV];
                 const uint2 w3 = q4[q + 3 * LPV];
                 R ax, ay, bx, by;
-                quad_terms<P>(w0, lds, xv.x, xv.y, ax, ay, mindd);
-                quad_terms<P>(w1, lds, xv.x, xv.y, bx, by, mindd);
+                quad_terms<P, WEIGHTED>(w0, lds, lw, xv.x, xv.y, ax, ay, mindd);
+                quad_terms<P, WEIGHTED>(w1, lds, lw, xv.x, xv.y, bx, by, mindd);
                 acc.add(ax + bx, ay + by);
-                quad_terms<P>(w2, lds, xv.x, xv.y, ax, ay, mindd);
-                quad_terms<P>(w3, lds, xv.x, xv.y, bx, by, mindd);
+                quad_terms<P, WEIGHTED>(w2, lds, lw, xv.x, xv.y, ax, ay, mindd);
+                quad_terms<P, WEIGHTED>(w3, lds, lw, xv.x, xv.y, bx, by, mindd);
                 acc.add(ax + bx, ay + by);
             }
             for (; q < nq; q += LPV) {
                 R ax, ay;
-                quad_terms<P>(q4[q], lds, xv.x, xv.y, ax, ay, mindd);
+                quad_terms<P, WEIGHTED>(q4[q], lds, lw, xv.x, xv.y, ax, ay, mindd);
                 acc.add(ax, ay);
             }
             if (mindd <= coincidence_bias<R>())
@@ -416,8 +430,9 @@ __device__ __forceinline__ void seg_slices(const SegArgs& a, int ib, int ie,
 }
 
 // FP32: eight waves per SIMD (the LDS of four workgroups per CU allows it);
-// FP64 needs more registers.
-template <int PREC>
+// FP64 needs more registers.  WEIGHTED stages each vertex's repulsion weight
+// after the positions (slot S of both holds the sentinel).
+template <int PREC, bool WEIGHTED>
 __global__ __launch_bounds__(kSegBlock, PREC == GILA_FP64 ? 4 : kSegWaves) void seg_force_kernel(SegArgs a) {
     using P = Prec<PREC>;
     using V = typename P::vec2;
@@ -433,6 +448,12 @@ __global__ __launch_bounds__(kSegBlock, PREC == GILA_FP64 ? 4 : kSegWaves) void 
     const int64_t left = (int64_t)a.na - base;
     const int cnt = (int)(left < a.seg ? left : a.seg);
     for (int i = threadIdx.x; i < cnt; i += kSegBlock) lp[i] = gpos[base + i];
+    using R = typename P::real;
+    R* lw = reinterpret_cast<R*>(s_raw + (size_t)(a.seg + 1) * sizeof(V));
+    if constexpr (WEIGHTED) {
+        const R* gw = reinterpret_cast<const R*>(a.mass);
+        for (int i = threadIdx.x; i < cnt; i += kSegBlock) lw[i] = gw[base + i];
+    }
     __shared__ int s_next;
     if (threadIdx.x == 0) {
         s_next = ib;
@@ -440,17 +461,18 @@ __global__ __launch_bounds__(kSegBlock, PREC == GILA_FP64 ? 4 : kSegWaves) void 
         far.x = sizeof(far.x) == 4 ? (decltype(far.x))1e30f : (decltype(far.x))1e300;
         far.y = far.x;
         lp[a.seg] = far;  // sentinel slot: padding terms vanish exactly
+        if constexpr (WEIGHTED) lw[a.seg] = R(0);
     }
     __syncthreads();
     int coinc = 0;
     switch (lpv) {
-        case 1: seg_slices<P, 1>(a, ib, ie, lp, &s_next, coinc); break;
-        case 2: seg_slices<P, 2>(a, ib, ie, lp, &s_next, coinc); break;
-        case 4: seg_slices<P, 4>(a, ib, ie, lp, &s_next, coinc); break;
-        case 8: seg_slices<P, 8>(a, ib, ie, lp, &s_next, coinc); break;
-        case 16: seg_slices<P, 16>(a, ib, ie, lp, &s_next, coinc); break;
-        case 32: seg_slices<P, 32>(a, ib, ie, lp, &s_next, coinc); break;
-        default: seg_slices<P, 64>(a, ib, ie, lp, &s_next, coinc); break;
+        case 1: seg_slices<P, 1, WEIGHTED>(a, ib, ie, lp, &s_next, coinc); break;
+        case 2: seg_slices<P, 2, WEIGHTED>(a, ib, ie, lp, &s_next, coinc); break;
+        case 4: seg_slices<P, 4, WEIGHTED>(a, ib, ie, lp, &s_next, coinc); break;
+        case 8: seg_slices<P, 8, WEIGHTED>(a, ib, ie, lp, &s_next, coinc); break;
+        case 16: seg_slices<P, 16, WEIGHTED>(a, ib, ie, lp, &s_next, coinc); break;
+        case 32: seg_slices<P, 32, WEIGHTED>(a, ib, ie, lp, &s_next, coinc); break;
+        default: seg_slices<P, 64, WEIGHTED>(a, ib, ie, lp, &s_next, coinc); break;
     }
     const int64_t wc = wave_sum((int64_t)coinc);
     if (lane64() == 0) s_c[wave_id()] = wc;
@@ -506,14 +528,28 @@ static int env_int(const char* name, int dflt) {
     return e ? atoi(e) : dflt;
 }
 
-int seg_size_for(int precision, int device) {
-    const int pos_bytes = precision == GILA_FP64 ? 16 : 8;
-    // LDS of one workgroup: the segment's positions plus ~1 KB of other state
-    const int64_t lds_cap = (int64_t)device_info(device).max_lds_per_block - 1024;
+static int pos_bytes_of(int precision) { return precision == GILA_FP64 ? 16 : 8; }
+
+// LDS bytes per staged vertex: its position, and its weight when the
+// repulsion is weighted (a weight is half a position).
+static int slot_bytes(const gila_khop* kh, int precision) {
+    const int pb = pos_bytes_of(precision);
+    return kh->mass64 ? pb + pb / 2 : pb;
+}
+
+int seg_size_for(const gila_khop* kh, int precision) {
+    const int pos_bytes = pos_bytes_of(precision);
+    // LDS of one workgroup: the segment's staged vertices plus ~1 KB of other state
+    const int64_t lds_cap = (int64_t)device_info(kh->device).max_lds_per_block - 1024;
     const int64_t want = std::min<int64_t>(env_int("GILA_SEG_BYTES", 32768), lds_cap);
-    int S = (int)(want / pos_bytes) - 1;  // one slot for the sentinel
+    int S = (int)(want / slot_bytes(kh, precision)) - 1;  // one slot for the sentinel
     S = std::min(S, 65535 / pos_bytes - 1);  // byte offsets, sentinel included, fit in 16 bits
     return std::max(64, S);
+}
+
+bool segment_ready_for(const gila_khop* kh, int precision) {
+    return kh->seg_ready && segment_path_enabled() && kh->seg == seg_size_for(kh, precision) &&
+           kh->seg_weighted == (kh->mass64 != nullptr);
 }
 
 void free_segments(gila_khop* kh, Release rel) {
@@ -560,8 +596,9 @@ struct Arena {
 int build_segments(gila_khop* kh, int precision, hipStream_t st) {
     const int32_t na = kh->n_active;
     const int pos_bytes = precision == GILA_FP64 ? 16 : 8;
-    const int S = seg_size_for(precision, kh->device);
-    if (kh->seg_ready && kh->seg == S) return GILA_OK;
+    const int S = seg_size_for(kh, precision);
+    const bool weighted = kh->mass64 != nullptr;
+    if (kh->seg_ready && kh->seg == S && kh->seg_weighted == weighted) return GILA_OK;
     free_segments(kh);
     if (na == 0) return GILA_OK;
     if (kh->nnz >= (int64_t)INT32_MAX) return fail(GILA_EUNSUPPORTED, "adjacency too large");
@@ -728,18 +765,21 @@ int build_segments(gila_khop* kh, int precision, hipStream_t st) {
                        dim3(kBlock), 0, st, (int32_t)plan.size(), slice_cost,
                        (int64_t)env_int("GILA_SEG_QPL", 8), starts, kh->sl_k, kh->sl_a, kh->seg_wg);
     GILA_HIP(hipGetLastError());
-    const size_t lds = (size_t)(S + 1) * pos_bytes;
+    const size_t lds = (size_t)(S + 1) * slot_bytes(kh, precision);
     if (lds > 48 * 1024) {
-        (void)hipFuncSetAttribute((const void*)seg_force_kernel<GILA_FP64>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        (void)hipFuncSetAttribute((const void*)seg_force_kernel<GILA_FP32>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        (void)hipFuncSetAttribute((const void*)seg_force_kernel<GILA_FP32_KAHAN>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        const void* kernels[] = {(const void*)seg_force_kernel<GILA_FP64, false>,
+                                 (const void*)seg_force_kernel<GILA_FP32, false>,
+                                 (const void*)seg_force_kernel<GILA_FP32_KAHAN, false>,
+                                 (const void*)seg_force_kernel<GILA_FP64, true>,
+                                 (const void*)seg_force_kernel<GILA_FP32, true>,
+                                 (const void*)seg_force_kernel<GILA_FP32_KAHAN, true>};
+        for (const void* k : kernels)
+            (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     }
     GILA_HIP(hipStreamSynchronize(st));
     pt.mark("fill+plan");
     kh->seg_precision = precision;
+    kh->seg_weighted = weighted;
     kh->seg_ready = true;
     kh->device_bytes += (int64_t)(na + 1) * 8 + T * (4 + 4 + 8 + 4 + 16) + 2 * (kstore + kh->nnz) +
                         (int64_t)sizeof(int4) * (int64_t)plan.size();
@@ -763,20 +803,30 @@ int launch_segment_step(const gila_khop* kh, int precision, const StepArgs& a, h
     g.part = kh->part;
     g.d = a.d;
     g.ctl = a.ctl;
+    g.mass = a.mass;
     StepArgs c = a;
     c.vsl = kh->vsl;
     c.part = kh->part;
     c.nblocks = kh->comb_grid;
-    const int pos_bytes = precision == GILA_FP64 ? 16 : 8;
-    const size_t lds = (size_t)(kh->seg + 1) * pos_bytes;
-    const dim3 sg(kh->seg_grid), sb(kSegBlock), cg(kh->comb_grid), cb(kBlock);
     if (precision != GILA_FP64 && precision != GILA_FP32 && precision != GILA_FP32_KAHAN)
         return fail(GILA_EINVAL, "unknown precision %d", precision);
+    if ((a.mass != nullptr) != kh->seg_weighted)
+        return fail(GILA_EINVAL, "segment layout built for other repulsion weights");
+    const size_t lds = (size_t)(kh->seg + 1) * slot_bytes(kh, precision);
+    const dim3 sg(kh->seg_grid), sb(kSegBlock), cg(kh->comb_grid), cb(kBlock);
     if (ev) GILA_HIP(hipEventRecord(ev[0], s));
-    switch (precision) {
-        case GILA_FP64: hipLaunchKernelGGL(seg_force_kernel<GILA_FP64>, sg, sb, lds, s, g); break;
-        case GILA_FP32: hipLaunchKernelGGL(seg_force_kernel<GILA_FP32>, sg, sb, lds, s, g); break;
-        default: hipLaunchKernelGGL(seg_force_kernel<GILA_FP32_KAHAN>, sg, sb, lds, s, g); break;
+    if (a.mass) {
+        switch (precision) {
+            case GILA_FP64: hipLaunchKernelGGL((seg_force_kernel<GILA_FP64, true>), sg, sb, lds, s, g); break;
+            case GILA_FP32: hipLaunchKernelGGL((seg_force_kernel<GILA_FP32, true>), sg, sb, lds, s, g); break;
+            default: hipLaunchKernelGGL((seg_force_kernel<GILA_FP32_KAHAN, true>), sg, sb, lds, s, g); break;
+        }
+    } else {
+        switch (precision) {
+            case GILA_FP64: hipLaunchKernelGGL((seg_force_kernel<GILA_FP64, false>), sg, sb, lds, s, g); break;
+            case GILA_FP32: hipLaunchKernelGGL((seg_force_kernel<GILA_FP32, false>), sg, sb, lds, s, g); break;
+            default: hipLaunchKernelGGL((seg_force_kernel<GILA_FP32_KAHAN, false>), sg, sb, lds, s, g); break;
+        }
     }
     if (ev) GILA_HIP(hipEventRecord(ev[1], s));
     switch (precision) {

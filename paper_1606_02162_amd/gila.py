@@ -92,6 +92,15 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "gila_khop_export": (ctypes.c_int, [vp, vp, vp]),
         "gila_khop_export_rows": (ctypes.c_int, [vp, i64, vp, vp, vp]),
         "gila_khop_free": (None, [vp]),
+        "gila_khop_set_mass": (ctypes.c_int, [vp, vp, vp]),
+        "gila_prune": (ctypes.c_int, [P(Csr), vp, P(vp)]),
+        "gila_pruned_info": (ctypes.c_int, [vp, P(i32), P(i64), P(i32), P(i32), P(i64)]),
+        "gila_pruned_graph": (ctypes.c_int, [vp, P(Csr), P(vp)]),
+        "gila_pruned_export": (ctypes.c_int, [vp, vp, vp, vp]),
+        "gila_pruned_gather": (ctypes.c_int, [vp, i32, vp, vp, vp]),
+        "gila_reinsert": (ctypes.c_int, [vp, dbl, i32, vp, vp, vp]),
+        "gila_pruned_free": (None, [vp]),
+        "gila_layout_pruned": (ctypes.c_int, [P(Csr), i32, P(_Params), vp, vp, P(Stats)]),
         "gila_init_positions": (ctypes.c_int, [i32, u64, dbl, dbl, i32, vp, vp]),
         "gila_step": (ctypes.c_int, [vp, P(_Params), i32, vp, vp, vp, vp, P(Stats)]),
         "gila_run": (ctypes.c_int, [vp, P(_Params), i32, i32, vp, vp, P(Stats)]),
@@ -226,11 +235,23 @@ def to_device_csr(graph, device="cuda"):
 class KHop:
     """Device k-neighbourhood lists of one graph (gila_build_khop)."""
 
-    def __init__(self, row_ptr, col_idx, k: int, stream=None):
+    def __init__(self, row_ptr, col_idx, k: int, stream=None, _csr: Csr | None = None):
         self._h = ctypes.c_void_p()
-        self._csr = make_csr(row_ptr, col_idx)
+        self._csr = _csr if _csr is not None else make_csr(row_ptr, col_idx)
         _check(_lib.gila_build_khop(ctypes.byref(self._csr), int(k), _stream(stream),
                                     ctypes.byref(self._h)), "gila_build_khop")
+
+    @classmethod
+    def from_csr(cls, csr: Csr, k: int, stream=None) -> "KHop":
+        """Build from a device CSR descriptor (e.g. ``Pruned.graph()``)."""
+        return cls(None, None, k, stream, _csr=csr)
+
+    def set_mass(self, mass=None, stream=None):
+        """Weights of the repulsion each vertex exerts (gila_khop_set_mass):
+        a float64 device tensor of n entries, a raw device address, or None
+        for unit weights."""
+        addr = mass if isinstance(mass, int) else _ptr(mass)
+        _check(_lib.gila_khop_set_mass(self._h, addr, _stream(stream)), "gila_khop_set_mass")
 
     @property
     def handle(self):
@@ -323,6 +344,81 @@ def layout(row_ptr, col_idx, k: int, params: LayoutParams, pos, stream=None) -> 
     p = params.as_struct()
     _check(_lib.gila_layout(ctypes.byref(csr), int(k), ctypes.byref(p), _ptr(pos),
                             _stream(stream), ctypes.byref(st)), "gila_layout")
+    return st
+
+
+# ---------------------------------------------------------------- pruning
+class Pruned:
+    """Degree-one vertices removed from a device graph (gila_prune)."""
+
+    def __init__(self, row_ptr, col_idx, stream=None, _csr: Csr | None = None):
+        self._h = ctypes.c_void_p()
+        self._csr = _csr if _csr is not None else make_csr(row_ptr, col_idx)
+        self.n = self._csr.n
+        _check(_lib.gila_prune(ctypes.byref(self._csr), _stream(stream), ctypes.byref(self._h)),
+               "gila_prune")
+
+    def info(self) -> dict:
+        nk, npr, na = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        nnz, b = ctypes.c_int64(), ctypes.c_int64()
+        _check(_lib.gila_pruned_info(self._h, ctypes.byref(nk), ctypes.byref(nnz),
+                                     ctypes.byref(npr), ctypes.byref(na), ctypes.byref(b)),
+               "gila_pruned_info")
+        return {"n_kept": nk.value, "nnz_kept": nnz.value, "n_pruned": npr.value,
+                "n_with_leaves": na.value, "device_bytes": b.value}
+
+    def graph(self):
+        """(Csr of the pruned graph, device address of its float64 weights);
+        both live as long as this handle."""
+        csr = Csr()
+        m = ctypes.c_void_p()
+        _check(_lib.gila_pruned_graph(self._h, ctypes.byref(csr), ctypes.byref(m)),
+               "gila_pruned_graph")
+        return csr, int(m.value or 0)
+
+    def export(self):
+        """Host (anchor, leaves, new_id), each int32[n] in original ids."""
+        a = np.zeros(max(self.n, 1), dtype=np.int32)
+        lv = np.zeros(max(self.n, 1), dtype=np.int32)
+        ni = np.zeros(max(self.n, 1), dtype=np.int32)
+        _check(_lib.gila_pruned_export(self._h, a.ctypes.data, lv.ctypes.data, ni.ctypes.data),
+               "gila_pruned_export")
+        return a[: self.n], lv[: self.n], ni[: self.n]
+
+    def gather(self, precision: int, pos_all, pos_kept, stream=None):
+        _check(_lib.gila_pruned_gather(self._h, int(precision), _ptr(pos_all), _ptr(pos_kept),
+                                       _stream(stream)), "gila_pruned_gather")
+        return pos_kept
+
+    def reinsert(self, ideal_length: float, precision: int, pos_kept, pos_all, stream=None):
+        _check(_lib.gila_reinsert(self._h, float(ideal_length), int(precision), _ptr(pos_kept),
+                                  _ptr(pos_all), _stream(stream)), "gila_reinsert")
+        return pos_all
+
+    def free(self):
+        if self._h:
+            _lib.gila_pruned_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def prune(row_ptr, col_idx, stream=None) -> Pruned:
+    return Pruned(row_ptr, col_idx, stream)
+
+
+def layout_pruned(row_ptr, col_idx, k: int, params: LayoutParams, pos, stream=None) -> Stats:
+    """Prune, lay out the pruned graph with leaf-weighted repulsion, reinsert
+    (gila_layout_pruned); pos holds every vertex, in and out."""
+    st = Stats()
+    csr = make_csr(row_ptr, col_idx)
+    p = params.as_struct()
+    _check(_lib.gila_layout_pruned(ctypes.byref(csr), int(k), ctypes.byref(p), _ptr(pos),
+                                   _stream(stream), ctypes.byref(st)), "gila_layout_pruned")
     return st
 
 

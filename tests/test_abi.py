@@ -28,7 +28,8 @@ def lib():
 def test_header_declares_the_boundary():
     names = _declared()
     for required in ("gila_build_khop", "gila_step", "gila_run", "gila_layout", "gila_submit",
-                     "gila_poll", "gila_layout_batch", "gila_khop_export"):
+                     "gila_poll", "gila_layout_batch", "gila_khop_export", "gila_prune",
+                     "gila_reinsert", "gila_khop_set_mass", "gila_layout_pruned"):
         assert required in names
 
 
@@ -73,6 +74,24 @@ def test_argument_validation_before_device_work():
     # init positions: negative n, bad precision
     assert L.gila_init_positions(-1, 0, 1.0, 1.0, 1, None, None) == gila.GILA_EINVAL
     assert L.gila_init_positions(0, 0, 1.0, 1.0, 1, None, None) == gila.GILA_OK
+    # pruning and weights: null graph / handles, bad k
+    assert L.gila_prune(None, None, ctypes.byref(out)) == gila.GILA_EINVAL
+    csr.n = 4
+    assert L.gila_prune(ctypes.byref(csr), None, ctypes.byref(out)) == gila.GILA_EINVAL
+    assert b"row_ptr is NULL" in L.gila_last_error()
+    assert L.gila_prune(ctypes.byref(csr), None, None) == gila.GILA_EINVAL
+    assert L.gila_pruned_info(None, None, None, None, None, None) == gila.GILA_EINVAL
+    assert L.gila_pruned_graph(None, None, None) == gila.GILA_EINVAL
+    assert L.gila_pruned_export(None, None, None, None) == gila.GILA_EINVAL
+    assert L.gila_pruned_gather(None, 1, None, None, None) == gila.GILA_EINVAL
+    assert L.gila_reinsert(None, 10.0, 1, None, None, None) == gila.GILA_EINVAL
+    assert L.gila_khop_set_mass(None, None, None) == gila.GILA_EINVAL
+    import numpy as np
+    p = gila.LayoutParams(temperature=np.ones(2)).as_struct()
+    st = gila.Stats()
+    assert L.gila_layout_pruned(ctypes.byref(csr), 0, ctypes.byref(p), None, None,
+                                ctypes.byref(st)) == gila.GILA_EINVAL
+    assert b"k must be" in L.gila_last_error()
 
 
 def test_params_validation():
