@@ -46,6 +46,7 @@ def _cpu_model() -> str:
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_seg_force_rmat18.json")
+TRAFFIC_FILE_PRUNED = os.path.join(ROOT, "profiles", "traffic_seg_force_weighted_rmat18_pruned.json")
 KERNEL_SOURCES = ["paper_1606_02162_amd/csrc/segment.hip", "paper_1606_02162_amd/csrc/iteration.h",
                   "paper_1606_02162_amd/csrc/gila_internal.h"]
 
@@ -72,11 +73,11 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic():
+def measured_traffic(path: str = TRAFFIC_FILE):
     """HBM bytes per force-kernel launch from the committed rocprofv3 counter
     summary, if it was taken on the kernel source as it is now."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
@@ -125,10 +126,13 @@ def main() -> int:
     ap.add_argument("--scale", type=int, default=18)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=8)
-    ap.add_argument("--workload", choices=["rmat", "ba", "grid", "batch", "serve"], default="rmat",
-                    help="rmat: one R-MAT graph (default line); ba: Barabasi-Albert 100k; "
-                         "grid: 32x32 grid in FP64; batch: 4096 graphs in one persistent "
-                         "launch; serve: Poisson stream through the layout server")
+    ap.add_argument("--workload", choices=["rmat", "rmat_pruned", "ba", "grid", "batch", "serve"],
+                    default="rmat",
+                    help="rmat: one R-MAT graph (default line); rmat_pruned: the same graph "
+                         "through pruning, leaf-weighted layout and reinsertion; ba: "
+                         "Barabasi-Albert 100k; grid: 32x32 grid in FP64; batch: 4096 graphs "
+                         "in one persistent launch; serve: Poisson stream through the layout "
+                         "server")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--serve-jobs", type=int, default=400)
     ap.add_argument("--serve-rate", type=float, default=200.0)
@@ -158,6 +162,8 @@ def main() -> int:
         return bench_batch(args)
     if args.workload == "serve":
         return bench_serve(args)
+    if args.workload == "rmat_pruned":
+        return bench_pruned(args, single_graph_workloads(args)["rmat"])
 
     return bench_single(args, single_graph_workloads(args)[args.workload])
 
@@ -287,6 +293,143 @@ def bench_single(args, wl) -> int:
                        f"build once ({cpu_build:.2f} s) + {args.cpu_iters} iterations "
                        f"({cpu_iter * 1e3:.0f} ms each) of the same graph, extrapolated to "
                        f"the {H}-iteration job"),
+        }
+    print(json.dumps(out))
+    return 0
+
+
+def bench_pruned(args, wl) -> int:
+    """The R-MAT workload through the pipeline of Sections 4.3 - 4.6: a step
+    is prune + k-hop build of the pruned graph + leaf weights + all
+    iterations (captured loop) + reinsertion."""
+    import torch
+
+    from paper_1606_02162_amd import gila
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    g = wl["make"]()
+    H, k, prec, d = wl["H"], wl["k"], wl["precision"], wl["d"]
+    rp, ci = gila.to_device_csr(g, dev)
+    pos0 = torch.empty((g.n, 2), dtype=gila.position_dtype(prec), device=dev)
+    gila.init_positions(g.n, wl["seed"], wl["frame"], wl["frame"], prec, pos0)
+    pos = torch.empty_like(pos0)
+    pos_bytes = 16 if prec == gila.FP64 else 8
+
+    P0 = gila.prune(rp, ci)
+    pinfo = P0.info()
+    csr0, _ = P0.graph()
+    g_pr = {"n": csr0.n, "nnz": csr0.nnz}
+    kh0 = gila.KHop.from_csr(csr0, k)
+    kinfo = kh0.info()
+    kh0.free()
+    n_active = kinfo["n_active"]
+    temps = gila.paper_schedule(n_active, 1.0, d, H)
+    params = gila.LayoutParams(temperature=temps, ideal_length=d, precision=prec)
+    kept = torch.empty((pinfo["n_kept"], 2), dtype=pos0.dtype, device=dev)
+    torch.cuda.synchronize()
+
+    def one_step():
+        pos.copy_(pos0)
+        Pr = gila.prune(rp, ci)
+        csr, mass = Pr.graph()
+        kh = gila.KHop.from_csr(csr, k)
+        kh.set_mass(mass)
+        Pr.gather(prec, pos, kept)
+        st = gila.run(kh, params, kept)
+        Pr.reinsert(d, prec, kept, pos)
+        return Pr, kh, st
+
+    for _ in range(args.warmup):
+        Pr, kh, _ = one_step()
+        kh.free()
+        Pr.free()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        Pr, kh, st = one_step()
+        kh.free()
+        Pr.free()
+    torch.cuda.synchronize()
+    total_s = time.perf_counter() - t0
+    assert st.iterations_run == H
+
+    # phases: pruning, reinsertion, weighted and unweighted force kernels
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev[0].record(stream)
+    Pr = gila.prune(rp, ci)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    prune_ms = ev[0].elapsed_time(ev[1])
+    csr, mass = Pr.graph()
+    kh = gila.KHop.from_csr(csr, k)
+    Pr.gather(prec, pos0, kept)
+    plain_ms, _ = gila.time_iterations(kh, params, kept, 0, min(50, H))
+    kh.set_mass(mass)
+    Pr.gather(prec, pos0, kept)
+    force_ms, combine_ms = gila.time_iterations(kh, params, kept, 0, min(50, H))
+    ev[2].record(stream)
+    Pr.reinsert(d, prec, kept, pos)
+    ev[3].record(stream)
+    torch.cuda.synchronize()
+    reinsert_ms = ev[2].elapsed_time(ev[3])
+    P = kinfo["total_pairs"]
+    nnz = g_pr["nnz"]
+    inter_per_iter = P + nnz
+    value = inter_per_iter * H * args.steps / total_s
+    # the weighted kernel also reads one FP32 weight per staged vertex
+    w_bytes = 4 if prec != gila.FP64 else 8
+    kern_bytes = force_kernel_bytes(P, nnz, n_active, pos_bytes) + w_bytes * n_active
+    achieved = kern_bytes / (force_ms * 1e-3) / 1e9
+    prec_name = {gila.FP64: "FP64", gila.FP32: "FP32", gila.FP32_KAHAN: "FP32_KAHAN"}[prec]
+    out = {
+        "metric": "k-hop force interactions/s of the pruned graph (P + 2m per iteration), "
+                  "prune + weighted layout + reinsertion",
+        "value": value, "unit": "interactions/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": total_s / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": wl["dtype"],
+        "data": "synthetic",
+        "config": {"workload": wl["name"](H).replace("rmat", "rmat_pruned", 1), "n": g.n,
+                   "m": g.m, "k": k, "iterations": H, "n_kept": pinfo["n_kept"],
+                   "n_pruned": pinfo["n_pruned"], "m_kept": nnz // 2, "total_pairs": P,
+                   "n_active": n_active},
+        "prune_ms": prune_ms, "reinsert_ms": reinsert_ms,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(TRAFFIC_FILE_PRUNED),
+                     "kernel": f"seg_force_kernel<{prec_name}, weighted>", "kernel_ms": force_ms,
+                     "algorithmic_bytes_per_launch": kern_bytes},
+        "unweighted_force_kernel_ms": plain_ms,
+        "combine_kernel_ms": combine_ms,
+    }
+    kh.free()
+    Pr.free()
+
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = oracle.num_threads()
+        tc0 = time.perf_counter()
+        pr = oracle.prune(g.n, g.row_ptr, g.col_idx)
+        optr, oidx = oracle.khop(pr.n, pr.row_ptr, pr.col_idx, k)
+        tc1 = time.perf_counter()
+        x = pos0.double().cpu().numpy()[pr.new_id >= 0]
+        m = pr.mass()
+        for h in range(args.cpu_iters):
+            x, _, _, _ = oracle.step(pr.n, pr.row_ptr, pr.col_idx, optr, oidx, d, temps[h], x,
+                                     mass=m)
+        tc2 = time.perf_counter()
+        oracle.reinsert(pr, d, x)
+        tc3 = time.perf_counter()
+        cpu_build, cpu_iter = tc1 - tc0, (tc2 - tc1) / args.cpu_iters
+        cpu_job = cpu_build + H * cpu_iter + (tc3 - tc2)
+        out["cpu_baseline"] = {
+            "value": inter_per_iter * H / cpu_job, "unit": "interactions/s", "cores": threads,
+            "kind": "oracle",
+            "sample": (f"FP64 oracle on this host ({_cpu_model()}, {threads} threads): prune + "
+                       f"k-hop build ({cpu_build:.2f} s), {args.cpu_iters} weighted iterations "
+                       f"({cpu_iter * 1e3:.0f} ms each) extrapolated to {H}, reinsertion "
+                       f"({(tc3 - tc2) * 1e3:.0f} ms)"),
         }
     print(json.dumps(out))
     return 0

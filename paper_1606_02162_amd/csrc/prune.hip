@@ -22,10 +22,11 @@
 //                         (fill pass), compacted with ballots
 //   anchor_kernel         thread per kept vertex: weights, leaf counts, the
 //                         list of vertices that have leaves
-//   reinsert_kernel       workgroup per vertex with leaves: edge angles, a
-//                         bitonic sort of their residues (in LDS, or in a
-//                         global scratch slice for very long rows), the widest
-//                         gap, and the leaves' positions
+//   reinsert_*_kernel     workgroup per vertex with leaves: residues of the
+//                         edge angles, the first widest gap between them, and
+//                         the leaves' positions.  Rows of up to 256 edges: one
+//                         wavefront sorts them in LDS; longer rows: 512
+//                         threads bin them into 2 deg buckets (no sort)
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -36,6 +37,7 @@
 struct gila_pruned {
     int device = 0;
     int32_t n = 0, n_kept = 0, n_pruned = 0, n_anchor = 0;
+    int32_t n_class[2] = {0, 0};    // vertices with leaves: short rows, long rows
     int64_t nnz = 0, nnz_kept = 0;
     int64_t max_anchor_deg = 0;     // longest pruned-graph row of a vertex with leaves
     int32_t* anchor = nullptr;      // [n] neighbour a pruned vertex hangs from, -1 if kept
@@ -47,13 +49,18 @@ struct gila_pruned {
     double* mass = nullptr;         // [n_kept] 1 + leaves, pruned ids
     int64_t* leaf_ptr = nullptr;    // [n_kept + 1] leaves of kept vertex i ...
     int32_t* leaf_ids = nullptr;    // [n_pruned] ... in ascending original id
-    int32_t* anchors = nullptr;     // [n_anchor] pruned ids of the vertices with leaves
+    int32_t* anchors = nullptr;     // [n_anchor] pruned ids of the vertices with leaves,
+                                    // grouped by row-length class
     int64_t device_bytes = 0;
 };
 
 namespace gila {
 
-constexpr int kSortLds = 4096;  // residues sorted in LDS (32 KB of doubles)
+// Reinsertion: rows of at most kShortRow edges are sorted in LDS by one
+// wavefront; longer rows are binned (kLongThreads threads per vertex).
+constexpr int kShortRow = 256;
+constexpr int kLongThreads = 512;
+constexpr int kSortClasses = 2;
 
 __global__ __launch_bounds__(kBlock) void prune_mark_kernel(int32_t n, const int64_t* __restrict__ rp,
                                                             const int32_t* __restrict__ ci,
@@ -142,36 +149,47 @@ __global__ __launch_bounds__(kBlock) void kept_rows_kernel(KeptRows a) {
     }
 }
 
+// Weights, leaf counts, and the row-length class of each vertex with leaves
+// (-1 without leaves).
 __global__ __launch_bounds__(kBlock) void anchor_kernel(int32_t n_kept, const int32_t* __restrict__ kept_of,
                                                         const int32_t* __restrict__ leaves,
                                                         const int64_t* __restrict__ krp,
                                                         double* __restrict__ mass,
                                                         int64_t* __restrict__ lcount,
-                                                        int64_t* __restrict__ aflag,
+                                                        int32_t* __restrict__ cls,
                                                         unsigned long long* __restrict__ maxdeg) {
     unsigned long long md = 0;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n_kept;
          i += (int64_t)gridDim.x * kBlock) {
         const int32_t L = leaves[kept_of[i]];
+        const int64_t deg = krp[i + 1] - krp[i];
         mass[i] = 1.0 + (double)L;
         lcount[i] = L;
-        aflag[i] = L > 0 ? 1 : 0;
+        int32_t c = -1;
         if (L > 0) {
-            const unsigned long long d = (unsigned long long)(krp[i + 1] - krp[i]);
-            md = d > md ? d : md;
+            c = deg <= kShortRow ? 0 : 1;
+            md = (unsigned long long)deg > md ? (unsigned long long)deg : md;
         }
+        cls[i] = c;
     }
     md = wave_max(md);
     if (lane64() == 0 && md) atomicMax(maxdeg, md);
 }
 
-__global__ __launch_bounds__(kBlock) void anchor_list_kernel(int32_t n_kept,
-                                                             const int64_t* __restrict__ aflag,
-                                                             const int64_t* __restrict__ ascan,
+__global__ __launch_bounds__(kBlock) void class_flag_kernel(int32_t n_kept, const int32_t* __restrict__ cls,
+                                                            int32_t c, int64_t* __restrict__ flag) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n_kept;
+         i += (int64_t)gridDim.x * kBlock)
+        flag[i] = cls[i] == c ? 1 : 0;
+}
+
+__global__ __launch_bounds__(kBlock) void anchor_list_kernel(int32_t n_kept, const int32_t* __restrict__ cls,
+                                                             int32_t c, const int64_t* __restrict__ scan,
+                                                             int64_t offset,
                                                              int32_t* __restrict__ anchors) {
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n_kept;
          i += (int64_t)gridDim.x * kBlock)
-        if (aflag[i]) anchors[ascan[i]] = (int32_t)i;
+        if (cls[i] == c) anchors[offset + scan[i]] = (int32_t)i;
 }
 
 // ------------------------------------------------------------------ reinsertion
@@ -196,7 +214,7 @@ __global__ __launch_bounds__(kBlock) void gather_kept_kernel(int32_t n_kept,
 }
 
 struct ReinsertArgs {
-    int32_t n_anchor;
+    int32_t n_anchor;          // vertices of `anchors` this launch handles
     const int32_t* anchors;
     const int32_t* kept_of;
     const int32_t* leaves;
@@ -205,128 +223,273 @@ struct ReinsertArgs {
     const int64_t* leaf_ptr;
     const int32_t* leaf_ids;
     double d;
-    double* scratch;           // [2 * nnz_kept] for rows longer than kSortLds (may be null)
+    unsigned long long* buckets;  // [4 * nnz_kept] bucket bounds of the long rows (null if none)
     const void* pos_kept;
     void* pos_all;
 };
 
-// Ascending bitonic sort of x[0, m) (m a power of two) by one workgroup.
-__device__ void block_bitonic_sort(double* x, int64_t m) {
-    for (int64_t k = 2; k <= m; k <<= 1) {
-        for (int64_t j = k >> 1; j > 0; j >>= 1) {
-            for (int64_t i = threadIdx.x; i < m; i += kBlock) {
-                const int64_t p = i ^ j;
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+// Angle of (dx, dy) in [0, 2 pi), reduced modulo the leaf spacing `period`
+// (a zero comes out as +0, so that the bit patterns of residues order as
+// their values).
+__device__ __forceinline__ double angle_residue(double dx, double dy, double period) {
+    double ang = atan2(dy, dx);
+    if (ang < 0.0) ang += kTwoPi;
+    double r = fmod(ang, period);
+    if (r < 0.0) r += period;
+    if (r >= period) r -= period;
+    return r + 0.0;
+}
+
+// Minimum over the workgroup, returned to every thread (sh: THREADS / 64 doubles).
+template <int THREADS>
+__device__ double block_min(double x, double* sh) {
+    for (int off = 32; off >= 1; off >>= 1) {
+        const double o = __shfl_xor(x, off, 64);
+        x = o < x ? o : x;
+    }
+    if (lane64() == 0) sh[wave_id()] = x;
+    __syncthreads();
+    x = sh[0];
+    for (int q = 1; q < THREADS / 64; ++q) x = sh[q] < x ? sh[q] : x;
+    __syncthreads();
+    return x;
+}
+
+// Widest gap over the workgroup: the larger gap wins, equal gaps go to the
+// smaller index.  Every thread receives the winner.
+template <int THREADS>
+__device__ void block_widest(double& g, int64_t& idx, double* sg, int64_t* si) {
+    for (int off = 32; off >= 1; off >>= 1) {
+        const double og = __shfl_xor(g, off, 64);
+        const int64_t oi = __shfl_xor(idx, off, 64);
+        if (og > g || (og == g && oi < idx)) {
+            g = og;
+            idx = oi;
+        }
+    }
+    if (lane64() == 0) {
+        sg[wave_id()] = g;
+        si[wave_id()] = idx;
+    }
+    __syncthreads();
+    g = sg[0];
+    idx = si[0];
+    for (int q = 1; q < THREADS / 64; ++q)
+        if (sg[q] > g || (sg[q] == g && si[q] < idx)) {
+            g = sg[q];
+            idx = si[q];
+        }
+    __syncthreads();
+}
+
+// The L leaves of kept vertex i (at xv, yv), in ascending id, at angles
+// phi + 2 pi j / L on the circle of radius rho.
+template <class V, int THREADS>
+__device__ void place_leaves(const ReinsertArgs& a, int32_t i, int32_t L, double xv, double yv,
+                             double phi, double rho) {
+    V* __restrict__ pa = reinterpret_cast<V*>(a.pos_all);
+    const int64_t lb = a.leaf_ptr[i];
+    for (int32_t j = threadIdx.x; j < L; j += THREADS) {
+        const double th = phi + kTwoPi * (double)j / (double)L;
+        V p;
+        p.x = (decltype(p.x))(xv + rho * cos(th));
+        p.y = (decltype(p.y))(yv + rho * sin(th));
+        pa[a.leaf_ids[lb + j]] = p;
+    }
+}
+
+// Ascending bitonic sort of x[0, m) (m a power of two, in LDS) by one
+// workgroup of THREADS threads.
+template <int THREADS>
+__device__ void block_bitonic_sort(double* x, int m) {
+    for (int k = 2; k <= m; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < m; i += THREADS) {
+                const int p = i ^ j;
                 if (p > i) {
-                    const double a = x[i], b = x[p];
-                    const bool up = (i & k) == 0;
-                    if ((a > b) == up) {
-                        x[i] = b;
-                        x[p] = a;
+                    const double u = x[i], w = x[p];
+                    if ((u > w) == ((i & k) == 0)) {
+                        x[i] = w;
+                        x[p] = u;
                     }
                 }
             }
-            __threadfence_block();
             __syncthreads();
         }
     }
 }
 
+// Rows of at most kShortRow edges: one wavefront per vertex sorts the
+// residues in LDS and scans consecutive pairs (around the circle) for the
+// first widest gap.
 template <class V>
-__global__ __launch_bounds__(kBlock) void reinsert_kernel(ReinsertArgs a) {
-    __shared__ double s_res[kSortLds];
-    __shared__ double s_min[kWaves];
-    __shared__ double s_gap[kWaves];
-    __shared__ int64_t s_idx[kWaves];
-    const double two_pi = 6.283185307179586476925286766559;
+__global__ __launch_bounds__(64) void reinsert_short_kernel(ReinsertArgs a) {
+    __shared__ double s_res[kShortRow];
+    __shared__ double s_g[1];
+    __shared__ int64_t s_i[1];
     const V* __restrict__ pk = reinterpret_cast<const V*>(a.pos_kept);
-    V* __restrict__ pa = reinterpret_cast<V*>(a.pos_all);
-    const int lane = lane64(), w = wave_id();
     for (int64_t t = blockIdx.x; t < a.n_anchor; t += gridDim.x) {
         const int32_t i = a.anchors[t];
         const int32_t L = a.leaves[a.kept_of[i]];
-        const int64_t rb = a.rp[i], deg = a.rp[i + 1] - rb;
+        const int64_t rb = a.rp[i];
+        const int deg = (int)(a.rp[i + 1] - rb);
         const double xv = (double)pk[i].x, yv = (double)pk[i].y;
-        const double period = two_pi / (double)L;
-        int64_t m = 1;
+        const double period = kTwoPi / (double)L;
+        int m = 1;
         while (m < deg) m <<= 1;
-        double* res = deg <= kSortLds ? s_res : a.scratch + 2 * rb;
-        // residues of the incident edges' angles modulo the leaf spacing, and
-        // the shortest incident edge; padding sorts last
         double shortest = INFINITY;
-        for (int64_t e = threadIdx.x; e < m; e += kBlock) {
-            double r = INFINITY;
+        for (int e = threadIdx.x; e < m; e += 64) {
+            double r = INFINITY;  // padding sorts last
             if (e < deg) {
                 const int32_t u = a.ci[rb + e];
                 const double dx = (double)pk[u].x - xv, dy = (double)pk[u].y - yv;
                 const double len = sqrt(dx * dx + dy * dy);
                 shortest = len < shortest ? len : shortest;
-                double ang = atan2(dy, dx);
-                if (ang < 0.0) ang += two_pi;
-                r = fmod(ang, period);
-                if (r < 0.0) r += period;
-                if (r >= period) r -= period;
+                r = angle_residue(dx, dy, period);
             }
-            res[e] = r;
+            s_res[e] = r;
         }
-        for (int off = 32; off >= 1; off >>= 1) {
-            const double o = __shfl_xor(shortest, off, 64);
-            shortest = o < shortest ? o : shortest;
-        }
-        if (lane == 0) s_min[w] = shortest;
-        __threadfence_block();
-        __syncthreads();
-        shortest = s_min[0];
-        for (int q = 1; q < kWaves; ++q) shortest = s_min[q] < shortest ? s_min[q] : shortest;
-        block_bitonic_sort(res, m);
-        // widest gap between consecutive residues (around the circle); ties go
-        // to the smallest index
+        shortest = block_min<64>(shortest, s_g);
+        block_bitonic_sort<64>(s_res, m);
         double best = -1.0;
         int64_t bi = 0;
-        for (int64_t e = threadIdx.x; e < deg; e += kBlock) {
-            const double lo = res[e];
-            const double hi = e + 1 < deg ? res[e + 1] : res[0] + period;
+        for (int e = threadIdx.x; e < deg; e += 64) {
+            const double lo = s_res[e];
+            const double hi = e + 1 < deg ? s_res[e + 1] : s_res[0] + period;
             if (hi - lo > best) {
                 best = hi - lo;
                 bi = e;
             }
         }
-        for (int off = 32; off >= 1; off >>= 1) {
-            const double og = __shfl_xor(best, off, 64);
-            const int64_t oi = __shfl_xor(bi, off, 64);
-            if (og > best || (og == best && oi < bi)) {
-                best = og;
-                bi = oi;
-            }
-        }
-        if (lane == 0) {
-            s_gap[w] = best;
-            s_idx[w] = bi;
-        }
-        __syncthreads();
-        best = s_gap[0];
-        bi = s_idx[0];
-        for (int q = 1; q < kWaves; ++q)
-            if (s_gap[q] > best || (s_gap[q] == best && s_idx[q] < bi)) {
-                best = s_gap[q];
-                bi = s_idx[q];
-            }
+        block_widest<64>(best, bi, s_g, s_i);
         double phi = 0.0;
         if (deg > 0) {
-            const double lo = res[bi];
-            const double hi = bi + 1 < deg ? res[bi + 1] : res[0] + period;
+            const double lo = s_res[bi];
+            const double hi = bi + 1 < deg ? s_res[bi + 1] : s_res[0] + period;
             phi = lo + 0.5 * (hi - lo);
             if (phi >= period) phi -= period;
         }
-        const double rho = 0.2 * (deg > 0 ? shortest : a.d);
-        const int64_t lb = a.leaf_ptr[i];
-        for (int32_t j = threadIdx.x; j < L; j += kBlock) {
-            const double th = phi + two_pi * (double)j / (double)L;
-            V p;
-            p.x = (decltype(p.x))(xv + rho * cos(th));
-            p.y = (decltype(p.y))(yv + rho * sin(th));
-            pa[a.leaf_ids[lb + j]] = p;
+        __syncthreads();  // s_res is reused by the next vertex
+        place_leaves<V, 64>(a, i, L, xv, yv, phi, 0.2 * (deg > 0 ? shortest : a.d));
+    }
+}
+
+__device__ __forceinline__ unsigned long long load_l2(const unsigned long long* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Longer rows, without sorting: the residues are binned into B = 2 deg
+// buckets of width period / B, keeping each bucket's smallest and largest
+// residue.  The widest gap is at least period / deg, more than any two
+// residues of one bucket are apart, so it runs from the largest residue of a
+// non-empty bucket to the smallest of the next non-empty bucket (cyclically);
+// scanning non-empty buckets in ascending order finds the same first widest
+// gap, with the same end points, as a scan of the sorted residues.  Residues
+// are non-negative, so their IEEE bit patterns order as the values do and the
+// bucket bounds are kept with 64-bit integer atomics (performed in L2; read
+// back with loads that bypass the L1 cache).
+template <class V>
+__global__ __launch_bounds__(kLongThreads) void reinsert_long_kernel(ReinsertArgs a) {
+    constexpr int T = kLongThreads;
+    __shared__ double s_g[T / 64];
+    __shared__ int64_t s_i[T / 64];
+    __shared__ int64_t s_next[T];  // first non-empty bucket at or after each thread's chunk
+    __shared__ double s_lohi[2];
+    constexpr int64_t kNone = INT64_MAX;
+    const V* __restrict__ pk = reinterpret_cast<const V*>(a.pos_kept);
+    for (int64_t t = blockIdx.x; t < a.n_anchor; t += gridDim.x) {
+        const int32_t i = a.anchors[t];
+        const int32_t L = a.leaves[a.kept_of[i]];
+        const int64_t rb = a.rp[i], deg = a.rp[i + 1] - rb;
+        const double xv = (double)pk[i].x, yv = (double)pk[i].y;
+        const double period = kTwoPi / (double)L;
+        const int64_t B = 2 * deg;
+        unsigned long long* bmin = a.buckets + 4 * rb;
+        unsigned long long* bmax = bmin + B;
+        for (int64_t b = threadIdx.x; b < B; b += T) {
+            bmin[b] = ~0ull;
+            bmax[b] = 0ull;
         }
-        __syncthreads();  // LDS is reused by the next vertex
+        __builtin_amdgcn_s_waitcnt(0);  // the stores have reached L2
+        __syncthreads();
+        const double scale = (double)B / period;
+        double shortest = INFINITY;
+        for (int64_t e = threadIdx.x; e < deg; e += T) {
+            const int32_t u = a.ci[rb + e];
+            const double dx = (double)pk[u].x - xv, dy = (double)pk[u].y - yv;
+            const double len = sqrt(dx * dx + dy * dy);
+            shortest = len < shortest ? len : shortest;
+            const double r = angle_residue(dx, dy, period);
+            const double q = r * scale;
+            int64_t b = q >= 0.0 ? (int64_t)q : 0;  // (a NaN position lands in bucket 0)
+            b = b < B ? b : B - 1;
+            const unsigned long long bits = (unsigned long long)__double_as_longlong(r);
+            atomicMin(&bmin[b], bits);
+            atomicMax(&bmax[b], bits);
+        }
+        __builtin_amdgcn_s_waitcnt(0);  // the atomics are done
+        shortest = block_min<T>(shortest, s_g);
+        // first non-empty bucket of each thread's chunk, then a suffix minimum
+        const int64_t C = (B + T - 1) / T;
+        const int64_t c0 = (int64_t)threadIdx.x * C, c1 = c0 + C < B ? c0 + C : B;
+        int64_t first = kNone;
+        for (int64_t b = c0; b < c1 && first == kNone; ++b)
+            if (load_l2(&bmin[b]) <= load_l2(&bmax[b])) first = b;
+        s_next[threadIdx.x] = first;
+        __syncthreads();
+        for (int off = 1; off < T; off <<= 1) {
+            int64_t v = s_next[threadIdx.x];
+            if (threadIdx.x + off < T) {
+                const int64_t o = s_next[threadIdx.x + off];
+                v = o < v ? o : v;
+            }
+            __syncthreads();
+            s_next[threadIdx.x] = v;
+            __syncthreads();
+        }
+        const int64_t first_all = s_next[0];
+        const int64_t after = threadIdx.x + 1 < T ? s_next[threadIdx.x + 1] : kNone;
+        // gaps that start in this chunk, in ascending order
+        double best = -1.0, blo = 0.0, bhi = 0.0;
+        int64_t bi = kNone;
+        int64_t prev = kNone;
+        double prev_max = 0.0;
+        auto consider = [&](int64_t from, double lo, double hi) {
+            if (hi - lo > best) {
+                best = hi - lo;
+                bi = from;
+                blo = lo;
+                bhi = hi;
+            }
+        };
+        for (int64_t b = c0; b < c1; ++b) {
+            const unsigned long long mn = load_l2(&bmin[b]), mx = load_l2(&bmax[b]);
+            if (mn > mx) continue;  // empty
+            if (prev != kNone) consider(prev, prev_max, __longlong_as_double((long long)mn));
+            prev = b;
+            prev_max = __longlong_as_double((long long)mx);
+        }
+        if (prev != kNone) {
+            const double hi = after != kNone
+                                  ? __longlong_as_double((long long)load_l2(&bmin[after]))
+                                  : __longlong_as_double((long long)load_l2(&bmin[first_all])) + period;
+            consider(prev, prev_max, hi);
+        }
+        int64_t win = bi;
+        double wg = best;
+        block_widest<T>(wg, win, s_g, s_i);
+        if (bi == win && bi != kNone) {
+            s_lohi[0] = blo;
+            s_lohi[1] = bhi;
+        }
+        __syncthreads();
+        const double lo = s_lohi[0], hi = s_lohi[1];
+        double phi = lo + 0.5 * (hi - lo);
+        if (phi >= period) phi -= period;
+        __syncthreads();  // s_next and s_lohi are reused by the next vertex
+        place_leaves<V, T>(a, i, L, xv, yv, phi, 0.2 * shortest);
     }
 }
 
@@ -429,7 +592,8 @@ static int prune(const gila_csr* g, hipStream_t s, gila_pruned** out) {
     kr.new_id = p->new_id;
     kr.kept_of = p->kept_of;
     const int rgrid = (int)std::max<int64_t>(1, std::min<int64_t>(16384, ((int64_t)n_kept + kWaves - 1) / kWaves));
-    int64_t sizes[3] = {0, 0, 0};  // nnz_kept, anchors, max anchor degree
+    int64_t sizes[2] = {0, 0};  // nnz_kept, longest row of a vertex with leaves
+    int64_t csizes[kSortClasses] = {0, 0};  // vertices with leaves per class
     if (n > 0) {
         hipLaunchKernelGGL(kept_kernel, dim3(grid_of(n)), dim3(kBlock), 0, s, n, p->anchor,
                            scan.as<int64_t>(), p->new_id, p->kept_of);
@@ -438,29 +602,45 @@ static int prune(const gila_csr* g, hipStream_t s, gila_pruned** out) {
         hipLaunchKernelGGL(kept_rows_kernel<false>, dim3(rgrid), dim3(kBlock), 0, s, kr);
         GILA_HIP(hipGetLastError());
         GILA_TRY(enqueue_exclusive_scan_i64(kr.kdeg, p->rp, n_kept, wsp.as<int64_t>(), s));
-        // weights, leaf counts -> leaf offsets, vertices with leaves -> list
+        // weights, leaf counts -> leaf offsets, vertices with leaves -> one
+        // list grouped by row-length class
         int64_t* lcount = flag.as<int64_t>();
-        int64_t* aflag = scan.as<int64_t>();
-        Tmp ascan(s);
-        GILA_TRY(ascan.alloc<int64_t>((size_t)n_kept + 1));
+        int64_t* cflag = scan.as<int64_t>();
+        Tmp cls(s), cscan(s);
+        GILA_TRY(cls.alloc<int32_t>((size_t)n_kept + 1));
+        GILA_TRY(cscan.alloc<int64_t>(((size_t)n_kept + 1) * kSortClasses));
         hipLaunchKernelGGL(anchor_kernel, dim3(grid_of(n_kept)), dim3(kBlock), 0, s, n_kept,
-                           p->kept_of, p->leaves, p->rp, p->mass, lcount, aflag,
+                           p->kept_of, p->leaves, p->rp, p->mass, lcount, cls.as<int32_t>(),
                            (unsigned long long*)d_small);
         GILA_HIP(hipGetLastError());
         GILA_TRY(enqueue_exclusive_scan_i64(lcount, p->leaf_ptr, n_kept, wsp.as<int64_t>(), s));
-        GILA_TRY(enqueue_exclusive_scan_i64(aflag, ascan.as<int64_t>(), n_kept, wsp.as<int64_t>(), s));
+        for (int c = 0; c < kSortClasses; ++c) {
+            int64_t* cs = cscan.as<int64_t>() + (size_t)c * (n_kept + 1);
+            hipLaunchKernelGGL(class_flag_kernel, dim3(grid_of(n_kept)), dim3(kBlock), 0, s, n_kept,
+                               cls.as<int32_t>(), c, cflag);
+            GILA_HIP(hipGetLastError());
+            GILA_TRY(enqueue_exclusive_scan_i64(cflag, cs, n_kept, wsp.as<int64_t>(), s));
+            GILA_HIP(hipMemcpyAsync(&csizes[c], cs + n_kept, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        }
         GILA_HIP(hipMemcpyAsync(&sizes[0], p->rp + n_kept, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-        GILA_HIP(hipMemcpyAsync(&sizes[1], ascan.as<int64_t>() + n_kept, sizeof(int64_t),
-                                hipMemcpyDeviceToHost, s));
-        GILA_HIP(hipMemcpyAsync(&sizes[2], d_small, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        GILA_HIP(hipMemcpyAsync(&sizes[1], d_small, sizeof(int64_t), hipMemcpyDeviceToHost, s));
         GILA_HIP(hipStreamSynchronize(s));
         p->nnz_kept = sizes[0];
-        p->n_anchor = (int32_t)sizes[1];
-        p->max_anchor_deg = sizes[2];
+        p->max_anchor_deg = sizes[1];
+        p->n_anchor = 0;
+        for (int c = 0; c < kSortClasses; ++c) {
+            p->n_class[c] = (int32_t)csizes[c];
+            p->n_anchor += p->n_class[c];
+        }
         GILA_TRY(dalloc_t(&p->ci, (size_t)p->nnz_kept));
         GILA_TRY(dalloc_t(&p->anchors, (size_t)p->n_anchor));
-        hipLaunchKernelGGL(anchor_list_kernel, dim3(grid_of(n_kept)), dim3(kBlock), 0, s, n_kept,
-                           aflag, ascan.as<int64_t>(), p->anchors);
+        int64_t off = 0;
+        for (int c = 0; c < kSortClasses; ++c) {
+            hipLaunchKernelGGL(anchor_list_kernel, dim3(grid_of(n_kept)), dim3(kBlock), 0, s, n_kept,
+                               cls.as<int32_t>(), c, cscan.as<int64_t>() + (size_t)c * (n_kept + 1),
+                               off, p->anchors);
+            off += csizes[c];
+        }
         kr.krp = p->rp;
         kr.kci = p->ci;
         kr.leaf_ptr = p->leaf_ptr;
@@ -503,9 +683,8 @@ static int reinsert(const gila_pruned* p, double d, int32_t precision, const voi
     GILA_HIP(hipGetLastError());
     if (p->n_anchor == 0) return GILA_OK;
     Tmp scratch(s);
-    if (p->max_anchor_deg > kSortLds) GILA_TRY(scratch.alloc<double>(2 * (size_t)p->nnz_kept));
+    if (p->n_class[1] > 0) GILA_TRY(scratch.alloc<unsigned long long>(4 * (size_t)p->nnz_kept));
     ReinsertArgs a{};
-    a.n_anchor = p->n_anchor;
     a.anchors = p->anchors;
     a.kept_of = p->kept_of;
     a.leaves = p->leaves;
@@ -514,13 +693,24 @@ static int reinsert(const gila_pruned* p, double d, int32_t precision, const voi
     a.leaf_ptr = p->leaf_ptr;
     a.leaf_ids = p->leaf_ids;
     a.d = d;
-    a.scratch = scratch.as<double>();
+    a.buckets = scratch.as<unsigned long long>();
     a.pos_kept = pos_kept;
     a.pos_all = pos_all;
-    const int grid = (int)std::min<int64_t>(65536, p->n_anchor);
-    if (f64) hipLaunchKernelGGL(reinsert_kernel<double2>, dim3(grid), dim3(kBlock), 0, s, a);
-    else hipLaunchKernelGGL(reinsert_kernel<float2>, dim3(grid), dim3(kBlock), 0, s, a);
-    GILA_HIP(hipGetLastError());
+    a.n_anchor = p->n_class[0];
+    if (a.n_anchor > 0) {
+        const dim3 grid((unsigned)std::min<int64_t>(65536, a.n_anchor));
+        if (f64) hipLaunchKernelGGL(reinsert_short_kernel<double2>, grid, dim3(64), 0, s, a);
+        else hipLaunchKernelGGL(reinsert_short_kernel<float2>, grid, dim3(64), 0, s, a);
+        GILA_HIP(hipGetLastError());
+    }
+    a.anchors += a.n_anchor;
+    a.n_anchor = p->n_class[1];
+    if (a.n_anchor > 0) {
+        const dim3 grid((unsigned)std::min<int64_t>(65536, a.n_anchor));
+        if (f64) hipLaunchKernelGGL(reinsert_long_kernel<double2>, grid, dim3(kLongThreads), 0, s, a);
+        else hipLaunchKernelGGL(reinsert_long_kernel<float2>, grid, dim3(kLongThreads), 0, s, a);
+        GILA_HIP(hipGetLastError());
+    }
     return GILA_OK;
 }
 

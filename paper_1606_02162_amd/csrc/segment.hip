@@ -49,6 +49,24 @@ constexpr int kSegTailPad = 64;    // slack entries after the k-hop offsets
 constexpr int kMaxSegments = 16384;  // segment counters of the build fit in 64 KB of LDS
 constexpr int kLongRow = 16;       // rows longer than kLongRow * nseg: binary search per segment
 constexpr int kFillLanes = 16;     // lanes per slice in the fill pass
+// Weighted repulsion: a segment holds at most kWeightBase bytes of positions
+// (2730 FP32 or 1365 FP64 ones), and its weights (half a position each) go to
+// a static LDS array, whose address is a constant the compiler folds into
+// the LDS instruction (the weight address is then o / 2 plus that constant).
+// Positions and weights together stay within 32 KB.
+constexpr int kWeightBase = 21840;
+
+template <bool WEIGHTED>
+struct WeightLds {
+    __device__ static unsigned char* get() { return nullptr; }
+};
+template <>
+struct WeightLds<true> {
+    __device__ static unsigned char* get() {
+        __shared__ __align__(16) unsigned char w[kWeightBase / 2];
+        return w;
+    }
+};
 
 bool segment_path_enabled() {
     const char* e = getenv("GILA_PATH");
@@ -367,12 +385,12 @@ __device__ __forceinline__ void quad_terms(uint2 w, const unsigned char* __restr
 template <class P, int LPV, bool WEIGHTED>
 __device__ __forceinline__ void seg_slices(const SegArgs& a, int ib, int ie,
                                            const typename P::vec2* __restrict__ lp,
-                                           int* s_next, int& coinc) {
+                                           const unsigned char* __restrict__ lw, int* s_next,
+                                           int& coinc) {
     using R = typename P::real;
     using V = typename P::vec2;
     const V* __restrict__ gpos = reinterpret_cast<const V*>(a.pos);
     const unsigned char* __restrict__ lds = reinterpret_cast<const unsigned char*>(lp);
-    const unsigned char* __restrict__ lw = lds + (size_t)(a.seg + 1) * sizeof(V);
     const double d2 = a.d * a.d;
     // attraction (x_u - x_v) delta / d enters the same sum divided by d^2
     const R dpar = sizeof(R) == 4 ? (R)(1.0 / (a.d * d2)) : (R)(a.d * d2);
@@ -431,7 +449,7 @@ __device__ __forceinline__ void seg_slices(const SegArgs& a, int ib, int ie,
 
 // FP32: eight waves per SIMD (the LDS of four workgroups per CU allows it);
 // FP64 needs more registers.  WEIGHTED stages each vertex's repulsion weight
-// after the positions (slot S of both holds the sentinel).
+// in a static LDS array (slot S of positions and weights holds the sentinel).
 template <int PREC, bool WEIGHTED>
 __global__ __launch_bounds__(kSegBlock, PREC == GILA_FP64 ? 4 : kSegWaves) void seg_force_kernel(SegArgs a) {
     using P = Prec<PREC>;
@@ -449,7 +467,7 @@ __global__ __launch_bounds__(kSegBlock, PREC == GILA_FP64 ? 4 : kSegWaves) void 
     const int cnt = (int)(left < a.seg ? left : a.seg);
     for (int i = threadIdx.x; i < cnt; i += kSegBlock) lp[i] = gpos[base + i];
     using R = typename P::real;
-    R* lw = reinterpret_cast<R*>(s_raw + (size_t)(a.seg + 1) * sizeof(V));
+    R* lw = reinterpret_cast<R*>(WeightLds<WEIGHTED>::get());
     if constexpr (WEIGHTED) {
         const R* gw = reinterpret_cast<const R*>(a.mass);
         for (int i = threadIdx.x; i < cnt; i += kSegBlock) lw[i] = gw[base + i];
@@ -465,14 +483,15 @@ __global__ __launch_bounds__(kSegBlock, PREC == GILA_FP64 ? 4 : kSegWaves) void 
     }
     __syncthreads();
     int coinc = 0;
+    const unsigned char* wb = reinterpret_cast<const unsigned char*>(lw);
     switch (lpv) {
-        case 1: seg_slices<P, 1, WEIGHTED>(a, ib, ie, lp, &s_next, coinc); break;
-        case 2: seg_slices<P, 2, WEIGHTED>(a, ib, ie, lp, &s_next, coinc); break;
-        case 4: seg_slices<P, 4, WEIGHTED>(a, ib, ie, lp, &s_next, coinc); break;
-        case 8: seg_slices<P, 8, WEIGHTED>(a, ib, ie, lp, &s_next, coinc); break;
-        case 16: seg_slices<P, 16, WEIGHTED>(a, ib, ie, lp, &s_next, coinc); break;
-        case 32: seg_slices<P, 32, WEIGHTED>(a, ib, ie, lp, &s_next, coinc); break;
-        default: seg_slices<P, 64, WEIGHTED>(a, ib, ie, lp, &s_next, coinc); break;
+        case 1: seg_slices<P, 1, WEIGHTED>(a, ib, ie, lp, wb, &s_next, coinc); break;
+        case 2: seg_slices<P, 2, WEIGHTED>(a, ib, ie, lp, wb, &s_next, coinc); break;
+        case 4: seg_slices<P, 4, WEIGHTED>(a, ib, ie, lp, wb, &s_next, coinc); break;
+        case 8: seg_slices<P, 8, WEIGHTED>(a, ib, ie, lp, wb, &s_next, coinc); break;
+        case 16: seg_slices<P, 16, WEIGHTED>(a, ib, ie, lp, wb, &s_next, coinc); break;
+        case 32: seg_slices<P, 32, WEIGHTED>(a, ib, ie, lp, wb, &s_next, coinc); break;
+        default: seg_slices<P, 64, WEIGHTED>(a, ib, ie, lp, wb, &s_next, coinc); break;
     }
     const int64_t wc = wave_sum((int64_t)coinc);
     if (lane64() == 0) s_c[wave_id()] = wc;
@@ -544,7 +563,15 @@ int seg_size_for(const gila_khop* kh, int precision) {
     const int64_t want = std::min<int64_t>(env_int("GILA_SEG_BYTES", 32768), lds_cap);
     int S = (int)(want / slot_bytes(kh, precision)) - 1;  // one slot for the sentinel
     S = std::min(S, 65535 / pos_bytes - 1);  // byte offsets, sentinel included, fit in 16 bits
+    if (kh->mass64) S = std::min(S, kWeightBase / pos_bytes - 1);  // positions below the weights
     return std::max(64, S);
+}
+
+// Dynamic LDS of the force kernel for segment size S (the positions; the
+// weights of the weighted kernel are in static LDS).
+static size_t seg_lds_bytes(const gila_khop* kh, int precision, int S) {
+    (void)kh;
+    return (size_t)(S + 1) * pos_bytes_of(precision);
 }
 
 bool segment_ready_for(const gila_khop* kh, int precision) {
@@ -765,7 +792,7 @@ int build_segments(gila_khop* kh, int precision, hipStream_t st) {
                        dim3(kBlock), 0, st, (int32_t)plan.size(), slice_cost,
                        (int64_t)env_int("GILA_SEG_QPL", 8), starts, kh->sl_k, kh->sl_a, kh->seg_wg);
     GILA_HIP(hipGetLastError());
-    const size_t lds = (size_t)(S + 1) * slot_bytes(kh, precision);
+    const size_t lds = seg_lds_bytes(kh, precision, S);
     if (lds > 48 * 1024) {
         const void* kernels[] = {(const void*)seg_force_kernel<GILA_FP64, false>,
                                  (const void*)seg_force_kernel<GILA_FP32, false>,
@@ -812,7 +839,7 @@ int launch_segment_step(const gila_khop* kh, int precision, const StepArgs& a, h
         return fail(GILA_EINVAL, "unknown precision %d", precision);
     if ((a.mass != nullptr) != kh->seg_weighted)
         return fail(GILA_EINVAL, "segment layout built for other repulsion weights");
-    const size_t lds = (size_t)(kh->seg + 1) * slot_bytes(kh, precision);
+    const size_t lds = seg_lds_bytes(kh, precision, kh->seg);
     const dim3 sg(kh->seg_grid), sb(kSegBlock), cg(kh->comb_grid), cb(kBlock);
     if (ev) GILA_HIP(hipEventRecord(ev[0], s));
     if (a.mass) {

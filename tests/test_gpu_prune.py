@@ -52,7 +52,9 @@ def prune_suite():
         inputs.barabasi_albert(3000, 2, seed=2),
         inputs.rmat(12, 4, 0.57, 0.19, 0.19, seed=3),
         inputs.grid_graph(16, 16),                        # nothing to prune
-        _wheel(5000, 7),                                  # a row longer than the LDS sort
+        _wheel(1000, 4),                                  # a row for the 256-thread sort
+        _wheel(5000, 7),                                  # a long row: the 1024-thread sort
+        _wheel(17000, 3),                                 # longer still: sorted in HBM
     ]
 
 
