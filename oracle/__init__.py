@@ -12,7 +12,8 @@ module compiles it with gcc and wraps it with ctypes and numpy.
 Passages followed (Arleo, Didimo, Liotta, Montecchiani, "A Distributed
 Force-Directed Algorithm on Giraph: Design and Experiments"):
   * Section 3.1, force equation and magnitudes ||f^a|| = delta^p/d,
-    ||f^r|| = d^2/delta^q with p = 2, q = 1;
+    ||f^r|| = d^2/delta^q (FR: p = 2, q = 1; the LinLog model of Section 6:
+    p = 0, q = 1);
   * Section 4.5, the k-neighbourhood N_v(k), adjacent vertices receiving both
     forces, and the synchronous coordinate update;
   * Section 5.1, the cap schedule sqrt((n/a) d) 0.93^h and the halting rule;
@@ -65,14 +66,16 @@ def _load():
                                    vp, _i64p]
     lib.orc_khop_fill.argtypes = [ctypes.c_int32, _i64p, _i32p, ctypes.c_int32, ctypes.c_int64,
                                   vp, _i64p, _i32p]
+    i32 = ctypes.c_int32
     lib.orc_forces.argtypes = [ctypes.c_int32, _i64p, _i32p, ctypes.c_int64, vp, _i64p, _i32p,
-                               ctypes.c_double, vp, _f64p, _f64p, ctypes.POINTER(ctypes.c_int64)]
+                               ctypes.c_double, vp, i32, i32, _f64p, _f64p,
+                               ctypes.POINTER(ctypes.c_int64)]
     lib.orc_cap.argtypes = [ctypes.c_int64, _f64p, ctypes.c_double, _f64p]
     lib.orc_step.argtypes = [ctypes.c_int32, _i64p, _i32p, _i64p, _i32p, ctypes.c_double, vp,
-                             ctypes.c_double, ctypes.c_double, _f64p, _f64p, _f64p,
+                             i32, i32, ctypes.c_double, ctypes.c_double, _f64p, _f64p, _f64p,
                              ctypes.POINTER(_IterStats)]
     lib.orc_layout.argtypes = [ctypes.c_int32, _i64p, _i32p, _i64p, _i32p, ctypes.c_double,
-                               vp, _f64p, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                               vp, i32, i32, _f64p, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                                ctypes.c_double, _f64p, ctypes.POINTER(ctypes.c_int32),
                                ctypes.POINTER(_IterStats)]
     lib.orc_paper_schedule.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double,
@@ -143,13 +146,15 @@ def khop(n: int, row_ptr, col_idx, k: int, verts=None):
     return ptr, idx[: int(ptr[-1])]
 
 
-def forces(n: int, row_ptr, col_idx, kptr, kidx, d: float, pos, verts=None, mass=None):
+def forces(n: int, row_ptr, col_idx, kptr, kidx, d: float, pos, verts=None, mass=None,
+           p: int = 2, q: int = 1):
     """F_v for verts (Section 3.1 with N_v(k) repulsion, Section 4.5).
 
     ``kptr``/``kidx`` hold the rows of exactly the vertices in ``verts``
     (all vertices when verts is None).  ``pos`` is float64[n, 2].  ``mass``
     (float64[n], optional) scales the repulsion each vertex exerts
-    (Section 4.6: 1 + its pruned leaves).
+    (Section 4.6: 1 + its pruned leaves).  ``p``, ``q``: force exponents,
+    ||f^a|| = delta^p / d and ||f^r|| = d^2 / delta^q (FR: 2, 1; LinLog: 0, 1).
     Returns (F float64[count, 2], coincident pair count).
     """
     lib = _load()
@@ -157,15 +162,15 @@ def forces(n: int, row_ptr, col_idx, kptr, kidx, d: float, pos, verts=None, mass
     marr, mptr = _mass(mass, n)
     varr, vptr = _verts(verts)
     count = n if varr is None else varr.size
-    p = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1)
+    pos_ = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1)
     kp = np.ascontiguousarray(kptr, dtype=np.int64)
     ki = np.ascontiguousarray(kidx, dtype=np.int32)
     if ki.size == 0:
         ki = np.zeros(1, dtype=np.int32)
     F = np.zeros(2 * max(count, 1), dtype=np.float64)
     coinc = ctypes.c_int64(0)
-    _check(lib.orc_forces(n, rp, ci, count, vptr, kp, ki, float(d), mptr, p, F,
-                          ctypes.byref(coinc)), "forces")
+    _check(lib.orc_forces(n, rp, ci, count, vptr, kp, ki, float(d), mptr, int(p), int(q), pos_,
+                          F, ctypes.byref(coinc)), "forces")
     return F[: 2 * count].reshape(count, 2), int(coinc.value)
 
 
@@ -187,12 +192,12 @@ class StepStats:
 
 
 def step(n: int, row_ptr, col_idx, kptr, kidx, d: float, t: float, pos,
-         stop_displacement: float = 0.01, mass=None):
+         stop_displacement: float = 0.01, mass=None, p: int = 2, q: int = 1):
     """One synchronous iteration.  Returns (new_pos, F, Delta, StepStats)."""
     lib = _load()
     rp, ci = _csr(row_ptr, col_idx)
     marr, mptr = _mass(mass, n)
-    p = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1).copy()
+    x = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1).copy()
     kp = np.ascontiguousarray(kptr, dtype=np.int64)
     ki = np.ascontiguousarray(kidx, dtype=np.int32)
     if ki.size == 0:
@@ -200,15 +205,15 @@ def step(n: int, row_ptr, col_idx, kptr, kidx, d: float, t: float, pos,
     F = np.zeros(2 * max(n, 1), dtype=np.float64)
     D = np.zeros(2 * max(n, 1), dtype=np.float64)
     st = _IterStats()
-    _check(lib.orc_step(n, rp, ci, kp, ki, float(d), mptr, float(t), float(stop_displacement),
-                        p, F, D, ctypes.byref(st)), "step")
-    return (p.reshape(-1, 2), F[: 2 * n].reshape(-1, 2), D[: 2 * n].reshape(-1, 2),
+    _check(lib.orc_step(n, rp, ci, kp, ki, float(d), mptr, int(p), int(q), float(t),
+                        float(stop_displacement), x, F, D, ctypes.byref(st)), "step")
+    return (x.reshape(-1, 2), F[: 2 * n].reshape(-1, 2), D[: 2 * n].reshape(-1, 2),
             StepStats(int(st.moved), float(st.max_disp), float(st.energy), int(st.coincident)))
 
 
 def layout(n: int, row_ptr, col_idx, kptr, kidx, d: float, temperature, pos,
            h0: int = 0, h_end: int | None = None, stop_fraction: float = 0.0,
-           stop_displacement: float = 0.01, mass=None):
+           stop_displacement: float = 0.01, mass=None, p: int = 2, q: int = 1):
     """Iterations h0 .. h_end-1.  Returns (pos, iterations_run, StepStats)."""
     lib = _load()
     rp, ci = _csr(row_ptr, col_idx)
@@ -218,7 +223,7 @@ def layout(n: int, row_ptr, col_idx, kptr, kidx, d: float, temperature, pos,
         h_end = temps.size
     if h_end > temps.size:
         raise ValueError("temperature schedule shorter than h_end")
-    p = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1).copy()
+    x = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1).copy()
     kp = np.ascontiguousarray(kptr, dtype=np.int64)
     ki = np.ascontiguousarray(kidx, dtype=np.int32)
     if ki.size == 0:
@@ -227,10 +232,10 @@ def layout(n: int, row_ptr, col_idx, kptr, kidx, d: float, temperature, pos,
         temps = np.zeros(1)
     run = ctypes.c_int32(0)
     st = _IterStats()
-    _check(lib.orc_layout(n, rp, ci, kp, ki, float(d), mptr, temps, int(h0), int(h_end),
-                          float(stop_fraction), float(stop_displacement), p, ctypes.byref(run),
-                          ctypes.byref(st)), "layout")
-    return (p.reshape(-1, 2), int(run.value),
+    _check(lib.orc_layout(n, rp, ci, kp, ki, float(d), mptr, int(p), int(q), temps, int(h0),
+                          int(h_end), float(stop_fraction), float(stop_displacement), x,
+                          ctypes.byref(run), ctypes.byref(st)), "layout")
+    return (x.reshape(-1, 2), int(run.value),
             StepStats(int(st.moved), float(st.max_disp), float(st.energy), int(st.coincident)))
 
 

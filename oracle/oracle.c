@@ -16,9 +16,11 @@
  *   - F_v = sum over adjacent u of the attractive force plus sum over
  *     u in N_v(k) of the repulsive force (Section 3.1 force equation with the
  *     repulsion sum restricted to N_v(k) by Section 4.5).  Magnitudes
- *     ||f^a|| = delta^p / d and ||f^r|| = d^2 / delta^q with p = 2, q = 1
- *     (Section 3.1).  Attraction points from v towards u, repulsion away from
- *     u.  Adjacent vertices contribute both (Section 4.5, second superstep).
+ *     ||f^a|| = delta^p / d and ||f^r|| = d^2 / delta^q (Section 3.1): FR's
+ *     p = 2, q = 1 by default, any non-negative integers otherwise (the
+ *     LinLog model of Section 6 is p = 0, q = 1).  Attraction points from v
+ *     towards u, repulsion away from u.  Adjacent vertices contribute both
+ *     (Section 4.5, second superstep).  Coincident ends exert no force.
  *   - Displacement capped by the temperature t_h, all vertices moved together
  *     once every force of the iteration is known (Section 3.1; Section 4.5,
  *     coordinates updated when no message is left).
@@ -159,28 +161,38 @@ int orc_khop_fill(int32_t n, const int64_t* row_ptr, const int32_t* col_idx, int
 }
 
 /* ------------------------------------------------------------------ */
-/* Forces (Section 3.1 with p = 2, q = 1; Section 4.5 locality)       */
+/* Forces (Section 3.1, exponents p and q; Section 4.5 locality)      */
 /* ------------------------------------------------------------------ */
 
 /* One vertex: F_v = attraction over adj(v) + repulsion over N_v(k).
- * pos is interleaved (x, y).  Returns the number of coincident pairs. */
+ * pos is interleaved (x, y).  Returns the number of coincident pairs.  The
+ * p = 2 and q = 1 branches are the general expressions with the powers
+ * cancelled by hand (no root, no pow). */
 static int64_t force_one(int32_t v, const int64_t* row_ptr, const int32_t* col_idx,
                          const int32_t* krow, int64_t klen, double d, const double* mass,
-                         const double* pos, double* fx_out, double* fy_out) {
+                         int32_t p, int32_t q, const double* pos, double* fx_out,
+                         double* fy_out) {
     const double xv = pos[2 * (int64_t)v], yv = pos[2 * (int64_t)v + 1];
     double ax = 0.0, ay = 0.0, rx = 0.0, ry = 0.0;
     int64_t coincident = 0;
-    /* attraction: ||f^a|| = delta^2 / d, pointing from v towards u */
+    /* attraction: ||f^a|| = delta^p / d, pointing from v towards u */
     for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
         int32_t u = col_idx[e];
         double dx = pos[2 * (int64_t)u] - xv;
         double dy = pos[2 * (int64_t)u + 1] - yv;
         double delta = sqrt(dx * dx + dy * dy);
-        /* unit vector (dx, dy) / delta times delta^2 / d */
-        ax += dx * (delta / d);
-        ay += dy * (delta / d);
+        if (p == 2) {
+            /* unit vector (dx, dy) / delta times delta^2 / d */
+            ax += dx * (delta / d);
+            ay += dy * (delta / d);
+        } else if (delta > 0.0) {
+            /* unit vector times delta^p / d; coincident ends exert nothing */
+            const double mag = pow(delta, (double)p) / d;
+            ax += (dx / delta) * mag;
+            ay += (dy / delta) * mag;
+        }
     }
-    /* repulsion: ||f^r|| = d^2 / delta, pointing from u towards v */
+    /* repulsion: ||f^r|| = d^2 / delta^q, pointing from u towards v */
     for (int64_t i = 0; i < klen; ++i) {
         int32_t u = krow[i];
         double dx = xv - pos[2 * (int64_t)u];
@@ -190,11 +202,19 @@ static int64_t force_one(int32_t v, const int64_t* row_ptr, const int32_t* col_i
             ++coincident;
             continue;
         }
-        /* unit vector (dx, dy) / delta times d^2 / delta, weighted by the
-         * leaves pruned from u (Section 4.6) when masses are given */
+        /* weighted by the leaves pruned from u (Section 4.6) when masses
+         * are given */
         const double w = mass ? mass[u] : 1.0;
-        rx += dx * (w * (d * d / dd));
-        ry += dy * (w * (d * d / dd));
+        if (q == 1) {
+            /* unit vector (dx, dy) / delta times d^2 / delta */
+            rx += dx * (w * (d * d / dd));
+            ry += dy * (w * (d * d / dd));
+        } else {
+            const double delta = sqrt(dd);
+            const double mag = d * d / pow(delta, (double)q);
+            rx += (dx / delta) * (w * mag);
+            ry += (dy / delta) * (w * mag);
+        }
     }
     *fx_out = ax + rx;
     *fy_out = ay + ry;
@@ -206,16 +226,16 @@ static int64_t force_one(int32_t v, const int64_t* row_ptr, const int32_t* col_i
  * verts, so a sampled subset carries only its own rows.  F is [count][2]. */
 int orc_forces(int32_t n, const int64_t* row_ptr, const int32_t* col_idx,
                int64_t count, const int32_t* verts, const int64_t* kptr,
-               const int32_t* kidx, double d, const double* mass, const double* pos, double* F,
-               int64_t* coincident_out) {
-    if (n < 0 || !(d > 0.0)) return ORC_EINVAL;
+               const int32_t* kidx, double d, const double* mass, int32_t p, int32_t q,
+               const double* pos, double* F, int64_t* coincident_out) {
+    if (n < 0 || !(d > 0.0) || p < 0 || q < 0) return ORC_EINVAL;
     if (verts == NULL) count = n;
     int64_t coincident = 0;
 #pragma omp parallel for schedule(dynamic, 64) reduction(+ : coincident)
     for (int64_t i = 0; i < count; ++i) {
         int32_t v = verts ? verts[i] : (int32_t)i;
         coincident += force_one(v, row_ptr, col_idx, kidx + kptr[i], kptr[i + 1] - kptr[i],
-                                d, mass, pos, &F[2 * i], &F[2 * i + 1]);
+                                d, mass, p, q, pos, &F[2 * i], &F[2 * i + 1]);
     }
     if (coincident_out) *coincident_out = coincident;
     return ORC_OK;
@@ -255,11 +275,12 @@ typedef struct {
  * place only after all forces are known.  F and D (both [n][2]) receive the
  * forces and displacements. */
 int orc_step(int32_t n, const int64_t* row_ptr, const int32_t* col_idx,
-             const int64_t* kptr, const int32_t* kidx, double d, const double* mass, double t,
-             double stop_displacement, double* pos, double* F, double* D,
+             const int64_t* kptr, const int32_t* kidx, double d, const double* mass, int32_t p,
+             int32_t q, double t, double stop_displacement, double* pos, double* F, double* D,
              orc_iter_stats* st) {
     int64_t coincident = 0;
-    int rc = orc_forces(n, row_ptr, col_idx, n, NULL, kptr, kidx, d, mass, pos, F, &coincident);
+    int rc = orc_forces(n, row_ptr, col_idx, n, NULL, kptr, kidx, d, mass, p, q, pos, F,
+                        &coincident);
     if (rc) return rc;
     rc = orc_cap(n, F, t, D);
     if (rc) return rc;
@@ -288,8 +309,8 @@ int orc_step(int32_t n, const int64_t* row_ptr, const int32_t* col_idx,
  * (Section 5.1); n_active counts the vertices with at least one edge.
  * Returns the number of iterations run in *iters_run. */
 int orc_layout(int32_t n, const int64_t* row_ptr, const int32_t* col_idx,
-               const int64_t* kptr, const int32_t* kidx, double d, const double* mass,
-               const double* temperature, int32_t h0, int32_t h_end,
+               const int64_t* kptr, const int32_t* kidx, double d, const double* mass, int32_t p,
+               int32_t q, const double* temperature, int32_t h0, int32_t h_end,
                double stop_fraction, double stop_displacement, double* pos,
                int32_t* iters_run, orc_iter_stats* last) {
     if (h0 < 0 || h_end < h0) return ORC_EINVAL;
@@ -306,7 +327,7 @@ int orc_layout(int32_t n, const int64_t* row_ptr, const int32_t* col_idx,
     int32_t run = 0;
     int rc = ORC_OK;
     for (int32_t h = h0; h < h_end; ++h) {
-        rc = orc_step(n, row_ptr, col_idx, kptr, kidx, d, mass, temperature[h],
+        rc = orc_step(n, row_ptr, col_idx, kptr, kidx, d, mass, p, q, temperature[h],
                       stop_displacement, pos, F, D, &st);
         if (rc) break;
         ++run;

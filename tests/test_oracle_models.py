@@ -1,0 +1,154 @@
+"""Pins of the oracle's general force exponents (Section 3.1: ||f^a|| =
+delta^p / d, ||f^r|| = d^2 / delta^q; the LinLog model of Section 6 is
+p = 0, q = 1).
+
+The forces are minus the gradient of an energy written here independently,
+in energy terms rather than force terms:
+
+    E = sum over edges     delta^(p+1) / ((p + 1) d)
+      + sum over pairs of N(k)  phi_q(delta),
+    phi_q = -d^2 ln(delta) for q = 1,  -d^2 delta^(1-q) / (1 - q) otherwise,
+
+with each unordered edge and each unordered k-hop pair counted once (N_v(k)
+is symmetric).  Central differences of E pin the oracle's F for every (p, q);
+a wrong exponent, sign or dropped term moves F by far more than the
+difference error.  Further pins: the two-vertex equilibrium distance
+d^(3/(p+q)), zero net force, LinLog's unit-magnitude attraction, and the FR
+branch against a direct unit-vector sum.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1606_02162_amd import inputs
+
+MODELS = [(0, 1), (1, 1), (2, 2), (3, 1), (1, 2), (2, 0), (0, 3), (4, 2)]
+
+
+def _pairs(kp, ki):
+    out = []
+    for v in range(kp.size - 1):
+        for u in ki[kp[v]:kp[v + 1]]:
+            if u > v:
+                out.append((v, int(u)))
+    return np.array(out, dtype=np.int64).reshape(-1, 2)
+
+
+def _energy(x, edges, pairs, d, p, q):
+    a = x[edges[:, 0]] - x[edges[:, 1]]
+    de = np.sqrt((a ** 2).sum(1))
+    e_att = (de ** (p + 1)).sum() / ((p + 1) * d)
+    b = x[pairs[:, 0]] - x[pairs[:, 1]]
+    dp = np.sqrt((b ** 2).sum(1))
+    if q == 1:
+        e_rep = -(d * d) * np.log(dp).sum()
+    else:
+        e_rep = -(d * d) * (dp ** (1 - q)).sum() / (1 - q)
+    return e_att + e_rep
+
+
+@pytest.mark.parametrize("p,q", MODELS)
+@pytest.mark.parametrize("k", [1, 2])
+def test_force_is_minus_energy_gradient(p, q, k):
+    g = inputs.random_tree_plus_edges(40, 20, seed=3)
+    d = 3.0
+    x = inputs.uniform_positions(g.n, seed=7, width=20.0, height=20.0).astype(np.float64)
+    kp, ki = oracle.khop(g.n, g.row_ptr, g.col_idx, k)
+    F, coinc = oracle.forces(g.n, g.row_ptr, g.col_idx, kp, ki, d, x, p=p, q=q)
+    assert coinc == 0
+    edges = g.edges()
+    pairs = _pairs(kp, ki)
+    h = 1e-6
+    G = np.zeros_like(x)
+    for v in range(g.n):
+        for c in range(2):
+            xp, xm = x.copy(), x.copy()
+            xp[v, c] += h
+            xm[v, c] -= h
+            G[v, c] = (_energy(xp, edges, pairs, d, p, q) - _energy(xm, edges, pairs, d, p, q)) / (2 * h)
+    scale = np.abs(F).max()
+    np.testing.assert_allclose(F, -G, rtol=0, atol=2e-5 * scale)
+
+
+@pytest.mark.parametrize("p,q", MODELS + [(2, 1)])
+def test_two_vertex_equilibrium(p, q):
+    """The net outward force d^2/delta^q - delta^p/d vanishes at
+    delta* = d^(3/(p+q)); inward below it is negative, outward above."""
+    d = 2.5
+    g = inputs.path_graph(2)
+    kp, ki = oracle.khop(2, g.row_ptr, g.col_idx, 1)
+    star = d ** (3.0 / (p + q))
+    ang = 0.7
+    u = np.array([math.cos(ang), math.sin(ang)])
+    for delta, sign in ((star, 0), (0.5 * star, 1), (2.0 * star, -1)):
+        x = np.array([[1.0, -1.0], [1.0 + delta * u[0], -1.0 + delta * u[1]]])
+        F, _ = oracle.forces(2, g.row_ptr, g.col_idx, kp, ki, d, x, p=p, q=q)
+        out = float(F[1] @ u)
+        expect = d * d / delta ** q - delta ** p / d
+        assert out == pytest.approx(expect, rel=1e-12, abs=1e-12 * d * d / star ** q)
+        if sign == 0:
+            assert abs(out) <= 1e-12 * d * d / star ** q
+        else:
+            assert np.sign(out) == sign
+        np.testing.assert_allclose(F[0], -F[1], rtol=1e-13, atol=1e-300)
+
+
+@pytest.mark.parametrize("p,q", MODELS)
+def test_zero_net_force(p, q):
+    g = inputs.barabasi_albert(300, 2, seed=4)
+    x = inputs.uniform_positions(g.n, seed=1, width=500.0, height=500.0).astype(np.float64)
+    kp, ki = oracle.khop(g.n, g.row_ptr, g.col_idx, 2)
+    F, _ = oracle.forces(g.n, g.row_ptr, g.col_idx, kp, ki, 30.0, x, p=p, q=q)
+    assert np.abs(F.sum(0)).max() <= 1e-11 * np.abs(F).sum()
+
+
+def test_linlog_attraction_has_unit_magnitude():
+    """p = 0: each edge pulls with magnitude 1/d whatever its length."""
+    d = 4.0
+    g = inputs.star_graph(6)
+    kp = np.zeros(g.n + 1, dtype=np.int64)  # no repulsion rows: attraction only
+    ki = np.zeros(0, dtype=np.int32)
+    th = np.linspace(0, 2 * math.pi, 7)[:-1]
+    r = np.array([1.0, 3.0, 10.0, 0.5, 7.0, 2.0])
+    x = np.vstack([[0.0, 0.0], np.stack([r * np.cos(th), r * np.sin(th)], 1)])
+    F, _ = oracle.forces(g.n, g.row_ptr, g.col_idx, kp, ki, d, x, p=0, q=1)
+    np.testing.assert_allclose(np.hypot(F[1:, 0], F[1:, 1]), 1.0 / d, rtol=1e-14)
+    np.testing.assert_allclose(F[0], (np.stack([np.cos(th), np.sin(th)], 1) / d).sum(0),
+                               rtol=0, atol=1e-14)
+
+
+def test_fr_branch_matches_unit_vector_form():
+    """The FR branch (powers cancelled by hand) equals a direct sum of unit
+    vector times magnitude, delta^2 / d and d^2 / delta, up to rounding."""
+    g = inputs.rmat(9, 4, 0.57, 0.19, 0.19, seed=2)
+    x = inputs.uniform_positions(g.n, seed=5, width=800.0, height=800.0).astype(np.float64)
+    kp, ki = oracle.khop(g.n, g.row_ptr, g.col_idx, 2)
+    F21, _ = oracle.forces(g.n, g.row_ptr, g.col_idx, kp, ki, 25.0, x)
+    att = np.zeros_like(x)
+    rep = np.zeros_like(x)
+    for v in range(g.n):
+        for u in g.col_idx[g.row_ptr[v]:g.row_ptr[v + 1]]:
+            dv = x[u] - x[v]
+            de = math.hypot(*dv)
+            att[v] += dv / de * de ** 2 / 25.0
+        for u in ki[kp[v]:kp[v + 1]]:
+            dv = x[v] - x[u]
+            de = math.hypot(*dv)
+            rep[v] += dv / de * 25.0 ** 2 / de
+    np.testing.assert_allclose(F21, att + rep, rtol=1e-11, atol=1e-11 * np.abs(F21).max())
+
+
+def test_step_and_layout_pass_exponents():
+    g = inputs.random_tree_plus_edges(60, 30, seed=8)
+    x = inputs.uniform_positions(g.n, seed=2, width=100.0, height=100.0).astype(np.float64)
+    kp, ki = oracle.khop(g.n, g.row_ptr, g.col_idx, 2)
+    F, _ = oracle.forces(g.n, g.row_ptr, g.col_idx, kp, ki, 10.0, x, p=0, q=1)
+    x1, F1, _, _ = oracle.step(g.n, g.row_ptr, g.col_idx, kp, ki, 10.0, 2.0, x, p=0, q=1)
+    assert np.array_equal(F, F1)
+    np.testing.assert_array_equal(x1, x + oracle.cap(F, 2.0))
+    xl, run, _ = oracle.layout(g.n, g.row_ptr, g.col_idx, kp, ki, 10.0, np.array([2.0, 1.0]), x,
+                               p=0, q=1)
+    x2, _, _, _ = oracle.step(g.n, g.row_ptr, g.col_idx, kp, ki, 10.0, 1.0, x1, p=0, q=1)
+    assert run == 2 and np.array_equal(xl, x2)
