@@ -65,6 +65,16 @@ enum {
  * global reductions (energy, max displacement, moved count) are done in
  * double (64-bit) arithmetic. */
 
+/* Force model (Section 3.1: ||f^a|| = delta^p / d, ||f^r|| = d^2 / delta^q
+ * with integer exponents).  The repulsion term on v from u is
+ * (x_v - x_u) d^2 / delta^(q+1) and the attraction term (x_u - x_v)
+ * delta^(p-1) / d; coincident ends exert no force. */
+enum {
+    GILA_MODEL_FR = 0,      /* p = 2, q = 1 (Fruchterman-Reingold; a zeroed struct) */
+    GILA_MODEL_LINLOG = 1,  /* p = 0, q = 1 (Noack's LinLog model, Section 6) */
+    GILA_MODEL_PQ = 2       /* p = force_p, q = force_q, each in [0, 8] */
+};
+
 const char* gila_strerror(int status);
 /* Message of the last failing call on this thread ("" if none). */
 const char* gila_last_error(void);
@@ -142,6 +152,10 @@ typedef struct gila_params {
                                    an iteration in which fewer than stop_fraction * n_active
                                    vertices moved more than stop_displacement; 0 = off */
     double stop_displacement;   /* threshold of that rule (the paper: 0.01) */
+    int32_t force_model;        /* GILA_MODEL_* (0 = FR).  The batched entry points and the
+                                   server run FR only (other models: EUNSUPPORTED) */
+    int32_t force_p;            /* GILA_MODEL_PQ: attraction exponent p */
+    int32_t force_q;            /* GILA_MODEL_PQ: repulsion exponent q */
 } gila_params;
 
 typedef struct gila_stats {

@@ -974,6 +974,8 @@ int batch_run(gila_batch* b, const gila_params* params, void* const* pos, hipStr
     int64_t total_t = 0;
     for (int32_t i = 0; i < count; ++i) {
         GILA_TRY(check_params(&params[i], true));
+        if (params[i].force_model != GILA_MODEL_FR)
+            return fail(GILA_EUNSUPPORTED, "graph %d: the batched kernel runs the FR model only", i);
         if (params[i].precision != precision)
             return fail(GILA_EINVAL, "graph %d: all graphs of a batch share one precision", i);
         if (b->n[i] > 0 && !pos[i]) return fail(GILA_EINVAL, "graph %d: pos is NULL", i);

@@ -52,18 +52,18 @@ __device__ __forceinline__ void vertex_partial(const StepArgs& a, int32_t v, int
         const int32_t u2 = a.kidx[e + 2 * STRIDE];
         const int32_t u3 = a.kidx[e + 3 * STRIDE];
         const V p0 = pos[u0], p1 = pos[u1], p2 = pos[u2], p3 = pos[u3];
-        repulse<P>(xv.x, xv.y, p0, scale(u0), acc, coinc);
-        repulse<P>(xv.x, xv.y, p1, scale(u1), acc, coinc);
-        repulse<P>(xv.x, xv.y, p2, scale(u2), acc, coinc);
-        repulse<P>(xv.x, xv.y, p3, scale(u3), acc, coinc);
+        repulse<P>(xv.x, xv.y, p0, scale(u0), acc, coinc, a.rep_q);
+        repulse<P>(xv.x, xv.y, p1, scale(u1), acc, coinc, a.rep_q);
+        repulse<P>(xv.x, xv.y, p2, scale(u2), acc, coinc, a.rep_q);
+        repulse<P>(xv.x, xv.y, p3, scale(u3), acc, coinc, a.rep_q);
     }
     for (; e < ke; e += STRIDE) {
         const int32_t u = a.kidx[e];
-        repulse<P>(xv.x, xv.y, pos[u], scale(u), acc, coinc);
+        repulse<P>(xv.x, xv.y, pos[u], scale(u), acc, coinc, a.rep_q);
     }
     const int64_t rb = a.rp[v], re = a.rp[v + 1];
     for (int64_t j = rb + lane0; j < re; j += STRIDE)
-        attract<P>(xv.x, xv.y, pos[a.ci[j]], inv_d, acc);
+        attract<P>(xv.x, xv.y, pos[a.ci[j]], inv_d, acc, a.att_p);
 }
 
 template <int PREC, int LPV, bool WEIGHTED>

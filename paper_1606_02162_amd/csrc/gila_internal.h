@@ -147,6 +147,8 @@ struct StepArgs {
     // weight of the repulsion each vertex exerts (internal ids; float for the
     // FP32 precisions, double for FP64); null = every weight 1
     const void* mass;
+    int32_t att_p;              // force exponents (FR: 2, 1)
+    int32_t rep_q;
 };
 
 // Arguments of the segment kernel (one workgroup = one id segment x a range
@@ -166,6 +168,8 @@ struct SegArgs {
     double d;
     Ctl* ctl;
     const void* mass;           // repulsion weights (internal ids), null = unit
+    int32_t att_p;              // force exponents (FR: 2, 1)
+    int32_t rep_q;
 };
 
 // Arguments of the k-hop frontier-expansion kernel (khop.hip).
@@ -288,6 +292,8 @@ int prepare_precision(gila_khop* kh, int precision, hipStream_t s);
 int run_iterations(gila_khop* kh, const gila_params* p, int32_t start_h, int32_t end_h,
                    void* pos_dev, hipStream_t stream, gila_stats* out, bool use_graph);
 int check_params(const gila_params* p, bool need_temps);
+// exponents (p, q) of the params' force model
+void force_exponents(const gila_params* p, int32_t* att_p, int32_t* rep_q);
 // Enqueues (no synchronisation) iterations [start_h, end_h) on pos_dev: reset
 // of the control block, permute in, the iterations, permute out.
 int enqueue_run(gila_khop* kh, const gila_params* p, int32_t start_h, int32_t end_h,

@@ -32,6 +32,32 @@ struct Prec<GILA_FP32_KAHAN> {
 
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
+template <class R>
+__device__ __forceinline__ R fast_rsqrt(R x) {
+    if constexpr (sizeof(R) == 4) return __builtin_amdgcn_rsqf(x);
+    else return R(1) / sqrt(x);
+}
+
+// x^k for a small non-negative integer k (uniform across the wavefront).
+template <class R>
+__device__ __forceinline__ R pow_int(R x, int k) {
+    R r = R(1);
+    for (int i = 0; i < k; ++i) r *= x;
+    return r;
+}
+
+// General repulsion exponent q (Section 3.1: magnitude d^2 / delta^q): the
+// factor multiplying (x_v - x_u) d^2 is delta^-(q+1) = (delta^2)^-(q+1)/2,
+// from inv = 1 / delta^2 and, for even q, one reciprocal square root.  A
+// coincident pair (dd at most the coincidence bias) gets 0, since its
+// power would overflow.  q = 1 returns inv itself.
+template <class R>
+__device__ __forceinline__ R repulsion_factor(R dd, R inv, int q, R bias) {
+    if (q == 1) return inv;
+    R r = (q & 1) ? pow_int(inv, (q + 1) >> 1) : pow_int(inv, q >> 1) * fast_rsqrt(dd);
+    return dd > bias ? r : R(0);
+}
+
 // Lane accumulator of 2-vectors: plain, or Kahan-compensated (the running
 // compensation c holds the negated low part lost by each add).
 template <class R, bool KAHAN>
@@ -102,14 +128,15 @@ __device__ __forceinline__ R coincidence_bias() {
 // contributes exactly 0.  `mindd` tracks the smallest biased delta^2, so rows
 // holding a coincident pair can be recounted exactly (rare).  With WEIGHTED,
 // the term of neighbour i is scaled by w[i], the weight of the repulsion that
-// neighbour exerts (1 + its pruned degree-one neighbours, Section 4.6).
-template <class P, bool WEIGHTED = false>
+// neighbour exerts (1 + its pruned degree-one neighbours, Section 4.6).  With
+// GENERAL_Q the exponent q of the repulsion is the argument q (FR: 1).
+template <class P, bool WEIGHTED = false, bool GENERAL_Q = false>
 __device__ __forceinline__ void repulse4(typename P::vec2 p0, typename P::vec2 p1,
                                          typename P::vec2 p2, typename P::vec2 p3,
                                          typename P::real xv, typename P::real yv,
                                          typename P::real& sx, typename P::real& sy,
                                          typename P::real& mindd,
-                                         const typename P::real* w = nullptr) {
+                                         const typename P::real* w = nullptr, int q = 1) {
     using R = typename P::real;
     const R bias = coincidence_bias<R>();
     const R dx0 = xv - p0.x, dy0 = yv - p0.y;
@@ -133,6 +160,12 @@ __device__ __forceinline__ void repulse4(typename P::vec2 p0, typename P::vec2 p
         r1 = R(1) / dd1;
         r2 = R(1) / dd2;
         r3 = R(1) / dd3;
+    }
+    if constexpr (GENERAL_Q) {
+        r0 = repulsion_factor(dd0, r0, q, bias);
+        r1 = repulsion_factor(dd1, r1, q, bias);
+        r2 = repulsion_factor(dd2, r2, q, bias);
+        r3 = repulsion_factor(dd3, r3, q, bias);
     }
     if constexpr (WEIGHTED) {
         r0 *= w[0];
@@ -173,39 +206,58 @@ __device__ __forceinline__ int count_coincident(V xv, const IDX* __restrict__ ro
 }
 
 // Repulsion on v (at xv, yv) from a neighbour at p: (x_v - x_u) d^2 / delta^2
-// (magnitude d^2 / delta, q = 1).  A coincident pair adds nothing and is counted.
+// (magnitude d^2 / delta, q = 1; d^2 / delta^q with (x_v - x_u) d^2 /
+// delta^(q+1) for another q).  A coincident pair adds nothing and is counted.
 template <class P>
 __device__ __forceinline__ void repulse(typename P::real xv, typename P::real yv,
                                         typename P::vec2 p, typename P::real d2,
-                                        Acc<typename P::real, P::kahan>& acc, int& coinc) {
+                                        Acc<typename P::real, P::kahan>& acc, int& coinc,
+                                        int q = 1) {
     using R = typename P::real;
     const R dx = xv - p.x;
     const R dy = yv - p.y;
     const R dd = dx * dx + dy * dy;
     R s;
-    if constexpr (sizeof(R) == 4) {
-        s = dd > R(0) ? d2 * fast_rcp(dd) : R(0);
+    if (q == 1) {
+        if constexpr (sizeof(R) == 4) {
+            s = dd > R(0) ? d2 * fast_rcp(dd) : R(0);
+        } else {
+            s = dd > R(0) ? d2 / dd : R(0);
+        }
     } else {
-        s = dd > R(0) ? d2 / dd : R(0);
+        const R inv = sizeof(R) == 4 ? fast_rcp(dd) : R(1) / dd;
+        s = dd > R(0) ? d2 * repulsion_factor(dd, inv, q, R(0)) : R(0);
     }
     coinc += (dd == R(0));
     acc.add(dx * s, dy * s);
 }
 
+// delta^(p-1) from dd = delta^2, for the attraction exponent p (Section 3.1:
+// magnitude delta^p / d, so the term is (x_u - x_v) delta^(p-1) / d); 0 for
+// coincident ends when p = 0.
+template <class R>
+__device__ __forceinline__ R attraction_factor(R dd, int p) {
+    if (p == 0) return dd > R(0) ? fast_rsqrt(dd) : R(0);
+    const int e = p - 1;
+    return (e & 1) ? pow_int(dd, e >> 1) * sqrt(dd) : pow_int(dd, e >> 1);
+}
+
 // Attraction on v from an adjacent u at p: (x_u - x_v) delta / d (magnitude
-// delta^2 / d, p = 2).  `dparam` is 1/d in FP32 and d itself in FP64.
+// delta^2 / d, p = 2; (x_u - x_v) delta^(pa-1) / d for another exponent pa).
+// `dparam` is 1/d in FP32 and d itself in FP64.
 template <class P>
 __device__ __forceinline__ void attract(typename P::real xv, typename P::real yv,
                                         typename P::vec2 p, typename P::real dparam,
-                                        Acc<typename P::real, P::kahan>& acc) {
+                                        Acc<typename P::real, P::kahan>& acc, int pa = 2) {
     using R = typename P::real;
     const R dx = p.x - xv;
     const R dy = p.y - yv;
+    const R f = pa == 2 ? sqrt(dx * dx + dy * dy) : attraction_factor(dx * dx + dy * dy, pa);
     R s;
     if constexpr (sizeof(R) == 4) {
-        s = sqrt(dx * dx + dy * dy) * dparam;
+        s = f * dparam;
     } else {
-        s = sqrt(dx * dx + dy * dy) / dparam;
+        s = f / dparam;
     }
     acc.add(dx * s, dy * s);
 }

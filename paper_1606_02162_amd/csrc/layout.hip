@@ -191,7 +191,22 @@ int check_params(const gila_params* p, bool need_temps) {
                 return fail(GILA_EINVAL, "temperature[%d] must be finite and >= 0", h);
     if (!(p->stop_fraction >= 0.0) || !(p->stop_displacement >= 0.0))
         return fail(GILA_EINVAL, "stop parameters must be >= 0");
+    if (p->force_model != GILA_MODEL_FR && p->force_model != GILA_MODEL_LINLOG &&
+        p->force_model != GILA_MODEL_PQ)
+        return fail(GILA_EINVAL, "unknown force model %d", p->force_model);
+    if (p->force_model == GILA_MODEL_PQ &&
+        (p->force_p < 0 || p->force_p > 8 || p->force_q < 0 || p->force_q > 8))
+        return fail(GILA_EINVAL, "force exponents p = %d, q = %d outside [0, 8]", p->force_p,
+                    p->force_q);
     return GILA_OK;
+}
+
+void force_exponents(const gila_params* p, int32_t* att_p, int32_t* rep_q) {
+    switch (p->force_model) {
+        case GILA_MODEL_LINLOG: *att_p = 0; *rep_q = 1; break;
+        case GILA_MODEL_PQ: *att_p = p->force_p; *rep_q = p->force_q; break;
+        default: *att_p = 2; *rep_q = 1; break;
+    }
 }
 
 static StepArgs base_args(const gila_khop* kh, const gila_params* p) {
@@ -214,6 +229,7 @@ static StepArgs base_args(const gila_khop* kh, const gila_params* p) {
     a.hist_slot = -1;
     if (kh->mass64)
         a.mass = p->precision == GILA_FP64 ? (const void*)kh->mass64 : (const void*)kh->mass32;
+    force_exponents(p, &a.att_p, &a.rep_q);
     return a;
 }
 

@@ -358,12 +358,12 @@ __device__ __forceinline__ int count_coincident_quads(V xv, const uint2* __restr
 // Repulsion from the four neighbours whose LDS byte offsets are packed in w.
 // With WEIGHTED, the weight of the vertex staged at byte offset o of the
 // positions is at byte offset o / 2 of `lw` (a weight is half a position).
-template <class P, bool WEIGHTED>
+template <class P, bool WEIGHTED, bool GQ>
 __device__ __forceinline__ void quad_terms(uint2 w, const unsigned char* __restrict__ lds,
                                            const unsigned char* __restrict__ lw,
                                            typename P::real xv, typename P::real yv,
                                            typename P::real& sx, typename P::real& sy,
-                                           typename P::real& mindd) {
+                                           typename P::real& mindd, int q) {
     using R = typename P::real;
     using V = typename P::vec2;
     const uint32_t o0 = w.x & 0xFFFFu, o1 = w.x >> 16, o2 = w.y & 0xFFFFu, o3 = w.y >> 16;
@@ -376,13 +376,13 @@ __device__ __forceinline__ void quad_terms(uint2 w, const unsigned char* __restr
                         *reinterpret_cast<const R*>(lw + (o1 >> 1)),
                         *reinterpret_cast<const R*>(lw + (o2 >> 1)),
                         *reinterpret_cast<const R*>(lw + (o3 >> 1))};
-        repulse4<P, true>(p0, p1, p2, p3, xv, yv, sx, sy, mindd, m);
+        repulse4<P, true, GQ>(p0, p1, p2, p3, xv, yv, sx, sy, mindd, m, q);
     } else {
-        repulse4<P>(p0, p1, p2, p3, xv, yv, sx, sy, mindd);
+        repulse4<P, false, GQ>(p0, p1, p2, p3, xv, yv, sx, sy, mindd, nullptr, q);
     }
 }
 
-template <class P, int LPV, bool WEIGHTED>
+template <class P, int LPV, bool WEIGHTED, bool GQ>
 __device__ __forceinline__ void seg_slices(const SegArgs& a, int ib, int ie,
                                            const typename P::vec2* __restrict__ lp,
                                            const unsigned char* __restrict__ lw, int* s_next,
@@ -423,23 +423,24 @@ __device__ __forceinline__ void seg_slices(const SegArgs& a, int ib, int ie,
                 const uint2 w2 = q4[q + 2 * LPV];
                 const uint2 w3 = q4[q + 3 * LPV];
                 R ax, ay, bx, by;
-                quad_terms<P, WEIGHTED>(w0, lds, lw, xv.x, xv.y, ax, ay, mindd);
-                quad_terms<P, WEIGHTED>(w1, lds, lw, xv.x, xv.y, bx, by, mindd);
+                quad_terms<P, WEIGHTED, GQ>(w0, lds, lw, xv.x, xv.y, ax, ay, mindd, a.rep_q);
+                quad_terms<P, WEIGHTED, GQ>(w1, lds, lw, xv.x, xv.y, bx, by, mindd, a.rep_q);
                 acc.add(ax + bx, ay + by);
-                quad_terms<P, WEIGHTED>(w2, lds, lw, xv.x, xv.y, ax, ay, mindd);
-                quad_terms<P, WEIGHTED>(w3, lds, lw, xv.x, xv.y, bx, by, mindd);
+                quad_terms<P, WEIGHTED, GQ>(w2, lds, lw, xv.x, xv.y, ax, ay, mindd, a.rep_q);
+                quad_terms<P, WEIGHTED, GQ>(w3, lds, lw, xv.x, xv.y, bx, by, mindd, a.rep_q);
                 acc.add(ax + bx, ay + by);
             }
             for (; q < nq; q += LPV) {
                 R ax, ay;
-                quad_terms<P, WEIGHTED>(q4[q], lds, lw, xv.x, xv.y, ax, ay, mindd);
+                quad_terms<P, WEIGHTED, GQ>(q4[q], lds, lw, xv.x, xv.y, ax, ay, mindd, a.rep_q);
                 acc.add(ax, ay);
             }
             if (mindd <= coincidence_bias<R>())
                 coinc += count_coincident_quads<V, LPV>(xv, q4, nq, gl, lds);
             const int32_t ab = a.sl_a[i], ae = a.sl_a[i + 1];
             for (int32_t j = ab + gl; j < ae; j += LPV)
-                attract<P>(xv.x, xv.y, *reinterpret_cast<const V*>(lds + a.aidx[j]), dpar, acc);
+                attract<P>(xv.x, xv.y, *reinterpret_cast<const V*>(lds + a.aidx[j]), dpar, acc,
+                           a.att_p);
         }
         const double fx = group_sum<LPV>(acc.x()) * d2;
         const double fy = group_sum<LPV>(acc.y()) * d2;
@@ -450,7 +451,7 @@ __device__ __forceinline__ void seg_slices(const SegArgs& a, int ib, int ie,
 // FP32: eight waves per SIMD (the LDS of four workgroups per CU allows it);
 // FP64 needs more registers.  WEIGHTED stages each vertex's repulsion weight
 // in a static LDS array (slot S of positions and weights holds the sentinel).
-template <int PREC, bool WEIGHTED>
+template <int PREC, bool WEIGHTED, bool GQ>
 __global__ __launch_bounds__(kSegBlock, PREC == GILA_FP64 ? 4 : kSegWaves) void seg_force_kernel(SegArgs a) {
     using P = Prec<PREC>;
     using V = typename P::vec2;
@@ -485,13 +486,13 @@ __global__ __launch_bounds__(kSegBlock, PREC == GILA_FP64 ? 4 : kSegWaves) void 
     int coinc = 0;
     const unsigned char* wb = reinterpret_cast<const unsigned char*>(lw);
     switch (lpv) {
-        case 1: seg_slices<P, 1, WEIGHTED>(a, ib, ie, lp, wb, &s_next, coinc); break;
-        case 2: seg_slices<P, 2, WEIGHTED>(a, ib, ie, lp, wb, &s_next, coinc); break;
-        case 4: seg_slices<P, 4, WEIGHTED>(a, ib, ie, lp, wb, &s_next, coinc); break;
-        case 8: seg_slices<P, 8, WEIGHTED>(a, ib, ie, lp, wb, &s_next, coinc); break;
-        case 16: seg_slices<P, 16, WEIGHTED>(a, ib, ie, lp, wb, &s_next, coinc); break;
-        case 32: seg_slices<P, 32, WEIGHTED>(a, ib, ie, lp, wb, &s_next, coinc); break;
-        default: seg_slices<P, 64, WEIGHTED>(a, ib, ie, lp, wb, &s_next, coinc); break;
+        case 1: seg_slices<P, 1, WEIGHTED, GQ>(a, ib, ie, lp, wb, &s_next, coinc); break;
+        case 2: seg_slices<P, 2, WEIGHTED, GQ>(a, ib, ie, lp, wb, &s_next, coinc); break;
+        case 4: seg_slices<P, 4, WEIGHTED, GQ>(a, ib, ie, lp, wb, &s_next, coinc); break;
+        case 8: seg_slices<P, 8, WEIGHTED, GQ>(a, ib, ie, lp, wb, &s_next, coinc); break;
+        case 16: seg_slices<P, 16, WEIGHTED, GQ>(a, ib, ie, lp, wb, &s_next, coinc); break;
+        case 32: seg_slices<P, 32, WEIGHTED, GQ>(a, ib, ie, lp, wb, &s_next, coinc); break;
+        default: seg_slices<P, 64, WEIGHTED, GQ>(a, ib, ie, lp, wb, &s_next, coinc); break;
     }
     const int64_t wc = wave_sum((int64_t)coinc);
     if (lane64() == 0) s_c[wave_id()] = wc;
@@ -794,12 +795,18 @@ int build_segments(gila_khop* kh, int precision, hipStream_t st) {
     GILA_HIP(hipGetLastError());
     const size_t lds = seg_lds_bytes(kh, precision, S);
     if (lds > 48 * 1024) {
-        const void* kernels[] = {(const void*)seg_force_kernel<GILA_FP64, false>,
-                                 (const void*)seg_force_kernel<GILA_FP32, false>,
-                                 (const void*)seg_force_kernel<GILA_FP32_KAHAN, false>,
-                                 (const void*)seg_force_kernel<GILA_FP64, true>,
-                                 (const void*)seg_force_kernel<GILA_FP32, true>,
-                                 (const void*)seg_force_kernel<GILA_FP32_KAHAN, true>};
+        const void* kernels[] = {(const void*)seg_force_kernel<GILA_FP64, false, false>,
+                                 (const void*)seg_force_kernel<GILA_FP32, false, false>,
+                                 (const void*)seg_force_kernel<GILA_FP32_KAHAN, false, false>,
+                                 (const void*)seg_force_kernel<GILA_FP64, true, false>,
+                                 (const void*)seg_force_kernel<GILA_FP32, true, false>,
+                                 (const void*)seg_force_kernel<GILA_FP32_KAHAN, true, false>,
+                                 (const void*)seg_force_kernel<GILA_FP64, false, true>,
+                                 (const void*)seg_force_kernel<GILA_FP32, false, true>,
+                                 (const void*)seg_force_kernel<GILA_FP32_KAHAN, false, true>,
+                                 (const void*)seg_force_kernel<GILA_FP64, true, true>,
+                                 (const void*)seg_force_kernel<GILA_FP32, true, true>,
+                                 (const void*)seg_force_kernel<GILA_FP32_KAHAN, true, true>};
         for (const void* k : kernels)
             (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     }
@@ -811,6 +818,16 @@ int build_segments(gila_khop* kh, int precision, hipStream_t st) {
     kh->device_bytes += (int64_t)(na + 1) * 8 + T * (4 + 4 + 8 + 4 + 16) + 2 * (kstore + kh->nnz) +
                         (int64_t)sizeof(int4) * (int64_t)plan.size();
     return GILA_OK;
+}
+
+template <bool WEIGHTED, bool GQ>
+static void launch_seg_force(int precision, dim3 sg, dim3 sb, size_t lds, hipStream_t s,
+                             const SegArgs& g) {
+    switch (precision) {
+        case GILA_FP64: hipLaunchKernelGGL((seg_force_kernel<GILA_FP64, WEIGHTED, GQ>), sg, sb, lds, s, g); break;
+        case GILA_FP32: hipLaunchKernelGGL((seg_force_kernel<GILA_FP32, WEIGHTED, GQ>), sg, sb, lds, s, g); break;
+        default: hipLaunchKernelGGL((seg_force_kernel<GILA_FP32_KAHAN, WEIGHTED, GQ>), sg, sb, lds, s, g); break;
+    }
 }
 
 int launch_segment_step(const gila_khop* kh, int precision, const StepArgs& a, hipStream_t s,
@@ -831,6 +848,8 @@ int launch_segment_step(const gila_khop* kh, int precision, const StepArgs& a, h
     g.d = a.d;
     g.ctl = a.ctl;
     g.mass = a.mass;
+    g.att_p = a.att_p;
+    g.rep_q = a.rep_q;
     StepArgs c = a;
     c.vsl = kh->vsl;
     c.part = kh->part;
@@ -842,18 +861,13 @@ int launch_segment_step(const gila_khop* kh, int precision, const StepArgs& a, h
     const size_t lds = seg_lds_bytes(kh, precision, kh->seg);
     const dim3 sg(kh->seg_grid), sb(kSegBlock), cg(kh->comb_grid), cb(kBlock);
     if (ev) GILA_HIP(hipEventRecord(ev[0], s));
+    const bool gq = a.rep_q != 1;
     if (a.mass) {
-        switch (precision) {
-            case GILA_FP64: hipLaunchKernelGGL((seg_force_kernel<GILA_FP64, true>), sg, sb, lds, s, g); break;
-            case GILA_FP32: hipLaunchKernelGGL((seg_force_kernel<GILA_FP32, true>), sg, sb, lds, s, g); break;
-            default: hipLaunchKernelGGL((seg_force_kernel<GILA_FP32_KAHAN, true>), sg, sb, lds, s, g); break;
-        }
+        if (gq) launch_seg_force<true, true>(precision, sg, sb, lds, s, g);
+        else launch_seg_force<true, false>(precision, sg, sb, lds, s, g);
     } else {
-        switch (precision) {
-            case GILA_FP64: hipLaunchKernelGGL((seg_force_kernel<GILA_FP64, false>), sg, sb, lds, s, g); break;
-            case GILA_FP32: hipLaunchKernelGGL((seg_force_kernel<GILA_FP32, false>), sg, sb, lds, s, g); break;
-            default: hipLaunchKernelGGL((seg_force_kernel<GILA_FP32_KAHAN, false>), sg, sb, lds, s, g); break;
-        }
+        if (gq) launch_seg_force<false, true>(precision, sg, sb, lds, s, g);
+        else launch_seg_force<false, false>(precision, sg, sb, lds, s, g);
     }
     if (ev) GILA_HIP(hipEventRecord(ev[1], s));
     switch (precision) {

@@ -594,6 +594,8 @@ int gila_submit(gila_server* s, const gila_csr* g_host, int32_t k, const gila_pa
     if (k < 1) return fail(GILA_EINVAL, "k must be >= 1");
     GILA_TRY(validate_host_csr(g_host));
     GILA_TRY(check_params(params, true));
+    if (params->force_model != GILA_MODEL_FR)
+        return fail(GILA_EUNSUPPORTED, "the server runs the FR model only");
     if (g_host->n > 0 && !init_pos_host) return fail(GILA_EINVAL, "init_pos_host is NULL");
     Job* j = new Job();
     j->k = k;

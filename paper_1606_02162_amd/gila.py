@@ -32,6 +32,10 @@ FP32_KAHAN = 2
 
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp32_kahan": FP32_KAHAN}
 
+MODEL_FR = 0      # p = 2, q = 1
+MODEL_LINLOG = 1  # p = 0, q = 1
+MODEL_PQ = 2      # exponents given explicitly
+
 
 class GilaError(RuntimeError):
     def __init__(self, code: int, where: str, message: str):
@@ -47,7 +51,9 @@ class Csr(ctypes.Structure):
 class _Params(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("ideal_length", ctypes.c_double),
                 ("iterations", ctypes.c_int32), ("temperature", ctypes.POINTER(ctypes.c_double)),
-                ("stop_fraction", ctypes.c_double), ("stop_displacement", ctypes.c_double)]
+                ("stop_fraction", ctypes.c_double), ("stop_displacement", ctypes.c_double),
+                ("force_model", ctypes.c_int32), ("force_p", ctypes.c_int32),
+                ("force_q", ctypes.c_int32)]
 
 
 # numpy mirrors of gila_csr and gila_params, for marshalling thousands at once
@@ -57,13 +63,16 @@ CSR_DTYPE = np.dtype({"names": ["n", "nnz", "row_ptr", "col_idx"],
                                   Csr.col_idx.offset],
                       "itemsize": ctypes.sizeof(Csr)})
 PARAMS_DTYPE = np.dtype({"names": ["precision", "ideal_length", "iterations", "temperature",
-                                   "stop_fraction", "stop_displacement"],
+                                   "stop_fraction", "stop_displacement", "force_model",
+                                   "force_p", "force_q"],
                          "formats": [np.int32, np.float64, np.int32, np.uint64, np.float64,
-                                     np.float64],
+                                     np.float64, np.int32, np.int32, np.int32],
                          "offsets": [_Params.precision.offset, _Params.ideal_length.offset,
                                      _Params.iterations.offset, _Params.temperature.offset,
                                      _Params.stop_fraction.offset,
-                                     _Params.stop_displacement.offset],
+                                     _Params.stop_displacement.offset,
+                                     _Params.force_model.offset, _Params.force_p.offset,
+                                     _Params.force_q.offset],
                          "itemsize": ctypes.sizeof(_Params)})
 
 
@@ -183,6 +192,9 @@ class LayoutParams:
     precision: int = FP32_KAHAN
     stop_fraction: float = 0.0
     stop_displacement: float = 0.01
+    force_model: int = MODEL_FR
+    force_p: int = 2
+    force_q: int = 1
     _keep: list = field(default_factory=list, repr=False)
 
     @property
@@ -199,6 +211,9 @@ class LayoutParams:
         p.temperature = t.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if t.size else None
         p.stop_fraction = float(self.stop_fraction)
         p.stop_displacement = float(self.stop_displacement)
+        p.force_model = int(self.force_model)
+        p.force_p = int(self.force_p)
+        p.force_q = int(self.force_q)
         return p
 
 

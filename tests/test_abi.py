@@ -107,6 +107,9 @@ def test_params_validation():
         gila.LayoutParams(temperature=np.ones(2), precision=7),
         gila.LayoutParams(temperature=np.array([1.0, float("nan")])),
         gila.LayoutParams(temperature=np.ones(2), stop_fraction=-0.1),
+        gila.LayoutParams(temperature=np.ones(2), force_model=7),
+        gila.LayoutParams(temperature=np.ones(2), force_model=gila.MODEL_PQ, force_p=9),
+        gila.LayoutParams(temperature=np.ones(2), force_model=gila.MODEL_PQ, force_q=-1),
     ]
     st = gila.Stats()
     for p in bad:

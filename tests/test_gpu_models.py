@@ -1,0 +1,169 @@
+"""GPU parity of the general force exponents (Section 3.1: ||f^a|| =
+delta^p / d, ||f^r|| = d^2 / delta^q; LinLog, Section 6: p = 0, q = 1)
+against the FP64 oracle, one step from identical positions, on the segment,
+tiny-segment and direct paths, with unit and leaf weights.  Gates as for FR:
+FP32 e_F, e_x <= 1e-5; FP64 1e-12.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_common import pos_err, rel_l2, require_gpu
+from paper_1606_02162_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+# (model, p, q) as passed to the library; p, q as the oracle takes them
+MODELS = [("linlog", 1, 0, 1), ("pq22", 2, 2, 2), ("pq11", 2, 1, 1), ("pq03", 2, 0, 3),
+          ("pq30", 2, 3, 0), ("pq41", 2, 4, 1)]
+
+
+@pytest.fixture(scope="module")
+def G():
+    require_gpu()
+    from paper_1606_02162_amd import gila
+    return gila
+
+
+PATHS = {"segment": {}, "segment_tiny": {"GILA_SEG_BYTES": "2048"},
+         "direct": {"GILA_PATH": "direct"}}
+
+
+@pytest.fixture(params=list(PATHS))
+def path_env(request):
+    old = {k: os.environ.get(k) for k in ("GILA_PATH", "GILA_SEG_BYTES")}
+    for k in old:
+        os.environ.pop(k, None)
+    os.environ.update(PATHS[request.param])
+    yield request.param
+    for k, v in old.items():
+        if v is None:
+            os.environ.pop(k, None)
+        else:
+            os.environ[k] = v
+
+
+def _params(G, prec, model, fp, fq, temps=(25.0,), d=30.0):
+    return G.LayoutParams(temperature=np.array(temps), ideal_length=d, precision=prec,
+                          force_model=model, force_p=fp, force_q=fq)
+
+
+def _gpu_step(G, kh, params, pos0):
+    import torch
+    n = pos0.shape[0]
+    pos = torch.from_numpy(pos0).to(dtype=G.position_dtype(params.precision), device="cuda")
+    F = torch.zeros((n, 2), dtype=torch.float64, device="cuda")
+    D = torch.zeros((n, 2), dtype=torch.float64, device="cuda")
+    st = G.step(kh, params, 0, pos, F, D)
+    return pos.double().cpu().numpy(), F.cpu().numpy(), st
+
+
+def _suite():
+    return [inputs.barabasi_albert(3000, 3, seed=2),
+            inputs.rmat(11, 4, 0.57, 0.19, 0.19, seed=3),
+            inputs.grid_graph(24, 24),
+            inputs.to_csr(10, [0, 1, 5], [1, 2, 6], name="sparse10")]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_kahan"])
+@pytest.mark.parametrize("name,model,p,q", MODELS)
+def test_model_step(G, precision, name, model, p, q, path_env):
+    prec = G.PRECISIONS[precision]
+    tol = 1e-12 if prec == G.FP64 else 1e-5
+    fp, fq = (p, q) if model == G.MODEL_PQ else (0, 0)
+    for g in _suite():
+        for k in (1, 2):
+            print(f"model {name} {g.name} k={k} {precision} {path_env}", flush=True)
+            rp, ci = G.to_device_csr(g)
+            kh = G.build_khop(rp, ci, k)
+            pos0 = inputs.uniform_positions(g.n, seed=13, width=400.0)
+            if prec != G.FP64:
+                pos0 = pos0.astype(np.float32).astype(np.float64)
+            x_g, F_g, st = _gpu_step(G, kh, _params(G, prec, model, fp, fq), pos0)
+            optr, oidx = oracle.khop(g.n, g.row_ptr, g.col_idx, k)
+            x_o, F_o, _, so = oracle.step(g.n, g.row_ptr, g.col_idx, optr, oidx, 30.0, 25.0,
+                                          pos0, p=p, q=q)
+            assert rel_l2(F_g, F_o) <= tol, (g.name, k, rel_l2(F_g, F_o))
+            if g.n > 1:
+                assert pos_err(x_g, x_o) <= tol, (g.name, k)
+            assert st.coincident == so.coincident
+            kh.free()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_kahan"])
+@pytest.mark.parametrize("name,model,p,q", [MODELS[0], MODELS[1]])
+def test_model_weighted_pruned(G, precision, name, model, p, q, path_env):
+    """LinLog and (2, 2) on a pruned graph with leaf weights."""
+    prec = G.PRECISIONS[precision]
+    tol = 1e-12 if prec == G.FP64 else 1e-5
+    fp, fq = (p, q) if model == G.MODEL_PQ else (0, 0)
+    g = inputs.random_tree_plus_edges(3000, 900, seed=5)
+    pr = oracle.prune(g.n, g.row_ptr, g.col_idx)
+    rp, ci = G.to_device_csr(g)
+    P = G.prune(rp, ci)
+    csr, mass = P.graph()
+    kh = G.KHop.from_csr(csr, 2)
+    kh.set_mass(mass)
+    pos0 = inputs.uniform_positions(pr.n, seed=3, width=600.0)
+    if prec != G.FP64:
+        pos0 = pos0.astype(np.float32).astype(np.float64)
+    x_g, F_g, _ = _gpu_step(G, kh, _params(G, prec, model, fp, fq), pos0)
+    optr, oidx = oracle.khop(pr.n, pr.row_ptr, pr.col_idx, 2)
+    x_o, F_o, _, _ = oracle.step(pr.n, pr.row_ptr, pr.col_idx, optr, oidx, 30.0, 25.0, pos0,
+                                 mass=pr.mass(), p=p, q=q)
+    assert rel_l2(F_g, F_o) <= tol and pos_err(x_g, x_o) <= tol
+
+
+def test_coincident_pairs_general_q(G):
+    """Coincident vertices exert nothing for q != 1 either (their power would
+    overflow) and are counted."""
+    import torch
+    g = inputs.cycle_graph(12)
+    rp, ci = G.to_device_csr(g)
+    kh = G.build_khop(rp, ci, 3)
+    pos0 = inputs.uniform_positions(g.n, seed=1, width=100.0)
+    pos0[5] = pos0[2]
+    pos0[9] = pos0[2]
+    optr, oidx = oracle.khop(g.n, g.row_ptr, g.col_idx, 3)
+    for prec in (G.FP64, G.FP32_KAHAN):
+        x0 = pos0 if prec == G.FP64 else pos0.astype(np.float32).astype(np.float64)
+        x_g, F_g, st = _gpu_step(G, kh, _params(G, prec, G.MODEL_PQ, 2, 3), x0)
+        _, F_o, _, so = oracle.step(g.n, g.row_ptr, g.col_idx, optr, oidx, 30.0, 25.0, x0,
+                                    p=2, q=3)
+        assert np.isfinite(F_g).all()
+        assert st.coincident == so.coincident > 0
+        assert rel_l2(F_g, F_o) <= (1e-12 if prec == G.FP64 else 1e-5)
+    del torch
+
+
+def test_model_run_matches_steps(G):
+    import torch
+    g = inputs.barabasi_albert(2000, 2, seed=6)
+    rp, ci = G.to_device_csr(g)
+    kh = G.build_khop(rp, ci, 2)
+    params = _params(G, G.FP32_KAHAN, G.MODEL_LINLOG, 0, 0,
+                     temps=G.paper_schedule(g.n, 1.0, 30.0, 10))
+    pos0 = torch.from_numpy(inputs.uniform_positions(g.n, 2, 800.0)).float().cuda()
+    a = pos0.clone()
+    G.run(kh, params, a)
+    b = pos0.clone()
+    for h in range(10):
+        G.step(kh, params, h, b)
+    assert torch.equal(a, b)
+
+
+def test_batch_and_server_refuse_other_models(G):
+    import torch
+    g = inputs.random_tree_plus_edges(100, 30, seed=1)
+    rp, ci = G.to_device_csr(g)
+    pos = torch.from_numpy(inputs.uniform_positions(g.n, 1, 100.0)).float().cuda()
+    params = _params(G, G.FP32, G.MODEL_LINLOG, 0, 0)
+    with pytest.raises(G.GilaError) as e:
+        G.layout_batch([(rp, ci)], [2], [params], [pos])
+    assert e.value.code == G.GILA_EUNSUPPORTED
+    with G.Server() as srv:
+        with pytest.raises(G.GilaError) as e:
+            srv.submit(g, 2, params, inputs.uniform_positions(g.n, 1, 100.0))
+        assert e.value.code == G.GILA_EUNSUPPORTED
