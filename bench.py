@@ -133,6 +133,9 @@ def main() -> int:
                          "Barabasi-Albert 100k; grid: 32x32 grid in FP64; batch: 4096 graphs "
                          "in one persistent launch; serve: Poisson stream through the layout "
                          "server")
+    ap.add_argument("--model", default="fr",
+                    help="force model of the single-graph workloads: fr (p = 2, q = 1), linlog "
+                         "(p = 0, q = 1) or explicit exponents 'p,q'")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--serve-jobs", type=int, default=400)
     ap.add_argument("--serve-rate", type=float, default=200.0)
@@ -168,6 +171,18 @@ def main() -> int:
     return bench_single(args, single_graph_workloads(args)[args.workload])
 
 
+def force_model(args):
+    """(library model id, p, q, name) of --model."""
+    from paper_1606_02162_amd import gila
+    m = args.model.strip().lower()
+    if m == "fr":
+        return gila.MODEL_FR, 2, 1, "fr"
+    if m == "linlog":
+        return gila.MODEL_LINLOG, 0, 1, "linlog"
+    p, q = (int(x) for x in m.split(","))
+    return gila.MODEL_PQ, p, q, f"p{p}q{q}"
+
+
 def bench_single(args, wl) -> int:
     """One graph: a step is gila_build_khop + all iterations."""
     import torch
@@ -182,7 +197,9 @@ def bench_single(args, wl) -> int:
     H, k, prec, d = wl["H"], wl["k"], wl["precision"], wl["d"]
     n_active = int((np.diff(g.row_ptr) > 0).sum())
     temps = wl["caps"](g, H)
-    params = gila.LayoutParams(temperature=temps, ideal_length=d, precision=prec)
+    model, fp, fq, mname = force_model(args)
+    params = gila.LayoutParams(temperature=temps, ideal_length=d, precision=prec,
+                               force_model=model, force_p=fp, force_q=fq)
     rp, ci = gila.to_device_csr(g, dev)
     pos0 = torch.empty((g.n, 2), dtype=gila.position_dtype(prec), device=dev)
     gila.init_positions(g.n, wl["seed"], wl["frame"], wl["frame"], prec, pos0)
@@ -257,15 +274,17 @@ def bench_single(args, wl) -> int:
         "vs_baseline": None,
         "dtype": wl["dtype"],
         "data": "synthetic",
-        "config": {"workload": wl["name"](H), "n": g.n,
-                   "m": g.m, "k": k, "iterations": H, "total_pairs": P,
-                   "n_active": n_active},
+        "config": {"workload": wl["name"](H) + ("" if mname == "fr" else "_" + mname),
+                   "n": g.n, "m": g.m, "k": k, "iterations": H, "total_pairs": P,
+                   "n_active": n_active, "force_model": {"p": fp, "q": fq}},
         "ms_per_iter": iter_ms,
         "build_ms": build_ms,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic() if args.workload == "rmat" else None,
-                     "kernel": f"seg_force_kernel<{prec_name}>",
+                     "traffic": (measured_traffic() if args.workload == "rmat" and mname == "fr"
+                                 else None),
+                     "kernel": f"seg_force_kernel<{prec_name}" + (">" if fq == 1 else ", q>") +
+                               ("" if mname == "fr" else f" ({mname})"),
                      "kernel_ms": force_ms,
                      "algorithmic_bytes_per_launch": kern_bytes},
         "iteration": {"ms": iter_ms, "force_kernel_ms": force_ms,
@@ -282,7 +301,8 @@ def bench_single(args, wl) -> int:
         tc1 = time.perf_counter()
         x = pos0.double().cpu().numpy()
         for h in range(args.cpu_iters):
-            x, _, _, _ = oracle.step(g.n, g.row_ptr, g.col_idx, optr, oidx, d, temps[h], x)
+            x, _, _, _ = oracle.step(g.n, g.row_ptr, g.col_idx, optr, oidx, d, temps[h], x,
+                                     p=fp, q=fq)
         tc2 = time.perf_counter()
         cpu_build, cpu_iter = tc1 - tc0, (tc2 - tc1) / args.cpu_iters
         cpu_job = cpu_build + H * cpu_iter
@@ -326,7 +346,9 @@ def bench_pruned(args, wl) -> int:
     kh0.free()
     n_active = kinfo["n_active"]
     temps = gila.paper_schedule(n_active, 1.0, d, H)
-    params = gila.LayoutParams(temperature=temps, ideal_length=d, precision=prec)
+    model, fp, fq, mname = force_model(args)
+    params = gila.LayoutParams(temperature=temps, ideal_length=d, precision=prec,
+                               force_model=model, force_p=fp, force_q=fq)
     kept = torch.empty((pinfo["n_kept"], 2), dtype=pos0.dtype, device=dev)
     torch.cuda.synchronize()
 
@@ -390,14 +412,15 @@ def bench_pruned(args, wl) -> int:
         "warmup": args.warmup, "ms_per_step": total_s / args.steps * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": wl["dtype"],
         "data": "synthetic",
-        "config": {"workload": wl["name"](H).replace("rmat", "rmat_pruned", 1), "n": g.n,
+        "config": {"workload": (wl["name"](H).replace("rmat", "rmat_pruned", 1) +
+                                ("" if mname == "fr" else "_" + mname)), "n": g.n,
                    "m": g.m, "k": k, "iterations": H, "n_kept": pinfo["n_kept"],
                    "n_pruned": pinfo["n_pruned"], "m_kept": nnz // 2, "total_pairs": P,
-                   "n_active": n_active},
+                   "n_active": n_active, "force_model": {"p": fp, "q": fq}},
         "prune_ms": prune_ms, "reinsert_ms": reinsert_ms,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(TRAFFIC_FILE_PRUNED),
+                     "traffic": measured_traffic(TRAFFIC_FILE_PRUNED) if mname == "fr" else None,
                      "kernel": f"seg_force_kernel<{prec_name}, weighted>", "kernel_ms": force_ms,
                      "algorithmic_bytes_per_launch": kern_bytes},
         "unweighted_force_kernel_ms": plain_ms,
@@ -417,7 +440,7 @@ def bench_pruned(args, wl) -> int:
         m = pr.mass()
         for h in range(args.cpu_iters):
             x, _, _, _ = oracle.step(pr.n, pr.row_ptr, pr.col_idx, optr, oidx, d, temps[h], x,
-                                     mass=m)
+                                     mass=m, p=fp, q=fq)
         tc2 = time.perf_counter()
         oracle.reinsert(pr, d, x)
         tc3 = time.perf_counter()

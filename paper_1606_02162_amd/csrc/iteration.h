@@ -50,11 +50,17 @@ __device__ __forceinline__ R pow_int(R x, int k) {
 // factor multiplying (x_v - x_u) d^2 is delta^-(q+1) = (delta^2)^-(q+1)/2,
 // from inv = 1 / delta^2 and, for even q, one reciprocal square root.  A
 // coincident pair (dd at most the coincidence bias) gets 0, since its
-// power would overflow.  q = 1 returns inv itself.
-template <class R>
+// power would overflow.  q = 1 returns inv itself.  Q >= 0 fixes q at
+// compile time; Q < 0 takes the run-time q.
+template <int Q = -1, class R>
 __device__ __forceinline__ R repulsion_factor(R dd, R inv, int q, R bias) {
+    if constexpr (Q >= 0) q = Q;
     if (q == 1) return inv;
-    R r = (q & 1) ? pow_int(inv, (q + 1) >> 1) : pow_int(inv, q >> 1) * fast_rsqrt(dd);
+    R r;
+    if constexpr (Q == 0) r = fast_rsqrt(dd);
+    else if constexpr (Q == 2) r = inv * fast_rsqrt(dd);
+    else if constexpr (Q == 3) r = inv * inv;
+    else r = (q & 1) ? pow_int(inv, (q + 1) >> 1) : pow_int(inv, q >> 1) * fast_rsqrt(dd);
     return dd > bias ? r : R(0);
 }
 
@@ -129,8 +135,8 @@ __device__ __forceinline__ R coincidence_bias() {
 // holding a coincident pair can be recounted exactly (rare).  With WEIGHTED,
 // the term of neighbour i is scaled by w[i], the weight of the repulsion that
 // neighbour exerts (1 + its pruned degree-one neighbours, Section 4.6).  With
-// GENERAL_Q the exponent q of the repulsion is the argument q (FR: 1).
-template <class P, bool WEIGHTED = false, bool GENERAL_Q = false>
+// Q != 1 the repulsion exponent is Q (0, 2 or 3), or the argument q (Q < 0).
+template <class P, bool WEIGHTED = false, int Q = 1>
 __device__ __forceinline__ void repulse4(typename P::vec2 p0, typename P::vec2 p1,
                                          typename P::vec2 p2, typename P::vec2 p3,
                                          typename P::real xv, typename P::real yv,
@@ -161,11 +167,11 @@ __device__ __forceinline__ void repulse4(typename P::vec2 p0, typename P::vec2 p
         r2 = R(1) / dd2;
         r3 = R(1) / dd3;
     }
-    if constexpr (GENERAL_Q) {
-        r0 = repulsion_factor(dd0, r0, q, bias);
-        r1 = repulsion_factor(dd1, r1, q, bias);
-        r2 = repulsion_factor(dd2, r2, q, bias);
-        r3 = repulsion_factor(dd3, r3, q, bias);
+    if constexpr (Q != 1) {
+        r0 = repulsion_factor<Q>(dd0, r0, q, bias);
+        r1 = repulsion_factor<Q>(dd1, r1, q, bias);
+        r2 = repulsion_factor<Q>(dd2, r2, q, bias);
+        r3 = repulsion_factor<Q>(dd3, r3, q, bias);
     }
     if constexpr (WEIGHTED) {
         r0 *= w[0];

@@ -358,7 +358,7 @@ __device__ __forceinline__ int count_coincident_quads(V xv, const uint2* __restr
 // Repulsion from the four neighbours whose LDS byte offsets are packed in w.
 // With WEIGHTED, the weight of the vertex staged at byte offset o of the
 // positions is at byte offset o / 2 of `lw` (a weight is half a position).
-template <class P, bool WEIGHTED, bool GQ>
+template <class P, bool WEIGHTED, int Q>
 __device__ __forceinline__ void quad_terms(uint2 w, const unsigned char* __restrict__ lds,
                                            const unsigned char* __restrict__ lw,
                                            typename P::real xv, typename P::real yv,
@@ -376,13 +376,13 @@ __device__ __forceinline__ void quad_terms(uint2 w, const unsigned char* __restr
                         *reinterpret_cast<const R*>(lw + (o1 >> 1)),
                         *reinterpret_cast<const R*>(lw + (o2 >> 1)),
                         *reinterpret_cast<const R*>(lw + (o3 >> 1))};
-        repulse4<P, true, GQ>(p0, p1, p2, p3, xv, yv, sx, sy, mindd, m, q);
+        repulse4<P, true, Q>(p0, p1, p2, p3, xv, yv, sx, sy, mindd, m, q);
     } else {
-        repulse4<P, false, GQ>(p0, p1, p2, p3, xv, yv, sx, sy, mindd, nullptr, q);
+        repulse4<P, false, Q>(p0, p1, p2, p3, xv, yv, sx, sy, mindd, nullptr, q);
     }
 }
 
-template <class P, int LPV, bool WEIGHTED, bool GQ>
+template <class P, int LPV, bool WEIGHTED, int Q>
 __device__ __forceinline__ void seg_slices(const SegArgs& a, int ib, int ie,
                                            const typename P::vec2* __restrict__ lp,
                                            const unsigned char* __restrict__ lw, int* s_next,
@@ -423,16 +423,16 @@ __device__ __forceinline__ void seg_slices(const SegArgs& a, int ib, int ie,
                 const uint2 w2 = q4[q + 2 * LPV];
                 const uint2 w3 = q4[q + 3 * LPV];
                 R ax, ay, bx, by;
-                quad_terms<P, WEIGHTED, GQ>(w0, lds, lw, xv.x, xv.y, ax, ay, mindd, a.rep_q);
-                quad_terms<P, WEIGHTED, GQ>(w1, lds, lw, xv.x, xv.y, bx, by, mindd, a.rep_q);
+                quad_terms<P, WEIGHTED, Q>(w0, lds, lw, xv.x, xv.y, ax, ay, mindd, a.rep_q);
+                quad_terms<P, WEIGHTED, Q>(w1, lds, lw, xv.x, xv.y, bx, by, mindd, a.rep_q);
                 acc.add(ax + bx, ay + by);
-                quad_terms<P, WEIGHTED, GQ>(w2, lds, lw, xv.x, xv.y, ax, ay, mindd, a.rep_q);
-                quad_terms<P, WEIGHTED, GQ>(w3, lds, lw, xv.x, xv.y, bx, by, mindd, a.rep_q);
+                quad_terms<P, WEIGHTED, Q>(w2, lds, lw, xv.x, xv.y, ax, ay, mindd, a.rep_q);
+                quad_terms<P, WEIGHTED, Q>(w3, lds, lw, xv.x, xv.y, bx, by, mindd, a.rep_q);
                 acc.add(ax + bx, ay + by);
             }
             for (; q < nq; q += LPV) {
                 R ax, ay;
-                quad_terms<P, WEIGHTED, GQ>(q4[q], lds, lw, xv.x, xv.y, ax, ay, mindd, a.rep_q);
+                quad_terms<P, WEIGHTED, Q>(q4[q], lds, lw, xv.x, xv.y, ax, ay, mindd, a.rep_q);
                 acc.add(ax, ay);
             }
             if (mindd <= coincidence_bias<R>())
@@ -451,7 +451,7 @@ __device__ __forceinline__ void seg_slices(const SegArgs& a, int ib, int ie,
 // FP32: eight waves per SIMD (the LDS of four workgroups per CU allows it);
 // FP64 needs more registers.  WEIGHTED stages each vertex's repulsion weight
 // in a static LDS array (slot S of positions and weights holds the sentinel).
-template <int PREC, bool WEIGHTED, bool GQ>
+template <int PREC, bool WEIGHTED, int Q>
 __global__ __launch_bounds__(kSegBlock, PREC == GILA_FP64 ? 4 : kSegWaves) void seg_force_kernel(SegArgs a) {
     using P = Prec<PREC>;
     using V = typename P::vec2;
@@ -486,13 +486,13 @@ __global__ __launch_bounds__(kSegBlock, PREC == GILA_FP64 ? 4 : kSegWaves) void 
     int coinc = 0;
     const unsigned char* wb = reinterpret_cast<const unsigned char*>(lw);
     switch (lpv) {
-        case 1: seg_slices<P, 1, WEIGHTED, GQ>(a, ib, ie, lp, wb, &s_next, coinc); break;
-        case 2: seg_slices<P, 2, WEIGHTED, GQ>(a, ib, ie, lp, wb, &s_next, coinc); break;
-        case 4: seg_slices<P, 4, WEIGHTED, GQ>(a, ib, ie, lp, wb, &s_next, coinc); break;
-        case 8: seg_slices<P, 8, WEIGHTED, GQ>(a, ib, ie, lp, wb, &s_next, coinc); break;
-        case 16: seg_slices<P, 16, WEIGHTED, GQ>(a, ib, ie, lp, wb, &s_next, coinc); break;
-        case 32: seg_slices<P, 32, WEIGHTED, GQ>(a, ib, ie, lp, wb, &s_next, coinc); break;
-        default: seg_slices<P, 64, WEIGHTED, GQ>(a, ib, ie, lp, wb, &s_next, coinc); break;
+        case 1: seg_slices<P, 1, WEIGHTED, Q>(a, ib, ie, lp, wb, &s_next, coinc); break;
+        case 2: seg_slices<P, 2, WEIGHTED, Q>(a, ib, ie, lp, wb, &s_next, coinc); break;
+        case 4: seg_slices<P, 4, WEIGHTED, Q>(a, ib, ie, lp, wb, &s_next, coinc); break;
+        case 8: seg_slices<P, 8, WEIGHTED, Q>(a, ib, ie, lp, wb, &s_next, coinc); break;
+        case 16: seg_slices<P, 16, WEIGHTED, Q>(a, ib, ie, lp, wb, &s_next, coinc); break;
+        case 32: seg_slices<P, 32, WEIGHTED, Q>(a, ib, ie, lp, wb, &s_next, coinc); break;
+        default: seg_slices<P, 64, WEIGHTED, Q>(a, ib, ie, lp, wb, &s_next, coinc); break;
     }
     const int64_t wc = wave_sum((int64_t)coinc);
     if (lane64() == 0) s_c[wave_id()] = wc;
@@ -795,18 +795,17 @@ int build_segments(gila_khop* kh, int precision, hipStream_t st) {
     GILA_HIP(hipGetLastError());
     const size_t lds = seg_lds_bytes(kh, precision, S);
     if (lds > 48 * 1024) {
-        const void* kernels[] = {(const void*)seg_force_kernel<GILA_FP64, false, false>,
-                                 (const void*)seg_force_kernel<GILA_FP32, false, false>,
-                                 (const void*)seg_force_kernel<GILA_FP32_KAHAN, false, false>,
-                                 (const void*)seg_force_kernel<GILA_FP64, true, false>,
-                                 (const void*)seg_force_kernel<GILA_FP32, true, false>,
-                                 (const void*)seg_force_kernel<GILA_FP32_KAHAN, true, false>,
-                                 (const void*)seg_force_kernel<GILA_FP64, false, true>,
-                                 (const void*)seg_force_kernel<GILA_FP32, false, true>,
-                                 (const void*)seg_force_kernel<GILA_FP32_KAHAN, false, true>,
-                                 (const void*)seg_force_kernel<GILA_FP64, true, true>,
-                                 (const void*)seg_force_kernel<GILA_FP32, true, true>,
-                                 (const void*)seg_force_kernel<GILA_FP32_KAHAN, true, true>};
+        const void* kernels[] = {
+#define GILA_SEG_KERNELS(W, Q)                                      \
+    (const void*)seg_force_kernel<GILA_FP64, W, Q>,                 \
+        (const void*)seg_force_kernel<GILA_FP32, W, Q>,             \
+        (const void*)seg_force_kernel<GILA_FP32_KAHAN, W, Q>
+            GILA_SEG_KERNELS(false, 1), GILA_SEG_KERNELS(true, 1),  GILA_SEG_KERNELS(false, 0),
+            GILA_SEG_KERNELS(true, 0),  GILA_SEG_KERNELS(false, 2), GILA_SEG_KERNELS(true, 2),
+            GILA_SEG_KERNELS(false, 3), GILA_SEG_KERNELS(true, 3),  GILA_SEG_KERNELS(false, -1),
+            GILA_SEG_KERNELS(true, -1)
+#undef GILA_SEG_KERNELS
+        };
         for (const void* k : kernels)
             (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     }
@@ -820,13 +819,26 @@ int build_segments(gila_khop* kh, int precision, hipStream_t st) {
     return GILA_OK;
 }
 
-template <bool WEIGHTED, bool GQ>
+template <bool WEIGHTED, int Q>
 static void launch_seg_force(int precision, dim3 sg, dim3 sb, size_t lds, hipStream_t s,
                              const SegArgs& g) {
     switch (precision) {
-        case GILA_FP64: hipLaunchKernelGGL((seg_force_kernel<GILA_FP64, WEIGHTED, GQ>), sg, sb, lds, s, g); break;
-        case GILA_FP32: hipLaunchKernelGGL((seg_force_kernel<GILA_FP32, WEIGHTED, GQ>), sg, sb, lds, s, g); break;
-        default: hipLaunchKernelGGL((seg_force_kernel<GILA_FP32_KAHAN, WEIGHTED, GQ>), sg, sb, lds, s, g); break;
+        case GILA_FP64: hipLaunchKernelGGL((seg_force_kernel<GILA_FP64, WEIGHTED, Q>), sg, sb, lds, s, g); break;
+        case GILA_FP32: hipLaunchKernelGGL((seg_force_kernel<GILA_FP32, WEIGHTED, Q>), sg, sb, lds, s, g); break;
+        default: hipLaunchKernelGGL((seg_force_kernel<GILA_FP32_KAHAN, WEIGHTED, Q>), sg, sb, lds, s, g); break;
+    }
+}
+
+// Repulsion exponents with a kernel of their own; others run the general one.
+template <bool WEIGHTED>
+static void launch_seg_force_q(int q, int precision, dim3 sg, dim3 sb, size_t lds, hipStream_t s,
+                               const SegArgs& g) {
+    switch (q) {
+        case 1: launch_seg_force<WEIGHTED, 1>(precision, sg, sb, lds, s, g); break;
+        case 0: launch_seg_force<WEIGHTED, 0>(precision, sg, sb, lds, s, g); break;
+        case 2: launch_seg_force<WEIGHTED, 2>(precision, sg, sb, lds, s, g); break;
+        case 3: launch_seg_force<WEIGHTED, 3>(precision, sg, sb, lds, s, g); break;
+        default: launch_seg_force<WEIGHTED, -1>(precision, sg, sb, lds, s, g); break;
     }
 }
 
@@ -861,14 +873,8 @@ int launch_segment_step(const gila_khop* kh, int precision, const StepArgs& a, h
     const size_t lds = seg_lds_bytes(kh, precision, kh->seg);
     const dim3 sg(kh->seg_grid), sb(kSegBlock), cg(kh->comb_grid), cb(kBlock);
     if (ev) GILA_HIP(hipEventRecord(ev[0], s));
-    const bool gq = a.rep_q != 1;
-    if (a.mass) {
-        if (gq) launch_seg_force<true, true>(precision, sg, sb, lds, s, g);
-        else launch_seg_force<true, false>(precision, sg, sb, lds, s, g);
-    } else {
-        if (gq) launch_seg_force<false, true>(precision, sg, sb, lds, s, g);
-        else launch_seg_force<false, false>(precision, sg, sb, lds, s, g);
-    }
+    if (a.mass) launch_seg_force_q<true>(a.rep_q, precision, sg, sb, lds, s, g);
+    else launch_seg_force_q<false>(a.rep_q, precision, sg, sb, lds, s, g);
     if (ev) GILA_HIP(hipEventRecord(ev[1], s));
     switch (precision) {
         case GILA_FP64: hipLaunchKernelGGL(seg_combine_kernel<GILA_FP64>, cg, cb, 0, s, c); break;
