@@ -18,7 +18,10 @@ Force-Directed Algorithm on Giraph: Design and Experiments"):
     forces, and the synchronous coordinate update;
   * Section 5.1, the cap schedule sqrt((n/a) d) 0.93^h and the halting rule;
   * Sections 4.3 and 4.6, pruning of degree-one vertices, repulsion weighted
-    by the pruned leaves, and reinsertion of the leaves on a small circle.
+    by the pruned leaves, and reinsertion of the leaves on a small circle;
+  * Sections 4.6 and 5.1, connected components laid out one by one, each
+    with the cap of its own vertex count and initial aspect ratio, and their
+    drawings packed in a matrix.
 """
 from __future__ import annotations
 
@@ -86,8 +89,12 @@ def _load():
     lib.orc_pruned_graph.argtypes = [ctypes.c_int32, _i64p, _i32p, _i32p, _i64p, _i32p]
     lib.orc_reinsert.argtypes = [ctypes.c_int32, _i32p, _i32p, _i32p, ctypes.c_int32, _i64p,
                                  _i32p, ctypes.c_double, _f64p, _f64p]
+    lib.orc_components.argtypes = [ctypes.c_int32, _i64p, _i32p, _i32p,
+                                   ctypes.POINTER(ctypes.c_int32)]
+    lib.orc_pack.argtypes = [ctypes.c_int32, _i32p, ctypes.c_double, _f64p]
     for f in ("orc_khop_count", "orc_khop_fill", "orc_forces", "orc_cap", "orc_step",
-              "orc_layout", "orc_prune", "orc_pruned_graph", "orc_reinsert"):
+              "orc_layout", "orc_prune", "orc_pruned_graph", "orc_reinsert", "orc_components",
+              "orc_pack"):
         getattr(lib, f).restype = ctypes.c_int
     lib.orc_paper_schedule.restype = None
     lib.orc_linear_schedule.restype = None
@@ -318,3 +325,78 @@ def reinsert(pr: Pruned, d: float, pos_kept) -> np.ndarray:
     _check(lib.orc_reinsert(n, anchor, leaves, new_id, pr.n, pr.row_ptr, ci, float(d), pk, out),
            "reinsert")
     return out[: 2 * n].reshape(-1, 2)
+
+
+def components(n: int, row_ptr, col_idx):
+    """Connected components: (label int32[n] = smallest id of the component,
+    count)."""
+    lib = _load()
+    rp, ci = _csr(row_ptr, col_idx)
+    if ci.size == 0:
+        ci = np.zeros(1, dtype=np.int32)
+    label = np.zeros(max(n, 1), dtype=np.int32)
+    c = ctypes.c_int32(0)
+    _check(lib.orc_components(n, rp, ci, label, ctypes.byref(c)), "components")
+    return label[:n], int(c.value)
+
+
+def pack(label, gap: float, pos) -> np.ndarray:
+    """Components' drawings packed in a matrix (Section 4.6); returns new
+    positions (float64[n, 2])."""
+    lab = np.ascontiguousarray(label, dtype=np.int32)
+    x = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1).copy()
+    n = lab.size
+    if n == 0:
+        return x.reshape(-1, 2)
+    _check(_load().orc_pack(n, lab, float(gap), x), "pack")
+    return x.reshape(-1, 2)
+
+
+def component_aspect(x: np.ndarray) -> float:
+    """Height / width of the frame enclosing a drawing (Section 5.1); 1 for a
+    degenerate frame (zero width or height)."""
+    w = float(x[:, 0].max() - x[:, 0].min())
+    h = float(x[:, 1].max() - x[:, 1].min())
+    return h / w if w > 0.0 and h > 0.0 else 1.0
+
+
+def subgraph(row_ptr, col_idx, verts):
+    """CSR of the subgraph induced by ascending vertex list verts, in local
+    ids (position in verts)."""
+    rp, ci = _csr(row_ptr, col_idx)
+    local = {int(v): i for i, v in enumerate(verts)}
+    out_rp = np.zeros(len(verts) + 1, dtype=np.int64)
+    cols = []
+    for i, v in enumerate(verts):
+        row = [local[int(u)] for u in ci[rp[v]:rp[v + 1]] if int(u) in local]
+        cols.extend(row)
+        out_rp[i + 1] = out_rp[i] + len(row)
+    return out_rp, np.asarray(cols, dtype=np.int32)
+
+
+def layout_components(n: int, row_ptr, col_idx, k: int, d: float, iterations: int, pos,
+                      stop_fraction: float = 0.15, stop_displacement: float = 0.01,
+                      p: int = 2, q: int = 1, gap: float | None = None):
+    """Sections 4.6 and 5.1: every connected component with at least two
+    vertices is laid out on its own, from its vertices' positions in pos, with
+    the cap sqrt((n_C / a_C) d) 0.93^h (n_C its vertex count, a_C the aspect
+    ratio of its initial drawing) and its own halting rule; then the drawings
+    are packed (gap d unless given).  Returns (pos, label, {label: iterations
+    run})."""
+    label, _ = components(n, row_ptr, col_idx)
+    x = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 2).copy()
+    runs = {}
+    for root in np.flatnonzero(label == np.arange(n)):
+        verts = np.flatnonzero(label == root)
+        if verts.size < 2:
+            continue
+        srp, sci = subgraph(row_ptr, col_idx, verts)
+        x0 = x[verts]
+        temps = paper_schedule(verts.size, component_aspect(x0), d, iterations)
+        kp, ki = khop(verts.size, srp, sci, k)
+        xf, run, _ = layout(verts.size, srp, sci, kp, ki, d, temps, x0,
+                            stop_fraction=stop_fraction, stop_displacement=stop_displacement,
+                            p=p, q=q)
+        x[verts] = xf
+        runs[int(root)] = run
+    return pack(label, d if gap is None else gap, x), label, runs

@@ -27,6 +27,10 @@
  *   - Halting statistic: number of vertices displaced by more than a
  *     threshold (Section 5.1: stop when fewer than 15% moved more than 0.01).
  *
+ *   - Connected components, each laid out on its own with the cap
+ *     sqrt((n_C / a_C) d) 0.93^h of its vertex count and initial aspect
+ *     ratio (Sections 4.6, 5.1), and the drawings packed in a matrix
+ *     (Section 4.6; the per-component driver is in __init__.py).
  *   - Pruning of degree-one vertices before the layout (Section 4.3), the
  *     repulsion exerted by a vertex weighted by its pruned leaves
  *     (Section 4.6), and reinsertion of the leaves on a circle around their
@@ -491,6 +495,135 @@ int orc_reinsert(int32_t n, const int32_t* anchor, const int32_t* leaves, const 
     free(next_j);
     free(phi);
     free(rho);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Connected components and packing (Section 4.6)                      */
+/* ------------------------------------------------------------------ */
+
+/* label[v] = the smallest vertex id of v's connected component (a BFS from
+ * every unlabelled vertex in ascending order).  *count_out = number of
+ * components. */
+int orc_components(int32_t n, const int64_t* row_ptr, const int32_t* col_idx, int32_t* label,
+                   int32_t* count_out) {
+    if (n < 0) return ORC_EINVAL;
+    int32_t* queue = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    if (!queue) return ORC_ENOMEM;
+    for (int32_t v = 0; v < n; ++v) label[v] = -1;
+    int32_t count = 0;
+    for (int32_t s = 0; s < n; ++s) {
+        if (label[s] >= 0) continue;
+        ++count;
+        int32_t head = 0, tail = 0;
+        label[s] = s;
+        queue[tail++] = s;
+        while (head < tail) {
+            const int32_t v = queue[head++];
+            for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+                const int32_t u = col_idx[e];
+                if (label[u] < 0) {
+                    label[u] = s;
+                    queue[tail++] = u;
+                }
+            }
+        }
+    }
+    free(queue);
+    *count_out = count;
+    return ORC_OK;
+}
+
+typedef struct {
+    int32_t label, size;
+    double minx, miny, maxx, maxy;
+} orc_comp;
+
+static int cmp_comp(const void* a, const void* b) {
+    const orc_comp* x = (const orc_comp*)a;
+    const orc_comp* y = (const orc_comp*)b;
+    if (x->size != y->size) return x->size > y->size ? -1 : 1;  /* larger first */
+    return (x->label > y->label) - (x->label < y->label);      /* then smaller label */
+}
+
+/* Packing of the components' drawings in a matrix (Section 4.6).  Components
+ * in order of decreasing vertex count (ties: smaller label first) fill a
+ * matrix of ceil(sqrt(C)) columns row by row.  Column c is as wide as the
+ * widest bounding box in it, row r as tall as the tallest; consecutive
+ * columns and rows are `gap` apart, the first cell's corner is the origin, and
+ * each drawing is translated so that its bounding box's lower-left corner is
+ * its cell's lower-left corner.  pos [n][2] is changed in place. */
+int orc_pack(int32_t n, const int32_t* label, double gap, double* pos) {
+    if (n < 0 || !(gap >= 0.0)) return ORC_EINVAL;
+    if (n == 0) return ORC_OK;
+    int32_t* slot = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);  /* root -> component index */
+    int32_t C = 0;
+    for (int32_t v = 0; v < n; ++v) C += label[v] == v;
+    orc_comp* comp = (orc_comp*)malloc(sizeof(orc_comp) * (size_t)C);
+    int32_t* rank = (int32_t*)malloc(sizeof(int32_t) * (size_t)C);
+    if (!slot || !comp || !rank) {
+        free(slot);
+        free(comp);
+        free(rank);
+        return ORC_ENOMEM;
+    }
+    int32_t c = 0;
+    for (int32_t v = 0; v < n; ++v)
+        if (label[v] == v) {
+            slot[v] = c;
+            comp[c].label = v;
+            comp[c].size = 0;
+            comp[c].minx = comp[c].miny = INFINITY;
+            comp[c].maxx = comp[c].maxy = -INFINITY;
+            ++c;
+        }
+    for (int32_t v = 0; v < n; ++v) {
+        orc_comp* k = &comp[slot[label[v]]];
+        const double x = pos[2 * (int64_t)v], y = pos[2 * (int64_t)v + 1];
+        k->size += 1;
+        if (x < k->minx) k->minx = x;
+        if (x > k->maxx) k->maxx = x;
+        if (y < k->miny) k->miny = y;
+        if (y > k->maxy) k->maxy = y;
+    }
+    qsort(comp, (size_t)C, sizeof(orc_comp), cmp_comp);
+    for (int32_t r = 0; r < C; ++r) slot[comp[r].label] = r;  /* root -> rank */
+    int32_t cols = 1;
+    while ((int64_t)cols * cols < C) ++cols;
+    const int32_t rows = (C + cols - 1) / cols;
+    double* colx = (double*)calloc((size_t)cols + 1, sizeof(double));
+    double* rowy = (double*)calloc((size_t)rows + 1, sizeof(double));
+    double* colw = (double*)calloc((size_t)cols, sizeof(double));
+    double* rowh = (double*)calloc((size_t)rows, sizeof(double));
+    if (!colx || !rowy || !colw || !rowh) {
+        free(slot);
+        free(comp);
+        free(rank);
+        free(colx);
+        free(rowy);
+        free(colw);
+        free(rowh);
+        return ORC_ENOMEM;
+    }
+    for (int32_t r = 0; r < C; ++r) {
+        const double w = comp[r].maxx - comp[r].minx, h = comp[r].maxy - comp[r].miny;
+        if (w > colw[r % cols]) colw[r % cols] = w;
+        if (h > rowh[r / cols]) rowh[r / cols] = h;
+    }
+    for (int32_t j = 0; j < cols; ++j) colx[j + 1] = colx[j] + colw[j] + gap;
+    for (int32_t j = 0; j < rows; ++j) rowy[j + 1] = rowy[j] + rowh[j] + gap;
+    for (int32_t v = 0; v < n; ++v) {
+        const int32_t r = slot[label[v]];
+        pos[2 * (int64_t)v] += colx[r % cols] - comp[r].minx;
+        pos[2 * (int64_t)v + 1] += rowy[r / cols] - comp[r].miny;
+    }
+    free(slot);
+    free(comp);
+    free(rank);
+    free(colx);
+    free(rowy);
+    free(colw);
+    free(rowh);
     return ORC_OK;
 }
 
