@@ -268,6 +268,43 @@ int gila_layout_pruned(const gila_csr* g_dev, int32_t k, const gila_params* para
                        void* stream, gila_stats* out);
 
 /* ------------------------------------------------------------------ */
+/* Connected components: each laid out alone, then packed (Section 4.6) */
+/* ------------------------------------------------------------------ */
+
+/* label_dev[v] (device int32[n]) = the smallest vertex id of v's connected
+ * component.  count_out (may be NULL) receives the number of components.
+ * The graph is validated as for gila_build_khop.  Synchronises `stream`. */
+int gila_components(const gila_csr* g_dev, int32_t* label_dev, int32_t* count_out, void* stream);
+
+/* Packs the drawings of the components in a matrix (Section 4.6), in place:
+ * components in order of decreasing vertex count (ties: smaller label) fill
+ * ceil(sqrt(C)) columns row by row; a column is as wide as its widest drawing
+ * and a row as tall as its tallest, consecutive columns and rows `gap` apart,
+ * the first cell's lower-left corner at the origin; every drawing is
+ * translated so that its bounding box's lower-left corner is its cell's.
+ * label_dev as gila_components writes it (each label in [0, n) and naming a
+ * vertex labelled with itself; EINVAL otherwise).  Synchronises `stream`. */
+int gila_pack_components(int32_t n, const int32_t* label_dev, double gap, int32_t precision,
+                         void* pos_dev, void* stream);
+
+/* Sections 4.6 and 5.1 on one graph: every connected component with at least
+ * two vertices is laid out on its own from its vertices' positions in pos_dev,
+ * for params->iterations iterations with the cap
+ * sqrt((n_C / a_C) d) 0.93^h -- n_C its vertex count, a_C the height / width
+ * of its initial drawing's bounding box (1 when that box has no area) -- and
+ * with params' halting rule applied to the component alone; then the
+ * drawings are packed with gap d (gila_pack_components).
+ * params->temperature is ignored (may be NULL).  Components of up to 2048
+ * vertices run together in one batched launch when the force model is FR,
+ * larger ones on the whole GPU one after another.  components_out: number of
+ * components; iterations_host (host int32[n]): for every vertex, the
+ * iterations its component ran (0 for a vertex without edges).  Either may
+ * be NULL.  Synchronises `stream`. */
+int gila_layout_components(const gila_csr* g_dev, int32_t k, const gila_params* params,
+                           void* pos_dev, void* stream, int32_t* components_out,
+                           int32_t* iterations_host);
+
+/* ------------------------------------------------------------------ */
 /* Many graphs in one launch                                            */
 /* ------------------------------------------------------------------ */
 typedef struct gila_batch gila_batch;

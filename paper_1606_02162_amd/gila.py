@@ -110,6 +110,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "gila_reinsert": (ctypes.c_int, [vp, dbl, i32, vp, vp, vp]),
         "gila_pruned_free": (None, [vp]),
         "gila_layout_pruned": (ctypes.c_int, [P(Csr), i32, P(_Params), vp, vp, P(Stats)]),
+        "gila_components": (ctypes.c_int, [P(Csr), vp, P(i32), vp]),
+        "gila_pack_components": (ctypes.c_int, [i32, vp, dbl, i32, vp, vp]),
+        "gila_layout_components": (ctypes.c_int, [P(Csr), i32, P(_Params), vp, vp, P(i32), vp]),
         "gila_init_positions": (ctypes.c_int, [i32, u64, dbl, dbl, i32, vp, vp]),
         "gila_step": (ctypes.c_int, [vp, P(_Params), i32, vp, vp, vp, vp, P(Stats)]),
         "gila_run": (ctypes.c_int, [vp, P(_Params), i32, i32, vp, vp, P(Stats)]),
@@ -435,6 +438,46 @@ def layout_pruned(row_ptr, col_idx, k: int, params: LayoutParams, pos, stream=No
     _check(_lib.gila_layout_pruned(ctypes.byref(csr), int(k), ctypes.byref(p), _ptr(pos),
                                    _stream(stream), ctypes.byref(st)), "gila_layout_pruned")
     return st
+
+
+# ---------------------------------------------------------------- components
+def components(row_ptr, col_idx, stream=None):
+    """(label int32 device tensor: smallest id of each vertex's component,
+    number of components) -- gila_components."""
+    import torch
+    csr = make_csr(row_ptr, col_idx)
+    label = torch.empty(max(csr.n, 1), dtype=torch.int32, device=row_ptr.device)
+    c = ctypes.c_int32()
+    _check(_lib.gila_components(ctypes.byref(csr), _ptr(label), ctypes.byref(c), _stream(stream)),
+           "gila_components")
+    return label[: csr.n], c.value
+
+
+def pack_components(label, gap: float, precision: int, pos, stream=None):
+    """Pack the components' drawings in place (gila_pack_components)."""
+    _check(_lib.gila_pack_components(int(label.shape[0]), _ptr(label), float(gap), int(precision),
+                                     _ptr(pos), _stream(stream)), "gila_pack_components")
+    return pos
+
+
+def layout_components(row_ptr, col_idx, k: int, params: LayoutParams, pos, iterations=None,
+                      stream=None):
+    """Lay out every component alone with its own cap and halting rule, then
+    pack (gila_layout_components).  The caps are the components' own:
+    params.temperature only gives the iteration count unless `iterations` is
+    set.  Returns (components, int32[n] iterations run by each vertex's
+    component)."""
+    csr = make_csr(row_ptr, col_idx)
+    p = params.as_struct()
+    if iterations is not None:
+        p.iterations = int(iterations)
+        p.temperature = None
+    c = ctypes.c_int32()
+    runs = np.zeros(max(csr.n, 1), dtype=np.int32)
+    _check(_lib.gila_layout_components(ctypes.byref(csr), int(k), ctypes.byref(p), _ptr(pos),
+                                       _stream(stream), ctypes.byref(c), runs.ctypes.data),
+           "gila_layout_components")
+    return c.value, runs[: csr.n]
 
 
 # ---------------------------------------------------------------- batches

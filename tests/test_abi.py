@@ -29,7 +29,8 @@ def test_header_declares_the_boundary():
     names = _declared()
     for required in ("gila_build_khop", "gila_step", "gila_run", "gila_layout", "gila_submit",
                      "gila_poll", "gila_layout_batch", "gila_khop_export", "gila_prune",
-                     "gila_reinsert", "gila_khop_set_mass", "gila_layout_pruned"):
+                     "gila_reinsert", "gila_khop_set_mass", "gila_layout_pruned",
+                     "gila_components", "gila_pack_components", "gila_layout_components"):
         assert required in names
 
 
@@ -92,6 +93,12 @@ def test_argument_validation_before_device_work():
     assert L.gila_layout_pruned(ctypes.byref(csr), 0, ctypes.byref(p), None, None,
                                 ctypes.byref(st)) == gila.GILA_EINVAL
     assert b"k must be" in L.gila_last_error()
+    # components: null graph, bad sizes, bad k
+    assert L.gila_components(None, None, None, None) == gila.GILA_EINVAL
+    assert L.gila_pack_components(-1, None, 1.0, 1, None, None) == gila.GILA_EINVAL
+    assert L.gila_pack_components(4, None, 1.0, 1, None, None) == gila.GILA_EINVAL
+    assert L.gila_layout_components(ctypes.byref(csr), 0, ctypes.byref(p), None, None, None,
+                                    None) == gila.GILA_EINVAL
 
 
 def test_params_validation():
