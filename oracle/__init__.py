@@ -361,17 +361,22 @@ def component_aspect(x: np.ndarray) -> float:
 
 
 def subgraph(row_ptr, col_idx, verts):
-    """CSR of the subgraph induced by ascending vertex list verts, in local
-    ids (position in verts)."""
+    """CSR of the subgraph induced by an ascending vertex list that is closed
+    under adjacency (a union of components), in local ids (position in
+    verts)."""
     rp, ci = _csr(row_ptr, col_idx)
-    local = {int(v): i for i, v in enumerate(verts)}
-    out_rp = np.zeros(len(verts) + 1, dtype=np.int64)
-    cols = []
-    for i, v in enumerate(verts):
-        row = [local[int(u)] for u in ci[rp[v]:rp[v + 1]] if int(u) in local]
-        cols.extend(row)
-        out_rp[i + 1] = out_rp[i] + len(row)
-    return out_rp, np.asarray(cols, dtype=np.int32)
+    verts = np.asarray(verts, dtype=np.int64)
+    local = np.full(rp.size - 1, -1, dtype=np.int64)
+    local[verts] = np.arange(verts.size)
+    lens = rp[verts + 1] - rp[verts]
+    out_rp = np.zeros(verts.size + 1, dtype=np.int64)
+    np.cumsum(lens, out=out_rp[1:])
+    # entry j of the output is entry rp[v] + (j - out_rp[i]) of v's row
+    first = np.repeat(rp[verts] - out_rp[:-1], lens)
+    cols = local[ci[first + np.arange(out_rp[-1])]]
+    if (cols < 0).any():
+        raise ValueError("vertex list is not closed under adjacency")
+    return out_rp, cols.astype(np.int32)
 
 
 def layout_components(n: int, row_ptr, col_idx, k: int, d: float, iterations: int, pos,
@@ -386,8 +391,13 @@ def layout_components(n: int, row_ptr, col_idx, k: int, d: float, iterations: in
     label, _ = components(n, row_ptr, col_idx)
     x = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 2).copy()
     runs = {}
-    for root in np.flatnonzero(label == np.arange(n)):
-        verts = np.flatnonzero(label == root)
+    # vertices grouped by label, ascending ids inside each group
+    order = np.argsort(label, kind="stable")
+    starts = np.flatnonzero(np.r_[True, label[order][1:] != label[order][:-1]]) if n else []
+    bounds = list(starts) + [n]
+    for j in range(len(bounds) - 1):
+        verts = order[bounds[j]:bounds[j + 1]]
+        root = label[verts[0]]
         if verts.size < 2:
             continue
         srp, sci = subgraph(row_ptr, col_idx, verts)
