@@ -21,7 +21,10 @@ Force-Directed Algorithm on Giraph: Design and Experiments"):
     by the pruned leaves, and reinsertion of the leaves on a small circle;
   * Sections 4.6 and 5.1, connected components laid out one by one, each
     with the cap of its own vertex count and initial aspect ratio, and their
-    drawings packed in a matrix.
+    drawings packed in a matrix;
+  * Section 5.2, the drawing-quality metrics: crossings, edge length
+    standard deviation, and the similarity of the drawing's Gabriel graph to
+    the graph.
 """
 from __future__ import annotations
 
@@ -92,9 +95,20 @@ def _load():
     lib.orc_components.argtypes = [ctypes.c_int32, _i64p, _i32p, _i32p,
                                    ctypes.POINTER(ctypes.c_int32)]
     lib.orc_pack.argtypes = [ctypes.c_int32, _i32p, ctypes.c_double, _f64p]
+    lib.orc_crossings.argtypes = [ctypes.c_int32, _i64p, _i32p, _f64p, vp,
+                                  ctypes.POINTER(ctypes.c_int64)]
+    lib.orc_edge_crossings.argtypes = [ctypes.c_int32, _i64p, _i32p, _f64p, ctypes.c_int64,
+                                       _i64p, _i64p]
+    lib.orc_edge_lengths.argtypes = [ctypes.c_int32, _i64p, _i32p, _f64p,
+                                     ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_double)]
+    lib.orc_gabriel.argtypes = [ctypes.c_int32, _f64p, _i64p, vp]
+    lib.orc_jaccard.argtypes = [ctypes.c_int32, _i64p, _i32p, _i64p, _i32p, vp,
+                                ctypes.POINTER(ctypes.c_double)]
     for f in ("orc_khop_count", "orc_khop_fill", "orc_forces", "orc_cap", "orc_step",
               "orc_layout", "orc_prune", "orc_pruned_graph", "orc_reinsert", "orc_components",
-              "orc_pack"):
+              "orc_pack", "orc_crossings", "orc_edge_crossings", "orc_edge_lengths", "orc_gabriel",
+              "orc_jaccard"):
         getattr(lib, f).restype = ctypes.c_int
     lib.orc_paper_schedule.restype = None
     lib.orc_linear_schedule.restype = None
@@ -410,3 +424,88 @@ def layout_components(n: int, row_ptr, col_idx, k: int, d: float, iterations: in
         x[verts] = xf
         runs[int(root)] = run
     return pack(label, d if gap is None else gap, x), label, runs
+
+
+def single(pos) -> np.ndarray:
+    """A drawing at single precision (where the metrics are evaluated), as
+    float64[n, 2]."""
+    return np.ascontiguousarray(np.asarray(pos, dtype=np.float64).reshape(-1, 2)
+                                .astype(np.float32).astype(np.float64))
+
+
+def edge_list(row_ptr, col_idx):
+    """Edges {u, v}, u < v, in row order: int32[m, 2]."""
+    rp, ci = _csr(row_ptr, col_idx)
+    v = np.repeat(np.arange(rp.size - 1, dtype=np.int32), np.diff(rp))
+    keep = ci > v
+    return np.stack([v[keep], ci[keep]], axis=1)
+
+
+def crossings(n: int, row_ptr, col_idx, pos, per_edge: bool = False):
+    """Number of crossing edge pairs of the drawing (Section 5.2), and with
+    per_edge the crossings of every edge (edge_list order)."""
+    rp, ci = _csr(row_ptr, col_idx)
+    if ci.size == 0:
+        ci = np.zeros(1, dtype=np.int32)
+    x = single(pos).reshape(-1)
+    if x.size == 0:
+        x = np.zeros(2)
+    m = int(edge_list(row_ptr, col_idx).shape[0])
+    pe = np.zeros(max(m, 1), dtype=np.int64)
+    tot = ctypes.c_int64(0)
+    _check(_load().orc_crossings(n, rp, ci, x, pe.ctypes.data_as(ctypes.c_void_p),
+                                 ctypes.byref(tot)), "crossings")
+    return (int(tot.value), pe[:m]) if per_edge else int(tot.value)
+
+
+def edge_crossings(n: int, row_ptr, col_idx, pos, edges):
+    """Crossings of the selected edges (indices into edge_list) with all edges."""
+    rp, ci = _csr(row_ptr, col_idx)
+    x = single(pos).reshape(-1)
+    sel = np.ascontiguousarray(edges, dtype=np.int64)
+    out = np.zeros(max(sel.size, 1), dtype=np.int64)
+    _check(_load().orc_edge_crossings(n, rp, ci, x, sel.size, sel, out), "edge_crossings")
+    return out[: sel.size]
+
+
+def edge_lengths(n: int, row_ptr, col_idx, pos):
+    """(mean, population standard deviation) of the edge lengths."""
+    rp, ci = _csr(row_ptr, col_idx)
+    if ci.size == 0:
+        ci = np.zeros(1, dtype=np.int32)
+    x = single(pos).reshape(-1)
+    if x.size == 0:
+        x = np.zeros(2)
+    mu, sd = ctypes.c_double(0), ctypes.c_double(0)
+    _check(_load().orc_edge_lengths(n, rp, ci, x, ctypes.byref(mu), ctypes.byref(sd)),
+           "edge_lengths")
+    return float(mu.value), float(sd.value)
+
+
+def gabriel(pos):
+    """Gabriel graph of the drawing's points (brute force): (ptr, idx)."""
+    x = single(pos)
+    n = x.shape[0]
+    xf = x.reshape(-1) if n else np.zeros(2)
+    ptr = np.zeros(n + 1, dtype=np.int64)
+    lib = _load()
+    _check(lib.orc_gabriel(n, xf, ptr, None), "gabriel")
+    idx = np.zeros(max(int(ptr[-1]), 1), dtype=np.int32)
+    _check(lib.orc_gabriel(n, xf, ptr, idx.ctypes.data_as(ctypes.c_void_p)), "gabriel")
+    return ptr, idx[: int(ptr[-1])]
+
+
+def similarity(n: int, row_ptr, col_idx, pos, per_vertex: bool = False):
+    """Mean Jaccard index between each vertex's neighbourhood in the graph
+    and in the drawing's Gabriel graph (Section 5.2)."""
+    rp, ci = _csr(row_ptr, col_idx)
+    gp, gi = gabriel(pos)
+    if ci.size == 0:
+        ci = np.zeros(1, dtype=np.int32)
+    if gi.size == 0:
+        gi = np.zeros(1, dtype=np.int32)
+    pv = np.zeros(max(n, 1))
+    mean = ctypes.c_double(0)
+    _check(_load().orc_jaccard(n, rp, ci, gp, gi, pv.ctypes.data_as(ctypes.c_void_p),
+                               ctypes.byref(mean)), "jaccard")
+    return (float(mean.value), pv[:n]) if per_vertex else float(mean.value)

@@ -31,6 +31,10 @@
  *     sqrt((n_C / a_C) d) 0.93^h of its vertex count and initial aspect
  *     ratio (Sections 4.6, 5.1), and the drawings packed in a matrix
  *     (Section 4.6; the per-component driver is in __init__.py).
+ *   - Drawing-quality metrics of Section 5.2: edge crossings, the standard
+ *     deviation of edge lengths, and the similarity of the drawing's Gabriel
+ *     graph to the graph (mean Jaccard index of the neighbourhoods),
+ *     evaluated on single-precision coordinates.
  *   - Pruning of degree-one vertices before the layout (Section 4.3), the
  *     repulsion exerted by a vertex weighted by its pruned leaves
  *     (Section 4.6), and reinsertion of the leaves on a circle around their
@@ -624,6 +628,213 @@ int orc_pack(int32_t n, const int32_t* label, double gap, double* pos) {
     free(rowy);
     free(colw);
     free(rowh);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Drawing-quality metrics (Section 5.2: crossings, edge length        */
+/* deviation, similarity of the drawing's Gabriel graph to the graph)   */
+/* ------------------------------------------------------------------ */
+
+/* Sign of the orientation of (a, b, c): > 0 counter-clockwise.  With
+ * single-precision coordinates every difference and product below is exact
+ * in double and one rounded subtraction keeps the sign, so the sign is
+ * exact. */
+static int orient(const double* a, const double* b, const double* c) {
+    const double l = (b[0] - a[0]) * (c[1] - a[1]);
+    const double r = (b[1] - a[1]) * (c[0] - a[0]);
+    const double d = l - r;
+    return (d > 0.0) - (d < 0.0);
+}
+
+/* Edges {u, v} (u < v) in row order: edge e is the e-th pair met when rows
+ * are read in ascending v and each row keeps its entries u > v. */
+static int64_t edge_list(int32_t n, const int64_t* row_ptr, const int32_t* col_idx, int32_t* eu,
+                         int32_t* ev) {
+    int64_t m = 0;
+    for (int32_t v = 0; v < n; ++v)
+        for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e)
+            if (col_idx[e] > v) {
+                if (eu) {
+                    eu[m] = v;
+                    ev[m] = col_idx[e];
+                }
+                ++m;
+            }
+    return m;
+}
+
+/* Two edges cross when they share no end vertex and each one's ends lie
+ * strictly on opposite sides of the other's line (touching, overlapping
+ * collinear edges and shared ends do not count). */
+static int edges_cross(const double* pos, int32_t a, int32_t b, int32_t c, int32_t d) {
+    if (a == c || a == d || b == c || b == d) return 0;
+    const double *pa = pos + 2 * (int64_t)a, *pb = pos + 2 * (int64_t)b;
+    const double *pc = pos + 2 * (int64_t)c, *pd = pos + 2 * (int64_t)d;
+    return orient(pa, pb, pc) * orient(pa, pb, pd) < 0 && orient(pc, pd, pa) * orient(pc, pd, pb) < 0;
+}
+
+/* Crossings of the drawing: per_edge[e] (may be NULL) = number of edges
+ * crossing edge e; *total = number of crossing pairs. */
+int orc_crossings(int32_t n, const int64_t* row_ptr, const int32_t* col_idx, const double* pos,
+                  int64_t* per_edge, int64_t* total) {
+    if (n < 0) return ORC_EINVAL;
+    const int64_t m = edge_list(n, row_ptr, col_idx, NULL, NULL);
+    int32_t* eu = (int32_t*)malloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));
+    int32_t* ev = (int32_t*)malloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));
+    if (!eu || !ev) {
+        free(eu);
+        free(ev);
+        return ORC_ENOMEM;
+    }
+    edge_list(n, row_ptr, col_idx, eu, ev);
+    int64_t sum = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : sum)
+    for (int64_t i = 0; i < m; ++i) {
+        int64_t c = 0;
+        for (int64_t j = 0; j < m; ++j)
+            if (j != i) c += edges_cross(pos, eu[i], ev[i], eu[j], ev[j]);
+        if (per_edge) per_edge[i] = c;
+        sum += c;
+    }
+    *total = sum / 2;
+    free(eu);
+    free(ev);
+    return ORC_OK;
+}
+
+/* Crossings of the edges sel[0..count) (indices into the edge list) with
+ * every edge. */
+int orc_edge_crossings(int32_t n, const int64_t* row_ptr, const int32_t* col_idx,
+                       const double* pos, int64_t count, const int64_t* sel, int64_t* out) {
+    const int64_t m = edge_list(n, row_ptr, col_idx, NULL, NULL);
+    int32_t* eu = (int32_t*)malloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));
+    int32_t* ev = (int32_t*)malloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));
+    if (!eu || !ev) {
+        free(eu);
+        free(ev);
+        return ORC_ENOMEM;
+    }
+    edge_list(n, row_ptr, col_idx, eu, ev);
+    int rc = ORC_OK;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t k = 0; k < count; ++k) {
+        const int64_t i = sel[k];
+        if (i < 0 || i >= m) {
+            rc = ORC_EINVAL;
+            continue;
+        }
+        int64_t c = 0;
+        for (int64_t j = 0; j < m; ++j)
+            if (j != i) c += edges_cross(pos, eu[i], ev[i], eu[j], ev[j]);
+        out[k] = c;
+    }
+    free(eu);
+    free(ev);
+    return rc;
+}
+
+/* Mean and standard deviation (population, two passes) of the edge lengths. */
+int orc_edge_lengths(int32_t n, const int64_t* row_ptr, const int32_t* col_idx,
+                     const double* pos, double* mean, double* stdev) {
+    double s = 0.0;
+    int64_t m = 0;
+    for (int32_t v = 0; v < n; ++v)
+        for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+            const int32_t u = col_idx[e];
+            if (u <= v) continue;
+            const double dx = pos[2 * (int64_t)u] - pos[2 * (int64_t)v];
+            const double dy = pos[2 * (int64_t)u + 1] - pos[2 * (int64_t)v + 1];
+            s += sqrt(dx * dx + dy * dy);
+            ++m;
+        }
+    if (m == 0) {
+        *mean = 0.0;
+        *stdev = 0.0;
+        return ORC_OK;
+    }
+    const double mu = s / (double)m;
+    double q = 0.0;
+    for (int32_t v = 0; v < n; ++v)
+        for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+            const int32_t u = col_idx[e];
+            if (u <= v) continue;
+            const double dx = pos[2 * (int64_t)u] - pos[2 * (int64_t)v];
+            const double dy = pos[2 * (int64_t)u + 1] - pos[2 * (int64_t)v + 1];
+            const double z = sqrt(dx * dx + dy * dy) - mu;
+            q += z * z;
+        }
+    *mean = mu;
+    *stdev = sqrt(q / (double)m);
+    return ORC_OK;
+}
+
+/* Gabriel graph of the points (brute force): u and v are adjacent when no
+ * other point lies in the closed disc with diameter uv, i.e. when
+ * (w - u).(w - v) > 0 for every other w.  deg[u] = Gabriel degree; with
+ * adj != NULL also the rows (ascending; adj_ptr [n+1] as computed by a
+ * first call with adj == NULL). */
+static int gabriel_pair(int32_t n, const double* pos, int32_t u, int32_t v) {
+    const double ux = pos[2 * (int64_t)u], uy = pos[2 * (int64_t)u + 1];
+    const double vx = pos[2 * (int64_t)v], vy = pos[2 * (int64_t)v + 1];
+    for (int32_t w = 0; w < n; ++w) {
+        if (w == u || w == v) continue;
+        const double wx = pos[2 * (int64_t)w], wy = pos[2 * (int64_t)w + 1];
+        const double dot = (wx - ux) * (wx - vx) + (wy - uy) * (wy - vy);
+        if (dot <= 0.0) return 0;
+    }
+    return 1;
+}
+
+int orc_gabriel(int32_t n, const double* pos, int64_t* adj_ptr, int32_t* adj) {
+    if (n < 0) return ORC_EINVAL;
+    if (!adj) {
+        adj_ptr[0] = 0;
+        int64_t* cnt = (int64_t*)calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));
+        if (!cnt) return ORC_ENOMEM;
+#pragma omp parallel for schedule(dynamic, 4)
+        for (int32_t u = 0; u < n; ++u)
+            for (int32_t v = 0; v < n; ++v)
+                if (v != u && gabriel_pair(n, pos, u, v)) cnt[u] += 1;
+        for (int32_t u = 0; u < n; ++u) adj_ptr[u + 1] = adj_ptr[u] + cnt[u];
+        free(cnt);
+        return ORC_OK;
+    }
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int32_t u = 0; u < n; ++u) {
+        int64_t o = adj_ptr[u];
+        for (int32_t v = 0; v < n; ++v)
+            if (v != u && gabriel_pair(n, pos, u, v)) adj[o++] = v;
+    }
+    return ORC_OK;
+}
+
+/* Similarity (Section 5.2): for every vertex the Jaccard index of its
+ * neighbourhood in the graph and in the Gabriel graph, |A n B| / |A u B|
+ * (1 when both are empty), averaged over the vertices; per_vertex (may be
+ * NULL) receives the indices.  Both row sets ascending. */
+int orc_jaccard(int32_t n, const int64_t* row_ptr, const int32_t* col_idx, const int64_t* gg_ptr,
+                const int32_t* gg, double* per_vertex, double* mean) {
+    double s = 0.0;
+    for (int32_t v = 0; v < n; ++v) {
+        int64_t i = row_ptr[v], j = gg_ptr[v], both = 0;
+        while (i < row_ptr[v + 1] && j < gg_ptr[v + 1]) {
+            if (col_idx[i] == gg[j]) {
+                ++both;
+                ++i;
+                ++j;
+            } else if (col_idx[i] < gg[j]) {
+                ++i;
+            } else {
+                ++j;
+            }
+        }
+        const int64_t uni = (row_ptr[v + 1] - row_ptr[v]) + (gg_ptr[v + 1] - gg_ptr[v]) - both;
+        const double J = uni == 0 ? 1.0 : (double)both / (double)uni;
+        if (per_vertex) per_vertex[v] = J;
+        s += J;
+    }
+    *mean = n > 0 ? s / (double)n : 1.0;
     return ORC_OK;
 }
 
