@@ -305,6 +305,41 @@ int gila_layout_components(const gila_csr* g_dev, int32_t k, const gila_params* 
                            int32_t* iterations_host);
 
 /* ------------------------------------------------------------------ */
+/* Drawing-quality metrics (Section 5.2)                                */
+/* ------------------------------------------------------------------ */
+enum {
+    GILA_METRIC_CROSSINGS = 1,   /* edge crossings (all pairs of edges: O(m^2) work) */
+    GILA_METRIC_LENGTHS = 2,     /* mean and standard deviation of the edge lengths */
+    GILA_METRIC_SIMILARITY = 4   /* Gabriel-graph similarity */
+};
+
+typedef struct gila_metrics {
+    int64_t edges;              /* m: undirected edges */
+    int64_t crossings;          /* pairs of edges that cross (no shared end; each end strictly
+                                   on the opposite side of the other edge's line) */
+    double edge_length_mean;
+    double edge_length_std;     /* population standard deviation */
+    double similarity;          /* mean over vertices of the Jaccard index of the vertex's
+                                   neighbours in the graph and in the Gabriel graph of the
+                                   drawing's points (1 for a vertex with neither) */
+    int64_t gabriel_edges;      /* edges of that Gabriel graph: u, v adjacent when no other
+                                   point lies in the closed disc with diameter uv */
+} gila_metrics;
+
+/* The quality measures of Section 5.2 for the drawing pos_dev (positions in
+ * `precision`'s layout, taken at single precision, where the orientation and
+ * in-disc tests are exact) of the graph g_dev (validated as for
+ * gila_build_khop).  `what` is an OR of GILA_METRIC_*; the others are left 0
+ * (similarity 1).  edge_crossings_dev (device int64[m], may be NULL)
+ * receives the crossings of every edge, edges {u, v} with u < v numbered in
+ * row order (row v, its entries above v); jaccard_dev (device double[n], may
+ * be NULL) the per-vertex Jaccard indices.  Positions must be finite for the
+ * similarity (EINVAL otherwise).  Synchronises `stream`. */
+int gila_drawing_metrics(const gila_csr* g_dev, int32_t precision, const void* pos_dev,
+                         int32_t what, void* stream, gila_metrics* out,
+                         int64_t* edge_crossings_dev, double* jaccard_dev);
+
+/* ------------------------------------------------------------------ */
 /* Many graphs in one launch                                            */
 /* ------------------------------------------------------------------ */
 typedef struct gila_batch gila_batch;

@@ -76,6 +76,20 @@ PARAMS_DTYPE = np.dtype({"names": ["precision", "ideal_length", "iterations", "t
                          "itemsize": ctypes.sizeof(_Params)})
 
 
+METRIC_CROSSINGS = 1
+METRIC_LENGTHS = 2
+METRIC_SIMILARITY = 4
+
+
+class Metrics(ctypes.Structure):
+    _fields_ = [("edges", ctypes.c_int64), ("crossings", ctypes.c_int64),
+                ("edge_length_mean", ctypes.c_double), ("edge_length_std", ctypes.c_double),
+                ("similarity", ctypes.c_double), ("gabriel_edges", ctypes.c_int64)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class Stats(ctypes.Structure):
     _fields_ = [("iterations_run", ctypes.c_int32), ("stopped", ctypes.c_int32),
                 ("moved", ctypes.c_int64), ("max_disp", ctypes.c_double),
@@ -111,6 +125,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "gila_pruned_free": (None, [vp]),
         "gila_layout_pruned": (ctypes.c_int, [P(Csr), i32, P(_Params), vp, vp, P(Stats)]),
         "gila_components": (ctypes.c_int, [P(Csr), vp, P(i32), vp]),
+        "gila_drawing_metrics": (ctypes.c_int, [P(Csr), i32, vp, i32, vp, P(Metrics), vp, vp]),
         "gila_pack_components": (ctypes.c_int, [i32, vp, dbl, i32, vp, vp]),
         "gila_layout_components": (ctypes.c_int, [P(Csr), i32, P(_Params), vp, vp, P(i32), vp]),
         "gila_init_positions": (ctypes.c_int, [i32, u64, dbl, dbl, i32, vp, vp]),
@@ -478,6 +493,21 @@ def layout_components(row_ptr, col_idx, k: int, params: LayoutParams, pos, itera
                                        _stream(stream), ctypes.byref(c), runs.ctypes.data),
            "gila_layout_components")
     return c.value, runs[: csr.n]
+
+
+# ---------------------------------------------------------------- quality metrics
+def drawing_metrics(row_ptr, col_idx, precision: int, pos, what: int = 7, edge_crossings=None,
+                    jaccard=None, stream=None) -> Metrics:
+    """Crossings, edge length mean / deviation and Gabriel similarity of a
+    drawing (gila_drawing_metrics); edge_crossings (int64 device tensor [m])
+    and jaccard (float64 device tensor [n]) are optional per-edge and
+    per-vertex outputs."""
+    csr = make_csr(row_ptr, col_idx)
+    out = Metrics()
+    _check(_lib.gila_drawing_metrics(ctypes.byref(csr), int(precision), _ptr(pos), int(what),
+                                     _stream(stream), ctypes.byref(out), _ptr(edge_crossings),
+                                     _ptr(jaccard)), "gila_drawing_metrics")
+    return out
 
 
 # ---------------------------------------------------------------- batches

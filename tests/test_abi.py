@@ -30,7 +30,8 @@ def test_header_declares_the_boundary():
     for required in ("gila_build_khop", "gila_step", "gila_run", "gila_layout", "gila_submit",
                      "gila_poll", "gila_layout_batch", "gila_khop_export", "gila_prune",
                      "gila_reinsert", "gila_khop_set_mass", "gila_layout_pruned",
-                     "gila_components", "gila_pack_components", "gila_layout_components"):
+                     "gila_components", "gila_pack_components", "gila_layout_components",
+                     "gila_drawing_metrics"):
         assert required in names
 
 
@@ -99,6 +100,12 @@ def test_argument_validation_before_device_work():
     assert L.gila_pack_components(4, None, 1.0, 1, None, None) == gila.GILA_EINVAL
     assert L.gila_layout_components(ctypes.byref(csr), 0, ctypes.byref(p), None, None, None,
                                     None) == gila.GILA_EINVAL
+    # metrics: no output struct, bad precision
+    mt = gila.Metrics()
+    assert L.gila_drawing_metrics(ctypes.byref(csr), 1, None, 7, None, None, None,
+                                  None) == gila.GILA_EINVAL
+    assert L.gila_drawing_metrics(ctypes.byref(csr), 9, None, 7, None, ctypes.byref(mt), None,
+                                  None) == gila.GILA_EINVAL
 
 
 def test_params_validation():

@@ -1,0 +1,145 @@
+"""GPU parity of the drawing-quality metrics (Section 5.2) against the FP64
+oracle: crossings (total and per edge) and per-vertex Jaccard indices
+bit-exact, edge length mean and deviation to 1e-12.  Degenerate drawings
+(grid points: collinear and cocircular; coincident points; collinear points)
+are included.  At full size (R-MAT 18): sampled per-edge crossings from the
+oracle, the edge lengths in full, and the similarity against a Gabriel
+graph built independently from scipy's Delaunay triangulation (a Delaunay
+edge is a Gabriel edge when both angles opposite it are acute).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_common import require_gpu
+from paper_1606_02162_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def G():
+    require_gpu()
+    from paper_1606_02162_amd import gila
+    return gila
+
+
+def _grid_xy(rows, cols):
+    n = rows * cols
+    return np.stack([np.arange(n) % cols, np.arange(n) // cols], axis=1).astype(float) * 3.0
+
+
+def metric_suite():
+    out = []
+    k = inputs.complete_graph(12)
+    th = 0.3 + 2 * math.pi * np.arange(12) / 12
+    out.append(("k12_convex", k, np.stack([100 * np.cos(th), 100 * np.sin(th)], 1)))
+    g = inputs.grid_graph(12, 15)
+    out.append(("grid_as_grid", g, _grid_xy(12, 15)))
+    out.append(("grid_random", g, inputs.uniform_positions(g.n, seed=3, width=50.0)))
+    e = inputs.erdos_renyi(400, 900, seed=5)
+    out.append(("er400", e, inputs.uniform_positions(e.n, seed=6, width=500.0)))
+    t = inputs.random_tree_plus_edges(500, 100, seed=7)
+    x = inputs.uniform_positions(t.n, seed=8, width=300.0)
+    x[10] = x[11]          # coincident points
+    x[20] = x[21] = x[22]
+    out.append(("tree_coincident", t, x))
+    p = inputs.path_graph(60)
+    out.append(("path_on_a_line", p, np.stack([np.arange(60.0) ** 1.5, np.zeros(60)], 1)))
+    s = inputs.star_graph(40)
+    out.append(("star", s, inputs.uniform_positions(s.n, seed=9, width=10.0)))
+    return out
+
+
+def _run(G, g, x, prec, what=7):
+    import torch
+    rp, ci = G.to_device_csr(g)
+    pos = torch.from_numpy(x).to(dtype=G.position_dtype(prec), device="cuda").contiguous()
+    m = int(oracle.edge_list(g.row_ptr, g.col_idx).shape[0])
+    ec = torch.zeros(max(m, 1), dtype=torch.int64, device="cuda")
+    jac = torch.zeros(max(g.n, 1), dtype=torch.float64, device="cuda")
+    out = G.drawing_metrics(rp, ci, prec, pos, what, ec, jac)
+    return out, ec.cpu().numpy()[:m], jac.cpu().numpy()[: g.n]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_metrics_small(G, precision):
+    prec = G.PRECISIONS[precision]
+    for name, g, x in metric_suite():
+        print(f"metrics {name} {precision}", flush=True)
+        xs = oracle.single(x)
+        out, ec, jac = _run(G, g, xs, prec)
+        tot, per = oracle.crossings(g.n, g.row_ptr, g.col_idx, xs, per_edge=True)
+        assert out.crossings == tot and np.array_equal(ec, per), name
+        mu, sd = oracle.edge_lengths(g.n, g.row_ptr, g.col_idx, xs)
+        assert out.edge_length_mean == pytest.approx(mu, rel=1e-12, abs=1e-300)
+        assert out.edge_length_std == pytest.approx(sd, rel=1e-10, abs=1e-12 * max(mu, 1.0))
+        sim, pj = oracle.similarity(g.n, g.row_ptr, g.col_idx, xs, per_vertex=True)
+        assert np.array_equal(jac, pj), name
+        assert out.similarity == pytest.approx(sim, rel=1e-12)
+        gp, _ = oracle.gabriel(xs)
+        assert out.gabriel_edges == int(gp[-1]) // 2
+        assert out.edges == g.m
+
+
+def test_metric_flags_and_empty(G):
+    import torch
+    g = inputs.erdos_renyi(100, 200, seed=2)
+    x = oracle.single(inputs.uniform_positions(g.n, seed=1, width=100.0))
+    out, _, _ = _run(G, g, x, G.FP32, what=G.METRIC_LENGTHS)
+    assert out.crossings == 0 and out.similarity == 1.0 and out.edge_length_mean > 0
+    e = inputs.to_csr(5, [], [])
+    out, _, jac = _run(G, e, oracle.single(inputs.uniform_positions(5, 2, 10.0)), G.FP32)
+    assert out.edges == 0 and out.crossings == 0
+    assert out.gabriel_edges > 0 and np.all(jac == 0.0)  # no graph edges, some Gabriel ones
+    bad = torch.full((4, 2), float("nan"), device="cuda")
+    rp, ci = G.to_device_csr(inputs.path_graph(4))
+    with pytest.raises(G.GilaError) as err:
+        G.drawing_metrics(rp, ci, G.FP32, bad, G.METRIC_SIMILARITY)
+    assert err.value.code == G.GILA_EINVAL
+
+
+def _delaunay_gabriel(x):
+    """Gabriel edges as the Delaunay edges whose opposite angles are acute."""
+    from scipy.spatial import Delaunay
+    tri = Delaunay(x)
+    opp = {}
+    for s in tri.simplices:
+        for a, b, c in ((s[0], s[1], s[2]), (s[1], s[2], s[0]), (s[2], s[0], s[1])):
+            key = (min(a, b), max(a, b))
+            opp.setdefault(key, []).append(c)
+    adj = [[] for _ in range(x.shape[0])]
+    for (a, b), cs in opp.items():
+        ok = all(((x[c] - x[a]) * (x[c] - x[b])).sum() > 0 for c in cs)
+        if ok:
+            adj[a].append(b)
+            adj[b].append(a)
+    return adj
+
+
+def test_metrics_full_size_rmat18(G):
+    """Random FP32 drawing of R-MAT 18: 64 sampled edges' crossings, the edge
+    lengths, and every vertex's Jaccard index against a Delaunay-derived
+    Gabriel graph."""
+    g = inputs.rmat(18, 4, 0.57, 0.19, 0.19, seed=3)
+    x = oracle.single(inputs.uniform_positions(g.n, seed=0, width=1200.0))
+    out, ec, jac = _run(G, g, x, G.FP32)
+    m = ec.size
+    sel = np.random.default_rng(4).choice(m, 64, replace=False)
+    assert np.array_equal(ec[sel], oracle.edge_crossings(g.n, g.row_ptr, g.col_idx, x, sel))
+    assert out.crossings == int(ec.sum()) // 2
+    mu, sd = oracle.edge_lengths(g.n, g.row_ptr, g.col_idx, x)
+    assert out.edge_length_mean == pytest.approx(mu, rel=1e-12)
+    assert out.edge_length_std == pytest.approx(sd, rel=1e-10)
+    adj = _delaunay_gabriel(x)
+    expect = np.empty(g.n)
+    for v in range(g.n):
+        gn = set(adj[v])
+        rn = set(g.col_idx[g.row_ptr[v]:g.row_ptr[v + 1]].tolist())
+        uni = len(gn | rn)
+        expect[v] = 1.0 if uni == 0 else len(gn & rn) / uni
+    assert np.array_equal(jac, expect)
+    assert out.gabriel_edges == sum(len(a) for a in adj) // 2
+    print(f"rmat18 crossings={out.crossings} sim={out.similarity:.6f} gabriel={out.gabriel_edges}")
