@@ -636,15 +636,47 @@ int orc_pack(int32_t n, const int32_t* label, double gap, double* pos) {
 /* deviation, similarity of the drawing's Gabriel graph to the graph)   */
 /* ------------------------------------------------------------------ */
 
-/* Sign of the orientation of (a, b, c): > 0 counter-clockwise.  With
- * single-precision coordinates every difference and product below is exact
- * in double and one rounded subtraction keeps the sign, so the sign is
- * exact. */
+/* Exact sign of a sum of doubles.  two_sum splits a + b into its rounded
+ * sum and the rounding error, both exact doubles (Knuth's algorithm).
+ * Adding the terms one by one into a list of such pieces, each new term
+ * passed through the list with two_sum, keeps the list's sum equal to the
+ * exact sum and leaves the pieces nonoverlapping in increasing magnitude
+ * (Shewchuk's expansion growth), so the sign of the sum is the sign of the
+ * last nonzero piece. */
+static void two_sum(double a, double b, double* s, double* e) {
+    const double x = a + b;
+    const double bv = x - a;
+    const double av = x - bv;
+    *s = x;
+    *e = (a - av) + (b - bv);
+}
+
+static int exact_sign(const double* term, int k) {
+    double piece[16];
+    int len = 0;
+    for (int i = 0; i < k; ++i) {
+        double q = term[i];
+        for (int j = 0; j < len; ++j) {
+            double s, e;
+            two_sum(q, piece[j], &s, &e);
+            piece[j] = e;
+            q = s;
+        }
+        piece[len++] = q;
+    }
+    for (int j = len - 1; j >= 0; --j)
+        if (piece[j] != 0.0) return piece[j] > 0.0 ? 1 : -1;
+    return 0;
+}
+
+/* Sign of the orientation of (a, b, c): > 0 counter-clockwise.  The
+ * determinant (b - a) x (c - a) is multiplied out into eight products of
+ * coordinates; coordinates are single-precision values, so each product is
+ * exact in double, and the sign of their sum is taken exactly. */
 static int orient(const double* a, const double* b, const double* c) {
-    const double l = (b[0] - a[0]) * (c[1] - a[1]);
-    const double r = (b[1] - a[1]) * (c[0] - a[0]);
-    const double d = l - r;
-    return (d > 0.0) - (d < 0.0);
+    const double t[8] = {b[0] * c[1], -(b[0] * a[1]), -(a[0] * c[1]), a[0] * a[1],
+                         -(b[1] * c[0]), b[1] * a[0], a[1] * c[0], -(a[1] * a[0])};
+    return exact_sign(t, 8);
 }
 
 /* Edges {u, v} (u < v) in row order: edge e is the e-th pair met when rows
@@ -780,8 +812,10 @@ static int gabriel_pair(int32_t n, const double* pos, int32_t u, int32_t v) {
     for (int32_t w = 0; w < n; ++w) {
         if (w == u || w == v) continue;
         const double wx = pos[2 * (int64_t)w], wy = pos[2 * (int64_t)w + 1];
-        const double dot = (wx - ux) * (wx - vx) + (wy - uy) * (wy - vy);
-        if (dot <= 0.0) return 0;
+        /* (w - u).(w - v) multiplied out; exact sign as in orient() */
+        const double t[8] = {wx * wx, -(wx * vx), -(ux * wx), ux * vx,
+                             wy * wy, -(wy * vy), -(uy * wy), uy * vy};
+        if (exact_sign(t, 8) <= 0) return 0;
     }
     return 1;
 }

@@ -11,6 +11,7 @@ the empty-disc test (Gabriel edges are Delaunay edges).  Jaccard: a hand
 computation on collinear points.
 """
 import math
+from fractions import Fraction
 from itertools import combinations
 
 import numpy as np
@@ -118,3 +119,82 @@ def test_jaccard_hand_computed():
     mean, per = oracle.similarity(4, g.row_ptr, g.col_idx, pos, per_vertex=True)
     np.testing.assert_allclose(per, [1 / 3, 1 / 2, 0, 0])
     assert mean == pytest.approx(5 / 24)
+
+
+# ---------------------------------------------------------------- exact signs
+def _frac_orient(a, b, c):
+    a, b, c = ([Fraction(float(t)) for t in p] for p in (a, b, c))
+    d = (b[0] - a[0]) * (c[1] - a[1]) - (b[1] - a[1]) * (c[0] - a[0])
+    return (d > 0) - (d < 0)
+
+
+def _frac_in_disc(u, v, w):
+    u, v, w = ([Fraction(float(t)) for t in p] for p in (u, v, w))
+    return (w[0] - u[0]) * (w[0] - v[0]) + (w[1] - u[1]) * (w[1] - v[1]) <= 0
+
+
+def _frac_crossings(edges, x):
+    per = np.zeros(len(edges), dtype=np.int64)
+    for i, (a, b) in enumerate(edges):
+        for j, (c, d) in enumerate(edges):
+            if i == j or len({a, b, c, d}) < 4:
+                continue
+            if (_frac_orient(x[a], x[b], x[c]) * _frac_orient(x[a], x[b], x[d]) < 0
+                    and _frac_orient(x[c], x[d], x[a]) * _frac_orient(x[c], x[d], x[b]) < 0):
+                per[i] += 1
+    return per
+
+
+def test_crossing_decided_exactly_near_tiny_coordinates():
+    """A vertex at (1e-20, 2e-20): the orientation of (256, 256) against the
+    edge to (512, 512) is (512 - 256)(d1 - d2), negative, but rounding each
+    difference in double gives 0; the edges do cross properly."""
+    d1, d2 = float(np.float32(1e-20)), float(np.float32(2e-20))
+    x = np.array([[d1, d2], [512.0, 512.0], [256.0, 256.0], [0.0, 512.0]])
+    g = inputs.to_csr(4, [0, 2], [1, 3])
+    naive = (x[1, 0] - x[0, 0]) * (x[2, 1] - x[0, 1]) - (x[1, 1] - x[0, 1]) * (x[2, 0] - x[0, 0])
+    assert naive == 0.0 and _frac_orient(x[0], x[1], x[2]) == -1
+    assert oracle.crossings(4, g.row_ptr, g.col_idx, x) == 1
+    # mirrored: the point lies on the other side, still a crossing
+    x2 = x.copy()
+    x2[0] = [d2, d1]
+    x2[3] = [512.0, 0.0]
+    assert _frac_orient(x2[0], x2[1], x2[2]) == 1
+    assert oracle.crossings(4, g.row_ptr, g.col_idx, x2) == 1
+
+
+def test_gabriel_disc_decided_exactly():
+    """u = (1e-20, 0), v = (2, 0), w = (1, 1): (w - u).(w - v) equals the tiny
+    x-coordinate of u, so w is just outside the disc on uv (rounded
+    differences give 0, inside); all three pairs are Gabriel edges."""
+    d = float(np.float32(1e-20))
+    x = np.array([[d, 0.0], [2.0, 0.0], [1.0, 1.0]])
+    assert not _frac_in_disc(x[0], x[1], x[2])
+    assert (x[2, 0] - x[0, 0]) * (x[2, 0] - x[1, 0]) + (x[2, 1] - x[0, 1]) * (x[2, 1] - x[1, 1]) == 0.0
+    ptr, idx = oracle.gabriel(x)
+    assert list(ptr) == [0, 2, 4, 6]
+    x[0, 0] = -d  # now w is inside: u and v are not adjacent
+    ptr, idx = oracle.gabriel(x)
+    assert list(idx[ptr[0]:ptr[1]]) == [2]
+
+
+@pytest.mark.parametrize("seed", [11, 12, 13])
+def test_exact_signs_on_near_degenerate_drawings(seed):
+    """Points drawn from a few coordinate values of very different
+    magnitudes (many collinear and cocircular triples, coincident points):
+    crossings per edge and the Gabriel graph against exact rational
+    arithmetic."""
+    rng = np.random.default_rng(seed)
+    vals = np.float32([0.0, 1e-20, -3e-20, 1.0, 2.0, 3.0, 1e-7, 1024.0, 1024.0000001, 5e9])
+    n = 11
+    x = vals[rng.integers(0, vals.size, (n, 2))].astype(np.float64)
+    g = inputs.erdos_renyi(n, 22, seed=seed)
+    edges = [tuple(e) for e in oracle.edge_list(g.row_ptr, g.col_idx)]
+    tot, per = oracle.crossings(g.n, g.row_ptr, g.col_idx, x, per_edge=True)
+    expect = _frac_crossings(edges, x)
+    assert np.array_equal(per, expect) and tot == expect.sum() // 2
+    ptr, idx = oracle.gabriel(x)
+    for u in range(n):
+        want = [v for v in range(n) if v != u and not any(
+            _frac_in_disc(x[u], x[v], x[w]) for w in range(n) if w not in (u, v))]
+        assert list(idx[ptr[u]:ptr[u + 1]]) == want, u
