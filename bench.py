@@ -126,13 +126,15 @@ def main() -> int:
     ap.add_argument("--scale", type=int, default=18)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=8)
-    ap.add_argument("--workload", choices=["rmat", "rmat_pruned", "rmat_components", "ba", "grid",
-                                           "batch", "serve"],
+    ap.add_argument("--workload", choices=["rmat", "rmat_pruned", "rmat_components",
+                                           "rmat_metrics", "ba", "grid", "batch", "serve"],
                     default="rmat",
                     help="rmat: one R-MAT graph (default line); rmat_pruned: the same graph "
                          "through pruning, leaf-weighted layout and reinsertion; ba: "
                          "Barabasi-Albert 100k; rmat_components: the same graph laid out "
-                         "component by component with their own caps, then packed; grid: "
+                         "component by component with their own caps, then packed; "
+                         "rmat_metrics: crossings, edge lengths and Gabriel similarity of its "
+                         "layout; grid: "
                          "32x32 grid in FP64; batch: 4096 graphs "
                          "in one persistent launch; serve: Poisson stream through the layout "
                          "server")
@@ -172,6 +174,8 @@ def main() -> int:
         return bench_pruned(args, single_graph_workloads(args)["rmat"])
     if args.workload == "rmat_components":
         return bench_components(args, single_graph_workloads(args)["rmat"])
+    if args.workload == "rmat_metrics":
+        return bench_metrics(args, single_graph_workloads(args)["rmat"])
 
     return bench_single(args, single_graph_workloads(args)[args.workload])
 
@@ -567,6 +571,91 @@ def bench_components(args, wl) -> int:
                        f"per-component pipeline with 1 and {1 + args.cpu_iters} iterations "
                        f"({tc1 - tc0:.2f} s, {tc2 - tc1:.2f} s); the difference gives "
                        f"{cpu_iter * 1e3:.0f} ms per iteration, extrapolated to {H}"),
+        }
+    print(json.dumps(out))
+    return 0
+
+
+# VALU lane operations per edge pair of the crossing test: four filtered
+# orientation signs (multiply, fused multiply-add, add and a bound compare
+# each) and two sign products with their compares; the combination of the
+# lane masks runs on the scalar unit
+CROSS_VALU_PER_PAIR = 20
+VALU_LANE_OPS_PER_S = 256 * 64 * 2.4e9  # CUs x lanes per cycle x clock
+
+
+def bench_metrics(args, wl) -> int:
+    """The drawing-quality metrics of Section 5.2 on the R-MAT 18 layout
+    (build + 500 iterations, untimed): a step is one gila_drawing_metrics
+    call with all three metrics (totals; no per-edge or per-vertex arrays).
+    value = m(m-1)/2 edge pairs tested per second."""
+    import torch
+
+    from paper_1606_02162_amd import gila
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    g = wl["make"]()
+    H, k, prec, d = wl["H"], wl["k"], wl["precision"], wl["d"]
+    rp, ci = gila.to_device_csr(g, dev)
+    pos = torch.empty((g.n, 2), dtype=gila.position_dtype(prec), device=dev)
+    gila.init_positions(g.n, wl["seed"], wl["frame"], wl["frame"], prec, pos)
+    params = gila.LayoutParams(temperature=wl["caps"](g, H), ideal_length=d, precision=prec)
+    kh = gila.build_khop(rp, ci, k)
+    gila.run(kh, params, pos)
+    kh.free()
+    m = g.m
+    for _ in range(args.warmup):
+        gila.drawing_metrics(rp, ci, prec, pos, 7)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        met = gila.drawing_metrics(rp, ci, prec, pos, 7)
+    torch.cuda.synchronize()
+    total_s = time.perf_counter() - t0
+    part = {}
+    for name, flag in (("crossings", gila.METRIC_CROSSINGS), ("lengths", gila.METRIC_LENGTHS),
+                       ("similarity", gila.METRIC_SIMILARITY)):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record(stream)
+        gila.drawing_metrics(rp, ci, prec, pos, flag)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        part[name] = ev[0].elapsed_time(ev[1])
+    pairs = float(m) * float(m - 1) / 2.0
+    value = pairs * args.steps / total_s
+    cross_rate = pairs / (part["crossings"] * 1e-3)
+    peak_rate = VALU_LANE_OPS_PER_S / CROSS_VALU_PER_PAIR
+    out = {
+        "metric": "edge pairs tested for crossings per second, with edge length deviation and "
+                  "Gabriel similarity, on the R-MAT 18 layout",
+        "value": value, "unit": "edge pairs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": total_s / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 coordinates, exact f64 signs; f64 sums", "data": "synthetic",
+        "config": {"workload": "rmat_metrics18_ef4_k2_fp32kahan_500iters_layout", "n": g.n, "m": m},
+        "metrics": met.as_dict(),
+        "ms": part,
+        "roofline": {"bound": "alu", "achieved": cross_rate / 1e9, "peak": peak_rate / 1e9,
+                     "unit": "Gpairs/s", "frac": cross_rate / peak_rate, "traffic": None,
+                     "kernel": "crossings_kernel", "kernel_ms": part["crossings"],
+                     "valu_per_rejected_pair": CROSS_VALU_PER_PAIR},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = oracle.num_threads()
+        x = pos.double().cpu().numpy()
+        sel = np.random.default_rng(1).choice(m, 64, replace=False)
+        tc0 = time.perf_counter()
+        oracle.edge_crossings(g.n, g.row_ptr, g.col_idx, x, sel)
+        tc1 = time.perf_counter()
+        out["cpu_baseline"] = {
+            "value": 64.0 * m / (tc1 - tc0), "unit": "edge pairs/s", "cores": threads,
+            "kind": "oracle",
+            "sample": (f"exact-sign oracle on this host ({_cpu_model()}, {threads} threads): the "
+                       f"crossings of 64 sampled edges with all {m} edges ({tc1 - tc0:.2f} s); "
+                       f"the oracle's Gabriel graph is cubic and not timed at this size"),
         }
     print(json.dumps(out))
     return 0

@@ -2,29 +2,35 @@
 // deviation of edge lengths, and the similarity of the drawing's Gabriel
 // graph to the graph (mean Jaccard index of the neighbourhoods).
 //
-// Coordinates are taken at single precision.  Differences of two floats and
-// products of two such differences are exact in double, and a correctly
-// rounded subtraction or sum of two exact doubles keeps its sign, so the
-// orientation and in-disc tests below have exact signs (whether or not the
-// compiler fuses a multiply into the subtraction).
+// Coordinates are taken at single precision, so a product of two coordinates
+// is exact in double.  Orientation and in-disc signs are first evaluated in
+// double with an a-priori error bound; where the value is within the bound
+// of zero the sign is taken exactly, from the polynomial multiplied out into
+// such products and summed with expansion arithmetic (two-sum chains).
 //
 //   edge_list_kernel      edges {u, v}, u < v, in row order (the part of a
 //                         sorted row above v is a suffix found by bisection)
-//   crossings_kernel      thread per edge, all other edges streamed through
-//                         LDS in tiles; an exact bounding-box reject, then
-//                         four orientation signs; per-edge counts
+//   crossings_kernel      4 edges per thread against a chunk of edges
+//                         streamed through LDS (each entry: end points and
+//                         line coefficients); per pair four filtered signs
+//                         decided by wavefront lane masks on the scalar unit;
+//                         each pair once for the total, or both ways for
+//                         per-edge counts
 //   lengths kernels       per-edge length, fixed-order sums (mean, then the
 //                         squared deviations)
 //   grid kernels          points binned into a uniform grid (about two per
 //                         cell)
-//   gabriel_degree_kernel thread per point u: rings of cells around u until,
-//                         in each of the eight 45-degree octants around u,
-//                         the nearest point w found so far blocks everything
-//                         at squared distance >= 2 |w - u|^2 (such a v sees w
-//                         within 45 degrees of its own direction, so w lies in
-//                         the disc with diameter uv) and the rings cover that
-//                         far; then every point not excluded that way is
-//                         tested for an empty disc with diameter uv
+//   gabriel_degree_kernel thread per point u (in cell order): rings of cells
+//                         around u until each of the eight 45-degree octants
+//                         around u is settled: the nearest point w found in it
+//                         blocks everything at squared distance >= 2 |w - u|^2
+//                         (such a v sees w within 45 degrees of its own
+//                         direction, so w lies in the disc with diameter uv),
+//                         or, with no point found, the rings cover the part of
+//                         the bounding box the octant reaches; then every
+//                         point not excluded that way is tested for an empty
+//                         disc with diameter uv (cells scanned outwards from
+//                         the disc's centre)
 //   gabriel_edge_kernel   the same disc test for each graph edge (for the
 //                         Jaccard intersections)
 #include <algorithm>
@@ -99,70 +105,209 @@ __global__ __launch_bounds__(kBlock) void edge_list_kernel(int32_t n, const int6
     }
 }
 
-// ------------------------------------------------------------------ crossings
-__device__ __forceinline__ int orient_sign(float ax, float ay, float bx, float by, float cx,
-                                           float cy) {
-    const double l = ((double)bx - (double)ax) * ((double)cy - (double)ay);
-    const double r = ((double)by - (double)ay) * ((double)cx - (double)ax);
-    const double d = l - r;
-    return (d > 0.0) - (d < 0.0);
+// ------------------------------------------------------------------ exact signs
+// Knuth's two-sum: s is the rounded a + b and s + e == a + b exactly.
+__device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
+#pragma clang fp contract(off)
+    s = a + b;
+    const double bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
 }
 
-struct Seg {
-    float x0, y0, x1, y1;
+// Exact sign of t[0] + ... + t[K-1].  Each term is merged into a growing
+// expansion by a chain of two-sums (Shewchuk's grow-expansion); the pieces
+// stay nonoverlapping with the largest last, so the sign of the sum is that
+// of the last nonzero piece.
+template <int K>
+__device__ __forceinline__ int exact_sum_sign(const double (&t)[K]) {
+    double h[K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        double q = t[i];
+#pragma unroll
+        for (int j = 0; j < i; ++j) two_sum(q, h[j], q, h[j]);
+        h[i] = q;
+    }
+    int sg = 0;
+#pragma unroll
+    for (int j = 0; j < K; ++j) sg = h[j] > 0.0 ? 1 : (h[j] < 0.0 ? -1 : sg);
+    return sg;
+}
+
+// orient(a, b, c) = (b - a) x (c - a) multiplied out (the two a.x a.y
+// products cancel); products of single-precision values are exact in double.
+__device__ __noinline__ int orient_exact(float ax, float ay, float bx, float by, float cx, float cy) {
+    const double t[6] = {(double)bx * cy, -((double)bx * ay), -((double)ax * cy),
+                         -((double)by * cx), (double)by * ax, (double)ay * cx};
+    return exact_sum_sign(t);
+}
+
+// ------------------------------------------------------------------ crossings
+// A segment's line in the form used by the sign filter: for a point x,
+// orient(p0, p1, x) = dx x.y - dy x.x - k, evaluated in double.  Its rounding
+// error is below 4u(|dx| |x.y| + |dy| |x.x|) + 2u(|x1 y0| + |y1 x0|) plus
+// second-order terms (u = 2^-53; coordinates are floats, so x1 y0 and y1 x0
+// are exact), hence below bnd = 8u((|dx| + |dy|) M + |x1 y0| + |y1 x0|) for
+// every point with coordinates of magnitude at most M.
+struct Line {
+    double dx, dy, k, bnd;
 };
 
-__global__ __launch_bounds__(kCrossTile) void crossings_kernel(int64_t m, const int2* __restrict__ ends,
-                                                               const float2* __restrict__ p,
-                                                               int64_t* __restrict__ per_edge,
-                                                               unsigned long long* __restrict__ total) {
-    __shared__ Seg s_seg[kCrossTile];
-    __shared__ float4 s_box[kCrossTile];  // xmin, xmax, ymin, ymax
-    __shared__ int2 s_end[kCrossTile];
-    const int64_t i = (int64_t)blockIdx.x * kCrossTile + threadIdx.x;
-    const bool live = i < m;
-    int2 ei = make_int2(-1, -1);
-    Seg a{0.f, 0.f, 0.f, 0.f};
-    if (live) {
-        ei = ends[i];
-        const float2 pa = p[ei.x], pb = p[ei.y];
-        a = Seg{pa.x, pa.y, pb.x, pb.y};
+__device__ __forceinline__ Line make_line(float x0, float y0, float x1, float y1, double M) {
+#pragma clang fp contract(off)
+    Line L;
+    L.dx = (double)x1 - (double)x0;
+    L.dy = (double)y1 - (double)y0;
+    const double s = (double)x1 * y0, t = (double)y1 * x0;
+    L.k = s - t;
+    L.bnd = ((fabs(L.dx) + fabs(L.dy)) * M + (fabs(s) + fabs(t))) * 0x1p-50;
+    return L;
+}
+
+// orient(p0, p1, (x, y)) up to rounding: its sign is certain where |d| > L.bnd
+__device__ __forceinline__ double side(const Line& L, double x, double y) {
+#pragma clang fp contract(off)
+    const double q = L.dy * x;
+    return fma(L.dx, y, -q) - L.k;
+}
+
+// One LDS entry: an edge's end points and line.
+struct alignas(16) CrossEntry {
+    double x0, y0, x1, y1;
+    Line L;
+};
+
+constexpr int kCrossRows = 4;                         // edges per thread
+constexpr int kCrossBlock = kCrossRows * kCrossTile;  // edges per block
+constexpr int64_t kCrossChunk = 8192;                 // edges streamed per block (at least)
+
+// Exact crossing decision for a pair the filter could not settle.
+__device__ __forceinline__ int cross_exact(int2 ea, int2 ec, const float2* __restrict__ p) {
+    if (ea.x == ec.x || ea.x == ec.y || ea.y == ec.x || ea.y == ec.y) return 0;
+    const float2 a = p[ea.x], b = p[ea.y], c = p[ec.x], d = p[ec.y];
+    const int o1 = orient_exact(a.x, a.y, b.x, b.y, c.x, c.y);
+    const int o2 = orient_exact(a.x, a.y, b.x, b.y, d.x, d.y);
+    if (o1 * o2 >= 0) return 0;
+    const int o3 = orient_exact(c.x, c.y, d.x, d.y, a.x, a.y);
+    const int o4 = orient_exact(c.x, c.y, d.x, d.y, b.x, b.y);
+    return o3 * o4 < 0 ? 1 : 0;
+}
+
+// The pairs (i, j) of one LDS tile for the edges a thread holds.  Lane
+// masks of the wavefront (one ballot per comparison, combined in scalar
+// registers) decide each pair: sure crossings of PAIRS_ONCE mode are counted
+// per wavefront (wcnt), other counts per lane (cnt).  DIAG: count j > i only.
+template <bool PAIRS_ONCE, bool DIAG>
+__device__ __forceinline__ void cross_tile(const CrossEntry* __restrict__ s_e, const int2* __restrict__ s_end,
+                                           int tn, int64_t t0, int64_t a0, const uint64_t (&live)[kCrossRows],
+                                           const double (&ax)[kCrossRows], const double (&ay)[kCrossRows],
+                                           const double (&bx)[kCrossRows], const double (&by)[kCrossRows],
+                                           const Line (&la)[kCrossRows], int (&cnt)[kCrossRows],
+                                           uint64_t& wcnt, const int2* __restrict__ ends,
+                                           const float2* __restrict__ p) {
+    const uint64_t me = 1ull << lane64();
+    for (int q = 0; q < tn; ++q) {
+        const CrossEntry c = s_e[q];
+#pragma unroll
+        for (int r = 0; r < kCrossRows; ++r) {
+            const int64_t i = a0 + r * kCrossTile + threadIdx.x;
+            const double d1 = side(la[r], c.x0, c.y0);
+            const double d2 = side(la[r], c.x1, c.y1);
+            const double d3 = side(c.L, ax[r], ay[r]);
+            const double d4 = side(c.L, bx[r], by[r]);
+            // the signs are certain where |d| > bnd; then |d| > bnd >= 2^-348
+            // (a float's nonzero difference or product is at least 2^-298 in
+            // magnitude), so the products below neither underflow nor overflow
+            const uint64_t sure = __builtin_amdgcn_ballot_w64(fabs(d1) > la[r].bnd) &
+                                  __builtin_amdgcn_ballot_w64(fabs(d2) > la[r].bnd) &
+                                  __builtin_amdgcn_ballot_w64(fabs(d3) > c.L.bnd) &
+                                  __builtin_amdgcn_ballot_w64(fabs(d4) > c.L.bnd);
+            const uint64_t cross = __builtin_amdgcn_ballot_w64(d1 * d2 < 0.0) &
+                                   __builtin_amdgcn_ballot_w64(d3 * d4 < 0.0);
+            const uint64_t keep = DIAG ? __builtin_amdgcn_ballot_w64(t0 + q > i) & live[r] : live[r];
+            if (PAIRS_ONCE)
+                wcnt += __popcll(sure & cross & keep);
+            else
+                cnt[r] += (sure & cross & keep & me) ? 1 : 0;
+            const uint64_t slow = ~sure & keep;
+            if (slow) [[unlikely]] {
+                if (slow & me) cnt[r] += cross_exact(ends[i], s_end[q], p);
+            }
+        }
     }
-    const float axmin = fminf(a.x0, a.x1), axmax = fmaxf(a.x0, a.x1);
-    const float aymin = fminf(a.y0, a.y1), aymax = fmaxf(a.y0, a.y1);
-    int64_t count = 0;
-    for (int64_t t0 = 0; t0 < m; t0 += kCrossTile) {
+}
+
+// Block (blockIdx.x, blockIdx.y): edges i of A-block x (thread t holds
+// i = x * kCrossBlock + r * kCrossTile + t, r < kCrossRows) against edges j
+// of chunk y, streamed through LDS in tiles.  A crossing is a pair with no
+// shared end whose ends lie strictly on opposite sides of the other's line.
+// PAIRS_ONCE: only j > i counts (each crossing once, for the total);
+// otherwise every j != i counts and per_edge[i] accumulates.  M bounds the
+// magnitude of every coordinate.
+template <bool PAIRS_ONCE>
+__global__ __launch_bounds__(kCrossTile) void crossings_kernel(int64_t m, int64_t chunk, double M,
+                                                               const int2* __restrict__ ends,
+                                                               const float2* __restrict__ p,
+                                                               unsigned long long* __restrict__ per_edge,
+                                                               unsigned long long* __restrict__ total) {
+    __shared__ CrossEntry s_e[kCrossTile];
+    __shared__ int2 s_end[kCrossTile];
+    const int64_t a0 = (int64_t)blockIdx.x * kCrossBlock;
+    const int64_t c0 = (int64_t)blockIdx.y * chunk;
+    const int64_t c1 = min(c0 + chunk, m);
+    int64_t jbeg = c0;
+    if (PAIRS_ONCE) {
+        if (c1 <= a0 + 1) return;  // every j of the chunk is <= every i of the block
+        jbeg = max(c0, a0);        // a0 is a multiple of the tile size
+    }
+    double ax[kCrossRows], ay[kCrossRows], bx[kCrossRows], by[kCrossRows];
+    Line la[kCrossRows];
+    int cnt[kCrossRows];
+    uint64_t live[kCrossRows];
+    uint64_t wcnt = 0;
+#pragma unroll
+    for (int r = 0; r < kCrossRows; ++r) {
+        const int64_t i = a0 + r * kCrossTile + threadIdx.x;
+        cnt[r] = 0;
+        live[r] = __builtin_amdgcn_ballot_w64(i < m);
+        float2 pa = make_float2(0.f, 0.f), pb = pa;
+        if (i < m) {
+            const int2 e = ends[i];
+            pa = p[e.x];
+            pb = p[e.y];
+        }
+        ax[r] = pa.x;
+        ay[r] = pa.y;
+        bx[r] = pb.x;
+        by[r] = pb.y;
+        la[r] = make_line(pa.x, pa.y, pb.x, pb.y, M);
+    }
+    for (int64_t t0 = jbeg; t0 < c1; t0 += kCrossTile) {
         const int64_t j = t0 + threadIdx.x;
-        if (j < m) {
+        if (j < c1) {
             const int2 e = ends[j];
             const float2 pc = p[e.x], pd = p[e.y];
-            s_seg[threadIdx.x] = Seg{pc.x, pc.y, pd.x, pd.y};
-            s_box[threadIdx.x] = make_float4(fminf(pc.x, pd.x), fmaxf(pc.x, pd.x), fminf(pc.y, pd.y),
-                                             fmaxf(pc.y, pd.y));
+            s_e[threadIdx.x] = CrossEntry{pc.x, pc.y, pd.x, pd.y, make_line(pc.x, pc.y, pd.x, pd.y, M)};
             s_end[threadIdx.x] = e;
         }
         __syncthreads();
-        const int tn = (int)(m - t0 < kCrossTile ? m - t0 : kCrossTile);
-        if (live) {
-            for (int q = 0; q < tn; ++q) {
-                const float4 b = s_box[q];
-                // a proper crossing lies inside both closed boxes
-                if (b.x > axmax || axmin > b.y || b.z > aymax || aymin > b.w) continue;
-                const int2 e = s_end[q];
-                if (e.x == ei.x || e.x == ei.y || e.y == ei.x || e.y == ei.y) continue;  // shared end or itself
-                const Seg c = s_seg[q];
-                const int o1 = orient_sign(a.x0, a.y0, a.x1, a.y1, c.x0, c.y0);
-                const int o2 = orient_sign(a.x0, a.y0, a.x1, a.y1, c.x1, c.y1);
-                if (o1 * o2 >= 0) continue;
-                const int o3 = orient_sign(c.x0, c.y0, c.x1, c.y1, a.x0, a.y0);
-                const int o4 = orient_sign(c.x0, c.y0, c.x1, c.y1, a.x1, a.y1);
-                count += o3 * o4 < 0 ? 1 : 0;
-            }
-        }
+        const int tn = (int)min<int64_t>(kCrossTile, c1 - t0);
+        // in PAIRS_ONCE mode, tiles that reach into the block's own range count j > i only
+        if (PAIRS_ONCE && t0 < a0 + kCrossBlock)
+            cross_tile<PAIRS_ONCE, true>(s_e, s_end, tn, t0, a0, live, ax, ay, bx, by, la, cnt, wcnt, ends, p);
+        else
+            cross_tile<PAIRS_ONCE, false>(s_e, s_end, tn, t0, a0, live, ax, ay, bx, by, la, cnt, wcnt, ends, p);
         __syncthreads();
     }
-    if (live && per_edge) per_edge[i] = count;
-    const int64_t w = wave_sum(count);
+    int64_t sum = 0;
+#pragma unroll
+    for (int r = 0; r < kCrossRows; ++r) {
+        const int64_t i = a0 + r * kCrossTile + threadIdx.x;
+        sum += cnt[r];
+        if (!PAIRS_ONCE && per_edge && cnt[r] && i < m)
+            atomicAdd(&per_edge[i], (unsigned long long)cnt[r]);
+    }
+    const int64_t w = wave_sum(sum) + (int64_t)wcnt;
     if (lane64() == 0 && w) atomicAdd(total, (unsigned long long)w);
 }
 
@@ -204,6 +349,7 @@ __device__ __forceinline__ int32_t cell_y(const Grid& g, float y) {
 __global__ __launch_bounds__(kBlock) void bounds_kernel(int32_t n, const float2* __restrict__ p,
                                                         unsigned int* __restrict__ box) {
     // box: ordered keys of xmin, ymin (min) and of -xmax, -ymax (min)
+    __shared__ unsigned int s_k[4][kBlock];
     unsigned int k[4] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
     auto key = [](float f) {
         const unsigned int u = __float_as_uint(f);
@@ -217,7 +363,14 @@ __global__ __launch_bounds__(kBlock) void bounds_kernel(int32_t n, const float2*
         k[2] = min(k[2], key(-q.x));
         k[3] = min(k[3], key(-q.y));
     }
-    for (int c = 0; c < 4; ++c) atomicMin(&box[c], k[c]);
+    for (int c = 0; c < 4; ++c) s_k[c][threadIdx.x] = k[c];
+    __syncthreads();
+    for (int h = kBlock / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h)
+            for (int c = 0; c < 4; ++c) s_k[c][threadIdx.x] = min(s_k[c][threadIdx.x], s_k[c][threadIdx.x + h]);
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) atomicMin(&box[threadIdx.x], s_k[threadIdx.x][0]);
 }
 
 __global__ __launch_bounds__(kBlock) void cell_count_kernel(int32_t n, Grid g, const float2* __restrict__ p,
@@ -243,14 +396,53 @@ __global__ __launch_bounds__(kBlock) void cell_fill_kernel(int32_t n, const int3
     }
 }
 
-// w lies in the closed disc with diameter uv: (w - u).(w - v) <= 0 (exact sign)
-__device__ __forceinline__ bool in_disc(float2 u, float2 v, float2 w) {
-    const double a = ((double)w.x - (double)u.x) * ((double)w.x - (double)v.x);
-    const double b = ((double)w.y - (double)u.y) * ((double)w.y - (double)v.y);
-    return a + b <= 0.0;
+// (w - u).(w - v) multiplied out into products of floats (exact in double)
+__device__ __noinline__ int disc_sign_exact(float2 u, float2 v, float2 w) {
+    const double t[8] = {(double)w.x * w.x, -((double)w.x * v.x), -((double)u.x * w.x),
+                         (double)u.x * v.x, (double)w.y * w.y, -((double)w.y * v.y),
+                         -((double)u.y * w.y), (double)u.y * v.y};
+    return exact_sum_sign(t);
 }
 
-// No point other than iu, iv in the closed disc with diameter uv.
+// w lies in the closed disc with diameter uv: (w - u).(w - v) <= 0.  The
+// double evaluation errs by less than 3u(|l| + |r|) plus second-order terms
+// (u = 2^-53, as for a 2x2 determinant of rounded differences); when the
+// result is within 8u of zero the sign is taken exactly.
+__device__ __forceinline__ bool in_disc(float2 u, float2 v, float2 w) {
+#pragma clang fp contract(off)
+    const double l = ((double)w.x - (double)u.x) * ((double)w.x - (double)v.x);
+    const double r = ((double)w.y - (double)u.y) * ((double)w.y - (double)v.y);
+    const double d = l + r;
+    const double b = (fabs(l) + fabs(r)) * 0x1p-50;
+    if (d > b) return false;
+    if (d < -b) return true;
+    return disc_sign_exact(u, v, w) <= 0;
+}
+
+// Visit the cells at Chebyshev distance exactly k from (cx, cy) that lie in
+// columns [x0, x1] and rows [y0, y1] (so a ring costs only its cells inside);
+// f(cell) returns true to stop, and then so does this (returning true).
+template <class F>
+__device__ __forceinline__ bool ring_cells(const Grid& g, int32_t cx, int32_t cy, int32_t k, int32_t x0,
+                                           int32_t x1, int32_t y0, int32_t y1, F&& f) {
+    const int32_t ya = max(cy - k, y0), yb = min(cy + k, y1);
+    const int32_t xa = max(cx - k, x0), xb = min(cx + k, x1);
+    for (int32_t y = ya; y <= yb; ++y) {
+        const int64_t row = (int64_t)y * g.gx;
+        if (y == cy - k || y == cy + k) {
+            for (int32_t x = xa; x <= xb; ++x)
+                if (f(row + x)) return true;
+        } else {
+            if (cx - k >= x0 && f(row + cx - k)) return true;
+            if (cx + k <= x1 && f(row + cx + k)) return true;
+        }
+    }
+    return false;
+}
+
+// No point other than iu, iv in the closed disc with diameter uv.  Cells are
+// scanned outwards from the disc's centre, where a blocking point is most
+// likely to be.
 __device__ bool gabriel_pair_dev(const Grid& g, const int64_t* __restrict__ start,
                                  const int32_t* __restrict__ pts, const float2* __restrict__ p,
                                  int32_t iu, int32_t iv) {
@@ -261,15 +453,18 @@ __device__ bool gabriel_pair_dev(const Grid& g, const int64_t* __restrict__ star
     const float r = (float)(0.5 * sqrt(dx * dx + dy * dy)) * 1.0001f + 1e-30f;
     const int32_t x0 = max(cell_x(g, cx - r) - 1, 0), x1 = min(cell_x(g, cx + r) + 1, g.gx - 1);
     const int32_t y0 = max(cell_y(g, cy - r) - 1, 0), y1 = min(cell_y(g, cy + r) + 1, g.gy - 1);
-    for (int32_t y = y0; y <= y1; ++y)
-        for (int32_t x = x0; x <= x1; ++x) {
-            const int64_t c = (int64_t)y * g.gx + x;
-            for (int64_t k = start[c]; k < start[c + 1]; ++k) {
-                const int32_t w = pts[k];
-                if (w == iu || w == iv) continue;
-                if (in_disc(u, v, p[w])) return false;
+    const int32_t ccx = min(max(cell_x(g, cx), x0), x1), ccy = min(max(cell_y(g, cy), y0), y1);
+    const int32_t K = max(max(ccx - x0, x1 - ccx), max(ccy - y0, y1 - ccy));
+    for (int32_t k = 0; k <= K; ++k) {
+        const bool blocked = ring_cells(g, ccx, ccy, k, x0, x1, y0, y1, [&](int64_t c) {
+            for (int64_t q = start[c]; q < start[c + 1]; ++q) {
+                const int32_t w = pts[q];
+                if (w != iu && w != iv && in_disc(u, v, p[w])) return true;
             }
-        }
+            return false;
+        });
+        if (blocked) return false;
+    }
     return true;
 }
 
@@ -278,69 +473,152 @@ __device__ __forceinline__ int octant(double dx, double dy) {
     return (dx < 0.0 ? 4 : 0) + (dy < 0.0 ? 2 : 0) + (fabs(dx) < fabs(dy) ? 1 : 0);
 }
 
-// Visit the points of the cells at Chebyshev distance exactly k from (cx, cy)
-// (rows and columns clamped to the grid, so a ring costs its cells inside).
+// Visit the points of the grid cells at Chebyshev distance exactly k from (cx, cy).
 template <class F>
 __device__ __forceinline__ void ring_points(const Grid& g, const int64_t* __restrict__ start,
                                             const int32_t* __restrict__ pts, int32_t cx,
                                             int32_t cy, int32_t k, F&& f) {
-    auto cell_points = [&](int32_t x, int32_t y) {
-        const int64_t c = (int64_t)y * g.gx + x;
+    ring_cells(g, cx, cy, k, 0, g.gx - 1, 0, g.gy - 1, [&](int64_t c) {
         for (int64_t q = start[c]; q < start[c + 1]; ++q) f(pts[q]);
+        return false;
+    });
+}
+
+// Visit the cells of ring k (k >= 4) around (cx, cy) that can hold points of
+// octant o.  With (p, q) a cell's index offsets along the octant's major and
+// minor axes, signed towards it, a point of the octant with true offsets
+// A >= B >= 0 (in cell widths) has |p - A| < 2 and |q - B| < 2 (one for its
+// place in the cell, one for a cell index computed in float), so p >= -1,
+// q >= -1 and p >= q - 3: on ring k these are p = k with q in [-1, k] and
+// q = k with p in [k - 3, k - 1].
+template <class F>
+__device__ __forceinline__ void sector_cells(const Grid& g, int32_t cx, int32_t cy, int32_t k, int o, F&& f) {
+    const int32_t sx = (o & 4) ? -1 : 1, sy = (o & 2) ? -1 : 1;
+    const bool major_y = o & 1;
+    // centre, extent and sign of the major (0) and minor (1) axes
+    const int32_t c0 = major_y ? cy : cx, n0 = major_y ? g.gy : g.gx, s0 = major_y ? sy : sx;
+    const int32_t c1 = major_y ? cx : cy, n1 = major_y ? g.gx : g.gy, s1 = major_y ? sx : sy;
+    // signed offsets t with c + s t inside [0, n): t in [lo, hi], lo <= 0 <= hi
+    auto lo = [](int32_t c, int32_t n, int32_t s) { return s > 0 ? -c : c - (n - 1); };
+    auto hi = [](int32_t c, int32_t n, int32_t s) { return s > 0 ? n - 1 - c : c; };
+    auto visit = [&](int32_t pp, int32_t qq) {
+        const int32_t a = c0 + s0 * pp, b = c1 + s1 * qq;
+        f((int64_t)(major_y ? a : b) * g.gx + (major_y ? b : a));
     };
-    const int32_t y0 = max(cy - k, 0), y1 = min(cy + k, g.gy - 1);
-    const int32_t x0 = max(cx - k, 0), x1 = min(cx + k, g.gx - 1);
-    for (int32_t y = y0; y <= y1; ++y) {
-        if (y == cy - k || y == cy + k) {
-            for (int32_t x = x0; x <= x1; ++x) cell_points(x, y);
-        } else {
-            if (cx - k >= 0) cell_points(cx - k, y);
-            if (cx + k < g.gx) cell_points(cx + k, y);
-        }
+    // loops run over the offsets inside the grid only (a degenerate grid of
+    // one row would otherwise cost k steps per ring)
+    if (k <= hi(c0, n0, s0)) {
+        const int32_t qa = max(-1, lo(c1, n1, s1)), qb = min(k, hi(c1, n1, s1));
+        for (int32_t qq = qa; qq <= qb; ++qq) visit(k, qq);
+    }
+    if (k <= hi(c1, n1, s1)) {
+        const int32_t pa = max(k - 3, lo(c0, n0, s0)), pb = min(k - 1, hi(c0, n0, s0));
+        for (int32_t pp = pa; pp <= pb; ++pp) visit(pp, k);
     }
 }
 
+// Full ring, or only the sectors of the octants in `open` when that visits
+// fewer cells (k + 5 per octant against 8k).
+__device__ __forceinline__ bool use_full_ring(int32_t k, unsigned open) {
+    return k <= 3 || (int32_t)__popc(open) * (k + 5) >= 8 * k;
+}
+
+// Thread per point u, points taken in cell order (a wavefront's points are
+// neighbours).  box = (xmin, xmax, ymin, ymax) of all points.
 __global__ __launch_bounds__(kBlock) void gabriel_degree_kernel(int32_t n, Grid g,
                                                                 const int64_t* __restrict__ start,
                                                                 const int32_t* __restrict__ pts,
                                                                 const float2* __restrict__ p,
-                                                                float cell, int32_t* __restrict__ gdeg) {
-    for (int64_t iu = (int64_t)blockIdx.x * kBlock + threadIdx.x; iu < n;
-         iu += (int64_t)gridDim.x * kBlock) {
+                                                                float cell, float4 box,
+                                                                int32_t* __restrict__ gdeg) {
+    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * kBlock) {
+        const int32_t iu = pts[t];
         const float2 u = p[iu];
         const int32_t cx = cell_x(g, u.x), cy = cell_y(g, u.y);
-        double best[8];
-        for (int o = 0; o < 8; ++o) best[o] = INFINITY;
-        // rings beyond kmax lie entirely outside the grid
-        const int32_t kmax = max(max(cx, g.gx - 1 - cx), max(cy, g.gy - 1 - cy));
-        int32_t K = 0;
-        for (int32_t k = 0;; ++k) {
-            ring_points(g, start, pts, cx, cy, k, [&](int32_t w) {
-                if (w == iu) return;
+        // reach[o]: the largest squared distance from u to a point of the
+        // bounding box in octant o (its wedge is bounded by the box edges A
+        // along x and B along y; the far corner of the wedge's part inside
+        // is at (A, min(A, B)) or (min(A, B), B))
+        double reach[8], best[8];
+        int32_t ko[8];
+        for (int o = 0; o < 8; ++o) {
+            const double A = (o & 4) ? (double)u.x - box.x : (double)box.y - u.x;
+            const double B = (o & 2) ? (double)u.y - box.z : (double)box.w - u.y;
+            const double mn = fmin(A, B);
+            reach[o] = ((o & 1) ? B * B : A * A) + mn * mn;
+            // an octant that needs dx < 0 (dy < 0) with u on the box's left
+            // (lower) edge holds no point at all
+            if (((o & 4) && A == 0.0) || ((o & 2) && B == 0.0)) reach[o] = 0.0;
+            best[o] = INFINITY;
+            ko[o] = 0;
+        }
+        auto nearest = [&](int64_t c) {
+            for (int64_t q = start[c]; q < start[c + 1]; ++q) {
+                const int32_t w = pts[q];
+                if (w == iu) continue;
                 const double dx = (double)p[w].x - (double)u.x, dy = (double)p[w].y - (double)u.y;
                 const double r2 = dx * dx + dy * dy;
-                if (r2 <= 0.0) return;  // a coincident point has no direction
+                if (r2 <= 0.0) continue;  // a coincident point has no direction
                 const int o = octant(dx, dy);
                 best[o] = r2 < best[o] ? r2 : best[o];
-            });
-            K = k;
-            if (k >= kmax) break;
-            // every point within (k - 2) cells' width of u has been seen (a
-            // cell index computed in float can be one off)
+            }
+            return false;
+        };
+        // rings beyond kmax lie entirely outside the grid
+        const int32_t kmax = max(max(cx, g.gx - 1 - cx), max(cy, g.gy - 1 - cy));
+        unsigned open = 0xFFu;  // octants not yet settled
+        for (int32_t k = 0; open; ++k) {
+            if (use_full_ring(k, open))
+                ring_cells(g, cx, cy, k, 0, g.gx - 1, 0, g.gy - 1, nearest);
+            else
+                for (int o = 0; o < 8; ++o)
+                    if (open >> o & 1) sector_cells(g, cx, cy, k, o, nearest);
+            // every point of an octant visited so far within (k - 2) cells'
+            // width of u has been seen (a cell index computed in float can be
+            // one off); an octant is settled at ring ko once that covers twice
+            // its nearest squared distance (beyond, its points are blocked)
+            // or, with no point found, its reach (it has none)
             const double cover = k >= 2 ? (double)(k - 2) * (double)cell : 0.0;
-            double need = 0.0;
-            for (int o = 0; o < 8; ++o) need = fmax(need, 2.0 * best[o] * (1.0 + 1e-9));
-            if (k >= 2 && need <= cover * cover) break;
+            for (int o = 0; o < 8; ++o) {
+                if (!(open >> o & 1)) continue;
+                const double need = (best[o] < INFINITY ? 2.0 * best[o] : reach[o]) * (1.0 + 1e-9);
+                if ((k >= 2 && need <= cover * cover) || k >= kmax) {
+                    ko[o] = k;
+                    open &= ~(1u << o);
+                }
+            }
         }
+        int32_t K = 0;
+        for (int o = 0; o < 8; ++o) K = max(K, ko[o]);
+        // candidates: points of octant o on rings up to ko[o] that are not blocked
         int32_t deg = 0;
-        for (int32_t k = 0; k <= K; ++k)
-            ring_points(g, start, pts, cx, cy, k, [&](int32_t iv) {
-                if (iv == iu) return;
-                const double dx = (double)p[iv].x - (double)u.x, dy = (double)p[iv].y - (double)u.y;
-                const double r2 = dx * dx + dy * dy;
-                if (r2 > 0.0 && r2 >= 2.0 * best[octant(dx, dy)] * (1.0 + 1e-9)) return;  // blocked
-                deg += gabriel_pair_dev(g, start, pts, p, (int32_t)iu, iv) ? 1 : 0;
-            });
+        for (int32_t k = 0; k <= K; ++k) {
+            unsigned live = 0;
+            for (int o = 0; o < 8; ++o) live |= (ko[o] >= k ? 1u : 0u) << o;
+            auto candidates = [&](int only, int64_t c) {
+                for (int64_t q = start[c]; q < start[c + 1]; ++q) {
+                    const int32_t iv = pts[q];
+                    if (iv == iu) continue;
+                    const double dx = (double)p[iv].x - (double)u.x, dy = (double)p[iv].y - (double)u.y;
+                    const double r2 = dx * dx + dy * dy;
+                    const int o = octant(dx, dy);
+                    if (r2 > 0.0) {
+                        if (only >= 0 ? o != only : !(live >> o & 1)) continue;
+                        if (r2 >= 2.0 * best[o] * (1.0 + 1e-9)) continue;  // blocked
+                    } else if (only >= 0 && only != 0) {
+                        continue;  // a coincident point is taken once, with octant 0
+                    }
+                    deg += gabriel_pair_dev(g, start, pts, p, iu, iv) ? 1 : 0;
+                }
+                return false;
+            };
+            if (use_full_ring(k, live))
+                ring_cells(g, cx, cy, k, 0, g.gx - 1, 0, g.gy - 1, [&](int64_t c) { return candidates(-1, c); });
+            else
+                for (int o = 0; o < 8; ++o)
+                    if (live >> o & 1) sector_cells(g, cx, cy, k, o, [&](int64_t c) { return candidates(o, c); });
+        }
         gdeg[iu] = deg;
     }
 }
@@ -388,13 +666,20 @@ __global__ __launch_bounds__(kBlock) void jaccard_kernel(int32_t n, const int64_
     if (lane64() == 0 && w) atomicAdd(gsum, w);
 }
 
-// Sum of partial[0 .. count) in order, by one thread.
-__global__ void ordered_sum_kernel(int32_t count, const double* __restrict__ partial,
-                                   double* __restrict__ out) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    double s = 0.0;
-    for (int32_t i = 0; i < count; ++i) s += partial[i];
-    *out = s;
+// Sum of partial[0 .. count) in a fixed order (the same bits on every run):
+// thread t adds partial[t], partial[t + 256], ... in turn, then a fixed tree.
+__global__ __launch_bounds__(kBlock) void ordered_sum_kernel(int32_t count, const double* __restrict__ partial,
+                                                             double* __restrict__ out) {
+    __shared__ double s_v[kBlock];
+    double a = 0.0;
+    for (int32_t i = threadIdx.x; i < count; i += kBlock) a += partial[i];
+    s_v[threadIdx.x] = a;
+    __syncthreads();
+    for (int h = kBlock / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) s_v[threadIdx.x] += s_v[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = s_v[0];
 }
 
 template <class V>
@@ -408,6 +693,27 @@ static int drawing_metrics(const gila_csr* g, const V* pos, int32_t what, hipStr
     GILA_TRY(pf.alloc<float2>((size_t)n));
     hipLaunchKernelGGL(to_float_kernel<V>, dim3(mgrid(n)), dim3(kBlock), 0, s, n, pos, pf.as<float2>());
     GILA_HIP(hipGetLastError());
+    // bounding box (finite coordinates only)
+    MBuf box(s);
+    GILA_TRY(box.alloc<unsigned int>(4));
+    GILA_HIP(hipMemsetAsync(box.p, 0xFF, 4 * sizeof(unsigned int), s));
+    hipLaunchKernelGGL(bounds_kernel, dim3(mgrid(n)), dim3(kBlock), 0, s, n, pf.as<float2>(),
+                       box.as<unsigned int>());
+    GILA_HIP(hipGetLastError());
+    unsigned int hb[4];
+    GILA_HIP(hipMemcpyAsync(hb, box.p, sizeof(hb), hipMemcpyDeviceToHost, s));
+    GILA_HIP(hipStreamSynchronize(s));
+    auto val = [](unsigned int k) {
+        const unsigned int u = (k >> 31) ? (k & 0x7FFFFFFFu) : ~k;
+        float f;
+        std::memcpy(&f, &u, 4);
+        return f;
+    };
+    const float xmin = val(hb[0]), ymin = val(hb[1]), xmax = -val(hb[2]), ymax = -val(hb[3]);
+    if (!std::isfinite(xmin) || !std::isfinite(xmax) || !std::isfinite(ymin) || !std::isfinite(ymax))
+        return fail(GILA_EINVAL, "positions must be finite");
+    const double M = std::max(std::max(std::fabs((double)xmin), std::fabs((double)xmax)),
+                              std::max(std::fabs((double)ymin), std::fabs((double)ymax)));
     // edge list
     GILA_TRY(first.alloc<int64_t>((size_t)n));
     GILA_TRY(cnt.alloc<int64_t>((size_t)n));
@@ -429,14 +735,25 @@ static int drawing_metrics(const gila_csr* g, const V* pos, int32_t what, hipStr
         MBuf tot(s);
         GILA_TRY(tot.alloc<unsigned long long>(1));
         GILA_HIP(hipMemsetAsync(tot.p, 0, sizeof(unsigned long long), s));
-        hipLaunchKernelGGL(crossings_kernel, dim3((unsigned)((m + kCrossTile - 1) / kCrossTile)),
-                           dim3(kCrossTile), 0, s, m, ends.as<int2>(), pf.as<float2>(), edge_crossings,
-                           tot.as<unsigned long long>());
+        // chunks of at least kCrossChunk edges, few enough for the grid's y extent
+        int64_t chunk = std::max<int64_t>(kCrossChunk, (m + 65534) / 65535);
+        chunk = (chunk + kCrossTile - 1) / kCrossTile * kCrossTile;
+        const dim3 grid((unsigned)((m + kCrossBlock - 1) / kCrossBlock), (unsigned)((m + chunk - 1) / chunk));
+        if (edge_crossings) {
+            GILA_HIP(hipMemsetAsync(edge_crossings, 0, sizeof(int64_t) * (size_t)m, s));
+            hipLaunchKernelGGL(crossings_kernel<false>, grid, dim3(kCrossTile), 0, s, m, chunk, M,
+                               ends.as<int2>(), pf.as<float2>(),
+                               reinterpret_cast<unsigned long long*>(edge_crossings),
+                               tot.as<unsigned long long>());
+        } else {
+            hipLaunchKernelGGL(crossings_kernel<true>, grid, dim3(kCrossTile), 0, s, m, chunk, M,
+                               ends.as<int2>(), pf.as<float2>(), nullptr, tot.as<unsigned long long>());
+        }
         GILA_HIP(hipGetLastError());
         unsigned long long t = 0;
         GILA_HIP(hipMemcpyAsync(&t, tot.p, sizeof(t), hipMemcpyDeviceToHost, s));
         GILA_HIP(hipStreamSynchronize(s));
-        out->crossings = (int64_t)(t / 2);
+        out->crossings = (int64_t)(edge_crossings ? t / 2 : t);
     }
     if ((what & GILA_METRIC_LENGTHS) && m > 0) {
         const int lg = mgrid(m);
@@ -446,38 +763,20 @@ static int drawing_metrics(const gila_csr* g, const V* pos, int32_t what, hipStr
         double tot = 0.0;
         hipLaunchKernelGGL(lengths_sum_kernel, dim3(lg), dim3(kBlock), 0, s, m, ends.as<int2>(),
                            pf.as<float2>(), 0.0, 0, part.as<double>());
-        hipLaunchKernelGGL(ordered_sum_kernel, dim3(1), dim3(64), 0, s, lg, part.as<double>(), sum.as<double>());
+        hipLaunchKernelGGL(ordered_sum_kernel, dim3(1), dim3(kBlock), 0, s, lg, part.as<double>(), sum.as<double>());
         GILA_HIP(hipMemcpyAsync(&tot, sum.p, sizeof(double), hipMemcpyDeviceToHost, s));
         GILA_HIP(hipStreamSynchronize(s));
         const double mean = tot / (double)m;
         hipLaunchKernelGGL(lengths_sum_kernel, dim3(lg), dim3(kBlock), 0, s, m, ends.as<int2>(),
                            pf.as<float2>(), mean, 1, part.as<double>());
-        hipLaunchKernelGGL(ordered_sum_kernel, dim3(1), dim3(64), 0, s, lg, part.as<double>(), sum.as<double>());
+        hipLaunchKernelGGL(ordered_sum_kernel, dim3(1), dim3(kBlock), 0, s, lg, part.as<double>(), sum.as<double>());
         GILA_HIP(hipMemcpyAsync(&tot, sum.p, sizeof(double), hipMemcpyDeviceToHost, s));
         GILA_HIP(hipStreamSynchronize(s));
         out->edge_length_mean = mean;
         out->edge_length_std = std::sqrt(tot / (double)m);
     }
     if (what & GILA_METRIC_SIMILARITY) {
-        // grid of about two points per cell over the points' bounding box
-        MBuf box(s);
-        GILA_TRY(box.alloc<unsigned int>(4));
-        GILA_HIP(hipMemsetAsync(box.p, 0xFF, 4 * sizeof(unsigned int), s));
-        hipLaunchKernelGGL(bounds_kernel, dim3(mgrid(n)), dim3(kBlock), 0, s, n, pf.as<float2>(),
-                           box.as<unsigned int>());
-        GILA_HIP(hipGetLastError());
-        unsigned int hb[4];
-        GILA_HIP(hipMemcpyAsync(hb, box.p, sizeof(hb), hipMemcpyDeviceToHost, s));
-        GILA_HIP(hipStreamSynchronize(s));
-        auto val = [](unsigned int k) {
-            const unsigned int u = (k >> 31) ? (k & 0x7FFFFFFFu) : ~k;
-            float f;
-            std::memcpy(&f, &u, 4);
-            return f;
-        };
-        const float xmin = val(hb[0]), ymin = val(hb[1]), xmax = -val(hb[2]), ymax = -val(hb[3]);
-        if (!std::isfinite(xmin) || !std::isfinite(xmax) || !std::isfinite(ymin) || !std::isfinite(ymax))
-            return fail(GILA_EINVAL, "positions must be finite for the similarity metric");
+        // grid of about two points per cell over the bounding box
         const double w = std::max(1e-30, (double)xmax - (double)xmin);
         const double h = std::max(1e-30, (double)ymax - (double)ymin);
         double cell = std::sqrt(2.0 * w * h / (double)n);
@@ -511,7 +810,7 @@ static int drawing_metrics(const gila_csr* g, const V* pos, int32_t what, hipStr
                            cstart.as<int64_t>(), cur.as<unsigned long long>(), pts.as<int32_t>());
         hipLaunchKernelGGL(gabriel_degree_kernel, dim3(mgrid(n)), dim3(kBlock), 0, s, n, gr,
                            cstart.as<int64_t>(), pts.as<int32_t>(), pf.as<float2>(), (float)cell,
-                           gdeg.as<int32_t>());
+                           make_float4(xmin, xmax, ymin, ymax), gdeg.as<int32_t>());
         hipLaunchKernelGGL(gabriel_edge_kernel, dim3(rgrid), dim3(kBlock), 0, s, n, gr,
                            cstart.as<int64_t>(), pts.as<int32_t>(), pf.as<float2>(), g->row_ptr,
                            g->col_idx, inter.as<int32_t>());
@@ -523,7 +822,7 @@ static int drawing_metrics(const gila_csr* g, const V* pos, int32_t what, hipStr
         GILA_HIP(hipMemsetAsync(gs.p, 0, sizeof(unsigned long long), s));
         hipLaunchKernelGGL(jaccard_kernel, dim3(jg), dim3(kBlock), 0, s, n, g->row_ptr, gdeg.as<int32_t>(),
                            inter.as<int32_t>(), jaccard, part.as<double>(), gs.as<unsigned long long>());
-        hipLaunchKernelGGL(ordered_sum_kernel, dim3(1), dim3(64), 0, s, jg, part.as<double>(), sum.as<double>());
+        hipLaunchKernelGGL(ordered_sum_kernel, dim3(1), dim3(kBlock), 0, s, jg, part.as<double>(), sum.as<double>());
         GILA_HIP(hipGetLastError());
         double tot = 0.0;
         unsigned long long ge = 0;

@@ -1,8 +1,10 @@
 """GPU parity of the drawing-quality metrics (Section 5.2) against the FP64
 oracle: crossings (total and per edge) and per-vertex Jaccard indices
 bit-exact, edge length mean and deviation to 1e-12.  Degenerate drawings
-(grid points: collinear and cocircular; coincident points; collinear points)
-are included.  At full size (R-MAT 18): sampled per-edge crossings from the
+(grid points: collinear and cocircular; coincident points; collinear points;
+coordinates of very different magnitude, where rounded differences get the
+orientation or in-disc sign wrong) are included, and the total without
+per-edge counts (each pair tested once) must equal the total with them.  At full size (R-MAT 18): sampled per-edge crossings from the
 oracle, the edge lengths in full, and the similarity against a Gabriel
 graph built independently from scipy's Delaunay triangulation (a Delaunay
 edge is a Gabriel edge when both angles opposite it are acute).
@@ -50,17 +52,27 @@ def metric_suite():
     out.append(("path_on_a_line", p, np.stack([np.arange(60.0) ** 1.5, np.zeros(60)], 1)))
     s = inputs.star_graph(40)
     out.append(("star", s, inputs.uniform_positions(s.n, seed=9, width=10.0)))
+    # rounded differences get these signs wrong (the oracle's exact-sign pins)
+    d1, d2 = float(np.float32(1e-20)), float(np.float32(2e-20))
+    x = np.array([[d1, d2], [512.0, 512.0], [256.0, 256.0], [0.0, 512.0]])
+    out.append(("tiny_crossing", inputs.to_csr(4, [0, 2], [1, 3]), x))
+    out.append(("tiny_disc", inputs.path_graph(3), np.array([[d1, 0.0], [2.0, 0.0], [1.0, 1.0]])))
+    rng = np.random.default_rng(5)
+    vals = np.float32([0.0, 1e-20, -3e-20, 1.0, 2.0, 3.0, 1e-7, 1024.0, 1024.0000001, 5e9])
+    for seed in (11, 12, 13):
+        e = inputs.erdos_renyi(60, 300, seed=seed)
+        out.append((f"near_degenerate{seed}", e, vals[rng.integers(0, vals.size, (60, 2))].astype(float)))
     return out
 
 
-def _run(G, g, x, prec, what=7):
+def _run(G, g, x, prec, what=7, per_edge=True):
     import torch
     rp, ci = G.to_device_csr(g)
     pos = torch.from_numpy(x).to(dtype=G.position_dtype(prec), device="cuda").contiguous()
     m = int(oracle.edge_list(g.row_ptr, g.col_idx).shape[0])
-    ec = torch.zeros(max(m, 1), dtype=torch.int64, device="cuda")
+    ec = torch.full((max(m, 1),), -7, dtype=torch.int64, device="cuda")
     jac = torch.zeros(max(g.n, 1), dtype=torch.float64, device="cuda")
-    out = G.drawing_metrics(rp, ci, prec, pos, what, ec, jac)
+    out = G.drawing_metrics(rp, ci, prec, pos, what, ec if per_edge else None, jac)
     return out, ec.cpu().numpy()[:m], jac.cpu().numpy()[: g.n]
 
 
@@ -73,6 +85,9 @@ def test_metrics_small(G, precision):
         out, ec, jac = _run(G, g, xs, prec)
         tot, per = oracle.crossings(g.n, g.row_ptr, g.col_idx, xs, per_edge=True)
         assert out.crossings == tot and np.array_equal(ec, per), name
+        # without per-edge counts each pair is tested once
+        once, _, _ = _run(G, g, xs, prec, what=G.METRIC_CROSSINGS, per_edge=False)
+        assert once.crossings == tot, name
         mu, sd = oracle.edge_lengths(g.n, g.row_ptr, g.col_idx, xs)
         assert out.edge_length_mean == pytest.approx(mu, rel=1e-12, abs=1e-300)
         assert out.edge_length_std == pytest.approx(sd, rel=1e-10, abs=1e-12 * max(mu, 1.0))
@@ -130,6 +145,8 @@ def test_metrics_full_size_rmat18(G):
     sel = np.random.default_rng(4).choice(m, 64, replace=False)
     assert np.array_equal(ec[sel], oracle.edge_crossings(g.n, g.row_ptr, g.col_idx, x, sel))
     assert out.crossings == int(ec.sum()) // 2
+    once, _, _ = _run(G, g, x, G.FP32, what=G.METRIC_CROSSINGS, per_edge=False)
+    assert once.crossings == out.crossings
     mu, sd = oracle.edge_lengths(g.n, g.row_ptr, g.col_idx, x)
     assert out.edge_length_mean == pytest.approx(mu, rel=1e-12)
     assert out.edge_length_std == pytest.approx(sd, rel=1e-10)
