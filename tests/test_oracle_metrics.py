@@ -198,3 +198,20 @@ def test_exact_signs_on_near_degenerate_drawings(seed):
         want = [v for v in range(n) if v != u and not any(
             _frac_in_disc(x[u], x[v], x[w]) for w in range(n) if w not in (u, v))]
         assert list(idx[ptr[u]:ptr[u + 1]]) == want, u
+
+
+def test_jaccard_of_vertices_with_empty_neighbourhoods():
+    """Three coincident points: every disc on one of them holds another (on
+    its boundary), so none has a Gabriel neighbour; without graph edges
+    their Jaccard index is 1 (both sets empty).  A vertex with Gabriel
+    neighbours but no graph edges has index 0."""
+    g = inputs.to_csr(5, [3], [4])
+    x = np.array([[0.0, 0.0], [0.0, 0.0], [0.0, 0.0], [5.0, 0.0], [5.0, 3.0]])
+    ptr, idx = oracle.gabriel(x)
+    assert list(ptr) == [0, 0, 0, 0, 1, 2]
+    mean, per = oracle.similarity(5, g.row_ptr, g.col_idx, x, per_vertex=True)
+    assert list(per) == [1.0, 1.0, 1.0, 1.0, 1.0] and mean == 1.0
+    h = inputs.to_csr(3, [0], [1])
+    y = np.array([[0.0, 0.0], [1.0, 0.0], [0.5, 5.0]])
+    _, per = oracle.similarity(3, h.row_ptr, h.col_idx, y, per_vertex=True)
+    np.testing.assert_allclose(per, [0.5, 0.5, 0.0])
