@@ -327,14 +327,16 @@ typedef struct gila_metrics {
 } gila_metrics;
 
 /* The quality measures of Section 5.2 for the drawing pos_dev (positions in
- * `precision`'s layout, taken at single precision, where the orientation and
- * in-disc tests are exact) of the graph g_dev (validated as for
+ * `precision`'s layout, taken at single precision, where every orientation
+ * and in-disc sign is decided exactly) of the graph g_dev (validated as for
  * gila_build_khop).  `what` is an OR of GILA_METRIC_*; the others are left 0
  * (similarity 1).  edge_crossings_dev (device int64[m], may be NULL)
  * receives the crossings of every edge, edges {u, v} with u < v numbered in
- * row order (row v, its entries above v); jaccard_dev (device double[n], may
- * be NULL) the per-vertex Jaccard indices.  Positions must be finite for the
- * similarity (EINVAL otherwise).  Synchronises `stream`. */
+ * row order (row v, its entries above v); without it each pair of edges is
+ * tested once, with it twice.  jaccard_dev (device double[n], may be NULL)
+ * receives the per-vertex Jaccard indices.  Crossings per edge (CRE) are
+ * crossings / edges.  Positions must be finite (EINVAL otherwise).
+ * Synchronises `stream`. */
 int gila_drawing_metrics(const gila_csr* g_dev, int32_t precision, const void* pos_dev,
                          int32_t what, void* stream, gila_metrics* out,
                          int64_t* edge_crossings_dev, double* jaccard_dev);
