@@ -148,6 +148,15 @@ def num_threads() -> int:
     return int(_load().orc_num_threads())
 
 
+def set_threads(t: int) -> None:
+    """Threads of the oracle's parallel loops from now on (results do not
+    depend on it)."""
+    lib = _load()
+    lib.orc_set_threads.argtypes = [ctypes.c_int32]
+    lib.orc_set_threads.restype = None
+    lib.orc_set_threads(int(t))
+
+
 def khop(n: int, row_ptr, col_idx, k: int, verts=None):
     """k-neighbourhood rows N_v(k) (Section 4.5), v excluded, ascending.
 

@@ -898,3 +898,13 @@ int orc_num_threads(void) {
     return 1;
 #endif
 }
+
+/* Threads of later parallel loops (results never depend on it: threads
+ * split vertices, never a sum). */
+void orc_set_threads(int32_t t) {
+#ifdef _OPENMP
+    omp_set_num_threads(t > 0 ? t : 1);
+#else
+    (void)t;
+#endif
+}

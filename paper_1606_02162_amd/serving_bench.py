@@ -15,6 +15,7 @@ from __future__ import annotations
 
 import json
 import threading
+import sys
 import time
 
 import numpy as np
@@ -87,17 +88,23 @@ def run_per_graph(jobs, sample):
     return svc
 
 
+def _progress(msg: str) -> None:
+    print(f"[serve] {msg}", file=sys.stderr, flush=True)
+
+
 def main(args) -> int:
     import torch
     torch.cuda.set_device(0)
     count, rate = args.serve_jobs, args.serve_rate
     jobs = make_jobs(count)
+    _progress(f"{count} jobs generated")
     arrivals = inputs.poisson_arrivals(count, rate, seed=5)
     arrivals = arrivals - arrivals[0]
     # warm-up: a few jobs (fills the batch autotuner's table, loads kernels)
     warm = make_jobs(8, seed=99)
     run_server(warm, np.zeros(len(warm)))
     lat, queued, wall, info = run_server(jobs, arrivals)
+    _progress(f"server run done in {wall:.1f} s")
     pairs = []
     for g, k, _ in jobs:
         # pairs per iteration counted by the library
@@ -108,7 +115,9 @@ def main(args) -> int:
     inter = float(np.sum(pairs)) * 200
     # plain per-graph solver on every 4th job; FIFO replay of the arrivals
     sample = list(range(0, count, 4))
+    _progress("pairs counted; per-graph solver on every 4th job")
     svc = run_per_graph(jobs, sample)
+    _progress("per-graph solver done")
     scale = float(np.sum([pairs[i] for i in range(count)])) / float(
         np.sum([pairs[i] for i in sample]))
     base_busy = sum(svc.values()) * scale
