@@ -10,7 +10,7 @@
 //
 //   edge_list_kernel      edges {u, v}, u < v, in row order (the part of a
 //                         sorted row above v is a suffix found by bisection)
-//   crossings_kernel      4 edges per thread against a chunk of edges
+//   crossings_kernel      an edge per thread against a chunk of edges
 //                         streamed through LDS (each entry: end points and
 //                         line coefficients); per pair four filtered signs
 //                         decided by wavefront lane masks on the scalar unit;
@@ -177,7 +177,7 @@ struct alignas(16) CrossEntry {
     Line L;
 };
 
-constexpr int kCrossRows = 4;                         // edges per thread
+constexpr int kCrossRows = 1;                         // edges per thread (64 VGPRs: 8 waves per SIMD)
 constexpr int kCrossBlock = kCrossRows * kCrossTile;  // edges per block
 constexpr int64_t kCrossChunk = 8192;                 // edges streamed per block (at least)
 
