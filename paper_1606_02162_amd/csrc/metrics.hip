@@ -35,6 +35,7 @@
 //                         Jaccard intersections)
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <vector>
 
 #include "device_util.h"
@@ -62,7 +63,8 @@ int mgrid(int64_t items) {
 }
 }  // namespace
 
-constexpr int kCrossTile = 256;  // edges per LDS tile of the crossing kernel
+constexpr int kCrossTile = 256;         // edges per LDS tile of the crossing kernel
+constexpr int64_t kGabrielBudget = 2048;  // cells and points one thread visits for a point
 
 // ------------------------------------------------------------------ points and edges
 template <class V>
@@ -419,33 +421,75 @@ __device__ __forceinline__ bool in_disc(float2 u, float2 v, float2 w) {
     return disc_sign_exact(u, v, w) <= 0;
 }
 
-// Visit the cells at Chebyshev distance exactly k from (cx, cy) that lie in
-// columns [x0, x1] and rows [y0, y1] (so a ring costs only its cells inside);
-// f(cell) returns true to stop, and then so does this (returning true).
+// The cells at Chebyshev distance exactly k from (cx, cy) inside columns
+// [x0, x1] and rows [y0, y1] ((cx, cy) itself inside), numbered
+// 0 .. count - 1 so that a thread or the lanes of a wavefront can take them
+// in turn: row cy - k in full (if inside), row cy + k in full (if inside and
+// k > 0), then the rows between at columns cx - k and cx + k (each if
+// inside).  A ring costs only its cells inside.
+struct RingShape {
+    int64_t gx, count;
+    int32_t cx, cy, k, xa, wtop, wbot, mid0, sides;  // sides: 1 left column, 2 right, 3 both
+};
+
+__device__ __forceinline__ RingShape ring_shape(const Grid& g, int32_t cx, int32_t cy, int32_t k, int32_t x0,
+                                                int32_t x1, int32_t y0, int32_t y1) {
+    RingShape R;
+    R.gx = g.gx;
+    R.cx = cx;
+    R.cy = cy;
+    R.k = k;
+    R.xa = max(cx - k, x0);
+    const int32_t w = min(cx + k, x1) - R.xa + 1;
+    R.wtop = cy - k >= y0 ? w : 0;
+    R.wbot = k > 0 && cy + k <= y1 ? w : 0;
+    R.mid0 = max(cy - k + 1, y0);
+    const int32_t nmid = k > 0 ? max(min(cy + k - 1, y1) - R.mid0 + 1, 0) : 0;
+    R.sides = k > 0 ? (cx - k >= x0 ? 1 : 0) | (cx + k <= x1 ? 2 : 0) : 0;
+    R.count = (int64_t)R.wtop + R.wbot + (int64_t)nmid * __popc(R.sides);
+    return R;
+}
+
+__device__ __forceinline__ int64_t ring_cell(const RingShape& R, int64_t i) {
+    if (i < R.wtop) return (int64_t)(R.cy - R.k) * R.gx + R.xa + i;
+    i -= R.wtop;
+    if (i < R.wbot) return (int64_t)(R.cy + R.k) * R.gx + R.xa + i;
+    i -= R.wbot;
+    int64_t y;
+    int32_t x;
+    if (R.sides == 3) {
+        y = R.mid0 + (i >> 1);
+        x = (i & 1) ? R.cx + R.k : R.cx - R.k;
+    } else {
+        y = R.mid0 + i;
+        x = R.sides == 1 ? R.cx - R.k : R.cx + R.k;
+    }
+    return y * R.gx + x;
+}
+
+// Visit the cells of a ring in order; f(cell) returns true to stop, and then
+// so does this (returning true).
 template <class F>
 __device__ __forceinline__ bool ring_cells(const Grid& g, int32_t cx, int32_t cy, int32_t k, int32_t x0,
                                            int32_t x1, int32_t y0, int32_t y1, F&& f) {
-    const int32_t ya = max(cy - k, y0), yb = min(cy + k, y1);
-    const int32_t xa = max(cx - k, x0), xb = min(cx + k, x1);
-    for (int32_t y = ya; y <= yb; ++y) {
-        const int64_t row = (int64_t)y * g.gx;
-        if (y == cy - k || y == cy + k) {
-            for (int32_t x = xa; x <= xb; ++x)
-                if (f(row + x)) return true;
-        } else {
-            if (cx - k >= x0 && f(row + cx - k)) return true;
-            if (cx + k <= x1 && f(row + cx + k)) return true;
-        }
-    }
+    const RingShape R = ring_shape(g, cx, cy, k, x0, x1, y0, y1);
+    for (int64_t i = 0; i < R.count; ++i)
+        if (f(ring_cell(R, i))) return true;
     return false;
 }
+
+// Cells visited (and points looked at) by the Gabriel searches, counted
+// against a thread's budget.
+struct Work {
+    int64_t n = 0;
+};
 
 // No point other than iu, iv in the closed disc with diameter uv.  Cells are
 // scanned outwards from the disc's centre, where a blocking point is most
 // likely to be.
 __device__ bool gabriel_pair_dev(const Grid& g, const int64_t* __restrict__ start,
                                  const int32_t* __restrict__ pts, const float2* __restrict__ p,
-                                 int32_t iu, int32_t iv) {
+                                 int32_t iu, int32_t iv, Work& work) {
     const float2 u = p[iu], v = p[iv];
     const float cx = 0.5f * (u.x + v.x), cy = 0.5f * (u.y + v.y);
     const double dx = (double)v.x - (double)u.x, dy = (double)v.y - (double)u.y;
@@ -457,7 +501,9 @@ __device__ bool gabriel_pair_dev(const Grid& g, const int64_t* __restrict__ star
     const int32_t K = max(max(ccx - x0, x1 - ccx), max(ccy - y0, y1 - ccy));
     for (int32_t k = 0; k <= K; ++k) {
         const bool blocked = ring_cells(g, ccx, ccy, k, x0, x1, y0, y1, [&](int64_t c) {
+            ++work.n;
             for (int64_t q = start[c]; q < start[c + 1]; ++q) {
+                ++work.n;
                 const int32_t w = pts[q];
                 if (w != iu && w != iv && in_disc(u, v, p[w])) return true;
             }
@@ -473,48 +519,49 @@ __device__ __forceinline__ int octant(double dx, double dy) {
     return (dx < 0.0 ? 4 : 0) + (dy < 0.0 ? 2 : 0) + (fabs(dx) < fabs(dy) ? 1 : 0);
 }
 
-// Visit the points of the grid cells at Chebyshev distance exactly k from (cx, cy).
-template <class F>
-__device__ __forceinline__ void ring_points(const Grid& g, const int64_t* __restrict__ start,
-                                            const int32_t* __restrict__ pts, int32_t cx,
-                                            int32_t cy, int32_t k, F&& f) {
-    ring_cells(g, cx, cy, k, 0, g.gx - 1, 0, g.gy - 1, [&](int64_t c) {
-        for (int64_t q = start[c]; q < start[c + 1]; ++q) f(pts[q]);
-        return false;
-    });
-}
+// The cells of ring k (k >= 4) around (cx, cy) that can hold points of
+// octant o, numbered like a ring's.  With (p, q) a cell's index offsets
+// along the octant's major and minor axes, signed towards it, a point of the
+// octant with true offsets A >= B >= 0 (in cell widths) has |p - A| < 2 and
+// |q - B| < 2 (one for its place in the cell, one for a cell index computed
+// in float), so p >= -1, q >= -1 and p >= q - 3: on ring k these are p = k
+// with q in [-1, k] and q = k with p in [k - 3, k - 1].  Only offsets inside
+// the grid are numbered (a degenerate grid of one row would otherwise cost k
+// steps per ring).
+struct SectorShape {
+    int64_t gx, count;
+    int32_t c0, c1, s0, s1, k, qa, na, pa;
+    bool major_y;
+};
 
-// Visit the cells of ring k (k >= 4) around (cx, cy) that can hold points of
-// octant o.  With (p, q) a cell's index offsets along the octant's major and
-// minor axes, signed towards it, a point of the octant with true offsets
-// A >= B >= 0 (in cell widths) has |p - A| < 2 and |q - B| < 2 (one for its
-// place in the cell, one for a cell index computed in float), so p >= -1,
-// q >= -1 and p >= q - 3: on ring k these are p = k with q in [-1, k] and
-// q = k with p in [k - 3, k - 1].
-template <class F>
-__device__ __forceinline__ void sector_cells(const Grid& g, int32_t cx, int32_t cy, int32_t k, int o, F&& f) {
+__device__ __forceinline__ SectorShape sector_shape(const Grid& g, int32_t cx, int32_t cy, int32_t k, int o) {
+    SectorShape S;
     const int32_t sx = (o & 4) ? -1 : 1, sy = (o & 2) ? -1 : 1;
-    const bool major_y = o & 1;
+    S.major_y = o & 1;
+    S.gx = g.gx;
+    S.k = k;
     // centre, extent and sign of the major (0) and minor (1) axes
-    const int32_t c0 = major_y ? cy : cx, n0 = major_y ? g.gy : g.gx, s0 = major_y ? sy : sx;
-    const int32_t c1 = major_y ? cx : cy, n1 = major_y ? g.gx : g.gy, s1 = major_y ? sx : sy;
+    S.c0 = S.major_y ? cy : cx;
+    S.s0 = S.major_y ? sy : sx;
+    S.c1 = S.major_y ? cx : cy;
+    S.s1 = S.major_y ? sx : sy;
+    const int32_t n0 = S.major_y ? g.gy : g.gx, n1 = S.major_y ? g.gx : g.gy;
     // signed offsets t with c + s t inside [0, n): t in [lo, hi], lo <= 0 <= hi
     auto lo = [](int32_t c, int32_t n, int32_t s) { return s > 0 ? -c : c - (n - 1); };
     auto hi = [](int32_t c, int32_t n, int32_t s) { return s > 0 ? n - 1 - c : c; };
-    auto visit = [&](int32_t pp, int32_t qq) {
-        const int32_t a = c0 + s0 * pp, b = c1 + s1 * qq;
-        f((int64_t)(major_y ? a : b) * g.gx + (major_y ? b : a));
-    };
-    // loops run over the offsets inside the grid only (a degenerate grid of
-    // one row would otherwise cost k steps per ring)
-    if (k <= hi(c0, n0, s0)) {
-        const int32_t qa = max(-1, lo(c1, n1, s1)), qb = min(k, hi(c1, n1, s1));
-        for (int32_t qq = qa; qq <= qb; ++qq) visit(k, qq);
-    }
-    if (k <= hi(c1, n1, s1)) {
-        const int32_t pa = max(k - 3, lo(c0, n0, s0)), pb = min(k - 1, hi(c0, n0, s0));
-        for (int32_t pp = pa; pp <= pb; ++pp) visit(pp, k);
-    }
+    S.qa = max(-1, lo(S.c1, n1, S.s1));
+    S.na = k <= hi(S.c0, n0, S.s0) ? max(min(k, hi(S.c1, n1, S.s1)) - S.qa + 1, 0) : 0;
+    S.pa = max(k - 3, lo(S.c0, n0, S.s0));
+    const int32_t nb = k <= hi(S.c1, n1, S.s1) ? max(min(k - 1, hi(S.c0, n0, S.s0)) - S.pa + 1, 0) : 0;
+    S.count = (int64_t)S.na + nb;
+    return S;
+}
+
+__device__ __forceinline__ int64_t sector_cell(const SectorShape& S, int64_t i) {
+    const int32_t pp = i < S.na ? S.k : S.pa + (int32_t)(i - S.na);
+    const int32_t qq = i < S.na ? S.qa + (int32_t)i : S.k;
+    const int64_t a = S.c0 + S.s0 * pp, b = S.c1 + S.s1 * qq;
+    return S.major_y ? a * S.gx + b : b * S.gx + a;
 }
 
 // Full ring, or only the sectors of the octants in `open` when that visits
@@ -523,38 +570,67 @@ __device__ __forceinline__ bool use_full_ring(int32_t k, unsigned open) {
     return k <= 3 || (int32_t)__popc(open) * (k + 5) >= 8 * k;
 }
 
-// Thread per point u, points taken in cell order (a wavefront's points are
-// neighbours).  box = (xmin, xmax, ymin, ymax) of all points.
-__global__ __launch_bounds__(kBlock) void gabriel_degree_kernel(int32_t n, Grid g,
-                                                                const int64_t* __restrict__ start,
-                                                                const int32_t* __restrict__ pts,
-                                                                const float2* __restrict__ p,
-                                                                float cell, float4 box,
-                                                                int32_t* __restrict__ gdeg) {
-    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < n;
-         t += (int64_t)gridDim.x * kBlock) {
-        const int32_t iu = pts[t];
-        const float2 u = p[iu];
-        const int32_t cx = cell_x(g, u.x), cy = cell_y(g, u.y);
-        // reach[o]: the largest squared distance from u to a point of the
-        // bounding box in octant o (its wedge is bounded by the box edges A
-        // along x and B along y; the far corner of the wedge's part inside
-        // is at (A, min(A, B)) or (min(A, B), B))
-        double reach[8], best[8];
-        int32_t ko[8];
-        for (int o = 0; o < 8; ++o) {
-            const double A = (o & 4) ? (double)u.x - box.x : (double)box.y - u.x;
-            const double B = (o & 2) ? (double)u.y - box.z : (double)box.w - u.y;
-            const double mn = fmin(A, B);
-            reach[o] = ((o & 1) ? B * B : A * A) + mn * mn;
-            // an octant that needs dx < 0 (dy < 0) with u on the box's left
-            // (lower) edge holds no point at all
-            if (((o & 4) && A == 0.0) || ((o & 2) && B == 0.0)) reach[o] = 0.0;
-            best[o] = INFINITY;
-            ko[o] = 0;
+__device__ __forceinline__ double wave_min_d(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// Gabriel degree of point iu.  Rings of cells around u find the nearest
+// point of each 45-degree octant until the octant is settled; a second walk
+// over the same rings (or sectors) tests every point of an octant that is
+// not blocked.  WAVE: the lanes of a wavefront take the cells of each ring in
+// turn (all lanes call this for the same point and get the same result);
+// otherwise one thread does it all and gives up (returns -1) once it has
+// visited more than `budget` cells and points.  box = (xmin, xmax, ymin, ymax).
+template <bool WAVE>
+__device__ int32_t gabriel_degree_of(int32_t iu, const Grid& g, const int64_t* __restrict__ start,
+                                     const int32_t* __restrict__ pts, const float2* __restrict__ p,
+                                     float cell, float4 box, int64_t budget) {
+    const int lane = WAVE ? lane64() : 0;
+    const int stride = WAVE ? 64 : 1;
+    Work work;
+    const float2 u = p[iu];
+    const int32_t cx = cell_x(g, u.x), cy = cell_y(g, u.y);
+    // reach[o]: the largest squared distance from u to a point of the
+    // bounding box in octant o (its wedge is bounded by the box edges A
+    // along x and B along y; the far corner of the wedge's part inside is at
+    // (A, min(A, B)) or (min(A, B), B))
+    double reach[8], best[8];
+    int32_t ko[8];
+    for (int o = 0; o < 8; ++o) {
+        const double A = (o & 4) ? (double)u.x - box.x : (double)box.y - u.x;
+        const double B = (o & 2) ? (double)u.y - box.z : (double)box.w - u.y;
+        const double mn = fmin(A, B);
+        reach[o] = ((o & 1) ? B * B : A * A) + mn * mn;
+        // an octant that needs dx < 0 (dy < 0) with u on the box's left
+        // (lower) edge holds no point at all
+        if (((o & 4) && A == 0.0) || ((o & 2) && B == 0.0)) reach[o] = 0.0;
+        best[o] = INFINITY;
+        ko[o] = 0;
+    }
+    // f(cell, octant) for this thread's (lane's) cells of ring k: the whole
+    // ring (octant -1) or the sectors of the octants in `open`
+    auto each_cell = [&](int32_t k, unsigned open, auto&& f) {
+        if (use_full_ring(k, open)) {
+            const RingShape R = ring_shape(g, cx, cy, k, 0, g.gx - 1, 0, g.gy - 1);
+            for (int64_t i = lane; i < R.count; i += stride) f(ring_cell(R, i), -1);
+        } else {
+            for (int o = 0; o < 8; ++o) {
+                if (!(open >> o & 1)) continue;
+                const SectorShape S = sector_shape(g, cx, cy, k, o);
+                for (int64_t i = lane; i < S.count; i += stride) f(sector_cell(S, i), o);
+            }
         }
-        auto nearest = [&](int64_t c) {
+    };
+    // rings beyond kmax lie entirely outside the grid
+    const int32_t kmax = max(max(cx, g.gx - 1 - cx), max(cy, g.gy - 1 - cy));
+    unsigned open = 0xFFu;  // octants not yet settled
+    for (int32_t k = 0; open; ++k) {
+        each_cell(k, open, [&](int64_t c, int) {
+            ++work.n;
             for (int64_t q = start[c]; q < start[c + 1]; ++q) {
+                ++work.n;
                 const int32_t w = pts[q];
                 if (w == iu) continue;
                 const double dx = (double)p[w].x - (double)u.x, dy = (double)p[w].y - (double)u.y;
@@ -563,63 +639,93 @@ __global__ __launch_bounds__(kBlock) void gabriel_degree_kernel(int32_t n, Grid 
                 const int o = octant(dx, dy);
                 best[o] = r2 < best[o] ? r2 : best[o];
             }
-            return false;
-        };
-        // rings beyond kmax lie entirely outside the grid
-        const int32_t kmax = max(max(cx, g.gx - 1 - cx), max(cy, g.gy - 1 - cy));
-        unsigned open = 0xFFu;  // octants not yet settled
-        for (int32_t k = 0; open; ++k) {
-            if (use_full_ring(k, open))
-                ring_cells(g, cx, cy, k, 0, g.gx - 1, 0, g.gy - 1, nearest);
-            else
-                for (int o = 0; o < 8; ++o)
-                    if (open >> o & 1) sector_cells(g, cx, cy, k, o, nearest);
-            // every point of an octant visited so far within (k - 2) cells'
-            // width of u has been seen (a cell index computed in float can be
-            // one off); an octant is settled at ring ko once that covers twice
-            // its nearest squared distance (beyond, its points are blocked)
-            // or, with no point found, its reach (it has none)
-            const double cover = k >= 2 ? (double)(k - 2) * (double)cell : 0.0;
-            for (int o = 0; o < 8; ++o) {
-                if (!(open >> o & 1)) continue;
-                const double need = (best[o] < INFINITY ? 2.0 * best[o] : reach[o]) * (1.0 + 1e-9);
-                if ((k >= 2 && need <= cover * cover) || k >= kmax) {
-                    ko[o] = k;
-                    open &= ~(1u << o);
-                }
+        });
+        if (WAVE)
+            for (int o = 0; o < 8; ++o) best[o] = wave_min_d(best[o]);
+        else if (work.n > budget)
+            return -1;
+        // every point of an octant visited so far within (k - 2) cells' width
+        // of u has been seen (a cell index computed in float can be one off);
+        // an octant is settled at ring ko once that covers twice its nearest
+        // squared distance (beyond, its points are blocked) or, with no point
+        // found, its reach (it has none)
+        const double cover = k >= 2 ? (double)(k - 2) * (double)cell : 0.0;
+        for (int o = 0; o < 8; ++o) {
+            if (!(open >> o & 1)) continue;
+            const double need = (best[o] < INFINITY ? 2.0 * best[o] : reach[o]) * (1.0 + 1e-9);
+            if ((k >= 2 && need <= cover * cover) || k >= kmax) {
+                ko[o] = k;
+                open &= ~(1u << o);
             }
         }
-        int32_t K = 0;
-        for (int o = 0; o < 8; ++o) K = max(K, ko[o]);
-        // candidates: points of octant o on rings up to ko[o] that are not blocked
-        int32_t deg = 0;
-        for (int32_t k = 0; k <= K; ++k) {
-            unsigned live = 0;
-            for (int o = 0; o < 8; ++o) live |= (ko[o] >= k ? 1u : 0u) << o;
-            auto candidates = [&](int only, int64_t c) {
-                for (int64_t q = start[c]; q < start[c + 1]; ++q) {
-                    const int32_t iv = pts[q];
-                    if (iv == iu) continue;
-                    const double dx = (double)p[iv].x - (double)u.x, dy = (double)p[iv].y - (double)u.y;
-                    const double r2 = dx * dx + dy * dy;
-                    const int o = octant(dx, dy);
-                    if (r2 > 0.0) {
-                        if (only >= 0 ? o != only : !(live >> o & 1)) continue;
-                        if (r2 >= 2.0 * best[o] * (1.0 + 1e-9)) continue;  // blocked
-                    } else if (only >= 0 && only != 0) {
-                        continue;  // a coincident point is taken once, with octant 0
-                    }
-                    deg += gabriel_pair_dev(g, start, pts, p, iu, iv) ? 1 : 0;
+    }
+    int32_t K = 0;
+    for (int o = 0; o < 8; ++o) K = max(K, ko[o]);
+    // candidates: points of octant o on rings up to ko[o] that are not blocked
+    int32_t deg = 0;
+    bool over = false;
+    for (int32_t k = 0; k <= K && !over; ++k) {
+        unsigned live = 0;
+        for (int o = 0; o < 8; ++o) live |= (ko[o] >= k ? 1u : 0u) << o;
+        each_cell(k, live, [&](int64_t c, int only) {
+            if (!WAVE && (over = over || work.n > budget)) return;
+            ++work.n;
+            for (int64_t q = start[c]; q < start[c + 1]; ++q) {
+                ++work.n;
+                const int32_t iv = pts[q];
+                if (iv == iu) continue;
+                const double dx = (double)p[iv].x - (double)u.x, dy = (double)p[iv].y - (double)u.y;
+                const double r2 = dx * dx + dy * dy;
+                const int o = octant(dx, dy);
+                if (r2 > 0.0) {
+                    if (only >= 0 ? o != only : !(live >> o & 1)) continue;
+                    if (r2 >= 2.0 * best[o] * (1.0 + 1e-9)) continue;  // blocked
+                } else if (only > 0) {
+                    continue;  // a coincident point is taken once, with octant 0
                 }
-                return false;
-            };
-            if (use_full_ring(k, live))
-                ring_cells(g, cx, cy, k, 0, g.gx - 1, 0, g.gy - 1, [&](int64_t c) { return candidates(-1, c); });
-            else
-                for (int o = 0; o < 8; ++o)
-                    if (live >> o & 1) sector_cells(g, cx, cy, k, o, [&](int64_t c) { return candidates(o, c); });
-        }
-        gdeg[iu] = deg;
+                deg += gabriel_pair_dev(g, start, pts, p, iu, iv, work) ? 1 : 0;
+            }
+        });
+    }
+    if (WAVE) return wave_sum(deg);
+    return over ? -1 : deg;
+}
+
+// Thread per point (in cell order: a wavefront's points are neighbours); a
+// point whose search exceeds the budget is listed in hard[] for
+// gabriel_wave_kernel instead.
+__global__ __launch_bounds__(kBlock) void gabriel_degree_kernel(int32_t n, Grid g,
+                                                                const int64_t* __restrict__ start,
+                                                                const int32_t* __restrict__ pts,
+                                                                const float2* __restrict__ p,
+                                                                float cell, float4 box, int64_t budget,
+                                                                int32_t* __restrict__ gdeg,
+                                                                int32_t* __restrict__ hard,
+                                                                int32_t* __restrict__ hard_count) {
+    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * kBlock) {
+        const int32_t iu = pts[t];
+        const int32_t deg = gabriel_degree_of<false>(iu, g, start, pts, p, cell, box, budget);
+        if (deg >= 0)
+            gdeg[iu] = deg;
+        else
+            hard[atomicAdd(hard_count, 1)] = iu;
+    }
+}
+
+// Wavefront per listed point.
+__global__ __launch_bounds__(kBlock) void gabriel_wave_kernel(Grid g, const int64_t* __restrict__ start,
+                                                              const int32_t* __restrict__ pts,
+                                                              const float2* __restrict__ p, float cell,
+                                                              float4 box, const int32_t* __restrict__ hard,
+                                                              const int32_t* __restrict__ hard_count,
+                                                              int32_t* __restrict__ gdeg) {
+    const int32_t count = *hard_count;
+    const int64_t waves = (int64_t)gridDim.x * kWaves;
+    for (int64_t i = (int64_t)blockIdx.x * kWaves + wave_id(); i < count; i += waves) {
+        const int32_t iu = hard[i];
+        const int32_t deg = gabriel_degree_of<true>(iu, g, start, pts, p, cell, box, 0);
+        if (lane64() == 0) gdeg[iu] = deg;
     }
 }
 
@@ -635,8 +741,9 @@ __global__ __launch_bounds__(kBlock) void gabriel_edge_kernel(int32_t n, Grid g,
     const int64_t waves = (int64_t)gridDim.x * kWaves;
     for (int64_t v = (int64_t)blockIdx.x * kWaves + wave_id(); v < n; v += waves) {
         int32_t c = 0;
+        Work work;
         for (int64_t e = rp[v] + lane64(); e < rp[v + 1]; e += 64)
-            c += gabriel_pair_dev(g, start, pts, p, (int32_t)v, ci[e]) ? 1 : 0;
+            c += gabriel_pair_dev(g, start, pts, p, (int32_t)v, ci[e], work) ? 1 : 0;
         c = wave_sum(c);
         if (lane64() == 0) inter[v] = c;
     }
@@ -808,9 +915,22 @@ static int drawing_metrics(const gila_csr* g, const V* pos, int32_t what, hipStr
                                             ws2.as<int64_t>(), s));
         hipLaunchKernelGGL(cell_fill_kernel, dim3(mgrid(n)), dim3(kBlock), 0, s, n, cellof.as<int32_t>(),
                            cstart.as<int64_t>(), cur.as<unsigned long long>(), pts.as<int32_t>());
+        // a point whose search visits more cells and points than this goes
+        // to a wavefront of its own (GILA_GABRIEL_BUDGET overrides; 0 sends
+        // every point there)
+        int64_t budget = kGabrielBudget;
+        if (const char* e = getenv("GILA_GABRIEL_BUDGET")) budget = std::max<int64_t>(0, std::atoll(e));
+        MBuf hard(s), hcount(s);
+        GILA_TRY(hard.alloc<int32_t>((size_t)n));
+        GILA_TRY(hcount.alloc<int32_t>(1));
+        GILA_HIP(hipMemsetAsync(hcount.p, 0, sizeof(int32_t), s));
+        const float4 fbox = make_float4(xmin, xmax, ymin, ymax);
         hipLaunchKernelGGL(gabriel_degree_kernel, dim3(mgrid(n)), dim3(kBlock), 0, s, n, gr,
-                           cstart.as<int64_t>(), pts.as<int32_t>(), pf.as<float2>(), (float)cell,
-                           make_float4(xmin, xmax, ymin, ymax), gdeg.as<int32_t>());
+                           cstart.as<int64_t>(), pts.as<int32_t>(), pf.as<float2>(), (float)cell, fbox,
+                           budget, gdeg.as<int32_t>(), hard.as<int32_t>(), hcount.as<int32_t>());
+        hipLaunchKernelGGL(gabriel_wave_kernel, dim3(mgrid((int64_t)n * 64)), dim3(kBlock), 0, s, gr,
+                           cstart.as<int64_t>(), pts.as<int32_t>(), pf.as<float2>(), (float)cell, fbox,
+                           hard.as<int32_t>(), hcount.as<int32_t>(), gdeg.as<int32_t>());
         hipLaunchKernelGGL(gabriel_edge_kernel, dim3(rgrid), dim3(kBlock), 0, s, n, gr,
                            cstart.as<int64_t>(), pts.as<int32_t>(), pf.as<float2>(), g->row_ptr,
                            g->col_idx, inter.as<int32_t>());

@@ -1,15 +1,19 @@
-"""GPU parity of the drawing-quality metrics (Section 5.2) against the FP64
+"""GPU parity of the drawing-quality metrics (Section 5.2) against the
 oracle: crossings (total and per edge) and per-vertex Jaccard indices
 bit-exact, edge length mean and deviation to 1e-12.  Degenerate drawings
 (grid points: collinear and cocircular; coincident points; collinear points;
 coordinates of very different magnitude, where rounded differences get the
 orientation or in-disc sign wrong) are included, and the total without
-per-edge counts (each pair tested once) must equal the total with them.  At full size (R-MAT 18): sampled per-edge crossings from the
-oracle, the edge lengths in full, and the similarity against a Gabriel
-graph built independently from scipy's Delaunay triangulation (a Delaunay
-edge is a Gabriel edge when both angles opposite it are acute).
+per-edge counts (each pair tested once) must equal the total with them.
+The Gabriel degrees are checked on both of the kernel's paths (a thread per
+point, and a wavefront per point for searches over the thread's budget).
+At full size (R-MAT 18): sampled per-edge crossings from the oracle, the
+edge lengths in full, and the similarity against a Gabriel graph built
+independently from scipy's Delaunay triangulation (a Delaunay edge is a
+Gabriel edge when both angles opposite it are acute).
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -76,11 +80,27 @@ def _run(G, g, x, prec, what=7, per_edge=True):
     return out, ec.cpu().numpy()[:m], jac.cpu().numpy()[: g.n]
 
 
+@pytest.fixture
+def gabriel_budget(request):
+    """GILA_GABRIEL_BUDGET for the test: None (the library's default), "0"
+    (every point's Gabriel search on a wavefront of its own) or a small
+    budget (a mix of both paths)."""
+    old = os.environ.get("GILA_GABRIEL_BUDGET")
+    if request.param is not None:
+        os.environ["GILA_GABRIEL_BUDGET"] = request.param
+    yield request.param
+    if old is None:
+        os.environ.pop("GILA_GABRIEL_BUDGET", None)
+    else:
+        os.environ["GILA_GABRIEL_BUDGET"] = old
+
+
+@pytest.mark.parametrize("gabriel_budget", [None, "0", "40"], indirect=True)
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_metrics_small(G, precision):
+def test_metrics_small(G, precision, gabriel_budget):
     prec = G.PRECISIONS[precision]
     for name, g, x in metric_suite():
-        print(f"metrics {name} {precision}", flush=True)
+        print(f"metrics {name} {precision} budget {gabriel_budget}", flush=True)
         xs = oracle.single(x)
         out, ec, jac = _run(G, g, xs, prec)
         tot, per = oracle.crossings(g.n, g.row_ptr, g.col_idx, xs, per_edge=True)
@@ -134,7 +154,8 @@ def _delaunay_gabriel(x):
     return adj
 
 
-def test_metrics_full_size_rmat18(G):
+@pytest.mark.parametrize("gabriel_budget", [None, "0"], indirect=True)
+def test_metrics_full_size_rmat18(G, gabriel_budget):
     """Random FP32 drawing of R-MAT 18: 64 sampled edges' crossings, the edge
     lengths, and every vertex's Jaccard index against a Delaunay-derived
     Gabriel graph."""
