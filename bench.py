@@ -789,6 +789,11 @@ def bench_batch(args) -> int:
     per_graph_rate = sp / sample_s
     value = inter * args.steps / total_s
     p50, p99 = _percentiles(lat)
+    # the persistent launch on the device clock: first graph's start to the
+    # last graph's end
+    launch_ms = float(np.max(lat))
+    launch_bytes = algorithmic_bytes_per_iter(P, nnz, nv, 8) * H
+    achieved = launch_bytes / (launch_ms * 1e-3) / 1e9
     out = {
         "metric": "batched layout: k-hop force interactions/s over 4096 graphs",
         "value": value, "unit": "interactions/s", "n_gpus": 1, "steps": args.steps,
@@ -799,6 +804,10 @@ def bench_batch(args) -> int:
                    "graphs": count, "vertices": nv, "total_pairs": P, "iterations": H},
         "run_only_ms": run_s * 1e3,
         "latency_ms_within_batch": {"p50": p50, "p99": p99, "max": float(np.max(lat))},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "batch_layout_kernel<FP32>", "kernel_ms": launch_ms,
+                     "algorithmic_bytes_per_launch": launch_bytes},
         "per_graph_solver": {"interactions_per_s": per_graph_rate,
                              "sample_graphs": len(sample),
                              "speedup_of_batch": value / per_graph_rate},
