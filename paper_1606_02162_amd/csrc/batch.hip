@@ -341,6 +341,22 @@ __device__ __forceinline__ void batch_graph_iteration(
             const int nq = (int)((ke - kb) >> 2);
             R mindd = R(1);
             int q = gl;
+            // four quads per lane per step (the adds in the same order as
+            // two-quad steps, so the same bits)
+            for (; q + 3 * LPV < nq; q += 4 * LPV) {
+                const uint2 w0 = q4[q], w1 = q4[q + LPV], w2 = q4[q + 2 * LPV], w3 = q4[q + 3 * LPV];
+                R ax, ay, bx, by;
+                repulse4<P>(cur[w0.x & 0xFFFFu], cur[w0.x >> 16], cur[w0.y & 0xFFFFu],
+                            cur[w0.y >> 16], xv.x, xv.y, ax, ay, mindd);
+                repulse4<P>(cur[w1.x & 0xFFFFu], cur[w1.x >> 16], cur[w1.y & 0xFFFFu],
+                            cur[w1.y >> 16], xv.x, xv.y, bx, by, mindd);
+                acc.add(ax + bx, ay + by);
+                repulse4<P>(cur[w2.x & 0xFFFFu], cur[w2.x >> 16], cur[w2.y & 0xFFFFu],
+                            cur[w2.y >> 16], xv.x, xv.y, ax, ay, mindd);
+                repulse4<P>(cur[w3.x & 0xFFFFu], cur[w3.x >> 16], cur[w3.y & 0xFFFFu],
+                            cur[w3.y >> 16], xv.x, xv.y, bx, by, mindd);
+                acc.add(ax + bx, ay + by);
+            }
             for (; q + LPV < nq; q += 2 * LPV) {
                 const uint2 w0 = q4[q];
                 const uint2 w1 = q4[q + LPV];
@@ -417,9 +433,10 @@ __global__ __launch_bounds__(kBatchBlock) void batch_layout_kernel(BatchArgs a) 
     using V = typename P::vec2;
     extern __shared__ __align__(16) unsigned char s_raw[];
     __shared__ int s_g;
-    __shared__ int s_stop;
-    __shared__ double s_e[kBatchWaves], s_m[kBatchWaves];
-    __shared__ int64_t s_mv[kBatchWaves], s_c[kBatchWaves];
+    // per-wave statistics, two sets used by alternate iterations (a set is
+    // rewritten two iterations later, after a barrier every reader has passed)
+    __shared__ double s_e[2][kBatchWaves], s_m[2][kBatchWaves];
+    __shared__ int64_t s_mv[2][kBatchWaves], s_c[2][kBatchWaves];
     const int lane = lane64(), w = wave_id();
     for (;;) {
         if (threadIdx.x == 0) s_g = atomicAdd(a.work, 1);
@@ -459,45 +476,39 @@ __global__ __launch_bounds__(kBatchBlock) void batch_layout_kernel(BatchArgs a) 
                 case 32: batch_graph_iteration<P, 32>(a, G, cur, nxt, t, energy, maxd, moved, coinc); break;
                 default: batch_graph_iteration<P, 64>(a, G, cur, nxt, t, energy, maxd, moved, coinc); break;
             }
-            // iteration statistics in a fixed order
+            // iteration statistics: per wave, then every thread combines the
+            // waves' values in the same fixed order (the same bits everywhere).
+            // The barrier also ends this iteration's reads of cur and writes
+            // of nxt before the next iteration swaps them.
+            const int par = h & 1;
             const double we = wave_sum(energy);
             const double wm = wave_max(maxd);
             const int64_t wmv = wave_sum(moved);
             const int64_t wc = wave_sum((int64_t)coinc);
             if (lane == 0) {
-                s_e[w] = we;
-                s_m[w] = wm;
-                s_mv[w] = wmv;
-                s_c[w] = wc;
+                s_e[par][w] = we;
+                s_m[par][w] = wm;
+                s_mv[par][w] = wmv;
+                s_c[par][w] = wc;
             }
             __syncthreads();
-            if (threadIdx.x == 0) {
-                double e = s_e[0], m = s_m[0];
-                int64_t mv = s_mv[0], c = s_c[0];
-                for (int i = 1; i < kBatchWaves; ++i) {
-                    e += s_e[i];
-                    m = s_m[i] > m ? s_m[i] : m;
-                    mv += s_mv[i];
-                    c += s_c[i];
-                }
-                s_e[0] = e;
-                s_m[0] = m;
-                s_mv[0] = mv;
-                s_c[0] = c;
-                s_stop = G.stop_fraction > 0.0 && (double)mv < G.stop_fraction * (double)G.n_active;
+            double e = s_e[par][0], m = s_m[par][0];
+            int64_t mv = s_mv[par][0], c = s_c[par][0];
+            for (int i = 1; i < kBatchWaves; ++i) {
+                e += s_e[par][i];
+                m = s_m[par][i] > m ? s_m[par][i] : m;
+                mv += s_mv[par][i];
+                c += s_c[par][i];
             }
-            __syncthreads();
-            E = s_e[0];
-            M = s_m[0];
-            MV = s_mv[0];
-            C = s_c[0];
+            E = e;
+            M = m;
+            MV = mv;
+            C = c;
             ++run;
             V* tmp = cur;
             cur = nxt;
             nxt = tmp;
-            const int stop = s_stop;
-            __syncthreads();  // everyone has read the statistics before they are reused
-            if (stop) {
+            if (G.stop_fraction > 0.0 && (double)mv < G.stop_fraction * (double)G.n_active) {
                 stopped = 1;
                 break;
             }
