@@ -86,6 +86,11 @@ class Metrics(ctypes.Structure):
                 ("edge_length_mean", ctypes.c_double), ("edge_length_std", ctypes.c_double),
                 ("similarity", ctypes.c_double), ("gabriel_edges", ctypes.c_int64)]
 
+    @property
+    def crossings_per_edge(self) -> float:
+        """CRE: crossings divided by the number of edges (0 without edges)."""
+        return self.crossings / self.edges if self.edges else 0.0
+
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
 

@@ -166,6 +166,7 @@ def test_metrics_full_size_rmat18(G, gabriel_budget):
     sel = np.random.default_rng(4).choice(m, 64, replace=False)
     assert np.array_equal(ec[sel], oracle.edge_crossings(g.n, g.row_ptr, g.col_idx, x, sel))
     assert out.crossings == int(ec.sum()) // 2
+    assert out.crossings_per_edge == out.crossings / g.m
     once, _, _ = _run(G, g, x, G.FP32, what=G.METRIC_CROSSINGS, per_edge=False)
     assert once.crossings == out.crossings
     mu, sd = oracle.edge_lengths(g.n, g.row_ptr, g.col_idx, x)
