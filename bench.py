@@ -150,8 +150,9 @@ def main() -> int:
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU only: there is no multi-GPU path (a large graph would "
+              "be split by rows of its k-hop lists, balanced by pair count, with the positions "
+              "all-gathered every iteration)", file=sys.stderr)
         return 2
 
     import torch

@@ -53,7 +53,7 @@ enum {
     GILA_EDEVICE = -3,      /* a HIP call failed (fault, launch error) */
     GILA_EAGAIN = -4,       /* result not ready yet (gila_poll) */
     GILA_ECANCELED = -5,    /* job was cancelled */
-    GILA_EUNSUPPORTED = -6  /* valid request this build does not support */
+    GILA_EUNSUPPORTED = -6  /* valid request the library does not support */
 };
 
 enum {
