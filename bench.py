@@ -47,6 +47,7 @@ def _cpu_model() -> str:
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_seg_force_rmat18.json")
 TRAFFIC_FILE_PRUNED = os.path.join(ROOT, "profiles", "traffic_seg_force_weighted_rmat18_pruned.json")
+TRAFFIC_FILE_METRICS = os.path.join(ROOT, "profiles", "traffic_crossings_rmat18_layout.json")
 KERNEL_SOURCES = ["paper_1606_02162_amd/csrc/segment.hip", "paper_1606_02162_amd/csrc/iteration.h",
                   "paper_1606_02162_amd/csrc/gila_internal.h"]
 
@@ -64,24 +65,25 @@ def force_kernel_bytes(P: int, nnz: int, n_active: int, pos_bytes: int = 8) -> i
     return 4 * P + 4 * nnz + (16 + pos_bytes) * n_active
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(sources=KERNEL_SOURCES) -> str:
     import hashlib
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
+    for rel in sources:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
 
 
 def measured_traffic(path: str = TRAFFIC_FILE):
-    """HBM bytes per force-kernel launch from the committed rocprofv3 counter
-    summary, if it was taken on the kernel source as it is now."""
+    """HBM bytes per launch of a kernel from a committed rocprofv3 counter
+    summary, if it was taken on the kernel's sources (listed in the summary)
+    as they are now."""
     try:
         with open(path) as f:
             t = json.load(f)
+        if t.get("source_sha256") != kernel_source_hash(t.get("source_files") or KERNEL_SOURCES):
+            return None
     except (OSError, ValueError):
-        return None
-    if t.get("source_sha256") != kernel_source_hash():
         return None
     return t.get("bytes_per_launch")
 
@@ -650,7 +652,8 @@ def bench_metrics(args, wl) -> int:
         "metrics": dict(met.as_dict(), crossings_per_edge=met.crossings_per_edge),
         "ms": part,
         "roofline": {"bound": "alu", "achieved": cross_rate / 1e9, "peak": peak_rate / 1e9,
-                     "unit": "Gpairs/s", "frac": cross_rate / peak_rate, "traffic": None,
+                     "unit": "Gpairs/s", "frac": cross_rate / peak_rate,
+                     "traffic": measured_traffic(TRAFFIC_FILE_METRICS),
                      "kernel": "crossings_kernel", "kernel_ms": part["crossings"],
                      "valu_per_pair": CROSS_VALU_PER_PAIR},
     }
