@@ -385,7 +385,13 @@ int gila_layout_batch(const gila_csr* graphs_dev, int32_t count, const int32_t* 
 typedef struct gila_server gila_server;
 
 /* A server owns four threads (admission, k-hop builds, batched small jobs,
- * ticks) and its own streams on `device`.  Jobs are admitted in arrival order
+ * ticks) and its own streams on `device`.  Unlike the other handles, a server
+ * may be used from several threads at once: gila_submit, gila_poll,
+ * gila_wait, gila_cancel, gila_job_latency and gila_server_info serialise on
+ * the server's lock (gila_wait sleeps without holding it).  A job's result is
+ * taken by one gila_poll or gila_wait; other calls on that ticket, also ones
+ * already waiting, then return GILA_EINVAL.  gila_server_destroy must not
+ * overlap any other call on the server.  Jobs are admitted in arrival order
  * while their device footprint bound fits in hbm_budget_bytes (0 = 90% of free
  * HBM) and fewer than max_slots jobs are in flight.  Small jobs are laid out
  * together in batched launches; larger ones are built, then advance together

@@ -636,6 +636,8 @@ static int take_result(gila_server* s, Job* j, double* out_pos, gila_stats* out)
     }
     s->jobs.erase(j->id);
     delete j;
+    // a gila_wait on the same ticket in another thread re-checks and returns
+    s->cv_done.notify_all();
     if (state == kDone) return GILA_OK;
     if (state == kCanceled) return fail(GILA_ECANCELED, "job was cancelled");
     return fail(status, "job failed: %s", gila_strerror(status));
@@ -656,11 +658,19 @@ int gila_wait(gila_server* s, uint64_t ticket, double* out_pos_host, gila_stats*
     clear_error();
     if (!s) return fail(GILA_EINVAL, "server is NULL");
     std::unique_lock<std::mutex> lk(s->mu);
-    auto it = s->jobs.find(ticket);
-    if (it == s->jobs.end()) return fail(GILA_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
-    Job* j = it->second;
-    s->cv_done.wait(lk, [&] { return j->state != kPending && j->state != kResident; });
-    return take_result(s, j, out_pos_host, out);
+    if (s->jobs.find(ticket) == s->jobs.end())
+        return fail(GILA_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+    // the job is looked up afresh on every wake-up: another thread may have
+    // taken its result (gila_poll or gila_wait on the same ticket) meanwhile
+    s->cv_done.wait(lk, [&] {
+        const auto it = s->jobs.find(ticket);
+        return it == s->jobs.end() || (it->second->state != kPending && it->second->state != kResident);
+    });
+    const auto it = s->jobs.find(ticket);
+    if (it == s->jobs.end())
+        return fail(GILA_EINVAL, "the result of ticket %llu was taken by another call",
+                    (unsigned long long)ticket);
+    return take_result(s, it->second, out_pos_host, out);
 }
 
 int gila_cancel(gila_server* s, uint64_t ticket) {

@@ -6,7 +6,7 @@ ones advanced a few iterations per tick) is compared bitwise with the same
 job run alone, and with the library's direct entry points.  Also: one-step
 parity against the oracle, admission under a small HBM budget (queueing and
 rejection), cancellation, malformed input, an injected allocation failure,
-and the halting rule."""
+the halting rule, and clients on several threads."""
 import time
 
 import numpy as np
@@ -77,6 +77,58 @@ def test_mix_equals_alone_and_direct(G):
         else:
             G.Batch([(rp, ci)], [k]).run([_params(G, g, H)], [pos])
         assert np.array_equal(pos.double().cpu().numpy(), xm), g.name
+
+
+def test_concurrent_clients_and_one_taker(G):
+    """Four client threads submit and wait at once and get the bits a serial
+    run gives; a gila_wait and gila_poll racing for one ticket: exactly one
+    takes the result, the other is told the ticket is gone, nobody hangs."""
+    import threading
+    jobs = _jobs(16, 5, big_every=8)
+    results, errors = {}, []
+    with G.Server(max_slots=64) as srv:
+        srv.config("small_max_vertices", SMALL_MAX)
+
+        def client(c):
+            try:
+                for i in range(c, len(jobs), 4):
+                    g, k, H, x0 = jobs[i]
+                    results[i] = srv.wait(srv.submit(g, k, _params(G, g, H), x0))[0]
+            except Exception as e:  # reported below
+                errors.append(e)
+
+        threads = [threading.Thread(target=client, args=(c,)) for c in range(4)]
+        for t in threads:
+            t.start()
+        for t in threads:
+            t.join(timeout=240)
+        assert not any(t.is_alive() for t in threads) and not errors, errors
+        g, k, H, x0 = jobs[1]
+        ticket = srv.submit(g, k, _params(G, g, 200), x0)
+        got = {}
+
+        def waiter():
+            try:
+                srv.wait(ticket)
+                got["wait"] = G.GILA_OK
+            except G.GilaError as e:
+                got["wait"] = e.code
+
+        w = threading.Thread(target=waiter)
+        w.start()
+        while True:
+            rc, _, _ = srv.poll(ticket)
+            if rc != G.GILA_EAGAIN:
+                break
+            time.sleep(0.001)
+        w.join(timeout=120)
+        assert not w.is_alive()
+        assert sorted([rc, got["wait"]]) == sorted([G.GILA_OK, G.GILA_EINVAL]), (rc, got)
+    with G.Server(max_slots=1) as srv:
+        srv.config("small_max_vertices", SMALL_MAX)
+        for i, (g, k, H, x0) in enumerate(jobs):
+            xs, _ = srv.wait(srv.submit(g, k, _params(G, g, H), x0))
+            assert np.array_equal(xs, results[i]), i
 
 
 def test_one_step_parity(G):
