@@ -162,3 +162,20 @@ def test_layout_components_halting_fp64(G):
     got, ref, C, most, _, runs = _pipeline(G, g, 2, 120, G.FP64, 0.15)
     assert min(runs.values()) < max(runs.values())   # the components stop at different times
     assert np.isfinite(got).all()
+
+
+def test_empty_graph(G):
+    """No vertices: no components, nothing to pack or lay out, no metrics."""
+    import torch
+    g = inputs.to_csr(0, [], [])
+    rp, ci = G.to_device_csr(g)
+    label, count = G.components(rp, ci)
+    assert count == 0 and label.numel() == 0
+    pos = torch.empty((0, 2), dtype=torch.float64, device="cuda")
+    G.pack_components(label, 10.0, G.FP64, pos)
+    params = G.LayoutParams(temperature=G.paper_schedule(1, 1.0, 10.0, 5), ideal_length=10.0,
+                            precision=G.FP64)
+    c, runs = G.layout_components(rp, ci, 2, params, pos)
+    assert c == 0 and len(runs) == 0
+    m = G.drawing_metrics(rp, ci, G.FP64, pos)
+    assert m.edges == 0 and m.crossings == 0 and m.similarity == 1.0 and m.gabriel_edges == 0
