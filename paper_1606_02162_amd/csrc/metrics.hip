@@ -693,8 +693,10 @@ __device__ int32_t gabriel_degree_of(int32_t iu, const Grid& g, const int64_t* _
 
 // Thread per point (in cell order: a wavefront's points are neighbours); a
 // point whose search exceeds the budget is listed in hard[] for
-// gabriel_wave_kernel instead.
-__global__ __launch_bounds__(kBlock) void gabriel_degree_kernel(int32_t n, Grid g,
+// gabriel_wave_kernel instead.  At most 128 VGPRs, so that four waves per
+// SIMD hold every point of a 262k-point drawing at once (the walks are
+// latency-bound: 14.4 ms against 18.2 ms at 137 VGPRs and three waves).
+__global__ __launch_bounds__(kBlock, 4) void gabriel_degree_kernel(int32_t n, Grid g,
                                                                 const int64_t* __restrict__ start,
                                                                 const int32_t* __restrict__ pts,
                                                                 const float2* __restrict__ p,
@@ -713,8 +715,8 @@ __global__ __launch_bounds__(kBlock) void gabriel_degree_kernel(int32_t n, Grid 
     }
 }
 
-// Wavefront per listed point.
-__global__ __launch_bounds__(kBlock) void gabriel_wave_kernel(Grid g, const int64_t* __restrict__ start,
+// Wavefront per listed point (at most 128 VGPRs, as above).
+__global__ __launch_bounds__(kBlock, 4) void gabriel_wave_kernel(Grid g, const int64_t* __restrict__ start,
                                                               const int32_t* __restrict__ pts,
                                                               const float2* __restrict__ p, float cell,
                                                               float4 box, const int32_t* __restrict__ hard,
