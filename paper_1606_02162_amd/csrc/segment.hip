@@ -51,11 +51,11 @@ constexpr int kMaxSegments = 16384;  // segment counters of the build fit in 64 
 constexpr int kLongRow = 16;       // rows longer than kLongRow * nseg: binary search per segment
 constexpr int kFillLanes = 16;     // lanes per slice in the fill pass
 // Weighted repulsion: a segment holds at most kWeightBase bytes of positions
-// (2730 FP32 or 1365 FP64 ones), and its weights (half a position each) go to
+// (5460 FP32 or 2730 FP64 ones), and its weights (half a position each) go to
 // a static LDS array, whose address is a constant the compiler folds into
 // the LDS instruction (the weight address is then o / 2 plus that constant).
-// Positions and weights together stay within 44 KB.
-constexpr int kWeightBase = 21840;
+// Positions and weights together stay within 66 KB (two workgroups per CU).
+constexpr int kWeightBase = 43680;
 
 template <bool WEIGHTED>
 struct WeightLds {
