@@ -51,16 +51,24 @@ __device__ __forceinline__ R pow_int(R x, int k) {
 // from inv = 1 / delta^2 and, for even q, one reciprocal square root.  A
 // coincident pair (dd at most the coincidence bias) gets 0, since its
 // power would overflow.  q = 1 returns inv itself.  Q >= 0 fixes q at
-// compile time; Q < 0 takes the run-time q.
+// compile time; Q < 0 takes the run-time q in [0, 8]: inv^e with
+// e = (q + 1) / 2 <= 4 from its three bits by selects, so that no loop sits
+// in the unrolled pair loop (a loop there made the compiler spill).
 template <int Q = -1, class R>
 __device__ __forceinline__ R repulsion_factor(R dd, R inv, int q, R bias) {
-    if constexpr (Q >= 0) q = Q;
-    if (q == 1) return inv;
+    if constexpr (Q == 1) return inv;
     R r;
     if constexpr (Q == 0) r = fast_rsqrt(dd);
     else if constexpr (Q == 2) r = inv * fast_rsqrt(dd);
     else if constexpr (Q == 3) r = inv * inv;
-    else r = (q & 1) ? pow_int(inv, (q + 1) >> 1) : pow_int(inv, q >> 1) * fast_rsqrt(dd);
+    else {
+        const int e = (q + 1) >> 1;
+        const R inv2 = inv * inv;
+        r = (e & 1) ? inv : R(1);
+        r = (e & 2) ? r * inv2 : r;
+        r = (e & 4) ? r * (inv2 * inv2) : r;
+        if (!(q & 1)) r *= fast_rsqrt(dd);
+    }
     return dd > bias ? r : R(0);
 }
 

@@ -1,8 +1,9 @@
 // Segment-blocked iteration: every neighbour gather comes from LDS.
 //
 // Internal vertex ids are split into segments of S consecutive ids (S
-// positions fill 64 KB of LDS by default: 8190 FP32 positions, the most that
-// 16-bit byte offsets address).  The k-hop row (and adjacency row)
+// positions fill 64 KB of LDS for large degree-ordered graphs: 8190 FP32
+// positions, the most that 16-bit byte offsets address; 32 KB for the
+// others).  The k-hop row (and adjacency row)
 // of an active vertex v is cut into slices, one per segment that the row
 // touches; only non-empty slices exist.  A slice holds its ids as 16-bit LDS
 // byte offsets (id - s*S) * sizeof(position).  Slices are stored
@@ -41,7 +42,12 @@
 
 namespace gila {
 
-constexpr int kSegBlock = 1024;    // threads per segment workgroup
+// Two workgroup shapes of the force kernel, chosen per graph (seg_big):
+// 1024 threads with 64 KB segments (two workgroups per CU) for graphs whose
+// rows scatter over many segments, 512 threads with 32 KB segments (four per
+// CU) for the others.  Both keep eight waves per SIMD.
+template <bool BIG>
+constexpr int seg_block() { return BIG ? 1024 : 512; }
 #ifndef GILA_SEG_WAVES
 #define GILA_SEG_WAVES 8
 #endif
@@ -50,21 +56,24 @@ constexpr int kSegTailPad = 64;    // slack entries after the k-hop offsets
 constexpr int kMaxSegments = 16384;  // segment counters of the build fit in 64 KB of LDS
 constexpr int kLongRow = 16;       // rows longer than kLongRow * nseg: binary search per segment
 constexpr int kFillLanes = 16;     // lanes per slice in the fill pass
-// Weighted repulsion: a segment holds at most kWeightBase bytes of positions
-// (5460 FP32 or 2730 FP64 ones), and its weights (half a position each) go to
-// a static LDS array, whose address is a constant the compiler folds into
-// the LDS instruction (the weight address is then o / 2 plus that constant).
-// Positions and weights together stay within 66 KB (two workgroups per CU).
-constexpr int kWeightBase = 43680;
+// Weighted repulsion: a segment holds at most weight_base<BIG>() bytes of
+// positions (5460 FP32 or 2730 FP64 ones for the large workgroups, half as
+// many for the small ones), and its weights (half a position each) go to a
+// static LDS array, whose address is a constant the compiler folds into the
+// LDS instruction (the weight address is then o / 2 plus that constant).
+// Positions and weights together stay within 66 KB (two large workgroups per
+// CU) or 33 KB (four small ones).
+template <bool BIG>
+constexpr int weight_base() { return BIG ? 43680 : 21840; }
 
-template <bool WEIGHTED>
+template <bool WEIGHTED, bool BIG>
 struct WeightLds {
     __device__ static unsigned char* get() { return nullptr; }
 };
-template <>
-struct WeightLds<true> {
+template <bool BIG>
+struct WeightLds<true, BIG> {
     __device__ static unsigned char* get() {
-        __shared__ __align__(16) unsigned char w[kWeightBase / 2];
+        __shared__ __align__(16) unsigned char w[weight_base<BIG>() / 2];
         return w;
     }
 };
@@ -450,12 +459,16 @@ __device__ __forceinline__ void seg_slices(const SegArgs& a, int ib, int ie,
 }
 
 // FP32: eight waves per SIMD, as two 1024-thread workgroups per CU with a
-// 64 KB segment each (against four 512-thread ones with 32 KB: half the
-// segments, so half the slices per row and twice the pairs per slice; 310
-// against 345 us per R-MAT 18 launch); FP64 needs more registers.  WEIGHTED stages each vertex's repulsion weight
-// in a static LDS array (slot S of positions and weights holds the sentinel).
-template <int PREC, bool WEIGHTED, int Q>
-__global__ __launch_bounds__(kSegBlock, PREC == GILA_FP64 ? 4 : kSegWaves) void seg_force_kernel(SegArgs a) {
+// 64 KB segment each (BIG) or four 512-thread ones with 32 KB.  Where rows
+// scatter, BIG halves the segments, so the slices per row, and doubles the
+// pairs per slice (310 against 345 us per R-MAT 18 launch); where rows are
+// local they touch one or two segments either way and the smaller
+// workgroups keep more of them per graph.  FP64 needs more registers.
+// WEIGHTED stages each vertex's repulsion weight in a static LDS array (slot
+// S of positions and weights holds the sentinel).
+template <int PREC, bool WEIGHTED, int Q, bool BIG>
+__global__ __launch_bounds__(seg_block<BIG>(), PREC == GILA_FP64 ? 4 : kSegWaves) void seg_force_kernel(SegArgs a) {
+    constexpr int kSegBlock = seg_block<BIG>();
     using P = Prec<PREC>;
     using V = typename P::vec2;
     extern __shared__ __align__(16) unsigned char s_raw[];
@@ -471,7 +484,7 @@ __global__ __launch_bounds__(kSegBlock, PREC == GILA_FP64 ? 4 : kSegWaves) void 
     const int cnt = (int)(left < a.seg ? left : a.seg);
     for (int i = threadIdx.x; i < cnt; i += kSegBlock) lp[i] = gpos[base + i];
     using R = typename P::real;
-    R* lw = reinterpret_cast<R*>(WeightLds<WEIGHTED>::get());
+    R* lw = reinterpret_cast<R*>(WeightLds<WEIGHTED, BIG>::get());
     if constexpr (WEIGHTED) {
         const R* gw = reinterpret_cast<const R*>(a.mass);
         for (int i = threadIdx.x; i < cnt; i += kSegBlock) lw[i] = gw[base + i];
@@ -560,14 +573,24 @@ static int slot_bytes(const gila_khop* kh, int precision) {
     return kh->mass64 ? pb + pb / 2 : pb;
 }
 
+// The large workgroup shape for degree-ordered graphs (rows scatter over the
+// ids) of more than one large segment; the small one for caller-ordered
+// graphs (meshes, rings, small worlds: rows stay in one or two segments).
+static bool seg_big(const gila_khop* kh) {
+    if (const char* e = getenv("GILA_SEG_SHAPE")) return std::strcmp(e, "small") != 0;
+    return !kh->caller_order && kh->n_active > 8190;
+}
+
 int seg_size_for(const gila_khop* kh, int precision) {
     const int pos_bytes = pos_bytes_of(precision);
+    const bool big = seg_big(kh);
     // LDS of one workgroup: the segment's staged vertices plus ~1 KB of other state
     const int64_t lds_cap = (int64_t)device_info(kh->device).max_lds_per_block - 1024;
-    const int64_t want = std::min<int64_t>(env_int("GILA_SEG_BYTES", 65536), lds_cap);
+    const int64_t want = std::min<int64_t>(env_int("GILA_SEG_BYTES", big ? 65536 : 32768), lds_cap);
     int S = (int)(want / slot_bytes(kh, precision)) - 1;  // one slot for the sentinel
     S = std::min(S, 65535 / pos_bytes - 1);  // byte offsets, sentinel included, fit in 16 bits
-    if (kh->mass64) S = std::min(S, kWeightBase / pos_bytes - 1);  // positions below the weights
+    if (kh->mass64)  // positions below the weights
+        S = std::min(S, (big ? weight_base<true>() : weight_base<false>()) / pos_bytes - 1);
     return std::max(64, S);
 }
 
@@ -799,14 +822,16 @@ int build_segments(gila_khop* kh, int precision, hipStream_t st) {
     const size_t lds = seg_lds_bytes(kh, precision, S);
     if (lds > 48 * 1024) {
         const void* kernels[] = {
-#define GILA_SEG_KERNELS(W, Q)                                      \
-    (const void*)seg_force_kernel<GILA_FP64, W, Q>,                 \
-        (const void*)seg_force_kernel<GILA_FP32, W, Q>,             \
-        (const void*)seg_force_kernel<GILA_FP32_KAHAN, W, Q>
-            GILA_SEG_KERNELS(false, 1), GILA_SEG_KERNELS(true, 1),  GILA_SEG_KERNELS(false, 0),
-            GILA_SEG_KERNELS(true, 0),  GILA_SEG_KERNELS(false, 2), GILA_SEG_KERNELS(true, 2),
-            GILA_SEG_KERNELS(false, 3), GILA_SEG_KERNELS(true, 3),  GILA_SEG_KERNELS(false, -1),
-            GILA_SEG_KERNELS(true, -1)
+#define GILA_SEG_KERNELS(W, Q, B)                                   \
+    (const void*)seg_force_kernel<GILA_FP64, W, Q, B>,              \
+        (const void*)seg_force_kernel<GILA_FP32, W, Q, B>,          \
+        (const void*)seg_force_kernel<GILA_FP32_KAHAN, W, Q, B>
+#define GILA_SEG_KERNELS_B(W, Q) GILA_SEG_KERNELS(W, Q, false), GILA_SEG_KERNELS(W, Q, true)
+            GILA_SEG_KERNELS_B(false, 1), GILA_SEG_KERNELS_B(true, 1),  GILA_SEG_KERNELS_B(false, 0),
+            GILA_SEG_KERNELS_B(true, 0),  GILA_SEG_KERNELS_B(false, 2), GILA_SEG_KERNELS_B(true, 2),
+            GILA_SEG_KERNELS_B(false, 3), GILA_SEG_KERNELS_B(true, 3),  GILA_SEG_KERNELS_B(false, -1),
+            GILA_SEG_KERNELS_B(true, -1)
+#undef GILA_SEG_KERNELS_B
 #undef GILA_SEG_KERNELS
         };
         for (const void* k : kernels)
@@ -822,26 +847,26 @@ int build_segments(gila_khop* kh, int precision, hipStream_t st) {
     return GILA_OK;
 }
 
-template <bool WEIGHTED, int Q>
-static void launch_seg_force(int precision, dim3 sg, dim3 sb, size_t lds, hipStream_t s,
-                             const SegArgs& g) {
+template <bool WEIGHTED, int Q, bool BIG>
+static void launch_seg_force(int precision, dim3 sg, size_t lds, hipStream_t s, const SegArgs& g) {
+    const dim3 sb(seg_block<BIG>());
     switch (precision) {
-        case GILA_FP64: hipLaunchKernelGGL((seg_force_kernel<GILA_FP64, WEIGHTED, Q>), sg, sb, lds, s, g); break;
-        case GILA_FP32: hipLaunchKernelGGL((seg_force_kernel<GILA_FP32, WEIGHTED, Q>), sg, sb, lds, s, g); break;
-        default: hipLaunchKernelGGL((seg_force_kernel<GILA_FP32_KAHAN, WEIGHTED, Q>), sg, sb, lds, s, g); break;
+        case GILA_FP64: hipLaunchKernelGGL((seg_force_kernel<GILA_FP64, WEIGHTED, Q, BIG>), sg, sb, lds, s, g); break;
+        case GILA_FP32: hipLaunchKernelGGL((seg_force_kernel<GILA_FP32, WEIGHTED, Q, BIG>), sg, sb, lds, s, g); break;
+        default: hipLaunchKernelGGL((seg_force_kernel<GILA_FP32_KAHAN, WEIGHTED, Q, BIG>), sg, sb, lds, s, g); break;
     }
 }
 
 // Repulsion exponents with a kernel of their own; others run the general one.
-template <bool WEIGHTED>
-static void launch_seg_force_q(int q, int precision, dim3 sg, dim3 sb, size_t lds, hipStream_t s,
+template <bool WEIGHTED, bool BIG>
+static void launch_seg_force_q(int q, int precision, dim3 sg, size_t lds, hipStream_t s,
                                const SegArgs& g) {
     switch (q) {
-        case 1: launch_seg_force<WEIGHTED, 1>(precision, sg, sb, lds, s, g); break;
-        case 0: launch_seg_force<WEIGHTED, 0>(precision, sg, sb, lds, s, g); break;
-        case 2: launch_seg_force<WEIGHTED, 2>(precision, sg, sb, lds, s, g); break;
-        case 3: launch_seg_force<WEIGHTED, 3>(precision, sg, sb, lds, s, g); break;
-        default: launch_seg_force<WEIGHTED, -1>(precision, sg, sb, lds, s, g); break;
+        case 1: launch_seg_force<WEIGHTED, 1, BIG>(precision, sg, lds, s, g); break;
+        case 0: launch_seg_force<WEIGHTED, 0, BIG>(precision, sg, lds, s, g); break;
+        case 2: launch_seg_force<WEIGHTED, 2, BIG>(precision, sg, lds, s, g); break;
+        case 3: launch_seg_force<WEIGHTED, 3, BIG>(precision, sg, lds, s, g); break;
+        default: launch_seg_force<WEIGHTED, -1, BIG>(precision, sg, lds, s, g); break;
     }
 }
 
@@ -874,10 +899,13 @@ int launch_segment_step(const gila_khop* kh, int precision, const StepArgs& a, h
     if ((a.mass != nullptr) != kh->seg_weighted)
         return fail(GILA_EINVAL, "segment layout built for other repulsion weights");
     const size_t lds = seg_lds_bytes(kh, precision, kh->seg);
-    const dim3 sg(kh->seg_grid), sb(kSegBlock), cg(kh->comb_grid), cb(kBlock);
+    const dim3 sg(kh->seg_grid), cg(kh->comb_grid), cb(kBlock);
+    const bool big = seg_big(kh);
     if (ev) GILA_HIP(hipEventRecord(ev[0], s));
-    if (a.mass) launch_seg_force_q<true>(a.rep_q, precision, sg, sb, lds, s, g);
-    else launch_seg_force_q<false>(a.rep_q, precision, sg, sb, lds, s, g);
+    if (a.mass && big) launch_seg_force_q<true, true>(a.rep_q, precision, sg, lds, s, g);
+    else if (a.mass) launch_seg_force_q<true, false>(a.rep_q, precision, sg, lds, s, g);
+    else if (big) launch_seg_force_q<false, true>(a.rep_q, precision, sg, lds, s, g);
+    else launch_seg_force_q<false, false>(a.rep_q, precision, sg, lds, s, g);
     if (ev) GILA_HIP(hipEventRecord(ev[1], s));
     switch (precision) {
         case GILA_FP64: hipLaunchKernelGGL(seg_combine_kernel<GILA_FP64>, cg, cb, 0, s, c); break;
