@@ -243,6 +243,7 @@ struct gila_khop {
     double2* part = nullptr;        // [T] partial force of each slice, row-major
     int32_t seg_precision = -1;     // precision the segment size was chosen for
     bool seg_weighted = false;      // segment size chosen with a weight per staged vertex
+    bool seg_large = false;         // force kernel shape: 1024 threads (else 512)
     // weights of the repulsion each vertex exerts (internal ids), null = unit
     double* mass64 = nullptr;
     float* mass32 = nullptr;

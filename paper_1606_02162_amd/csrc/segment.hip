@@ -577,7 +577,10 @@ static int slot_bytes(const gila_khop* kh, int precision) {
 // ids) of more than one large segment; the small one for caller-ordered
 // graphs (meshes, rings, small worlds: rows stay in one or two segments).
 static bool seg_big(const gila_khop* kh) {
-    if (const char* e = getenv("GILA_SEG_SHAPE")) return std::strcmp(e, "small") != 0;
+    if (const char* e = getenv("GILA_SEG_SHAPE")) {
+        if (!std::strcmp(e, "small")) return false;
+        if (!std::strcmp(e, "large")) return true;
+    }
     return !kh->caller_order && kh->n_active > 8190;
 }
 
@@ -603,7 +606,7 @@ static size_t seg_lds_bytes(const gila_khop* kh, int precision, int S) {
 
 bool segment_ready_for(const gila_khop* kh, int precision) {
     return kh->seg_ready && segment_path_enabled() && kh->seg == seg_size_for(kh, precision) &&
-           kh->seg_weighted == (kh->mass64 != nullptr);
+           kh->seg_weighted == (kh->mass64 != nullptr) && kh->seg_large == seg_big(kh);
 }
 
 void free_segments(gila_khop* kh, Release rel) {
@@ -652,7 +655,8 @@ int build_segments(gila_khop* kh, int precision, hipStream_t st) {
     const int pos_bytes = precision == GILA_FP64 ? 16 : 8;
     const int S = seg_size_for(kh, precision);
     const bool weighted = kh->mass64 != nullptr;
-    if (kh->seg_ready && kh->seg == S && kh->seg_weighted == weighted) return GILA_OK;
+    if (kh->seg_ready && kh->seg == S && kh->seg_weighted == weighted && kh->seg_large == seg_big(kh))
+        return GILA_OK;
     free_segments(kh);
     if (na == 0) return GILA_OK;
     if (kh->nnz >= (int64_t)INT32_MAX) return fail(GILA_EUNSUPPORTED, "adjacency too large");
@@ -794,6 +798,7 @@ int build_segments(gila_khop* kh, int precision, hipStream_t st) {
         for (int t = 0; t < c; ++t) plan.push_back(make_int4(sg, t, c, 0));
     }
     kh->seg = S;
+    kh->seg_large = seg_big(kh);  // the shape S was chosen for; launches use this one
     kh->nseg = nseg;
     kh->nslices = T;
     kh->seg_grid = (int32_t)plan.size();
@@ -900,7 +905,7 @@ int launch_segment_step(const gila_khop* kh, int precision, const StepArgs& a, h
         return fail(GILA_EINVAL, "segment layout built for other repulsion weights");
     const size_t lds = seg_lds_bytes(kh, precision, kh->seg);
     const dim3 sg(kh->seg_grid), cg(kh->comb_grid), cb(kBlock);
-    const bool big = seg_big(kh);
+    const bool big = kh->seg_large;
     if (ev) GILA_HIP(hipEventRecord(ev[0], s));
     if (a.mass && big) launch_seg_force_q<true, true>(a.rep_q, precision, sg, lds, s, g);
     else if (a.mass) launch_seg_force_q<true, false>(a.rep_q, precision, sg, lds, s, g);
