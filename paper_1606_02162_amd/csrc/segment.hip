@@ -788,8 +788,15 @@ int build_segments(gila_khop* kh, int precision, hipStream_t st) {
     // --- workgroups: per segment, ranges of about equal work
     const int cus = device_info(kh->device).cus;
     const int64_t total = hs[2 * nseg + 1] - hs[1];
-    const int64_t target_wgs = (int64_t)cus * env_int("GILA_SEG_WG_PER_CU", 16);
-    const int64_t per_wg = std::max<int64_t>(4096, total / std::max<int64_t>(1, target_wgs));
+    // About 16 workgroups per CU, but no fewer than ~96K work units each
+    // while that still leaves 8 per CU: staging the segment costs every
+    // thread the same few loads whatever its share of pairs (BA 100k, k = 3:
+    // 194 -> 182 us per launch; R-MAT 18, whose workgroups get ~130K at 16
+    // per CU, is unchanged).  Small graphs keep workgroups of 4096 units.
+    const int64_t wpc = std::max<int64_t>(1, env_int("GILA_SEG_WG_PER_CU", 16));
+    const int64_t floor_w = std::min<int64_t>(env_int("GILA_SEG_WG_MIN_WORK", 98304),
+                                              total / ((int64_t)cus * std::max<int64_t>(1, wpc / 2)));
+    const int64_t per_wg = std::max<int64_t>({4096, floor_w, total / ((int64_t)cus * wpc)});
     std::vector<int4> plan;
     for (int32_t sg = 0; sg < nseg; ++sg) {
         if (hs[2 * sg + 2] == hs[2 * sg]) continue;
