@@ -57,14 +57,14 @@ constexpr int kMaxSegments = 16384;  // segment counters of the build fit in 64 
 constexpr int kLongRow = 16;       // rows longer than kLongRow * nseg: binary search per segment
 constexpr int kFillLanes = 16;     // lanes per slice in the fill pass
 // Weighted repulsion: a segment holds at most weight_base<BIG>() bytes of
-// positions (5460 FP32 or 2730 FP64 ones for the large workgroups, half as
-// many for the small ones), and its weights (half a position each) go to a
+// positions (6500 FP32 or 3250 FP64 ones for the large workgroups, 2730 or
+// 1365 for the small ones), and its weights (half a position each) go to a
 // static LDS array, whose address is a constant the compiler folds into the
 // LDS instruction (the weight address is then o / 2 plus that constant).
-// Positions and weights together stay within 66 KB (two large workgroups per
-// CU) or 33 KB (four small ones).
+// Positions and weights together take 78 KB (two large workgroups in the
+// 160 KB of a CU) or 33 KB (four small ones).
 template <bool BIG>
-constexpr int weight_base() { return BIG ? 43680 : 21840; }
+constexpr int weight_base() { return BIG ? 52000 : 21840; }
 
 template <bool WEIGHTED, bool BIG>
 struct WeightLds {
@@ -589,7 +589,11 @@ int seg_size_for(const gila_khop* kh, int precision) {
     const bool big = seg_big(kh);
     // LDS of one workgroup: the segment's staged vertices plus ~1 KB of other state
     const int64_t lds_cap = (int64_t)device_info(kh->device).max_lds_per_block - 1024;
-    const int64_t want = std::min<int64_t>(env_int("GILA_SEG_BYTES", big ? 65536 : 32768), lds_cap);
+    // positions (and weights) of one segment: 64 KB or 32 KB, or all that
+    // the weight array of the shape allows
+    const int64_t dflt = kh->mass64 ? (int64_t)(big ? weight_base<true>() : weight_base<false>()) * 3 / 2
+                                    : (big ? 65536 : 32768);
+    const int64_t want = std::min<int64_t>(env_int("GILA_SEG_BYTES", dflt), lds_cap);
     int S = (int)(want / slot_bytes(kh, precision)) - 1;  // one slot for the sentinel
     S = std::min(S, 65535 / pos_bytes - 1);  // byte offsets, sentinel included, fit in 16 bits
     if (kh->mass64)  // positions below the weights
