@@ -425,8 +425,12 @@ __device__ __forceinline__ void seg_slices(const SegArgs& a, int ib, int ie,
             const int nq = (int)((ke - kb) >> 2);
             R mindd = R(1);
             // four quads (16 neighbours) per lane per step, one compensated
-            // add per eight terms; then the remaining quads one by one
+            // add per eight terms; then the remaining quads one by one.  FP64
+            // with a run-time exponent takes them one by one throughout: 16
+            // pairs in flight exceed the 128 VGPRs of four waves per SIMD.
+            constexpr bool kFourQuads = !(sizeof(R) == 8 && Q < 0);
             int q = gl;
+            if constexpr (kFourQuads)
             for (; q + 3 * LPV < nq; q += 4 * LPV) {
                 const uint2 w0 = q4[q];
                 const uint2 w1 = q4[q + LPV];
