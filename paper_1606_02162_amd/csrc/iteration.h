@@ -38,6 +38,14 @@ __device__ __forceinline__ R fast_rsqrt(R x) {
     else return R(1) / sqrt(x);
 }
 
+// 1 / sqrt(dd) where inv = 1 / dd is at hand: in FP64 the square root of
+// inv, which saves a double division per pair.
+template <class R>
+__device__ __forceinline__ R rsqrt_with_inv(R dd, R inv) {
+    if constexpr (sizeof(R) == 4) return fast_rsqrt(dd);
+    else return sqrt(inv);
+}
+
 // x^k for a small non-negative integer k (uniform across the wavefront).
 template <class R>
 __device__ __forceinline__ R pow_int(R x, int k) {
@@ -58,8 +66,8 @@ template <int Q = -1, class R>
 __device__ __forceinline__ R repulsion_factor(R dd, R inv, int q, R bias) {
     if constexpr (Q == 1) return inv;
     R r;
-    if constexpr (Q == 0) r = fast_rsqrt(dd);
-    else if constexpr (Q == 2) r = inv * fast_rsqrt(dd);
+    if constexpr (Q == 0) r = rsqrt_with_inv(dd, inv);
+    else if constexpr (Q == 2) r = inv * rsqrt_with_inv(dd, inv);
     else if constexpr (Q == 3) r = inv * inv;
     else {
         const int e = (q + 1) >> 1;
@@ -67,6 +75,8 @@ __device__ __forceinline__ R repulsion_factor(R dd, R inv, int q, R bias) {
         r = (e & 1) ? inv : R(1);
         r = (e & 2) ? r * inv2 : r;
         r = (e & 4) ? r * (inv2 * inv2) : r;
+        // (1 / sqrt(dd) here, not sqrt(inv): the compiler keeps a branch
+        // around its division for odd q but computes sqrt(inv) for every q)
         if (!(q & 1)) r *= fast_rsqrt(dd);
     }
     return dd > bias ? r : R(0);
