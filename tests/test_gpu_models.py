@@ -16,8 +16,10 @@ from paper_1606_02162_amd import inputs
 pytestmark = pytest.mark.gpu
 
 # (model, p, q) as passed to the library; p, q as the oracle takes them
+# q in {0, 1, 2, 3} has a force kernel of its own; q = 5 and q = 8 (odd and
+# even, the largest allowed) take the run-time exponent path.
 MODELS = [("linlog", 1, 0, 1), ("pq22", 2, 2, 2), ("pq11", 2, 1, 1), ("pq03", 2, 0, 3),
-          ("pq30", 2, 3, 0), ("pq41", 2, 4, 1)]
+          ("pq30", 2, 3, 0), ("pq41", 2, 4, 1), ("pq45", 2, 4, 5), ("pq28", 2, 2, 8)]
 
 
 @pytest.fixture(scope="module")
