@@ -24,7 +24,7 @@ import pytest
 import oracle
 from paper_1606_02162_amd import inputs
 
-MODELS = [(0, 1), (1, 1), (2, 2), (3, 1), (1, 2), (2, 0), (0, 3), (4, 2)]
+MODELS = [(0, 1), (1, 1), (2, 2), (3, 1), (1, 2), (2, 0), (0, 3), (4, 2), (4, 5), (2, 8)]
 
 
 def _pairs(kp, ki):
