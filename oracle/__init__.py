@@ -76,6 +76,8 @@ def _load():
     lib.orc_forces.argtypes = [ctypes.c_int32, _i64p, _i32p, ctypes.c_int64, vp, _i64p, _i32p,
                                ctypes.c_double, vp, i32, i32, _f64p, _f64p,
                                ctypes.POINTER(ctypes.c_int64)]
+    lib.orc_force_magnitudes.argtypes = [ctypes.c_int32, _i64p, _i32p, ctypes.c_int64, vp, _i64p,
+                                         _i32p, ctypes.c_double, vp, i32, i32, _f64p, _f64p]
     lib.orc_cap.argtypes = [ctypes.c_int64, _f64p, ctypes.c_double, _f64p]
     lib.orc_step.argtypes = [ctypes.c_int32, _i64p, _i32p, _i64p, _i32p, ctypes.c_double, vp,
                              i32, i32, ctypes.c_double, ctypes.c_double, _f64p, _f64p, _f64p,
@@ -105,7 +107,8 @@ def _load():
     lib.orc_gabriel.argtypes = [ctypes.c_int32, _f64p, _i64p, vp]
     lib.orc_jaccard.argtypes = [ctypes.c_int32, _i64p, _i32p, _i64p, _i32p, vp,
                                 ctypes.POINTER(ctypes.c_double)]
-    for f in ("orc_khop_count", "orc_khop_fill", "orc_forces", "orc_cap", "orc_step",
+    for f in ("orc_khop_count", "orc_khop_fill", "orc_forces", "orc_force_magnitudes", "orc_cap",
+              "orc_step",
               "orc_layout", "orc_prune", "orc_pruned_graph", "orc_reinsert", "orc_components",
               "orc_pack", "orc_crossings", "orc_edge_crossings", "orc_edge_lengths", "orc_gabriel",
               "orc_jaccard"):
@@ -202,6 +205,32 @@ def forces(n: int, row_ptr, col_idx, kptr, kidx, d: float, pos, verts=None, mass
     _check(lib.orc_forces(n, rp, ci, count, vptr, kp, ki, float(d), mptr, int(p), int(q), pos_,
                           F, ctypes.byref(coinc)), "forces")
     return F[: 2 * count].reshape(count, 2), int(coinc.value)
+
+
+def force_magnitudes(n: int, row_ptr, col_idx, kptr, kidx, d: float, pos, verts=None, mass=None,
+                     p: int = 2, q: int = 1):
+    """S_v = sum of the magnitudes of the terms of F_v (Section 3.1:
+    delta^p / d per adjacent u, w_u d^2 / delta^q per u in N_v(k)); rows and
+    arguments as in :func:`forces`.  Returns float64[count].
+
+    S_v bounds |F_v|, and a force whose every term is rounded to a relative
+    error e is off by at most e * S_v: the scale of a per-vertex gate.
+    kappa_v = S_v / |F_v| is the condition number of the sum.
+    """
+    lib = _load()
+    rp, ci = _csr(row_ptr, col_idx)
+    marr, mptr = _mass(mass, n)
+    varr, vptr = _verts(verts)
+    count = n if varr is None else varr.size
+    pos_ = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1)
+    kp = np.ascontiguousarray(kptr, dtype=np.int64)
+    ki = np.ascontiguousarray(kidx, dtype=np.int32)
+    if ki.size == 0:
+        ki = np.zeros(1, dtype=np.int32)
+    S = np.zeros(max(count, 1), dtype=np.float64)
+    _check(lib.orc_force_magnitudes(n, rp, ci, count, vptr, kp, ki, float(d), mptr, int(p),
+                                    int(q), pos_, S), "force_magnitudes")
+    return S[:count]
 
 
 def cap(F, t: float):

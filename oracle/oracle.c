@@ -249,6 +249,41 @@ int orc_forces(int32_t n, const int64_t* row_ptr, const int32_t* col_idx,
     return ORC_OK;
 }
 
+/* Sum of the magnitudes of the terms that make up F_v (Section 3.1:
+ * ||f^a|| = delta^p / d per adjacent u, ||f^r|| = d^2 / delta^q per u in
+ * N_v(k), the latter scaled by u's weight when masses are given; coincident
+ * ends contribute nothing, as in the force).  S_v bounds |F_v| and sets the
+ * scale of the rounding error of any evaluation of F_v that rounds each term:
+ * a sum of terms each off by a relative e is off by at most e * S_v.  Rows as
+ * in orc_forces; S is [count]. */
+int orc_force_magnitudes(int32_t n, const int64_t* row_ptr, const int32_t* col_idx,
+                         int64_t count, const int32_t* verts, const int64_t* kptr,
+                         const int32_t* kidx, double d, const double* mass, int32_t p,
+                         int32_t q, const double* pos, double* S) {
+    if (n < 0 || !(d > 0.0) || p < 0 || q < 0) return ORC_EINVAL;
+    if (verts == NULL) count = n;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < count; ++i) {
+        const int32_t v = verts ? verts[i] : (int32_t)i;
+        const double xv = pos[2 * (int64_t)v], yv = pos[2 * (int64_t)v + 1];
+        double s = 0.0;
+        for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+            const int32_t u = col_idx[e];
+            const double dx = pos[2 * (int64_t)u] - xv, dy = pos[2 * (int64_t)u + 1] - yv;
+            const double delta = sqrt(dx * dx + dy * dy);
+            if (delta > 0.0) s += pow(delta, (double)p) / d;
+        }
+        for (int64_t j = kptr[i]; j < kptr[i + 1]; ++j) {
+            const int32_t u = kidx[j];
+            const double dx = xv - pos[2 * (int64_t)u], dy = yv - pos[2 * (int64_t)u + 1];
+            const double delta = sqrt(dx * dx + dy * dy);
+            if (delta > 0.0) s += (mass ? mass[u] : 1.0) * (d * d / pow(delta, (double)q));
+        }
+        S[i] = s;
+    }
+    return ORC_OK;
+}
+
 /* ------------------------------------------------------------------ */
 /* Capped move (Section 3.1: displacement limited by the temperature)  */
 /* ------------------------------------------------------------------ */
@@ -747,15 +782,18 @@ int orc_edge_crossings(int32_t n, const int64_t* row_ptr, const int32_t* col_idx
         free(ev);
         return ORC_ENOMEM;
     }
+    /* every index is checked before any thread starts, so no thread writes
+     * shared state */
+    for (int64_t k = 0; k < count; ++k)
+        if (sel[k] < 0 || sel[k] >= m) {
+            free(eu);
+            free(ev);
+            return ORC_EINVAL;
+        }
     edge_list(n, row_ptr, col_idx, eu, ev);
-    int rc = ORC_OK;
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t k = 0; k < count; ++k) {
         const int64_t i = sel[k];
-        if (i < 0 || i >= m) {
-            rc = ORC_EINVAL;
-            continue;
-        }
         int64_t c = 0;
         for (int64_t j = 0; j < m; ++j)
             if (j != i) c += edges_cross(pos, eu[i], ev[i], eu[j], ev[j]);
@@ -763,7 +801,7 @@ int orc_edge_crossings(int32_t n, const int64_t* row_ptr, const int32_t* col_idx
     }
     free(eu);
     free(ev);
-    return rc;
+    return ORC_OK;
 }
 
 /* Mean and standard deviation (population, two passes) of the edge lengths. */
