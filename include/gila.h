@@ -53,7 +53,10 @@ enum {
     GILA_EDEVICE = -3,      /* a HIP call failed (fault, launch error) */
     GILA_EAGAIN = -4,       /* result not ready yet (gila_poll) */
     GILA_ECANCELED = -5,    /* job was cancelled */
-    GILA_EUNSUPPORTED = -6  /* valid request the library does not support */
+    GILA_EUNSUPPORTED = -6, /* valid request the library does not support */
+    GILA_ENONFINITE = -7    /* a force was not finite in the chosen precision (points too
+                               close for the force exponents): those vertices did not move
+                               and the run stopped after that iteration */
 };
 
 enum {
@@ -165,7 +168,21 @@ typedef struct gila_stats {
     double max_disp;            /* last iteration: max_v |Delta_v| */
     double energy;              /* last iteration: sum_v |F_v|^2 */
     int64_t coincident;         /* last iteration: ordered pairs at distance 0 (no force) */
+    int64_t nonfinite;          /* last iteration: vertices whose force was not finite
+                                   (they did not move; the call returns GILA_ENONFINITE) */
 } gila_stats;
+
+/* Cap schedules (Section 5.1), written to temperature_host[0 .. iterations):
+ *   paper:  t_h = sqrt((n / a) d) 0.93^h, h from 0 -- the paper's cap with n
+ *           the vertex count and a the height / width ratio of the initial
+ *           drawing's bounding box (both > 0; EINVAL otherwise);
+ *   linear: t_h = t0 - t0 h / iterations (t0 >= 0), from t0 down to
+ *           t0 / iterations.
+ * Host only (no device work).  iterations >= 0; temperature_host may be NULL
+ * only when iterations is 0. */
+int gila_paper_schedule(double n, double aspect, double ideal_length, int32_t iterations,
+                        double* temperature_host);
+int gila_linear_schedule(double t0, int32_t iterations, double* temperature_host);
 
 /* Seeded uniform placement in [0, width) x [0, height) (Section 5.1 places the
  * vertices at random in a 1200 x 1200 frame).  Coordinate c in {0: x, 1: y}
@@ -176,17 +193,26 @@ int gila_init_positions(int32_t n, uint64_t seed, double width, double height,
                         int32_t precision, void* pos_dev, void* stream);
 
 /* One iteration h (cap params->temperature[h]) on pos_dev (caller ids,
- * in/out).  If force_dev / disp_dev are not NULL they receive F_v and Delta_v
- * (double[2n], caller ids).  `out` (may be NULL) receives the iteration's
- * statistics; the call synchronises when out != NULL.  The halting rule is
- * not applied by a single step. */
+ * in/out): every F_v from the current positions (Section 3.1 force equation,
+ * repulsion over N_v(k) and attraction over the edges as in the second
+ * superstep of Section 4.5), then every vertex moved at once by the capped
+ * displacement (Section 3.1 cap; the synchronous coordinate update at the end
+ * of a Section 4.5 iteration).  If force_dev / disp_dev are not NULL they
+ * receive F_v and Delta_v (double[2n], caller ids).  `out` (may be NULL)
+ * receives the iteration's statistics; the call synchronises when
+ * out != NULL.  The halting rule is not applied by a single step.
+ * GILA_ENONFINITE: some F_v was not finite; those vertices did not move. */
 int gila_step(const gila_khop* kh, const gila_params* params, int32_t h, void* pos_dev,
               double* force_dev, double* disp_dev, void* stream, gila_stats* out);
 
 /* Iterations h = start_h .. end_h-1 (end_h <= params->iterations) on a built
- * handle, positions in/out at pos_dev (caller ids).  The loop runs on the
- * device (captured as a HIP graph), the halting rule included; a run split at
- * any h gives the same bits as one run.  Synchronises `stream`. */
+ * handle, positions in/out at pos_dev (caller ids): the iteration of gila_step
+ * repeated with the caps of the schedule (Section 5.1) and, when
+ * params->stop_fraction > 0, the halting rule of Section 5.1 evaluated after
+ * every iteration.  The loop runs on the device (captured as a HIP graph); a
+ * run split at any h gives the same bits as one run.  GILA_ENONFINITE: the
+ * run stopped after an iteration with a non-finite force (`out` describes
+ * it).  Synchronises `stream`. */
 int gila_run(const gila_khop* kh, const gila_params* params, int32_t start_h, int32_t end_h,
              void* pos_dev, void* stream, gila_stats* out);
 
@@ -200,8 +226,10 @@ int gila_run(const gila_khop* kh, const gila_params* params, int32_t start_h, in
 int gila_time_iterations(const gila_khop* kh, const gila_params* params, int32_t h,
                          int32_t reps, void* pos_dev, void* stream, double* ms_out);
 
-/* Whole layout of one graph: gila_build_khop, gila_run over all
- * params->iterations, free.  Synchronises `stream`. */
+/* Whole layout of one graph (the layout phase of Section 4.5 on a graph the
+ * caller has already reduced as Sections 4.3 and 4.6 describe, or not):
+ * gila_build_khop, gila_run over all params->iterations, free.
+ * Synchronises `stream`. */
 int gila_layout(const gila_csr* g_dev, int32_t k, const gila_params* params, void* pos_dev,
                 void* stream, gila_stats* out);
 

@@ -317,7 +317,7 @@ template <class P, int LPV>
 __device__ __forceinline__ void batch_graph_iteration(
     const BatchArgs& a, const BatchDesc& G, const typename P::vec2* __restrict__ cur,
     typename P::vec2* __restrict__ nxt, double t, double& energy, double& maxd, int64_t& moved,
-    int& coinc) {
+    int& coinc, int& nonfinite) {
     using R = typename P::real;
     using V = typename P::vec2;
     const double d2 = G.d * G.d;
@@ -389,33 +389,38 @@ __device__ __forceinline__ void batch_graph_iteration(
         const double fy = group_sum<LPV>(acc.y()) * d2;
         if (v < G.n && gl == 0) {
             // temperature cap and synchronous move (into the other buffer)
-            energy += fx * fx + fy * fy;
-            V nx;
-            if constexpr (sizeof(R) == 4) {
+            V nx = xv;
+            if (!(fabs(fx) <= DBL_MAX) || !(fabs(fy) <= DBL_MAX)) {
+                ++nonfinite;  // a term overflowed: the vertex stays, the graph stops
+            } else if constexpr (sizeof(R) == 4) {
+                energy += fx * fx + fy * fy;
                 // FP32 positions: the move in FP32 (one lane per vertex does
                 // this part, so its instruction count matters); |Delta| = the
                 // capped length
                 const float fxf = (float)fx, fyf = (float)fy;
                 const float norm = sqrtf(fmaf(fxf, fxf, fyf * fyf));
                 float l = 0.f, dx = 0.f, dy = 0.f;
-                if (norm > 0.f) {
+                if (norm > 0.f && norm <= FLT_MAX) {
                     l = fminf(norm, (float)t);
                     const float sc = l * fast_rcp(norm);
                     dx = fxf * sc;
                     dy = fyf * sc;
+                } else if (fx != 0.0 || fy != 0.0) {
+                    // the square left float's range: the scaled double cap
+                    double ddx, ddy;
+                    capped_move(fx, fy, t, ddx, ddy);
+                    dx = (float)ddx;
+                    dy = (float)ddy;
+                    l = (float)sqrt(ddx * ddx + ddy * ddy);
                 }
                 nx.x = xv.x + dx;
                 nx.y = xv.y + dy;
                 maxd = (double)l > maxd ? (double)l : maxd;
                 moved += (double)l > G.stop_displacement ? 1 : 0;
             } else {
-                const double norm = sqrt(fx * fx + fy * fy);
-                double dx = 0.0, dy = 0.0;
-                if (norm > 0.0) {
-                    const double l = norm < t ? norm : t;
-                    dx = fx * (l / norm);
-                    dy = fy * (l / norm);
-                }
+                energy += fx * fx + fy * fy;
+                double dx, dy;
+                capped_move(fx, fy, t, dx, dy);
                 nx.x = (R)((double)xv.x + dx);
                 nx.y = (R)((double)xv.y + dy);
                 const double dl = sqrt(dx * dx + dy * dy);
@@ -437,6 +442,7 @@ __global__ __launch_bounds__(kBatchBlock) void batch_layout_kernel(BatchArgs a) 
     // rewritten two iterations later, after a barrier every reader has passed)
     __shared__ double s_e[2][kBatchWaves], s_m[2][kBatchWaves];
     __shared__ int64_t s_mv[2][kBatchWaves], s_c[2][kBatchWaves];
+    __shared__ int32_t s_nf[2][kBatchWaves];
     const int lane = lane64(), w = wave_id();
     for (;;) {
         if (threadIdx.x == 0) s_g = atomicAdd(a.work, 1);
@@ -460,21 +466,21 @@ __global__ __launch_bounds__(kBatchBlock) void batch_layout_kernel(BatchArgs a) 
         }
         __syncthreads();
         double E = 0.0, M = 0.0;
-        int64_t MV = 0, C = 0;
+        int64_t MV = 0, C = 0, NF = 0;
         int run = 0, stopped = 0;
         for (int h = 0; h < G.iters; ++h) {
             const double t = a.temps[G.t_off + h];
             double energy = 0.0, maxd = 0.0;
             int64_t moved = 0;
-            int coinc = 0;
+            int coinc = 0, nonfinite = 0;
             switch (G.lpv) {
-                case 1: batch_graph_iteration<P, 1>(a, G, cur, nxt, t, energy, maxd, moved, coinc); break;
-                case 2: batch_graph_iteration<P, 2>(a, G, cur, nxt, t, energy, maxd, moved, coinc); break;
-                case 4: batch_graph_iteration<P, 4>(a, G, cur, nxt, t, energy, maxd, moved, coinc); break;
-                case 8: batch_graph_iteration<P, 8>(a, G, cur, nxt, t, energy, maxd, moved, coinc); break;
-                case 16: batch_graph_iteration<P, 16>(a, G, cur, nxt, t, energy, maxd, moved, coinc); break;
-                case 32: batch_graph_iteration<P, 32>(a, G, cur, nxt, t, energy, maxd, moved, coinc); break;
-                default: batch_graph_iteration<P, 64>(a, G, cur, nxt, t, energy, maxd, moved, coinc); break;
+                case 1: batch_graph_iteration<P, 1>(a, G, cur, nxt, t, energy, maxd, moved, coinc, nonfinite); break;
+                case 2: batch_graph_iteration<P, 2>(a, G, cur, nxt, t, energy, maxd, moved, coinc, nonfinite); break;
+                case 4: batch_graph_iteration<P, 4>(a, G, cur, nxt, t, energy, maxd, moved, coinc, nonfinite); break;
+                case 8: batch_graph_iteration<P, 8>(a, G, cur, nxt, t, energy, maxd, moved, coinc, nonfinite); break;
+                case 16: batch_graph_iteration<P, 16>(a, G, cur, nxt, t, energy, maxd, moved, coinc, nonfinite); break;
+                case 32: batch_graph_iteration<P, 32>(a, G, cur, nxt, t, energy, maxd, moved, coinc, nonfinite); break;
+                default: batch_graph_iteration<P, 64>(a, G, cur, nxt, t, energy, maxd, moved, coinc, nonfinite); break;
             }
             // iteration statistics: per wave, then every thread combines the
             // waves' values in the same fixed order (the same bits everywhere).
@@ -485,29 +491,34 @@ __global__ __launch_bounds__(kBatchBlock) void batch_layout_kernel(BatchArgs a) 
             const double wm = wave_max(maxd);
             const int64_t wmv = wave_sum(moved);
             const int64_t wc = wave_sum((int64_t)coinc);
+            const int32_t wnf = wave_sum(nonfinite);
             if (lane == 0) {
                 s_e[par][w] = we;
                 s_m[par][w] = wm;
                 s_mv[par][w] = wmv;
                 s_c[par][w] = wc;
+                s_nf[par][w] = wnf;
             }
             __syncthreads();
             double e = s_e[par][0], m = s_m[par][0];
-            int64_t mv = s_mv[par][0], c = s_c[par][0];
+            int64_t mv = s_mv[par][0], c = s_c[par][0], nf = s_nf[par][0];
             for (int i = 1; i < kBatchWaves; ++i) {
                 e += s_e[par][i];
                 m = s_m[par][i] > m ? s_m[par][i] : m;
                 mv += s_mv[par][i];
                 c += s_c[par][i];
+                nf += s_nf[par][i];
             }
             E = e;
             M = m;
             MV = mv;
             C = c;
+            NF = nf;
             ++run;
             V* tmp = cur;
             cur = nxt;
             nxt = tmp;
+            if (nf > 0) break;  // a non-finite force ends this graph's run
             if (G.stop_fraction > 0.0 && (double)mv < G.stop_fraction * (double)G.n_active) {
                 stopped = 1;
                 break;
@@ -523,6 +534,7 @@ __global__ __launch_bounds__(kBatchBlock) void batch_layout_kernel(BatchArgs a) 
             st.max_disp = M;
             st.energy = E;
             st.coincident = C;
+            st.nonfinite = NF;
             a.stats[gid] = st;
         }
         __syncthreads();
@@ -1090,6 +1102,12 @@ int batch_run(gila_batch* b, const gila_params* params, void* const* pos, hipStr
                             hipMemcpyDeviceToHost, s));
     GILA_HIP(hipStreamSynchronize(s));
     if (out) std::memcpy(out, st.data(), sizeof(gila_stats) * count);
+    for (int32_t i = 0; i < count; ++i)
+        if (st[i].nonfinite > 0)
+            return fail(GILA_ENONFINITE,
+                        "graph %d: %lld vertices had a non-finite force in iteration %d; they "
+                        "did not move and the graph's run stopped",
+                        i, (long long)st[i].nonfinite, st[i].iterations_run - 1);
     return GILA_OK;
 }
 

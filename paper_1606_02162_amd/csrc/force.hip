@@ -77,7 +77,7 @@ __global__ __launch_bounds__(kBlock) void fr_step_kernel(StepArgs a) {
     const int lane = lane64();
     const int w = wave_id();
     double energy = 0.0, maxd = 0.0;
-    int64_t moved = 0;
+    int64_t moved = 0, nonfinite = 0;
     int coinc = 0;
 
     if ((int32_t)blockIdx.x < a.nhub) {
@@ -99,7 +99,7 @@ __global__ __launch_bounds__(kBlock) void fr_step_kernel(StepArgs a) {
                 fx += s_fx[i];
                 fy += s_fy[i];
             }
-            finish_vertex<P>(a, v, xv, fx, fy, energy, maxd, moved);
+            finish_vertex<P>(a, v, xv, fx, fy, energy, maxd, moved, nonfinite);
         }
     } else {
         constexpr int G = 64 / LPV;                 // vertices in flight per wavefront
@@ -117,11 +117,12 @@ __global__ __launch_bounds__(kBlock) void fr_step_kernel(StepArgs a) {
             if (live) vertex_partial<P, LPV, WEIGHTED>(a, v, gl, acc, coinc, xv);
             const double fx = group_sum<LPV>(acc.x());
             const double fy = group_sum<LPV>(acc.y());
-            if (live && gl == 0) finish_vertex<P>(a, v, xv, fx, fy, energy, maxd, moved);
+            if (live && gl == 0)
+                finish_vertex<P>(a, v, xv, fx, fy, energy, maxd, moved, nonfinite);
         }
     }
 
-    end_iteration(a, energy, maxd, moved, (int64_t)coinc);
+    end_iteration(a, energy, maxd, moved, (int64_t)coinc, nonfinite);
 }
 
 // ------------------------------------------------------------------ launch

@@ -106,6 +106,7 @@ struct Ctl {
     double energy;
     int64_t coincident;
     int64_t coinc_pending;  // coincident pairs counted by the segment kernel, not yet published
+    int64_t nonfinite;      // last iteration: vertices with a non-finite force (stopped = 2)
 };
 
 // Per-workgroup partial statistics of one iteration.
@@ -114,6 +115,7 @@ struct Partial {
     double max_disp;
     int64_t moved;
     int64_t coincident;
+    int64_t nonfinite;
 };
 
 // ------------------------------------------------------------------ iteration kernel arguments
@@ -293,6 +295,9 @@ int prepare_precision(gila_khop* kh, int precision, hipStream_t s);
 int run_iterations(gila_khop* kh, const gila_params* p, int32_t start_h, int32_t end_h,
                    void* pos_dev, hipStream_t stream, gila_stats* out, bool use_graph);
 int check_params(const gila_params* p, bool need_temps);
+// GILA_ENONFINITE (with a message) when the control block records a
+// non-finite force, else GILA_OK
+int nonfinite_status(const Ctl& c);
 // exponents (p, q) of the params' force model
 void force_exponents(const gila_params* p, int32_t* att_p, int32_t* rep_q);
 // Enqueues (no synchronisation) iterations [start_h, end_h) on pos_dev: reset

@@ -3,6 +3,8 @@
 // fixed-order statistics reduction that ends every iteration.
 #pragma once
 
+#include <cfloat>
+
 #include "device_util.h"
 #include "gila_internal.h"
 
@@ -291,20 +293,47 @@ __device__ __forceinline__ R attract_param(double d) {
     return sizeof(R) == 4 ? (R)(1.0 / d) : (R)d;
 }
 
+// Temperature-capped displacement (Section 3.1): Delta = F min(|F|, t) / |F|,
+// and 0 for F = 0.  When squaring F would overflow or underflow, |F| and the
+// direction come from F divided by its largest component, so every finite
+// F != 0 moves min(|F|, t) along F.  A non-finite F (a term overflowed in the
+// precision) gives no move and returns false.
+__device__ __forceinline__ bool capped_move(double fx, double fy, double t, double& dx,
+                                            double& dy) {
+    dx = 0.0;
+    dy = 0.0;
+    if (!(fabs(fx) <= DBL_MAX) || !(fabs(fy) <= DBL_MAX)) return false;
+    const double norm = sqrt(fx * fx + fy * fy);
+    if (norm > 0.0 && norm <= DBL_MAX) {
+        const double len = norm < t ? norm : t;
+        dx = fx * (len / norm);
+        dy = fy * (len / norm);
+    } else if (fx != 0.0 || fy != 0.0) {
+        const double s = fmax(fabs(fx), fabs(fy));
+        const double ux = fx / s, uy = fy / s;
+        const double nu = sqrt(ux * ux + uy * uy);  // in [1, sqrt(2)]
+        // |F| = s nu; s nu > t when the square overflowed, < t when it underflowed
+        const double len = (s > 1.0 ? t : fmin(s * nu, t));
+        dx = ux * (len / nu);
+        dy = uy * (len / nu);
+    }
+    return true;
+}
+
 // Cap, move and record one vertex (Section 3.1 temperature cap; the move is
-// written to the other buffer, so all vertices move together).
+// written to the other buffer, so all vertices move together).  A vertex
+// whose force is not finite stays put and is counted in `nonfinite`.
 template <class P>
 __device__ __forceinline__ void finish_vertex(const StepArgs& a, int32_t v, typename P::vec2 xv,
                                               double fx, double fy, double& energy, double& maxd,
-                                              int64_t& moved) {
+                                              int64_t& moved, int64_t& nonfinite) {
     using V = typename P::vec2;
     using R = typename P::real;
-    const double norm = sqrt(fx * fx + fy * fy);
-    double dx = 0.0, dy = 0.0;
-    if (norm > 0.0) {
-        const double len = norm < a.t ? norm : a.t;
-        dx = fx * (len / norm);
-        dy = fy * (len / norm);
+    double dx, dy;
+    if (!capped_move(fx, fy, a.t, dx, dy)) {
+        ++nonfinite;
+        fx = 0.0;  // keeps the energy statistic finite
+        fy = 0.0;
     }
     V nx;
     nx.x = (R)((double)xv.x + dx);
@@ -330,20 +359,22 @@ __device__ __forceinline__ void finish_vertex(const StepArgs& a, int32_t v, type
 // device-wide cache writeback per workgroup).  Every thread of the workgroup
 // must call it.
 __device__ __forceinline__ void end_iteration(const StepArgs& a, double energy, double maxd,
-                                              int64_t moved, int64_t coinc) {
+                                              int64_t moved, int64_t coinc, int64_t nonfinite) {
     __shared__ double s_e[kWaves], s_m[kWaves];
-    __shared__ int64_t s_mv[kWaves], s_c[kWaves];
+    __shared__ int64_t s_mv[kWaves], s_c[kWaves], s_nf[kWaves];
     const int lane = lane64();
     const int w = wave_id();
     const double we = wave_sum(energy);
     const double wm = wave_max(maxd);
     const int64_t wmv = wave_sum(moved);
     const int64_t wc = wave_sum(coinc);
+    const int64_t wnf = wave_sum(nonfinite);
     if (lane == 0) {
         s_e[w] = we;
         s_m[w] = wm;
         s_mv[w] = wmv;
         s_c[w] = wc;
+        s_nf[w] = wnf;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -352,11 +383,13 @@ __device__ __forceinline__ void end_iteration(const StepArgs& a, double energy, 
         p.max_disp = s_m[0];
         p.moved = s_mv[0];
         p.coincident = s_c[0];
+        p.nonfinite = s_nf[0];
         for (int i = 1; i < kWaves; ++i) {
             p.energy += s_e[i];
             p.max_disp = s_m[i] > p.max_disp ? s_m[i] : p.max_disp;
             p.moved += s_mv[i];
             p.coincident += s_c[i];
+            p.nonfinite += s_nf[i];
         }
         a.partials[blockIdx.x] = p;
     }

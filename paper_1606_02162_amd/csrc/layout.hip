@@ -15,29 +15,32 @@ namespace gila {
 // iteration's statistics (Section 5.1 halting rule included).
 __global__ __launch_bounds__(kBlock) void iteration_stats_kernel(StepArgs a) {
     __shared__ double s_e[kWaves], s_m[kWaves];
-    __shared__ int64_t s_mv[kWaves], s_c[kWaves];
+    __shared__ int64_t s_mv[kWaves], s_c[kWaves], s_nf[kWaves];
     Ctl* ctl = a.ctl;
     if (ctl->stopped) return;
     const int lane = lane64();
     const int w = wave_id();
     double e = 0.0, m = 0.0;
-    int64_t mv = 0, c = 0;
+    int64_t mv = 0, c = 0, nf = 0;
     for (int i = threadIdx.x; i < a.nblocks; i += kBlock) {
         const Partial p = a.partials[i];
         e += p.energy;
         m = p.max_disp > m ? p.max_disp : m;
         mv += p.moved;
         c += p.coincident;
+        nf += p.nonfinite;
     }
     e = wave_sum(e);
     m = wave_max(m);
     mv = wave_sum(mv);
     c = wave_sum(c);
+    nf = wave_sum(nf);
     if (lane == 0) {
         s_e[w] = e;
         s_m[w] = m;
         s_mv[w] = mv;
         s_c[w] = c;
+        s_nf[w] = nf;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -45,11 +48,13 @@ __global__ __launch_bounds__(kBlock) void iteration_stats_kernel(StepArgs a) {
         m = s_m[0];
         mv = s_mv[0];
         c = s_c[0];
+        nf = s_nf[0];
         for (int i = 1; i < kWaves; ++i) {
             e += s_e[i];
             m = s_m[i] > m ? s_m[i] : m;
             mv += s_mv[i];
             c += s_c[i];
+            nf += s_nf[i];
         }
         c += ctl->coinc_pending;
         ctl->coinc_pending = 0;
@@ -57,8 +62,11 @@ __global__ __launch_bounds__(kBlock) void iteration_stats_kernel(StepArgs a) {
         ctl->max_disp = m;
         ctl->moved = mv;
         ctl->coincident = c;
+        ctl->nonfinite = nf;
         ctl->iters_run += 1;
         if (a.check_stop && (double)mv < a.stop_fraction * (double)a.n_active) ctl->stopped = 1;
+        // a non-finite force ends the run (2: stopped by the error, not the rule)
+        if (nf > 0) ctl->stopped = 2;
         if (a.hist_slot >= 0) {
             double* hrow = a.hist + 4 * (int64_t)a.hist_slot;
             hrow[0] = e;
@@ -109,6 +117,7 @@ __global__ void reset_ctl_kernel(Ctl* ctl) {
     ctl->energy = 0.0;
     ctl->coincident = 0;
     ctl->coinc_pending = 0;
+    ctl->nonfinite = 0;
 }
 
 // Caller positions -> internal buffer 0; isolated vertices (the tail of the
@@ -235,11 +244,22 @@ static StepArgs base_args(const gila_khop* kh, const gila_params* p) {
 
 static void to_stats(const Ctl& c, gila_stats* out) {
     out->iterations_run = c.iters_run;
-    out->stopped = c.stopped;
+    out->stopped = c.stopped == 1 ? 1 : 0;
     out->moved = c.moved;
     out->max_disp = c.max_disp;
     out->energy = c.energy;
     out->coincident = c.coincident;
+    out->nonfinite = c.nonfinite;
+}
+
+int nonfinite_status(const Ctl& c) {
+    if (c.nonfinite > 0)
+        return fail(GILA_ENONFINITE,
+                    "%lld vertices had a non-finite force in iteration %d (points too close "
+                    "for the force exponents in this precision); they did not move and the "
+                    "run stopped",
+                    (long long)c.nonfinite, c.iters_run - 1);
+    return GILA_OK;
 }
 
 // Enqueue: reset, permute in, iterations, permute out.
@@ -282,16 +302,25 @@ int launch_iteration(const gila_khop* kh, int precision, const StepArgs& a, hipS
     return launch_step(kh, precision, a, s);
 }
 
-static std::vector<uint64_t> graph_key(const gila_params* p, int32_t start_h, int32_t end_h,
-                                       void* pos_dev) {
+// Everything the captured loop depends on besides the handle's own buffers
+// (a change of weights or of the segment layout destroys the cached graph
+// where it happens): the positions' address, the iteration range and
+// schedule, the parameters, the force law (the kernel instantiation and its
+// exponent arguments) and the kernel path.
+static std::vector<uint64_t> graph_key(const gila_khop* kh, const gila_params* p,
+                                       int32_t start_h, int32_t end_h, void* pos_dev) {
     auto bits = [](double x) {
         uint64_t u;
         std::memcpy(&u, &x, 8);
         return u;
     };
+    int32_t att_p = 0, rep_q = 0;
+    force_exponents(p, &att_p, &rep_q);
     std::vector<uint64_t> key = {(uint64_t)(uintptr_t)pos_dev, (uint64_t)start_h, (uint64_t)end_h,
                                  (uint64_t)p->precision, bits(p->ideal_length),
-                                 bits(p->stop_fraction), bits(p->stop_displacement)};
+                                 bits(p->stop_fraction), bits(p->stop_displacement),
+                                 (uint64_t)(uint32_t)att_p, (uint64_t)(uint32_t)rep_q,
+                                 (uint64_t)segment_ready_for(kh, p->precision)};
     for (int32_t h = start_h; h < end_h; ++h) key.push_back(bits(p->temperature[h]));
     return key;
 }
@@ -304,7 +333,7 @@ int run_iterations(gila_khop* kh, const gila_params* p, int32_t start_h, int32_t
                     p->iterations);
     GILA_TRY(prepare_precision(kh, p->precision, stream));
     if (use_graph && end_h > start_h) {
-        std::vector<uint64_t> key = graph_key(p, start_h, end_h, pos_dev);
+        std::vector<uint64_t> key = graph_key(kh, p, start_h, end_h, pos_dev);
         if (!kh->gexec || key != kh->gkey) {
             if (kh->gexec) {
                 (void)hipGraphExecDestroy(kh->gexec);
@@ -339,7 +368,7 @@ int run_iterations(gila_khop* kh, const gila_params* p, int32_t start_h, int32_t
     GILA_HIP(hipStreamSynchronize(stream));
     if (kh->nblocks == 0) c.iters_run = end_h - start_h;  // nothing can move
     if (out) to_stats(c, out);
-    return GILA_OK;
+    return nonfinite_status(c);
 }
 
 }  // namespace gila
@@ -347,6 +376,30 @@ int run_iterations(gila_khop* kh, const gila_params* p, int32_t start_h, int32_t
 using namespace gila;
 
 extern "C" {
+
+int gila_paper_schedule(double n, double aspect, double ideal_length, int32_t iterations,
+                        double* temperature_host) {
+    clear_error();
+    if (iterations < 0) return fail(GILA_EINVAL, "iterations must be >= 0");
+    if (iterations > 0 && !temperature_host) return fail(GILA_EINVAL, "temperature_host is NULL");
+    if (!(n > 0.0) || !(aspect > 0.0) || !(ideal_length > 0.0) || !std::isfinite(n) ||
+        !std::isfinite(aspect) || !std::isfinite(ideal_length))
+        return fail(GILA_EINVAL, "n, aspect and ideal_length must be finite and > 0");
+    // Section 5.1: sqrt((n / a) d) 0.93^h, h counted from 0
+    const double base = std::sqrt(n / aspect * ideal_length);
+    for (int32_t h = 0; h < iterations; ++h) temperature_host[h] = base * std::pow(0.93, (double)h);
+    return GILA_OK;
+}
+
+int gila_linear_schedule(double t0, int32_t iterations, double* temperature_host) {
+    clear_error();
+    if (iterations < 0) return fail(GILA_EINVAL, "iterations must be >= 0");
+    if (iterations > 0 && !temperature_host) return fail(GILA_EINVAL, "temperature_host is NULL");
+    if (!(t0 >= 0.0) || !std::isfinite(t0)) return fail(GILA_EINVAL, "t0 must be finite and >= 0");
+    for (int32_t h = 0; h < iterations; ++h)
+        temperature_host[h] = t0 - (t0 * (double)h) / (double)iterations;
+    return GILA_OK;
+}
 
 int gila_init_positions(int32_t n, uint64_t seed, double width, double height, int32_t precision,
                         void* pos_dev, void* stream) {
@@ -412,6 +465,7 @@ int gila_step(const gila_khop* kh_c, const gila_params* params, int32_t h, void*
         GILA_HIP(hipStreamSynchronize(s));
         if (kh->nblocks == 0) c.iters_run = 1;
         to_stats(c, out);
+        return nonfinite_status(c);
     }
     return GILA_OK;
 }

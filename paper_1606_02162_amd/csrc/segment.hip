@@ -531,7 +531,7 @@ __global__ __launch_bounds__(kBlock) void seg_combine_kernel(StepArgs a) {
     using V = typename P::vec2;
     if (a.ctl->stopped) return;
     double energy = 0.0, maxd = 0.0;
-    int64_t moved = 0;
+    int64_t moved = 0, nonfinite = 0;
     const int32_t v = blockIdx.x * kBlock + threadIdx.x;
     if (v < a.n_active) {
         // partials added one after another in segment order; loads are
@@ -557,9 +557,9 @@ __global__ __launch_bounds__(kBlock) void seg_combine_kernel(StepArgs a) {
             fy += p.y;
         }
         const V xv = reinterpret_cast<const V*>(a.pos_cur)[v];
-        finish_vertex<P>(a, v, xv, fx, fy, energy, maxd, moved);
+        finish_vertex<P>(a, v, xv, fx, fy, energy, maxd, moved, nonfinite);
     }
-    end_iteration(a, energy, maxd, moved, 0);
+    end_iteration(a, energy, maxd, moved, 0, nonfinite);
 }
 
 // ------------------------------------------------------------------ host: plan and build

@@ -474,16 +474,18 @@ static void ticker(gila_server* s) {
                     finished = true;
                 } else {
                     j->stats.iterations_run += j->h_target > j->h ? c.iters_run : 0;
-                    j->stats.stopped = c.stopped;
+                    j->stats.stopped = c.stopped == 1 ? 1 : 0;
                     if (j->h_target > j->h) {
                         j->stats.moved = c.moved;
                         j->stats.max_disp = c.max_disp;
                         j->stats.energy = c.energy;
                         j->stats.coincident = c.coincident;
+                        j->stats.nonfinite = c.nonfinite;
                     }
                     j->h = j->h_target;
                     finished = c.stopped || j->h >= j->params.iterations;
-                    if (finished) rc = download_positions(j, s->compute[j->lane]);
+                    if (finished) rc = nonfinite_status(c);
+                    if (finished && rc == GILA_OK) rc = download_positions(j, s->compute[j->lane]);
                 }
             }
             if (!finished) {

@@ -319,6 +319,7 @@ const char* gila_strerror(int status) {
         case GILA_EAGAIN: return "not ready";
         case GILA_ECANCELED: return "cancelled";
         case GILA_EUNSUPPORTED: return "unsupported";
+        case GILA_ENONFINITE: return "non-finite force";
         default: return "unknown status";
     }
 }

@@ -9,7 +9,6 @@ built -- there is no fallback path.
 from __future__ import annotations
 
 import ctypes
-import math
 import os
 from dataclasses import dataclass, field
 
@@ -25,6 +24,7 @@ GILA_EDEVICE = -3
 GILA_EAGAIN = -4
 GILA_ECANCELED = -5
 GILA_EUNSUPPORTED = -6
+GILA_ENONFINITE = -7
 
 FP64 = 0
 FP32 = 1
@@ -98,7 +98,8 @@ class Metrics(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("iterations_run", ctypes.c_int32), ("stopped", ctypes.c_int32),
                 ("moved", ctypes.c_int64), ("max_disp", ctypes.c_double),
-                ("energy", ctypes.c_double), ("coincident", ctypes.c_int64)]
+                ("energy", ctypes.c_double), ("coincident", ctypes.c_int64),
+                ("nonfinite", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -134,6 +135,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "gila_pack_components": (ctypes.c_int, [i32, vp, dbl, i32, vp, vp]),
         "gila_layout_components": (ctypes.c_int, [P(Csr), i32, P(_Params), vp, vp, P(i32), vp]),
         "gila_init_positions": (ctypes.c_int, [i32, u64, dbl, dbl, i32, vp, vp]),
+        "gila_paper_schedule": (ctypes.c_int, [dbl, dbl, dbl, i32, vp]),
+        "gila_linear_schedule": (ctypes.c_int, [dbl, i32, vp]),
         "gila_step": (ctypes.c_int, [vp, P(_Params), i32, vp, vp, vp, vp, P(Stats)]),
         "gila_run": (ctypes.c_int, [vp, P(_Params), i32, i32, vp, vp, P(Stats)]),
         "gila_layout": (ctypes.c_int, [P(Csr), i32, P(_Params), vp, vp, P(Stats)]),
@@ -194,24 +197,32 @@ def _ptr(t) -> int:
 
 
 # ---------------------------------------------------------------- schedules
+# The paper's ideal edge length d = 20 + sqrt(800) (Section 5.1).
+PAPER_IDEAL_LENGTH = 48.2842712474619
 def paper_schedule(n_vertices: float, aspect: float, ideal_length: float,
                    iterations: int) -> np.ndarray:
-    """Cap of Section 5.1: sqrt((n / a) d) 0.93^h, h = 0 .. iterations-1."""
-    base = math.sqrt(n_vertices / aspect * ideal_length)
-    return base * np.power(0.93, np.arange(iterations, dtype=np.float64))
+    """Cap of Section 5.1 (``gila_paper_schedule``): sqrt((n / a) d) 0.93^h,
+    h = 0 .. iterations-1."""
+    t = np.zeros(max(int(iterations), 1), dtype=np.float64)
+    _check(_lib.gila_paper_schedule(float(n_vertices), float(aspect), float(ideal_length),
+                                    int(iterations), t.ctypes.data), "gila_paper_schedule")
+    return t[: int(iterations)]
 
 
 def linear_schedule(t0: float, iterations: int) -> np.ndarray:
-    """t0 - t0 h / iterations, h = 0 .. iterations-1 (t0 down to t0/iterations)."""
-    h = np.arange(iterations, dtype=np.float64)
-    return t0 - (t0 * h) / iterations
+    """``gila_linear_schedule``: t0 - t0 h / iterations, h = 0 .. iterations-1
+    (t0 down to t0 / iterations)."""
+    t = np.zeros(max(int(iterations), 1), dtype=np.float64)
+    _check(_lib.gila_linear_schedule(float(t0), int(iterations), t.ctypes.data),
+           "gila_linear_schedule")
+    return t[: int(iterations)]
 
 
 # ---------------------------------------------------------------- params
 @dataclass
 class LayoutParams:
     temperature: np.ndarray
-    ideal_length: float = 20.0 + math.sqrt(800.0)
+    ideal_length: float = PAPER_IDEAL_LENGTH
     precision: int = FP32_KAHAN
     stop_fraction: float = 0.0
     stop_displacement: float = 0.01
@@ -620,7 +631,7 @@ class BatchParams:
     list of per-graph schedules; ideal_length, precision and the halting
     settings are shared."""
 
-    def __init__(self, temperatures, ideal_length=20.0 + math.sqrt(800.0),
+    def __init__(self, temperatures, ideal_length=PAPER_IDEAL_LENGTH,
                  precision=FP32_KAHAN, stop_fraction=0.0, stop_displacement=0.01):
         lens = np.array([len(t) for t in temperatures], dtype=np.int64)
         self._t = np.ascontiguousarray(np.concatenate(temperatures) if len(temperatures) else

@@ -142,3 +142,21 @@ def test_schedules_match_closed_forms():
     p = gila.paper_schedule(1000, 1.0, d, 10)
     assert abs(p[0] ** 2 - 1000 * d) < 1e-9
     assert np.allclose(p[1:] / p[:-1], 0.93, rtol=1e-14, atol=0)
+
+
+def test_schedule_argument_checks_and_new_status():
+    import numpy as np
+    from paper_1606_02162_amd import gila
+    L = gila.lib()
+    L.gila_strerror.restype = ctypes.c_char_p
+    t = np.zeros(4)
+    assert L.gila_paper_schedule(0.0, 1.0, 10.0, 4, t.ctypes.data) == gila.GILA_EINVAL
+    assert L.gila_paper_schedule(10.0, -1.0, 10.0, 4, t.ctypes.data) == gila.GILA_EINVAL
+    assert L.gila_paper_schedule(10.0, 1.0, 10.0, 4, None) == gila.GILA_EINVAL
+    assert L.gila_paper_schedule(10.0, 1.0, 10.0, 0, None) == gila.GILA_OK
+    assert L.gila_linear_schedule(-1.0, 4, t.ctypes.data) == gila.GILA_EINVAL
+    assert L.gila_linear_schedule(5.0, -1, t.ctypes.data) == gila.GILA_EINVAL
+    # a non-square frame: n / a with a = height / width (Section 5.1)
+    p = gila.paper_schedule(500, 2.0, 8.0, 3)
+    assert abs(p[0] ** 2 - 500 / 2.0 * 8.0) < 1e-9 and abs(p[2] / p[0] - 0.93 ** 2) < 1e-15
+    assert L.gila_strerror(gila.GILA_ENONFINITE) == b"non-finite force"

@@ -169,3 +169,69 @@ def test_batch_and_server_refuse_other_models(G):
         with pytest.raises(G.GilaError) as e:
             srv.submit(g, 2, params, inputs.uniform_positions(g.n, 1, 100.0))
         assert e.value.code == G.GILA_EUNSUPPORTED
+
+
+def test_cached_run_follows_a_change_of_force_model(G):
+    """gila_run keeps its captured loop between calls; switching the force law
+    on the same handle and position buffer must not replay the previous
+    law's kernels (each run equals the same steps taken one by one)."""
+    import torch
+    g = inputs.barabasi_albert(1500, 2, seed=8)
+    rp, ci = G.to_device_csr(g)
+    kh = G.build_khop(rp, ci, 2)
+    temps = G.paper_schedule(g.n, 1.0, 30.0, 6)
+    x0 = torch.from_numpy(inputs.uniform_positions(g.n, 4, 700.0)).float().cuda()
+    pos = torch.empty_like(x0)
+    for model, fp, fq in ((G.MODEL_FR, 2, 1), (G.MODEL_LINLOG, 0, 1), (G.MODEL_PQ, 4, 5),
+                          (G.MODEL_FR, 2, 1), (G.MODEL_PQ, 2, 2)):
+        params = _params(G, G.FP32_KAHAN, model, fp, fq, temps=temps)
+        pos.copy_(x0)
+        G.run(kh, params, pos)          # the same tensor every time
+        ref = x0.clone()
+        for h in range(len(temps)):
+            G.step(kh, params, h, ref)
+        assert torch.equal(pos, ref), (model, fp, fq)
+
+
+def test_nonfinite_force_is_an_error(G):
+    """Two vertices so close that d^2 / delta^(q+1) overflows FP32 (q = 8):
+    the call reports GILA_ENONFINITE, neither vertex moves, nothing becomes
+    NaN, and the run stops after that iteration."""
+    import torch
+    g = inputs.to_csr(3, [0, 1], [1, 2])
+    rp, ci = G.to_device_csr(g)
+    kh = G.build_khop(rp, ci, 2)
+    x0 = np.array([[0.0, 0.0], [1e-6, 0.0], [40.0, 3.0]])
+    params = _params(G, G.FP32, G.MODEL_PQ, 2, 8, temps=(5.0, 4.0, 3.0), d=30.0)
+    pos = torch.from_numpy(x0).float().cuda()
+    with pytest.raises(G.GilaError) as e:
+        G.run(kh, params, pos)
+    assert e.value.code == G.GILA_ENONFINITE
+    got = pos.double().cpu().numpy()
+    assert np.isfinite(got).all()
+    assert np.array_equal(got[:2], x0[:2].astype(np.float32).astype(np.float64))
+    st = G.Stats()
+    F = torch.zeros((3, 2), dtype=torch.float64, device="cuda")
+    D = torch.zeros((3, 2), dtype=torch.float64, device="cuda")
+    pos = torch.from_numpy(x0).float().cuda()
+    with pytest.raises(G.GilaError) as e:
+        G.step(kh, params, 0, pos, F, D)
+    assert e.value.code == G.GILA_ENONFINITE
+    assert np.isfinite(D.cpu().numpy()).all() and (D.cpu().numpy()[:2] == 0).all()
+
+
+def test_huge_finite_force_moves_by_the_cap(G):
+    """FP64, q = 8, two vertices 1e-20 apart: |F| ~ d^2 / delta^8 = 1e160 is
+    finite but its square overflows; each end still moves by the cap t, away
+    from the other (Section 3.1 cap), with no error."""
+    import torch
+    g = inputs.path_graph(2)
+    rp, ci = G.to_device_csr(g)
+    kh = G.build_khop(rp, ci, 1)
+    x0 = np.array([[0.0, 0.0], [1e-20, 0.0]])
+    params = _params(G, G.FP64, G.MODEL_PQ, 2, 8, temps=(5.0,), d=1.0)
+    pos = torch.from_numpy(x0).cuda()
+    st = G.run(kh, params, pos)
+    got = pos.cpu().numpy()
+    assert st.nonfinite == 0
+    np.testing.assert_allclose(got, [[-5.0, 0.0], [5.0, 0.0]], rtol=1e-15, atol=0)
