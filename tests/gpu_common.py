@@ -27,6 +27,21 @@ def rel_l2(a, b):
     return na / nb
 
 
+def per_vertex_force_err(F, F_ref, S):
+    """max_v |F_v - F_ref_v| / S_v over vertices with S_v > 0, where S_v is the
+    sum of the magnitudes of the terms of F_v (oracle.force_magnitudes): a
+    vertex whose force nearly cancels is held to the scale of its terms,
+    which a global norm of the field could hide (0 if no vertex has terms)."""
+    F = np.asarray(F, dtype=np.float64)
+    F_ref = np.asarray(F_ref, dtype=np.float64)
+    S = np.asarray(S, dtype=np.float64)
+    live = S > 0
+    if not live.any():
+        return 0.0
+    diff = np.hypot(F[live, 0] - F_ref[live, 0], F[live, 1] - F_ref[live, 1])
+    return float((diff / S[live]).max())
+
+
 def pos_err(x, ref):
     """max_v |x_v - ref_v| / extent(ref): the position gate."""
     ref = np.asarray(ref, dtype=np.float64)

@@ -141,12 +141,47 @@ def test_layout_components_linlog_fp64(G):
 
 
 def test_layout_components_fp32(G):
+    """Three iterations in one call (a short trajectory: rounding differences
+    grow along it, hence the looser bound; the per-step test below holds the
+    1e-5 gate)."""
     g = _many(5)
     got, ref, C, most, _, _ = _pipeline(G, g, 2, 3, G.FP32_KAHAN, 0.0)
     assert np.isfinite(got).all()
     e = pos_err(got, ref)
     print(f"components fp32 e_x={e:.2e}")
     assert e <= 1e-4
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp32_kahan"])
+def test_layout_components_fp32_per_step(G, precision):
+    """Per-step parity of the per-component pipeline in FP32 (Sections 4.6,
+    5.1): one-iteration calls (each component's own cap from its bounding box,
+    the layout step, the packing) from identical FP32 positions, compared with
+    the oracle's pipeline at the 1e-5 position gate.  Each next call starts
+    from the GPU's output, so the steps follow the GPU's own trajectory; small
+    components go through the batched launch, the 3000-vertex one through the
+    whole-GPU path."""
+    import torch
+    prec = G.PRECISIONS[precision]
+    g = _many(5)
+    rp, ci = G.to_device_csr(g)
+    d = 20.0
+    x = inputs.uniform_positions(g.n, seed=6, width=800.0, height=600.0)
+    x = x.astype(np.float32).astype(np.float64)
+    params = G.LayoutParams(temperature=np.zeros(1), ideal_length=d, precision=prec)
+    worst = 0.0
+    for step in range(4):
+        pos = torch.from_numpy(x).to(dtype=torch.float32, device="cuda").contiguous()
+        C, its = G.layout_components(rp, ci, 2, params, pos)
+        got = pos.double().cpu().numpy()
+        ref, label, runs = oracle.layout_components(g.n, g.row_ptr, g.col_idx, 2, d, 1, x)
+        assert np.array_equal(its, np.array([runs.get(int(lab), 0) for lab in label]))
+        e = pos_err(got, ref)
+        worst = max(worst, e)
+        print(f"components {precision} step {step}: e_x={e:.2e}", flush=True)
+        assert e <= 1e-5, (step, e)
+        x = got
+    print(f"components {precision} per-step worst e_x={worst:.2e}")
 
 
 def test_layout_components_halting_fp64(G):

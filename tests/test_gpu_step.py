@@ -14,7 +14,8 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_common import oracle_rows, pos_err, rel_l2, require_gpu, small_graph_suite
+from gpu_common import (oracle_rows, per_vertex_force_err, pos_err, rel_l2, require_gpu,
+                        small_graph_suite)
 from paper_1606_02162_amd import inputs
 
 pytestmark = pytest.mark.gpu
@@ -82,6 +83,9 @@ def test_single_step_small_suite(G, precision, path_env):
                                               pos0)
             tol = 1e-12 if prec == G.FP64 else 1e-5
             assert rel_l2(F_g, F_o) <= tol, (g.name, k, rel_l2(F_g, F_o))
+            S = oracle.force_magnitudes(g.n, g.row_ptr, g.col_idx, optr, oidx, 48.0, pos0)
+            pv = per_vertex_force_err(F_g, F_o, S)
+            assert pv <= tol, (g.name, k, pv)
             if g.n > 1:
                 assert pos_err(x_g, x_o) <= tol, (g.name, k)
             assert st_g.iterations_run == 1
@@ -161,9 +165,12 @@ def test_full_size_step(G, which, path_env):
     for h in range(3):
         x_g, F_g, D_g, st = _gpu_step(G, kh, params, h, x)
         x_o, F_o, D_o, so = oracle.step(g.n, g.row_ptr, g.col_idx, optr, oidx, d, temps[h], x)
+        S = oracle.force_magnitudes(g.n, g.row_ptr, g.col_idx, optr, oidx, d, x)
         eF, ex, eD = rel_l2(F_g, F_o), pos_err(x_g, x_o), rel_l2(D_g, D_o)
-        print(f"{which} {path_env} h={h} e_F={eF:.2e} e_x={ex:.2e} e_D={eD:.2e}", flush=True)
-        assert eF <= 1e-5 and ex <= 1e-5
+        pv = per_vertex_force_err(F_g, F_o, S)
+        print(f"{which} {path_env} h={h} e_F={eF:.2e} e_x={ex:.2e} e_D={eD:.2e} "
+              f"max|dF_v|/S_v={pv:.2e}", flush=True)
+        assert eF <= 1e-5 and ex <= 1e-5 and pv <= 1e-5
         assert st.coincident == so.coincident
         x = x_g
     del oidx
