@@ -304,6 +304,20 @@ int gila_layout_pruned(const gila_csr* g_dev, int32_t k, const gila_params* para
  * The graph is validated as for gila_build_khop.  Synchronises `stream`. */
 int gila_components(const gila_csr* g_dev, int32_t* label_dev, int32_t* count_out, void* stream);
 
+/* gila_components for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same labels (label_dev as gila_components writes it, bit for bit) and
+ * count, with no hipMalloc, hipFree or other allocating call.  The graph is
+ * validated on the device (EINVAL as for gila_build_khop).  Its scratch (CSR
+ * flags, the per-pass hooked flag, per-workgroup root counts) is a fixed
+ * 16 KiB array of device memory inside the library, one copy per device,
+ * held until the process ends; no graph needs more, so no size is refused
+ * for it.  Every call on a device uses that device's copy: calls that
+ * overlap on one device (other threads or streams) race and must be
+ * serialised by the caller.  Synchronises `stream`. */
+int gila_components_noalloc(const gila_csr* g_dev, int32_t* label_dev, int32_t* count_out,
+                            void* stream);
+
 /* Packs the drawings of the components in a matrix (Section 4.6), in place:
  * components in order of decreasing vertex count (ties: smaller label) fill
  * ceil(sqrt(C)) columns row by row; a column is as wide as its widest drawing

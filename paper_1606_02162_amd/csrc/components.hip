@@ -26,6 +26,7 @@
 // bounding box's lower-left corner is its cell's.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "device_util.h"
@@ -683,11 +684,176 @@ static int layout_components(const gila_csr* g, int32_t k, const gila_params* pa
     return GILA_OK;
 }
 
+// ------------------------------------------------------------------ labels without allocation
+// gila_components_noalloc keeps its scratch in a fixed array per device,
+// never in allocated memory.  Layout (64-bit words):
+//   [0] CSR flags (int32 in the low half), [1] hooked-this-pass flag (int32),
+//   [2] number of components, [8, 8 + kNoAllocPartials) per-workgroup root
+//   counts.  The counting grid never exceeds kNoAllocPartials workgroups, so
+//   no graph needs more than these 16 KiB.
+constexpr int kNoAllocHeader = 8;
+constexpr int kNoAllocPartials = 2040;
+constexpr int kNoAllocWords = kNoAllocHeader + kNoAllocPartials;
+static __device__ __align__(256) unsigned long long scratch[kNoAllocWords];
+
+constexpr int kMaxScratchDevices = 64;
+static std::mutex g_scratch_mu;
+static unsigned long long* g_scratch_ptr[kMaxScratchDevices];
+
+// Device address of `scratch` on the current device (each device holds its own
+// copy); looked up once per device.  In host code the array's name is only a
+// stand-in, so kernels and copies must use this address.
+static int scratch_address(unsigned long long** out) {
+    int dev = 0;
+    GILA_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxScratchDevices) return fail(GILA_EUNSUPPORTED, "device %d", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(GILA_EDEVICE, "hipGetSymbolAddress(scratch) failed: %s",
+                        hipGetErrorString(e));
+        g_scratch_ptr[dev] = static_cast<unsigned long long*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return GILA_OK;
+}
+
+// Zeroes words [0, count) (a kernel, not a memset node, so the call can sit in
+// a captured graph).
+__global__ void clear_words_kernel(unsigned long long* w, int count) {
+    for (int i = threadIdx.x; i < count; i += blockDim.x) w[i] = 0ull;
+}
+
+// row_ptr rules (0 first, nnz last, monotone, every offset in [0, nnz]) on the
+// device: flag bit 16.  The CSR checks of validate_csr_kernel read col_idx
+// through row_ptr and may run only once these hold.
+__global__ __launch_bounds__(kBlock) void rowptr_check_kernel(int32_t n, int64_t nnz,
+                                                              const int64_t* __restrict__ rp,
+                                                              int32_t* __restrict__ flag) {
+    int32_t bad = 0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i <= n;
+         i += (int64_t)gridDim.x * kBlock) {
+        const int64_t r = rp[i];
+        if ((i == 0 && r != 0) || (i == n && r != nnz) || r < 0 || r > nnz ||
+            (i > 0 && rp[i - 1] > r))
+            bad = 16;
+    }
+    if (bad) atomicOr(flag, bad);
+}
+
+// Roots (label[v] == v) counted per workgroup into partial[blockIdx.x].
+__global__ __launch_bounds__(kBlock) void count_roots_kernel(int32_t n,
+                                                             const int32_t* __restrict__ label,
+                                                             unsigned long long* __restrict__ partial) {
+    __shared__ int64_t s_red[kWaves];
+    int64_t c = 0;
+    for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * kBlock)
+        c += label[v] == (int32_t)v ? 1 : 0;
+    const int64_t tot = block_sum<int64_t>(c, s_red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = (unsigned long long)tot;
+}
+
+// total = partial[0] + ... + partial[count - 1] (one workgroup, fixed order).
+__global__ __launch_bounds__(kBlock) void sum_partials_kernel(const unsigned long long* __restrict__ partial,
+                                                              int count,
+                                                              unsigned long long* __restrict__ total) {
+    __shared__ int64_t s_red[kWaves];
+    int64_t c = 0;
+    for (int i = threadIdx.x; i < count; i += kBlock) c += (int64_t)partial[i];
+    const int64_t tot = block_sum<int64_t>(c, s_red);
+    if (threadIdx.x == 0) *total = (unsigned long long)tot;
+}
+
+// Reads an int32 flag word of the scratch (synchronises the stream).
+static int read_flag(const unsigned long long* word, hipStream_t s, int32_t* out) {
+    GILA_HIP(hipMemcpyAsync(out, word, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    GILA_HIP(hipStreamSynchronize(s));
+    return GILA_OK;
+}
+
+static int components_noalloc(const gila_csr* g, int32_t* label, int32_t* count_out,
+                              hipStream_t s) {
+    if (!g) return fail(GILA_EINVAL, "graph is NULL");
+    const int32_t n = g->n;
+    const int64_t nnz = g->nnz;
+    if (n < 0 || nnz < 0) return fail(GILA_EINVAL, "negative n or nnz");
+    if (n > 0 && !g->row_ptr) return fail(GILA_EINVAL, "row_ptr is NULL");
+    if (nnz > 0 && !g->col_idx) return fail(GILA_EINVAL, "col_idx is NULL");
+    if (nnz % 2) return fail(GILA_EINVAL, "nnz must be even for a symmetric CSR");
+    if (nnz > (int64_t)n * (int64_t)(n > 0 ? n - 1 : 0))
+        return fail(GILA_EINVAL, "nnz exceeds n(n-1)");
+    if (n > 0 && !label) return fail(GILA_EINVAL, "label_dev is NULL");
+    unsigned long long* w = nullptr;
+    GILA_TRY(scratch_address(&w));
+    if (n == 0) {
+        if (count_out) *count_out = 0;
+        return GILA_OK;
+    }
+    int32_t* csr_flag = reinterpret_cast<int32_t*>(w);
+    int32_t* hooked = reinterpret_cast<int32_t*>(w + 1);
+    unsigned long long* partial = w + kNoAllocHeader;
+    hipLaunchKernelGGL(clear_words_kernel, dim3(1), dim3(64), 0, s, w, kNoAllocHeader);
+    hipLaunchKernelGGL(rowptr_check_kernel, dim3(grid_for((int64_t)n + 1)), dim3(kBlock), 0, s, n,
+                       nnz, g->row_ptr, csr_flag);
+    GILA_HIP(hipGetLastError());
+    int32_t flag = 0;
+    GILA_TRY(read_flag(w, s, &flag));
+    if (flag) return fail(GILA_EINVAL, "row_ptr must run from 0 to nnz without decreasing");
+    if (nnz > 0) {
+        GILA_TRY(launch_validate_csr(n, nnz, g->row_ptr, g->col_idx, csr_flag, s));
+        GILA_TRY(read_flag(w, s, &flag));
+        if (flag)
+            return fail(GILA_EINVAL, "malformed CSR:%s%s%s%s", (flag & 1) ? " column out of range" : "",
+                        (flag & 2) ? " self-loop" : "", (flag & 4) ? " row not strictly ascending" : "",
+                        (flag & 8) ? " not symmetric" : "");
+    }
+    // the labelling passes of label_components, with the hooked flag in scratch
+    hipLaunchKernelGGL(cc_init_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, n, label);
+    GILA_HIP(hipGetLastError());
+    if (nnz > 0) {
+        const int hgrid =
+            (int)std::max<int64_t>(1, std::min<int64_t>(16384, ((int64_t)n + kWaves - 1) / kWaves));
+        for (int pass = 0;; ++pass) {
+            if (pass > 4096) return fail(GILA_EDEVICE, "component labels did not settle");
+            hipLaunchKernelGGL(clear_words_kernel, dim3(1), dim3(64), 0, s, w + 1, 1);
+            hipLaunchKernelGGL(cc_hook_kernel, dim3(hgrid), dim3(kBlock), 0, s, n, g->row_ptr,
+                               g->col_idx, label, hooked);
+            hipLaunchKernelGGL(cc_compress_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, n, label);
+            GILA_HIP(hipGetLastError());
+            int32_t changed = 0;
+            GILA_TRY(read_flag(w + 1, s, &changed));
+            if (!changed) break;
+        }
+    }
+    if (count_out) {
+        // every component has exactly one root (its smallest id)
+        const int cgrid = (int)std::min<int64_t>(kNoAllocPartials, ((int64_t)n + kBlock - 1) / kBlock);
+        hipLaunchKernelGGL(count_roots_kernel, dim3(cgrid), dim3(kBlock), 0, s, n, label, partial);
+        hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(kBlock), 0, s, partial, cgrid, w + 2);
+        GILA_HIP(hipGetLastError());
+        unsigned long long c = 0;
+        GILA_HIP(hipMemcpyAsync(&c, w + 2, sizeof(c), hipMemcpyDeviceToHost, s));
+        GILA_HIP(hipStreamSynchronize(s));
+        *count_out = (int32_t)c;
+    }
+    GILA_HIP(hipStreamSynchronize(s));
+    return GILA_OK;
+}
+
 }  // namespace gila
 
 using namespace gila;
 
 extern "C" {
+
+int gila_components_noalloc(const gila_csr* g_dev, int32_t* label_dev, int32_t* count_out,
+                            void* stream) {
+    clear_error();
+    return components_noalloc(g_dev, label_dev, count_out, (hipStream_t)stream);
+}
 
 int gila_components(const gila_csr* g_dev, int32_t* label_dev, int32_t* count_out, void* stream) {
     clear_error();

@@ -118,19 +118,18 @@ PhaseTimer::~PhaseTimer() {
                     log.c_str());
 }
 
-static thread_local std::string t_last_error;
+// A fixed buffer per thread: recording an error never allocates.
+static thread_local char t_last_error[1024];
 
 int fail(int code, const char* fmt, ...) {
-    char buf[1024];
     va_list ap;
     va_start(ap, fmt);
-    vsnprintf(buf, sizeof(buf), fmt, ap);
+    vsnprintf(t_last_error, sizeof(t_last_error), fmt, ap);
     va_end(ap);
-    t_last_error = buf;
     return code;
 }
 
-void clear_error() { t_last_error.clear(); }
+void clear_error() { t_last_error[0] = '\0'; }
 
 // ------------------------------------------------------------------ device memory cache
 // hipFree synchronises the whole device.  Blocks released with dfree_on() go to
@@ -324,7 +323,7 @@ const char* gila_strerror(int status) {
     }
 }
 
-const char* gila_last_error(void) { return gila::t_last_error.c_str(); }
+const char* gila_last_error(void) { return gila::t_last_error; }
 
 int gila_version(void) { return 10000; }
 

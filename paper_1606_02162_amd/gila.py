@@ -131,6 +131,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "gila_pruned_free": (None, [vp]),
         "gila_layout_pruned": (ctypes.c_int, [P(Csr), i32, P(_Params), vp, vp, P(Stats)]),
         "gila_components": (ctypes.c_int, [P(Csr), vp, P(i32), vp]),
+        "gila_components_noalloc": (ctypes.c_int, [P(Csr), vp, P(i32), vp]),
         "gila_drawing_metrics": (ctypes.c_int, [P(Csr), i32, vp, i32, vp, P(Metrics), vp, vp]),
         "gila_pack_components": (ctypes.c_int, [i32, vp, dbl, i32, vp, vp]),
         "gila_layout_components": (ctypes.c_int, [P(Csr), i32, P(_Params), vp, vp, P(i32), vp]),
@@ -482,6 +483,17 @@ def components(row_ptr, col_idx, stream=None):
     _check(_lib.gila_components(ctypes.byref(csr), _ptr(label), ctypes.byref(c), _stream(stream)),
            "gila_components")
     return label[: csr.n], c.value
+
+
+def components_noalloc(row_ptr, col_idx, label, stream=None) -> int:
+    """gila_components_noalloc: the labels of gila_components written into the
+    caller's int32 device tensor ``label`` (n entries) with no device
+    allocation by the library; returns the number of components."""
+    csr = make_csr(row_ptr, col_idx)
+    c = ctypes.c_int32()
+    _check(_lib.gila_components_noalloc(ctypes.byref(csr), _ptr(label), ctypes.byref(c),
+                                        _stream(stream)), "gila_components_noalloc")
+    return c.value
 
 
 def pack_components(label, gap: float, precision: int, pos, stream=None):
