@@ -216,13 +216,18 @@ int gila_step(const gila_khop* kh, const gila_params* params, int32_t h, void* p
 int gila_run(const gila_khop* kh, const gila_params* params, int32_t start_h, int32_t end_h,
              void* pos_dev, void* stream, gila_stats* out);
 
-/* Measurement: `reps` iterations h, h+1, ... (eager launches, no HIP graph)
- * on pos_dev with HIP events recorded on `stream` around every kernel.
- * ms_out[0] receives the average duration of the force kernel (the segment
- * kernel, or the direct-gather kernel with the statistics kernel on that
- * path), ms_out[1] that of the rest of the iteration on the segment path (the
- * combine and statistics kernels; 0 on the direct path).  pos_dev is advanced by the
- * iterations.  Synchronises `stream`. */
+/* Measurement: `reps` iterations h, h+1, ... on pos_dev, captured as a HIP
+ * graph with event-record nodes before the force kernel, after it and after
+ * the rest of each iteration, and replayed once on `stream` (eager launches
+ * with the same events if the capture is refused).  ms_out[0] receives the
+ * average duration of the force kernel (the segment kernel, or the
+ * direct-gather kernel with the statistics kernel on that path), ms_out[1]
+ * that of the rest of the iteration on the segment path (the combine and
+ * statistics kernels; 0 on the direct path), ms_out[2] 1 if the times come
+ * from a graph replay, 0 if from eager launches; ms_out holds 3 doubles.
+ * Both durations come from one run, so ms_out[0] + ms_out[1] is that run's
+ * iteration time.  pos_dev is advanced by the iterations.  Synchronises
+ * `stream`. */
 int gila_time_iterations(const gila_khop* kh, const gila_params* params, int32_t h,
                          int32_t reps, void* pos_dev, void* stream, double* ms_out);
 
@@ -388,21 +393,49 @@ int gila_drawing_metrics(const gila_csr* g_dev, int32_t precision, const void* p
 /* ------------------------------------------------------------------ */
 typedef struct gila_batch gila_batch;
 
-/* Build the k-hop lists of `count` independent graphs (graphs_dev[i] is a
- * device CSR, k[i] >= 1) into one segmented handle.  Each graph's plan
- * (threads per vertex, resident or streamed) depends only on that graph, so a
- * graph's result is the same bits alone or in any batch.  Synchronises. */
+/* Build the k-hop lists N_v(k) (Section 4.5) of `count` independent graphs
+ * (graphs_dev[i] is a device CSR with at most 65535 vertices, k[i] >= 1) into
+ * one segmented handle, and fix each graph's plan: its lanes per vertex (the
+ * order in which its force terms are summed, hence its result bits), from
+ * its mean |N_v(k)| -- about eight entries per lane, a power of two in
+ * [1, 64].  The plan depends only on the graph, so a graph's result is the
+ * same bits alone, in any batch and in any process.  Synchronises. */
 int gila_batch_build(const gila_csr* graphs_dev, int32_t count, const int32_t* k,
                      void* stream, gila_batch** out);
 
 /* All iterations of every graph of the batch in one persistent segmented
- * launch.  params[i] and pos_dev[i] belong to graph i; all graphs must use
- * the same precision.  out (may be NULL) is [count].  Synchronises. */
+ * launch (the Section 4.5 iteration with each graph's own cap schedule and
+ * halting rule, Section 5.1), each graph with its plan's lanes per vertex.
+ * params[i] and pos_dev[i] belong to graph i; all graphs must use the same
+ * precision and the FR model.  out (may be NULL) is [count].
+ * GILA_ENONFINITE: some graph met a non-finite force (its out[] entry counts
+ * the vertices; its run stopped there; the other graphs are unaffected).
+ * Synchronises. */
 int gila_batch_run(gila_batch* b, const gila_params* params, void* const* pos_dev,
                    void* stream, gila_stats* out);
 
 int gila_batch_info(const gila_batch* b, int32_t* count, int64_t* total_pairs,
                     int64_t* device_bytes);
+
+/* The handle's plan: lanes_host[count] receives each graph's lanes per vertex,
+ * class_host[count] its row-length class c = the largest c <= 7 with
+ * mean |N_v(k)| >= 4 * 2^c (0 below 8).  Either may be NULL. */
+int gila_batch_plan(const gila_batch* b, int32_t* lanes_host, int32_t* class_host);
+
+/* Replaces the plan: lanes_host[count], each a power of two in [1, 64]
+ * (EINVAL otherwise, plan unchanged).  A plan read with gila_batch_plan (or
+ * derived from a gila_batch_tune table by class) and set again reproduces
+ * that run's bits. */
+int gila_batch_set_plan(gila_batch* b, const int32_t* lanes_host);
+
+/* Tuner (the project's own): for each row-length class present in the batch,
+ * times every lanes-per-vertex choice on up to 48 of its graphs (8 iterations
+ * at cap 0 from seeded positions, in scratch memory; the caller's positions
+ * are not touched) in `precision`, and sets the fastest in the plan of every
+ * graph of the class.  class_lanes_host[8] (may be NULL) receives the choice
+ * per class (0: class absent), for the caller to keep and apply to later
+ * batches.  Never run implicitly.  Synchronises `stream`. */
+int gila_batch_tune(gila_batch* b, int32_t precision, void* stream, int32_t* class_lanes_host);
 
 /* Latency of each graph in the last gila_batch_run: ms_host[count] receives
  * the time from the start of the first graph's work to the moment graph i's
@@ -426,7 +459,7 @@ int gila_layout_batch(const gila_csr* graphs_dev, int32_t count, const int32_t* 
 /* ------------------------------------------------------------------ */
 typedef struct gila_server gila_server;
 
-/* A server owns four threads (admission, k-hop builds, batched small jobs,
+/* A server owns five threads (admission, k-hop builds, two for batched small jobs,
  * ticks) and its own streams on `device`.  Unlike the other handles, a server
  * may be used from several threads at once: gila_submit, gila_poll,
  * gila_wait, gila_cancel, gila_job_latency and gila_server_info serialise on
@@ -436,8 +469,10 @@ typedef struct gila_server gila_server;
  * overlap any other call on the server.  Jobs are admitted in arrival order
  * while their device footprint bound fits in hbm_budget_bytes (0 = 90% of free
  * HBM) and fewer than max_slots jobs are in flight.  Small jobs are laid out
- * together in batched launches; larger ones are built, then advance together
- * a few iterations per tick; builds, batched launches and ticks overlap.
+ * together in batched launches; larger ones are built, then advance a few
+ * iterations per tick, each job's next tick queued as soon as its previous
+ * one has ended (a replay of the job's captured tick); builds, batched
+ * launches and ticks overlap.
  * Device memory released by the server goes to the library's block cache
  * (reused without device-wide synchronisation). */
 int gila_server_create(int32_t device, int64_t hbm_budget_bytes, int32_t max_slots,
@@ -466,7 +501,7 @@ int gila_cancel(gila_server* s, uint64_t ticket);
 
 /* Server settings: "tick_iterations" (iterations a resident job advances per
  * tick, default 50), "small_max_vertices" (largest job laid out by the batched
- * LDS-resident kernel, default 2048 -- one workgroup per graph, so larger jobs
+ * LDS-resident kernel, default 1024 -- one workgroup per graph, so larger jobs
  * finish sooner on the whole-GPU path; 0 = the most that fits in LDS),
  * "fail_alloc_ticket" (test hook: the job with this ticket fails its device
  * allocation with ENOMEM). */
@@ -476,7 +511,8 @@ int gila_server_config(gila_server* s, const char* key, int64_t value);
  * GILA_EAGAIN before it finished.  Kept until the server is destroyed. */
 int gila_job_latency(gila_server* s, uint64_t ticket, double* queued_ms, double* total_ms);
 
-/* Counters: jobs done, ticks run, peak resident jobs, device bytes reserved. */
+/* Counters: jobs done, ticks queued (one per resident large job per tick),
+ * peak resident large jobs, device bytes reserved. */
 int gila_server_info(gila_server* s, int64_t* jobs_done, int64_t* ticks, int32_t* peak_resident,
                      int64_t* bytes_in_use);
 

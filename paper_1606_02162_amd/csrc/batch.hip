@@ -12,9 +12,11 @@
 // the synchronous move into the other buffer, the statistics and the halting
 // rule -- with only workgroup barriers between iterations; then it writes the
 // positions back and takes the next graph.  A graph's arithmetic depends only
-// on that graph (its lanes per vertex come from a per-class table fixed for
-// the process), so its result is the same bits alone or in any batch.  The
-// launch is captured as a HIP graph and replayed on later runs.
+// on that graph and its lanes per vertex, which the handle's plan fixes at
+// build (from the graph's mean row length; gila_batch_tune or
+// gila_batch_set_plan may replace it), so its result is the same bits alone,
+// in any batch and in any process.  The launch is captured as a HIP graph and
+// replayed on later runs.
 #include <algorithm>
 #include <cstring>
 #include <cmath>
@@ -33,7 +35,7 @@ struct BatchDesc {
     int32_t lpv;               // lanes per vertex
     int32_t iters;             // iterations to run
     int32_t t_off;             // offset of its temperatures
-    int32_t cls;               // row-length class (autotuner key)
+    int32_t cls;               // row-length class (key of the tuner's table)
     double d;
     double stop_fraction;
     double stop_displacement;
@@ -65,6 +67,7 @@ struct gila_batch {
     int32_t nmax = 0;
     std::vector<int64_t> vbase, ebase, Pg;
     std::vector<int32_t> n, n_active, k, cls;
+    std::vector<int32_t> lpv;  // the plan: lanes per vertex of each graph
     int64_t* kptr = nullptr;
     uint16_t* kidx = nullptr;
     int64_t* rp = nullptr;
@@ -87,6 +90,10 @@ namespace gila {
 constexpr int kBatchBlock = 512;
 constexpr int kBatchWaves = kBatchBlock / 64;
 constexpr int kClasses = 8;
+// A vertex with a non-finite force is counted in the high 32 bits of the
+// per-thread moved counter (a batched graph has at most 65535 vertices, so
+// the low half never carries into them): no extra register in the kernel.
+constexpr int64_t kNonfiniteOne = int64_t(1) << 32;
 
 // ------------------------------------------------------------------ build kernels
 struct GraphSrc {
@@ -317,7 +324,7 @@ template <class P, int LPV>
 __device__ __forceinline__ void batch_graph_iteration(
     const BatchArgs& a, const BatchDesc& G, const typename P::vec2* __restrict__ cur,
     typename P::vec2* __restrict__ nxt, double t, double& energy, double& maxd, int64_t& moved,
-    int& coinc, int& nonfinite) {
+    int& coinc) {
     using R = typename P::real;
     using V = typename P::vec2;
     const double d2 = G.d * G.d;
@@ -389,43 +396,35 @@ __device__ __forceinline__ void batch_graph_iteration(
         const double fy = group_sum<LPV>(acc.y()) * d2;
         if (v < G.n && gl == 0) {
             // temperature cap and synchronous move (into the other buffer)
+            // (a non-finite force -- a term overflowed -- leaves the vertex in
+            // place and stops the graph's run)
             V nx = xv;
-            if (!(fabs(fx) <= DBL_MAX) || !(fabs(fy) <= DBL_MAX)) {
-                ++nonfinite;  // a term overflowed: the vertex stays, the graph stops
-            } else if constexpr (sizeof(R) == 4) {
-                energy += fx * fx + fy * fy;
+            if constexpr (sizeof(R) == 4) {
                 // FP32 positions: the move in FP32 (one lane per vertex does
                 // this part, so its instruction count matters); |Delta| = the
                 // capped length
-                const float fxf = (float)fx, fyf = (float)fy;
-                const float norm = sqrtf(fmaf(fxf, fxf, fyf * fyf));
-                float l = 0.f, dx = 0.f, dy = 0.f;
-                if (norm > 0.f && norm <= FLT_MAX) {
-                    l = fminf(norm, (float)t);
-                    const float sc = l * fast_rcp(norm);
-                    dx = fxf * sc;
-                    dy = fyf * sc;
-                } else if (fx != 0.0 || fy != 0.0) {
-                    // the square left float's range: the scaled double cap
-                    double ddx, ddy;
-                    capped_move(fx, fy, t, ddx, ddy);
-                    dx = (float)ddx;
-                    dy = (float)ddy;
-                    l = (float)sqrt(ddx * ddx + ddy * ddy);
+                float l, dx, dy;
+                if (capped_move_f32(fx, fy, t, dx, dy, l)) {
+                    energy += fx * fx + fy * fy;
+                    nx.x = xv.x + dx;
+                    nx.y = xv.y + dy;
+                    maxd = (double)l > maxd ? (double)l : maxd;
+                    moved += (double)l > G.stop_displacement ? 1 : 0;
+                } else {
+                    moved += kNonfiniteOne;
                 }
-                nx.x = xv.x + dx;
-                nx.y = xv.y + dy;
-                maxd = (double)l > maxd ? (double)l : maxd;
-                moved += (double)l > G.stop_displacement ? 1 : 0;
             } else {
-                energy += fx * fx + fy * fy;
                 double dx, dy;
-                capped_move(fx, fy, t, dx, dy);
-                nx.x = (R)((double)xv.x + dx);
-                nx.y = (R)((double)xv.y + dy);
-                const double dl = sqrt(dx * dx + dy * dy);
-                maxd = dl > maxd ? dl : maxd;
-                moved += dl > G.stop_displacement ? 1 : 0;
+                if (capped_move(fx, fy, t, dx, dy)) {
+                    energy += fx * fx + fy * fy;
+                    nx.x = (R)((double)xv.x + dx);
+                    nx.y = (R)((double)xv.y + dy);
+                    const double dl = sqrt(dx * dx + dy * dy);
+                    maxd = dl > maxd ? dl : maxd;
+                    moved += dl > G.stop_displacement ? 1 : 0;
+                } else {
+                    moved += kNonfiniteOne;
+                }
             }
             nxt[v] = nx;
         }
@@ -433,7 +432,7 @@ __device__ __forceinline__ void batch_graph_iteration(
 }
 
 template <int PREC>
-__global__ __launch_bounds__(kBatchBlock) void batch_layout_kernel(BatchArgs a) {
+__device__ __forceinline__ void batch_layout_body(const BatchArgs& a) {
     using P = Prec<PREC>;
     using V = typename P::vec2;
     extern __shared__ __align__(16) unsigned char s_raw[];
@@ -442,7 +441,6 @@ __global__ __launch_bounds__(kBatchBlock) void batch_layout_kernel(BatchArgs a) 
     // rewritten two iterations later, after a barrier every reader has passed)
     __shared__ double s_e[2][kBatchWaves], s_m[2][kBatchWaves];
     __shared__ int64_t s_mv[2][kBatchWaves], s_c[2][kBatchWaves];
-    __shared__ int32_t s_nf[2][kBatchWaves];
     const int lane = lane64(), w = wave_id();
     for (;;) {
         if (threadIdx.x == 0) s_g = atomicAdd(a.work, 1);
@@ -472,15 +470,15 @@ __global__ __launch_bounds__(kBatchBlock) void batch_layout_kernel(BatchArgs a) 
             const double t = a.temps[G.t_off + h];
             double energy = 0.0, maxd = 0.0;
             int64_t moved = 0;
-            int coinc = 0, nonfinite = 0;
+            int coinc = 0;
             switch (G.lpv) {
-                case 1: batch_graph_iteration<P, 1>(a, G, cur, nxt, t, energy, maxd, moved, coinc, nonfinite); break;
-                case 2: batch_graph_iteration<P, 2>(a, G, cur, nxt, t, energy, maxd, moved, coinc, nonfinite); break;
-                case 4: batch_graph_iteration<P, 4>(a, G, cur, nxt, t, energy, maxd, moved, coinc, nonfinite); break;
-                case 8: batch_graph_iteration<P, 8>(a, G, cur, nxt, t, energy, maxd, moved, coinc, nonfinite); break;
-                case 16: batch_graph_iteration<P, 16>(a, G, cur, nxt, t, energy, maxd, moved, coinc, nonfinite); break;
-                case 32: batch_graph_iteration<P, 32>(a, G, cur, nxt, t, energy, maxd, moved, coinc, nonfinite); break;
-                default: batch_graph_iteration<P, 64>(a, G, cur, nxt, t, energy, maxd, moved, coinc, nonfinite); break;
+                case 1: batch_graph_iteration<P, 1>(a, G, cur, nxt, t, energy, maxd, moved, coinc); break;
+                case 2: batch_graph_iteration<P, 2>(a, G, cur, nxt, t, energy, maxd, moved, coinc); break;
+                case 4: batch_graph_iteration<P, 4>(a, G, cur, nxt, t, energy, maxd, moved, coinc); break;
+                case 8: batch_graph_iteration<P, 8>(a, G, cur, nxt, t, energy, maxd, moved, coinc); break;
+                case 16: batch_graph_iteration<P, 16>(a, G, cur, nxt, t, energy, maxd, moved, coinc); break;
+                case 32: batch_graph_iteration<P, 32>(a, G, cur, nxt, t, energy, maxd, moved, coinc); break;
+                default: batch_graph_iteration<P, 64>(a, G, cur, nxt, t, energy, maxd, moved, coinc); break;
             }
             // iteration statistics: per wave, then every thread combines the
             // waves' values in the same fixed order (the same bits everywhere).
@@ -491,34 +489,32 @@ __global__ __launch_bounds__(kBatchBlock) void batch_layout_kernel(BatchArgs a) 
             const double wm = wave_max(maxd);
             const int64_t wmv = wave_sum(moved);
             const int64_t wc = wave_sum((int64_t)coinc);
-            const int32_t wnf = wave_sum(nonfinite);
             if (lane == 0) {
                 s_e[par][w] = we;
                 s_m[par][w] = wm;
                 s_mv[par][w] = wmv;
                 s_c[par][w] = wc;
-                s_nf[par][w] = wnf;
             }
             __syncthreads();
             double e = s_e[par][0], m = s_m[par][0];
-            int64_t mv = s_mv[par][0], c = s_c[par][0], nf = s_nf[par][0];
+            int64_t mv = s_mv[par][0], c = s_c[par][0];
             for (int i = 1; i < kBatchWaves; ++i) {
                 e += s_e[par][i];
                 m = s_m[par][i] > m ? s_m[par][i] : m;
                 mv += s_mv[par][i];
                 c += s_c[par][i];
-                nf += s_nf[par][i];
             }
             E = e;
             M = m;
-            MV = mv;
             C = c;
-            NF = nf;
+            NF = mv >> 32;  // vertices with a non-finite force
+            mv &= 0xFFFFFFFFll;
+            MV = mv;
             ++run;
             V* tmp = cur;
             cur = nxt;
             nxt = tmp;
-            if (nf > 0) break;  // a non-finite force ends this graph's run
+            if (NF > 0) break;  // a non-finite force ends this graph's run
             if (G.stop_fraction > 0.0 && (double)mv < G.stop_fraction * (double)G.n_active) {
                 stopped = 1;
                 break;
@@ -548,6 +544,20 @@ __global__ __launch_bounds__(kBatchBlock) void batch_layout_kernel(BatchArgs a) 
     }
 }
 
+// The FP32 launches are held to 128 VGPRs, i.e. four waves per SIMD: the
+// launch waits on the latency of each iteration's row loads, and the
+// compiler's free choice sits just above 128 (three waves per SIMD).  The
+// FP64 launch keeps its free allocation, which the cap would make spill.
+template <int PREC>
+__global__ __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(4)))
+void batch_layout_kernel(BatchArgs a) {
+    batch_layout_body<PREC>(a);
+}
+
+__global__ __launch_bounds__(kBatchBlock) void batch_layout_kernel_f64(BatchArgs a) {
+    batch_layout_body<GILA_FP64>(a);
+}
+
 __global__ void reset_work_kernel(int32_t* w) { *w = 0; }
 
 // ------------------------------------------------------------------ lanes per vertex
@@ -567,31 +577,6 @@ static int default_lpv(int cls) {
     return l;
 }
 
-struct TuneTable {
-    int lpv[3][kClasses];
-    bool tuned[3][kClasses];
-};
-static std::mutex g_tune_mu;
-static std::map<int, TuneTable> g_tune;  // per device
-
-static TuneTable& tune_table(int device) {
-    auto it = g_tune.find(device);
-    if (it == g_tune.end()) {
-        TuneTable t{};
-        for (int p = 0; p < 3; ++p)
-            for (int c = 0; c < kClasses; ++c) {
-                t.lpv[p][c] = default_lpv(c);
-                t.tuned[p][c] = false;
-            }
-        it = g_tune.emplace(device, t).first;
-    }
-    return it->second;
-}
-
-static bool autotune_enabled() {
-    const char* e = getenv("GILA_AUTOTUNE");
-    return !(e && e[0] == '0');
-}
 
 size_t batch_lds_bytes(int32_t nmax, int precision) {
     return (size_t)2 * ((size_t)std::max(nmax, 1) + 1) * (precision == GILA_FP64 ? 16 : 8);
@@ -601,7 +586,7 @@ static void launch_batch_kernel(int precision, int grid, size_t lds, hipStream_t
                                 const BatchArgs& a) {
     switch (precision) {
         case GILA_FP64:
-            hipLaunchKernelGGL(batch_layout_kernel<GILA_FP64>, dim3(grid), dim3(kBatchBlock), lds, s, a);
+            hipLaunchKernelGGL(batch_layout_kernel_f64, dim3(grid), dim3(kBatchBlock), lds, s, a);
             break;
         case GILA_FP32:
             hipLaunchKernelGGL(batch_layout_kernel<GILA_FP32>, dim3(grid), dim3(kBatchBlock), lds, s, a);
@@ -615,7 +600,7 @@ static void launch_batch_kernel(int precision, int grid, size_t lds, hipStream_t
 
 static void set_lds_attr(size_t lds) {
     if (lds <= 48 * 1024) return;
-    (void)hipFuncSetAttribute((const void*)batch_layout_kernel<GILA_FP64>,
+    (void)hipFuncSetAttribute((const void*)batch_layout_kernel_f64,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     (void)hipFuncSetAttribute((const void*)batch_layout_kernel<GILA_FP32>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -629,22 +614,33 @@ static int batch_grid(const gila_batch* b, size_t lds) {
     return (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)di.cus * (int64_t)per_cu, b->count));
 }
 
-// Times every candidate lanes-per-vertex on up to 48 graphs of each class not
-// tuned yet (8 iterations on scratch copies of their positions) and keeps the
-// fastest.  The choice is made once per device, class and precision.
-static int autotune(gila_batch* b, int precision, hipStream_t s,
-                    const std::vector<BatchDesc>& desc) {
-    TuneTable& tt = tune_table(b->device);
+// The tuner: for every row-length class present in the batch, times each
+// candidate lanes per vertex (1, 2, ..., 64) on up to 48 of the class's
+// graphs (8 iterations at cap 0 from seeded positions in scratch memory) and
+// keeps the fastest.  table[c] receives the choice for class c (0 where the
+// class is absent), and every graph of the class takes it in the handle's
+// plan.  Only an explicit gila_batch_tune runs it.
+static int tune_plan(gila_batch* b, int precision, hipStream_t s, int32_t* table) {
     std::vector<int> todo;
     for (int c = 0; c < kClasses; ++c) {
-        if (tt.tuned[precision][c]) continue;
+        table[c] = 0;
         for (int32_t i = 0; i < b->count; ++i)
-            if (b->cls[i] == c && desc[i].n > 0) {
+            if (b->cls[i] == c && b->n[i] > 0) {
                 todo.push_back(c);
                 break;
             }
     }
     if (todo.empty()) return GILA_OK;
+    std::vector<BatchDesc> desc((size_t)b->count);
+    for (int32_t i = 0; i < b->count; ++i) {
+        BatchDesc& d = desc[i];
+        d.vbase = b->vbase[i];
+        d.n = b->n[i];
+        d.n_active = b->n_active[i];
+        d.cls = b->cls[i];
+        d.d = 48.0;
+        d.stop_displacement = 0.01;
+    }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     GILA_HIP(hipEventCreate(&e0));
     GILA_HIP(hipEventCreate(&e1));
@@ -653,7 +649,7 @@ static int autotune(gila_batch* b, int precision, hipStream_t s,
     for (int c : todo) {
         std::vector<int32_t> ids;
         for (int32_t i = 0; i < b->count && ids.size() < 48; ++i)
-            if (b->cls[i] == c && desc[i].n > 0) ids.push_back(i);
+            if (b->cls[i] == c && b->n[i] > 0) ids.push_back(i);
         int64_t vtot = 0;
         int32_t nmax = 0;
         for (int32_t i : ids) {
@@ -674,11 +670,11 @@ static int autotune(gila_batch* b, int precision, hipStream_t s,
         std::vector<int32_t> ord(ids.size());
         std::iota(ord.begin(), ord.end(), 0);
         if (!rc && hipMemcpyAsync(d_t, temps.data(), 8 * sizeof(double), hipMemcpyHostToDevice, s))
-            rc = fail(GILA_EDEVICE, "autotune upload");
+            rc = fail(GILA_EDEVICE, "tuner upload");
         if (!rc && hipMemcpyAsync(d_order, ord.data(), ord.size() * 4, hipMemcpyHostToDevice, s))
-            rc = fail(GILA_EDEVICE, "autotune upload");
+            rc = fail(GILA_EDEVICE, "tuner upload");
         float best_ms = 1e30f;
-        int best = tt.lpv[precision][c];
+        int best = default_lpv(c);
         const size_t lds = batch_lds_bytes(nmax, precision);
         set_lds_attr(lds);
         for (int lpv = 1; lpv <= 64 && !rc; lpv *= 2) {
@@ -686,12 +682,11 @@ static int autotune(gila_batch* b, int precision, hipStream_t s,
             int64_t off = 0;
             for (int32_t i : ids) {
                 BatchDesc d = desc[i];
-                if (hipMemcpyAsync((char*)scratch + off * pb, d.pos, (size_t)d.n * pb,
-                                   hipMemcpyDeviceToDevice, s) != hipSuccess) {
-                    rc = fail(GILA_EDEVICE, "autotune copy");
-                    break;
-                }
                 d.pos = (char*)scratch + off * pb;
+                // seeded positions in the paper's frame (the timing does not
+                // depend on them beyond rare coincident pairs)
+                rc = gila_init_positions(d.n, (uint64_t)i, 1200.0, 1200.0, precision, d.pos, s);
+                if (rc) break;
                 d.lpv = lpv;
                 d.iters = 8;
                 d.t_off = 0;
@@ -702,7 +697,7 @@ static int autotune(gila_batch* b, int precision, hipStream_t s,
             if (rc) break;
             if (hipMemcpyAsync(d_desc, sub.data(), sub.size() * sizeof(BatchDesc),
                                hipMemcpyHostToDevice, s) != hipSuccess) {
-                rc = fail(GILA_EDEVICE, "autotune upload");
+                rc = fail(GILA_EDEVICE, "tuner upload");
                 break;
             }
             BatchArgs a{};
@@ -722,7 +717,7 @@ static int autotune(gila_batch* b, int precision, hipStream_t s,
             launch_batch_kernel(precision, grid, lds, s, a);
             (void)hipEventRecord(e1, s);
             if (hipStreamSynchronize(s) != hipSuccess) {
-                rc = fail(GILA_EDEVICE, "autotune run failed");
+                rc = fail(GILA_EDEVICE, "tuner run failed");
                 break;
             }
             float ms = 0.f;
@@ -738,8 +733,9 @@ static int autotune(gila_batch* b, int precision, hipStream_t s,
         dfree_on(d_t, s);
         dfree_on(d_st, s);
         if (rc) break;
-        tt.lpv[precision][c] = best;
-        tt.tuned[precision][c] = true;
+        table[c] = best;
+        for (int32_t i = 0; i < b->count; ++i)
+            if (b->cls[i] == c) b->lpv[i] = best;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -921,8 +917,10 @@ int batch_build(const gila_csr* graphs, int32_t count, const int32_t* k, hipStre
         GILA_HIP(hipGetLastError());
     }
     GILA_TRY(exclusive_scan_i64(d_padded.p, b->kptr, b->nv, s));
-    GILA_HIP(hipMemcpy(&b->P, d_ktrue.p + b->nv, sizeof(int64_t), hipMemcpyDeviceToHost));
-    GILA_HIP(hipMemcpy(&b->P_padded, b->kptr + b->nv, sizeof(int64_t), hipMemcpyDeviceToHost));
+    GILA_HIP(hipMemcpyAsync(&b->P, d_ktrue.p + b->nv, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    GILA_HIP(hipMemcpyAsync(&b->P_padded, b->kptr + b->nv, sizeof(int64_t),
+                            hipMemcpyDeviceToHost, s));
+    GILA_HIP(hipStreamSynchronize(s));
     GILA_TRY(dalloc_t(&b->kidx, (size_t)b->P_padded + 64));
     if (b->nv > 0 && b->P > 0) {
         if (per_graph) {
@@ -962,10 +960,12 @@ int batch_build(const gila_csr* graphs, int32_t count, const int32_t* k, hipStre
     pt.mark("localize+bounds");
     b->Pg.assign(count, 0);
     b->cls.assign(count, 0);
+    b->lpv.assign(count, 1);
     std::vector<int64_t> work(count);
     for (int32_t i = 0; i < count; ++i) {
         b->Pg[i] = bounds[i + 1] - bounds[i];
         b->cls[i] = row_class(b->Pg[i], b->n[i]);
+        b->lpv[i] = default_lpv(b->cls[i]);
         work[i] = b->Pg[i] + (b->ebase[i + 1] - b->ebase[i]) + 8ll * b->n[i];
     }
     b->order.resize(count);
@@ -1028,12 +1028,7 @@ int batch_run(gila_batch* b, const gila_params* params, void* const* pos, hipStr
                         sizeof(double) * params[i].iterations);
         off += params[i].iterations;
     }
-    {
-        std::lock_guard<std::mutex> lk(g_tune_mu);
-        if (autotune_enabled()) GILA_TRY(autotune(b, precision, s, desc));
-        const TuneTable& tt = tune_table(b->device);
-        for (int32_t i = 0; i < count; ++i) desc[i].lpv = tt.lpv[precision][desc[i].cls];
-    }
+    for (int32_t i = 0; i < count; ++i) desc[i].lpv = b->lpv[i];
     if ((int64_t)temps.size() > b->temps_cap) {
         dfree(b->d_temps);
         b->d_temps = nullptr;
@@ -1077,7 +1072,8 @@ int batch_run(gila_batch* b, const gila_params* params, void* const* pos, hipStr
         }
         hipStream_t cs = capture_stream(b->device);
         if (!cs) return fail(GILA_EDEVICE, "cannot create capture stream");
-        GILA_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        (void)hipGetLastError();  // no stale status may fail a check inside the capture
+        GILA_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
         hipLaunchKernelGGL(reset_work_kernel, dim3(1), dim3(1), 0, cs, b->d_work);
         launch_batch_kernel(precision, grid, lds, cs, a);
         hipGraph_t graph = nullptr;
@@ -1183,6 +1179,44 @@ int gila_batch_latency(const gila_batch* b, double* ms_host) {
     for (int32_t i = 0; i < b->count; ++i) t0 = std::min(t0, clk[i]);
     for (int32_t i = 0; i < b->count; ++i)
         ms_host[i] = (double)(clk[b->count + i] - t0) / (double)khz;
+    return GILA_OK;
+}
+
+int gila_batch_plan(const gila_batch* b, int32_t* lanes_host, int32_t* class_host) {
+    clear_error();
+    if (!b) return fail(GILA_EINVAL, "batch is NULL");
+    for (int32_t i = 0; i < b->count; ++i) {
+        if (lanes_host) lanes_host[i] = b->lpv[i];
+        if (class_host) class_host[i] = b->cls[i];
+    }
+    return GILA_OK;
+}
+
+int gila_batch_set_plan(gila_batch* b, const int32_t* lanes_host) {
+    clear_error();
+    if (!b) return fail(GILA_EINVAL, "batch is NULL");
+    if (b->count > 0 && !lanes_host) return fail(GILA_EINVAL, "lanes_host is NULL");
+    for (int32_t i = 0; i < b->count; ++i) {
+        const int32_t l = lanes_host[i];
+        if (l < 1 || l > 64 || (l & (l - 1)))
+            return fail(GILA_EINVAL, "graph %d: lanes per vertex %d is not a power of two in "
+                                     "[1, 64]", i, l);
+    }
+    std::lock_guard<std::mutex> lk(b->mu);
+    for (int32_t i = 0; i < b->count; ++i) b->lpv[i] = lanes_host[i];
+    return GILA_OK;
+}
+
+int gila_batch_tune(gila_batch* b, int32_t precision, void* stream, int32_t* class_lanes_host) {
+    clear_error();
+    if (!b) return fail(GILA_EINVAL, "batch is NULL");
+    if (precision != GILA_FP64 && precision != GILA_FP32 && precision != GILA_FP32_KAHAN)
+        return fail(GILA_EINVAL, "unknown precision %d", precision);
+    std::lock_guard<std::mutex> lk(b->mu);
+    DeviceGuard dg(b->device);
+    int32_t table[kClasses];
+    GILA_TRY(tune_plan(b, precision, (hipStream_t)stream, table));
+    if (class_lanes_host) std::memcpy(class_lanes_host, table, sizeof(table));
     return GILA_OK;
 }
 

@@ -164,7 +164,7 @@ int launch_step(const gila_khop* kh, int precision, const StepArgs& a, hipStream
 static constexpr int64_t kVertexCost = 32;
 
 int plan_iteration(gila_khop* kh, const std::vector<int64_t>& counts,
-                   const std::vector<int64_t>& rp_internal) {
+                   const std::vector<int64_t>& rp_internal, hipStream_t s) {
     const int32_t na = kh->n_active;
     int32_t nhub = 0;
     while (nhub < na && counts[nhub] >= kHubMin) ++nhub;
@@ -198,8 +198,11 @@ int plan_iteration(gila_khop* kh, const std::vector<int64_t>& counts,
     const int32_t nnormal = (int32_t)starts.size() - 1;
     kh->nblocks = nhub + nnormal;
     GILA_TRY(dalloc_t(&kh->block_start, starts.size()));
-    GILA_HIP(hipMemcpy(kh->block_start, starts.data(), sizeof(int32_t) * starts.size(),
-                       hipMemcpyHostToDevice));
+    // on the build's stream (never the legacy one, which must not meet a
+    // capture in progress on another thread); `starts` lives until the copy ends
+    GILA_HIP(hipMemcpyAsync(kh->block_start, starts.data(), sizeof(int32_t) * starts.size(),
+                            hipMemcpyHostToDevice, s));
+    GILA_HIP(hipStreamSynchronize(s));
     return GILA_OK;
 }
 

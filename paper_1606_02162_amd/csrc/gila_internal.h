@@ -100,7 +100,7 @@ struct Ctl {
     int32_t stopped;
     int32_t iters_run;
     uint32_t done_blocks;  // reserved
-    int32_t pad;
+    int32_t h_base;        // first iteration of a captured tick (caps read on the device)
     int64_t moved;
     double max_disp;
     double energy;
@@ -131,7 +131,9 @@ struct StepArgs {
     const void* pos_cur;
     void* pos_next;
     double d;
-    double t;
+    double t;                   // cap of the iteration, unless temps is set:
+    const double* temps;        // device schedule: the cap is temps[ctl->h_base + tick_j]
+    int32_t tick_j;             // (captured ticks, whose first iteration is set at replay)
     double stop_fraction;
     double stop_displacement;
     int32_t check_stop;
@@ -252,6 +254,12 @@ struct gila_khop {
     // cached HIP graph of the last gila_run call
     hipGraphExec_t gexec = nullptr;
     std::vector<uint64_t> gkey;
+    // captured tick of the layout server: a fixed number of iterations whose
+    // caps come from the device copy of the schedule at ctl->h_base
+    hipGraphExec_t tick_exec = nullptr;
+    std::vector<uint64_t> tick_key;
+    double* d_temps = nullptr;
+    std::vector<double> temps_host;  // the schedule d_temps holds
     std::mutex mu;
 };
 
@@ -259,7 +267,7 @@ namespace gila {
 // implemented in force.hip
 int launch_step(const gila_khop* kh, int precision, const StepArgs& a, hipStream_t s);
 int plan_iteration(gila_khop* kh, const std::vector<int64_t>& counts_internal,
-                   const std::vector<int64_t>& rp_internal);
+                   const std::vector<int64_t>& rp_internal, hipStream_t s);
 // implemented in khop.hip
 int build_khop(const gila_csr* g, int32_t k, hipStream_t s, gila_khop** out);
 void free_khop(gila_khop* kh, Release rel = Release{});
@@ -291,6 +299,8 @@ int launch_iteration_stats(const StepArgs& a, hipStream_t s);
 // implemented in layout.hip: one iteration on whichever path the handle is ready for
 int launch_iteration(const gila_khop* kh, int precision, const StepArgs& a, hipStream_t s);
 int prepare_precision(gila_khop* kh, int precision, hipStream_t s);
+// destroys the handle's captured graphs (their kernels or arguments changed)
+void drop_graphs(gila_khop* kh);
 // implemented in layout.hip
 int run_iterations(gila_khop* kh, const gila_params* p, int32_t start_h, int32_t end_h,
                    void* pos_dev, hipStream_t stream, gila_stats* out, bool use_graph);
@@ -304,6 +314,12 @@ void force_exponents(const gila_params* p, int32_t* att_p, int32_t* rep_q);
 // of the control block, permute in, the iterations, permute out.
 int enqueue_run(gila_khop* kh, const gila_params* p, int32_t start_h, int32_t end_h,
                 void* pos_dev, hipStream_t s);
+// Enqueues iterations [h, h + count) like enqueue_run, with the same bits;
+// when count == graph_len they replay one captured graph per handle (built on
+// first use, the caps read from a device copy of the schedule), so a tick of
+// the server costs two launches instead of three per iteration.
+int enqueue_tick(gila_khop* kh, const gila_params* p, int32_t h, int32_t count,
+                 int32_t graph_len, void* pos_dev, hipStream_t s);
 // implemented in batch.hip
 int batch_build(const gila_csr* graphs, int32_t count, const int32_t* k, hipStream_t s,
                 gila_batch** out);

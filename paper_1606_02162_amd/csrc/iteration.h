@@ -294,28 +294,64 @@ __device__ __forceinline__ R attract_param(double d) {
 }
 
 // Temperature-capped displacement (Section 3.1): Delta = F min(|F|, t) / |F|,
-// and 0 for F = 0.  When squaring F would overflow or underflow, |F| and the
-// direction come from F divided by its largest component, so every finite
-// F != 0 moves min(|F|, t) along F.  A non-finite F (a term overflowed in the
-// precision) gives no move and returns false.
+// and 0 for F = 0.  When squaring F would overflow or underflow, F is first
+// scaled by a power of two (exact) that brings its largest component into
+// [0.5, 1), so every finite F != 0 moves min(|F|, t) along F.  A non-finite F
+// (a term overflowed in the precision) gives no move and returns false.
 __device__ __forceinline__ bool capped_move(double fx, double fy, double t, double& dx,
                                             double& dy) {
     dx = 0.0;
     dy = 0.0;
     if (!(fabs(fx) <= DBL_MAX) || !(fabs(fy) <= DBL_MAX)) return false;
-    const double norm = sqrt(fx * fx + fy * fy);
-    if (norm > 0.0 && norm <= DBL_MAX) {
+    const double n2 = fx * fx + fy * fy;
+    if (n2 > 0.0 && n2 <= DBL_MAX) {
+        const double norm = sqrt(n2);
         const double len = norm < t ? norm : t;
         dx = fx * (len / norm);
         dy = fy * (len / norm);
     } else if (fx != 0.0 || fy != 0.0) {
-        const double s = fmax(fabs(fx), fabs(fy));
-        const double ux = fx / s, uy = fy / s;
-        const double nu = sqrt(ux * ux + uy * uy);  // in [1, sqrt(2)]
-        // |F| = s nu; s nu > t when the square overflowed, < t when it underflowed
-        const double len = (s > 1.0 ? t : fmin(s * nu, t));
-        dx = ux * (len / nu);
-        dy = uy * (len / nu);
+        int e = 0;
+        (void)frexp(fmax(fabs(fx), fabs(fy)), &e);
+        const double ux = ldexp(fx, -e), uy = ldexp(fy, -e);
+        const double nu = sqrt(ux * ux + uy * uy);  // in [0.5, sqrt(2))
+        const double sc = fmin(ldexp(nu, e), t) / nu;  // |F| = nu 2^e (inf: the cap)
+        dx = ux * sc;
+        dy = uy * sc;
+    }
+    return true;
+}
+
+// The same cap computed in float (FP32 positions), returning the capped
+// length in l.  The common branch's test implies finite components, so the
+// rare branch -- |F|^2 outside float's range, or F not finite -- costs the
+// common case nothing.  A finite F whose square overflows is scaled by 2^-96
+// (exact) first: forces summed from float terms over at most 64 lanes and
+// scaled by d^2 stay below 2^146, so the scaled square is finite.  A finite
+// F whose square underflows (|F| < 2^-63) gives no move: it could not change
+// a float position away from the origin.  Returns false (no move) for a
+// non-finite F.
+__device__ __forceinline__ bool capped_move_f32(double fx, double fy, double t, float& dx,
+                                                float& dy, float& l) {
+    const float fxf = (float)fx, fyf = (float)fy;
+    const float n2 = fmaf(fxf, fxf, fyf * fyf);
+    dx = 0.f;
+    dy = 0.f;
+    l = 0.f;
+    if (n2 > 0.f && n2 <= FLT_MAX) {
+        const float norm = sqrtf(n2);
+        l = fminf(norm, (float)t);
+        const float sc = l * __builtin_amdgcn_rcpf(norm);
+        dx = fxf * sc;
+        dy = fyf * sc;
+    } else if (!(fabs(fx) <= DBL_MAX) || !(fabs(fy) <= DBL_MAX)) {
+        return false;
+    } else if (n2 > 0.f) {
+        const float ux = (float)(fx * 0x1p-96), uy = (float)(fy * 0x1p-96);
+        const float nu = sqrtf(fmaf(ux, ux, uy * uy));
+        l = fminf(nu * 0x1p96f, (float)t);  // |F| = nu 2^96 (inf in float: the cap)
+        const float sc = l * __builtin_amdgcn_rcpf(nu);
+        dx = ux * sc;
+        dy = uy * sc;
     }
     return true;
 }
@@ -330,7 +366,8 @@ __device__ __forceinline__ void finish_vertex(const StepArgs& a, int32_t v, type
     using V = typename P::vec2;
     using R = typename P::real;
     double dx, dy;
-    if (!capped_move(fx, fy, a.t, dx, dy)) {
+    const double t = a.temps ? a.temps[a.ctl->h_base + a.tick_j] : a.t;
+    if (!capped_move(fx, fy, t, dx, dy)) {
         ++nonfinite;
         fx = 0.0;  // keeps the energy statistic finite
         fy = 0.0;

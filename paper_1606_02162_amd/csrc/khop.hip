@@ -401,6 +401,8 @@ void free_khop(gila_khop* kh, Release rel) {
     if (!kh) return;
     DeviceGuard g(kh->device);
     if (kh->gexec) (void)hipGraphExecDestroy(kh->gexec);
+    if (kh->tick_exec) (void)hipGraphExecDestroy(kh->tick_exec);
+    rel(kh->d_temps);
     rel(kh->perm);
     rel(kh->iperm);
     rel(kh->rp);
@@ -584,8 +586,9 @@ int build_khop(const gila_csr* g, int32_t k, hipStream_t s, gila_khop** out) {
         a.work = d_work;
         int rc = run_bfs(false, dev, s, a);
         if (rc == GILA_OK) {
-            hipError_t e = hipMemcpy(counts.data(), d_counts, sizeof(int64_t) * n,
-                                     hipMemcpyDeviceToHost);
+            hipError_t e = hipMemcpyAsync(counts.data(), d_counts, sizeof(int64_t) * n,
+                                          hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
             if (e != hipSuccess) rc = fail(GILA_EDEVICE, "copy counts: %s", hipGetErrorString(e));
         }
         dfree_on(d_counts, s);
@@ -676,7 +679,7 @@ int build_khop(const gila_csr* g, int32_t k, hipStream_t s, gila_khop** out) {
 
     pt.mark("fill");
     // --- plan of the iteration kernel and its workspace
-    GILA_TRY(plan_iteration(kh, cnt_int, rp_int));
+    GILA_TRY(plan_iteration(kh, cnt_int, rp_int, s));
     GILA_TRY(dalloc_t(reinterpret_cast<double**>(&kh->pos[0]), 2 * (size_t)std::max(n, 1)));
     GILA_TRY(dalloc_t(reinterpret_cast<double**>(&kh->pos[1]), 2 * (size_t)std::max(n, 1)));
     GILA_TRY(dalloc_t(&kh->partials, (size_t)std::max(kh->nblocks, 1)));
@@ -832,12 +835,8 @@ int gila_khop_set_mass(gila_khop* kh, const double* mass_dev, void* stream) {
         kh->mass32 = nullptr;
         kh->device_bytes -= 12 * (int64_t)kh->n;
     }
-    // the captured loop holds the previous kernels and arguments
-    if (kh->gexec) {
-        (void)hipGraphExecDestroy(kh->gexec);
-        kh->gexec = nullptr;
-        kh->gkey.clear();
-    }
+    // the captured loops hold the previous kernels and arguments
+    drop_graphs(kh);
     return GILA_OK;
 }
 

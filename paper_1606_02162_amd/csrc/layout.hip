@@ -2,6 +2,7 @@
 // steps captured as a HIP graph, and the whole-layout entry point.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 
 #include "device_util.h"
@@ -281,14 +282,99 @@ int enqueue_run(gila_khop* kh, const gila_params* p, int32_t start_h, int32_t en
     return GILA_OK;
 }
 
+void drop_graphs(gila_khop* kh) {
+    if (kh->gexec) (void)hipGraphExecDestroy(kh->gexec);
+    if (kh->tick_exec) (void)hipGraphExecDestroy(kh->tick_exec);
+    kh->gexec = nullptr;
+    kh->tick_exec = nullptr;
+    kh->gkey.clear();
+    kh->tick_key.clear();
+}
+
+__global__ void set_h_base_kernel(Ctl* ctl, int32_t h) { ctl->h_base = h; }
+
+int enqueue_tick(gila_khop* kh, const gila_params* p, int32_t h, int32_t count,
+                 int32_t graph_len, void* pos_dev, hipStream_t s) {
+    if (count != graph_len || count <= 0 || h < 0 || h + count > p->iterations)
+        return enqueue_run(kh, p, h, h + count, pos_dev, s);
+    // the device copy of the schedule (the same for every tick of a job)
+    const size_t H = (size_t)p->iterations;
+    if (!kh->d_temps || kh->temps_host.size() != H ||
+        std::memcmp(kh->temps_host.data(), p->temperature, H * sizeof(double)) != 0) {
+        drop_graphs(kh);
+        dfree_on(kh->d_temps, s);
+        kh->d_temps = nullptr;
+        kh->temps_host.assign(p->temperature, p->temperature + H);
+        GILA_TRY(dalloc_t(&kh->d_temps, H));
+        GILA_HIP(hipMemcpyAsync(kh->d_temps, kh->temps_host.data(), H * sizeof(double),
+                                hipMemcpyHostToDevice, s));
+    }
+    int32_t att_p = 0, rep_q = 0;
+    force_exponents(p, &att_p, &rep_q);
+    auto bits = [](double x) {
+        uint64_t u;
+        std::memcpy(&u, &x, 8);
+        return u;
+    };
+    const std::vector<uint64_t> key = {(uint64_t)(uintptr_t)pos_dev, (uint64_t)count,
+                                       (uint64_t)p->precision, bits(p->ideal_length),
+                                       bits(p->stop_fraction), bits(p->stop_displacement),
+                                       (uint64_t)(uint32_t)att_p, (uint64_t)(uint32_t)rep_q,
+                                       (uint64_t)segment_ready_for(kh, p->precision),
+                                       (uint64_t)(uintptr_t)kh->d_temps};
+    if (!kh->tick_exec || key != kh->tick_key) {
+        if (kh->tick_exec) (void)hipGraphExecDestroy(kh->tick_exec);
+        kh->tick_exec = nullptr;
+        kh->tick_key.clear();
+        hipStream_t cs = capture_stream(kh->device);
+        (void)hipGetLastError();  // no stale status may fail a check inside the capture
+        if (!cs || hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed) != hipSuccess) {
+            (void)hipGetLastError();
+            return enqueue_run(kh, p, h, h + count, pos_dev, s);
+        }
+        int rc = GILA_OK;
+        hipLaunchKernelGGL(reset_ctl_kernel, dim3(1), dim3(1), 0, cs, kh->ctl);
+        if (hipGetLastError() != hipSuccess) rc = fail(GILA_EDEVICE, "tick capture: reset");
+        if (rc == GILA_OK) rc = launch_permute_in(kh, p->precision, pos_dev, cs);
+        StepArgs a = base_args(kh, p);
+        a.check_stop = p->stop_fraction > 0.0 ? 1 : 0;
+        a.temps = kh->d_temps;
+        for (int32_t j = 0; j < count && rc == GILA_OK; ++j) {
+            a.pos_cur = kh->pos[j & 1];
+            a.pos_next = kh->pos[(j + 1) & 1];
+            a.tick_j = j;
+            rc = launch_iteration(kh, p->precision, a, cs);
+        }
+        if (rc == GILA_OK) rc = launch_permute_out(kh, p->precision, pos_dev, cs);
+        hipGraph_t graph = nullptr;
+        const hipError_t ee = hipStreamEndCapture(cs, &graph);
+        hipError_t ie = hipErrorUnknown;
+        if (rc == GILA_OK && ee == hipSuccess && graph)
+            ie = hipGraphInstantiate(&kh->tick_exec, graph, nullptr, nullptr, 0);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (ie != hipSuccess) {
+            // a capture another thread's call invalidated, or one the runtime
+            // refused: this tick runs eagerly (the same bits); the next tries again
+            if (getenv("GILA_DEBUG"))
+                fprintf(stderr, "[gila] tick capture refused: enqueue %d, end %s, instantiate %s\n",
+                        rc, hipGetErrorString(ee), hipGetErrorString(ie));
+            kh->tick_exec = nullptr;
+            (void)hipGetLastError();
+            clear_error();
+            return enqueue_run(kh, p, h, h + count, pos_dev, s);
+        }
+        kh->tick_key = key;
+    }
+    hipLaunchKernelGGL(set_h_base_kernel, dim3(1), dim3(1), 0, s, kh->ctl, h);
+    GILA_HIP(hipGetLastError());
+    GILA_HIP(hipGraphLaunch(kh->tick_exec, s));
+    return GILA_OK;
+}
+
 int prepare_precision(gila_khop* kh, int precision, hipStream_t s) {
     if (!segment_path_enabled()) return GILA_OK;
     if (segment_ready_for(kh, precision)) return GILA_OK;
-    if (kh->gexec) {
-        (void)hipGraphExecDestroy(kh->gexec);
-        kh->gexec = nullptr;
-        kh->gkey.clear();
-    }
+    drop_graphs(kh);
     const int rc = build_segments(kh, precision, s);
     if (rc == GILA_EUNSUPPORTED) {
         clear_error();
@@ -341,7 +427,8 @@ int run_iterations(gila_khop* kh, const gila_params* p, int32_t start_h, int32_t
             }
             hipStream_t cs = capture_stream(kh->device);
             if (!cs) return fail(GILA_EDEVICE, "cannot create capture stream");
-            GILA_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+            (void)hipGetLastError();  // no stale status may fail a check inside the capture
+            GILA_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
             const int rc = enqueue_run(kh, p, start_h, end_h, pos_dev, cs);
             hipGraph_t graph = nullptr;
             const hipError_t ee = hipStreamEndCapture(cs, &graph);
@@ -505,28 +592,63 @@ int gila_time_iterations(const gila_khop* kh_c, const gila_params* params, int32
     int rc = GILA_OK;
     for (auto& e : ev)
         if (!e) rc = fail(GILA_EDEVICE, "hipEventCreate failed");
+    // the iterations with an event before the force kernel, after it, and
+    // after the rest of the iteration
+    auto enqueue = [&](hipStream_t q) -> int {
+        hipLaunchKernelGGL(reset_ctl_kernel, dim3(1), dim3(1), 0, q, kh->ctl);
+        GILA_HIP(hipGetLastError());
+        GILA_TRY(launch_permute_in(kh, params->precision, pos_dev, q));
+        StepArgs a = base_args(kh, params);
+        for (int32_t r = 0; r < reps; ++r) {
+            a.pos_cur = kh->pos[r & 1];
+            a.pos_next = kh->pos[(r + 1) & 1];
+            a.t = params->temperature[h + r];
+            hipEvent_t* e3 = &ev[(size_t)r * 3];
+            if (seg) {
+                GILA_TRY(launch_segment_step(kh, params->precision, a, q, e3));
+            } else {
+                GILA_HIP(hipEventRecordWithFlags(e3[0], q, hipEventRecordExternal));
+                GILA_TRY(launch_step(kh, params->precision, a, q));
+                GILA_HIP(hipEventRecordWithFlags(e3[1], q, hipEventRecordExternal));
+                GILA_HIP(hipEventRecordWithFlags(e3[2], q, hipEventRecordExternal));
+            }
+        }
+        return launch_permute_out(kh, params->precision, pos_dev, q);
+    };
+    // Preferred: one replay of the captured iterations, timed by the event
+    // nodes inside the graph (the way gila_run executes them).  If capture of
+    // event records is refused, the same launches run eagerly.
+    bool in_graph = false;
     if (rc == GILA_OK) {
-        hipLaunchKernelGGL(reset_ctl_kernel, dim3(1), dim3(1), 0, s, kh->ctl);
-        rc = launch_permute_in(kh, params->precision, pos_dev, s);
-    }
-    StepArgs a = base_args(kh, params);
-    for (int32_t r = 0; r < reps && rc == GILA_OK; ++r) {
-        a.pos_cur = kh->pos[r & 1];
-        a.pos_next = kh->pos[(r + 1) & 1];
-        a.t = params->temperature[h + r];
-        hipEvent_t* e3 = &ev[(size_t)r * 3];
-        if (seg) {
-            rc = launch_segment_step(kh, params->precision, a, s, e3);
+        hipGraphExec_t exec = nullptr;
+        hipStream_t cs = capture_stream(kh->device);
+        (void)hipGetLastError();  // no stale status may fail a check inside the capture
+        hipError_t be = hipErrorUnknown, ee = hipErrorUnknown, ie = hipErrorUnknown;
+        int erc = GILA_EDEVICE;
+        // (thread-local mode: the runtime refuses external event records in a
+        // relaxed capture)
+        if (cs && (be = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal)) == hipSuccess) {
+            erc = enqueue(cs);
+            hipGraph_t graph = nullptr;
+            ee = hipStreamEndCapture(cs, &graph);
+            if (erc == GILA_OK && ee == hipSuccess && graph &&
+                (ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0)) == hipSuccess)
+                in_graph = true;
+            if (graph) (void)hipGraphDestroy(graph);
+        }
+        if (!in_graph && getenv("GILA_DEBUG"))
+            fprintf(stderr, "[gila] timing capture refused: begin %s, enqueue %d (%s), end %s, "
+                            "instantiate %s\n", hipGetErrorString(be), erc, gila_last_error(),
+                    hipGetErrorString(ee), hipGetErrorString(ie));
+        (void)hipGetLastError();
+        clear_error();
+        if (in_graph) {
+            if (hipGraphLaunch(exec, s) != hipSuccess) rc = fail(GILA_EDEVICE, "graph launch");
+            (void)hipGraphExecDestroy(exec);
         } else {
-            if (hipEventRecord(e3[0], s) != hipSuccess) rc = fail(GILA_EDEVICE, "event record");
-            if (rc == GILA_OK) rc = launch_step(kh, params->precision, a, s);
-            if (rc == GILA_OK && hipEventRecord(e3[1], s) != hipSuccess)
-                rc = fail(GILA_EDEVICE, "event record");
-            if (rc == GILA_OK && hipEventRecord(e3[2], s) != hipSuccess)
-                rc = fail(GILA_EDEVICE, "event record");
+            rc = enqueue(s);
         }
     }
-    if (rc == GILA_OK) rc = launch_permute_out(kh, params->precision, pos_dev, s);
     if (rc == GILA_OK && hipStreamSynchronize(s) != hipSuccess)
         rc = fail(GILA_EDEVICE, "stream synchronise failed");
     double f = 0.0, c = 0.0;
@@ -543,6 +665,7 @@ int gila_time_iterations(const gila_khop* kh_c, const gila_params* params, int32
     if (rc == GILA_OK) {
         ms_out[0] = f / reps;
         ms_out[1] = c / reps;
+        ms_out[2] = in_graph ? 1.0 : 0.0;
     }
     return rc;
 }

@@ -921,19 +921,21 @@ int launch_segment_step(const gila_khop* kh, int precision, const StepArgs& a, h
     const size_t lds = seg_lds_bytes(kh, precision, kh->seg);
     const dim3 sg(kh->seg_grid), cg(kh->comb_grid), cb(kBlock);
     const bool big = kh->seg_large;
-    if (ev) GILA_HIP(hipEventRecord(ev[0], s));
+    // external records: under stream capture each becomes an event node that
+    // records when the replay reaches it (a timing point inside the graph)
+    if (ev) GILA_HIP(hipEventRecordWithFlags(ev[0], s, hipEventRecordExternal));
     if (a.mass && big) launch_seg_force_q<true, true>(a.rep_q, precision, sg, lds, s, g);
     else if (a.mass) launch_seg_force_q<true, false>(a.rep_q, precision, sg, lds, s, g);
     else if (big) launch_seg_force_q<false, true>(a.rep_q, precision, sg, lds, s, g);
     else launch_seg_force_q<false, false>(a.rep_q, precision, sg, lds, s, g);
-    if (ev) GILA_HIP(hipEventRecord(ev[1], s));
+    if (ev) GILA_HIP(hipEventRecordWithFlags(ev[1], s, hipEventRecordExternal));
     switch (precision) {
         case GILA_FP64: hipLaunchKernelGGL(seg_combine_kernel<GILA_FP64>, cg, cb, 0, s, c); break;
         case GILA_FP32: hipLaunchKernelGGL(seg_combine_kernel<GILA_FP32>, cg, cb, 0, s, c); break;
         default: hipLaunchKernelGGL(seg_combine_kernel<GILA_FP32_KAHAN>, cg, cb, 0, s, c); break;
     }
     GILA_TRY(launch_iteration_stats(c, s));
-    if (ev) GILA_HIP(hipEventRecord(ev[2], s));
+    if (ev) GILA_HIP(hipEventRecordWithFlags(ev[2], s, hipEventRecordExternal));
     GILA_HIP(hipGetLastError());
     return GILA_OK;
 }

@@ -1,18 +1,22 @@
 // Layout server: continuous batching of layout jobs on one GPU.
 //
 // Jobs (host graph, k, parameters, initial positions) are queued by
-// gila_submit.  Three threads own the device work, each on streams of its own:
+// gila_submit.  Five threads own the device work, each on streams of its own:
 //   admitter  admits queued jobs in arrival order as slots and the HBM budget
 //             allow (footprint bound from the graph).  Jobs small enough for
 //             the LDS-resident batch kernel go to the small-job worker, larger
 //             ones to the builder.
-//   small     lays out all waiting small jobs together in one batched launch.
+//   small     two workers: each lays out the small jobs waiting when it wakes
+//             together in one batched launch, on a stream of its own.
 //   builder   uploads a large job's graph and builds its k-hop lists on its
 //             build stream, then hands the job to the ticker.
 //   ticker    advances every resident large job by `tick_iterations`
-//             iterations per tick on the compute streams, waits for the tick,
-//             and retires jobs that finished (all iterations, or the halting
-//             rule).  Builds and batched launches overlap with the ticks.
+//             iterations per tick on the compute streams -- a replay of the
+//             job's captured tick graph, whose caps are read from the device
+//             copy of its schedule -- copies each job's control block to a
+//             pinned host slot, waits for the tick, and retires jobs that
+//             finished (all iterations, or the halting rule).  Builds and
+//             batched launches overlap with the ticks.
 // A job's arithmetic depends only on its own graph and parameters (the
 // iteration plan is per graph; ticks split a run without changing its bits),
 // so each result is the same alone and in any mix of concurrent jobs.
@@ -20,6 +24,7 @@
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <deque>
@@ -56,6 +61,9 @@ struct Job {
     int32_t h = 0;
     int32_t h_target = 0;
     int lane = 0;  // which compute stream the job's ticks run on
+    int32_t slot = -1;  // its pinned host control-block slot (and event) while resident
+    bool in_tick = false;  // a tick is queued and its event not yet seen
+    char msg[256] = {0};  // why it failed (the failing thread's last error)
     gila_stats stats{};
     double t_submit = 0.0, t_admit = 0.0, t_done = 0.0;
 };
@@ -99,7 +107,7 @@ struct gila_server {
     int64_t budget = 0;
     int32_t max_slots = 1;
     int32_t tick_iters = 50;
-    int32_t small_max_n = 2048;      // 0 = the most that fits the batch kernel's LDS
+    int32_t small_max_n = 1024;      // 0 = the most that fits the batch kernel's LDS
     std::atomic<uint64_t> fail_alloc_ticket{0};  // test hook: this job's allocation fails
     std::mutex mu;
     std::condition_variable cv;        // wakes the admitter
@@ -118,11 +126,17 @@ struct gila_server {
     int64_t reserved = 0;
     int32_t in_flight = 0;
     bool stop = false;
-    std::thread th_admit, th_small, th_build, th_tick;
+    std::thread th_admit, th_build, th_tick;
+    static constexpr int kSmallWorkers = 2;
+    std::thread th_small[kSmallWorkers];
     static constexpr int kComputeStreams = 3;
     hipStream_t compute[kComputeStreams] = {nullptr, nullptr, nullptr};
     hipStream_t build = nullptr;
-    hipStream_t small = nullptr;
+    hipStream_t small[kSmallWorkers] = {nullptr, nullptr};
+    gila::Ctl* host_ctl = nullptr;      // pinned, [max_slots]: resident jobs' control blocks
+    std::vector<hipEvent_t> slot_ev;    // [max_slots]: end of each resident job's tick
+    std::vector<int32_t> free_slots;
+    hipStream_t download = nullptr;     // final positions of large jobs
     int64_t jobs_done = 0, ticks = 0;
     int32_t peak_resident = 0;
 };
@@ -147,6 +161,7 @@ static void release_device(Job* j, hipStream_t st) {
 static void finish_job(gila_server* s, Job* j, int state, int status) {
     j->state = state;
     j->status = status;
+    if (state == kFailed) std::snprintf(j->msg, sizeof(j->msg), "%s", gila_last_error());
     j->t_done = now_s();
     s->reserved -= j->footprint;
     s->in_flight -= 1;
@@ -200,7 +215,7 @@ static int download_positions(Job* j, hipStream_t st) {
 // Lays out a group of small jobs of one precision in one batched launch.
 // The group's graphs and positions travel in one device allocation and one
 // copy each way.
-static void run_small_group(gila_server* s, std::vector<Job*>& group) {
+static void run_small_group(gila_server* s, std::vector<Job*>& group, hipStream_t sst) {
     std::vector<Job*> ok;
     for (Job* j : group) {
         if (s->fail_alloc_ticket == j->id) {
@@ -244,15 +259,15 @@ static void run_small_group(gila_server* s, std::vector<Job*>& group) {
     int rc = dalloc(&arena, bytes);
     char* base = static_cast<char*>(arena);
     if (rc == GILA_OK && hipMemcpyAsync(base, h_rp.data(), nrp * 8, hipMemcpyHostToDevice,
-                                        s->small) != hipSuccess)
+                                        sst) != hipSuccess)
         rc = fail(GILA_EDEVICE, "upload");
     if (rc == GILA_OK && nci > 0 &&
-        hipMemcpyAsync(base + brp, h_ci.data(), nci * 4, hipMemcpyHostToDevice, s->small) !=
+        hipMemcpyAsync(base + brp, h_ci.data(), nci * 4, hipMemcpyHostToDevice, sst) !=
             hipSuccess)
         rc = fail(GILA_EDEVICE, "upload");
     if (rc == GILA_OK && npos > 0 &&
         hipMemcpyAsync(base + brp + bci, h_pos.data(), npos * pb, hipMemcpyHostToDevice,
-                       s->small) != hipSuccess)
+                       sst) != hipSuccess)
         rc = fail(GILA_EDEVICE, "upload");
     std::vector<gila_csr> csr(ok.size());
     std::vector<int32_t> ks(ok.size());
@@ -271,9 +286,9 @@ static void run_small_group(gila_server* s, std::vector<Job*>& group) {
     auto run_range = [&](size_t lo, size_t hi) {
         gila_batch* b = nullptr;
         const int32_t cnt = (int32_t)(hi - lo);
-        int r = batch_build(&csr[lo], cnt, &ks[lo], s->small, &b);
-        if (r == GILA_OK) r = batch_run(b, &ps[lo], &pos[lo], s->small, &st[lo], false);
-        if (b) free_batch(b, Release{true, s->small});
+        int r = batch_build(&csr[lo], cnt, &ks[lo], sst, &b);
+        if (r == GILA_OK) r = batch_run(b, &ps[lo], &pos[lo], sst, &st[lo], false);
+        if (b) free_batch(b, Release{true, sst});
         for (size_t i = lo; i < hi; ++i) rcs[i] = r;
         return r;
     };
@@ -283,10 +298,10 @@ static void run_small_group(gila_server* s, std::vector<Job*>& group) {
         for (size_t i = 0; i < ok.size(); ++i) run_range(i, i + 1);
     if (rc == GILA_OK && npos > 0 &&
         (hipMemcpyAsync(h_pos.data(), base + brp + bci, npos * pb, hipMemcpyDeviceToHost,
-                        s->small) != hipSuccess ||
-         hipStreamSynchronize(s->small) != hipSuccess))
+                        sst) != hipSuccess ||
+         hipStreamSynchronize(sst) != hipSuccess))
         for (auto& r : rcs) r = GILA_EDEVICE;
-    dfree_on(arena, s->small);
+    dfree_on(arena, sst);
     for (size_t i = 0; i < ok.size(); ++i) {
         Job* j = ok[i];
         const int r = rcs[i];
@@ -409,9 +424,11 @@ static void builder(gila_server* s) {
     }
 }
 
-// Small-job worker: lays out everything admitted so far in batched launches
-// (one per precision).
-static void small_worker(gila_server* s) {
+// Small-job workers (kSmallWorkers, each with a stream of its own): a worker
+// lays out everything admitted so far in batched launches (one per
+// precision); jobs admitted while it runs go to the other worker, so they do
+// not wait for that group to finish.
+static void small_worker(gila_server* s, int w) {
     (void)hipSetDevice(s->device);
     for (;;) {
         std::vector<Job*> take;
@@ -423,56 +440,59 @@ static void small_worker(gila_server* s) {
         }
         std::map<int, std::vector<Job*>> groups;
         for (Job* j : take) groups[j->params.precision].push_back(j);
-        for (auto& kv : groups) run_small_group(s, kv.second);
+        for (auto& kv : groups) run_small_group(s, kv.second, s->small[w]);
     }
 }
 
-// Ticker: advances every resident large job by one tick per loop.
+// Ticker: keeps every resident large job advancing.  A job's tick -- a replay
+// of its tick graph, then its control block into its pinned slot -- is
+// followed by an event on its compute stream; as soon as that event has
+// completed the job is retired or given its next tick, whatever the other
+// jobs are doing (a job waits only for the work queued before it on the
+// stream it shares).  Final positions are copied on a stream of their own, so
+// they do not queue behind other jobs' ticks.
 static void ticker(gila_server* s) {
     (void)hipSetDevice(s->device);
-    constexpr int NC = gila_server::kComputeStreams;
-    hipEvent_t tick_done[NC] = {nullptr, nullptr, nullptr};
-    for (int c = 0; c < NC; ++c) (void)hipEventCreateWithFlags(&tick_done[c], hipEventDisableTiming);
+    std::vector<Job*> mine;  // resident jobs, owned by this thread
     for (;;) {
-        std::vector<Job*> active;
         int32_t tick_iters = 1;
         {
             std::unique_lock<std::mutex> lk(s->mu);
-            s->cv_tick.wait(lk, [&] { return s->stop || !s->ready.empty() || !s->resident.empty(); });
+            if (mine.empty())
+                s->cv_tick.wait(lk, [&] { return s->stop || !s->ready.empty(); });
+            else
+                s->cv_tick.wait_for(lk, std::chrono::microseconds(20),
+                                    [&] { return s->stop || !s->ready.empty(); });
             if (s->stop) break;
-            s->resident.insert(s->resident.end(), s->ready.begin(), s->ready.end());
+            for (Job* j : s->ready) {  // at most max_slots jobs are in flight
+                j->slot = s->free_slots.back();
+                s->free_slots.pop_back();
+                j->in_tick = false;
+                mine.push_back(j);
+            }
             s->ready.clear();
-            s->peak_resident = std::max<int32_t>(s->peak_resident, (int32_t)s->resident.size());
-            active = s->resident;
+            s->resident = mine;
+            s->peak_resident = std::max<int32_t>(s->peak_resident, (int32_t)mine.size());
             tick_iters = s->tick_iters;
         }
-        // the next iterations of every resident job, asynchronously
-        std::vector<int> enq_rc(active.size(), GILA_OK);
-        for (size_t i = 0; i < active.size(); ++i) {
-            Job* j = active[i];
-            if (j->cancel) continue;
-            j->h_target = std::min(j->h + tick_iters, j->params.iterations);
-            enq_rc[i] = enqueue_run(j->kh, &j->params, j->h, j->h_target, j->d_pos,
-                                    s->compute[j->lane]);
-        }
-        for (int c = 0; c < NC; ++c) (void)hipEventRecord(tick_done[c], s->compute[c]);
-        hipError_t we = hipSuccess;
-        for (int c = 0; c < NC; ++c) {
-            const hipError_t e = hipEventSynchronize(tick_done[c]);
-            if (e != hipSuccess) we = e;
-        }
-        // retire finished jobs
         std::vector<Job*> keep;
-        for (size_t i = 0; i < active.size(); ++i) {
-            Job* j = active[i];
-            int rc = we == hipSuccess ? enq_rc[i] : GILA_EDEVICE;
-            bool finished = j->cancel || rc != GILA_OK;
-            if (!finished) {
-                Ctl c{};
-                if (hipMemcpy(&c, j->kh->ctl, sizeof(Ctl), hipMemcpyDeviceToHost) != hipSuccess) {
-                    rc = GILA_EDEVICE;
+        int64_t ticks = 0;
+        for (Job* j : mine) {
+            int rc = GILA_OK;
+            bool finished = false;
+            if (j->in_tick) {
+                const hipError_t q = hipEventQuery(s->slot_ev[j->slot]);
+                if (q == hipErrorNotReady) {
+                    (void)hipGetLastError();  // pending work, not an error
+                    keep.push_back(j);
+                    continue;
+                }
+                j->in_tick = false;
+                if (q != hipSuccess) {
+                    rc = fail(GILA_EDEVICE, "tick failed: %s", hipGetErrorString(q));
                     finished = true;
                 } else {
+                    const Ctl c = s->host_ctl[j->slot];  // copied at the end of the tick
                     j->stats.iterations_run += j->h_target > j->h ? c.iters_run : 0;
                     j->stats.stopped = c.stopped == 1 ? 1 : 0;
                     if (j->h_target > j->h) {
@@ -485,23 +505,42 @@ static void ticker(gila_server* s) {
                     j->h = j->h_target;
                     finished = c.stopped || j->h >= j->params.iterations;
                     if (finished) rc = nonfinite_status(c);
-                    if (finished && rc == GILA_OK) rc = download_positions(j, s->compute[j->lane]);
+                    if (finished && rc == GILA_OK) rc = download_positions(j, s->download);
                 }
             }
+            if (!finished && j->cancel) finished = true;  // between ticks only
             if (!finished) {
-                keep.push_back(j);
-                continue;
+                // the next tick, asynchronously
+                j->h_target = std::min(j->h + tick_iters, j->params.iterations);
+                hipStream_t st = s->compute[j->lane];
+                rc = enqueue_tick(j->kh, &j->params, j->h, j->h_target - j->h, tick_iters,
+                                  j->d_pos, st);
+                if (rc == GILA_OK && hipMemcpyAsync(&s->host_ctl[j->slot], j->kh->ctl, sizeof(Ctl),
+                                                    hipMemcpyDeviceToHost, st) != hipSuccess)
+                    rc = fail(GILA_EDEVICE, "control block copy failed");
+                if (rc == GILA_OK && hipEventRecord(s->slot_ev[j->slot], st) != hipSuccess)
+                    rc = fail(GILA_EDEVICE, "tick event record failed");
+                if (rc == GILA_OK) {
+                    j->in_tick = true;
+                    ++ticks;
+                    keep.push_back(j);
+                    continue;
+                }
+                // a job whose tick could not be queued waits for what it queued
+                (void)hipStreamSynchronize(st);
             }
             release_device(j, s->compute[j->lane]);
             std::lock_guard<std::mutex> lk(s->mu);
+            s->free_slots.push_back(j->slot);
+            j->slot = -1;
             finish_job(s, j, j->cancel ? kCanceled : (rc == GILA_OK ? kDone : kFailed),
                        j->cancel ? GILA_ECANCELED : rc);
         }
+        mine.swap(keep);
         std::lock_guard<std::mutex> lk(s->mu);
-        s->resident = keep;
-        s->ticks += 1;
+        s->resident = mine;
+        s->ticks += ticks;
     }
-    for (int c = 0; c < NC; ++c) (void)hipEventDestroy(tick_done[c]);
 }
 
 // Cheap host checks at submission (every index in range, so the footprint
@@ -551,20 +590,36 @@ int gila_server_create(int32_t device, int64_t hbm_budget_bytes, int32_t max_slo
         hbm_budget_bytes = (int64_t)(0.9 * (double)fr);
     }
     s->budget = hbm_budget_bytes;
+    if (hipHostMalloc((void**)&s->host_ctl, sizeof(Ctl) * (size_t)max_slots,
+                      hipHostMallocDefault) != hipSuccess) {
+        delete s;
+        return fail(GILA_ENOMEM, "pinned control blocks");
+    }
+    for (int32_t i = max_slots - 1; i >= 0; --i) s->free_slots.push_back(i);
+    s->slot_ev.assign((size_t)max_slots, nullptr);
     bool ok = hipStreamCreateWithFlags(&s->build, hipStreamNonBlocking) == hipSuccess &&
-              hipStreamCreateWithFlags(&s->small, hipStreamNonBlocking) == hipSuccess;
+              hipStreamCreateWithFlags(&s->small[0], hipStreamNonBlocking) == hipSuccess &&
+              hipStreamCreateWithFlags(&s->small[1], hipStreamNonBlocking) == hipSuccess &&
+              hipStreamCreateWithFlags(&s->download, hipStreamNonBlocking) == hipSuccess;
+    for (auto& e : s->slot_ev)
+        ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
     for (int c = 0; c < gila_server::kComputeStreams && ok; ++c)
         ok = hipStreamCreateWithFlags(&s->compute[c], hipStreamNonBlocking) == hipSuccess;
     if (!ok) {
         for (int c = 0; c < gila_server::kComputeStreams; ++c)
             if (s->compute[c]) (void)hipStreamDestroy(s->compute[c]);
         if (s->build) (void)hipStreamDestroy(s->build);
-        if (s->small) (void)hipStreamDestroy(s->small);
+        for (auto& q : s->small)
+            if (q) (void)hipStreamDestroy(q);
+        if (s->download) (void)hipStreamDestroy(s->download);
+        for (auto& e : s->slot_ev)
+            if (e) (void)hipEventDestroy(e);
+        (void)hipHostFree(s->host_ctl);
         delete s;
-        return fail(GILA_EDEVICE, "cannot create streams");
+        return fail(GILA_EDEVICE, "cannot create streams or events");
     }
     s->th_admit = std::thread(admitter, s);
-    s->th_small = std::thread(small_worker, s);
+    for (int w = 0; w < gila_server::kSmallWorkers; ++w) s->th_small[w] = std::thread(small_worker, s, w);
     s->th_build = std::thread(builder, s);
     s->th_tick = std::thread(ticker, s);
     *out = s;
@@ -632,6 +687,8 @@ int gila_submit(gila_server* s, const gila_csr* g_host, int32_t k, const gila_pa
 static int take_result(gila_server* s, Job* j, double* out_pos, gila_stats* out) {
     // mutex held
     const int state = j->state, status = j->status;
+    char msg[sizeof(j->msg)];
+    std::memcpy(msg, j->msg, sizeof(msg));
     if (state == kDone) {
         if (out_pos && j->n > 0) std::memcpy(out_pos, j->result.data(), sizeof(double) * 2 * j->n);
         if (out) *out = j->stats;
@@ -642,7 +699,7 @@ static int take_result(gila_server* s, Job* j, double* out_pos, gila_stats* out)
     s->cv_done.notify_all();
     if (state == kDone) return GILA_OK;
     if (state == kCanceled) return fail(GILA_ECANCELED, "job was cancelled");
-    return fail(status, "job failed: %s", gila_strerror(status));
+    return fail(status, "job failed: %s (%s)", gila_strerror(status), msg);
 }
 
 int gila_poll(gila_server* s, uint64_t ticket, double* out_pos_host, gila_stats* out) {
@@ -723,19 +780,24 @@ void gila_server_destroy(gila_server* s) {
     s->cv_build.notify_all();
     s->cv_tick.notify_all();
     if (s->th_admit.joinable()) s->th_admit.join();
-    if (s->th_small.joinable()) s->th_small.join();
+    for (auto& t : s->th_small)
+        if (t.joinable()) t.join();
     if (s->th_build.joinable()) s->th_build.join();
     if (s->th_tick.joinable()) s->th_tick.join();
     DeviceGuard dg(s->device);
     for (int c = 0; c < gila_server::kComputeStreams; ++c) (void)hipStreamSynchronize(s->compute[c]);
     (void)hipStreamSynchronize(s->build);
-    (void)hipStreamSynchronize(s->small);
+    for (auto& q : s->small) (void)hipStreamSynchronize(q);
+    (void)hipStreamSynchronize(s->download);
     for (Job* j : s->resident) release_device(j, s->build);
     for (Job* j : s->ready) release_device(j, s->build);
     for (auto& kv : s->jobs) delete kv.second;
     for (int c = 0; c < gila_server::kComputeStreams; ++c) (void)hipStreamDestroy(s->compute[c]);
     (void)hipStreamDestroy(s->build);
-    (void)hipStreamDestroy(s->small);
+    for (auto& q : s->small) (void)hipStreamDestroy(q);
+    (void)hipStreamDestroy(s->download);
+    for (auto& e : s->slot_ev) (void)hipEventDestroy(e);
+    (void)hipHostFree(s->host_ctl);
     delete s;
 }
 

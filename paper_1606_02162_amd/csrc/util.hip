@@ -165,7 +165,15 @@ size_t size_class(size_t b) {
     return r;
 }
 
-bool block_ready(const CachedBlock& c) { return !c.ev || hipEventQuery(c.ev) == hipSuccess; }
+// hipEventQuery reports pending work as hipErrorNotReady, which HIP also keeps
+// as the thread's last error: it is taken back here, so that the next launch
+// check does not report it.
+bool block_ready(const CachedBlock& c) {
+    if (!c.ev) return true;
+    const hipError_t q = hipEventQuery(c.ev);
+    if (q == hipErrorNotReady) (void)hipGetLastError();
+    return q == hipSuccess;
+}
 
 // Returns ready cached blocks to the device until at most `keep` bytes stay
 // cached (all ready blocks for keep = 0).  Lock held.

@@ -149,6 +149,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "gila_batch_free": (None, [vp]),
         "gila_batch_latency": (ctypes.c_int, [vp, vp]),
         "gila_batch_export": (ctypes.c_int, [vp, i32, vp, vp]),
+        "gila_batch_plan": (ctypes.c_int, [vp, vp, vp]),
+        "gila_batch_set_plan": (ctypes.c_int, [vp, vp]),
+        "gila_batch_tune": (ctypes.c_int, [vp, i32, vp, vp]),
         "gila_layout_batch": (ctypes.c_int, [vp, i32, vp, vp, vp, vp, vp]),
         "gila_server_create": (ctypes.c_int, [i32, i64, i32, P(vp)]),
         "gila_server_config": (ctypes.c_int, [vp, ctypes.c_char_p, i64]),
@@ -378,13 +381,18 @@ def run(kh: KHop, params: LayoutParams, pos, start_h: int = 0, end_h: int | None
 
 
 def time_iterations(kh: KHop, params: LayoutParams, pos, h: int = 0, reps: int = 10,
-                    stream=None) -> tuple[float, float]:
-    """Average (force kernel, combine kernel) milliseconds over `reps` eager
-    iterations starting at h, timed with HIP events on the launch stream."""
-    ms = (ctypes.c_double * 2)()
+                    stream=None, with_mode: bool = False):
+    """Average (force kernel, rest of the iteration) milliseconds over `reps`
+    iterations starting at h, timed by HIP events inside one replay of the
+    captured iterations (gila_time_iterations).  With ``with_mode`` a third
+    value tells whether the times come from a graph replay (True) or, when
+    capture was refused, from eager launches (False)."""
+    ms = (ctypes.c_double * 3)()
     p = params.as_struct()
     _check(_lib.gila_time_iterations(kh.handle, ctypes.byref(p), int(h), int(reps), _ptr(pos),
                                      _stream(stream), ms), "gila_time_iterations")
+    if with_mode:
+        return float(ms[0]), float(ms[1]), bool(ms[2] == 1.0)
     return float(ms[0]), float(ms[1])
 
 
@@ -619,6 +627,30 @@ class Batch:
         _check(_lib.gila_batch_export(self._h, graph, ptr.ctypes.data, idx.ctypes.data),
                "gila_batch_export")
         return ptr, idx[: int(ptr[-1])]
+
+    def plan(self):
+        """(lanes per vertex, row-length class) of every graph: gila_batch_plan."""
+        lanes = np.zeros(max(self.count, 1), dtype=np.int32)
+        cls = np.zeros(max(self.count, 1), dtype=np.int32)
+        _check(_lib.gila_batch_plan(self._h, lanes.ctypes.data, cls.ctypes.data),
+               "gila_batch_plan")
+        return lanes[: self.count], cls[: self.count]
+
+    def set_plan(self, lanes):
+        """gila_batch_set_plan: lanes per vertex of every graph."""
+        arr = np.ascontiguousarray(lanes, dtype=np.int32)
+        if arr.size != self.count:
+            raise ValueError("one lanes-per-vertex value per graph")
+        _check(_lib.gila_batch_set_plan(self._h, arr.ctypes.data if arr.size else None),
+               "gila_batch_set_plan")
+
+    def tune(self, precision: int, stream=None) -> np.ndarray:
+        """gila_batch_tune: times the choices per row-length class, sets the
+        fastest in the plan; returns the table (8 classes, 0 = absent)."""
+        table = np.zeros(8, dtype=np.int32)
+        _check(_lib.gila_batch_tune(self._h, int(precision), _stream(stream), table.ctypes.data),
+               "gila_batch_tune")
+        return table
 
     def latency_ms(self) -> np.ndarray:
         """Per-graph completion time (ms) of the last run, from its first start."""

@@ -220,3 +220,62 @@ def test_batch_edge_cases(G):
     with pytest.raises(G.GilaError):
         b.run([p, G.LayoutParams(temperature=np.ones(3), ideal_length=4.0, precision=G.FP32)],
               pos)
+
+
+def test_plan_is_fixed_at_build_and_reproducible(G):
+    """Each graph's lanes per vertex (its summation order, hence its bits) is
+    fixed at build from its mean row length -- the same for the same graph in
+    any batch or process -- and a tuned plan read back and set on a fresh
+    handle reproduces the tuned run's bits without tuning again."""
+    import torch
+    gs = _mixed_graphs(48, 13)
+    dev = [G.to_device_csr(g) for g, _ in gs]
+    ks = [k for _, k in gs]
+    H = 6
+    temps = [G.paper_schedule(max(g.n, 1), 1.0, 40.0, H) for g, _ in gs]
+    params = [G.LayoutParams(temperature=t, ideal_length=40.0, precision=G.FP32_KAHAN)
+              for t in temps]
+    x0 = [inputs.uniform_positions(g.n, seed=i, width=900.0) for i, (g, _) in enumerate(gs)]
+
+    def run(b):
+        pos = [_t(G, x, G.FP32_KAHAN) for x in x0]
+        b.run(params, pos)
+        return [p.cpu() for p in pos]
+
+    b1 = G.Batch(dev, ks)
+    lanes1, cls1 = b1.plan()
+    # the rule: about eight entries per lane for the class's upper mean length
+    for lanes, c in zip(lanes1, cls1):
+        want = 1
+        while want < 64 and want * 8 < (4 << int(c)):
+            want *= 2
+        assert lanes == want
+    a = run(b1)
+    # a graph's plan does not depend on its batch: every 3rd graph alone
+    sub = list(range(0, len(gs), 3))
+    b2 = G.Batch([dev[i] for i in sub], [ks[i] for i in sub])
+    assert np.array_equal(b2.plan()[0], lanes1[sub])
+    b2.free()
+    # tuned plan, read back, set on a new handle: the same bits
+    table = b1.tune(G.FP32_KAHAN)
+    assert table.shape == (8,) and all(v == 0 or v in (1, 2, 4, 8, 16, 32, 64) for v in table)
+    lanes_t, _ = b1.plan()
+    assert all(table[c] == l for l, c in zip(lanes_t, cls1))
+    tuned = run(b1)
+    b3 = G.Batch(dev, ks)
+    assert np.array_equal(b3.plan()[0], lanes1)        # a fresh handle starts from the rule
+    b3.set_plan(lanes_t)
+    again = run(b3)
+    for x, y in zip(tuned, again):
+        assert torch.equal(x, y)
+    # and the rule's plan set back gives the first run's bits
+    b3.set_plan(lanes1)
+    for x, y in zip(a, run(b3)):
+        assert torch.equal(x, y)
+    with pytest.raises(G.GilaError) as e:
+        b3.set_plan(np.full(len(gs), 3))
+    assert e.value.code == G.GILA_EINVAL
+    with pytest.raises(G.GilaError):
+        b3.set_plan(np.full(len(gs), 128))
+    b1.free()
+    b3.free()
