@@ -48,6 +48,7 @@ def _cpu_model() -> str:
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_seg_force_rmat18.json")
 TRAFFIC_FILE_PRUNED = os.path.join(ROOT, "profiles", "traffic_seg_force_weighted_rmat18_pruned.json")
 TRAFFIC_FILE_METRICS = os.path.join(ROOT, "profiles", "traffic_crossings_rmat18_layout.json")
+TRAFFIC_FILE_BATCH = os.path.join(ROOT, "profiles", "traffic_batch_layout_batch4096.json")
 KERNEL_SOURCES = ["paper_1606_02162_amd/csrc/segment.hip", "paper_1606_02162_amd/csrc/iteration.h",
                   "paper_1606_02162_amd/csrc/gila_internal.h"]
 
@@ -144,6 +145,12 @@ def main() -> int:
                     help="force model of the single-graph workloads: fr (p = 2, q = 1), linlog "
                          "(p = 0, q = 1) or explicit exponents 'p,q'")
     ap.add_argument("--batch-count", type=int, default=4096)
+    ap.add_argument("--no-batched", action="store_true",
+                    help="default line without its batched (4096-graph) object")
+    ap.add_argument("--no-served", action="store_true",
+                    help="default line without its served (Poisson stream) object")
+    ap.add_argument("--parity-samples", type=int, default=10000,
+                    help="vertices sampled for the default line's parity object (0: none)")
     ap.add_argument("--serve-jobs", type=int, default=2000)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -246,7 +253,8 @@ def bench_single(args, wl) -> int:
     # --- build time and iteration time, HIP events on the launch stream
     kh = gila.build_khop(rp, ci, k)
     pos.copy_(pos0)
-    force_ms, combine_ms = gila.time_iterations(kh, params, pos, 0, min(50, H))
+    force_ms, combine_ms, timed_in_graph = gila.time_iterations(kh, params, pos, 0, min(50, H),
+                                                                with_mode=True)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
     pos.copy_(pos0)
     gila.run(kh, params, pos)                  # instantiate the graph for this buffer
@@ -302,14 +310,22 @@ def bench_single(args, wl) -> int:
                      "algorithmic_bytes_per_launch": kern_bytes,
                      "copy_GBps": copy_gbs, "frac_of_copy": achieved / copy_gbs},
         "iteration": {"ms": iter_ms, "force_kernel_ms": force_ms,
-                      "combine_kernel_ms": combine_ms,
+                      "combine_and_stats_ms": combine_ms,
+                      "kernel_timing": ("HIP event nodes inside one replay of 50 captured "
+                                        "iterations; force + rest = that replay's iteration "
+                                        f"time, {force_ms + combine_ms:.4f} ms"
+                                        if timed_in_graph else
+                                        "HIP events around eager launches of 50 iterations"),
                       "algorithmic_bytes": alg_bytes,
                       "achieved_GBps": alg_bytes / (iter_ms * 1e-3) / 1e9},
     }
 
     if not args.no_cpu_baseline:
+        # the oracle leg: the only place the benchmark calls the oracle
         import oracle
         threads = oracle.num_threads()
+        if args.workload == "rmat" and mname == "fr" and args.parity_samples > 0:
+            out["parity"] = parity_leg(args, g, k, d, temps, kh, pos0, oracle)
         tc0 = time.perf_counter()
         optr, oidx = oracle.khop(g.n, g.row_ptr, g.col_idx, k)
         tc1 = time.perf_counter()
@@ -337,8 +353,86 @@ def bench_single(args, wl) -> int:
                        f"{single_iter * 1e3:.0f} ms"),
             "single_core_iteration_value": inter_per_iter / single_iter,
         }
+    kh.free()
+    if args.workload == "rmat" and mname == "fr":
+        if not args.no_batched:
+            print("[bench] batched form", file=sys.stderr, flush=True)
+            out["batched"] = batched_leg(args, args.steps, args.warmup)
+        if not args.no_served:
+            print("[bench] served form", file=sys.stderr, flush=True)
+            from paper_1606_02162_amd import serving_bench
+            out["served"] = serving_bench.measure(args)
     print(json.dumps(out))
     return 0
+
+
+def parity_leg(args, g, k, d, temps, kh, pos0, oracle) -> dict:
+    """Per-step error of the benchmark's GPU trajectory against the FP64 oracle
+    (part of the oracle leg).  The GPU runs the benchmark's iterations; at
+    h in {0, H/10, H/4, H/2, 3H/4, H-1} one step is taken with its force and
+    displacement outputs, and the oracle recomputes that step from the same
+    positions for a sample of non-isolated vertices (uniform, plus the 16
+    largest degrees): F_v, S_v (sum of the term magnitudes), Delta_v
+    (Section 3.1 cap) and x_v + Delta_v.  Reported per checkpoint:
+    e_F = ||F_gpu - F_orc|| / ||F_orc|| and e_D (the same for Delta) over the
+    sample, e_x = max |x_gpu - x_orc| / extent of the step's output
+    positions, max_v |F_gpu - F_orc| / S_v, and kappa_v = S_v / |F_orc,v|
+    (p50 / p99 / max).  Plain FP32 is run beside FP32 + Kahan."""
+    import torch
+
+    from paper_1606_02162_amd import gila
+
+    H = len(temps)
+    checks = sorted({0, H // 10, H // 4, H // 2, 3 * H // 4, H - 1})
+    deg = np.diff(g.row_ptr)
+    active = np.nonzero(deg > 0)[0]
+    rng = np.random.default_rng(17)
+    take = min(args.parity_samples, active.size)
+    sample = np.unique(np.concatenate([rng.choice(active, take, replace=False),
+                                       np.argsort(-deg)[:16]])).astype(np.int32)
+    t0 = time.perf_counter()
+    sp, si = oracle.khop(g.n, g.row_ptr, g.col_idx, k, verts=sample)
+    res = {"config": "the benchmark graph and schedule (R-MAT 18, k = 2, 500 iterations), "
+                     "initial positions as timed",
+           "sample_vertices": int(sample.size), "sample_pairs": int(sp[-1]),
+           "checkpoints": checks, "gates": {"e_F": 1e-5, "e_x": 1e-5}}
+    for name, prec in (("fp32_kahan", gila.FP32_KAHAN), ("fp32", gila.FP32)):
+        params = gila.LayoutParams(temperature=temps, ideal_length=d, precision=prec)
+        pos = pos0.clone()
+        F = torch.zeros((g.n, 2), dtype=torch.float64, device=pos.device)
+        D = torch.zeros_like(F)
+        done, rows = 0, {}
+        for h in checks:
+            if h > done:
+                gila.run(kh, params, pos, done, h)
+            x = pos.double().cpu().numpy()
+            gila.step(kh, params, h, pos, F, D)
+            xn = pos.double().cpu().numpy()
+            done = h + 1
+            Fg, Dg = F.cpu().numpy()[sample], D.cpu().numpy()[sample]
+            Fo, _ = oracle.forces(g.n, g.row_ptr, g.col_idx, sp, si, d, x, verts=sample)
+            So = oracle.force_magnitudes(g.n, g.row_ptr, g.col_idx, sp, si, d, x, verts=sample)
+            Do = oracle.cap(Fo, float(temps[h]))
+            xo = x[sample] + Do
+            ext = max(float(np.ptp(xn[:, 0])), float(np.ptp(xn[:, 1])))
+            nF = np.hypot(Fo[:, 0], Fo[:, 1])
+            live = nF > 0
+            kappa = So[live] / nF[live]
+            dF = np.hypot(Fg[:, 0] - Fo[:, 0], Fg[:, 1] - Fo[:, 1])
+            rows[str(h)] = {
+                "e_F": float(np.linalg.norm(Fg - Fo) / np.linalg.norm(Fo)),
+                "e_x": float(np.hypot(*(xn[sample] - xo).T).max() / ext),
+                "e_D": float(np.linalg.norm(Dg - Do) / max(np.linalg.norm(Do), 1e-300)),
+                "max_dF_over_S": float((dF[So > 0] / So[So > 0]).max()),
+                "kappa": {"p50": float(np.percentile(kappa, 50)),
+                          "p99": float(np.percentile(kappa, 99)), "max": float(kappa.max())},
+                "cap": float(temps[h])}
+        worst = {key: max(r[key] for r in rows.values()) for key in ("e_F", "e_x", "e_D",
+                                                                    "max_dF_over_S")}
+        res[name] = {"steps": rows, "worst": worst,
+                     "gates_met": worst["e_F"] <= 1e-5 and worst["e_x"] <= 1e-5}
+    res["oracle_s"] = time.perf_counter() - t0
+    return res
 
 
 def bench_pruned(args, wl) -> int:
@@ -703,12 +797,13 @@ def _percentiles(x):
     return float(np.percentile(x, 50)), float(np.percentile(x, 99))
 
 
-def bench_batch(args) -> int:
-    """4096 connected graphs (random recursive tree + 0.5n extra edges, n
-    log-uniform in [50, 5000]), k = 3, FP32, 200 iterations each, in one
-    persistent launch.  A step is build + run of the whole batch.  The same
-    graphs through the plain per-graph solver (gila_layout one after another)
-    are timed on a sample of every 16th graph and scaled by pair count."""
+def batched_leg(args, steps: int, warmup: int) -> dict:
+    """Many graphs in one persistent launch: 4096 connected graphs (random
+    recursive tree + 0.5n extra edges, n log-uniform in [50, 5000]), k = 3,
+    FP32, 200 iterations each.  A step is the k-hop build + the captured
+    launch over the whole batch.  The same graphs through the plain per-graph
+    solver (gila_layout one after another) are timed on every 16th graph and
+    scaled by pair count."""
     import torch
 
     from paper_1606_02162_amd import gila, inputs
@@ -745,18 +840,28 @@ def bench_batch(args) -> int:
     bparams = gila.BatchParams([p.temperature for p in params], d, gila.FP32)
     torch.cuda.synchronize()
 
+    # the tuner's table (lanes per vertex by row-length class), taken once on
+    # this batch and applied to every step's handle: each graph's plan is
+    # then fixed and its bits reproducible
+    b = gila.Batch.concatenated(rp_all, ci_all, n_arr, nnz_arr, k)
+    default_lanes, cls = b.plan()
+    table = b.tune(gila.FP32)
+    tuned_lanes = table[cls]
+    b.free()
+
     def one_step():
         pos.copy_(pos0)
         b = gila.Batch.concatenated(rp_all, ci_all, n_arr, nnz_arr, k)
+        b.set_plan(tuned_lanes)
         st = b.run(bparams, (pos, voff))
         return b, st
 
-    for _ in range(args.warmup):
-        b, _ = one_step()          # the first run also fills the autotuner's table
+    for _ in range(warmup):
+        b, _ = one_step()
         b.free()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         b, st = one_step()
         info = b.info()
         lat = b.latency_ms()
@@ -769,6 +874,7 @@ def bench_batch(args) -> int:
     inter = (P + nnz) * H
     # run-only time (lists already built)
     b = gila.Batch.concatenated(rp_all, ci_all, n_arr, nnz_arr, k)
+    b.set_plan(tuned_lanes)
     pos.copy_(pos0)
     torch.cuda.synchronize()
     tr0 = time.perf_counter()
@@ -791,30 +897,50 @@ def bench_batch(args) -> int:
         sp += (kh.info()["total_pairs"] + graphs[i].nnz) * H
         kh.free()
     per_graph_rate = sp / sample_s
-    value = inter * args.steps / total_s
+    value = inter * steps / total_s
     p50, p99 = _percentiles(lat)
     # the persistent launch on the device clock: first graph's start to the
     # last graph's end
     launch_ms = float(np.max(lat))
     launch_bytes = algorithmic_bytes_per_iter(P, nnz, nv, 8) * H
     achieved = launch_bytes / (launch_ms * 1e-3) / 1e9
-    out = {
-        "metric": "batched layout: k-hop force interactions/s over 4096 graphs",
-        "value": value, "unit": "interactions/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": total_s / args.steps * 1e3,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic",
+    return {
         "config": {"workload": f"batch{count}_tree+0.5n_k{k}_fp32_{H}iters",
-                   "graphs": count, "vertices": nv, "total_pairs": P, "iterations": H},
+                   "graphs": count, "n_range": [50, 5000], "vertices": nv, "edges": nnz // 2,
+                   "k": k, "iterations": H, "total_pairs": P, "precision": "f32",
+                   "data": "synthetic: random recursive tree + floor(n/2) extra edges per graph, "
+                           "n log-uniform, init uniform in [0,1200)^2"},
+        "interactions_per_s": value,
+        "steps": steps, "warmup": warmup,
+        "ms_per_step": total_s / steps * 1e3,
         "run_only_ms": run_s * 1e3,
-        "latency_ms_within_batch": {"p50": p50, "p99": p99, "max": float(np.max(lat))},
+        "latency_ms_within_launch": {"p50": p50, "p99": p99, "max": launch_ms},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(TRAFFIC_FILE_BATCH),
                      "kernel": "batch_layout_kernel<FP32>", "kernel_ms": launch_ms,
                      "algorithmic_bytes_per_launch": launch_bytes},
         "per_graph_solver": {"interactions_per_s": per_graph_rate,
                              "sample_graphs": len(sample),
                              "speedup_of_batch": value / per_graph_rate},
+        "plan": {"tuned_lanes_by_class": [int(x) for x in table],
+                 "rule_lanes_by_class": [int(default_lanes[cls == c][0]) if (cls == c).any()
+                                         else 0 for c in range(8)],
+                 "graphs_by_class": [int((cls == c).sum()) for c in range(8)]},
+    }
+
+
+def bench_batch(args) -> int:
+    """The batched form on its own line (see batched_leg)."""
+    r = batched_leg(args, args.steps, args.warmup)
+    out = {
+        "metric": "batched layout: k-hop force interactions/s over 4096 graphs",
+        "value": r["interactions_per_s"], "unit": "interactions/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic", "config": r["config"], "run_only_ms": r["run_only_ms"],
+        "latency_ms_within_batch": r["latency_ms_within_launch"], "roofline": r["roofline"],
+        "per_graph_solver": r["per_graph_solver"], "plan": r["plan"],
     }
     print(json.dumps(out))
     return 0

@@ -267,9 +267,12 @@ def watts_strogatz(n: int, degree: int, p: float, seed: int) -> Graph:
     """Watts-Strogatz small world: ring lattice, each edge rewired with prob. p.
 
     Each vertex u is joined to u+1 .. u+degree/2 (mod n).  Every lattice edge
-    (u, u+j) is independently selected with probability p and its far end is
-    replaced by a uniform vertex w such that (u, w) is neither a loop nor an
-    existing edge; if no such w is found after a few draws the edge is kept.
+    (u, u+j) is independently selected with probability p; a selected edge is
+    replaced by (u, w) with w the first of four uniform draws that is neither
+    u nor a lattice neighbour of u, and whose edge no earlier selected edge
+    (in lattice order) has taken; if there is none the edge is kept.  The
+    result is simple and keeps the lattice's edge count (all array work, so
+    graphs of 10^5 vertices take milliseconds).
     """
     if degree % 2 or degree >= n:
         raise ValueError("degree must be even and < n")
@@ -278,22 +281,20 @@ def watts_strogatz(n: int, degree: int, p: float, seed: int) -> Graph:
     us = np.tile(np.arange(n, dtype=np.int64), half)
     js = np.repeat(np.arange(1, half + 1, dtype=np.int64), n)
     vs = (us + js) % n
-    keyset = set((np.minimum(us, vs) * n + np.maximum(us, vs)).tolist())
-    rewire = np.nonzero(rng.random(us.size) < p)[0]
-    cand = rng.integers(0, n, size=(rewire.size, 4))
-    for idx, row in zip(rewire.tolist(), cand.tolist()):
-        u, v = int(us[idx]), int(vs[idx])
-        for w in row:
-            if w == u:
-                continue
-            kk = min(u, w) * n + max(u, w)
-            if kk in keyset:
-                continue
-            keyset.discard(min(u, v) * n + max(u, v))
-            keyset.add(kk)
-            vs[idx] = w
-            break
-    keys = np.fromiter(keyset, dtype=np.int64, count=len(keyset))
+    keys = np.minimum(us, vs) * n + np.maximum(us, vs)   # distinct, since degree < n
+    sel = np.nonzero(rng.random(us.size) < p)[0]
+    cand = rng.integers(0, n, size=(sel.size, 4))
+    u_sel = us[sel][:, None]
+    ckeys = np.minimum(u_sel, cand) * n + np.maximum(u_sel, cand)
+    ring = np.abs(cand - u_sel)
+    ok = np.minimum(ring, n - ring) > half   # neither u nor a lattice neighbour of u
+    has = ok.any(axis=1)
+    new = ckeys[np.arange(sel.size), ok.argmax(axis=1)]
+    took = np.nonzero(has)[0]
+    _, first = np.unique(new[took], return_index=True)   # first selected edge per new edge
+    took = took[np.sort(first)]
+    keys = keys.copy()
+    keys[sel[took]] = new[took]
     return to_csr(n, keys // n, keys % n, name=f"ws{n}_k{degree}_p{p}",
                   meta={"seed": seed})
 
