@@ -7,6 +7,7 @@
 
 #include "device_util.h"
 #include "gila_internal.h"
+#include "host_logic.h"
 
 namespace gila {
 
@@ -186,29 +187,9 @@ static int launch_permute_out(const gila_khop* kh, int precision, void* pos, hip
 }
 
 int check_params(const gila_params* p, bool need_temps) {
-    if (!p) return fail(GILA_EINVAL, "params is NULL");
-    if (p->precision != GILA_FP64 && p->precision != GILA_FP32 &&
-        p->precision != GILA_FP32_KAHAN)
-        return fail(GILA_EINVAL, "unknown precision %d", p->precision);
-    if (!(p->ideal_length > 0.0) || !std::isfinite(p->ideal_length))
-        return fail(GILA_EINVAL, "ideal_length must be finite and > 0");
-    if (p->iterations < 0) return fail(GILA_EINVAL, "iterations must be >= 0");
-    if (need_temps && p->iterations > 0 && !p->temperature)
-        return fail(GILA_EINVAL, "temperature is NULL");
-    if (p->temperature)
-        for (int32_t h = 0; h < p->iterations; ++h)
-            if (!(p->temperature[h] >= 0.0) || !std::isfinite(p->temperature[h]))
-                return fail(GILA_EINVAL, "temperature[%d] must be finite and >= 0", h);
-    if (!(p->stop_fraction >= 0.0) || !(p->stop_displacement >= 0.0))
-        return fail(GILA_EINVAL, "stop parameters must be >= 0");
-    if (p->force_model != GILA_MODEL_FR && p->force_model != GILA_MODEL_LINLOG &&
-        p->force_model != GILA_MODEL_PQ)
-        return fail(GILA_EINVAL, "unknown force model %d", p->force_model);
-    if (p->force_model == GILA_MODEL_PQ &&
-        (p->force_p < 0 || p->force_p > 8 || p->force_q < 0 || p->force_q > 8))
-        return fail(GILA_EINVAL, "force exponents p = %d, q = %d outside [0, 8]", p->force_p,
-                    p->force_q);
-    return GILA_OK;
+    char msg[256];
+    const int rc = host::check_params(p, need_temps, msg, sizeof(msg));
+    return rc == GILA_OK ? GILA_OK : fail(rc, "%s", msg);
 }
 
 void force_exponents(const gila_params* p, int32_t* att_p, int32_t* rep_q) {
@@ -467,25 +448,17 @@ extern "C" {
 int gila_paper_schedule(double n, double aspect, double ideal_length, int32_t iterations,
                         double* temperature_host) {
     clear_error();
-    if (iterations < 0) return fail(GILA_EINVAL, "iterations must be >= 0");
-    if (iterations > 0 && !temperature_host) return fail(GILA_EINVAL, "temperature_host is NULL");
-    if (!(n > 0.0) || !(aspect > 0.0) || !(ideal_length > 0.0) || !std::isfinite(n) ||
-        !std::isfinite(aspect) || !std::isfinite(ideal_length))
-        return fail(GILA_EINVAL, "n, aspect and ideal_length must be finite and > 0");
-    // Section 5.1: sqrt((n / a) d) 0.93^h, h counted from 0
-    const double base = std::sqrt(n / aspect * ideal_length);
-    for (int32_t h = 0; h < iterations; ++h) temperature_host[h] = base * std::pow(0.93, (double)h);
-    return GILA_OK;
+    char msg[256];
+    const int rc = host::paper_schedule(n, aspect, ideal_length, iterations, temperature_host,
+                                        msg, sizeof(msg));
+    return rc == GILA_OK ? GILA_OK : fail(rc, "%s", msg);
 }
 
 int gila_linear_schedule(double t0, int32_t iterations, double* temperature_host) {
     clear_error();
-    if (iterations < 0) return fail(GILA_EINVAL, "iterations must be >= 0");
-    if (iterations > 0 && !temperature_host) return fail(GILA_EINVAL, "temperature_host is NULL");
-    if (!(t0 >= 0.0) || !std::isfinite(t0)) return fail(GILA_EINVAL, "t0 must be finite and >= 0");
-    for (int32_t h = 0; h < iterations; ++h)
-        temperature_host[h] = t0 - (t0 * (double)h) / (double)iterations;
-    return GILA_OK;
+    char msg[256];
+    const int rc = host::linear_schedule(t0, iterations, temperature_host, msg, sizeof(msg));
+    return rc == GILA_OK ? GILA_OK : fail(rc, "%s", msg);
 }
 
 int gila_init_positions(int32_t n, uint64_t seed, double width, double height, int32_t precision,

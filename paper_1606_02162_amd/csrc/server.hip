@@ -32,6 +32,7 @@
 #include <thread>
 
 #include "gila_internal.h"
+#include "host_logic.h"
 
 namespace gila {
 
@@ -73,39 +74,16 @@ static double now_s() {
     return duration<double>(steady_clock::now().time_since_epoch()).count();
 }
 
-// Upper bound of P = sum_v |N_v(k)| from the adjacency alone: the number of
-// walks of length <= k from v, capped at n - 1 per vertex.
-static int64_t pairs_upper_bound(const Job& j) {
-    const int32_t n = j.n;
-    std::vector<int64_t> cur(n), nxt(n), tot(n);
-    for (int32_t v = 0; v < n; ++v) cur[v] = tot[v] = j.rp[v + 1] - j.rp[v];
-    for (int32_t level = 2; level <= j.k; ++level) {
-        for (int32_t v = 0; v < n; ++v) {
-            int64_t s = 0;
-            for (int64_t e = j.rp[v]; e < j.rp[v + 1]; ++e) s += cur[j.ci[e]];
-            nxt[v] = std::min<int64_t>(s, (int64_t)n);
-            tot[v] = std::min<int64_t>(tot[v] + nxt[v], (int64_t)n - 1);
-        }
-        cur.swap(nxt);
-    }
-    int64_t P = 0;
-    for (int32_t v = 0; v < n; ++v) P += tot[v];
-    return P;
-}
-
-// Bytes a job may hold on the device: graph, positions, lists (int32 and
-// 16-bit padded copies), per-slice offsets and partials (bounded by the lists).
+// Bytes a job may hold on the device (host_logic.h: walk-count bound of P).
 static int64_t footprint_bytes(const Job& j) {
-    const int64_t P = pairs_upper_bound(j);
-    return 64ll * j.n + 16ll * j.nnz + 8ll * P + (1ll << 20);
+    return host::footprint_bytes(j.n, j.nnz, j.k, j.rp.data(), j.ci.data());
 }
 
 }  // namespace gila
 
 struct gila_server {
     int device = 0;
-    int64_t budget = 0;
-    int32_t max_slots = 1;
+    gila::host::AdmitState adm;        // budget, slots, bytes reserved, jobs in flight
     int32_t tick_iters = 50;
     int32_t small_max_n = 1024;      // 0 = the most that fits the batch kernel's LDS
     std::atomic<uint64_t> fail_alloc_ticket{0};  // test hook: this job's allocation fails
@@ -123,8 +101,6 @@ struct gila_server {
     std::vector<gila::Job*> ready;        // built large jobs, not yet ticked
     std::vector<gila::Job*> resident;     // large jobs owned by the ticker
     uint64_t next_id = 1;
-    int64_t reserved = 0;
-    int32_t in_flight = 0;
     bool stop = false;
     std::thread th_admit, th_build, th_tick;
     static constexpr int kSmallWorkers = 2;
@@ -163,8 +139,7 @@ static void finish_job(gila_server* s, Job* j, int state, int status) {
     j->status = status;
     if (state == kFailed) std::snprintf(j->msg, sizeof(j->msg), "%s", gila_last_error());
     j->t_done = now_s();
-    s->reserved -= j->footprint;
-    s->in_flight -= 1;
+    host::admit_release(s->adm, j->footprint);
     if (state == kDone) s->jobs_done += 1;
     s->times[j->id] = {(j->t_admit - j->t_submit) * 1e3, (j->t_done - j->t_submit) * 1e3};
     s->cv_done.notify_all();
@@ -344,8 +319,7 @@ static void admitter(gila_server* s) {
                 if (s->stop) return true;
                 if (s->pending.empty()) return false;
                 const Job* j = s->jobs[s->pending.front()];
-                return j->footprint < 0 || j->cancel || j->footprint > s->budget ||
-                       (s->in_flight < s->max_slots && s->reserved + j->footprint <= s->budget);
+                return host::admit_can_progress(s->adm, host::QueuedJob{j->footprint, j->cancel});
             });
             if (s->stop) break;
             for (uint64_t id : s->pending)
@@ -362,27 +336,22 @@ static void admitter(gila_server* s) {
         bool small_added = false, large_added = false;
         while (!s->pending.empty()) {
             Job* j = s->jobs[s->pending.front()];
-            if (j->cancel) {
-                s->pending.pop_front();
-                j->state = kCanceled;
-                j->status = GILA_ECANCELED;
-                j->t_done = now_s();
-                s->cv_done.notify_all();
-                continue;
-            }
-            if (j->footprint < 0) break;  // arrived after the bounds were taken
-            if (j->footprint > s->budget) {
-                s->pending.pop_front();
-                j->state = kFailed;
-                j->status = GILA_ENOMEM;
-                j->t_done = now_s();
-                s->cv_done.notify_all();
-                continue;
-            }
-            if (s->in_flight >= s->max_slots || s->reserved + j->footprint > s->budget) break;
+            // (a job that arrived after the bounds were taken waits: footprint < 0)
+            const host::AdmitOutcome o =
+                host::admit_front(s->adm, host::QueuedJob{j->footprint, j->cancel});
+            if (o == host::kAdmitWait) break;
             s->pending.pop_front();
-            s->reserved += j->footprint;
-            s->in_flight += 1;
+            if (o == host::kAdmitDrop || o == host::kAdmitReject) {
+                j->state = o == host::kAdmitDrop ? kCanceled : kFailed;
+                j->status = o == host::kAdmitDrop ? GILA_ECANCELED : GILA_ENOMEM;
+                if (o == host::kAdmitReject)
+                    std::snprintf(j->msg, sizeof(j->msg), "footprint bound %lld bytes exceeds "
+                                  "the budget of %lld", (long long)j->footprint,
+                                  (long long)s->adm.budget);
+                j->t_done = now_s();
+                s->cv_done.notify_all();
+                continue;
+            }
             j->state = kResident;
             j->t_admit = now_s();
             if (j->small) {
@@ -543,22 +512,11 @@ static void ticker(gila_server* s) {
     }
 }
 
-// Cheap host checks at submission (every index in range, so the footprint
-// bound can walk the graph); sortedness, self-loops and symmetry are checked
-// on the device when the job is admitted.
+// Cheap host checks at submission (host_logic.h).
 static int validate_host_csr(const gila_csr* g) {
-    if (!g) return fail(GILA_EINVAL, "graph is NULL");
-    if (g->n < 0 || g->nnz < 0 || g->nnz % 2) return fail(GILA_EINVAL, "bad n or nnz");
-    if (g->n > 0 && !g->row_ptr) return fail(GILA_EINVAL, "row_ptr is NULL");
-    if (g->nnz > 0 && !g->col_idx) return fail(GILA_EINVAL, "col_idx is NULL");
-    if (g->n > 0 && (g->row_ptr[0] != 0 || g->row_ptr[g->n] != g->nnz))
-        return fail(GILA_EINVAL, "row_ptr must run from 0 to nnz");
-    for (int32_t v = 0; v < g->n; ++v)
-        if (g->row_ptr[v + 1] < g->row_ptr[v]) return fail(GILA_EINVAL, "row_ptr not monotone");
-    for (int64_t e = 0; e < g->nnz; ++e)
-        if (g->col_idx[e] < 0 || g->col_idx[e] >= g->n)
-            return fail(GILA_EINVAL, "column out of range");
-    return GILA_OK;
+    char msg[256];
+    const int rc = host::validate_host_csr(g, msg, sizeof(msg));
+    return rc == GILA_OK ? GILA_OK : fail(rc, "%s", msg);
 }
 
 }  // namespace gila
@@ -580,7 +538,7 @@ int gila_server_create(int32_t device, int64_t hbm_budget_bytes, int32_t max_slo
     DeviceGuard dg(device);
     gila_server* s = new gila_server();
     s->device = device;
-    s->max_slots = max_slots;
+    s->adm.max_slots = max_slots;
     if (hbm_budget_bytes == 0) {
         size_t fr = 0, tot = 0;
         if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
@@ -589,7 +547,7 @@ int gila_server_create(int32_t device, int64_t hbm_budget_bytes, int32_t max_slo
         }
         hbm_budget_bytes = (int64_t)(0.9 * (double)fr);
     }
-    s->budget = hbm_budget_bytes;
+    s->adm.budget = hbm_budget_bytes;
     if (hipHostMalloc((void**)&s->host_ctl, sizeof(Ctl) * (size_t)max_slots,
                       hipHostMallocDefault) != hipSuccess) {
         delete s;
@@ -765,7 +723,7 @@ int gila_server_info(gila_server* s, int64_t* jobs_done, int64_t* ticks, int32_t
     if (jobs_done) *jobs_done = s->jobs_done;
     if (ticks) *ticks = s->ticks;
     if (peak_resident) *peak_resident = s->peak_resident;
-    if (bytes_in_use) *bytes_in_use = s->reserved;
+    if (bytes_in_use) *bytes_in_use = s->adm.reserved;
     return GILA_OK;
 }
 
