@@ -145,6 +145,9 @@ def main() -> int:
                     help="force model of the single-graph workloads: fr (p = 2, q = 1), linlog "
                          "(p = 0, q = 1) or explicit exponents 'p,q'")
     ap.add_argument("--batch-count", type=int, default=4096)
+    ap.add_argument("--per-graph-every", type=int, default=16,
+                    help="the batched object times the plain per-graph solver on every N-th "
+                         "graph, scaled by pair count")
     ap.add_argument("--no-batched", action="store_true",
                     help="default line without its batched (4096-graph) object")
     ap.add_argument("--no-served", action="store_true",
@@ -802,8 +805,8 @@ def batched_leg(args, steps: int, warmup: int) -> dict:
     recursive tree + 0.5n extra edges, n log-uniform in [50, 5000]), k = 3,
     FP32, 200 iterations each.  A step is the k-hop build + the captured
     launch over the whole batch.  The same graphs through the plain per-graph
-    solver (gila_layout one after another) are timed on every 16th graph and
-    scaled by pair count."""
+    solver (gila_layout one after another) are timed on every 16th graph
+    (--per-graph-every) and scaled by pair count."""
     import torch
 
     from paper_1606_02162_amd import gila, inputs
@@ -846,7 +849,7 @@ def batched_leg(args, steps: int, warmup: int) -> dict:
     b = gila.Batch.concatenated(rp_all, ci_all, n_arr, nnz_arr, k)
     default_lanes, cls = b.plan()
     table = b.tune(gila.FP32)
-    tuned_lanes = table[cls]
+    tuned_lanes, _ = b.plan()      # the table by class, small graphs raised to fill
     b.free()
 
     def one_step():
@@ -883,7 +886,7 @@ def batched_leg(args, steps: int, warmup: int) -> dict:
     run_s = time.perf_counter() - tr0
     b.free()
     # plain per-graph solver on a sample, scaled by pair count
-    sample = list(range(0, count, 16))
+    sample = list(range(0, count, max(1, args.per_graph_every)))
     sp = 0
     torch.cuda.synchronize()
     ts0 = time.perf_counter()
@@ -924,9 +927,9 @@ def batched_leg(args, steps: int, warmup: int) -> dict:
                              "sample_graphs": len(sample),
                              "speedup_of_batch": value / per_graph_rate},
         "plan": {"tuned_lanes_by_class": [int(x) for x in table],
-                 "rule_lanes_by_class": [int(default_lanes[cls == c][0]) if (cls == c).any()
-                                         else 0 for c in range(8)],
-                 "graphs_by_class": [int((cls == c).sum()) for c in range(8)]},
+                 "graphs_by_class": [int((cls == c).sum()) for c in range(8)],
+                 "graphs_by_lanes": {str(int(l)): int((tuned_lanes == l).sum())
+                                     for l in np.unique(tuned_lanes)}},
     }
 
 

@@ -397,9 +397,12 @@ typedef struct gila_batch gila_batch;
  * (graphs_dev[i] is a device CSR with at most 65535 vertices, k[i] >= 1) into
  * one segmented handle, and fix each graph's plan: its lanes per vertex (the
  * order in which its force terms are summed, hence its result bits), from
- * its mean |N_v(k)| -- about eight entries per lane, a power of two in
- * [1, 64].  The plan depends only on the graph, so a graph's result is the
- * same bits alone, in any batch and in any process.  Synchronises. */
+ * its row-length class c (see gila_batch_plan) -- one lane while
+ * 4 * 2^c <= 128, else about 128 entries per lane, a power of two in
+ * [1, 64] -- and, for a graph of fewer than 256 vertices, at least the
+ * largest power of two L with n L <= 512 (so its vertices fill a
+ * workgroup).  The plan depends only on the graph, so a graph's result is
+ * the same bits alone, in any batch and in any process.  Synchronises. */
 int gila_batch_build(const gila_csr* graphs_dev, int32_t count, const int32_t* k,
                      void* stream, gila_batch** out);
 
@@ -419,7 +422,8 @@ int gila_batch_info(const gila_batch* b, int32_t* count, int64_t* total_pairs,
 
 /* The handle's plan: lanes_host[count] receives each graph's lanes per vertex,
  * class_host[count] its row-length class c = the largest c <= 7 with
- * mean |N_v(k)| >= 4 * 2^c (0 below 8).  Either may be NULL. */
+ * mean |N_v(k)| >= 2^(c+1) (0 below 4), so that the class's means lie below
+ * 4 * 2^c.  Either may be NULL. */
 int gila_batch_plan(const gila_batch* b, int32_t* lanes_host, int32_t* class_host);
 
 /* Replaces the plan: lanes_host[count], each a power of two in [1, 64]
@@ -432,9 +436,10 @@ int gila_batch_set_plan(gila_batch* b, const int32_t* lanes_host);
  * times every lanes-per-vertex choice on up to 48 of its graphs (8 iterations
  * at cap 0 from seeded positions, in scratch memory; the caller's positions
  * are not touched) in `precision`, and sets the fastest in the plan of every
- * graph of the class.  class_lanes_host[8] (may be NULL) receives the choice
- * per class (0: class absent), for the caller to keep and apply to later
- * batches.  Never run implicitly.  Synchronises `stream`. */
+ * graph of the class (raised, for small graphs, to the lanes that fill a
+ * workgroup, as at build).  class_lanes_host[8] (may be NULL) receives the
+ * choice per class (0: class absent), for the caller to keep and apply to
+ * later batches.  Never run implicitly.  Synchronises `stream`. */
 int gila_batch_tune(gila_batch* b, int32_t precision, void* stream, int32_t* class_lanes_host);
 
 /* Latency of each graph in the last gila_batch_run: ms_host[count] receives

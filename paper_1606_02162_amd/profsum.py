@@ -43,29 +43,46 @@ def kernel_stats(path: str):
              "max_ns": r[5], "pct": 100.0 * r[2] / total} for r in rows]
 
 
-def counters(path: str, kernel: str | None = None):
+def counters(path: str, kernel: str | None = None, min_grid: int = 0, longest: bool = False):
+    """Counter averages per kernel over its dispatches with at least min_grid
+    threads; with `longest`, the values of each kernel's longest dispatch
+    only (one launch among shorter ones of the same kernel)."""
     con = sqlite3.connect(_db(path))
-    rows = con.execute("select kernel_name, counter_name, avg(value), count(*), avg(duration) "
-                       "from counters_collection group by kernel_name, counter_name").fetchall()
-    out = []
-    for name, cname, val, cnt, dur in rows:
+    rows = con.execute("select kernel_name, counter_name, value, dispatch_id, duration, grid_size "
+                       "from counters_collection").fetchall()
+    picked = {}
+    if longest:
+        for name, _, _, did, dur, grid in rows:
+            if grid >= min_grid and (name not in picked or dur > picked[name][1]):
+                picked[name] = (did, dur)
+    acc = {}
+    for name, cname, val, did, dur, grid in rows:
         if kernel and kernel not in name:
             continue
-        out.append({"kernel": name, "counter": cname, "avg": val, "dispatches": cnt,
-                    "avg_duration_ns": dur})
+        if grid < min_grid or (longest and picked[name][0] != did):
+            continue
+        a = acc.setdefault((name, cname), [0.0, 0, 0.0])
+        a[0] += val
+        a[1] += 1
+        a[2] += dur
+    out = []
+    for (name, cname), (s, cnt, dur) in sorted(acc.items()):
+        out.append({"kernel": name, "counter": cname, "avg": s / cnt, "dispatches": cnt,
+                    "avg_duration_ns": dur / cnt})
     return out
 
 
-def _one(path: str, kernel: str, counter: str) -> float:
-    vals = [c["avg"] for c in counters(path, kernel) if c["counter"] == counter]
+def _one(path: str, kernel: str, counter: str, min_grid: int = 0, longest: bool = False) -> float:
+    vals = [c["avg"] for c in counters(path, kernel, min_grid, longest) if c["counter"] == counter]
     if not vals:
         raise KeyError(f"{counter} for {kernel} not in {path}")
     return float(vals[0])
 
 
-def traffic(fetch, write, calib_fetch, calib_write, kernel, calib_bytes=1 << 30):
-    f = _one(fetch, kernel, "FETCH_SIZE")
-    w = _one(write, kernel, "WRITE_SIZE")
+def traffic(fetch, write, calib_fetch, calib_write, kernel, calib_bytes=1 << 30, min_grid=0,
+            longest=False):
+    f = _one(fetch, kernel, "FETCH_SIZE", min_grid, longest)
+    w = _one(write, kernel, "WRITE_SIZE", min_grid, longest)
     cf = _one(calib_fetch, "copyBuffer", "FETCH_SIZE")
     cw = _one(calib_write, "copyBuffer", "WRITE_SIZE")
     fs = calib_bytes / (cf * 1024.0)
@@ -92,10 +109,14 @@ def main(argv=None) -> int:
     c = sub.add_parser("counters")
     c.add_argument("dir")
     c.add_argument("kernel", nargs="?")
+    c.add_argument("--min-grid", type=int, default=0, help="only dispatches of >= this many threads")
+    c.add_argument("--longest", action="store_true", help="only each kernel's longest dispatch")
     tr = sub.add_parser("traffic")
     for k in ("fetch", "write", "calib_fetch", "calib_write"):
         tr.add_argument("--" + k.replace("_", "-"), required=True)
     tr.add_argument("--kernel", required=True)
+    tr.add_argument("--min-grid", type=int, default=0)
+    tr.add_argument("--longest", action="store_true")
     tr.add_argument("--out", required=True)
     tr.add_argument("--sources", nargs="*", default=[])
     a = ap.parse_args(argv)
@@ -107,11 +128,12 @@ def main(argv=None) -> int:
                   f"{r['min_ns'] / 1e3:>9.1f} {r['max_ns'] / 1e3:>9.1f} "
                   f"{r['total_ns'] / 1e6:>10.2f} {r['pct']:>6.2f}")
     elif a.cmd == "counters":
-        for r in counters(a.dir, a.kernel):
+        for r in counters(a.dir, a.kernel, a.min_grid, a.longest):
             print(f"{r['kernel'][:60]:<60} {r['counter']:<28} {r['avg']:>16.6g} "
                   f"{r['dispatches']:>6}")
     else:
-        res = traffic(a.fetch, a.write, a.calib_fetch, a.calib_write, a.kernel)
+        res = traffic(a.fetch, a.write, a.calib_fetch, a.calib_write, a.kernel,
+                      min_grid=a.min_grid, longest=a.longest)
         root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
         if a.sources:
             res["source_files"] = a.sources

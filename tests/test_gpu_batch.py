@@ -244,12 +244,17 @@ def test_plan_is_fixed_at_build_and_reproducible(G):
 
     b1 = G.Batch(dev, ks)
     lanes1, cls1 = b1.plan()
-    # the rule: about eight entries per lane for the class's upper mean length
-    for lanes, c in zip(lanes1, cls1):
+    # the rule: one lane per vertex up to a class upper mean length of 128,
+    # then about 128 entries per lane, and for small graphs at least the
+    # lanes that fill 512 threads
+    for (g, _), lanes, c in zip(gs, lanes1, cls1):
         want = 1
-        while want < 64 and want * 8 < (4 << int(c)):
+        while want < 64 and want * 128 < (4 << int(c)):
             want *= 2
-        assert lanes == want
+        fill = 1
+        while fill < 64 and g.n * fill * 2 <= 512:
+            fill *= 2
+        assert lanes == max(want, fill), (g.n, lanes, want, fill)
     a = run(b1)
     # a graph's plan does not depend on its batch: every 3rd graph alone
     sub = list(range(0, len(gs), 3))
@@ -260,7 +265,11 @@ def test_plan_is_fixed_at_build_and_reproducible(G):
     table = b1.tune(G.FP32_KAHAN)
     assert table.shape == (8,) and all(v == 0 or v in (1, 2, 4, 8, 16, 32, 64) for v in table)
     lanes_t, _ = b1.plan()
-    assert all(table[c] == l for l, c in zip(lanes_t, cls1))
+    for (g, _), l, c in zip(gs, lanes_t, cls1):
+        fill = 1
+        while fill < 64 and g.n * fill * 2 <= 512:
+            fill *= 2
+        assert l == max(table[c], fill)
     tuned = run(b1)
     b3 = G.Batch(dev, ks)
     assert np.array_equal(b3.plan()[0], lanes1)        # a fresh handle starts from the rule
