@@ -11,7 +11,15 @@
 // graph's iterations there -- forces from LDS gathers, the temperature cap,
 // the synchronous move into the other buffer, the statistics and the halting
 // rule -- with only workgroup barriers between iterations; then it writes the
-// positions back and takes the next graph.  A graph's arithmetic depends only
+// positions back and takes the next graph.
+//
+// Graphs run with one lane per vertex read their rows from wave slices: the
+// graph's vertices sorted by decreasing row length, cut into slices of 64
+// (one per wavefront step), and each slice's rows stored interleaved -- quad
+// j of the slice's lane l at word j * 64 + l -- padded to the slice's longest
+// row (an even number of quads).  A wavefront then loads 512 contiguous bytes
+// per quad step, its lanes walk rows of similar length, and each vertex still
+// adds its terms in its own row order (the same bits as the row layout).  A graph's arithmetic depends only
 // on that graph and its lanes per vertex, which the handle's plan fixes at
 // build (from the graph's mean row length; gila_batch_tune or
 // gila_batch_set_plan may replace it), so its result is the same bits alone,
@@ -30,6 +38,7 @@ namespace gila {
 
 struct BatchDesc {
     int64_t vbase;             // first vertex of the graph in the union
+    int64_t sbase;             // its first wave slice
     int32_t n;
     int32_t n_active;
     int32_t lpv;               // lanes per vertex
@@ -42,6 +51,16 @@ struct BatchDesc {
     void* pos;                 // caller's positions (n, precision layout)
 };
 
+// A wave slice: 64 vertices of one graph (a lane each), with their rows
+// interleaved at sk + koff (nq quad words per lane, nq even) and their
+// adjacency interleaved at sa + aoff (na ids per lane).
+struct SellSlice {
+    int64_t koff;
+    int64_t aoff;
+    int32_t nq;
+    int32_t na;
+};
+
 struct BatchArgs {
     int32_t count;
     const BatchDesc* graphs;
@@ -50,6 +69,12 @@ struct BatchArgs {
     const uint16_t* kidx;      // local ids
     const int64_t* rp;         // union adjacency row offsets
     const uint16_t* ci;        // local ids
+    const SellSlice* sell;     // wave slices (graphs with one lane per vertex)
+    const uint2* smeta;        // [64 per slice]: (vertex, row quads | degree << 16)
+    const uint2* sk;           // interleaved rows (quads of local ids)
+    const uint16_t* sa;        // interleaved adjacency (local ids)
+    double* escratch;          // [grid][2][slices_max] per-slice energies
+    int32_t slices_max;        // slices of the largest graph
     const double* temps;
     gila_stats* stats;         // [count], indexed like graphs
     uint64_t* t_start;         // [count] device wall clock when the graph was taken
@@ -65,13 +90,20 @@ struct gila_batch {
     int64_t nv = 0, nnz = 0, P = 0, P_padded = 0;  // pairs; entries of the quad-padded rows
     int64_t device_bytes = 0;
     int32_t nmax = 0;
-    std::vector<int64_t> vbase, ebase, Pg;
+    std::vector<int64_t> vbase, ebase, Pg, sbase;
     std::vector<int32_t> n, n_active, k, cls;
     std::vector<int32_t> lpv;  // the plan: lanes per vertex of each graph
     int64_t* kptr = nullptr;
     uint16_t* kidx = nullptr;
     int64_t* rp = nullptr;
     uint16_t* ci16 = nullptr;
+    int64_t nslices = 0, sell_quads = 0, sell_adj = 0;
+    gila::SellSlice* d_sell = nullptr;
+    uint2* d_smeta = nullptr;
+    uint2* d_sk = nullptr;
+    uint16_t* d_sa = nullptr;
+    double* d_escratch = nullptr;  // per-slice energies, [grid][2][slices of the largest graph]
+    int64_t escratch_grid = 0;     // workgroups it has room for
     gila::BatchDesc* d_desc = nullptr;
     int32_t* d_order = nullptr;
     double* d_temps = nullptr;
@@ -319,7 +351,154 @@ __global__ __launch_bounds__(kBlock) void pad_rows_kernel(const int64_t* __restr
     }
 }
 
+// ------------------------------------------------------------------ wave slices
+// One workgroup per graph: its vertices' local ids by decreasing row length in
+// quads (ties by id) -- a bitonic sort of (key, id) words in LDS.  Graphs of
+// more than kOrderMax vertices keep the identity order (their slices are then
+// less even, the results are the same).
+constexpr int kOrderMax = 8192;
+
+__global__ __launch_bounds__(kBlock) void row_order_kernel(const int64_t* __restrict__ vbase,
+                                                           const int64_t* __restrict__ kptr,
+                                                           uint16_t* __restrict__ order) {
+    __shared__ uint32_t s_key[kOrderMax];
+    const int64_t vb = vbase[blockIdx.x];
+    const int n = (int)(vbase[blockIdx.x + 1] - vb);
+    if (n > kOrderMax) {
+        for (int i = threadIdx.x; i < n; i += kBlock) order[vb + i] = (uint16_t)i;
+        return;
+    }
+    int np = 1;
+    while (np < n) np <<= 1;
+    for (int i = threadIdx.x; i < np; i += kBlock) {
+        // a row has at most 65534 entries, so at most 16384 quads
+        const uint32_t q = i < n ? (uint32_t)((kptr[vb + i + 1] - kptr[vb + i]) >> 2) : 0u;
+        s_key[i] = i < n ? ((0xFFFFu - q) << 16) | (uint32_t)i : 0xFFFFFFFFu;
+    }
+    __syncthreads();
+    for (int size = 2; size <= np; size <<= 1)
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = threadIdx.x; i < np; i += kBlock) {
+                const int j = i ^ stride;
+                if (j > i) {
+                    const bool up = (i & size) == 0;
+                    const uint32_t x = s_key[i], y = s_key[j];
+                    if ((x > y) == up) {
+                        s_key[i] = y;
+                        s_key[j] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    for (int i = threadIdx.x; i < n; i += kBlock) order[vb + i] = (uint16_t)(s_key[i] & 0xFFFFu);
+}
+
+// One wavefront per slice: its lanes' vertices (the graph's sentinel id n for
+// lanes past the end), row quads and degrees, and the slice's sizes (quads
+// rounded up to even, adjacency entries) for the offset scans.
+__global__ __launch_bounds__(kBlock) void sell_dims_kernel(
+    int64_t nslices, const int32_t* __restrict__ sgraph, const int64_t* __restrict__ vbase,
+    const int64_t* __restrict__ sbase, const int64_t* __restrict__ kptr,
+    const int64_t* __restrict__ rp, const uint16_t* __restrict__ order,
+    SellSlice* __restrict__ hdr, uint2* __restrict__ smeta, int64_t* __restrict__ szk,
+    int64_t* __restrict__ sza) {
+    const int64_t sl = (int64_t)blockIdx.x * (kBlock / 64) + wave_id();
+    if (sl >= nslices) return;
+    const int lane = lane64();
+    const int g = sgraph[sl];
+    const int64_t vb = vbase[g];
+    const int n = (int)(vbase[g + 1] - vb);
+    const int i = (int)(sl - sbase[g]) * 64 + lane;
+    const bool live = i < n;
+    const int v = live ? (int)order[vb + i] : n;
+    const int nq = live ? (int)((kptr[vb + v + 1] - kptr[vb + v]) >> 2) : 0;
+    const int deg = live ? (int)(rp[vb + v + 1] - rp[vb + v]) : 0;
+    const int Q = (wave_max(nq) + 1) & ~1;
+    const int D = wave_max(deg);
+    smeta[sl * 64 + lane] = make_uint2((uint32_t)v, (uint32_t)nq | ((uint32_t)deg << 16));
+    if (lane == 0) {
+        szk[sl] = (int64_t)Q * 64;
+        sza[sl] = (int64_t)D * 64;
+        hdr[sl].nq = Q;
+        hdr[sl].na = D;
+    }
+}
+
+// One wavefront per slice: the interleaved rows (sentinel quads past a row's
+// end) and adjacency (sentinel ids past a vertex's degree), and the slice's
+// offsets.
+__global__ __launch_bounds__(kBlock) void sell_fill_kernel(
+    int64_t nslices, const int32_t* __restrict__ sgraph, const int64_t* __restrict__ vbase,
+    const int64_t* __restrict__ kptr, const uint16_t* __restrict__ kidx,
+    const int64_t* __restrict__ rp, const uint16_t* __restrict__ ci16,
+    const int64_t* __restrict__ koff, const int64_t* __restrict__ aoff,
+    const uint2* __restrict__ smeta, SellSlice* __restrict__ hdr, uint2* __restrict__ sk,
+    uint16_t* __restrict__ sa) {
+    const int64_t sl = (int64_t)blockIdx.x * (kBlock / 64) + wave_id();
+    if (sl >= nslices) return;
+    const int lane = lane64();
+    const int g = sgraph[sl];
+    const int64_t vb = vbase[g];
+    const uint32_t n = (uint32_t)(vbase[g + 1] - vb);
+    const uint2 m = smeta[sl * 64 + lane];
+    const int v = (int)m.x;
+    const int nq = (int)(m.y & 0xFFFFu), deg = (int)(m.y >> 16);
+    const int Q = hdr[sl].nq, D = hdr[sl].na;
+    const int64_t ko = koff[sl], ao = aoff[sl];
+    // v <= n, so both row offsets are in range (a lane past the end reads none)
+    const uint2* row = reinterpret_cast<const uint2*>(kidx + kptr[vb + v]);
+    const uint2 sent = make_uint2(n | (n << 16), n | (n << 16));
+    for (int j = 0; j < Q; ++j) sk[ko + (int64_t)j * 64 + lane] = j < nq ? row[j] : sent;
+    const uint16_t* arow = ci16 + rp[vb + v];
+    for (int j = 0; j < D; ++j) sa[ao + (int64_t)j * 64 + lane] = j < deg ? arow[j] : (uint16_t)n;
+    if (lane == 0) {
+        hdr[sl].koff = ko;
+        hdr[sl].aoff = ao;
+    }
+}
+
 // ------------------------------------------------------------------ the persistent kernel
+// The temperature cap and synchronous move of one vertex (its new position),
+// with its share of the iteration statistics.  A non-finite force -- a term
+// overflowed -- leaves the vertex in place and counts it (the graph's run
+// stops).
+template <class P>
+__device__ __forceinline__ typename P::vec2 batch_move(const BatchDesc& G, typename P::vec2 xv,
+                                                       double fx, double fy, double t,
+                                                       double& energy, double& maxd,
+                                                       int64_t& moved) {
+    using R = typename P::real;
+    typename P::vec2 nx = xv;
+    if constexpr (sizeof(R) == 4) {
+        // FP32 positions: the move in FP32 (one lane per vertex does this
+        // part, so its instruction count matters); |Delta| = the capped length
+        float l, dx, dy;
+        if (capped_move_f32(fx, fy, t, dx, dy, l)) {
+            energy += fx * fx + fy * fy;
+            nx.x = xv.x + dx;
+            nx.y = xv.y + dy;
+            maxd = (double)l > maxd ? (double)l : maxd;
+            moved += (double)l > G.stop_displacement ? 1 : 0;
+        } else {
+            moved += kNonfiniteOne;
+        }
+    } else {
+        double dx, dy;
+        if (capped_move(fx, fy, t, dx, dy)) {
+            energy += fx * fx + fy * fy;
+            nx.x = (R)((double)xv.x + dx);
+            nx.y = (R)((double)xv.y + dy);
+            const double dl = sqrt(dx * dx + dy * dy);
+            maxd = dl > maxd ? dl : maxd;
+            moved += dl > G.stop_displacement ? 1 : 0;
+        } else {
+            moved += kNonfiniteOne;
+        }
+    }
+    return nx;
+}
+
 template <class P, int LPV>
 __device__ __forceinline__ void batch_graph_iteration(
     const BatchArgs& a, const BatchDesc& G, const typename P::vec2* __restrict__ cur,
@@ -394,40 +573,96 @@ __device__ __forceinline__ void batch_graph_iteration(
         }
         const double fx = group_sum<LPV>(acc.x()) * d2;
         const double fy = group_sum<LPV>(acc.y()) * d2;
-        if (v < G.n && gl == 0) {
-            // temperature cap and synchronous move (into the other buffer)
-            // (a non-finite force -- a term overflowed -- leaves the vertex in
-            // place and stops the graph's run)
-            V nx = xv;
-            if constexpr (sizeof(R) == 4) {
-                // FP32 positions: the move in FP32 (one lane per vertex does
-                // this part, so its instruction count matters); |Delta| = the
-                // capped length
-                float l, dx, dy;
-                if (capped_move_f32(fx, fy, t, dx, dy, l)) {
-                    energy += fx * fx + fy * fy;
-                    nx.x = xv.x + dx;
-                    nx.y = xv.y + dy;
-                    maxd = (double)l > maxd ? (double)l : maxd;
-                    moved += (double)l > G.stop_displacement ? 1 : 0;
-                } else {
-                    moved += kNonfiniteOne;
-                }
-            } else {
-                double dx, dy;
-                if (capped_move(fx, fy, t, dx, dy)) {
-                    energy += fx * fx + fy * fy;
-                    nx.x = (R)((double)xv.x + dx);
-                    nx.y = (R)((double)xv.y + dy);
-                    const double dl = sqrt(dx * dx + dy * dy);
-                    maxd = dl > maxd ? dl : maxd;
-                    moved += dl > G.stop_displacement ? 1 : 0;
-                } else {
-                    moved += kNonfiniteOne;
-                }
-            }
-            nxt[v] = nx;
+        if (v < G.n && gl == 0) nxt[v] = batch_move<P>(G, xv, fx, fy, t, energy, maxd, moved);
+    }
+}
+
+// Rows of graphs run with one lane per vertex, from the graph's wave slices:
+// each wavefront takes the next slice (longest rows first) from the
+// iteration's counter in LDS, and writes the slice's energy to e_slice[slice]
+// (the iteration's energy is their sum in slice order).  All lanes load and evaluate every quad step of
+// the slice; a lane adds a step's terms only within its own row, in the same
+// grouping as the row layout (pairs of quads, a last odd quad alone), and its
+// adjacency terms only within its degree, so each vertex gets the same bits.
+template <class P>
+__device__ __forceinline__ void batch_graph_iteration_slices(
+    const BatchArgs& a, const BatchDesc& G, const typename P::vec2* __restrict__ cur,
+    typename P::vec2* __restrict__ nxt, double t, int* s_next, double* e_slice, double& maxd,
+    int64_t& moved, int& coinc) {
+    using R = typename P::real;
+    using V = typename P::vec2;
+    const double d2 = G.d * G.d;
+    const R dpar = sizeof(R) == 4 ? (R)(1.0 / (G.d * d2)) : (R)(G.d * d2);
+    const int lane = lane64();
+    const int ns = (G.n + 63) >> 6;
+    for (;;) {
+        int sl = 0;
+        if (lane == 0) sl = atomicAdd(s_next, 1);
+        sl = __builtin_amdgcn_readfirstlane(sl);
+        if (sl >= ns) break;
+        const int64_t si = G.sbase + sl;
+        const SellSlice S = a.sell[si];
+        const uint2 m = a.smeta[si * 64 + lane];
+        const int v = (int)m.x;  // n (the far sentinel) past the graph's end
+        const int nq = (int)(m.y & 0xFFFFu), deg = (int)(m.y >> 16);
+        const V xv = cur[v];
+        Acc<R, P::kahan> acc;
+        R mindd = R(1);
+        const uint2* __restrict__ q = a.sk + S.koff + lane;
+        int j = 0;
+        for (; j + 3 < S.nq; j += 4) {
+            const uint2 w0 = q[(int64_t)j * 64], w1 = q[(int64_t)(j + 1) * 64],
+                        w2 = q[(int64_t)(j + 2) * 64], w3 = q[(int64_t)(j + 3) * 64];
+            R ax, ay, bx, by;
+            repulse4<P>(cur[w0.x & 0xFFFFu], cur[w0.x >> 16], cur[w0.y & 0xFFFFu],
+                        cur[w0.y >> 16], xv.x, xv.y, ax, ay, mindd);
+            repulse4<P>(cur[w1.x & 0xFFFFu], cur[w1.x >> 16], cur[w1.y & 0xFFFFu],
+                        cur[w1.y >> 16], xv.x, xv.y, bx, by, mindd);
+            if (j + 1 < nq) acc.add(ax + bx, ay + by);
+            else if (j < nq) acc.add(ax, ay);
+            repulse4<P>(cur[w2.x & 0xFFFFu], cur[w2.x >> 16], cur[w2.y & 0xFFFFu],
+                        cur[w2.y >> 16], xv.x, xv.y, ax, ay, mindd);
+            repulse4<P>(cur[w3.x & 0xFFFFu], cur[w3.x >> 16], cur[w3.y & 0xFFFFu],
+                        cur[w3.y >> 16], xv.x, xv.y, bx, by, mindd);
+            if (j + 3 < nq) acc.add(ax + bx, ay + by);
+            else if (j + 2 < nq) acc.add(ax, ay);
         }
+        for (; j < S.nq; j += 2) {  // S.nq is even
+            const uint2 w0 = q[(int64_t)j * 64], w1 = q[(int64_t)(j + 1) * 64];
+            R ax, ay, bx, by;
+            repulse4<P>(cur[w0.x & 0xFFFFu], cur[w0.x >> 16], cur[w0.y & 0xFFFFu],
+                        cur[w0.y >> 16], xv.x, xv.y, ax, ay, mindd);
+            repulse4<P>(cur[w1.x & 0xFFFFu], cur[w1.x >> 16], cur[w1.y & 0xFFFFu],
+                        cur[w1.y >> 16], xv.x, xv.y, bx, by, mindd);
+            if (j + 1 < nq) acc.add(ax + bx, ay + by);
+            else if (j < nq) acc.add(ax, ay);
+        }
+        const bool live = v < G.n;
+        // padding quads hold the far sentinel (an infinite squared distance),
+        // so mindd sees only the row's own pairs
+        if (live && mindd <= coincidence_bias<R>()) {
+            const int64_t kb = a.kptr[G.vbase + v], ke = a.kptr[G.vbase + v + 1];
+            const uint16_t* row = a.kidx + kb;
+            for (int64_t e = 0; e < ke - kb; ++e) {
+                const V p = cur[row[e]];
+                coinc += (row[e] != G.n && p.x == xv.x && p.y == xv.y) ? 1 : 0;
+            }
+        }
+        const uint16_t* __restrict__ aq = a.sa + S.aoff + lane;
+        for (int e = 0; e < S.na; ++e) {
+            const int u = aq[(int64_t)e * 64];
+            if (e < deg) attract<P>(xv.x, xv.y, cur[u], dpar, acc);
+        }
+        double energy = 0.0;
+        if (live) {
+            const double fx = acc.x() * d2;
+            const double fy = acc.y() * d2;
+            nxt[v] = batch_move<P>(G, xv, fx, fy, t, energy, maxd, moved);
+        }
+        // the slice's energy, summed in a fixed order whichever wavefront
+        // took the slice
+        const double se = wave_sum(energy);
+        if (lane == 0) e_slice[sl] = se;
     }
 }
 
@@ -437,6 +672,7 @@ __device__ __forceinline__ void batch_layout_body(const BatchArgs& a) {
     using V = typename P::vec2;
     extern __shared__ __align__(16) unsigned char s_raw[];
     __shared__ int s_g;
+    __shared__ int s_sl[2];  // next wave slice, for alternate iterations
     // per-wave statistics, two sets used by alternate iterations (a set is
     // rewritten two iterations later, after a barrier every reader has passed)
     __shared__ double s_e[2][kBatchWaves], s_m[2][kBatchWaves];
@@ -445,7 +681,9 @@ __device__ __forceinline__ void batch_layout_body(const BatchArgs& a) {
     for (;;) {
         if (threadIdx.x == 0) s_g = atomicAdd(a.work, 1);
         __syncthreads();
-        const int gi = s_g;
+        // uniform across the workgroup: the graph's descriptor goes to scalar
+        // registers
+        const int gi = __builtin_amdgcn_readfirstlane(s_g);
         if (gi >= a.count) break;
         const int gid = a.order[gi];
         const BatchDesc G = a.graphs[gid];
@@ -453,6 +691,10 @@ __device__ __forceinline__ void batch_layout_body(const BatchArgs& a) {
         // two position buffers of n + 1 slots; slot n holds the far sentinel
         V* cur = reinterpret_cast<V*>(s_raw);
         V* nxt = cur + G.n + 1;
+        // per-slice energies of alternate iterations (one lane per vertex), in
+        // the workgroup's own part of the scratch
+        const int ns = (G.n + 63) >> 6;
+        double* e_sl = a.escratch + (int64_t)blockIdx.x * 2 * a.slices_max;
         const V* src = reinterpret_cast<const V*>(G.pos);
         for (int i = threadIdx.x; i < G.n; i += kBatchBlock) cur[i] = src[i];
         if (threadIdx.x == 0) {
@@ -461,6 +703,8 @@ __device__ __forceinline__ void batch_layout_body(const BatchArgs& a) {
             far.y = far.x;
             cur[G.n] = far;
             nxt[G.n] = far;
+            s_sl[0] = 0;
+            s_sl[1] = 0;
         }
         __syncthreads();
         double E = 0.0, M = 0.0;
@@ -471,8 +715,14 @@ __device__ __forceinline__ void batch_layout_body(const BatchArgs& a) {
             double energy = 0.0, maxd = 0.0;
             int64_t moved = 0;
             int coinc = 0;
+            // the other iteration's slice counter was last used before the
+            // previous barrier: reset it for the next iteration
+            if (threadIdx.x == 0) s_sl[(h + 1) & 1] = 0;
             switch (G.lpv) {
-                case 1: batch_graph_iteration<P, 1>(a, G, cur, nxt, t, energy, maxd, moved, coinc); break;
+                case 1:
+                    batch_graph_iteration_slices<P>(a, G, cur, nxt, t, &s_sl[h & 1],
+                                                    e_sl + (h & 1) * ns, maxd, moved, coinc);
+                    break;
                 case 2: batch_graph_iteration<P, 2>(a, G, cur, nxt, t, energy, maxd, moved, coinc); break;
                 case 4: batch_graph_iteration<P, 4>(a, G, cur, nxt, t, energy, maxd, moved, coinc); break;
                 case 8: batch_graph_iteration<P, 8>(a, G, cur, nxt, t, energy, maxd, moved, coinc); break;
@@ -519,6 +769,13 @@ __device__ __forceinline__ void batch_layout_body(const BatchArgs& a) {
                 stopped = 1;
                 break;
             }
+        }
+        if (G.lpv == 1 && run > 0) {
+            // the last iteration's slice energies (written before its barrier)
+            const double* es = e_sl + ((run - 1) & 1) * ns;
+            double e = 0.0;
+            for (int i = 0; i < ns; ++i) e += es[i];
+            E = e;
         }
         V* dst = reinterpret_cast<V*>(G.pos);
         for (int i = threadIdx.x; i < G.n; i += kBatchBlock) dst[i] = cur[i];
@@ -626,7 +883,9 @@ static void set_lds_attr(size_t lds) {
 static int batch_grid(const gila_batch* b, size_t lds) {
     const DeviceInfo& di = device_info(b->device);
     const size_t per_cu = std::max<size_t>(1, std::min<size_t>(4, (160u * 1024u) / (lds + 1024)));
-    return (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)di.cus * (int64_t)per_cu, b->count));
+    return (int)std::max<int64_t>(
+        1, std::min<int64_t>(std::min<int64_t>((int64_t)di.cus * (int64_t)per_cu, b->count),
+                             b->escratch_grid));
 }
 
 // The tuner: for every row-length class present in the batch, times each
@@ -650,6 +909,7 @@ static int tune_plan(gila_batch* b, int precision, hipStream_t s, int32_t* table
     for (int32_t i = 0; i < b->count; ++i) {
         BatchDesc& d = desc[i];
         d.vbase = b->vbase[i];
+        d.sbase = b->sbase[i];
         d.n = b->n[i];
         d.n_active = b->n_active[i];
         d.cls = b->cls[i];
@@ -723,10 +983,17 @@ static int tune_plan(gila_batch* b, int precision, hipStream_t s, int32_t* table
             a.kidx = b->kidx;
             a.rp = b->rp;
             a.ci = b->ci16;
+            a.sell = b->d_sell;
+            a.smeta = b->d_smeta;
+            a.sk = b->d_sk;
+            a.sa = b->d_sa;
+            a.escratch = b->d_escratch;
+            a.slices_max = (b->nmax + 63) / 64;
             a.temps = d_t;
             a.stats = d_st;
             a.work = b->d_work;
-            const int grid = (int)std::min<int64_t>(a.count, device_info(b->device).cus);
+            const int grid = (int)std::min<int64_t>(std::min<int64_t>(a.count, device_info(b->device).cus),
+                                                    b->escratch_grid);
             hipLaunchKernelGGL(reset_work_kernel, dim3(1), dim3(1), 0, s, b->d_work);
             (void)hipEventRecord(e0, s);
             launch_batch_kernel(precision, grid, lds, s, a);
@@ -765,6 +1032,11 @@ void free_batch(gila_batch* b, Release rel) {
     rel(b->kidx);
     rel(b->rp);
     rel(b->ci16);
+    rel(b->d_sell);
+    rel(b->d_smeta);
+    rel(b->d_sk);
+    rel(b->d_sa);
+    rel(b->d_escratch);
     rel(b->d_desc);
     rel(b->d_order);
     rel(b->d_temps);
@@ -787,6 +1059,59 @@ struct DevTmp {
     explicit DevTmp(hipStream_t st) : s(st) {}
     ~DevTmp() { dfree_on(p, s); }
 };
+
+// The wave slices of every graph (see the file comment): vertex order, slice
+// sizes, offsets, interleaved rows and adjacency.  Needs the padded rows
+// (kptr, kidx), the union adjacency (rp) and its local ids (ci16).
+static int build_slices(gila_batch* b, const int64_t* d_vb, hipStream_t s) {
+    const int32_t count = b->count;
+    b->sbase.assign((size_t)count + 1, 0);
+    for (int32_t i = 0; i < count; ++i) b->sbase[i + 1] = b->sbase[i] + (b->n[i] + 63) / 64;
+    const int64_t S = b->sbase[count];
+    b->nslices = S;
+    // room for the largest persistent grid (four workgroups per CU)
+    b->escratch_grid = (int64_t)device_info(b->device).cus * 4;
+    GILA_TRY(dalloc_t(&b->d_escratch,
+                      (size_t)b->escratch_grid * 2 * (size_t)std::max(1, (b->nmax + 63) / 64)));
+    if (S == 0) return GILA_OK;
+    std::vector<int32_t> sgraph((size_t)S);
+    for (int32_t i = 0; i < count; ++i)
+        for (int64_t j = b->sbase[i]; j < b->sbase[i + 1]; ++j) sgraph[(size_t)j] = i;
+    DevTmp<uint16_t> d_order(s);
+    DevTmp<int32_t> d_sgraph(s);
+    DevTmp<int64_t> d_sb(s), d_szk(s), d_sza(s), d_koff(s), d_aoff(s);
+    GILA_TRY(dalloc_t(&d_order.p, (size_t)std::max<int64_t>(b->nv, 1)));
+    GILA_TRY(dalloc_t(&d_sgraph.p, (size_t)S));
+    GILA_TRY(dalloc_t(&d_sb.p, (size_t)count + 1));
+    GILA_TRY(dalloc_t(&d_szk.p, (size_t)S));
+    GILA_TRY(dalloc_t(&d_sza.p, (size_t)S));
+    GILA_TRY(dalloc_t(&d_koff.p, (size_t)S + 1));
+    GILA_TRY(dalloc_t(&d_aoff.p, (size_t)S + 1));
+    GILA_TRY(dalloc_t(&b->d_sell, (size_t)S));
+    GILA_TRY(dalloc_t(&b->d_smeta, (size_t)S * 64));
+    GILA_HIP(hipMemcpyAsync(d_sgraph.p, sgraph.data(), sizeof(int32_t) * S, hipMemcpyHostToDevice, s));
+    GILA_HIP(hipMemcpyAsync(d_sb.p, b->sbase.data(), sizeof(int64_t) * (count + 1),
+                            hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(row_order_kernel, dim3(count), dim3(kBlock), 0, s, d_vb, b->kptr, d_order.p);
+    GILA_HIP(hipGetLastError());
+    const int per_block = kBlock / 64;
+    const dim3 sg((unsigned)((S + per_block - 1) / per_block));
+    hipLaunchKernelGGL(sell_dims_kernel, sg, dim3(kBlock), 0, s, S, d_sgraph.p, d_vb, d_sb.p,
+                       b->kptr, b->rp, d_order.p, b->d_sell, b->d_smeta, d_szk.p, d_sza.p);
+    GILA_HIP(hipGetLastError());
+    GILA_TRY(exclusive_scan_i64(d_szk.p, d_koff.p, S, s));
+    GILA_TRY(exclusive_scan_i64(d_sza.p, d_aoff.p, S, s));
+    GILA_HIP(hipMemcpyAsync(&b->sell_quads, d_koff.p + S, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    GILA_HIP(hipMemcpyAsync(&b->sell_adj, d_aoff.p + S, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    GILA_HIP(hipStreamSynchronize(s));
+    GILA_TRY(dalloc_t(&b->d_sk, (size_t)std::max<int64_t>(b->sell_quads, 1)));
+    GILA_TRY(dalloc_t(&b->d_sa, (size_t)std::max<int64_t>(b->sell_adj, 1)));
+    hipLaunchKernelGGL(sell_fill_kernel, sg, dim3(kBlock), 0, s, S, d_sgraph.p, d_vb, b->kptr,
+                       b->kidx, b->rp, b->ci16, d_koff.p, d_aoff.p, b->d_smeta, b->d_sell,
+                       b->d_sk, b->d_sa);
+    GILA_HIP(hipGetLastError());
+    return GILA_OK;
+}
 
 int batch_build(const gila_csr* graphs, int32_t count, const int32_t* k, hipStream_t s,
                 gila_batch** out) {
@@ -973,6 +1298,8 @@ int batch_build(const gila_csr* graphs, int32_t count, const int32_t* k, hipStre
                                 hipMemcpyDeviceToHost, s));
     GILA_HIP(hipStreamSynchronize(s));
     pt.mark("localize+bounds");
+    GILA_TRY(build_slices(b, d_vb.p, s));
+    pt.mark("slices");
     b->Pg.assign(count, 0);
     b->cls.assign(count, 0);
     b->lpv.assign(count, 1);
@@ -997,7 +1324,10 @@ int batch_build(const gila_csr* graphs, int32_t count, const int32_t* k, hipStre
     GILA_HIP(hipStreamSynchronize(s));
     pt.mark("order");
     b->device_bytes = 8 * (2 * (b->nv + 1)) + 2 * (b->P_padded + b->nnz) +
-                      (int64_t)(sizeof(BatchDesc) + 4 + sizeof(gila_stats)) * count;
+                      (int64_t)(sizeof(BatchDesc) + 4 + sizeof(gila_stats)) * count +
+                      (int64_t)(sizeof(SellSlice) + 64 * sizeof(uint2)) * b->nslices +
+                      8 * b->sell_quads + 2 * b->sell_adj +
+                      16 * b->escratch_grid * (int64_t)std::max(1, (b->nmax + 63) / 64);
     *out = b;
     h.p = nullptr;
     return GILA_OK;
@@ -1029,6 +1359,7 @@ int batch_run(gila_batch* b, const gila_params* params, void* const* pos, hipStr
     for (int32_t i = 0; i < count; ++i) {
         BatchDesc& d = desc[i];
         d.vbase = b->vbase[i];
+        d.sbase = b->sbase[i];
         d.n = b->n[i];
         d.n_active = b->n_active[i];
         d.cls = b->cls[i];
@@ -1068,6 +1399,12 @@ int batch_run(gila_batch* b, const gila_params* params, void* const* pos, hipStr
     a.kidx = b->kidx;
     a.rp = b->rp;
     a.ci = b->ci16;
+    a.sell = b->d_sell;
+    a.smeta = b->d_smeta;
+    a.sk = b->d_sk;
+    a.sa = b->d_sa;
+    a.escratch = b->d_escratch;
+    a.slices_max = (b->nmax + 63) / 64;
     a.temps = b->d_temps;
     a.stats = b->d_stats;
     a.t_start = b->d_clock;

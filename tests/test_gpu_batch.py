@@ -288,3 +288,61 @@ def test_plan_is_fixed_at_build_and_reproducible(G):
         b3.set_plan(np.full(len(gs), 128))
     b1.free()
     b3.free()
+
+
+def test_wave_slices_forces_stats_and_large_graph(G):
+    """Graphs planned at one lane per vertex run from wave slices: FP64 forces
+    (one iteration, unbounded cap) and every statistic against the oracle,
+    with a coincident pair inside a row; and, in FP32, a 9,000-vertex graph
+    (beyond the sorted-order limit of 8,192, so its slices keep the identity
+    order) stepped against the oracle at the 1e-5 gate."""
+    gs = [(inputs.random_tree_plus_edges(300, 150, seed=31), 3),
+          (inputs.watts_strogatz(1000, 6, 0.1, seed=32), 2),
+          (inputs.barabasi_albert(2500, 2, seed=33), 2)]
+    dev = [G.to_device_csr(g) for g, _ in gs]
+    b = G.Batch(dev, [k for _, k in gs])
+    lanes, _ = b.plan()
+    assert (lanes == 1).all(), lanes
+    x0 = [inputs.uniform_positions(g.n, seed=40 + i, width=700.0) for i, (g, _) in enumerate(gs)]
+    g0 = gs[0][0]
+    u = int(g0.col_idx[g0.row_ptr[5]])
+    x0[0][u] = x0[0][5]                        # a coincident pair, one hop apart
+    pos = [_t(G, x, G.FP64) for x in x0]
+    params = [G.LayoutParams(temperature=np.array([1e300]), ideal_length=30.0, precision=G.FP64)
+              for _ in gs]
+    st = b.run(params, pos)
+    for i, (g, k) in enumerate(gs):
+        optr, oidx = oracle_rows(g, k)
+        xo, F, D, ost = oracle.step(g.n, g.row_ptr, g.col_idx, optr, oidx, 30.0, 1e300, x0[i])
+        Fg = pos[i].cpu().numpy() - x0[i]
+        assert rel_l2(Fg, F) <= 1e-10, (i, rel_l2(Fg, F))
+        assert st[i].coincident == ost.coincident, (i, st[i].coincident, ost.coincident)
+        assert st[i].moved == ost.moved, (i, st[i].moved, ost.moved)
+        assert abs(st[i].energy - ost.energy) <= 1e-10 * ost.energy, (i, st[i].energy, ost.energy)
+        assert abs(st[i].max_disp - ost.max_disp) <= 1e-10 * ost.max_disp, i
+    assert st[0].coincident > 0
+    b.free()
+
+    big = inputs.random_tree_plus_edges(9000, 4500, seed=34)
+    small = inputs.random_tree_plus_edges(700, 350, seed=35)
+    gs = [(big, 2), (small, 3)]
+    b = G.Batch([G.to_device_csr(g) for g, _ in gs], [k for _, k in gs])
+    assert (b.plan()[0] == 1).all()
+    rows = [oracle_rows(g, k) for g, k in gs]
+    xs = [inputs.uniform_positions(g.n, seed=50 + i, width=1200.0).astype(np.float32)
+          .astype(np.float64) for i, (g, _) in enumerate(gs)]
+    H = 4
+    temps = [G.paper_schedule(g.n, 1.0, 40.0, H) for g, _ in gs]
+    for h in range(H):
+        pos = [_t(G, x, G.FP32) for x in xs]
+        params = [G.LayoutParams(temperature=temps[i][h:h + 1], ideal_length=40.0,
+                                 precision=G.FP32) for i in range(len(gs))]
+        st = b.run(params, pos)
+        for i, (g, k) in enumerate(gs):
+            xo, _, _, ost = oracle.step(g.n, g.row_ptr, g.col_idx, rows[i][0], rows[i][1], 40.0,
+                                        temps[i][h], xs[i])
+            xn = pos[i].double().cpu().numpy()
+            assert pos_err(xn, xo) <= 1e-5, (h, i, pos_err(xn, xo))
+            assert abs(st[i].energy - ost.energy) <= 1e-4 * ost.energy, (h, i)
+            xs[i] = xn
+    b.free()
