@@ -216,17 +216,16 @@ int gila_step(const gila_khop* kh, const gila_params* params, int32_t h, void* p
 int gila_run(const gila_khop* kh, const gila_params* params, int32_t start_h, int32_t end_h,
              void* pos_dev, void* stream, gila_stats* out);
 
-/* Measurement: `reps` iterations h, h+1, ... on pos_dev, captured as a HIP
- * graph with event-record nodes before the force kernel, after it and after
- * the rest of each iteration, and replayed once on `stream` (eager launches
- * with the same events if the capture is refused).  ms_out[0] receives the
- * average duration of the force kernel (the segment kernel, or the
- * direct-gather kernel with the statistics kernel on that path), ms_out[1]
- * that of the rest of the iteration on the segment path (the combine and
- * statistics kernels; 0 on the direct path), ms_out[2] 1 if the times come
- * from a graph replay, 0 if from eager launches; ms_out holds 3 doubles.
- * Both durations come from one run, so ms_out[0] + ms_out[1] is that run's
- * iteration time.  pos_dev is advanced by the iterations.  Synchronises
+/* Measurement: iterations h .. h + reps - 1 run on `stream` exactly as
+ * gila_run runs them (captured as one HIP graph; eager launches if the
+ * capture is refused), advancing pos_dev, between two HIP events; on the
+ * segment path each force kernel also records on the device wall clock when
+ * its first workgroup started and its last one ended.  ms_out[0] receives the
+ * force kernel's average span (on the direct path, the whole iteration: its
+ * gather kernel moves the vertices itself), ms_out[1] the iteration's average
+ * from the events minus ms_out[0] (the combine and statistics kernels and the
+ * launch gaps; 0 on the direct path), ms_out[2] 1 if the iterations ran as a
+ * graph replay, 0 if eagerly; ms_out holds 3 doubles.  Synchronises
  * `stream`. */
 int gila_time_iterations(const gila_khop* kh, const gila_params* params, int32_t h,
                          int32_t reps, void* pos_dev, void* stream, double* ms_out);

@@ -174,6 +174,9 @@ struct SegArgs {
     const void* mass;           // repulsion weights (internal ids), null = unit
     int32_t att_p;              // force exponents (FR: 2, 1)
     int32_t rep_q;
+    // null, or [2]: the device wall clock when the launch's first workgroup
+    // started (atomic min) and its last one ended (atomic max)
+    unsigned long long* span;
 };
 
 // Arguments of the k-hop frontier-expansion kernel (khop.hip).
@@ -285,8 +288,9 @@ int enqueue_exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, int64
 // implemented in segment.hip
 int build_segments(gila_khop* kh, int precision, hipStream_t s);
 void free_segments(gila_khop* kh, Release rel = Release{});
+// span: null, or where the force kernel records its start and end (SegArgs)
 int launch_segment_step(const gila_khop* kh, int precision, const StepArgs& a, hipStream_t s,
-                        hipEvent_t* ev = nullptr);
+                        unsigned long long* span = nullptr);
 bool segment_path_enabled();
 // segment size S for the handle's graph in `precision` (weighted repulsion
 // stores a weight beside each staged position)

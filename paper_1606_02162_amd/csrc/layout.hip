@@ -559,14 +559,21 @@ int gila_time_iterations(const gila_khop* kh_c, const gila_params* params, int32
     hipStream_t s = (hipStream_t)stream;
     GILA_TRY(prepare_precision(kh, params->precision, s));
     const bool seg = segment_ready_for(kh, params->precision);
-    std::vector<hipEvent_t> ev((size_t)reps * 3, nullptr);
-    for (auto& e : ev)
-        if (hipEventCreate(&e) != hipSuccess) e = nullptr;
-    int rc = GILA_OK;
-    for (auto& e : ev)
-        if (!e) rc = fail(GILA_EDEVICE, "hipEventCreate failed");
-    // the iterations with an event before the force kernel, after it, and
-    // after the rest of the iteration
+    int khz = 0;
+    GILA_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, kh->device));
+    if (khz <= 0) return fail(GILA_EDEVICE, "no device wall clock rate");
+    // per iteration: the force kernel's first start and last end
+    std::vector<unsigned long long> span_h((size_t)2 * reps);
+    for (int32_t r = 0; r < reps; ++r) {
+        span_h[2 * r] = ~0ull;
+        span_h[2 * r + 1] = 0ull;
+    }
+    unsigned long long* span = nullptr;
+    GILA_TRY(dalloc_t(&span, span_h.size()));
+    GILA_HIP(hipMemcpyAsync(span, span_h.data(), sizeof(unsigned long long) * span_h.size(),
+                            hipMemcpyHostToDevice, s));
+    // the iterations h .. h + reps - 1 exactly as gila_run runs them (which
+    // advance pos_dev), the force kernels recording their spans
     auto enqueue = [&](hipStream_t q) -> int {
         hipLaunchKernelGGL(reset_ctl_kernel, dim3(1), dim3(1), 0, q, kh->ctl);
         GILA_HIP(hipGetLastError());
@@ -576,68 +583,70 @@ int gila_time_iterations(const gila_khop* kh_c, const gila_params* params, int32
             a.pos_cur = kh->pos[r & 1];
             a.pos_next = kh->pos[(r + 1) & 1];
             a.t = params->temperature[h + r];
-            hipEvent_t* e3 = &ev[(size_t)r * 3];
-            if (seg) {
-                GILA_TRY(launch_segment_step(kh, params->precision, a, q, e3));
-            } else {
-                GILA_HIP(hipEventRecordWithFlags(e3[0], q, hipEventRecordExternal));
-                GILA_TRY(launch_step(kh, params->precision, a, q));
-                GILA_HIP(hipEventRecordWithFlags(e3[1], q, hipEventRecordExternal));
-                GILA_HIP(hipEventRecordWithFlags(e3[2], q, hipEventRecordExternal));
-            }
+            if (seg) GILA_TRY(launch_segment_step(kh, params->precision, a, q, span + 2 * r));
+            else GILA_TRY(launch_step(kh, params->precision, a, q));
         }
         return launch_permute_out(kh, params->precision, pos_dev, q);
     };
-    // Preferred: one replay of the captured iterations, timed by the event
-    // nodes inside the graph (the way gila_run executes them).  If capture of
-    // event records is refused, the same launches run eagerly.
+    hipGraphExec_t exec = nullptr;
     bool in_graph = false;
-    if (rc == GILA_OK) {
-        hipGraphExec_t exec = nullptr;
+    {
         hipStream_t cs = capture_stream(kh->device);
         (void)hipGetLastError();  // no stale status may fail a check inside the capture
-        hipError_t be = hipErrorUnknown, ee = hipErrorUnknown, ie = hipErrorUnknown;
-        int erc = GILA_EDEVICE;
-        // (thread-local mode: the runtime refuses external event records in a
-        // relaxed capture)
-        if (cs && (be = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal)) == hipSuccess) {
-            erc = enqueue(cs);
+        if (cs && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+            const int erc = enqueue(cs);
             hipGraph_t graph = nullptr;
-            ee = hipStreamEndCapture(cs, &graph);
-            if (erc == GILA_OK && ee == hipSuccess && graph &&
-                (ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0)) == hipSuccess)
-                in_graph = true;
+            const hipError_t ee = hipStreamEndCapture(cs, &graph);
+            in_graph = erc == GILA_OK && ee == hipSuccess && graph &&
+                       hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
             if (graph) (void)hipGraphDestroy(graph);
+            if (!in_graph && getenv("GILA_DEBUG"))
+                fprintf(stderr, "[gila] timing capture refused: %d (%s), end %s\n", erc,
+                        gila_last_error(), hipGetErrorString(ee));
         }
-        if (!in_graph && getenv("GILA_DEBUG"))
-            fprintf(stderr, "[gila] timing capture refused: begin %s, enqueue %d (%s), end %s, "
-                            "instantiate %s\n", hipGetErrorString(be), erc, gila_last_error(),
-                    hipGetErrorString(ee), hipGetErrorString(ie));
         (void)hipGetLastError();
         clear_error();
+    }
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    int rc = GILA_OK;
+    for (auto& e : ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            e = nullptr;
+            rc = fail(GILA_EDEVICE, "hipEventCreate failed");
+        }
+    if (rc == GILA_OK && hipEventRecord(ev[0], s) != hipSuccess) rc = fail(GILA_EDEVICE, "event record");
+    if (rc == GILA_OK) {
         if (in_graph) {
             if (hipGraphLaunch(exec, s) != hipSuccess) rc = fail(GILA_EDEVICE, "graph launch");
-            (void)hipGraphExecDestroy(exec);
         } else {
             rc = enqueue(s);
         }
     }
+    if (rc == GILA_OK && hipEventRecord(ev[1], s) != hipSuccess) rc = fail(GILA_EDEVICE, "event record");
+    if (rc == GILA_OK &&
+        hipMemcpyAsync(span_h.data(), span, sizeof(unsigned long long) * span_h.size(),
+                       hipMemcpyDeviceToHost, s) != hipSuccess)
+        rc = fail(GILA_EDEVICE, "span download");
     if (rc == GILA_OK && hipStreamSynchronize(s) != hipSuccess)
         rc = fail(GILA_EDEVICE, "stream synchronise failed");
-    double f = 0.0, c = 0.0;
-    for (int32_t r = 0; r < reps && rc == GILA_OK; ++r) {
-        float t1 = 0.f, t2 = 0.f;
-        if (hipEventElapsedTime(&t1, ev[(size_t)r * 3], ev[(size_t)r * 3 + 1]) != hipSuccess ||
-            hipEventElapsedTime(&t2, ev[(size_t)r * 3 + 1], ev[(size_t)r * 3 + 2]) != hipSuccess)
-            rc = fail(GILA_EDEVICE, "hipEventElapsedTime failed");
-        f += t1;
-        c += t2;
-    }
+    float t = 0.f;
+    if (rc == GILA_OK && hipEventElapsedTime(&t, ev[0], ev[1]) != hipSuccess)
+        rc = fail(GILA_EDEVICE, "hipEventElapsedTime failed");
+    if (exec) (void)hipGraphExecDestroy(exec);
     for (auto& e : ev)
         if (e) (void)hipEventDestroy(e);
+    dfree_on(span, s);
     if (rc == GILA_OK) {
-        ms_out[0] = f / reps;
-        ms_out[1] = c / reps;
+        const double iter = (double)t / reps;
+        double f = iter;
+        if (seg) {
+            uint64_t ticks = 0;
+            for (int32_t r = 0; r < reps; ++r)
+                if (span_h[2 * r + 1] > span_h[2 * r]) ticks += span_h[2 * r + 1] - span_h[2 * r];
+            f = (double)ticks / (double)khz / reps;  // ticks / kHz = ms
+        }
+        ms_out[0] = f;
+        ms_out[1] = seg ? iter - f : 0.0;
         ms_out[2] = in_graph ? 1.0 : 0.0;
     }
     return rc;

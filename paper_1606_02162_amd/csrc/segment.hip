@@ -478,7 +478,11 @@ __global__ __launch_bounds__(seg_block<BIG>(), PREC == GILA_FP64 ? 4 : kSegWaves
     extern __shared__ __align__(16) unsigned char s_raw[];
     V* lp = reinterpret_cast<V*>(s_raw);
     __shared__ int64_t s_c[kSegBlock / 64];
-    if (a.ctl->stopped) return;
+    if (a.span && threadIdx.x == 0) atomicMin(&a.span[0], (unsigned long long)wall_clock64());
+    if (a.ctl->stopped) {
+        if (a.span && threadIdx.x == 0) atomicMax(&a.span[1], (unsigned long long)wall_clock64());
+        return;
+    }
     const int4 w = a.wg[blockIdx.x];
     const int s = w.x, ib = w.y, ie = w.z, lpv = w.w;
     // stage the segment's positions
@@ -521,6 +525,7 @@ __global__ __launch_bounds__(seg_block<BIG>(), PREC == GILA_FP64 ? 4 : kSegWaves
         int64_t c = 0;
         for (int i = 0; i < kSegBlock / 64; ++i) c += s_c[i];
         if (c) atomicAdd((unsigned long long*)&a.ctl->coinc_pending, (unsigned long long)c);
+        if (a.span) atomicMax(&a.span[1], (unsigned long long)wall_clock64());
     }
 }
 
@@ -891,7 +896,7 @@ static void launch_seg_force_q(int q, int precision, dim3 sg, size_t lds, hipStr
 }
 
 int launch_segment_step(const gila_khop* kh, int precision, const StepArgs& a, hipStream_t s,
-                        hipEvent_t* ev) {
+                        unsigned long long* span) {
     if (kh->n_active == 0) return GILA_OK;
     SegArgs g{};
     g.na = kh->n_active;
@@ -910,6 +915,7 @@ int launch_segment_step(const gila_khop* kh, int precision, const StepArgs& a, h
     g.mass = a.mass;
     g.att_p = a.att_p;
     g.rep_q = a.rep_q;
+    g.span = span;
     StepArgs c = a;
     c.vsl = kh->vsl;
     c.part = kh->part;
@@ -921,21 +927,16 @@ int launch_segment_step(const gila_khop* kh, int precision, const StepArgs& a, h
     const size_t lds = seg_lds_bytes(kh, precision, kh->seg);
     const dim3 sg(kh->seg_grid), cg(kh->comb_grid), cb(kBlock);
     const bool big = kh->seg_large;
-    // external records: under stream capture each becomes an event node that
-    // records when the replay reaches it (a timing point inside the graph)
-    if (ev) GILA_HIP(hipEventRecordWithFlags(ev[0], s, hipEventRecordExternal));
     if (a.mass && big) launch_seg_force_q<true, true>(a.rep_q, precision, sg, lds, s, g);
     else if (a.mass) launch_seg_force_q<true, false>(a.rep_q, precision, sg, lds, s, g);
     else if (big) launch_seg_force_q<false, true>(a.rep_q, precision, sg, lds, s, g);
     else launch_seg_force_q<false, false>(a.rep_q, precision, sg, lds, s, g);
-    if (ev) GILA_HIP(hipEventRecordWithFlags(ev[1], s, hipEventRecordExternal));
     switch (precision) {
         case GILA_FP64: hipLaunchKernelGGL(seg_combine_kernel<GILA_FP64>, cg, cb, 0, s, c); break;
         case GILA_FP32: hipLaunchKernelGGL(seg_combine_kernel<GILA_FP32>, cg, cb, 0, s, c); break;
         default: hipLaunchKernelGGL(seg_combine_kernel<GILA_FP32_KAHAN>, cg, cb, 0, s, c); break;
     }
     GILA_TRY(launch_iteration_stats(c, s));
-    if (ev) GILA_HIP(hipEventRecordWithFlags(ev[2], s, hipEventRecordExternal));
     GILA_HIP(hipGetLastError());
     return GILA_OK;
 }

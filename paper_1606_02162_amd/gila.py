@@ -383,10 +383,11 @@ def run(kh: KHop, params: LayoutParams, pos, start_h: int = 0, end_h: int | None
 def time_iterations(kh: KHop, params: LayoutParams, pos, h: int = 0, reps: int = 10,
                     stream=None, with_mode: bool = False):
     """Average (force kernel, rest of the iteration) milliseconds over `reps`
-    iterations starting at h, timed by HIP events inside one replay of the
-    captured iterations (gila_time_iterations).  With ``with_mode`` a third
-    value tells whether the times come from a graph replay (True) or, when
-    capture was refused, from eager launches (False)."""
+    iterations starting at h, run as gila_run runs them between HIP events,
+    the force kernel's share from its own start/end stamps on the device wall
+    clock (gila_time_iterations).  With ``with_mode`` a third value tells
+    whether the iterations ran as a graph replay (True) or, when capture was
+    refused, eagerly (False)."""
     ms = (ctypes.c_double * 3)()
     p = params.as_struct()
     _check(_lib.gila_time_iterations(kh.handle, ctypes.byref(p), int(h), int(reps), _ptr(pos),

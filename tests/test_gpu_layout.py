@@ -210,3 +210,36 @@ def test_layout_is_deterministic(G):
         G.layout(rp, ci, 2, params, pos)
         outs.append(_np(pos))
     assert np.array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("path", ["segment", "direct"])
+def test_time_iterations_advances_like_run(G, path):
+    """gila_time_iterations times graph replays (force kernel alone, then the
+    iterations) and leaves the positions exactly where gila_run does; the
+    force kernel's average does not exceed the iteration's."""
+    if path == "direct":
+        os.environ["GILA_PATH"] = "direct"
+    try:
+        g = inputs.random_tree_plus_edges(3000, 1500, seed=22)
+        rp, ci = G.to_device_csr(g)
+        kh = G.build_khop(rp, ci, 3)
+        H = 12
+        params = G.LayoutParams(temperature=G.paper_schedule(g.n, 1.0, 48.0, H),
+                                ideal_length=48.0, precision=G.FP32_KAHAN)
+        x0 = inputs.uniform_positions(g.n, seed=4, width=1200.0)
+        a = _t(G, x0, G.FP32_KAHAN)
+        G.run(kh, params, a, 0, 4)
+        G.run(kh, params, a, 4, H)
+        b = _t(G, x0, G.FP32_KAHAN)
+        G.run(kh, params, b, 0, 4)
+        force_ms, rest_ms, in_graph = G.time_iterations(kh, params, b, 4, H - 4, with_mode=True)
+        assert np.array_equal(_np(a), _np(b))
+        assert in_graph
+        assert force_ms > 0.0 and rest_ms >= 0.0, (force_ms, rest_ms)
+        if path == "direct":
+            assert rest_ms == 0.0
+        with pytest.raises(G.GilaError):
+            G.time_iterations(kh, params, b, 4, H)     # beyond the schedule
+        kh.free()
+    finally:
+        os.environ.pop("GILA_PATH", None)
