@@ -169,6 +169,10 @@ def main() -> int:
                     help="default line without its served (Poisson stream) object")
     ap.add_argument("--parity-samples", type=int, default=10000,
                     help="vertices sampled for the default line's parity object (0: none)")
+    ap.add_argument("--jsonl", default=None, metavar="PATH",
+                    help="also write JSON-lines records: every iteration's statistics of one "
+                         "more run of the workload, one record for the timed layout, and one per "
+                         "served job")
     ap.add_argument("--serve-jobs", type=int, default=2000)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -267,6 +271,8 @@ def bench_single(args, wl) -> int:
     t1 = time.perf_counter()
     total_s = t1 - t0
     assert st.iterations_run == H
+    print(f"[bench] {args.steps} timed steps: {total_s * 1e3 / args.steps:.1f} ms each",
+          file=sys.stderr, flush=True)
 
     # --- build time and iteration time, HIP events on the launch stream
     kh = gila.build_khop(rp, ci, k)
@@ -344,7 +350,9 @@ def bench_single(args, wl) -> int:
         import oracle
         threads = oracle.num_threads()
         if args.workload == "rmat" and mname == "fr" and args.parity_samples > 0:
+            print("[bench] parity against the oracle", file=sys.stderr, flush=True)
             out["parity"] = parity_leg(args, g, k, d, temps, kh, pos0, oracle)
+        print("[bench] oracle baseline", file=sys.stderr, flush=True)
         tc0 = time.perf_counter()
         optr, oidx = oracle.khop(g.n, g.row_ptr, g.col_idx, k)
         tc1 = time.perf_counter()
@@ -372,6 +380,17 @@ def bench_single(args, wl) -> int:
                        f"{single_iter * 1e3:.0f} ms"),
             "single_core_iteration_value": inter_per_iter / single_iter,
         }
+    if args.jsonl:
+        from paper_1606_02162_amd import records
+        kh.enable_history(H)
+        pos.copy_(pos0)
+        gila.run(kh, params, pos)
+        recs = records.iteration_records(kh.history(), temps, workload=out["config"]["workload"])
+        recs.append(records.job_record(total_s / args.steps, P, g.nnz, n_active, H,
+                                       workload=out["config"]["workload"],
+                                       note="one timed step: k-hop build + all iterations"))
+        records.write_jsonl(args.jsonl, recs)
+        kh.enable_history(0)
     kh.free()
     if args.workload == "rmat" and mname == "fr":
         if not args.no_batched:
@@ -380,7 +399,11 @@ def bench_single(args, wl) -> int:
         if not args.no_served:
             print("[bench] served form", file=sys.stderr, flush=True)
             from paper_1606_02162_amd import serving_bench
-            out["served"] = serving_bench.measure(args)
+            job_recs = [] if args.jsonl else None
+            out["served"] = serving_bench.measure(args, job_recs)
+            if args.jsonl:
+                from paper_1606_02162_amd import records
+                records.write_jsonl(args.jsonl, job_recs, append=True)
     print(json.dumps(with_traffic_rate(out)))
     return 0
 

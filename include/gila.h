@@ -230,6 +230,23 @@ int gila_run(const gila_khop* kh, const gila_params* params, int32_t start_h, in
 int gila_time_iterations(const gila_khop* kh, const gila_params* params, int32_t h,
                          int32_t reps, void* pos_dev, void* stream, double* ms_out);
 
+/* Per-iteration statistics.  After gila_enable_history(kh, capacity, ...),
+ * every iteration h < capacity that gila_step, gila_run or
+ * gila_time_iterations then runs on this handle writes its FP64 statistics --
+ * the energy sum_v |F_v|^2, the largest |Delta_v| and the number of vertices
+ * that moved more than stop_displacement (Section 5.1's halting statistic),
+ * and the coincident pairs -- as row h of a device table, the same values
+ * gila_stats reports for that iteration.  gila_history copies rows
+ * [h0, h0 + count) to rows_host[count][4] (energy, max_disp, moved,
+ * coincident); rows of iterations not run (past the schedule, or after the
+ * halting rule stopped the run) read as NaN.  capacity 0 frees the table.
+ * Enabling replaces the table (all rows NaN again) and drops the handle's
+ * captured loops.  EINVAL for a negative capacity or rows outside the table.
+ * Both synchronise `stream`. */
+int gila_enable_history(gila_khop* kh, int32_t capacity, void* stream);
+int gila_history(const gila_khop* kh, int32_t h0, int32_t count, double* rows_host,
+                 void* stream);
+
 /* Whole layout of one graph (the layout phase of Section 4.5 on a graph the
  * caller has already reduced as Sections 4.3 and 4.6 describe, or not):
  * gila_build_khop, gila_run over all params->iterations, free.

@@ -1473,6 +1473,7 @@ int gila_batch_build(const gila_csr* graphs_dev, int32_t count, const int32_t* k
 
 int gila_batch_run(gila_batch* b, const gila_params* params, void* const* pos_dev, void* stream,
                    gila_stats* out) {
+    TraceRange trace_range("gila_batch_run");
     clear_error();
     if (!b) return fail(GILA_EINVAL, "batch is NULL");
     std::lock_guard<std::mutex> lk(b->mu);
@@ -1577,6 +1578,7 @@ void gila_batch_free(gila_batch* b) { free_batch(b); }
 int gila_layout_batch(const gila_csr* graphs_dev, int32_t count, const int32_t* k,
                       const gila_params* params, void* const* pos_dev, void* stream,
                       gila_stats* out) {
+    TraceRange trace_range("gila_layout_batch");
     clear_error();
     gila_batch* b = nullptr;
     GILA_TRY(batch_build(graphs_dev, count, k, (hipStream_t)stream, &b));

@@ -856,6 +856,7 @@ int gila_components_noalloc(const gila_csr* g_dev, int32_t* label_dev, int32_t* 
 }
 
 int gila_components(const gila_csr* g_dev, int32_t* label_dev, int32_t* count_out, void* stream) {
+    TraceRange trace_range("gila_components");
     clear_error();
     hipStream_t s = (hipStream_t)stream;
     GILA_TRY(validate_graph(g_dev, s));
@@ -872,6 +873,7 @@ int gila_components(const gila_csr* g_dev, int32_t* label_dev, int32_t* count_ou
 
 int gila_pack_components(int32_t n, const int32_t* label_dev, double gap, int32_t precision,
                          void* pos_dev, void* stream) {
+    TraceRange trace_range("gila_pack_components");
     clear_error();
     if (n < 0) return fail(GILA_EINVAL, "n must be >= 0");
     if (n > 0 && (!label_dev || !pos_dev)) return fail(GILA_EINVAL, "label_dev or pos_dev is NULL");
@@ -903,6 +905,7 @@ int gila_pack_components(int32_t n, const int32_t* label_dev, double gap, int32_
 int gila_layout_components(const gila_csr* g_dev, int32_t k, const gila_params* params,
                            void* pos_dev, void* stream, int32_t* components_out,
                            int32_t* iterations_host) {
+    TraceRange trace_range("gila_layout_components");
     clear_error();
     if (!params) return fail(GILA_EINVAL, "params is NULL");
     gila_params p = *params;

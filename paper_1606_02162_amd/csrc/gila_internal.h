@@ -79,6 +79,15 @@ struct PhaseTimer {
     ~PhaseTimer();
 };
 
+// A roctx range (visible to rocprofv3 --marker-trace) for the lifetime of
+// the object: the library's entry points and the server's units of work.
+struct TraceRange {
+    explicit TraceRange(const char* name);
+    ~TraceRange();
+    TraceRange(const TraceRange&) = delete;
+    TraceRange& operator=(const TraceRange&) = delete;
+};
+
 // A library-owned, default-priority stream per device for graph capture.
 hipStream_t capture_stream(int device);
 

@@ -257,6 +257,7 @@ int enqueue_run(gila_khop* kh, const gila_params* p, int32_t start_h, int32_t en
         a.pos_cur = kh->pos[j & 1];
         a.pos_next = kh->pos[(j + 1) & 1];
         a.t = p->temperature[h];
+        a.hist_slot = h < kh->hist_cap ? h : -1;
         GILA_TRY(launch_iteration(kh, p->precision, a, s));
     }
     GILA_TRY(launch_permute_out(kh, p->precision, pos_dev, s));
@@ -489,6 +490,7 @@ int gila_init_positions(int32_t n, uint64_t seed, double width, double height, i
 
 int gila_step(const gila_khop* kh_c, const gila_params* params, int32_t h, void* pos_dev,
               double* force_dev, double* disp_dev, void* stream, gila_stats* out) {
+    TraceRange trace_range("gila_step");
     clear_error();
     gila_khop* kh = const_cast<gila_khop*>(kh_c);
     if (!kh) return fail(GILA_EINVAL, "handle is NULL");
@@ -515,6 +517,7 @@ int gila_step(const gila_khop* kh_c, const gila_params* params, int32_t h, void*
     a.pos_cur = kh->pos[0];
     a.pos_next = kh->pos[1];
     a.t = params->temperature[h];
+    a.hist_slot = h < kh->hist_cap ? h : -1;
     a.F_out = force_dev;
     a.D_out = disp_dev;
     GILA_TRY(launch_iteration(kh, params->precision, a, s));
@@ -532,6 +535,7 @@ int gila_step(const gila_khop* kh_c, const gila_params* params, int32_t h, void*
 
 int gila_run(const gila_khop* kh_c, const gila_params* params, int32_t start_h, int32_t end_h,
              void* pos_dev, void* stream, gila_stats* out) {
+    TraceRange trace_range("gila_run");
     clear_error();
     gila_khop* kh = const_cast<gila_khop*>(kh_c);
     if (!kh) return fail(GILA_EINVAL, "handle is NULL");
@@ -546,6 +550,7 @@ int gila_run(const gila_khop* kh_c, const gila_params* params, int32_t start_h, 
 
 int gila_time_iterations(const gila_khop* kh_c, const gila_params* params, int32_t h,
                          int32_t reps, void* pos_dev, void* stream, double* ms_out) {
+    TraceRange trace_range("gila_time_iterations");
     clear_error();
     gila_khop* kh = const_cast<gila_khop*>(kh_c);
     if (!kh) return fail(GILA_EINVAL, "handle is NULL");
@@ -583,6 +588,7 @@ int gila_time_iterations(const gila_khop* kh_c, const gila_params* params, int32
             a.pos_cur = kh->pos[r & 1];
             a.pos_next = kh->pos[(r + 1) & 1];
             a.t = params->temperature[h + r];
+            a.hist_slot = h + r < kh->hist_cap ? h + r : -1;
             if (seg) GILA_TRY(launch_segment_step(kh, params->precision, a, q, span + 2 * r));
             else GILA_TRY(launch_step(kh, params->precision, a, q));
         }
@@ -652,8 +658,51 @@ int gila_time_iterations(const gila_khop* kh_c, const gila_params* params, int32
     return rc;
 }
 
+int gila_enable_history(gila_khop* kh, int32_t capacity, void* stream) {
+    clear_error();
+    if (!kh) return fail(GILA_EINVAL, "handle is NULL");
+    if (capacity < 0) return fail(GILA_EINVAL, "capacity must be >= 0");
+    std::lock_guard<std::mutex> lk(kh->mu);
+    DeviceGuard dg(kh->device);
+    hipStream_t s = (hipStream_t)stream;
+    // captured loops hold the table's rows in their arguments
+    drop_graphs(kh);
+    dfree_on(kh->hist, s);
+    kh->hist = nullptr;
+    kh->hist_cap = 0;
+    if (capacity == 0) return GILA_OK;
+    GILA_TRY(dalloc_t(&kh->hist, (size_t)capacity * 4));
+    // rows of iterations not run read as NaN
+    const std::vector<double> nan((size_t)capacity * 4, std::nan(""));
+    GILA_HIP(hipMemcpyAsync(kh->hist, nan.data(), nan.size() * sizeof(double),
+                            hipMemcpyHostToDevice, s));
+    GILA_HIP(hipStreamSynchronize(s));
+    kh->hist_cap = capacity;
+    return GILA_OK;
+}
+
+int gila_history(const gila_khop* kh_c, int32_t h0, int32_t count, double* rows_host,
+                 void* stream) {
+    clear_error();
+    gila_khop* kh = const_cast<gila_khop*>(kh_c);
+    if (!kh) return fail(GILA_EINVAL, "handle is NULL");
+    if (h0 < 0 || count < 0 || (int64_t)h0 + count > kh->hist_cap)
+        return fail(GILA_EINVAL, "rows [%d, %lld) outside the history of %d rows", h0,
+                    (long long)h0 + count, kh->hist_cap);
+    if (count > 0 && !rows_host) return fail(GILA_EINVAL, "rows_host is NULL");
+    if (count == 0) return GILA_OK;
+    std::lock_guard<std::mutex> lk(kh->mu);
+    DeviceGuard dg(kh->device);
+    hipStream_t s = (hipStream_t)stream;
+    GILA_HIP(hipMemcpyAsync(rows_host, kh->hist + 4 * (int64_t)h0,
+                            sizeof(double) * 4 * (size_t)count, hipMemcpyDeviceToHost, s));
+    GILA_HIP(hipStreamSynchronize(s));
+    return GILA_OK;
+}
+
 int gila_layout(const gila_csr* g_dev, int32_t k, const gila_params* params, void* pos_dev,
                 void* stream, gila_stats* out) {
+    TraceRange trace_range("gila_layout");
     clear_error();
     GILA_TRY(check_params(params, true));
     gila_khop* kh = nullptr;

@@ -968,6 +968,7 @@ extern "C" {
 int gila_drawing_metrics(const gila_csr* g_dev, int32_t precision, const void* pos_dev,
                          int32_t what, void* stream, gila_metrics* out,
                          int64_t* edge_crossings_dev, double* jaccard_dev) {
+    TraceRange trace_range("gila_drawing_metrics");
     clear_error();
     if (!out) return fail(GILA_EINVAL, "out is NULL");
     if (precision != GILA_FP64 && precision != GILA_FP32 && precision != GILA_FP32_KAHAN)

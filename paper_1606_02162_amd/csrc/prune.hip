@@ -738,6 +738,7 @@ using namespace gila;
 extern "C" {
 
 int gila_prune(const gila_csr* g_dev, void* stream, gila_pruned** out) {
+    TraceRange trace_range("gila_prune");
     clear_error();
     return prune(g_dev, (hipStream_t)stream, out);
 }
@@ -788,6 +789,7 @@ int gila_pruned_gather(const gila_pruned* p, int32_t precision, const void* pos_
 
 int gila_reinsert(const gila_pruned* p, double ideal_length, int32_t precision,
                   const void* pos_kept_dev, void* pos_all_dev, void* stream) {
+    TraceRange trace_range("gila_reinsert");
     clear_error();
     return reinsert(p, ideal_length, precision, pos_kept_dev, pos_all_dev, (hipStream_t)stream);
 }
@@ -796,6 +798,7 @@ void gila_pruned_free(gila_pruned* p) { free_pruned(p); }
 
 int gila_layout_pruned(const gila_csr* g_dev, int32_t k, const gila_params* params, void* pos_dev,
                        void* stream, gila_stats* out) {
+    TraceRange trace_range("gila_layout_pruned");
     clear_error();
     GILA_TRY(check_params(params, true));
     if (k < 1) return fail(GILA_EINVAL, "k must be >= 1 (got %d)", k);

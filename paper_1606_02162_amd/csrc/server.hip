@@ -259,6 +259,7 @@ static void run_small_group(gila_server* s, std::vector<Job*>& group, hipStream_
     std::vector<gila_stats> st(ok.size());
     std::vector<int> rcs(ok.size(), rc);
     auto run_range = [&](size_t lo, size_t hi) {
+        TraceRange trace_range("gila_server: small-job batch");
         gila_batch* b = nullptr;
         const int32_t cnt = (int32_t)(hi - lo);
         int r = batch_build(&csr[lo], cnt, &ks[lo], sst, &b);
@@ -297,6 +298,7 @@ static void run_small_group(gila_server* s, std::vector<Job*>& group, hipStream_
 }
 
 static int admit_large(gila_server* s, Job* j) {
+    TraceRange trace_range("gila_server: large-job build");
     GILA_TRY(upload_job(s, j, s->build));
     gila_csr c{j->n, j->nnz, j->d_rp, j->d_ci};
     GILA_TRY(build_khop(&c, j->k, s->build, &j->kh));
@@ -480,6 +482,7 @@ static void ticker(gila_server* s) {
             if (!finished && j->cancel) finished = true;  // between ticks only
             if (!finished) {
                 // the next tick, asynchronously
+                TraceRange trace_range("gila_server: tick enqueue");
                 j->h_target = std::min(j->h + tick_iters, j->params.iterations);
                 hipStream_t st = s->compute[j->lane];
                 rc = enqueue_tick(j->kh, &j->params, j->h, j->h_target - j->h, tick_iters,

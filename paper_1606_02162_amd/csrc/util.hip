@@ -7,6 +7,8 @@
 #include <vector>
 #include <algorithm>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "device_util.h"
 #include "gila_internal.h"
 
@@ -97,13 +99,22 @@ static double wall_s() {
         .count();
 }
 
+TraceRange::TraceRange(const char* name) { roctxRangePushA(name); }
+TraceRange::~TraceRange() { roctxRangePop(); }
+
+// A phase timer is also a roctx range of the whole call, with a marker at
+// the end of each phase.
 PhaseTimer::PhaseTimer(const char* w, hipStream_t s) : what(w), stream(s) {
+    roctxRangePushA(w);
     const char* e = getenv("GILA_TIMING");
     on = e && e[0] == '1';
     t0 = last = on ? wall_s() : 0.0;
 }
 
 void PhaseTimer::mark(const char* phase) {
+    char name[96];
+    snprintf(name, sizeof(name), "%s: %s done", what, phase);
+    roctxMarkA(name);
     if (!on) return;
     (void)hipStreamSynchronize(stream);
     const double t = wall_s();
@@ -116,6 +127,7 @@ void PhaseTimer::mark(const char* phase) {
 PhaseTimer::~PhaseTimer() {
     if (on) fprintf(stderr, "[gila timing] %s total=%.2f ms:%s\n", what, (wall_s() - t0) * 1e3,
                     log.c_str());
+    roctxRangePop();
 }
 
 // A fixed buffer per thread: recording an error never allocates.

@@ -139,6 +139,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "gila_paper_schedule": (ctypes.c_int, [dbl, dbl, dbl, i32, vp]),
         "gila_linear_schedule": (ctypes.c_int, [dbl, i32, vp]),
         "gila_step": (ctypes.c_int, [vp, P(_Params), i32, vp, vp, vp, vp, P(Stats)]),
+        "gila_enable_history": (ctypes.c_int, [vp, i32, vp]),
+        "gila_history": (ctypes.c_int, [vp, i32, i32, vp, vp]),
         "gila_run": (ctypes.c_int, [vp, P(_Params), i32, i32, vp, vp, P(Stats)]),
         "gila_layout": (ctypes.c_int, [P(Csr), i32, P(_Params), vp, vp, P(Stats)]),
         "gila_time_iterations": (ctypes.c_int, [vp, P(_Params), i32, i32, vp, vp,
@@ -317,6 +319,24 @@ class KHop:
                                    ctypes.byref(na), ctypes.byref(b)), "gila_khop_info")
         return {"n": n.value, "k": k.value, "total_pairs": P.value, "n_active": na.value,
                 "device_bytes": b.value}
+
+    def enable_history(self, capacity: int, stream=None):
+        """Record the statistics of iterations 0 .. capacity-1 of later runs
+        on this handle (gila_enable_history; 0 frees the table)."""
+        _check(_lib.gila_enable_history(self._h, int(capacity), _stream(stream)),
+               "gila_enable_history")
+        self._hist_cap = int(capacity)
+
+    def history(self, h0: int = 0, count: int | None = None, stream=None) -> np.ndarray:
+        """Rows [h0, h0 + count) of the per-iteration statistics as float64
+        (count, 4): energy, max displacement, moved, coincident; NaN for
+        iterations not run (gila_history)."""
+        if count is None:
+            count = getattr(self, "_hist_cap", 0) - h0
+        rows = np.zeros((max(count, 0), 4), dtype=np.float64)
+        _check(_lib.gila_history(self._h, int(h0), int(count), rows.ctypes.data if count > 0 else None,
+                                 _stream(stream)), "gila_history")
+        return rows
 
     def export(self):
         inf = self.info()

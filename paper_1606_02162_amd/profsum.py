@@ -2,6 +2,7 @@
 
     python -m paper_1606_02162_amd.profsum trace DIR            # per-kernel stats
     python -m paper_1606_02162_amd.profsum counters DIR [KERNEL] # counter averages
+    python -m paper_1606_02162_amd.profsum ranges DIR            # roctx ranges (--marker-trace)
 
 and the traffic summary that bench.py reads:
 
@@ -100,6 +101,20 @@ def source_hash(root: str, files) -> str:
     return h.hexdigest()
 
 
+def range_stats(path: str):
+    """Per-name count, total, average and longest duration (ns) of the
+    marker regions (roctx ranges and marks) of a --marker-trace run."""
+    con = sqlite3.connect(_db(path))
+    # the range's text is the message argument in the region's extdata
+    rows = con.execute("select coalesce(json_extract(extdata, '$.message'), name) as label, "
+                       "category, count(*), sum(duration), avg(duration), max(duration) "
+                       "from regions where category like '%MARKER%' "
+                       "group by label, category order by sum(duration) desc").fetchall()
+    con.close()
+    return [{"name": r[0], "category": r[1], "calls": r[2], "total_ns": r[3] or 0,
+             "avg_ns": r[4] or 0, "max_ns": r[5] or 0} for r in rows]
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -111,6 +126,8 @@ def main(argv=None) -> int:
     c.add_argument("kernel", nargs="?")
     c.add_argument("--min-grid", type=int, default=0, help="only dispatches of >= this many threads")
     c.add_argument("--longest", action="store_true", help="only each kernel's longest dispatch")
+    rg = sub.add_parser("ranges")
+    rg.add_argument("dir")
     tr = sub.add_parser("traffic")
     for k in ("fetch", "write", "calib_fetch", "calib_write"):
         tr.add_argument("--" + k.replace("_", "-"), required=True)
@@ -127,6 +144,11 @@ def main(argv=None) -> int:
             print(f"{r['name'][:64]:<64} {r['calls']:>6} {r['avg_ns'] / 1e3:>10.1f} "
                   f"{r['min_ns'] / 1e3:>9.1f} {r['max_ns'] / 1e3:>9.1f} "
                   f"{r['total_ns'] / 1e6:>10.2f} {r['pct']:>6.2f}")
+    elif a.cmd == "ranges":
+        print(f"{'range':<48} {'calls':>7} {'avg ms':>10} {'max ms':>10} {'total ms':>11}")
+        for r in range_stats(a.dir):
+            print(f"{r['name'][:48]:<48} {r['calls']:>7} {r['avg_ns'] / 1e6:>10.3f} "
+                  f"{r['max_ns'] / 1e6:>10.3f} {r['total_ns'] / 1e6:>11.2f}")
     elif a.cmd == "counters":
         for r in counters(a.dir, a.kernel, a.min_grid, a.longest):
             print(f"{r['kernel'][:60]:<60} {r['counter']:<28} {r['avg']:>16.6g} "

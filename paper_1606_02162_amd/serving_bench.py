@@ -100,10 +100,12 @@ def _progress(msg: str) -> None:
     print(f"[serve] {msg}", file=sys.stderr, flush=True)
 
 
-def measure(args) -> dict:
+def measure(args, job_records=None) -> dict:
     """The served form: the Poisson stream through the server, the same jobs
     through the per-graph solver as a FIFO queue.  Returns the result object
-    (sub-config, throughput, latencies overall and by class, comparison)."""
+    (sub-config, throughput, latencies overall and by class, comparison);
+    with a list as ``job_records``, appends one ``served_job`` record per job
+    (its latency, interactions/s, algorithmic bytes/s, roofline fraction)."""
     import torch
     torch.cuda.set_device(0)
     count, rate = args.serve_jobs, args.serve_rate
@@ -116,13 +118,23 @@ def measure(args) -> dict:
     run_server(warm, np.zeros(len(warm)))
     lat, queued, wall, info = run_server(jobs, arrivals)
     _progress(f"server run done in {wall:.1f} s")
-    pairs = []
+    pairs, kpairs, actives = [], [], []
     for g, k, _ in jobs:
         # pairs per iteration counted by the library
         rp, ci = gila.to_device_csr(g)
         kh = gila.build_khop(rp, ci, k)
-        pairs.append(kh.info()["total_pairs"] + g.nnz)
+        inf = kh.info()
+        pairs.append(inf["total_pairs"] + g.nnz)
+        kpairs.append(inf["total_pairs"])
+        actives.append(inf["n_active"])
         kh.free()
+    if job_records is not None:
+        from paper_1606_02162_amd import records
+        for i, (g, k, _) in enumerate(jobs):
+            job_records.append(records.job_record(
+                lat[i] * 1e-3, kpairs[i], g.nnz, actives[i], 200, kind="served_job", job=i,
+                n=g.n, k=k, queued_ms=float(queued[i]),
+                note="submit to completion, host buffers in and out"))
     inter = float(np.sum(pairs)) * 200
     # plain per-graph solver on every 4th job; FIFO replay of the arrivals
     sample = list(range(0, count, 4))
@@ -172,7 +184,12 @@ def measure(args) -> dict:
 
 
 def main(args) -> int:
-    r = measure(args)
+    jsonl = getattr(args, "jsonl", None)
+    job_recs = [] if jsonl else None
+    r = measure(args, job_recs)
+    if jsonl:
+        from paper_1606_02162_amd import records
+        records.write_jsonl(jsonl, job_recs)
     out = {
         "metric": "served layouts: k-hop force interactions/s and p50/p99 latency",
         "value": r["interactions_per_s"], "unit": "interactions/s", "n_gpus": 1, "steps": 1,

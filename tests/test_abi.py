@@ -73,6 +73,8 @@ def test_argument_validation_before_device_work():
     assert L.gila_khop_info(None, None, None, None, None, None) == gila.GILA_EINVAL
     assert L.gila_run(None, None, 0, 0, None, None, None) == gila.GILA_EINVAL
     assert L.gila_step(None, None, 0, None, None, None, None, None) == gila.GILA_EINVAL
+    assert L.gila_enable_history(None, 10, None) == gila.GILA_EINVAL
+    assert L.gila_history(None, 0, 1, None, None) == gila.GILA_EINVAL
     # init positions: negative n, bad precision
     assert L.gila_init_positions(-1, 0, 1.0, 1.0, 1, None, None) == gila.GILA_EINVAL
     assert L.gila_init_positions(0, 0, 1.0, 1.0, 1, None, None) == gila.GILA_OK

@@ -243,3 +243,50 @@ def test_time_iterations_advances_like_run(G, path):
         kh.free()
     finally:
         os.environ.pop("GILA_PATH", None)
+
+
+@pytest.mark.parametrize("path", ["segment", "direct"])
+def test_history_rows_equal_step_statistics(G, path):
+    """Per-iteration history: each row of a run equals the statistics the same
+    iteration reports when taken alone (bitwise), rows past the schedule and
+    after the halting rule stopped the run stay NaN, and the table's bounds
+    are checked."""
+    if path == "direct":
+        os.environ["GILA_PATH"] = "direct"
+    try:
+        g = inputs.random_tree_plus_edges(2000, 1000, seed=23)
+        rp, ci = G.to_device_csr(g)
+        kh = G.build_khop(rp, ci, 2)
+        H = 15
+        params = G.LayoutParams(temperature=G.paper_schedule(g.n, 1.0, 48.0, H),
+                                ideal_length=48.0, precision=G.FP32_KAHAN)
+        x0 = inputs.uniform_positions(g.n, seed=5, width=1200.0)
+        kh.enable_history(H + 5)
+        a = _t(G, x0, G.FP32_KAHAN)
+        st = G.run(kh, params, a)
+        hist = kh.history()
+        assert hist.shape == (H + 5, 4)
+        assert np.isnan(hist[H:]).all() and np.isfinite(hist[:H]).all()
+        assert tuple(hist[H - 1]) == (st.energy, st.max_disp, float(st.moved), float(st.coincident))
+        b = _t(G, x0, G.FP32_KAHAN)
+        for h in range(H):
+            sh = G.step(kh, params, h, b)
+            assert tuple(hist[h]) == (sh.energy, sh.max_disp, float(sh.moved),
+                                      float(sh.coincident)), h
+        # the halting rule: rows after the last iteration run stay NaN
+        long = G.LayoutParams(temperature=G.paper_schedule(g.n, 1.0, 48.0, 400), ideal_length=48.0,
+                              precision=G.FP32_KAHAN, stop_fraction=0.15)
+        kh.enable_history(400)
+        c = _t(G, x0, G.FP32_KAHAN)
+        st = G.run(kh, long, c)
+        r = st.iterations_run
+        assert st.stopped == 1 and r < 400
+        hist = kh.history()
+        assert np.isfinite(hist[:r]).all() and np.isnan(hist[r:]).all()
+        assert hist[r - 1, 2] < 0.15 * int((np.diff(g.row_ptr) > 0).sum())
+        with pytest.raises(G.GilaError):
+            kh.history(395, 10)
+        kh.enable_history(0)
+        kh.free()
+    finally:
+        os.environ.pop("GILA_PATH", None)
