@@ -78,20 +78,25 @@ __global__ __launch_bounds__(kBlock) void validate_csr_kernel(int32_t n, int64_t
 // With the bitmap in LDS, a summary bitmap (one bit per bitmap word) records
 // the words a source touched, so clearing and scanning cost O(n/1024 + |row|)
 // per source instead of O(n/32).
+// Frontier rows at least this long are walked by a whole wavefront.
+constexpr int64_t kWaveRow = 32;
+
 template <bool FILL, bool LDS_BITMAP>
 __global__ __launch_bounds__(kBlock) void khop_bfs_kernel(BfsArgs a) {
     extern __shared__ uint32_t s_dyn[];
     constexpr bool SUMMARY = LDS_BITMAP;
     __shared__ int32_t s_v;
     __shared__ int32_t s_qtail;
-    __shared__ int64_t s_incl[kBlock];   // inclusive prefix of frontier-chunk degrees
-    __shared__ int64_t s_start[kBlock];  // row start of each frontier-chunk vertex
+    __shared__ int64_t s_incl[kBlock];   // degree of each listed long frontier row
+    __shared__ int64_t s_start[kBlock];  // row start of each listed long frontier row
+    __shared__ int32_t s_nbig;           // long rows listed in this chunk
     __shared__ int64_t s_red[4];
 
     uint32_t* bm = LDS_BITMAP ? s_dyn : a.gbitmap + (size_t)blockIdx.x * a.nwords;
     uint32_t* sm = s_dyn + a.nwords;  // summary (LDS bitmap only)
     int32_t* queue = a.queue ? a.queue + (size_t)blockIdx.x * a.qcap : nullptr;
 
+    if (threadIdx.x == 0) s_nbig = 0;
     for (int i = threadIdx.x; i < a.nwords; i += kBlock) bm[i] = 0u;
     if constexpr (SUMMARY)
         for (int i = threadIdx.x; i < (a.nwords + 31) / 32; i += kBlock) sm[i] = 0u;
@@ -136,12 +141,27 @@ __global__ __launch_bounds__(kBlock) void khop_bfs_kernel(BfsArgs a) {
             for (int64_t e = rb + threadIdx.x; e < re; e += kBlock)
                 if (visit(a.ci[e] - base)) ++mycount;
             __syncthreads();
-            // levels 2..k: expand the previous level's new vertices
+            // levels 2..k: expand the previous level's new vertices.  A frontier
+            // vertex with a short row is walked by one lane; long rows are
+            // listed in LDS and walked by whole wavefronts (coalesced reads).
+            // The visited set does not depend on the order of the visits.
             int64_t fb = rb, fe = re;
             bool from_queue = false;
             for (int level = 2; level <= k; ++level) {
                 const bool record = level < k;
                 const int32_t qstart = s_qtail;
+                // every thread has read the level's queue start before any
+                // thread appends to the queue
+                __syncthreads();
+                auto expand = [&](int32_t ug) {
+                    if (visit(ug - base)) {
+                        ++mycount;
+                        if (record) {
+                            const int32_t q = atomicAdd(&s_qtail, 1);
+                            queue[q] = ug;
+                        }
+                    }
+                };
                 for (int64_t c = fb; c < fe; c += kBlock) {
                     const int64_t i = c + threadIdx.x;
                     int64_t deg = 0, start = 0;
@@ -150,28 +170,21 @@ __global__ __launch_bounds__(kBlock) void khop_bfs_kernel(BfsArgs a) {
                         start = a.rp[w];
                         deg = a.rp[w + 1] - start;
                     }
-                    int64_t total;
-                    const int64_t ex = block_exclusive_scan<int64_t>(deg, s_red, total);
-                    s_incl[threadIdx.x] = ex + deg;
-                    s_start[threadIdx.x] = start;
-                    __syncthreads();
-                    for (int64_t j = threadIdx.x; j < total; j += kBlock) {
-                        int lo = 0, hi = kBlock - 1;
-                        while (lo < hi) {
-                            const int mid = (lo + hi) >> 1;
-                            if (s_incl[mid] > j) hi = mid;
-                            else lo = mid + 1;
-                        }
-                        const int64_t off = j - (lo ? s_incl[lo - 1] : 0);
-                        const int32_t ug = a.ci[s_start[lo] + off];
-                        if (visit(ug - base)) {
-                            ++mycount;
-                            if (record) {
-                                const int32_t q = atomicAdd(&s_qtail, 1);
-                                queue[q] = ug;
-                            }
-                        }
+                    if (deg >= kWaveRow) {
+                        const int b = atomicAdd(&s_nbig, 1);
+                        s_start[b] = start;
+                        s_incl[b] = deg;
+                    } else {
+                        for (int64_t e = 0; e < deg; ++e) expand(a.ci[start + e]);
                     }
+                    __syncthreads();
+                    const int nbig = s_nbig;
+                    for (int b = wave_id(); b < nbig; b += kWaves) {
+                        const int64_t bs = s_start[b], bd = s_incl[b];
+                        for (int64_t e = lane64(); e < bd; e += 64) expand(a.ci[bs + e]);
+                    }
+                    __syncthreads();
+                    if (threadIdx.x == 0) s_nbig = 0;
                     __syncthreads();
                 }
                 fb = qstart;
@@ -331,7 +344,10 @@ int run_bfs(bool fill, int device, hipStream_t s, BfsArgs a) {
     const DeviceInfo& di = device_info(device);
     // LDS bitmap: one bit per vertex id plus the summary (one bit per word)
     const size_t bm_bytes = ((size_t)a.nwords + ((size_t)a.nwords + 31) / 32) * 4;
-    const bool lds = bm_bytes + 8 * 1024 * 2 + 1024 <= di.max_lds_per_block;
+    // (GILA_BFS_BITMAP=global takes the global-memory bitmap whatever n is)
+    const char* bm_env = getenv("GILA_BFS_BITMAP");
+    const bool lds = bm_bytes + 8 * 1024 * 2 + 1024 <= di.max_lds_per_block &&
+                     !(bm_env && std::strcmp(bm_env, "global") == 0);
     // workgroups resident per CU limited by LDS (160 KB per CU on gfx950)
     int per_cu = 8;
     if (lds) {

@@ -41,6 +41,39 @@ def test_small_graphs_bit_exact(G, k):
         kh.free()
 
 
+@pytest.mark.parametrize("k", [2, 3])
+def test_global_bitmap_path_bit_exact(G, k, monkeypatch):
+    """The frontier expansion with its bitmap in global memory (the path of
+    graphs too large for an LDS bitmap), forced on graphs of every family:
+    the same rows as the oracle."""
+    monkeypatch.setenv("GILA_BFS_BITMAP", "global")
+    for g in small_graph_suite():
+        if g.n > 5000:
+            continue
+        kh = _build(G, g, k)
+        ptr, idx = kh.export()
+        optr, oidx = oracle_rows(g, k)
+        assert np.array_equal(ptr, optr), g.name
+        assert np.array_equal(idx, oidx), g.name
+        kh.free()
+
+
+def test_repeated_builds_with_queued_frontiers(G):
+    """k >= 3 records each level's new vertices in a per-workgroup queue that
+    the next level expands; repeated builds of graphs with many short and some
+    long frontier rows give the oracle's rows every time."""
+    cases = [(inputs.barabasi_albert(20000, 3, seed=41), 3),
+             (inputs.watts_strogatz(20000, 6, 0.1, seed=42), 4)]
+    for g, k in cases:
+        optr, oidx = oracle_rows(g, k)
+        for rep in range(4):
+            kh = _build(G, g, k)
+            ptr, idx = kh.export()
+            assert np.array_equal(ptr, optr), (g.name, k, rep)
+            assert np.array_equal(idx, oidx), (g.name, k, rep)
+            kh.free()
+
+
 def test_grid32_config_total(G):
     g = inputs.grid_graph(32, 32)
     kh = _build(G, g, 2)
