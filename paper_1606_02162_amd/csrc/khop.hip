@@ -15,6 +15,7 @@
 
 #include "device_util.h"
 #include "gila_internal.h"
+#include "host_logic.h"
 
 namespace gila {
 
@@ -478,43 +479,7 @@ static bool use_caller_order(unsigned long long near_edges, int64_t nnz) {
     return nnz > 0 && (double)near_edges >= 0.7 * (double)nnz;
 }
 
-// perm[i] = caller id of internal vertex i.  Isolated vertices last (caller
-// order).  Degree order: |N_v(k)| descending, ties by caller id.  Caller
-// order: rows of at least kHubMin entries first, then the others, each in
-// the caller's order.  Stable LSD radix sort (11-bit digits) on the key.
-static void order_vertices(const std::vector<int64_t>& counts, const std::vector<int64_t>& rp,
-                           bool caller_order, std::vector<int32_t>& perm) {
-    const int32_t n = (int32_t)counts.size();
-    int64_t maxc = 0;
-    for (int32_t v = 0; v < n; ++v) maxc = std::max(maxc, counts[v]);
-    std::vector<uint64_t> key((size_t)n);
-    for (int32_t v = 0; v < n; ++v) {
-        const bool isolated = rp[v + 1] == rp[v];
-        if (caller_order)
-            key[v] = isolated ? 2 : (counts[v] >= kHubMin ? 0 : 1);
-        else
-            key[v] = isolated ? (uint64_t)maxc + 1 : (uint64_t)(maxc - counts[v]);
-    }
-    const uint64_t kmax = caller_order ? 2 : (uint64_t)maxc + 1;
-    std::vector<int32_t> tmp((size_t)n);
-    for (int32_t v = 0; v < n; ++v) perm[v] = v;
-    constexpr int kBits = 11;
-    std::vector<int64_t> cnt((size_t)1 << kBits);
-    for (int shift = 0; shift < 64 && (kmax >> shift) > 0; shift += kBits) {
-        std::fill(cnt.begin(), cnt.end(), 0);
-        const uint64_t mask = ((uint64_t)1 << kBits) - 1;
-        for (int32_t i = 0; i < n; ++i) ++cnt[(key[perm[i]] >> shift) & mask];
-        int64_t run = 0;
-        for (auto& c : cnt) {
-            const int64_t t = c;
-            c = run;
-            run += t;
-        }
-        for (int32_t i = 0; i < n; ++i) tmp[cnt[(key[perm[i]] >> shift) & mask]++] = perm[i];
-        perm.swap(tmp);
-    }
-}
-
+// The internal order itself: host::order_vertices (host_logic.h).
 int build_khop(const gila_csr* g, int32_t k, hipStream_t s, gila_khop** out) {
     if (!out) return fail(GILA_EINVAL, "out is NULL");
     *out = nullptr;
@@ -615,7 +580,10 @@ int build_khop(const gila_csr* g, int32_t k, hipStream_t s, gila_khop** out) {
     // --- internal order (non-isolated vertices first)
     kh->caller_order = use_caller_order(near_edges, nnz);
     std::vector<int32_t> perm((size_t)n), iperm((size_t)n);
-    order_vertices(counts, rp_host, kh->caller_order, perm);
+    {
+        std::vector<uint64_t> w, tmp;
+        host::order_vertices(counts, rp_host, kh->caller_order, kHubMin, perm, w, tmp);
+    }
     for (int32_t i = 0; i < n; ++i) iperm[perm[i]] = i;
     int64_t P = 0;
     int32_t n_active = 0;
