@@ -49,6 +49,9 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_seg_force_rmat18.json")
 TRAFFIC_FILE_PRUNED = os.path.join(ROOT, "profiles", "traffic_seg_force_weighted_rmat18_pruned.json")
 TRAFFIC_FILE_METRICS = os.path.join(ROOT, "profiles", "traffic_crossings_rmat18_layout.json")
 TRAFFIC_FILE_BATCH = os.path.join(ROOT, "profiles", "traffic_batch_layout_batch4096.json")
+TRAFFIC_FILE_BA = os.path.join(ROOT, "profiles", "traffic_seg_force_ba100k.json")
+# counter summaries of the single-graph force kernels (FR model), by workload
+TRAFFIC_FILE_BY_WORKLOAD = {"rmat": TRAFFIC_FILE, "ba": TRAFFIC_FILE_BA}
 KERNEL_SOURCES = ["paper_1606_02162_amd/csrc/segment.hip", "paper_1606_02162_amd/csrc/iteration.h",
                   "paper_1606_02162_amd/csrc/gila_internal.h"]
 
@@ -326,7 +329,8 @@ def bench_single(args, wl) -> int:
         "build_ms": build_ms,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": (measured_traffic() if args.workload == "rmat" and mname == "fr"
+                     "traffic": (measured_traffic(TRAFFIC_FILE_BY_WORKLOAD[args.workload])
+                                 if mname == "fr" and args.workload in TRAFFIC_FILE_BY_WORKLOAD
                                  else None),
                      "kernel": f"seg_force_kernel<{prec_name}" + (">" if fq == 1 else ", q>") +
                                ("" if mname == "fr" else f" ({mname})"),
