@@ -65,7 +65,8 @@ struct BatchArgs {
     int32_t count;
     const BatchDesc* graphs;
     const int32_t* order;      // graphs in decreasing work
-    const int64_t* kptr;       // union k-hop row offsets
+    const int64_t* kstart;     // [nv]: start of each k-hop row in kidx
+    const int32_t* klen;       // [nv]: its length, padded to whole quads
     const uint16_t* kidx;      // local ids
     const int64_t* rp;         // union adjacency row offsets
     const uint16_t* ci;        // local ids
@@ -87,14 +88,16 @@ struct BatchArgs {
 struct gila_batch {
     int device = 0;
     int32_t count = 0;
-    int64_t nv = 0, nnz = 0, P = 0, P_padded = 0;  // pairs; entries of the quad-padded rows
+    int64_t nv = 0, nnz = 0, P = 0;  // vertices, adjacency entries, pairs
     int64_t device_bytes = 0;
     int32_t nmax = 0;
     std::vector<int64_t> vbase, ebase, Pg, sbase;
     std::vector<int32_t> n, n_active, k, cls;
     std::vector<int32_t> lpv;  // the plan: lanes per vertex of each graph
-    int64_t* kptr = nullptr;
+    int64_t* kstart = nullptr;  // [nv]: start of each k-hop row in kidx
+    int32_t* klen = nullptr;    // [nv]: its length, padded to whole quads
     uint16_t* kidx = nullptr;
+    int64_t kidx_size = 0;      // entries of kidx (the rows and the blocks' slack)
     int64_t* rp = nullptr;
     uint16_t* ci16 = nullptr;
     int64_t nslices = 0, sell_quads = 0, sell_adj = 0;
@@ -203,9 +206,11 @@ struct BatchBfsArgs {
     const int64_t* rp;       // union CSR (global ids)
     const int32_t* ci;
     const int32_t* gk;       // k of each graph
-    int64_t* counts;         // count pass: [nv]
-    const int64_t* kptr;     // fill pass: [nv + 1]
-    uint16_t* kidx;          // fill pass: local ids
+    const int64_t* gbase;    // [count]: start of each graph's block of kidx
+    int64_t* counts;         // [nv]: |N_v(k)|
+    int64_t* kstart;         // [nv]: start of each row in kidx
+    int32_t* klen;           // [nv]: its length, padded to whole quads
+    uint16_t* kidx;          // local ids, each row padded with the sentinel n
     int32_t* work;           // next graph (atomic)
     int32_t nmax;            // largest graph: vertices ...
     int64_t nnzmax;          // ... and adjacency entries
@@ -217,10 +222,16 @@ size_t batch_bfs_lds_bytes(int32_t nmax, int64_t nnzmax) {
            4 * nwords * 3 * kBfsWaves;
 }
 
-template <bool FILL>
+// One pass per source: after its BFS the wavefront knows |N_v(k)|, takes the
+// row's place (padded to quads) from the graph's cursor in LDS inside the
+// graph's block of kidx -- sized by a walk-count bound of the graph's rows
+// (walk_bound_kernel), so it never overflows -- and writes the row ascending
+// from the visited bitmap, then the padding.  Where a row lands in the block
+// depends on which wavefront finishes first; what it holds does not.
 __global__ __launch_bounds__(kBfsBlock) void batch_khop_kernel(BatchBfsArgs a) {
     extern __shared__ __align__(16) unsigned char s_raw[];
     __shared__ int s_g;
+    __shared__ unsigned long long s_cursor;
     const int nwords_max = (a.nmax + 31) / 32;
     int32_t* s_rp = reinterpret_cast<int32_t*>(s_raw);
     uint16_t* s_ci = reinterpret_cast<uint16_t*>(s_rp + a.nmax + 1);
@@ -241,8 +252,10 @@ __global__ __launch_bounds__(kBfsBlock) void batch_khop_kernel(BatchBfsArgs a) {
         const int64_t ne = a.rp[vb + n] - eb;
         for (int i = threadIdx.x; i <= n; i += kBfsBlock) s_rp[i] = (int32_t)(a.rp[vb + i] - eb);
         for (int64_t j = threadIdx.x; j < ne; j += kBfsBlock) s_ci[j] = (uint16_t)(a.ci[eb + j] - vb);
+        if (threadIdx.x == 0) s_cursor = 0ull;
         __syncthreads();
         const int nw = (n + 31) >> 5;
+        const int64_t gb = a.gbase[g];
         for (int src = w; src < n; src += kBfsWaves) {
             uint32_t* cur = vis + nwords_max;
             uint32_t* nxt = cur + nwords_max;
@@ -284,49 +297,109 @@ __global__ __launch_bounds__(kBfsBlock) void batch_khop_kernel(BatchBfsArgs a) {
                 nxt = t;
                 if (__ballot(added > 0) == 0ull) break;
             }
-            if constexpr (!FILL) {
-                const int total = wave_sum(found);
-                if (lane == 0) a.counts[vb + src] = total;
-            } else {
-                // the row: visited ids except src, ascending
-                int64_t out = a.kptr[vb + src];
-                for (int i0 = 0; i0 < nw; i0 += 64) {
-                    const int i = i0 + lane;
-                    uint32_t bits = i < nw ? vis[i] : 0u;
-                    if (i == (src >> 5)) bits &= ~(1u << (src & 31));
-                    const int c = __popc(bits);
-                    const int incl = wave_inclusive_scan(c);
-                    int64_t at = out + incl - c;
-                    while (bits) {
-                        a.kidx[at++] = (uint16_t)(i * 32 + __builtin_ctz(bits));
-                        bits &= bits - 1u;
-                    }
-                    out += __shfl(incl, 63, 64);
-                }
+            // the row's place: |N_v(k)| padded to quads, from the graph's cursor
+            const int total = wave_sum(found);
+            const int padded = (total + 3) & ~3;
+            unsigned long long off = 0ull;
+            if (lane == 0) off = atomicAdd(&s_cursor, (unsigned long long)padded);
+            off = __shfl(off, 0, 64);
+            const int64_t start = gb + (int64_t)off;
+            if (lane == 0) {
+                a.counts[vb + src] = total;
+                a.kstart[vb + src] = start;
+                a.klen[vb + src] = padded;
             }
+            // the row: visited ids except src, ascending
+            int64_t out = start;
+            for (int i0 = 0; i0 < nw; i0 += 64) {
+                const int i = i0 + lane;
+                uint32_t bits = i < nw ? vis[i] : 0u;
+                if (i == (src >> 5)) bits &= ~(1u << (src & 31));
+                const int c = __popc(bits);
+                const int incl = wave_inclusive_scan(c);
+                int64_t at = out + incl - c;
+                while (bits) {
+                    a.kidx[at++] = (uint16_t)(i * 32 + __builtin_ctz(bits));
+                    bits &= bits - 1u;
+                }
+                out += __shfl(incl, 63, 64);
+            }
+            for (int j = total + lane; j < padded; j += 64) a.kidx[start + j] = (uint16_t)n;
             __builtin_amdgcn_wave_barrier();
         }
         __syncthreads();
     }
 }
 
-static int run_batch_bfs(bool fill, const BatchBfsArgs& a, size_t lds, int device, hipStream_t s) {
-    if (lds > 48 * 1024) {
-        (void)hipFuncSetAttribute((const void*)batch_khop_kernel<false>,
+static int run_batch_bfs(const BatchBfsArgs& a, size_t lds, int device, hipStream_t s) {
+    if (lds > 48 * 1024)
+        (void)hipFuncSetAttribute((const void*)batch_khop_kernel,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        (void)hipFuncSetAttribute((const void*)batch_khop_kernel<true>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    }
     const DeviceInfo& di = device_info(device);
     const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(4, (160u * 1024u) / (lds + 1024)));
     const int grid = std::min(a.count, di.cus * per_cu);
     GILA_HIP(hipMemsetAsync(a.work, 0, sizeof(int32_t), s));
-    if (fill)
-        hipLaunchKernelGGL(batch_khop_kernel<true>, dim3(grid), dim3(kBfsBlock), lds, s, a);
-    else
-        hipLaunchKernelGGL(batch_khop_kernel<false>, dim3(grid), dim3(kBfsBlock), lds, s, a);
+    hipLaunchKernelGGL(batch_khop_kernel, dim3(grid), dim3(kBfsBlock), lds, s, a);
     GILA_HIP(hipGetLastError());
     return GILA_OK;
+}
+
+// ------------------------------------------------------------------ row blocks
+// An upper bound of each vertex's padded row: the walks of length <= k (its
+// graph's k) from v, capped at n_g - 1 (|N_v(k)| counts distinct vertices
+// reached by such walks), rounded up to whole quads.  Level l adds the walks
+// of length l: w_l(v) = sum of w_{l-1}(u) over u adjacent to v (capped at
+// n_g, which keeps the sums small and the bound valid).  One launch per level.
+__global__ void vertex_graph_kernel(const int64_t* __restrict__ vbase, int32_t* __restrict__ vgraph) {
+    const int64_t vb = vbase[blockIdx.x], ve = vbase[blockIdx.x + 1];
+    for (int64_t v = vb + threadIdx.x; v < ve; v += blockDim.x) vgraph[v] = (int32_t)blockIdx.x;
+}
+
+__global__ void walk_init_kernel(int64_t nv, const int64_t* __restrict__ rp,
+                                 int64_t* __restrict__ cur, int64_t* __restrict__ tot) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nv;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t d = rp[v + 1] - rp[v];
+        cur[v] = d;
+        tot[v] = d;
+    }
+}
+
+__global__ void walk_level_kernel(int64_t nv, const int64_t* __restrict__ rp,
+                                  const int32_t* __restrict__ ci, const int32_t* __restrict__ vgraph,
+                                  const int64_t* __restrict__ vbase, const int32_t* __restrict__ gk,
+                                  int32_t level, const int64_t* __restrict__ cur,
+                                  int64_t* __restrict__ nxt, int64_t* __restrict__ tot) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nv;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t g = vgraph[v];
+        const int64_t ng = vbase[g + 1] - vbase[g];
+        int64_t w = 0;
+        if (level <= gk[g]) {
+            for (int64_t e = rp[v]; e < rp[v + 1]; ++e) w += cur[ci[e]];
+            w = w < ng ? w : ng;
+            const int64_t t = tot[v] + w;
+            tot[v] = t < ng - 1 ? t : ng - 1;
+        }
+        nxt[v] = w;
+    }
+}
+
+__global__ void walk_pad_kernel(int64_t nv, const int64_t* __restrict__ tot,
+                                int64_t* __restrict__ padded) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nv;
+         v += (int64_t)gridDim.x * blockDim.x)
+        padded[v] = (tot[v] + 3) & ~(int64_t)3;
+}
+
+// Row starts and padded lengths from prefix offsets (the per-source path).
+__global__ void rows_from_offsets_kernel(int64_t nv, const int64_t* __restrict__ kptr,
+                                         int64_t* __restrict__ kstart, int32_t* __restrict__ klen) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nv;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        kstart[v] = kptr[v];
+        klen[v] = (int32_t)(kptr[v + 1] - kptr[v]);
+    }
 }
 
 // Rows of the layout kernel are padded to whole quads of ids: padded counts,
@@ -359,7 +432,7 @@ __global__ __launch_bounds__(kBlock) void pad_rows_kernel(const int64_t* __restr
 constexpr int kOrderMax = 8192;
 
 __global__ __launch_bounds__(kBlock) void row_order_kernel(const int64_t* __restrict__ vbase,
-                                                           const int64_t* __restrict__ kptr,
+                                                           const int32_t* __restrict__ klen,
                                                            uint16_t* __restrict__ order) {
     __shared__ uint32_t s_key[kOrderMax];
     const int64_t vb = vbase[blockIdx.x];
@@ -372,7 +445,7 @@ __global__ __launch_bounds__(kBlock) void row_order_kernel(const int64_t* __rest
     while (np < n) np <<= 1;
     for (int i = threadIdx.x; i < np; i += kBlock) {
         // a row has at most 65534 entries, so at most 16384 quads
-        const uint32_t q = i < n ? (uint32_t)((kptr[vb + i + 1] - kptr[vb + i]) >> 2) : 0u;
+        const uint32_t q = i < n ? (uint32_t)(klen[vb + i] >> 2) : 0u;
         s_key[i] = i < n ? ((0xFFFFu - q) << 16) | (uint32_t)i : 0xFFFFFFFFu;
     }
     __syncthreads();
@@ -399,7 +472,7 @@ __global__ __launch_bounds__(kBlock) void row_order_kernel(const int64_t* __rest
 // rounded up to even, adjacency entries) for the offset scans.
 __global__ __launch_bounds__(kBlock) void sell_dims_kernel(
     int64_t nslices, const int32_t* __restrict__ sgraph, const int64_t* __restrict__ vbase,
-    const int64_t* __restrict__ sbase, const int64_t* __restrict__ kptr,
+    const int64_t* __restrict__ sbase, const int32_t* __restrict__ klen,
     const int64_t* __restrict__ rp, const uint16_t* __restrict__ order,
     SellSlice* __restrict__ hdr, uint2* __restrict__ smeta, int64_t* __restrict__ szk,
     int64_t* __restrict__ sza) {
@@ -412,7 +485,7 @@ __global__ __launch_bounds__(kBlock) void sell_dims_kernel(
     const int i = (int)(sl - sbase[g]) * 64 + lane;
     const bool live = i < n;
     const int v = live ? (int)order[vb + i] : n;
-    const int nq = live ? (int)((kptr[vb + v + 1] - kptr[vb + v]) >> 2) : 0;
+    const int nq = live ? klen[vb + v] >> 2 : 0;
     const int deg = live ? (int)(rp[vb + v + 1] - rp[vb + v]) : 0;
     const int Q = (wave_max(nq) + 1) & ~1;
     const int D = wave_max(deg);
@@ -430,7 +503,7 @@ __global__ __launch_bounds__(kBlock) void sell_dims_kernel(
 // offsets.
 __global__ __launch_bounds__(kBlock) void sell_fill_kernel(
     int64_t nslices, const int32_t* __restrict__ sgraph, const int64_t* __restrict__ vbase,
-    const int64_t* __restrict__ kptr, const uint16_t* __restrict__ kidx,
+    const int64_t* __restrict__ kstart, const uint16_t* __restrict__ kidx,
     const int64_t* __restrict__ rp, const uint16_t* __restrict__ ci16,
     const int64_t* __restrict__ koff, const int64_t* __restrict__ aoff,
     const uint2* __restrict__ smeta, SellSlice* __restrict__ hdr, uint2* __restrict__ sk,
@@ -446,8 +519,8 @@ __global__ __launch_bounds__(kBlock) void sell_fill_kernel(
     const int nq = (int)(m.y & 0xFFFFu), deg = (int)(m.y >> 16);
     const int Q = hdr[sl].nq, D = hdr[sl].na;
     const int64_t ko = koff[sl], ao = aoff[sl];
-    // v <= n, so both row offsets are in range (a lane past the end reads none)
-    const uint2* row = reinterpret_cast<const uint2*>(kidx + kptr[vb + v]);
+    // a lane past the graph's end (v = n) reads no row
+    const uint2* row = reinterpret_cast<const uint2*>(kidx + (v < (int)n ? kstart[vb + v] : 0));
     const uint2 sent = make_uint2(n | (n << 16), n | (n << 16));
     for (int j = 0; j < Q; ++j) sk[ko + (int64_t)j * 64 + lane] = j < nq ? row[j] : sent;
     const uint16_t* arow = ci16 + rp[vb + v];
@@ -522,7 +595,7 @@ __device__ __forceinline__ void batch_graph_iteration(
         if (v < G.n) {
             xv = cur[v];
             // the row as quads of 16-bit local ids (padded with the sentinel id n)
-            const int64_t kb = a.kptr[G.vbase + v], ke = a.kptr[G.vbase + v + 1];
+            const int64_t kb = a.kstart[G.vbase + v], ke = kb + a.klen[G.vbase + v];
             const uint2* __restrict__ q4 = reinterpret_cast<const uint2*>(a.kidx + kb);
             const int nq = (int)((ke - kb) >> 2);
             R mindd = R(1);
@@ -641,7 +714,7 @@ __device__ __forceinline__ void batch_graph_iteration_slices(
         // padding quads hold the far sentinel (an infinite squared distance),
         // so mindd sees only the row's own pairs
         if (live && mindd <= coincidence_bias<R>()) {
-            const int64_t kb = a.kptr[G.vbase + v], ke = a.kptr[G.vbase + v + 1];
+            const int64_t kb = a.kstart[G.vbase + v], ke = kb + a.klen[G.vbase + v];
             const uint16_t* row = a.kidx + kb;
             for (int64_t e = 0; e < ke - kb; ++e) {
                 const V p = cur[row[e]];
@@ -979,7 +1052,8 @@ static int tune_plan(gila_batch* b, int precision, hipStream_t s, int32_t* table
             a.count = (int32_t)sub.size();
             a.graphs = d_desc;
             a.order = d_order;
-            a.kptr = b->kptr;
+            a.kstart = b->kstart;
+            a.klen = b->klen;
             a.kidx = b->kidx;
             a.rp = b->rp;
             a.ci = b->ci16;
@@ -1028,7 +1102,8 @@ void free_batch(gila_batch* b, Release rel) {
     if (!b) return;
     DeviceGuard g(b->device);
     if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
-    rel(b->kptr);
+    rel(b->kstart);
+    rel(b->klen);
     rel(b->kidx);
     rel(b->rp);
     rel(b->ci16);
@@ -1062,7 +1137,7 @@ struct DevTmp {
 
 // The wave slices of every graph (see the file comment): vertex order, slice
 // sizes, offsets, interleaved rows and adjacency.  Needs the padded rows
-// (kptr, kidx), the union adjacency (rp) and its local ids (ci16).
+// (kstart, klen, kidx), the union adjacency (rp) and its local ids (ci16).
 static int build_slices(gila_batch* b, const int64_t* d_vb, hipStream_t s) {
     const int32_t count = b->count;
     b->sbase.assign((size_t)count + 1, 0);
@@ -1092,12 +1167,12 @@ static int build_slices(gila_batch* b, const int64_t* d_vb, hipStream_t s) {
     GILA_HIP(hipMemcpyAsync(d_sgraph.p, sgraph.data(), sizeof(int32_t) * S, hipMemcpyHostToDevice, s));
     GILA_HIP(hipMemcpyAsync(d_sb.p, b->sbase.data(), sizeof(int64_t) * (count + 1),
                             hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(row_order_kernel, dim3(count), dim3(kBlock), 0, s, d_vb, b->kptr, d_order.p);
+    hipLaunchKernelGGL(row_order_kernel, dim3(count), dim3(kBlock), 0, s, d_vb, b->klen, d_order.p);
     GILA_HIP(hipGetLastError());
     const int per_block = kBlock / 64;
     const dim3 sg((unsigned)((S + per_block - 1) / per_block));
     hipLaunchKernelGGL(sell_dims_kernel, sg, dim3(kBlock), 0, s, S, d_sgraph.p, d_vb, d_sb.p,
-                       b->kptr, b->rp, d_order.p, b->d_sell, b->d_smeta, d_szk.p, d_sza.p);
+                       b->klen, b->rp, d_order.p, b->d_sell, b->d_smeta, d_szk.p, d_sza.p);
     GILA_HIP(hipGetLastError());
     GILA_TRY(exclusive_scan_i64(d_szk.p, d_koff.p, S, s));
     GILA_TRY(exclusive_scan_i64(d_sza.p, d_aoff.p, S, s));
@@ -1106,7 +1181,7 @@ static int build_slices(gila_batch* b, const int64_t* d_vb, hipStream_t s) {
     GILA_HIP(hipStreamSynchronize(s));
     GILA_TRY(dalloc_t(&b->d_sk, (size_t)std::max<int64_t>(b->sell_quads, 1)));
     GILA_TRY(dalloc_t(&b->d_sa, (size_t)std::max<int64_t>(b->sell_adj, 1)));
-    hipLaunchKernelGGL(sell_fill_kernel, sg, dim3(kBlock), 0, s, S, d_sgraph.p, d_vb, b->kptr,
+    hipLaunchKernelGGL(sell_fill_kernel, sg, dim3(kBlock), 0, s, S, d_sgraph.p, d_vb, b->kstart,
                        b->kidx, b->rp, b->ci16, d_koff.p, d_aoff.p, b->d_smeta, b->d_sell,
                        b->d_sk, b->d_sa);
     GILA_HIP(hipGetLastError());
@@ -1195,89 +1270,123 @@ int batch_build(const gila_csr* graphs, int32_t count, const int32_t* k, hipStre
                     (flag & 8) ? " not symmetric" : "");
 
     pt.mark("gather+validate");
-    // k-hop counts, offsets and 16-bit local rows
+    // k-hop rows as 16-bit local ids, each padded to whole quads with the
+    // graph's sentinel id n; counts |N_v(k)|; per-graph blocks of kidx
     const int32_t nwords = std::max<int32_t>(1, (b->nmax + 31) / 32);
     GILA_TRY(dalloc_t(&d_counts.p, (size_t)std::max<int64_t>(b->nv, 1)));
-    GILA_TRY(dalloc_t(&b->kptr, (size_t)b->nv + 1));
-    BfsArgs a{};
-    a.n = (int32_t)b->nv;
-    a.k = kmax;
-    a.kmax = kmax;
-    a.nverts = (int32_t)b->nv;
-    a.nwords = nwords;
-    a.rp = b->rp;
-    a.ci = d_ci32.p;
-    a.counts = d_counts.p;
-    a.work = d_flag.p + 1;
-    a.gvbase = d_vb.p;
-    a.gk = d_k.p;
-    a.ngraphs = count;
-    a.qcap = std::max<int32_t>(1, b->nmax);
+    GILA_TRY(dalloc_t(&b->kstart, (size_t)std::max<int64_t>(b->nv, 1)));
+    GILA_TRY(dalloc_t(&b->klen, (size_t)std::max<int64_t>(b->nv, 1)));
     // graphs whose CSR and three bitmaps per wavefront fit in LDS: one
-    // workgroup per graph; otherwise one workgroup per source
+    // workgroup per graph, one pass; otherwise one workgroup per source,
+    // count then fill
     int64_t nnzmax = 0;
     for (int32_t i = 0; i < count; ++i) nnzmax = std::max(nnzmax, b->ebase[i + 1] - b->ebase[i]);
     const size_t bfs_lds = batch_bfs_lds_bytes(b->nmax, nnzmax);
     const bool per_graph = bfs_lds + 1024 <= device_info(dev).max_lds_per_block &&
                            !(getenv("GILA_BATCH_BFS") && std::strcmp(getenv("GILA_BATCH_BFS"), "source") == 0);
-    BatchBfsArgs ga{};
-    DevTmp<int32_t> d_gorder(s);
+    const int vg = (int)std::min<int64_t>(4096, (std::max<int64_t>(b->nv, 1) + kBlock - 1) / kBlock);
     if (per_graph) {
+        // each graph's block: the sum of its rows' walk bounds
+        DevTmp<int32_t> d_vgraph(s);
+        DevTmp<int64_t> d_w0(s), d_w1(s), d_tot(s), d_bound(s), d_bscan(s), d_gbase(s);
+        GILA_TRY(dalloc_t(&d_vgraph.p, (size_t)std::max<int64_t>(b->nv, 1)));
+        GILA_TRY(dalloc_t(&d_w0.p, (size_t)std::max<int64_t>(b->nv, 1)));
+        GILA_TRY(dalloc_t(&d_w1.p, (size_t)std::max<int64_t>(b->nv, 1)));
+        GILA_TRY(dalloc_t(&d_tot.p, (size_t)std::max<int64_t>(b->nv, 1)));
+        GILA_TRY(dalloc_t(&d_bound.p, (size_t)std::max<int64_t>(b->nv, 1)));
+        GILA_TRY(dalloc_t(&d_bscan.p, (size_t)b->nv + 1));
+        GILA_TRY(dalloc_t(&d_gbase.p, (size_t)count + 1));
+        hipLaunchKernelGGL(vertex_graph_kernel, dim3(count), dim3(kBlock), 0, s, d_vb.p,
+                           d_vgraph.p);
+        hipLaunchKernelGGL(walk_init_kernel, dim3(vg), dim3(kBlock), 0, s, b->nv, b->rp, d_w0.p,
+                           d_tot.p);
+        int64_t* cur = d_w0.p;
+        int64_t* nxt = d_w1.p;
+        for (int32_t level = 2; level <= kmax; ++level) {
+            hipLaunchKernelGGL(walk_level_kernel, dim3(vg), dim3(kBlock), 0, s, b->nv, b->rp,
+                               d_ci32.p, d_vgraph.p, d_vb.p, d_k.p, level, cur, nxt, d_tot.p);
+            std::swap(cur, nxt);
+        }
+        hipLaunchKernelGGL(walk_pad_kernel, dim3(vg), dim3(kBlock), 0, s, b->nv, d_tot.p,
+                           d_bound.p);
+        GILA_HIP(hipGetLastError());
+        GILA_TRY(exclusive_scan_i64(d_bound.p, d_bscan.p, b->nv, s));
+        hipLaunchKernelGGL(gather_bounds_kernel, dim3((count + 256) / 256), dim3(256), 0, s,
+                           d_bscan.p, d_vb.p, count, d_gbase.p);
+        GILA_HIP(hipGetLastError());
+        GILA_HIP(hipMemcpyAsync(&b->kidx_size, d_gbase.p + count, sizeof(int64_t),
+                                hipMemcpyDeviceToHost, s));
+        GILA_HIP(hipStreamSynchronize(s));
+        GILA_TRY(dalloc_t(&b->kidx, (size_t)b->kidx_size + 64));
+        pt.mark("bounds");
         std::vector<int32_t> gorder((size_t)count);
         std::iota(gorder.begin(), gorder.end(), 0);
         std::stable_sort(gorder.begin(), gorder.end(),
                          [&](int32_t x, int32_t y) { return b->n[x] > b->n[y]; });
+        DevTmp<int32_t> d_gorder(s);
         GILA_TRY(dalloc_t(&d_gorder.p, (size_t)count));
         GILA_HIP(hipMemcpyAsync(d_gorder.p, gorder.data(), sizeof(int32_t) * count,
                                 hipMemcpyHostToDevice, s));
+        BatchBfsArgs ga{};
         ga.count = count;
         ga.gorder = d_gorder.p;
         ga.vbase = d_vb.p;
         ga.rp = b->rp;
         ga.ci = d_ci32.p;
         ga.gk = d_k.p;
+        ga.gbase = d_gbase.p;
         ga.counts = d_counts.p;
+        ga.kstart = b->kstart;
+        ga.klen = b->klen;
+        ga.kidx = b->kidx;
         ga.work = d_flag.p + 1;
         ga.nmax = b->nmax;
         ga.nnzmax = nnzmax;
-        GILA_TRY(run_batch_bfs(false, ga, bfs_lds, dev, s));
+        GILA_TRY(run_batch_bfs(ga, bfs_lds, dev, s));
+        GILA_HIP(hipStreamSynchronize(s));
     } else if (b->nv > 0) {
+        BfsArgs a{};
+        a.n = (int32_t)b->nv;
+        a.k = kmax;
+        a.kmax = kmax;
+        a.nverts = (int32_t)b->nv;
+        a.nwords = nwords;
+        a.rp = b->rp;
+        a.ci = d_ci32.p;
+        a.counts = d_counts.p;
+        a.work = d_flag.p + 1;
+        a.gvbase = d_vb.p;
+        a.gk = d_k.p;
+        a.ngraphs = count;
+        a.qcap = std::max<int32_t>(1, b->nmax);
         GILA_TRY(run_bfs(false, dev, s, a));
-    }
-    pt.mark("count");
-    // true row offsets (pair counts) and quad-padded offsets (layout rows)
-    DevTmp<int64_t> d_ktrue(s), d_padded(s);
-    GILA_TRY(dalloc_t(&d_ktrue.p, (size_t)b->nv + 1));
-    GILA_TRY(dalloc_t(&d_padded.p, (size_t)std::max<int64_t>(b->nv, 1)));
-    GILA_TRY(exclusive_scan_i64(d_counts.p, d_ktrue.p, b->nv, s));
-    if (b->nv > 0) {
-        const int pg = (int)std::min<int64_t>(4096, (b->nv + kBlock - 1) / kBlock);
-        hipLaunchKernelGGL(pad_counts_kernel, dim3(pg), dim3(kBlock), 0, s, b->nv, d_counts.p,
+        DevTmp<int64_t> d_padded(s), d_kptr(s);
+        GILA_TRY(dalloc_t(&d_padded.p, (size_t)b->nv));
+        GILA_TRY(dalloc_t(&d_kptr.p, (size_t)b->nv + 1));
+        hipLaunchKernelGGL(pad_counts_kernel, dim3(vg), dim3(kBlock), 0, s, b->nv, d_counts.p,
                            d_padded.p);
         GILA_HIP(hipGetLastError());
-    }
-    GILA_TRY(exclusive_scan_i64(d_padded.p, b->kptr, b->nv, s));
-    GILA_HIP(hipMemcpyAsync(&b->P, d_ktrue.p + b->nv, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    GILA_HIP(hipMemcpyAsync(&b->P_padded, b->kptr + b->nv, sizeof(int64_t),
-                            hipMemcpyDeviceToHost, s));
-    GILA_HIP(hipStreamSynchronize(s));
-    GILA_TRY(dalloc_t(&b->kidx, (size_t)b->P_padded + 64));
-    if (b->nv > 0 && b->P > 0) {
-        if (per_graph) {
-            ga.kptr = b->kptr;
-            ga.kidx = b->kidx;
-            GILA_TRY(run_batch_bfs(true, ga, bfs_lds, dev, s));
-        } else {
-            a.kptr = b->kptr;
-            a.kidx16 = b->kidx;
-            GILA_TRY(run_bfs(true, dev, s, a));
-        }
-    }
-    if (b->P_padded > b->P) {
-        hipLaunchKernelGGL(pad_rows_kernel, dim3(count), dim3(kBlock), 0, s, d_vb.p, b->kptr,
+        GILA_TRY(exclusive_scan_i64(d_padded.p, d_kptr.p, b->nv, s));
+        GILA_HIP(hipMemcpyAsync(&b->kidx_size, d_kptr.p + b->nv, sizeof(int64_t),
+                                hipMemcpyDeviceToHost, s));
+        GILA_HIP(hipStreamSynchronize(s));
+        GILA_TRY(dalloc_t(&b->kidx, (size_t)b->kidx_size + 64));
+        a.kptr = d_kptr.p;
+        a.kidx16 = b->kidx;
+        GILA_TRY(run_bfs(true, dev, s, a));
+        hipLaunchKernelGGL(pad_rows_kernel, dim3(count), dim3(kBlock), 0, s, d_vb.p, d_kptr.p,
                            d_counts.p, b->kidx);
+        hipLaunchKernelGGL(rows_from_offsets_kernel, dim3(vg), dim3(kBlock), 0, s, b->nv,
+                           d_kptr.p, b->kstart, b->klen);
         GILA_HIP(hipGetLastError());
+        GILA_HIP(hipStreamSynchronize(s));
     }
+    // true row offsets: the pair counts
+    DevTmp<int64_t> d_ktrue(s);
+    GILA_TRY(dalloc_t(&d_ktrue.p, (size_t)b->nv + 1));
+    GILA_TRY(exclusive_scan_i64(d_counts.p, d_ktrue.p, b->nv, s));
+    GILA_HIP(hipMemcpyAsync(&b->P, d_ktrue.p + b->nv, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    GILA_HIP(hipStreamSynchronize(s));
     pt.mark("fill");
     if (count > 0) {
         hipLaunchKernelGGL(localize_kernel, dim3(count), dim3(kBlock), 0, s, d_src.p, d_ci32.p,
@@ -1323,7 +1432,7 @@ int batch_build(const gila_csr* graphs, int32_t count, const int32_t* k, hipStre
                                 hipMemcpyHostToDevice, s));
     GILA_HIP(hipStreamSynchronize(s));
     pt.mark("order");
-    b->device_bytes = 8 * (2 * (b->nv + 1)) + 2 * (b->P_padded + b->nnz) +
+    b->device_bytes = 8 * (b->nv + 1) + 12 * b->nv + 2 * (b->kidx_size + b->nnz) +
                       (int64_t)(sizeof(BatchDesc) + 4 + sizeof(gila_stats)) * count +
                       (int64_t)(sizeof(SellSlice) + 64 * sizeof(uint2)) * b->nslices +
                       8 * b->sell_quads + 2 * b->sell_adj +
@@ -1395,7 +1504,8 @@ int batch_run(gila_batch* b, const gila_params* params, void* const* pos, hipStr
     a.count = count;
     a.graphs = b->d_desc;
     a.order = b->d_order;
-    a.kptr = b->kptr;
+    a.kstart = b->kstart;
+    a.klen = b->klen;
     a.kidx = b->kidx;
     a.rp = b->rp;
     a.ci = b->ci16;
@@ -1496,22 +1606,32 @@ int gila_batch_export(const gila_batch* b, int32_t graph, int64_t* ptr_host, int
     if (graph < 0 || graph >= b->count) return fail(GILA_EINVAL, "graph %d out of range", graph);
     DeviceGuard dg(b->device);
     const int32_t n = b->n[graph];
-    std::vector<int64_t> kp((size_t)n + 1);
-    GILA_HIP(hipMemcpy(kp.data(), b->kptr + b->vbase[graph], sizeof(int64_t) * (n + 1),
-                       hipMemcpyDeviceToHost));
-    // rows are stored padded to quads with the sentinel id n: strip it
-    std::vector<uint16_t> rows((size_t)(kp[n] - kp[0]));
-    if (!rows.empty())
-        GILA_HIP(hipMemcpy(rows.data(), b->kidx + kp[0], sizeof(uint16_t) * rows.size(),
-                           hipMemcpyDeviceToHost));
     ptr_host[0] = 0;
+    if (n == 0) return GILA_OK;
+    std::vector<int64_t> ks((size_t)n);
+    std::vector<int32_t> kl((size_t)n);
+    GILA_HIP(hipMemcpy(ks.data(), b->kstart + b->vbase[graph], sizeof(int64_t) * n,
+                       hipMemcpyDeviceToHost));
+    GILA_HIP(hipMemcpy(kl.data(), b->klen + b->vbase[graph], sizeof(int32_t) * n,
+                       hipMemcpyDeviceToHost));
+    // the graph's rows lie in one block of kidx, in any order
+    int64_t lo = INT64_MAX, hi = 0;
     for (int32_t v = 0; v < n; ++v) {
-        int64_t e = kp[v + 1] - kp[0];
-        while (e > kp[v] - kp[0] && rows[(size_t)e - 1] == (uint16_t)n) --e;
-        const int64_t len = e - (kp[v] - kp[0]);
+        lo = std::min(lo, ks[v]);
+        hi = std::max(hi, ks[v] + kl[v]);
+    }
+    std::vector<uint16_t> rows((size_t)std::max<int64_t>(hi - lo, 0));
+    if (!rows.empty())
+        GILA_HIP(hipMemcpy(rows.data(), b->kidx + lo, sizeof(uint16_t) * rows.size(),
+                           hipMemcpyDeviceToHost));
+    // rows are padded to quads with the sentinel id n: strip it
+    for (int32_t v = 0; v < n; ++v) {
+        const int64_t r0 = ks[v] - lo;
+        int64_t e = r0 + kl[v];
+        while (e > r0 && rows[(size_t)e - 1] == (uint16_t)n) --e;
+        const int64_t len = e - r0;
         if (idx_host)
-            for (int64_t j = 0; j < len; ++j)
-                idx_host[ptr_host[v] + j] = rows[(size_t)(kp[v] - kp[0] + j)];
+            for (int64_t j = 0; j < len; ++j) idx_host[ptr_host[v] + j] = rows[(size_t)(r0 + j)];
         ptr_host[v + 1] = ptr_host[v] + len;
     }
     return GILA_OK;
