@@ -84,6 +84,20 @@ const char* gila_last_error(void);
 /* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
 int gila_version(void);
 
+/* Device memory of freed handles.  gila_khop_free, gila_pruned_free and
+ * gila_batch_free wait once for the whole device (so a handle may be freed
+ * while work on it is still queued on any stream), then keep the handle's
+ * device blocks in the library's per-device cache, where later handles of
+ * similar sizes reuse them without a hipMalloc.  The cache holds at most
+ * 16 GiB (older blocks beyond that are returned to the device), and all of it
+ * is returned before an allocation of the library is reported as failed.
+ * The one-shot calls (gila_layout, gila_layout_pruned, gila_layout_batch)
+ * release their handles into the cache ordered on their stream, without a
+ * device-wide wait.  gila_release_cached_memory returns every cached block
+ * whose releasing work has completed to the device (hipFree) and gives the
+ * bytes returned; it never fails. */
+int64_t gila_release_cached_memory(void);
+
 /* ------------------------------------------------------------------ */
 /* Graph                                                                */
 /* ------------------------------------------------------------------ */

@@ -1693,7 +1693,11 @@ int gila_batch_tune(gila_batch* b, int32_t precision, void* stream, int32_t* cla
     return GILA_OK;
 }
 
-void gila_batch_free(gila_batch* b) { free_batch(b); }
+void gila_batch_free(gila_batch* b) {
+    if (!b) return;
+    DeviceGuard g(b->device);
+    free_batch(b, public_release());
+}
 
 int gila_layout_batch(const gila_csr* graphs_dev, int32_t count, const int32_t* k,
                       const gila_params* params, void* const* pos_dev, void* stream,
@@ -1707,7 +1711,7 @@ int gila_layout_batch(const gila_csr* graphs_dev, int32_t count, const int32_t* 
         std::lock_guard<std::mutex> lk(b->mu);
         rc = batch_run(b, params, pos_dev, (hipStream_t)stream, out, false);
     }
-    free_batch(b);
+    free_batch(b, Release{true, (hipStream_t)stream});
     return rc;
 }
 

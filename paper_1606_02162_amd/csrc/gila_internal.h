@@ -52,11 +52,22 @@ void dfree_on(void* p, hipStream_t s, bool idle = false);
 struct Release {
     bool cached = false;
     hipStream_t stream = nullptr;
+    bool idle = false;  // cached, with the device known to be idle: reusable at once
     void operator()(void* p) const {
-        if (cached) dfree_on(p, stream);
+        if (cached) dfree_on(p, stream, idle);
         else dfree(p);
     }
 };
+
+// Release for the public free calls: waits once for the whole device (the
+// caller's work on the handle may be queued on any stream), then caches every
+// block as reusable at once.  If the device cannot be synchronised, the blocks
+// take plain hipFree instead.
+Release public_release();
+
+// Returns every cached block whose releasing work has completed to the device;
+// the bytes returned.
+int64_t release_cached();
 
 // Restores the caller's current device on scope exit.
 struct DeviceGuard {
@@ -146,7 +157,8 @@ struct StepArgs {
     double stop_fraction;
     double stop_displacement;
     int32_t check_stop;
-    int32_t hist_slot;          // < 0: no history
+    int32_t hist_slot;          // < 0: no history (with temps: ctl->h_base + tick_j)
+    int32_t hist_cap;           // rows of the history table
     const int32_t* perm;        // internal -> caller ids (for F/D outputs)
     double* F_out;              // caller ids, may be null
     double* D_out;
@@ -270,6 +282,8 @@ struct gila_khop {
     // caps come from the device copy of the schedule at ctl->h_base
     hipGraphExec_t tick_exec = nullptr;
     std::vector<uint64_t> tick_key;
+    hipGraphExec_t chunk_exec = nullptr;  // kRunChunk iterations of gila_run, caps from d_temps
+    std::vector<uint64_t> chunk_key;
     double* d_temps = nullptr;
     std::vector<double> temps_host;  // the schedule d_temps holds
     std::mutex mu;

@@ -419,6 +419,7 @@ void free_khop(gila_khop* kh, Release rel) {
     DeviceGuard g(kh->device);
     if (kh->gexec) (void)hipGraphExecDestroy(kh->gexec);
     if (kh->tick_exec) (void)hipGraphExecDestroy(kh->tick_exec);
+    if (kh->chunk_exec) (void)hipGraphExecDestroy(kh->chunk_exec);
     rel(kh->d_temps);
     rel(kh->perm);
     rel(kh->iperm);
@@ -824,6 +825,10 @@ int gila_khop_set_mass(gila_khop* kh, const double* mass_dev, void* stream) {
     return GILA_OK;
 }
 
-void gila_khop_free(gila_khop* kh) { free_khop(kh); }
+void gila_khop_free(gila_khop* kh) {
+    if (!kh) return;
+    DeviceGuard g(kh->device);
+    free_khop(kh, public_release());
+}
 
 }  // extern "C"

@@ -69,8 +69,15 @@ __global__ __launch_bounds__(kBlock) void iteration_stats_kernel(StepArgs a) {
         if (a.check_stop && (double)mv < a.stop_fraction * (double)a.n_active) ctl->stopped = 1;
         // a non-finite force ends the run (2: stopped by the error, not the rule)
         if (nf > 0) ctl->stopped = 2;
-        if (a.hist_slot >= 0) {
-            double* hrow = a.hist + 4 * (int64_t)a.hist_slot;
+        // the history row: this iteration's h (from the replay's base in a
+        // captured chunk or tick)
+        int32_t slot = a.hist_slot;
+        if (a.temps) {
+            const int32_t hh = ctl->h_base + a.tick_j;
+            slot = hh < a.hist_cap ? hh : -1;
+        }
+        if (slot >= 0) {
+            double* hrow = a.hist + 4 * (int64_t)slot;
             hrow[0] = e;
             hrow[1] = m;
             hrow[2] = (double)mv;
@@ -218,6 +225,7 @@ static StepArgs base_args(const gila_khop* kh, const gila_params* p) {
     a.ctl = kh->ctl;
     a.hist = kh->hist;
     a.hist_slot = -1;
+    a.hist_cap = kh->hist_cap;
     if (kh->mass64)
         a.mass = p->precision == GILA_FP64 ? (const void*)kh->mass64 : (const void*)kh->mass32;
     force_exponents(p, &a.att_p, &a.rep_q);
@@ -267,30 +275,44 @@ int enqueue_run(gila_khop* kh, const gila_params* p, int32_t start_h, int32_t en
 void drop_graphs(gila_khop* kh) {
     if (kh->gexec) (void)hipGraphExecDestroy(kh->gexec);
     if (kh->tick_exec) (void)hipGraphExecDestroy(kh->tick_exec);
+    if (kh->chunk_exec) (void)hipGraphExecDestroy(kh->chunk_exec);
     kh->gexec = nullptr;
     kh->tick_exec = nullptr;
+    kh->chunk_exec = nullptr;
     kh->gkey.clear();
     kh->tick_key.clear();
+    kh->chunk_key.clear();
+}
+
+// The device copy of the schedule, replaced (with the graphs that read it)
+// when the schedule changes.
+static int upload_schedule(gila_khop* kh, const gila_params* p, hipStream_t s) {
+    const size_t H = (size_t)p->iterations;
+    if (kh->d_temps && kh->temps_host.size() == H &&
+        std::memcmp(kh->temps_host.data(), p->temperature, H * sizeof(double)) == 0)
+        return GILA_OK;
+    drop_graphs(kh);
+    dfree_on(kh->d_temps, s);
+    kh->d_temps = nullptr;
+    kh->temps_host.assign(p->temperature, p->temperature + H);
+    GILA_TRY(dalloc_t(&kh->d_temps, std::max<size_t>(H, 1)));
+    if (H > 0)
+        GILA_HIP(hipMemcpyAsync(kh->d_temps, kh->temps_host.data(), H * sizeof(double),
+                                hipMemcpyHostToDevice, s));
+    return GILA_OK;
 }
 
 __global__ void set_h_base_kernel(Ctl* ctl, int32_t h) { ctl->h_base = h; }
+
+// Iterations per captured chunk of a long gila_run (even).
+constexpr int32_t kRunChunk = 50;
 
 int enqueue_tick(gila_khop* kh, const gila_params* p, int32_t h, int32_t count,
                  int32_t graph_len, void* pos_dev, hipStream_t s) {
     if (count != graph_len || count <= 0 || h < 0 || h + count > p->iterations)
         return enqueue_run(kh, p, h, h + count, pos_dev, s);
     // the device copy of the schedule (the same for every tick of a job)
-    const size_t H = (size_t)p->iterations;
-    if (!kh->d_temps || kh->temps_host.size() != H ||
-        std::memcmp(kh->temps_host.data(), p->temperature, H * sizeof(double)) != 0) {
-        drop_graphs(kh);
-        dfree_on(kh->d_temps, s);
-        kh->d_temps = nullptr;
-        kh->temps_host.assign(p->temperature, p->temperature + H);
-        GILA_TRY(dalloc_t(&kh->d_temps, H));
-        GILA_HIP(hipMemcpyAsync(kh->d_temps, kh->temps_host.data(), H * sizeof(double),
-                                hipMemcpyHostToDevice, s));
-    }
+    GILA_TRY(upload_schedule(kh, p, s));
     int32_t att_p = 0, rep_q = 0;
     force_exponents(p, &att_p, &rep_q);
     auto bits = [](double x) {
@@ -393,6 +415,82 @@ static std::vector<uint64_t> graph_key(const gila_khop* kh, const gila_params* p
     return key;
 }
 
+// Long runs replay one captured chunk of kRunChunk iterations (an even
+// number: each chunk starts and ends in the first position buffer) whose caps
+// are read from the device copy of the schedule at the base that a small
+// kernel sets before each replay; capturing and instantiating the whole run
+// would cost a few milliseconds per handle.  The chunk's iterations are the
+// same launches as the whole run's, so the result is the same bits.
+static int enqueue_chunked_run(gila_khop* kh, const gila_params* p, int32_t start_h,
+                               int32_t end_h, void* pos_dev, hipStream_t s) {
+    GILA_TRY(upload_schedule(kh, p, s));
+    int32_t att_p = 0, rep_q = 0;
+    force_exponents(p, &att_p, &rep_q);
+    auto bits = [](double x) {
+        uint64_t u;
+        std::memcpy(&u, &x, 8);
+        return u;
+    };
+    const std::vector<uint64_t> key = {(uint64_t)p->precision, bits(p->ideal_length),
+                                       bits(p->stop_fraction), bits(p->stop_displacement),
+                                       (uint64_t)(uint32_t)att_p, (uint64_t)(uint32_t)rep_q,
+                                       (uint64_t)segment_ready_for(kh, p->precision),
+                                       (uint64_t)(uintptr_t)kh->d_temps,
+                                       (uint64_t)(uintptr_t)kh->hist, (uint64_t)kh->hist_cap};
+    StepArgs a = base_args(kh, p);
+    a.check_stop = p->stop_fraction > 0.0 ? 1 : 0;
+    a.temps = kh->d_temps;
+    if (!kh->chunk_exec || key != kh->chunk_key) {
+        if (kh->chunk_exec) (void)hipGraphExecDestroy(kh->chunk_exec);
+        kh->chunk_exec = nullptr;
+        kh->chunk_key.clear();
+        hipStream_t cs = capture_stream(kh->device);
+        if (!cs) return fail(GILA_EDEVICE, "cannot create capture stream");
+        (void)hipGetLastError();  // no stale status may fail a check inside the capture
+        GILA_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
+        int rc = GILA_OK;
+        for (int32_t j = 0; j < kRunChunk && rc == GILA_OK; ++j) {
+            a.pos_cur = kh->pos[j & 1];
+            a.pos_next = kh->pos[(j + 1) & 1];
+            a.tick_j = j;
+            rc = launch_iteration(kh, p->precision, a, cs);
+        }
+        hipGraph_t graph = nullptr;
+        const hipError_t ee = hipStreamEndCapture(cs, &graph);
+        if (rc != GILA_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        if (ee != hipSuccess) return fail(GILA_EDEVICE, "chunk capture: %s", hipGetErrorString(ee));
+        const hipError_t ie = hipGraphInstantiate(&kh->chunk_exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ie != hipSuccess) {
+            kh->chunk_exec = nullptr;
+            return fail(GILA_EDEVICE, "chunk instantiate: %s", hipGetErrorString(ie));
+        }
+        kh->chunk_key = key;
+    }
+    hipLaunchKernelGGL(reset_ctl_kernel, dim3(1), dim3(1), 0, s, kh->ctl);
+    GILA_HIP(hipGetLastError());
+    GILA_TRY(launch_permute_in(kh, p->precision, pos_dev, s));
+    int32_t h = start_h;
+    for (; end_h - h >= kRunChunk; h += kRunChunk) {
+        hipLaunchKernelGGL(set_h_base_kernel, dim3(1), dim3(1), 0, s, kh->ctl, h);
+        GILA_HIP(hipGetLastError());
+        GILA_HIP(hipGraphLaunch(kh->chunk_exec, s));
+    }
+    // the rest one launch at a time, continuing in the first buffer
+    a.temps = nullptr;
+    for (int32_t j = 0; h < end_h; ++h, ++j) {
+        a.pos_cur = kh->pos[j & 1];
+        a.pos_next = kh->pos[(j + 1) & 1];
+        a.t = p->temperature[h];
+        a.hist_slot = h < kh->hist_cap ? h : -1;
+        GILA_TRY(launch_iteration(kh, p->precision, a, s));
+    }
+    return launch_permute_out(kh, p->precision, pos_dev, s);
+}
+
 int run_iterations(gila_khop* kh, const gila_params* p, int32_t start_h, int32_t end_h,
                    void* pos_dev, hipStream_t stream, gila_stats* out, bool use_graph) {
     if (kh->n > 0 && !pos_dev) return fail(GILA_EINVAL, "pos_dev is NULL");
@@ -400,7 +498,9 @@ int run_iterations(gila_khop* kh, const gila_params* p, int32_t start_h, int32_t
         return fail(GILA_EINVAL, "iteration range [%d, %d) outside [0, %d]", start_h, end_h,
                     p->iterations);
     GILA_TRY(prepare_precision(kh, p->precision, stream));
-    if (use_graph && end_h > start_h) {
+    if (use_graph && end_h - start_h >= 2 * kRunChunk) {
+        GILA_TRY(enqueue_chunked_run(kh, p, start_h, end_h, pos_dev, stream));
+    } else if (use_graph && end_h > start_h) {
         std::vector<uint64_t> key = graph_key(kh, p, start_h, end_h, pos_dev);
         if (!kh->gexec || key != kh->gkey) {
             if (kh->gexec) {
@@ -713,7 +813,7 @@ int gila_layout(const gila_csr* g_dev, int32_t k, const gila_params* params, voi
         rc = run_iterations(kh, params, 0, params->iterations, pos_dev, (hipStream_t)stream, out,
                             false);
     }
-    gila_khop_free(kh);
+    free_khop(kh, Release{true, (hipStream_t)stream});
     return rc;
 }
 

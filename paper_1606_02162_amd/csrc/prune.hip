@@ -497,26 +497,27 @@ static int grid_of(int64_t items) {
     return (int)std::max<int64_t>(1, std::min<int64_t>(8192, (items + kBlock - 1) / kBlock));
 }
 
-static void free_pruned(gila_pruned* p) {
+static void free_pruned(gila_pruned* p, Release rel = Release{}) {
     if (!p) return;
     DeviceGuard g(p->device);
-    dfree(p->anchor);
-    dfree(p->leaves);
-    dfree(p->new_id);
-    dfree(p->kept_of);
-    dfree(p->rp);
-    dfree(p->ci);
-    dfree(p->mass);
-    dfree(p->leaf_ptr);
-    dfree(p->leaf_ids);
-    dfree(p->anchors);
+    rel(p->anchor);
+    rel(p->leaves);
+    rel(p->new_id);
+    rel(p->kept_of);
+    rel(p->rp);
+    rel(p->ci);
+    rel(p->mass);
+    rel(p->leaf_ptr);
+    rel(p->leaf_ids);
+    rel(p->anchors);
     delete p;
 }
 
 namespace {
 struct PrunedHolder {
     gila_pruned* p;
-    ~PrunedHolder() { free_pruned(p); }
+    Release rel{};
+    ~PrunedHolder() { free_pruned(p, rel); }
 };
 
 // Scratch freed into the block cache once the work on its stream is done.
@@ -794,7 +795,11 @@ int gila_reinsert(const gila_pruned* p, double ideal_length, int32_t precision,
     return reinsert(p, ideal_length, precision, pos_kept_dev, pos_all_dev, (hipStream_t)stream);
 }
 
-void gila_pruned_free(gila_pruned* p) { free_pruned(p); }
+void gila_pruned_free(gila_pruned* p) {
+    if (!p) return;
+    DeviceGuard g(p->device);
+    free_pruned(p, public_release());
+}
 
 int gila_layout_pruned(const gila_csr* g_dev, int32_t k, const gila_params* params, void* pos_dev,
                        void* stream, gila_stats* out) {
@@ -806,14 +811,15 @@ int gila_layout_pruned(const gila_csr* g_dev, int32_t k, const gila_params* para
     hipStream_t s = (hipStream_t)stream;
     gila_pruned* p = nullptr;
     GILA_TRY(prune(g_dev, s, &p));
-    PrunedHolder ph{p};
+    PrunedHolder ph{p, Release{true, s}};
     gila_csr pg{p->n_kept, p->nnz_kept, p->rp, p->ci};
     gila_khop* kh = nullptr;
     GILA_TRY(build_khop(&pg, k, s, &kh));
     struct KH {
         gila_khop* k;
-        ~KH() { free_khop(k); }
-    } kguard{kh};
+        hipStream_t s;
+        ~KH() { free_khop(k, Release{true, s}); }
+    } kguard{kh, s};
     GILA_TRY(gila_khop_set_mass(kh, p->mass, stream));
     const size_t pb = params->precision == GILA_FP64 ? 16 : 8;
     Tmp kept(s);

@@ -277,6 +277,21 @@ void dfree_on(void* p, hipStream_t s, bool idle) {
     if (g_cached_bytes > kCacheLimit) trim_locked(kCacheLimit / 2);
 }
 
+int64_t release_cached() {
+    std::lock_guard<std::mutex> lk(g_mem_mu);
+    const size_t before = g_cached_bytes;
+    trim_locked(0);
+    return (int64_t)(before - g_cached_bytes);
+}
+
+Release public_release() {
+    if (hipDeviceSynchronize() != hipSuccess) {
+        (void)hipGetLastError();
+        return Release{};
+    }
+    return Release{true, nullptr, true};
+}
+
 DeviceGuard::DeviceGuard(int dev) {
     if (hipGetDevice(&prev) != hipSuccess) prev = -1;
     ok = (prev == dev) || (hipSetDevice(dev) == hipSuccess);
@@ -346,5 +361,7 @@ const char* gila_strerror(int status) {
 const char* gila_last_error(void) { return gila::t_last_error; }
 
 int gila_version(void) { return 10000; }
+
+int64_t gila_release_cached_memory(void) { return gila::release_cached(); }
 
 }  // extern "C"

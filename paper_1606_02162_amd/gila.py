@@ -116,6 +116,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "gila_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         "gila_last_error": (ctypes.c_char_p, []),
         "gila_version": (ctypes.c_int, []),
+        "gila_release_cached_memory": (i64, []),
         "gila_build_khop": (ctypes.c_int, [P(Csr), i32, vp, P(vp)]),
         "gila_khop_info": (ctypes.c_int, [vp, P(i32), P(i32), P(i64), P(i32), P(i64)]),
         "gila_khop_export": (ctypes.c_int, [vp, vp, vp]),
@@ -205,6 +206,11 @@ def _ptr(t) -> int:
 # ---------------------------------------------------------------- schedules
 # The paper's ideal edge length d = 20 + sqrt(800) (Section 5.1).
 PAPER_IDEAL_LENGTH = 48.2842712474619
+def release_cached_memory() -> int:
+    """Returns the library's cached device blocks to the device; the bytes returned."""
+    return int(lib().gila_release_cached_memory())
+
+
 def paper_schedule(n_vertices: float, aspect: float, ideal_length: float,
                    iterations: int) -> np.ndarray:
     """Cap of Section 5.1 (``gila_paper_schedule``): sqrt((n / a) d) 0.93^h,

@@ -74,6 +74,23 @@ def test_repeated_builds_with_queued_frontiers(G):
             kh.free()
 
 
+def test_freed_handles_reuse_and_return_cached_memory(G):
+    """A freed handle's device blocks stay in the library's cache: a rebuild of
+    the same graph reuses them and gives the same rows, and releasing the cache
+    returns them to the device (a second release finds nothing)."""
+    g = inputs.barabasi_albert(20000, 3, seed=43)
+    G.release_cached_memory()
+    kh = _build(G, g, 2)
+    ptr0, idx0 = kh.export()
+    kh.free()
+    kh = _build(G, g, 2)
+    ptr1, idx1 = kh.export()
+    kh.free()
+    assert np.array_equal(ptr0, ptr1) and np.array_equal(idx0, idx1)
+    assert G.release_cached_memory() > 0
+    assert G.release_cached_memory() == 0
+
+
 def test_grid32_config_total(G):
     g = inputs.grid_graph(32, 32)
     kh = _build(G, g, 2)

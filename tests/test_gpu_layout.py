@@ -88,6 +88,63 @@ def _run_equals_steps_and_resume(G, prec):
     assert np.array_equal(_np(a), _np(f))
 
 
+@pytest.mark.parametrize("path", ["segment", "direct"])
+def test_long_run_in_chunks_equals_steps(G, path):
+    """Runs of 100 or more iterations replay a captured chunk of iterations
+    whose temperatures are read on the device: the result is bitwise that of
+    single steps, of eager launches and of a run split at any iteration, the
+    chunk is re-captured when the parameters change, and the history rows
+    match the steps."""
+    if path == "direct":
+        os.environ["GILA_PATH"] = "direct"
+    try:
+        g = inputs.random_tree_plus_edges(1500, 700, seed=27)
+        rp, ci = G.to_device_csr(g)
+        kh = G.build_khop(rp, ci, 2)
+        H = 137
+        params = G.LayoutParams(temperature=G.paper_schedule(g.n, 1.0, 40.0, H),
+                                ideal_length=40.0, precision=G.FP32_KAHAN)
+        x0 = inputs.uniform_positions(g.n, seed=6, width=1000.0)
+        kh.enable_history(H)
+        a = _t(G, x0, G.FP32_KAHAN)
+        st = G.run(kh, params, a)
+        assert st.iterations_run == H and st.stopped == 0
+        hist = kh.history()
+        b = _t(G, x0, G.FP32_KAHAN)
+        for h in range(H):
+            sh = G.step(kh, params, h, b)
+            assert tuple(hist[h]) == (sh.energy, sh.max_disp, float(sh.moved),
+                                      float(sh.coincident)), h
+        assert np.array_equal(_np(a), _np(b))
+        c = _t(G, x0, G.FP32_KAHAN)
+        G.run(kh, params, c, 0, 105)
+        G.run(kh, params, c, 105, H)
+        assert np.array_equal(_np(a), _np(c))
+        os.environ["GILA_NO_GRAPH"] = "1"
+        try:
+            e = _t(G, x0, G.FP32_KAHAN)
+            G.run(kh, params, e)
+        finally:
+            del os.environ["GILA_NO_GRAPH"]
+        assert np.array_equal(_np(a), _np(e))
+        # other parameters: the captured chunk must not be reused
+        other = G.LayoutParams(temperature=G.paper_schedule(g.n, 1.0, 30.0, H),
+                               ideal_length=30.0, precision=G.FP32_KAHAN)
+        f = _t(G, x0, G.FP32_KAHAN)
+        G.run(kh, other, f)
+        os.environ["GILA_NO_GRAPH"] = "1"
+        try:
+            q = _t(G, x0, G.FP32_KAHAN)
+            G.run(kh, other, q)
+        finally:
+            del os.environ["GILA_NO_GRAPH"]
+        assert np.array_equal(_np(f), _np(q))
+        assert not np.array_equal(_np(f), _np(a))
+        kh.free()
+    finally:
+        os.environ.pop("GILA_PATH", None)
+
+
 def test_grid_fp64_trajectory_matches_oracle(G):
     """Config-1 layout end to end (FP64, 100 iterations, device-resident loop).
 
