@@ -138,6 +138,16 @@ int gila_khop_info(const gila_khop* kh, int32_t* n, int32_t* k, int64_t* total_p
  * NULL to skip it.  Synchronises the handle's internal work. */
 int gila_khop_export(const gila_khop* kh, int64_t* ptr_host, int32_t* idx_host);
 
+/* The handle's internal vertex order: order_host[i] (i < n) is the caller id
+ * of the vertex the iteration kernels hold at position i.  Without
+ * degree-order override (GILA_ORDER) it is either |N_v(k)| descending, or,
+ * when most edges join vertices less than 1024 apart in the caller's ids,
+ * rows of at least 8192 k-hop entries first and then the caller's order; in
+ * both, isolated vertices come last and ties keep ascending caller ids.  It
+ * decides the order of every sum, hence the bits of every result.  EINVAL for
+ * a NULL handle or order_host.  Synchronous. */
+int gila_khop_order(const gila_khop* kh, int32_t* order_host);
+
 /* Rows of selected vertices only: for i < count, row verts_host[i] goes to
  * idx_host[ptr_host[i] .. ptr_host[i+1]) in caller ids, ascending.  With
  * idx_host == NULL only ptr_host[count+1] is written (to size the buffer). */

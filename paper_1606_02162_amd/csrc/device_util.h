@@ -23,9 +23,10 @@ __device__ __forceinline__ T wave_inclusive_scan(T x) {
     return x;
 }
 
-// Exclusive prefix sum over a 256-thread workgroup.  `sh` is LDS scratch of
-// at least 4 elements.  Contains two barriers; every thread must call it.
-template <class T>
+// Exclusive prefix sum over a workgroup of NW wavefronts (256 threads by
+// default).  `sh` is LDS scratch of at least NW elements.  Contains two
+// barriers; every thread must call it.
+template <class T, int NW = 4>
 __device__ __forceinline__ T block_exclusive_scan(T v, T* sh, T& total) {
     const int w = wave_id();
     T inc = wave_inclusive_scan(v);
@@ -33,7 +34,7 @@ __device__ __forceinline__ T block_exclusive_scan(T v, T* sh, T& total) {
     __syncthreads();
     T before = 0, tot = 0;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < NW; ++i) {
         T s = sh[i];
         before += (i < w) ? s : T(0);
         tot += s;
@@ -43,9 +44,10 @@ __device__ __forceinline__ T block_exclusive_scan(T v, T* sh, T& total) {
     return before + inc - v;
 }
 
-// Sum over a 256-thread workgroup in a fixed order (butterfly within each
-// wavefront, then wavefronts 0..3 in order).  Result valid in every thread.
-template <class T>
+// Sum over a workgroup of NW wavefronts (256 threads by default) in a fixed
+// order (butterfly within each wavefront, then wavefronts 0..NW-1 in order).
+// Result valid in every thread.
+template <class T, int NW = 4>
 __device__ __forceinline__ T block_sum(T v, T* sh) {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -53,7 +55,7 @@ __device__ __forceinline__ T block_sum(T v, T* sh) {
     __syncthreads();
     T r = sh[0];
 #pragma unroll
-    for (int i = 1; i < 4; ++i) r += sh[i];
+    for (int i = 1; i < NW; ++i) r += sh[i];
     __syncthreads();
     return r;
 }

@@ -310,6 +310,12 @@ int enqueue_exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, int64
                                hipStream_t s);
 // implemented in segment.hip
 int build_segments(gila_khop* kh, int precision, hipStream_t s);
+// Stable sort of the ids 0 .. n-1 by key (ascending; equal keys keep
+// ascending ids) into out[n], ordered on `s`: LSD counting-sort passes of
+// 11-bit digits over the bits of max_key (every key <= max_key).  Scratch is
+// released into the block cache after the work on `s`.
+int stable_order_by_key(int32_t n, const uint32_t* key, uint32_t max_key, int32_t* out,
+                        hipStream_t s);
 void free_segments(gila_khop* kh, Release rel = Release{});
 // span: null, or where the force kernel records its start and end (SegArgs)
 int launch_segment_step(const gila_khop* kh, int precision, const StepArgs& a, hipStream_t s,

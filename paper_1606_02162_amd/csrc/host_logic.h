@@ -143,50 +143,6 @@ inline void admit_release(AdmitState& st, int64_t footprint) {
     st.in_flight -= 1;
 }
 
-// The internal vertex order of a k-hop handle: perm[i] = caller id of
-// internal vertex i.  Isolated vertices last (in caller order).  Degree
-// order: |N_v(k)| descending, ties by caller id.  Caller order: rows of at
-// least hub_min entries first, then the others, each in the caller's order.
-// An LSD radix sort (11-bit digits) of (key << 32 | id) words over the key
-// bits; it is stable, so equal keys keep ascending ids.  counts[n], rp[n+1],
-// perm[n]; every count < 2^31; w and tmp are scratch (resized to n).
-inline void order_vertices(const std::vector<int64_t>& counts, const std::vector<int64_t>& rp,
-                           bool caller_order, int64_t hub_min, std::vector<int32_t>& perm,
-                           std::vector<uint64_t>& w, std::vector<uint64_t>& tmp) {
-    const int32_t n = (int32_t)counts.size();
-    int64_t maxc = 0;
-    for (int32_t v = 0; v < n; ++v) maxc = std::max(maxc, counts[v]);
-    w.resize((size_t)n);
-    tmp.resize((size_t)n);
-    for (int32_t v = 0; v < n; ++v) {
-        const bool isolated = rp[v + 1] == rp[v];
-        uint64_t key;
-        if (caller_order)
-            key = isolated ? 2 : (counts[v] >= hub_min ? 0 : 1);
-        else
-            key = isolated ? (uint64_t)maxc + 1 : (uint64_t)(maxc - counts[v]);
-        w[v] = key << 32 | (uint32_t)v;
-    }
-    const uint64_t kmax = caller_order ? 2 : (uint64_t)maxc + 1;
-    constexpr int kBits = 11;
-    std::vector<int64_t> cnt((size_t)1 << kBits);
-    const uint64_t mask = ((uint64_t)1 << kBits) - 1;
-    for (int shift = 0; shift < 32 && (kmax >> shift) > 0; shift += kBits) {
-        std::fill(cnt.begin(), cnt.end(), 0);
-        for (int32_t i = 0; i < n; ++i) ++cnt[(w[i] >> (32 + shift)) & mask];
-        int64_t run = 0;
-        for (auto& c : cnt) {
-            const int64_t t = c;
-            c = run;
-            run += t;
-        }
-        for (int32_t i = 0; i < n; ++i) tmp[cnt[(w[i] >> (32 + shift)) & mask]++] = w[i];
-        w.swap(tmp);
-    }
-    perm.resize((size_t)n);
-    for (int32_t i = 0; i < n; ++i) perm[i] = (int32_t)(uint32_t)w[i];
-}
-
 // Cap schedules of Section 5.1 (see gila_paper_schedule).
 inline int paper_schedule(double n, double aspect, double d, int32_t iterations, double* t,
                           char* msg, size_t len) {

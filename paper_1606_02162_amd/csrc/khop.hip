@@ -81,26 +81,32 @@ __global__ __launch_bounds__(kBlock) void validate_csr_kernel(int32_t n, int64_t
 // per source instead of O(n/32).
 // Frontier rows at least this long are walked by a whole wavefront.
 constexpr int64_t kWaveRow = 32;
+constexpr int32_t kBfsTake = 4;
 
-template <bool FILL, bool LDS_BITMAP>
-__global__ __launch_bounds__(kBlock) void khop_bfs_kernel(BfsArgs a) {
+// BS threads per workgroup (256 or 512; see run_bfs).  With 512, registers
+// are capped so that 8 wavefronts fit per SIMD.
+
+template <int BS, bool FILL, bool LDS_BITMAP>
+__global__ __launch_bounds__(BS, BS / 64) void khop_bfs_kernel(BfsArgs a) {
+    constexpr int kBfsBlock = BS;
+    constexpr int kBfsWaves = BS / 64;
     extern __shared__ uint32_t s_dyn[];
     constexpr bool SUMMARY = LDS_BITMAP;
     __shared__ int32_t s_v;
     __shared__ int32_t s_qtail;
-    __shared__ int64_t s_incl[kBlock];   // degree of each listed long frontier row
-    __shared__ int64_t s_start[kBlock];  // row start of each listed long frontier row
-    __shared__ int32_t s_nbig;           // long rows listed in this chunk
-    __shared__ int64_t s_red[4];
+    __shared__ int32_t s_bw[kBfsBlock];    // frontier vertex of each listed long row
+    __shared__ int32_t s_bdeg[kBfsBlock];  // its degree
+    __shared__ int32_t s_nbig;             // long rows listed in this chunk
+    __shared__ int64_t s_red[kBfsWaves];
 
     uint32_t* bm = LDS_BITMAP ? s_dyn : a.gbitmap + (size_t)blockIdx.x * a.nwords;
     uint32_t* sm = s_dyn + a.nwords;  // summary (LDS bitmap only)
     int32_t* queue = a.queue ? a.queue + (size_t)blockIdx.x * a.qcap : nullptr;
 
     if (threadIdx.x == 0) s_nbig = 0;
-    for (int i = threadIdx.x; i < a.nwords; i += kBlock) bm[i] = 0u;
+    for (int i = threadIdx.x; i < a.nwords; i += kBfsBlock) bm[i] = 0u;
     if constexpr (SUMMARY)
-        for (int i = threadIdx.x; i < (a.nwords + 31) / 32; i += kBlock) sm[i] = 0u;
+        for (int i = threadIdx.x; i < (a.nwords + 31) / 32; i += kBfsBlock) sm[i] = 0u;
     __syncthreads();
     // sets bit u; true if it was clear
     auto visit = [&](int64_t u) -> bool {
@@ -111,163 +117,211 @@ __global__ __launch_bounds__(kBlock) void khop_bfs_kernel(BfsArgs a) {
         return !(old & bit);
     };
 
+    // sources are taken kBfsTake at a time (one atomic per group)
     for (;;) {
-        if (threadIdx.x == 0) s_v = atomicAdd(a.work, 1);
+        if (threadIdx.x == 0) s_v = atomicAdd(a.work, kBfsTake);
         __syncthreads();
-        const int32_t v = s_v;
-        if (v >= a.nverts) break;
-        // the source's graph: id base, bitmap words and k
-        int64_t base = 0;
-        int32_t nw = a.nwords, k = a.k;
-        if (a.gvbase) {
-            int32_t lo = 0, hi = a.ngraphs - 1;
-            while (lo < hi) {
-                const int32_t mid = lo + (hi - lo + 1) / 2;
-                if (a.gvbase[mid] <= v) lo = mid;
-                else hi = mid - 1;
-            }
-            base = a.gvbase[lo];
-            nw = (int32_t)((a.gvbase[lo + 1] - base + 31) / 32);
-            k = a.gk[lo];
-        }
-        const int64_t rb = a.rp[v], re = a.rp[v + 1];
-        int64_t mycount = 0;
-        if (re > rb) {
-            if (threadIdx.x == 0) {
-                visit(v - base);
-                s_qtail = 0;
-            }
-            __syncthreads();
-            // level 1: the adjacency row (distinct, never v in a simple graph)
-            for (int64_t e = rb + threadIdx.x; e < re; e += kBlock)
-                if (visit(a.ci[e] - base)) ++mycount;
-            __syncthreads();
-            // levels 2..k: expand the previous level's new vertices.  A frontier
-            // vertex with a short row is walked by one lane; long rows are
-            // listed in LDS and walked by whole wavefronts (coalesced reads).
-            // The visited set does not depend on the order of the visits.
-            int64_t fb = rb, fe = re;
-            bool from_queue = false;
-            for (int level = 2; level <= k; ++level) {
-                const bool record = level < k;
-                const int32_t qstart = s_qtail;
-                // every thread has read the level's queue start before any
-                // thread appends to the queue
-                __syncthreads();
-                auto expand = [&](int32_t ug) {
-                    if (visit(ug - base)) {
-                        ++mycount;
-                        if (record) {
-                            const int32_t q = atomicAdd(&s_qtail, 1);
-                            queue[q] = ug;
-                        }
-                    }
-                };
-                for (int64_t c = fb; c < fe; c += kBlock) {
-                    const int64_t i = c + threadIdx.x;
-                    int64_t deg = 0, start = 0;
-                    if (i < fe) {
-                        const int32_t w = from_queue ? queue[i] : a.ci[i];
-                        start = a.rp[w];
-                        deg = a.rp[w + 1] - start;
-                    }
-                    if (deg >= kWaveRow) {
-                        const int b = atomicAdd(&s_nbig, 1);
-                        s_start[b] = start;
-                        s_incl[b] = deg;
-                    } else {
-                        for (int64_t e = 0; e < deg; ++e) expand(a.ci[start + e]);
-                    }
-                    __syncthreads();
-                    const int nbig = s_nbig;
-                    for (int b = wave_id(); b < nbig; b += kWaves) {
-                        const int64_t bs = s_start[b], bd = s_incl[b];
-                        for (int64_t e = lane64(); e < bd; e += 64) expand(a.ci[bs + e]);
-                    }
-                    __syncthreads();
-                    if (threadIdx.x == 0) s_nbig = 0;
-                    __syncthreads();
+        const int32_t v0 = s_v;
+        if (v0 >= a.nverts) break;
+        const int32_t v1 = min(v0 + kBfsTake, a.nverts);
+        for (int32_t v = v0; v < v1; ++v) {
+            // the source's graph: id base, bitmap words and k
+            int64_t base = 0;
+            int32_t nw = a.nwords, k = a.k;
+            if (a.gvbase) {
+                int32_t lo = 0, hi = a.ngraphs - 1;
+                while (lo < hi) {
+                    const int32_t mid = lo + (hi - lo + 1) / 2;
+                    if (a.gvbase[mid] <= v) lo = mid;
+                    else hi = mid - 1;
                 }
-                fb = qstart;
-                fe = s_qtail;
-                from_queue = true;
-                __syncthreads();
+                base = a.gvbase[lo];
+                nw = (int32_t)((a.gvbase[lo + 1] - base + 31) / 32);
+                k = a.gk[lo];
             }
-        }
-        if constexpr (!FILL) {
-            const int64_t cnt = block_sum<int64_t>(mycount, s_red);
-            if (threadIdx.x == 0) a.counts[v] = cnt;
-            if (re > rb) {
-                if constexpr (SUMMARY) {
-                    for (int i = threadIdx.x; i < (nw + 31) / 32; i += kBlock) {
-                        uint32_t t = sm[i];
-                        while (t) {
-                            bm[i * 32 + __builtin_ctz(t)] = 0u;
-                            t &= t - 1u;
-                        }
-                        sm[i] = 0u;
-                    }
-                } else {
-                    for (int i = threadIdx.x; i < nw; i += kBlock) bm[i] = 0u;
-                }
-            }
-        } else {
+            const int64_t rb = a.rp[v], re = a.rp[v + 1];
+            int64_t mycount = 0;
             if (re > rb) {
                 if (threadIdx.x == 0) {
-                    const int64_t lv = v - base;
-                    bm[lv >> 5] &= ~(1u << (lv & 31));
+                    visit(v - base);
+                    s_qtail = 0;
                 }
                 __syncthreads();
-                int64_t pos = a.kptr[v];
-                const int64_t end = a.kptr[v + 1];
-                auto emit = [&](int wi, uint32_t word, int64_t& o) {
-                    while (word) {
-                        const int b = __ffs(word) - 1;
-                        const int64_t local = (int64_t)wi * 32 + b;
-                        if (o < end) {
-                            if (a.kidx16) a.kidx16[o] = (uint16_t)local;
-                            else a.kidx[o] = (int32_t)(base + local);
+                // level 1: the adjacency row (distinct, never v in a simple graph)
+                for (int64_t e = rb + threadIdx.x; e < re; e += kBfsBlock)
+                    if (visit(a.ci[e] - base)) ++mycount;
+                __syncthreads();
+                // levels 2..k: expand the previous level's new vertices.  A frontier
+                // vertex with a short row is walked by one lane; long rows are
+                // listed in LDS and walked by whole wavefronts (coalesced reads).
+                // The visited set does not depend on the order of the visits.
+                int64_t fb = rb, fe = re;
+                bool from_queue = false;
+                for (int level = 2; level <= k; ++level) {
+                    const bool record = level < k;
+                    const int32_t qstart = s_qtail;
+                    // every thread has read the level's queue start before any
+                    // thread appends to the queue
+                    __syncthreads();
+                    auto expand = [&](int32_t ug) {
+                        if (visit(ug - base)) {
+                            ++mycount;
+                            if (record) {
+                                const int32_t q = atomicAdd(&s_qtail, 1);
+                                queue[q] = ug;
+                            }
                         }
-                        ++o;
-                        word &= word - 1u;
-                    }
-                };
-                if constexpr (SUMMARY) {
-                    // thread t owns summary word i: the 32 bitmap words of ids
-                    // [1024 i, 1024 (i + 1)), emitted in order after a scan
-                    const int ns = (nw + 31) / 32;
-                    for (int s0 = 0; s0 < ns; s0 += kBlock) {
-                        const int si = s0 + threadIdx.x;
-                        const uint32_t t0 = si < ns ? sm[si] : 0u;
-                        int64_t c = 0;
-                        for (uint32_t t = t0; t; t &= t - 1u) c += __popc(bm[si * 32 + __builtin_ctz(t)]);
-                        int64_t total;
-                        const int64_t ex = block_exclusive_scan<int64_t>(c, s_red, total);
-                        int64_t o = pos + ex;
-                        for (uint32_t t = t0; t; t &= t - 1u) {
-                            const int wi = si * 32 + __builtin_ctz(t);
-                            emit(wi, bm[wi], o);
-                            bm[wi] = 0u;
+                    };
+                    for (int64_t c = fb; c < fe; c += kBfsBlock) {
+                        const int64_t i = c + threadIdx.x;
+                        int64_t deg = 0, start = 0;
+                        int32_t w = 0;
+                        if (i < fe) {
+                            w = from_queue ? queue[i] : a.ci[i];
+                            start = a.rp[w];
+                            deg = a.rp[w + 1] - start;
                         }
-                        if (si < ns) sm[si] = 0u;
-                        pos += total;
+                        if (deg >= kWaveRow) {
+                            const int b = atomicAdd(&s_nbig, 1);
+                            s_bw[b] = w;
+                            s_bdeg[b] = (int32_t)deg;
+                        } else {
+                            int64_t e = 0;
+                            for (; e + 4 <= deg; e += 4) {
+                                const int32_t u0 = a.ci[start + e], u1 = a.ci[start + e + 1];
+                                const int32_t u2 = a.ci[start + e + 2], u3 = a.ci[start + e + 3];
+                                expand(u0);
+                                expand(u1);
+                                expand(u2);
+                                expand(u3);
+                            }
+                            for (; e < deg; ++e) expand(a.ci[start + e]);
+                        }
+                        __syncthreads();
+                        const int nbig = s_nbig;
+                        for (int b = wave_id(); b < nbig; b += kBfsWaves) {
+                            const int64_t bs = a.rp[s_bw[b]], bd = s_bdeg[b];
+                            int64_t e = lane64();
+                            for (; e + 192 < bd; e += 256) {
+                                const int32_t u0 = a.ci[bs + e], u1 = a.ci[bs + e + 64];
+                                const int32_t u2 = a.ci[bs + e + 128], u3 = a.ci[bs + e + 192];
+                                expand(u0);
+                                expand(u1);
+                                expand(u2);
+                                expand(u3);
+                            }
+                            for (; e < bd; e += 64) expand(a.ci[bs + e]);
+                        }
+                        __syncthreads();
+                        if (threadIdx.x == 0) s_nbig = 0;
+                        __syncthreads();
                     }
-                } else {
-                    for (int w0 = 0; w0 < nw; w0 += kBlock) {
-                        const int wi = w0 + threadIdx.x;
-                        const uint32_t word = wi < nw ? bm[wi] : 0u;
-                        int64_t total;
-                        const int64_t ex =
-                            block_exclusive_scan<int64_t>((int64_t)__popc(word), s_red, total);
-                        int64_t o = pos + ex;
-                        emit(wi, word, o);
-                        if (wi < nw) bm[wi] = 0u;
-                        pos += total;
+                    fb = qstart;
+                    fe = s_qtail;
+                    from_queue = true;
+                    __syncthreads();
+                }
+            }
+            if constexpr (!FILL) {
+                const int64_t cnt = block_sum<int64_t, kBfsWaves>(mycount, s_red);
+                if (threadIdx.x == 0) a.counts[v] = cnt;
+                if (re > rb) {
+                    if constexpr (SUMMARY) {
+                        for (int i = threadIdx.x; i < (nw + 31) / 32; i += kBfsBlock) {
+                            uint32_t t = sm[i];
+                            while (t) {
+                                bm[i * 32 + __builtin_ctz(t)] = 0u;
+                                t &= t - 1u;
+                            }
+                            sm[i] = 0u;
+                        }
+                    } else {
+                        for (int i = threadIdx.x; i < nw; i += kBfsBlock) bm[i] = 0u;
+                    }
+                }
+            } else {
+                if (re > rb) {
+                    if (threadIdx.x == 0) {
+                        const int64_t lv = v - base;
+                        bm[lv >> 5] &= ~(1u << (lv & 31));
+                    }
+                    __syncthreads();
+                    int64_t pos = a.kptr[v];
+                    const int64_t end = a.kptr[v + 1];
+                    auto emit = [&](int wi, uint32_t word, int64_t& o) {
+                        while (word) {
+                            const int b = __ffs(word) - 1;
+                            const int64_t local = (int64_t)wi * 32 + b;
+                            if (o < end) {
+                                if (a.kidx16) a.kidx16[o] = (uint16_t)local;
+                                else a.kidx[o] = (int32_t)(base + local);
+                            }
+                            ++o;
+                            word &= word - 1u;
+                        }
+                    };
+                    if constexpr (SUMMARY) {
+                        // Rounds of kBfsBlock summary words (1024 ids each).  Thread
+                        // t counts the ids under summary word t; the non-empty
+                        // words are listed with their first output position, then
+                        // each half wavefront emits one listed word at a time,
+                        // lane h taking bitmap word h of it: ids come out in
+                        // order, and a few dense summary words (the hubs, which
+                        // most rows reach) are shared by 32 lanes, not walked by
+                        // one thread.
+                        int32_t* s_lex = s_bdeg;  // offset within the round
+                        int32_t* s_lsi = s_bw;
+                        const int ns = (nw + 31) / 32;
+                        const int half = lane64() >> 5, h = lane64() & 31;
+                        for (int s0 = 0; s0 < ns; s0 += kBfsBlock) {
+                            const int si = s0 + threadIdx.x;
+                            const uint32_t t0 = si < ns ? sm[si] : 0u;
+                            int64_t c = 0;
+                            for (uint32_t t = t0; t; t &= t - 1u) c += __popc(bm[si * 32 + __builtin_ctz(t)]);
+                            if (si < ns) sm[si] = 0u;
+                            int64_t total, nlist;
+                            const int64_t ex = block_exclusive_scan<int64_t, kBfsWaves>(c, s_red, total);
+                            const int64_t li = block_exclusive_scan<int64_t, kBfsWaves>(c > 0 ? 1 : 0, s_red, nlist);
+                            if (c > 0) {
+                                s_lsi[li] = si;
+                                s_lex[li] = (int32_t)ex;
+                            }
+                            __syncthreads();
+                            for (int64_t j = wave_id() * 2 + half; j < nlist; j += 2 * kBfsWaves) {
+                                const int wi = s_lsi[j] * 32 + h;
+                                const uint32_t word = wi < nw ? bm[wi] : 0u;
+                                // exclusive prefix of the popcounts over the half
+                                const int32_t cnt = __popc(word);
+                                int32_t inc = cnt;
+#pragma unroll
+                                for (int off = 1; off < 32; off <<= 1) {
+                                    const int32_t y = __shfl_up(inc, off, 32);
+                                    if (h >= off) inc += y;
+                                }
+                                int64_t o = pos + s_lex[j] + (inc - cnt);
+                                emit(wi, word, o);
+                                if (wi < nw) bm[wi] = 0u;
+                            }
+                            pos += total;
+                            __syncthreads();
+                        }
+                    } else {
+                        for (int w0 = 0; w0 < nw; w0 += kBfsBlock) {
+                            const int wi = w0 + threadIdx.x;
+                            const uint32_t word = wi < nw ? bm[wi] : 0u;
+                            int64_t total;
+                            const int64_t ex =
+                                block_exclusive_scan<int64_t, kBfsWaves>((int64_t)__popc(word), s_red, total);
+                            int64_t o = pos + ex;
+                            emit(wi, word, o);
+                            if (wi < nw) bm[wi] = 0u;
+                            pos += total;
+                        }
                     }
                 }
             }
+            __syncthreads();
         }
-        __syncthreads();
     }
 }
 
@@ -349,15 +403,28 @@ int run_bfs(bool fill, int device, hipStream_t s, BfsArgs a) {
     const char* bm_env = getenv("GILA_BFS_BITMAP");
     const bool lds = bm_bytes + 8 * 1024 * 2 + 1024 <= di.max_lds_per_block &&
                      !(bm_env && std::strcmp(bm_env, "global") == 0);
-    // workgroups resident per CU limited by LDS (160 KB per CU on gfx950)
+    // Workgroup shape.  256 threads while the LDS lets 8 such workgroups
+    // share a CU (32 wavefronts); larger bitmaps (more than ~2^17 ids) take
+    // 512-thread workgroups, at most 4 per CU, so that 32 wavefronts per CU
+    // still keep the frontier's scattered row reads in flight.  The k = 1
+    // pass (short rows, no expansion) keeps 256.  Static LDS: the long-row
+    // lists (8 bytes per thread) and a few words.
+    const int32_t kmax = a.gvbase ? a.kmax : a.k;
+    auto fit = [&](int bs) {
+        const size_t per = bm_bytes + 8 * (size_t)bs + 256;
+        return (int)std::max<size_t>(1, std::min<size_t>(2048 / bs, (160u * 1024u) / per));
+    };
+    int bs = 256;
     int per_cu = 8;
     if (lds) {
-        size_t per = bm_bytes + 4096;
-        per_cu = (int)std::max<size_t>(1, std::min<size_t>(8, (160u * 1024u) / per));
+        per_cu = fit(256);
+        if (per_cu < 8 && kmax >= 2) {
+            bs = 512;
+            per_cu = fit(512);
+        }
     }
     int grid = di.cus * per_cu;
     if (a.nverts < grid) grid = std::max(1, a.nverts);
-    const int32_t kmax = a.gvbase ? a.kmax : a.k;
     if (kmax >= 3) {
         // frontier queues: one graph's vertex count per workgroup (the
         // largest graph in batch mode), capped at ~1 GiB in total
@@ -382,26 +449,21 @@ int run_bfs(bool fill, int device, hipStream_t s, BfsArgs a) {
     hipError_t e = hipSuccess;
     hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, a.work);
     const size_t shm = lds ? bm_bytes : 0;
-    if (fill) {
-        if (lds) {
-            if (shm > 65536)
-                (void)hipFuncSetAttribute((const void*)khop_bfs_kernel<true, true>,
-                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-            hipLaunchKernelGGL((khop_bfs_kernel<true, true>), dim3(grid), dim3(kBlock), shm, s, a);
-        } else {
-            hipLaunchKernelGGL((khop_bfs_kernel<true, false>), dim3(grid), dim3(kBlock), 0, s, a);
-        }
+    auto launch = [&](auto kernel, int threads) {
+        if (shm > 65536)
+            (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)shm);
+        hipLaunchKernelGGL(kernel, dim3(grid), dim3(threads), shm, s, a);
+    };
+    if (bs == 512) {
+        if (fill) launch(khop_bfs_kernel<512, true, true>, 512);
+        else launch(khop_bfs_kernel<512, false, true>, 512);
+    } else if (lds) {
+        if (fill) launch(khop_bfs_kernel<256, true, true>, 256);
+        else launch(khop_bfs_kernel<256, false, true>, 256);
     } else {
-        if (lds) {
-            if (shm > 65536)
-                (void)hipFuncSetAttribute((const void*)khop_bfs_kernel<false, true>,
-                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-            hipLaunchKernelGGL((khop_bfs_kernel<false, true>), dim3(grid), dim3(kBlock), shm, s,
-                               a);
-        } else {
-            hipLaunchKernelGGL((khop_bfs_kernel<false, false>), dim3(grid), dim3(kBlock), 0, s,
-                               a);
-        }
+        if (fill) launch(khop_bfs_kernel<256, true, false>, 256);
+        else launch(khop_bfs_kernel<256, false, false>, 256);
     }
     e = hipGetLastError();
     if (e != hipSuccess) rc = fail(GILA_EDEVICE, "k-hop kernel launch: %s", hipGetErrorString(e));
@@ -480,7 +542,42 @@ static bool use_caller_order(unsigned long long near_edges, int64_t nnz) {
     return nnz > 0 && (double)near_edges >= 0.7 * (double)nnz;
 }
 
-// The internal order itself: host::order_vertices (host_logic.h).
+// Sort key of each caller vertex; the internal order is the ascending order
+// of the keys, equal keys by ascending caller id.  Degree order: |N_v(k)|
+// descending (n - 1 - |N_v(k)|), isolated vertices last (n).  Caller order:
+// rows of at least hub_min entries (0), then the other non-isolated vertices
+// (1), then the isolated ones (2).
+__global__ __launch_bounds__(kBlock) void order_key_kernel(int32_t n, const int64_t* __restrict__ rp,
+                                                           const int64_t* __restrict__ counts,
+                                                           int32_t caller_order, int64_t hub_min,
+                                                           uint32_t* __restrict__ key) {
+    for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * kBlock) {
+        const bool isolated = rp[v + 1] == rp[v];
+        const int64_t c = counts[v];
+        uint32_t kv;
+        if (caller_order) kv = isolated ? 2u : (c >= hub_min ? 0u : 1u);
+        else kv = isolated ? (uint32_t)n : (uint32_t)(n - 1 - c);
+        key[v] = kv;
+    }
+}
+
+// Internal vertex i = caller vertex perm[i]: the inverse permutation and the
+// degree and list length of each internal row (their exclusive sums are the
+// internal row pointers and list offsets).
+__global__ __launch_bounds__(kBlock) void internal_rows_kernel(
+    int32_t n, const int32_t* __restrict__ perm, const int64_t* __restrict__ rp,
+    const int64_t* __restrict__ counts, int32_t* __restrict__ iperm, int64_t* __restrict__ deg,
+    int64_t* __restrict__ cnt) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock) {
+        const int32_t v = perm[i];
+        iperm[v] = (int32_t)i;
+        deg[i] = rp[v + 1] - rp[v];
+        cnt[i] = counts[v];
+    }
+}
+
 int build_khop(const gila_csr* g, int32_t k, hipStream_t s, gila_khop** out) {
     if (!out) return fail(GILA_EINVAL, "out is NULL");
     *out = nullptr;
@@ -512,8 +609,14 @@ int build_khop(const gila_csr* g, int32_t k, hipStream_t s, gila_khop** out) {
         GILA_HIP(hipStreamSynchronize(s));
         if (rp_host[0] != 0 || rp_host[n] != nnz)
             return fail(GILA_EINVAL, "row_ptr[0] must be 0 and row_ptr[n] must equal nnz");
-        for (int32_t v = 0; v < n; ++v)
-            if (rp_host[v + 1] < rp_host[v]) return fail(GILA_EINVAL, "row_ptr not monotone");
+        int32_t bad = -1, active = 0;
+        for (int32_t v = 0; v < n; ++v) {
+            const int64_t d = rp_host[v + 1] - rp_host[v];
+            bad = (d < 0 && bad < 0) ? v : bad;
+            active += d > 0 ? 1 : 0;
+        }
+        if (bad >= 0) return fail(GILA_EINVAL, "row_ptr not monotone");
+        kh->n_active = active;
         if (nnz % 2) return fail(GILA_EINVAL, "nnz must be even for a symmetric CSR");
     }
 
@@ -553,10 +656,14 @@ int build_khop(const gila_csr* g, int32_t k, hipStream_t s, gila_khop** out) {
     pt.mark("validate");
     // --- count pass on the caller's graph
     const int32_t nwords = (n + 31) / 32;
-    std::vector<int64_t> counts((size_t)n, 0);
     int64_t* d_counts = nullptr;
+    GILA_TRY(dalloc_t(&d_counts, (size_t)std::max(n, 1)));
+    struct C {
+        int64_t* p;
+        hipStream_t s;
+        ~C() { dfree_on(p, s); }
+    } cguard{d_counts, s};
     if (n > 0) {
-        GILA_TRY(dalloc_t(&d_counts, (size_t)n));
         BfsArgs a{};
         a.n = n;
         a.k = k;
@@ -566,55 +673,56 @@ int build_khop(const gila_csr* g, int32_t k, hipStream_t s, gila_khop** out) {
         a.ci = g->col_idx;
         a.counts = d_counts;
         a.work = d_work;
-        int rc = run_bfs(false, dev, s, a);
-        if (rc == GILA_OK) {
-            hipError_t e = hipMemcpyAsync(counts.data(), d_counts, sizeof(int64_t) * n,
-                                          hipMemcpyDeviceToHost, s);
-            if (e == hipSuccess) e = hipStreamSynchronize(s);
-            if (e != hipSuccess) rc = fail(GILA_EDEVICE, "copy counts: %s", hipGetErrorString(e));
-        }
-        dfree_on(d_counts, s);
-        if (rc) return rc;
+        GILA_TRY(run_bfs(false, dev, s, a));
     }
 
     pt.mark("count");
-    // --- internal order (non-isolated vertices first)
+    // --- internal order (non-isolated vertices first), its graph and list
+    // offsets, all on the device
     kh->caller_order = use_caller_order(near_edges, nnz);
-    std::vector<int32_t> perm((size_t)n), iperm((size_t)n);
-    {
-        std::vector<uint64_t> w, tmp;
-        host::order_vertices(counts, rp_host, kh->caller_order, kHubMin, perm, w, tmp);
-    }
-    for (int32_t i = 0; i < n; ++i) iperm[perm[i]] = i;
-    int64_t P = 0;
-    int32_t n_active = 0;
-    std::vector<int64_t> rp_int((size_t)n + 1, 0), kptr((size_t)n + 1, 0), cnt_int((size_t)n);
-    for (int32_t i = 0; i < n; ++i) {
-        const int32_t v = perm[i];
-        cnt_int[i] = counts[v];
-        rp_int[i + 1] = rp_int[i] + (rp_host[v + 1] - rp_host[v]);
-        kptr[i + 1] = kptr[i] + counts[v];
-        if (rp_host[v + 1] > rp_host[v]) ++n_active;
-    }
-    P = kptr[n];
-    kh->P = P;
-    kh->n_active = n_active;
-
-    pt.mark("order");
-    // --- internal graph copy
     GILA_TRY(dalloc_t(&kh->perm, (size_t)n));
     GILA_TRY(dalloc_t(&kh->iperm, (size_t)n));
     GILA_TRY(dalloc_t(&kh->rp, (size_t)n + 1));
     GILA_TRY(dalloc_t(&kh->ci, (size_t)nnz));
     GILA_TRY(dalloc_t(&kh->kptr, (size_t)n + 1));
+    int64_t P = 0;
+    if (n > 0) {
+        struct T {
+            void* p = nullptr;
+            hipStream_t s;
+            ~T() { dfree_on(p, s); }
+        } key{nullptr, s}, deg{nullptr, s}, cnt{nullptr, s}, ws{nullptr, s};
+        GILA_TRY(dalloc_t(reinterpret_cast<uint32_t**>(&key.p), (size_t)n));
+        GILA_TRY(dalloc_t(reinterpret_cast<int64_t**>(&deg.p), (size_t)n));
+        GILA_TRY(dalloc_t(reinterpret_cast<int64_t**>(&cnt.p), (size_t)n));
+        GILA_TRY(dalloc_t(reinterpret_cast<int64_t**>(&ws.p), (size_t)scan_workspace_count(n)));
+        const unsigned grid = (unsigned)std::min<int64_t>(4096, ((int64_t)n + kBlock - 1) / kBlock);
+        hipLaunchKernelGGL(order_key_kernel, dim3(grid), dim3(kBlock), 0, s, n, g->row_ptr,
+                           d_counts, (int32_t)kh->caller_order, kHubMin,
+                           static_cast<uint32_t*>(key.p));
+        GILA_HIP(hipGetLastError());
+        const uint32_t max_key = kh->caller_order ? 2u : (uint32_t)n;
+        GILA_TRY(stable_order_by_key(n, static_cast<const uint32_t*>(key.p), max_key, kh->perm, s));
+        hipLaunchKernelGGL(internal_rows_kernel, dim3(grid), dim3(kBlock), 0, s, n, kh->perm,
+                           g->row_ptr, d_counts, kh->iperm, static_cast<int64_t*>(deg.p),
+                           static_cast<int64_t*>(cnt.p));
+        GILA_HIP(hipGetLastError());
+        int64_t* sws = static_cast<int64_t*>(ws.p);
+        GILA_TRY(enqueue_exclusive_scan_i64(static_cast<int64_t*>(deg.p), kh->rp, n, sws, s));
+        GILA_TRY(enqueue_exclusive_scan_i64(static_cast<int64_t*>(cnt.p), kh->kptr, n, sws, s));
+        int64_t tail[2] = {0, 0};
+        GILA_HIP(hipMemcpyAsync(&tail[0], kh->kptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        GILA_HIP(hipMemcpyAsync(&tail[1], kh->rp + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        GILA_HIP(hipStreamSynchronize(s));
+        if (tail[1] != nnz) return fail(GILA_EDEVICE, "internal row pointers do not sum to nnz");
+        P = tail[0];
+    }
+    kh->P = P;
     GILA_TRY(dalloc_t(&kh->kidx, (size_t)P));
-    GILA_HIP(hipMemcpyAsync(kh->perm, perm.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
-    GILA_HIP(hipMemcpyAsync(kh->iperm, iperm.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice,
-                            s));
-    GILA_HIP(hipMemcpyAsync(kh->rp, rp_int.data(), sizeof(int64_t) * (n + 1),
-                            hipMemcpyHostToDevice, s));
-    GILA_HIP(hipMemcpyAsync(kh->kptr, kptr.data(), sizeof(int64_t) * (n + 1),
-                            hipMemcpyHostToDevice, s));
+
+    pt.mark("order");
+    const int32_t n_active = kh->n_active;
+    // --- internal graph copy
     if (n > 0 && nnz > 0) {
         const int grid = (int)std::min<int64_t>(8192, ((int64_t)n * 64 + kBlock - 1) / kBlock);
         hipLaunchKernelGGL(relabel_csr_kernel, dim3(grid), dim3(kBlock), 0, s, n, kh->perm,
@@ -663,12 +771,10 @@ int build_khop(const gila_csr* g, int32_t k, hipStream_t s, gila_khop** out) {
     }
 
     pt.mark("fill");
-    // --- plan of the iteration kernel and its workspace
-    GILA_TRY(plan_iteration(kh, cnt_int, rp_int, s));
+    // --- iteration workspace (the direct path's plan and partials are made
+    // on its first use)
     GILA_TRY(dalloc_t(reinterpret_cast<double**>(&kh->pos[0]), 2 * (size_t)std::max(n, 1)));
     GILA_TRY(dalloc_t(reinterpret_cast<double**>(&kh->pos[1]), 2 * (size_t)std::max(n, 1)));
-    GILA_TRY(dalloc_t(&kh->partials, (size_t)std::max(kh->nblocks, 1)));
-    kh->partials_cap = std::max(kh->nblocks, 1);
     GILA_TRY(dalloc_t(&kh->ctl, 1));
     GILA_HIP(hipMemsetAsync(kh->ctl, 0, sizeof(Ctl), s));
     GILA_HIP(hipStreamSynchronize(s));
@@ -682,7 +788,7 @@ int build_khop(const gila_csr* g, int32_t k, hipStream_t s, gila_khop** out) {
     }
     kh->device_bytes = (int64_t)sizeof(int32_t) * 2 * n + sizeof(int64_t) * 2 * (n + 1) +
                        sizeof(int32_t) * (nnz + P) + 32 * (int64_t)n +
-                       (int64_t)sizeof(Partial) * kh->nblocks + sizeof(int32_t) * (kh->nblocks + 1);
+                       (int64_t)sizeof(Partial) * kh->partials_cap;
     *out = kh;
     h.p = nullptr;
     return GILA_OK;
@@ -707,6 +813,16 @@ int gila_khop_info(const gila_khop* kh, int32_t* n, int32_t* k, int64_t* total_p
     if (total_pairs) *total_pairs = kh->P;
     if (n_active) *n_active = kh->n_active;
     if (device_bytes) *device_bytes = kh->device_bytes;
+    return GILA_OK;
+}
+
+int gila_khop_order(const gila_khop* kh, int32_t* order_host) {
+    clear_error();
+    if (!kh) return fail(GILA_EINVAL, "handle is NULL");
+    if (!order_host) return fail(GILA_EINVAL, "order_host is NULL");
+    if (kh->n == 0) return GILA_OK;
+    DeviceGuard dg(kh->device);
+    GILA_HIP(hipMemcpy(order_host, kh->perm, sizeof(int32_t) * kh->n, hipMemcpyDeviceToHost));
     return GILA_OK;
 }
 

@@ -375,16 +375,46 @@ int enqueue_tick(gila_khop* kh, const gila_params* p, int32_t h, int32_t count,
     return GILA_OK;
 }
 
-int prepare_precision(gila_khop* kh, int precision, hipStream_t s) {
-    if (!segment_path_enabled()) return GILA_OK;
-    if (segment_ready_for(kh, precision)) return GILA_OK;
-    drop_graphs(kh);
-    const int rc = build_segments(kh, precision, s);
-    if (rc == GILA_EUNSUPPORTED) {
-        clear_error();
-        return GILA_OK;  // the direct-gather kernel serves this graph
+// The direct-gather kernel's workgroup plan, made from the list lengths and
+// degrees on its first use, and its partials.
+static int ensure_direct_plan(gila_khop* kh, hipStream_t s) {
+    if (kh->block_start) return GILA_OK;
+    const int32_t n = kh->n;
+    std::vector<int64_t> kptr((size_t)n + 1, 0), rp((size_t)n + 1, 0);
+    if (n > 0) {
+        GILA_HIP(hipMemcpyAsync(kptr.data(), kh->kptr, sizeof(int64_t) * (n + 1),
+                                hipMemcpyDeviceToHost, s));
+        GILA_HIP(hipMemcpyAsync(rp.data(), kh->rp, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost,
+                                s));
+        GILA_HIP(hipStreamSynchronize(s));
     }
-    return rc;
+    std::vector<int64_t> counts((size_t)n);
+    for (int32_t i = 0; i < n; ++i) counts[i] = kptr[i + 1] - kptr[i];
+    GILA_TRY(plan_iteration(kh, counts, rp, s));
+    kh->device_bytes += (int64_t)sizeof(int32_t) * (kh->nblocks + 1);
+    if (kh->nblocks > kh->partials_cap) {
+        drop_graphs(kh);  // captured graphs hold the old partials
+        dfree_on(kh->partials, s);
+        kh->partials = nullptr;
+        kh->device_bytes -= (int64_t)sizeof(Partial) * kh->partials_cap;
+        kh->partials_cap = 0;
+        GILA_TRY(dalloc_t(&kh->partials, (size_t)kh->nblocks));
+        kh->partials_cap = kh->nblocks;
+        kh->device_bytes += (int64_t)sizeof(Partial) * kh->partials_cap;
+    }
+    return GILA_OK;
+}
+
+int prepare_precision(gila_khop* kh, int precision, hipStream_t s) {
+    if (segment_path_enabled()) {
+        if (segment_ready_for(kh, precision)) return GILA_OK;
+        drop_graphs(kh);
+        const int rc = build_segments(kh, precision, s);
+        if (rc == GILA_OK) return GILA_OK;
+        if (rc != GILA_EUNSUPPORTED) return rc;
+        clear_error();  // the direct-gather kernel serves this graph
+    }
+    return ensure_direct_plan(kh, s);
 }
 
 int launch_iteration(const gila_khop* kh, int precision, const StepArgs& a, hipStream_t s) {
@@ -535,7 +565,7 @@ int run_iterations(gila_khop* kh, const gila_params* p, int32_t start_h, int32_t
     Ctl c{};
     GILA_HIP(hipMemcpyAsync(&c, kh->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
     GILA_HIP(hipStreamSynchronize(stream));
-    if (kh->nblocks == 0) c.iters_run = end_h - start_h;  // nothing can move
+    if (kh->n_active == 0) c.iters_run = end_h - start_h;  // nothing can move
     if (out) to_stats(c, out);
     return nonfinite_status(c);
 }
@@ -626,7 +656,7 @@ int gila_step(const gila_khop* kh_c, const gila_params* params, int32_t h, void*
         Ctl c{};
         GILA_HIP(hipMemcpyAsync(&c, kh->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
         GILA_HIP(hipStreamSynchronize(s));
-        if (kh->nblocks == 0) c.iters_run = 1;
+        if (kh->n_active == 0) c.iters_run = 1;
         to_stats(c, out);
         return nonfinite_status(c);
     }

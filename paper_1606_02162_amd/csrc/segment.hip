@@ -234,6 +234,59 @@ __global__ __launch_bounds__(64) void slice_scatter_kernel(int64_t T, int64_t tj
     }
 }
 
+// One 11-bit digit of each element's key, for the LSD passes below.
+constexpr int kOrderDigitBits = 11;
+__global__ __launch_bounds__(kBlock) void key_digit_kernel(int32_t n, const uint32_t* __restrict__ key,
+                                                           int shift, int32_t* __restrict__ digit) {
+    for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * kBlock)
+        digit[v] = (int32_t)((key[v] >> shift) & ((1u << kOrderDigitBits) - 1u));
+}
+
+int stable_order_by_key(int32_t n, const uint32_t* key, uint32_t max_key, int32_t* out,
+                        hipStream_t s) {
+    if (n <= 0) return GILA_OK;
+    int passes = 1;
+    while (passes * kOrderDigitBits < 32 && (max_key >> (passes * kOrderDigitBits)) > 0) ++passes;
+    const int32_t nkeys_max = 1 << kOrderDigitBits;
+    const int64_t tj = std::max<int64_t>(4096, ((int64_t)n * nkeys_max + (1 << 24) - 1) >> 24);
+    const int64_t ntiles = (n + tj - 1) / tj;
+    const int64_t H = ntiles * nkeys_max;
+    struct Tmp {
+        void* p = nullptr;
+        hipStream_t s;
+        ~Tmp() { dfree_on(p, s); }
+    } digit{nullptr, s}, buf{nullptr, s}, hist{nullptr, s}, hscan{nullptr, s}, ws{nullptr, s};
+    GILA_TRY(dalloc_t(reinterpret_cast<int32_t**>(&digit.p), (size_t)n));
+    GILA_TRY(dalloc_t(reinterpret_cast<int32_t**>(&buf.p), (size_t)n));
+    GILA_TRY(dalloc_t(reinterpret_cast<int64_t**>(&hist.p), (size_t)H));
+    GILA_TRY(dalloc_t(reinterpret_cast<int64_t**>(&hscan.p), (size_t)H + 1));
+    GILA_TRY(dalloc_t(reinterpret_cast<int64_t**>(&ws.p), (size_t)scan_workspace_count(H)));
+    const unsigned grid = (unsigned)std::min<int64_t>(4096, ((int64_t)n + kBlock - 1) / kBlock);
+    // the last pass writes `out`; earlier ones alternate so that it does
+    const int32_t* src = nullptr;
+    for (int p = 0; p < passes; ++p) {
+        const int shift = p * kOrderDigitBits;
+        const int32_t nkeys = (int32_t)std::min<uint64_t>((uint64_t)nkeys_max, ((uint64_t)max_key >> shift) + 1);
+        int32_t* dst = ((passes - 1 - p) & 1) ? static_cast<int32_t*>(buf.p) : out;
+        hipLaunchKernelGGL(key_digit_kernel, dim3(grid), dim3(kBlock), 0, s, n, key, shift,
+                           static_cast<int32_t*>(digit.p));
+        const size_t lds = sizeof(int32_t) * (size_t)nkeys;
+        hipLaunchKernelGGL(slice_hist_kernel, dim3((unsigned)ntiles), dim3(kBlock), lds, s, (int64_t)n,
+                           tj, ntiles, nkeys, static_cast<const int32_t*>(digit.p), src,
+                           static_cast<int64_t*>(hist.p));
+        GILA_HIP(hipGetLastError());
+        GILA_TRY(enqueue_exclusive_scan_i64(static_cast<int64_t*>(hist.p), static_cast<int64_t*>(hscan.p),
+                                            ntiles * nkeys, static_cast<int64_t*>(ws.p), s));
+        hipLaunchKernelGGL(slice_scatter_kernel, dim3((unsigned)ntiles), dim3(64), lds, s, (int64_t)n, tj,
+                           ntiles, nkeys, static_cast<const int32_t*>(digit.p), src,
+                           static_cast<const int64_t*>(hscan.p), dst);
+        GILA_HIP(hipGetLastError());
+        src = dst;
+    }
+    return GILA_OK;
+}
+
 // Length key of each slice: slices with more quads get smaller keys (longest
 // first), clamped to kLenKeys buckets.
 constexpr int kLenKeys = 1024;

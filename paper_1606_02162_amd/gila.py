@@ -122,6 +122,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "gila_khop_export": (ctypes.c_int, [vp, vp, vp]),
         "gila_khop_export_rows": (ctypes.c_int, [vp, i64, vp, vp, vp]),
         "gila_khop_free": (None, [vp]),
+        "gila_khop_order": (ctypes.c_int, [vp, vp]),
         "gila_khop_set_mass": (ctypes.c_int, [vp, vp, vp]),
         "gila_prune": (ctypes.c_int, [P(Csr), vp, P(vp)]),
         "gila_pruned_info": (ctypes.c_int, [vp, P(i32), P(i64), P(i32), P(i32), P(i64)]),
@@ -361,6 +362,12 @@ class KHop:
         _check(_lib.gila_khop_export_rows(self._h, v.size, v.ctypes.data, ptr.ctypes.data,
                                           idx.ctypes.data), "gila_khop_export_rows")
         return ptr, idx[: int(ptr[-1])]
+
+    def order(self) -> np.ndarray:
+        """Caller id of each internal position (gila_khop_order)."""
+        out = np.zeros(max(self.info()["n"], 1), dtype=np.int32)
+        _check(_lib.gila_khop_order(self._h, out.ctypes.data), "gila_khop_order")
+        return out[: self.info()["n"]]
 
     def free(self):
         if self._h:

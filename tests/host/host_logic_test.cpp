@@ -260,42 +260,11 @@ static void test_schedules() {
 
 // The internal vertex order against a comparison sort of the same keys
 // (stable, so equal keys keep ascending ids).
-static void test_vertex_order() {
-    std::mt19937_64 rng(11);
-    for (int trial = 0; trial < 40; ++trial) {
-        const int32_t n = trial == 0 ? 0 : (int32_t)(rng() % 5000) + 1;
-        const int64_t cap = trial % 3 == 0 ? 3 : (trial % 3 == 1 ? 9000 : (1ll << 30));
-        std::vector<int64_t> counts((size_t)n), rp((size_t)n + 1, 0);
-        for (int32_t v = 0; v < n; ++v) {
-            const bool isolated = rng() % 7 == 0;
-            counts[v] = isolated ? 0 : (int64_t)(rng() % (uint64_t)cap);
-            rp[v + 1] = rp[v] + (isolated ? 0 : 1 + (int64_t)(rng() % 5));
-        }
-        for (int caller = 0; caller < 2; ++caller) {
-            const int64_t hub_min = 8192;
-            std::vector<int32_t> perm;
-            std::vector<uint64_t> w, tmp;
-            order_vertices(counts, rp, caller == 1, hub_min, perm, w, tmp);
-            std::vector<int32_t> ref((size_t)n);
-            for (int32_t v = 0; v < n; ++v) ref[v] = v;
-            auto key = [&](int32_t v) -> int64_t {
-                const bool iso = rp[v + 1] == rp[v];
-                if (caller) return iso ? 2 : (counts[v] >= hub_min ? 0 : 1);
-                return iso ? (int64_t)1 << 40 : -counts[v];
-            };
-            std::stable_sort(ref.begin(), ref.end(),
-                             [&](int32_t a, int32_t b) { return key(a) < key(b); });
-            CHECK(perm == ref, "vertex order, n = %d, caller order %d", n, caller);
-        }
-    }
-}
-
 int main() {
     test_admission();
     test_param_and_csr_checks();
     test_pairs_bound();
     test_schedules();
-    test_vertex_order();
     std::printf("OK %d\n", g_checks);
     return 0;
 }

@@ -91,6 +91,53 @@ def test_freed_handles_reuse_and_return_cached_memory(G):
     assert G.release_cached_memory() == 0
 
 
+def _expected_order(g, counts):
+    """The internal order rule written out with numpy sorts: the caller's
+    order (hub rows of >= 8192 entries first) when >= 70% of the adjacency
+    entries join ids less than 1024 apart, else |N_v(k)| descending; isolated
+    vertices last; ties by ascending caller id."""
+    deg = np.diff(g.row_ptr)
+    src = np.repeat(np.arange(g.n), deg)
+    near = int((np.abs(g.col_idx.astype(np.int64) - src) < 1024).sum())
+    caller = g.col_idx.size > 0 and near >= 0.7 * g.col_idx.size
+    iso = deg == 0
+    if caller:
+        key = np.where(iso, 2, np.where(counts >= 8192, 0, 1))
+    else:
+        key = np.where(iso, g.n, g.n - 1 - counts)
+    return np.lexsort((np.arange(g.n), key)).astype(np.int32), caller
+
+
+def test_internal_order_follows_the_rule(G):
+    """The device-built internal order equals the rule computed on the host
+    from the exported list lengths, for degree-ordered graphs (R-MAT with
+    isolated vertices, Barabasi-Albert), a caller-ordered mesh, and a ring
+    with a far-connected hub (caller order with a hub row first)."""
+    ring_n, hub_deg = 20000, 3500
+    rng = np.random.default_rng(5)
+    hub = ring_n // 2
+    others = np.delete(np.arange(ring_n), hub)
+    spokes = np.sort(rng.choice(others, hub_deg, replace=False))
+    u = np.concatenate([np.arange(ring_n), np.full(hub_deg, hub, np.int64)])
+    v = np.concatenate([(np.arange(ring_n) + 1) % ring_n, spokes])
+    ring_hub = inputs.to_csr(ring_n, u, v, name="ring_hub")
+    cases = [(inputs.rmat(14, 4, 0.57, 0.19, 0.19, seed=3), 2, False),
+             (inputs.barabasi_albert(5000, 3, seed=9), 3, False),
+             (inputs.grid_graph(60, 70), 2, True),
+             (ring_hub, 2, True)]
+    for g, k, want_caller in cases:
+        kh = _build(G, g, k)
+        ptr, _ = kh.export()
+        want, caller = _expected_order(g, np.diff(ptr))
+        assert caller == want_caller, g.name
+        assert np.array_equal(kh.order(), want), g.name
+        kh.free()
+    assert np.diff(inputs.rmat(14, 4, 0.57, 0.19, 0.19, seed=3).row_ptr).min() == 0
+    kh = _build(G, ring_hub, 2)
+    assert kh.order()[0] == hub  # the hub (|N(2)| >= 8192) leads
+    kh.free()
+
+
 def test_grid32_config_total(G):
     g = inputs.grid_graph(32, 32)
     kh = _build(G, g, 2)
