@@ -296,11 +296,17 @@ def bench_single(args, wl) -> int:
     overhead_ms = ev[0].elapsed_time(ev[1])
     loop_ms = ev[2].elapsed_time(ev[3])
     iter_ms = max(loop_ms - overhead_ms, 1e-9) / H
-    tb0 = time.perf_counter()
-    kh2 = gila.build_khop(rp, ci, k)
-    torch.cuda.synchronize()
-    build_ms = (time.perf_counter() - tb0) * 1e3
-    kh2.free()
+    # build time as in the timed steps, where each build follows the free of
+    # the previous handle and reuses its cached blocks: the first of three
+    # builds allocates afresh (the timing handle above still holds memory)
+    builds = []
+    for _ in range(3):
+        tb0 = time.perf_counter()
+        kh2 = gila.build_khop(rp, ci, k)
+        torch.cuda.synchronize()
+        builds.append((time.perf_counter() - tb0) * 1e3)
+        kh2.free()
+    build_ms = min(builds[1:])
 
     copy_gbs = stream_copy_gbps(stream)
     inter_per_iter = P + g.nnz
@@ -327,6 +333,7 @@ def bench_single(args, wl) -> int:
                    "n_active": n_active, "force_model": {"p": fp, "q": fq}},
         "ms_per_iter": iter_ms,
         "build_ms": build_ms,
+        "build_ms_fresh_memory": builds[0],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": (measured_traffic(TRAFFIC_FILE_BY_WORKLOAD[args.workload])
