@@ -249,7 +249,7 @@ int stable_order_by_key(int32_t n, const uint32_t* key, uint32_t max_key, int32_
     int passes = 1;
     while (passes * kOrderDigitBits < 32 && (max_key >> (passes * kOrderDigitBits)) > 0) ++passes;
     const int32_t nkeys_max = 1 << kOrderDigitBits;
-    const int64_t tj = std::max<int64_t>(4096, ((int64_t)n * nkeys_max + (1 << 24) - 1) >> 24);
+    const int64_t tj = std::max<int64_t>(1024, ((int64_t)n * nkeys_max + (1 << 24) - 1) >> 24);
     const int64_t ntiles = (n + tj - 1) / tj;
     const int64_t H = ntiles * nkeys_max;
     struct Tmp {
@@ -762,7 +762,7 @@ int build_segments(gila_khop* kh, int precision, hipStream_t st) {
     // row: two stable counting sorts (length, then segment).  Groups of
     // lanes in one wavefront then walk slices of about the same length.
     auto tiling = [&](int32_t nkeys, int64_t& tj, int64_t& ntiles) {
-        tj = std::max<int64_t>(4096, (T * (int64_t)nkeys + (1 << 24) - 1) >> 24);
+        tj = std::max<int64_t>(1024, (T * (int64_t)nkeys + (1 << 24) - 1) >> 24);
         ntiles = (T + tj - 1) / tj;
     };
     int64_t tj1, nt1, tj2, nt2;
