@@ -198,6 +198,11 @@ struct SegArgs {
     // null, or [2]: the device wall clock when the launch's first workgroup
     // started (atomic min) and its last one ended (atomic max)
     unsigned long long* span;
+    // dense slices (see segment.hip): null, or [T + 1] dense slices before
+    // each slice; their bitmaps, dense_blocks lane masks of 64 slots each
+    const int64_t* sl_dn;
+    const uint64_t* dmask;
+    int32_t dense_blocks;
 };
 
 // Arguments of the k-hop frontier-expansion kernel (khop.hip).
@@ -265,6 +270,10 @@ struct gila_khop {
     int32_t* sl_a = nullptr;        // [T + 1]
     uint16_t* sk_idx = nullptr;     // [sl_k[T] + tail pad]
     uint16_t* sa_idx = nullptr;     // [nnz + pad]
+    int64_t* sl_dn = nullptr;       // [T + 1] dense slices before each slice (null: none)
+    uint64_t* dmask = nullptr;      // [dense slices][dense_blocks] lane masks of 64 slots
+    int32_t dense_blocks = 0;
+    int64_t ndense = 0;
     int4* seg_wg = nullptr;         // [seg_grid]
     int32_t seg_grid = 0;
     int32_t comb_grid = 0;

@@ -287,52 +287,68 @@ int stable_order_by_key(int32_t n, const uint32_t* key, uint32_t max_key, int32_
     return GILA_OK;
 }
 
-// Length key of each slice: slices with more quads get smaller keys (longest
-// first), clamped to kLenKeys buckets.
+// Length key of each slice: dense slices (at least dmin k-hop ids; dmin <= 0:
+// none) key 0, the others by their quads, more quads smaller keys (longest
+// first), clamped to keys 1 .. kLenKeys - 1.  Within a segment the dense
+// slices therefore come first.
 constexpr int kLenKeys = 1024;
 __global__ __launch_bounds__(kBlock) void slice_lenkey_kernel(int64_t T, const int32_t* __restrict__ d_kn,
+                                                              int32_t dmin,
                                                               int32_t* __restrict__ lenkey) {
     const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (j >= T) return;
     const int32_t nq = (d_kn[j] + 3) >> 2;
-    lenkey[j] = kLenKeys - 1 - (nq < kLenKeys - 1 ? nq : kLenKeys - 1);
+    const bool dense = dmin > 0 && d_kn[j] >= dmin;
+    lenkey[j] = dense ? 0 : kLenKeys - 1 - (nq < kLenKeys - 2 ? nq : kLenKeys - 2);
 }
 
-// Padded k-hop and adjacency lengths of each segment-major slice.
+// Padded k-hop and adjacency lengths of each segment-major slice, and
+// whether it is dense (its k-hop ids then take no offsets, only a bitmap).
 __global__ __launch_bounds__(kBlock) void slice_lengths_kernel(int64_t T,
                                                                const int32_t* __restrict__ order,
                                                                const int32_t* __restrict__ d_kn,
                                                                const int32_t* __restrict__ d_an,
+                                                               int32_t dmin,
                                                                int64_t* __restrict__ wk,
-                                                               int64_t* __restrict__ wa) {
+                                                               int64_t* __restrict__ wa,
+                                                               int64_t* __restrict__ dn) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= T) return;
     const int32_t j = order[i];
-    wk[i] = (d_kn[j] + 3) & ~3;
+    const bool dense = dmin > 0 && d_kn[j] >= dmin;
+    wk[i] = dense ? 0 : (d_kn[j] + 3) & ~3;
     wa[i] = d_an[j];
+    dn[i] = dense ? 1 : 0;
 }
 
-// Cumulative work of the slices before i: entries plus a fixed cost per slice.
-__device__ __forceinline__ int64_t slice_work(const int64_t* sl_k, const int64_t* sl_a, int64_t i,
-                                              int64_t slice_cost) {
-    return sl_k[i] + sl_a[i] + slice_cost * i;
+// Cumulative work of the slices before i: entries plus a fixed cost per
+// slice; a dense slice evaluates every slot of its segment (dense_work).
+__device__ __forceinline__ int64_t slice_work(const int64_t* sl_k, const int64_t* sl_a,
+                                              const int64_t* sl_dn, int64_t i, int64_t slice_cost,
+                                              int64_t dense_work) {
+    return sl_k[i] + sl_a[i] + slice_cost * i + (sl_dn ? dense_work * sl_dn[i] : 0);
 }
 
 // For each segment s (and s = nseg): its first segment-major slice and the
 // cumulative work there; last entry: total padded k-hop length.
 __global__ __launch_bounds__(kBlock) void segment_starts_kernel(
-    int32_t nseg, int64_t T, int64_t ntiles, int64_t slice_cost, const int64_t* __restrict__ base,
-    const int64_t* __restrict__ sl_k, const int64_t* __restrict__ sl_a, int64_t* __restrict__ out) {
+    int32_t nseg, int64_t T, int64_t ntiles, int64_t slice_cost, int64_t dense_work,
+    const int64_t* __restrict__ base, const int64_t* __restrict__ sl_k,
+    const int64_t* __restrict__ sl_a, const int64_t* __restrict__ sl_dn, int64_t* __restrict__ out) {
     const int s = blockIdx.x * kBlock + threadIdx.x;
     if (s > nseg) return;
     const int64_t f = s < nseg ? base[(int64_t)s * ntiles] : T;
     out[2 * s] = f;
-    out[2 * s + 1] = slice_work(sl_k, sl_a, f, slice_cost);
-    if (s == nseg) out[2 * s + 2] = sl_k[T];
+    out[2 * s + 1] = slice_work(sl_k, sl_a, sl_dn, f, slice_cost, dense_work);
+    if (s == nseg) {
+        out[2 * s + 2] = sl_k[T];
+        out[2 * s + 3] = sl_dn ? sl_dn[T] : 0;
+    }
 }
 
 // kFillLanes lanes per segment-major slice: LDS byte offsets of its ids, the
-// k-hop part padded with the sentinel; the slice records.
+// k-hop part padded with the sentinel (a dense slice has none: see
+// dense_mask_kernel); the slice records.
 __global__ __launch_bounds__(kBlock) void slice_fill_kernel(
     SliceBuild b, int64_t T, const int32_t* __restrict__ order, const int64_t* __restrict__ sl_k,
     const int64_t* __restrict__ sl_a64, uint16_t* __restrict__ sk_idx, uint16_t* __restrict__ sa_idx,
@@ -363,6 +379,51 @@ __global__ __launch_bounds__(kBlock) void slice_fill_kernel(
     }
 }
 
+// The bitmap of each dense slice, one wavefront per slice: slot 64 b + l is
+// bit l of mask b.  The slice's ids are ascending, so each 64-id chunk spans
+// a few consecutive masks; each mask is the OR over the wavefront of its
+// lanes' bits, kept in a register while later chunks may still add to it and
+// written once (masks no id reaches stay zero).
+__global__ __launch_bounds__(kBlock) void dense_mask_kernel(SliceBuild b, int64_t T,
+                                                            const int32_t* __restrict__ order,
+                                                            const int64_t* __restrict__ sl_dn,
+                                                            int32_t dense_blocks,
+                                                            uint64_t* __restrict__ dmask) {
+    const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * kBlock) >> 6;
+    const int lane = lane64();
+    for (int64_t i = wave; i < T; i += nwaves) {
+        if (sl_dn[i + 1] == sl_dn[i]) continue;
+        const int32_t j = order[i];
+        const int32_t lo = b.d_seg[j] * b.S;
+        const int64_t k0 = b.d_k0[j];
+        const int32_t kn = b.d_kn[j];
+        uint64_t* m = dmask + sl_dn[i] * dense_blocks;
+        uint64_t cur = 0;
+        int32_t curw = -1;
+        for (int32_t c = 0; c < kn; c += 64) {
+            const int32_t t = c + lane;
+            const int32_t local = t < kn ? b.kidx[k0 + t] - lo : 0;
+            const int32_t w = t < kn ? local >> 6 : -1;
+            const uint64_t bit = t < kn ? 1ull << (local & 63) : 0ull;
+            const int32_t wlo = __builtin_amdgcn_readfirstlane(w);
+            const int32_t whi = __shfl(w, kn - c < 64 ? kn - c - 1 : 63, 64);
+            for (int32_t ww = wlo; ww <= whi; ++ww) {
+                uint64_t v = w == ww ? bit : 0ull;
+#pragma unroll
+                for (int off = 32; off >= 1; off >>= 1) v |= __shfl_xor(v, off, 64);
+                if (ww != curw) {
+                    if (curw >= 0 && lane == 0) m[curw] = cur;
+                    cur = 0;
+                    curw = ww;
+                }
+                cur |= v;
+            }
+        }
+        if (curw >= 0 && lane == 0) m[curw] = cur;
+    }
+}
+
 // Enough quads per lane (qpl) to amortise the per-slice reduction.
 __host__ __device__ __forceinline__ int lanes_for_length(int64_t len, int64_t qpl) {
     int l = 1;
@@ -375,8 +436,9 @@ __host__ __device__ __forceinline__ int lanes_for_length(int64_t len, int64_t qp
 // where the cumulative work crosses equal fractions; lanes per slice follow
 // the mean slice length of the range.
 __global__ __launch_bounds__(kBlock) void segment_plan_kernel(
-    int32_t nwg, int64_t slice_cost, int64_t qpl, const int64_t* __restrict__ starts,
-    const int64_t* __restrict__ sl_k, const int32_t* __restrict__ sl_a, int4* __restrict__ wg) {
+    int32_t nwg, int64_t slice_cost, int64_t qpl, int64_t dense_work,
+    const int64_t* __restrict__ starts, const int64_t* __restrict__ sl_k,
+    const int32_t* __restrict__ sl_a, const int64_t* __restrict__ sl_dn, int4* __restrict__ wg) {
     const int w = blockIdx.x * kBlock + threadIdx.x;
     if (w >= nwg) return;
     const int4 d = wg[w];
@@ -384,7 +446,9 @@ __global__ __launch_bounds__(kBlock) void segment_plan_kernel(
     const int64_t f0 = starts[2 * s], f1 = starts[2 * s + 2];
     const int64_t c0 = starts[2 * s + 1], c1 = starts[2 * s + 3];
     const int64_t W = c1 - c0;
-    auto work = [&](int64_t i) { return sl_k[i] + (int64_t)sl_a[i] + slice_cost * i; };
+    auto work = [&](int64_t i) {
+        return sl_k[i] + (int64_t)sl_a[i] + slice_cost * i + (sl_dn ? dense_work * sl_dn[i] : 0);
+    };
     auto cut = [&](int64_t target) {
         int64_t lo = f0, hi = f1;
         while (lo < hi) {
@@ -396,7 +460,9 @@ __global__ __launch_bounds__(kBlock) void segment_plan_kernel(
     };
     const int64_t ib = t == 0 ? f0 : cut(c0 + W * t / c);
     const int64_t ie = t == c - 1 ? f1 : cut(c0 + W * (t + 1) / c);
-    const int64_t len = ie > ib ? ((sl_k[ie] - sl_k[ib]) + (int64_t)(sl_a[ie] - sl_a[ib])) / (ie - ib) : 0;
+    // lanes per slice from the mean length of the range's offset-listed slices
+    const int64_t is = ib + (sl_dn ? sl_dn[ie] - sl_dn[ib] : 0);
+    const int64_t len = ie > is ? ((sl_k[ie] - sl_k[is]) + (int64_t)(sl_a[ie] - sl_a[is])) / (ie - is) : 0;
     wg[w] = make_int4(s, (int)ib, (int)ie, lanes_for_length(len, qpl));
 }
 
@@ -515,6 +581,84 @@ __device__ __forceinline__ void seg_slices(const SegArgs& a, int ib, int ie,
     }
 }
 
+// Repulsion from the four vertices staged at LDS byte offsets o0 .. o3.
+template <class P, int Q>
+__device__ __forceinline__ void offsets_terms(uint32_t o0, uint32_t o1, uint32_t o2, uint32_t o3,
+                                              const unsigned char* __restrict__ lds,
+                                              typename P::real xv, typename P::real yv,
+                                              typename P::real& sx, typename P::real& sy,
+                                              typename P::real& mindd, int q) {
+    using V = typename P::vec2;
+    const V p0 = *reinterpret_cast<const V*>(lds + o0);
+    const V p1 = *reinterpret_cast<const V*>(lds + o1);
+    const V p2 = *reinterpret_cast<const V*>(lds + o2);
+    const V p3 = *reinterpret_cast<const V*>(lds + o3);
+    repulse4<P, false, Q>(p0, p1, p2, p3, xv, yv, sx, sy, mindd, nullptr, q);
+}
+
+// A dense slice, by one whole wavefront: every slot of the segment's nblk
+// blocks of 64 is evaluated against the row's vertex, lane l taking slot
+// 64 b + l of block b.  Block b's mask (bit l: slot 64 b + l is in the slice)
+// is uniform, read by scalar loads, and becomes the lane condition of one
+// select per slot: the slot's LDS byte offset, or the sentinel, whose term
+// is exactly zero.  Eight blocks per step, one compensated add per eight
+// terms, as in the offset-listed slices.  Then the slice's adjacency terms
+// and the wavefront's sum.
+template <class P, int Q>
+__device__ __forceinline__ void dense_slice(const SegArgs& a, int i, int nblk,
+                                            const unsigned char* __restrict__ lds, int& coinc) {
+    using R = typename P::real;
+    using V = typename P::vec2;
+    const V* __restrict__ gpos = reinterpret_cast<const V*>(a.pos);
+    const int lane = lane64();
+    const V xv = gpos[a.sl_v[i]];
+    // the masks never change during the launch: read through the constant
+    // address space, so that the uniform loads are scalar
+    typedef const __attribute__((address_space(4))) uint64_t* MaskPtr;
+    const int32_t di = __builtin_amdgcn_readfirstlane((int32_t)a.sl_dn[i]);
+    const MaskPtr mk = (MaskPtr)(a.dmask + (int64_t)di * a.dense_blocks);
+    // (both select values below 64 KB, so that the LDS base folds into the reads)
+    const uint32_t sent = ((uint32_t)a.seg * (uint32_t)sizeof(V)) & 0xFFFFu;
+    constexpr uint32_t kStep = 64 * (uint32_t)sizeof(V);
+    Acc<R, P::kahan> acc;
+    R mindd = R(1);
+#pragma unroll 1
+    for (int b0 = 0; b0 < nblk; b0 += 8) {
+        // slot 64 b0 + lane; block b0 + t adds t * kStep (an immediate of the
+        // LDS read), so the sentinel's select value is sent - t * kStep
+        const uint32_t base = ((uint32_t)b0 * kStep + (uint32_t)lane * (uint32_t)sizeof(V)) & 0xFFFFu;
+        uint32_t o[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+            o[t] = (__builtin_amdgcn_inverse_ballot_w64(mk[b0 + t]) ? base : sent - t * kStep) +
+                   t * kStep;
+        R ax, ay, bx, by;
+        offsets_terms<P, Q>(o[0], o[1], o[2], o[3], lds, xv.x, xv.y, ax, ay, mindd, a.rep_q);
+        offsets_terms<P, Q>(o[4], o[5], o[6], o[7], lds, xv.x, xv.y, bx, by, mindd, a.rep_q);
+        acc.add(ax + bx, ay + by);
+    }
+    if (mindd <= coincidence_bias<R>()) {
+        int c = 0;
+#pragma unroll 1
+        for (int b = 0; b < nblk; ++b) {
+            if (__builtin_amdgcn_inverse_ballot_w64(mk[b])) {
+                const V p = *reinterpret_cast<const V*>(lds + (uint32_t)b * kStep +
+                                                        (uint32_t)lane * (uint32_t)sizeof(V));
+                c += (p.x == xv.x && p.y == xv.y) ? 1 : 0;
+            }
+        }
+        coinc += c;
+    }
+    const double d2 = a.d * a.d;
+    const R dpar = sizeof(R) == 4 ? (R)(1.0 / (a.d * d2)) : (R)(a.d * d2);
+    const int32_t ab = a.sl_a[i], ae = a.sl_a[i + 1];
+    for (int32_t j = ab + lane; j < ae; j += 64)
+        attract<P>(xv.x, xv.y, *reinterpret_cast<const V*>(lds + a.aidx[j]), dpar, acc, a.att_p);
+    const double fx = group_sum<64>(acc.x()) * d2;
+    const double fy = group_sum<64>(acc.y()) * d2;
+    if (lane == 0) a.part[a.sl_p[i]] = make_double2(fx, fy);
+}
+
 // FP32: eight waves per SIMD, as two 1024-thread workgroups per CU with a
 // 64 KB segment each (BIG) or four 512-thread ones with 32 KB.  Where rows
 // scatter, BIG halves the segments, so the slices per row, and doubles the
@@ -550,9 +694,13 @@ __global__ __launch_bounds__(seg_block<BIG>(), PREC == GILA_FP64 ? 4 : kSegWaves
         const R* gw = reinterpret_cast<const R*>(a.mass);
         for (int i = threadIdx.x; i < cnt; i += kSegBlock) lw[i] = gw[base + i];
     }
-    __shared__ int s_next;
+    // the range's dense slices are its head (the sort puts them first in
+    // each segment): [ib, id) by whole wavefronts, then [id, ie)
+    const int id = ib + (a.sl_dn ? (int)(a.sl_dn[ie] - a.sl_dn[ib]) : 0);
+    __shared__ int s_next, s_dnext;
     if (threadIdx.x == 0) {
-        s_next = ib;
+        s_next = id;
+        s_dnext = ib;
         V far;
         far.x = sizeof(far.x) == 4 ? (decltype(far.x))1e30f : (decltype(far.x))1e300;
         far.y = far.x;
@@ -561,15 +709,28 @@ __global__ __launch_bounds__(seg_block<BIG>(), PREC == GILA_FP64 ? 4 : kSegWaves
     }
     __syncthreads();
     int coinc = 0;
+    if constexpr (PREC != GILA_FP64 && !WEIGHTED) {
+        if (id > ib) {
+            const int nblk = (cnt + 63) >> 6;
+            const unsigned char* lds = reinterpret_cast<const unsigned char*>(lp);
+            for (;;) {
+                int i = 0;
+                if (lane64() == 0) i = atomicAdd(&s_dnext, 1);
+                i = __builtin_amdgcn_readfirstlane(i);
+                if (i >= id) break;
+                dense_slice<P, Q>(a, i, nblk, lds, coinc);
+            }
+        }
+    }
     const unsigned char* wb = reinterpret_cast<const unsigned char*>(lw);
     switch (lpv) {
-        case 1: seg_slices<P, 1, WEIGHTED, Q>(a, ib, ie, lp, wb, &s_next, coinc); break;
-        case 2: seg_slices<P, 2, WEIGHTED, Q>(a, ib, ie, lp, wb, &s_next, coinc); break;
-        case 4: seg_slices<P, 4, WEIGHTED, Q>(a, ib, ie, lp, wb, &s_next, coinc); break;
-        case 8: seg_slices<P, 8, WEIGHTED, Q>(a, ib, ie, lp, wb, &s_next, coinc); break;
-        case 16: seg_slices<P, 16, WEIGHTED, Q>(a, ib, ie, lp, wb, &s_next, coinc); break;
-        case 32: seg_slices<P, 32, WEIGHTED, Q>(a, ib, ie, lp, wb, &s_next, coinc); break;
-        default: seg_slices<P, 64, WEIGHTED, Q>(a, ib, ie, lp, wb, &s_next, coinc); break;
+        case 1: seg_slices<P, 1, WEIGHTED, Q>(a, id, ie, lp, wb, &s_next, coinc); break;
+        case 2: seg_slices<P, 2, WEIGHTED, Q>(a, id, ie, lp, wb, &s_next, coinc); break;
+        case 4: seg_slices<P, 4, WEIGHTED, Q>(a, id, ie, lp, wb, &s_next, coinc); break;
+        case 8: seg_slices<P, 8, WEIGHTED, Q>(a, id, ie, lp, wb, &s_next, coinc); break;
+        case 16: seg_slices<P, 16, WEIGHTED, Q>(a, id, ie, lp, wb, &s_next, coinc); break;
+        case 32: seg_slices<P, 32, WEIGHTED, Q>(a, id, ie, lp, wb, &s_next, coinc); break;
+        default: seg_slices<P, 64, WEIGHTED, Q>(a, id, ie, lp, wb, &s_next, coinc); break;
     }
     const int64_t wc = wave_sum((int64_t)coinc);
     if (lane64() == 0) s_c[wave_id()] = wc;
@@ -685,12 +846,18 @@ void free_segments(gila_khop* kh, Release rel) {
     rel(kh->sa_idx);
     rel(kh->seg_wg);
     rel(kh->part);
+    rel(kh->sl_dn);
+    rel(kh->dmask);
     kh->vsl = nullptr;
     kh->sl_v = kh->sl_p = kh->sl_a = nullptr;
     kh->sl_k = nullptr;
     kh->sk_idx = kh->sa_idx = nullptr;
     kh->seg_wg = nullptr;
     kh->part = nullptr;
+    kh->sl_dn = nullptr;
+    kh->dmask = nullptr;
+    kh->dense_blocks = 0;
+    kh->ndense = 0;
     kh->seg_ready = false;
     kh->nslices = 0;
 }
@@ -770,11 +937,23 @@ int build_segments(gila_khop* kh, int precision, hipStream_t st) {
     tiling(nseg, tj2, nt2);
     const int64_t H = std::max(nt1 * kLenKeys, nt2 * nseg);
     const size_t ws = (size_t)std::max(scan_workspace_count(H), scan_workspace_count(T));
+    // Dense slices (FP32 positions, unit weights): a k-hop slice with at least
+    // dmin ids (GILA_DENSE_MIN per mille of the segment; 0: none) is kept as
+    // a bitmap over the segment's slots, one 64-bit mask per block of 64
+    // (dblocks, a whole number of the kernel's eight-block steps).
+    const int32_t dblocks = ((S + 63) / 64 + 7) / 8 * 8;
+    const int dense_permille = env_int("GILA_DENSE_MIN", 750);
+    // (segments of at least 1024 slots: the kernel's select values stay
+    // non-negative)
+    const bool dense_ok = precision != GILA_FP64 && !weighted && dense_permille > 0 && S >= 1024;
+    const int32_t dmin =
+        dense_ok ? std::max<int32_t>(64, (int32_t)((int64_t)S * dense_permille / 1000)) : 0;
+    const int64_t dense_work = S;
     Arena ar(st);
     GILA_TRY(dalloc(&ar.base, Arena::size<int32_t>(T) * 5 + Arena::size<int64_t>(T) +  // d_*
                                   Arena::size<int64_t>(H) + Arena::size<int64_t>(H + 1) +  // hist, its scan
                                   Arena::size<int32_t>(T) * 3 +                            // lenkey, order1, order
-                                  Arena::size<int64_t>(T) * 2 + Arena::size<int64_t>(T + 1) +  // wk, wa, sl_a64
+                                  Arena::size<int64_t>(T) * 3 + Arena::size<int64_t>(T + 1) +  // wk, wa, dn, sl_a64
                                   Arena::size<int64_t>(ws) + Arena::size<int64_t>(2 * nseg + 4)));
     SliceBuild b{};
     b.na = na;
@@ -799,6 +978,7 @@ int build_segments(gila_khop* kh, int precision, hipStream_t st) {
     int32_t* order = ar.take<int32_t>(T);
     int64_t* wk = ar.take<int64_t>(T);
     int64_t* wa = ar.take<int64_t>(T);
+    int64_t* dn = ar.take<int64_t>(T);
     int64_t* sl_a64 = ar.take<int64_t>(T + 1);
     int64_t* sws = ar.take<int64_t>(ws);
     int64_t* starts = ar.take<int64_t>(2 * nseg + 4);
@@ -808,10 +988,11 @@ int build_segments(gila_khop* kh, int precision, hipStream_t st) {
     GILA_TRY(dalloc_t(&kh->sl_k, (size_t)T + 1));
     GILA_TRY(dalloc_t(&kh->sl_a, (size_t)T + 1));
     GILA_TRY(dalloc_t(&kh->part, (size_t)T));
+    if (dense_ok) GILA_TRY(dalloc_t(&kh->sl_dn, (size_t)T + 1));
 
     hipLaunchKernelGGL(slice_rows_kernel<true>, dim3(grid_rows), dim3(kBlock), 0, st, b);
     const unsigned tgrid = (unsigned)((T + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(slice_lenkey_kernel, dim3(tgrid), dim3(kBlock), 0, st, T, b.d_kn, lenkey);
+    hipLaunchKernelGGL(slice_lenkey_kernel, dim3(tgrid), dim3(kBlock), 0, st, T, b.d_kn, dmin, lenkey);
     GILA_HIP(hipGetLastError());
     auto counting_sort = [&](int32_t nkeys, int64_t tj, int64_t ntiles, const int32_t* key,
                              const int32_t* perm, int32_t* out) -> int {
@@ -835,20 +1016,25 @@ int build_segments(gila_khop* kh, int precision, hipStream_t st) {
     GILA_TRY(counting_sort(nseg, tj2, nt2, b.d_seg, order1, order));
     const int64_t ntiles = nt2;  // hscan now holds the segment sort's offsets
     hipLaunchKernelGGL(slice_lengths_kernel, dim3((unsigned)((T + kBlock - 1) / kBlock)),
-                       dim3(kBlock), 0, st, T, order, b.d_kn, b.d_an, wk, wa);
+                       dim3(kBlock), 0, st, T, order, b.d_kn, b.d_an, dmin, wk, wa, dn);
     GILA_HIP(hipGetLastError());
     GILA_TRY(enqueue_exclusive_scan_i64(wk, kh->sl_k, T, sws, st));
     GILA_TRY(enqueue_exclusive_scan_i64(wa, sl_a64, T, sws, st));
+    if (dense_ok) GILA_TRY(enqueue_exclusive_scan_i64(dn, kh->sl_dn, T, sws, st));
     const int64_t slice_cost = env_int("GILA_SEG_ROW_COST", 24);
     hipLaunchKernelGGL(segment_starts_kernel, dim3((nseg + 1 + kBlock - 1) / kBlock), dim3(kBlock), 0,
-                       st, nseg, T, ntiles, slice_cost, hscan, kh->sl_k, sl_a64, starts);
+                       st, nseg, T, ntiles, slice_cost, dense_work, hscan, kh->sl_k, sl_a64,
+                       kh->sl_dn, starts);
     GILA_HIP(hipGetLastError());
-    std::vector<int64_t> hs((size_t)2 * nseg + 3);
+    std::vector<int64_t> hs((size_t)2 * nseg + 4);
     GILA_HIP(hipMemcpyAsync(hs.data(), starts, sizeof(int64_t) * hs.size(), hipMemcpyDeviceToHost, st));
     GILA_HIP(hipStreamSynchronize(st));
     const int64_t kstore = hs[2 * nseg + 2];
-    if (hs[2 * nseg] != T || hs[0] != 0 || kstore < kh->P)
+    const int64_t ndense = hs[2 * nseg + 3];
+    if (hs[2 * nseg] != T || hs[0] != 0 || ndense < 0 || ndense > T ||
+        (ndense == 0 && kstore < kh->P))
         return fail(GILA_EDEVICE, "segment slices do not cover the lists");
+    if (pt.on) pt.log += " dense=" + std::to_string(ndense);
     pt.mark("sort");
 
     // --- workgroups: per segment, ranges of about equal work
@@ -880,6 +1066,13 @@ int build_segments(gila_khop* kh, int precision, hipStream_t st) {
     GILA_TRY(dalloc_t(&kh->sk_idx, (size_t)kstore + kSegTailPad));
     GILA_TRY(dalloc_t(&kh->sa_idx, (size_t)kh->nnz + 64));
     GILA_TRY(dalloc_t(&kh->seg_wg, plan.size()));
+    kh->ndense = ndense;
+    kh->dense_blocks = ndense > 0 ? dblocks : 0;
+    if (ndense > 0) {
+        const size_t masks = (size_t)ndense * dblocks;
+        GILA_TRY(dalloc_t(&kh->dmask, masks));
+        GILA_HIP(hipMemsetAsync(kh->dmask, 0, masks * sizeof(uint64_t), st));
+    }
     if (kh->comb_grid > kh->partials_cap) {
         dfree_on(kh->partials, st);
         kh->partials = nullptr;
@@ -893,9 +1086,15 @@ int build_segments(gila_khop* kh, int precision, hipStream_t st) {
         (int)std::min<int64_t>(65536, (T * kFillLanes + kBlock - 1) / kBlock);
     hipLaunchKernelGGL(slice_fill_kernel, dim3(fill_grid), dim3(kBlock), 0, st, b, T, order,
                        kh->sl_k, sl_a64, kh->sk_idx, kh->sa_idx, kh->sl_v, kh->sl_p, kh->sl_a);
+    if (ndense > 0) {
+        const int mgrid = (int)std::min<int64_t>(4096, (T * 64 + kBlock - 1) / kBlock);
+        hipLaunchKernelGGL(dense_mask_kernel, dim3(mgrid), dim3(kBlock), 0, st, b, T, order,
+                           kh->sl_dn, dblocks, kh->dmask);
+    }
     hipLaunchKernelGGL(segment_plan_kernel, dim3((unsigned)((plan.size() + kBlock - 1) / kBlock)),
                        dim3(kBlock), 0, st, (int32_t)plan.size(), slice_cost,
-                       (int64_t)env_int("GILA_SEG_QPL", 8), starts, kh->sl_k, kh->sl_a, kh->seg_wg);
+                       (int64_t)env_int("GILA_SEG_QPL", 8), dense_work, starts, kh->sl_k, kh->sl_a,
+                       kh->ndense > 0 ? kh->sl_dn : nullptr, kh->seg_wg);
     GILA_HIP(hipGetLastError());
     const size_t lds = seg_lds_bytes(kh, precision, S);
     if (lds > 48 * 1024) {
@@ -921,7 +1120,8 @@ int build_segments(gila_khop* kh, int precision, hipStream_t st) {
     kh->seg_weighted = weighted;
     kh->seg_ready = true;
     kh->device_bytes += (int64_t)(na + 1) * 8 + T * (4 + 4 + 8 + 4 + 16) + 2 * (kstore + kh->nnz) +
-                        (int64_t)sizeof(int4) * (int64_t)plan.size();
+                        (int64_t)sizeof(int4) * (int64_t)plan.size() +
+                        (dense_ok ? (T + 1) * 8 : 0) + ndense * dblocks * 8;
     return GILA_OK;
 }
 
@@ -969,6 +1169,9 @@ int launch_segment_step(const gila_khop* kh, int precision, const StepArgs& a, h
     g.att_p = a.att_p;
     g.rep_q = a.rep_q;
     g.span = span;
+    g.sl_dn = kh->ndense > 0 ? kh->sl_dn : nullptr;
+    g.dmask = kh->dmask;
+    g.dense_blocks = kh->dense_blocks;
     StepArgs c = a;
     c.vsl = kh->vsl;
     c.part = kh->part;

@@ -1,6 +1,6 @@
 """GPU parity of the k-hop lists N_v(k) (Section 4.5): bit-exact against the
-oracle's BFS, on small graphs of every family (every row) and at the full
-benchmark sizes (exact row lengths for every vertex, sampled rows in full)."""
+oracle's BFS, on small graphs of every family and at the full benchmark sizes
+(every row of R-MAT 18 and Barabasi-Albert 100k, compared in chunks)."""
 import ctypes
 
 import numpy as np

@@ -46,13 +46,15 @@ def _gpu_step(G, kh, params, h, pos_np):
 PATHS = {
     "segment": {},                                   # LDS segments of 64 KB
     "segment_tiny": {"GILA_SEG_BYTES": "2048"},      # 2 KB segments: many segments per graph
+    # every slice of 64 or more ids as a slot bitmap evaluated densely (FP32)
+    "segment_dense": {"GILA_DENSE_MIN": "1"},
     "direct": {"GILA_PATH": "direct"},               # direct global gathers
 }
 
 
 @pytest.fixture(params=list(PATHS))
 def path_env(request):
-    old = {k: os.environ.get(k) for k in ("GILA_PATH", "GILA_SEG_BYTES")}
+    old = {k: os.environ.get(k) for k in ("GILA_PATH", "GILA_SEG_BYTES", "GILA_DENSE_MIN")}
     for k in old:
         os.environ.pop(k, None)
     os.environ.update(PATHS[request.param])
@@ -201,3 +203,28 @@ def test_coincident_vertices(G):
     assert st.coincident == 2
     assert np.all(np.isfinite(F_g)) and np.all(np.isfinite(x_g))
     np.testing.assert_allclose(F_g[0], [-1.0, 0.0], rtol=1e-6)
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_dense_slice_coincident_and_forces(G, k, monkeypatch):
+    """Rows of 100 ids stored as slot bitmaps (GILA_DENSE_MIN=1 makes every
+    slice of 64 or more ids dense): forces and move match the oracle, and the
+    coincident pairs (three leaves placed on the hub) are counted exactly."""
+    monkeypatch.setenv("GILA_DENSE_MIN", "1")
+    g = inputs.star_graph(100)
+    rp, ci = _dev(G, g)
+    kh = G.build_khop(rp, ci, k)
+    x = inputs.uniform_positions(g.n, seed=4, width=300.0).astype(np.float32).astype(np.float64)
+    for leaf in (5, 17, 60):
+        x[leaf] = x[0]
+    params = G.LayoutParams(temperature=np.array([10.0]), ideal_length=20.0,
+                            precision=G.FP32_KAHAN)
+    x_g, F_g, D_g, st = _gpu_step(G, kh, params, 0, x)
+    optr, oidx = oracle_rows(g, k)
+    x_o, F_o, D_o, so = oracle.step(g.n, g.row_ptr, g.col_idx, optr, oidx, 20.0, 10.0, x)
+    assert so.coincident > 0 and st.coincident == so.coincident
+    S = oracle.force_magnitudes(g.n, g.row_ptr, g.col_idx, optr, oidx, 20.0, x)
+    assert rel_l2(F_g, F_o) <= 1e-5
+    assert per_vertex_force_err(F_g, F_o, S) <= 1e-5
+    assert pos_err(x_g, x_o) <= 1e-5
+    kh.free()
