@@ -29,13 +29,14 @@ def G():
     return gila
 
 
+# segment_dense: every slice of 64 or more ids as a slot bitmap (FP32, unit weights)
 PATHS = {"segment": {}, "segment_tiny": {"GILA_SEG_BYTES": "2048"},
-         "direct": {"GILA_PATH": "direct"}}
+         "segment_dense": {"GILA_DENSE_MIN": "1"}, "direct": {"GILA_PATH": "direct"}}
 
 
 @pytest.fixture(params=list(PATHS))
 def path_env(request):
-    old = {k: os.environ.get(k) for k in ("GILA_PATH", "GILA_SEG_BYTES")}
+    old = {k: os.environ.get(k) for k in ("GILA_PATH", "GILA_SEG_BYTES", "GILA_DENSE_MIN")}
     for k in old:
         os.environ.pop(k, None)
     os.environ.update(PATHS[request.param])
