@@ -581,19 +581,30 @@ __device__ __forceinline__ void seg_slices(const SegArgs& a, int ib, int ie,
     }
 }
 
-// Repulsion from the four vertices staged at LDS byte offsets o0 .. o3.
-template <class P, int Q>
+// Repulsion from the four vertices staged at LDS byte offsets o0 .. o3 (with
+// WEIGHTED, their weights at byte offsets o / 2 of lw, as in quad_terms).
+template <class P, bool WEIGHTED, int Q>
 __device__ __forceinline__ void offsets_terms(uint32_t o0, uint32_t o1, uint32_t o2, uint32_t o3,
                                               const unsigned char* __restrict__ lds,
+                                              const unsigned char* __restrict__ lw,
                                               typename P::real xv, typename P::real yv,
                                               typename P::real& sx, typename P::real& sy,
                                               typename P::real& mindd, int q) {
+    using R = typename P::real;
     using V = typename P::vec2;
     const V p0 = *reinterpret_cast<const V*>(lds + o0);
     const V p1 = *reinterpret_cast<const V*>(lds + o1);
     const V p2 = *reinterpret_cast<const V*>(lds + o2);
     const V p3 = *reinterpret_cast<const V*>(lds + o3);
-    repulse4<P, false, Q>(p0, p1, p2, p3, xv, yv, sx, sy, mindd, nullptr, q);
+    if constexpr (WEIGHTED) {
+        const R m[4] = {*reinterpret_cast<const R*>(lw + (o0 >> 1)),
+                        *reinterpret_cast<const R*>(lw + (o1 >> 1)),
+                        *reinterpret_cast<const R*>(lw + (o2 >> 1)),
+                        *reinterpret_cast<const R*>(lw + (o3 >> 1))};
+        repulse4<P, true, Q>(p0, p1, p2, p3, xv, yv, sx, sy, mindd, m, q);
+    } else {
+        repulse4<P, false, Q>(p0, p1, p2, p3, xv, yv, sx, sy, mindd, nullptr, q);
+    }
 }
 
 // A dense slice, by one whole wavefront: every slot of the segment's nblk
@@ -604,9 +615,10 @@ __device__ __forceinline__ void offsets_terms(uint32_t o0, uint32_t o1, uint32_t
 // is exactly zero.  Eight blocks per step, one compensated add per eight
 // terms, as in the offset-listed slices.  Then the slice's adjacency terms
 // and the wavefront's sum.
-template <class P, int Q>
+template <class P, bool WEIGHTED, int Q>
 __device__ __forceinline__ void dense_slice(const SegArgs& a, int i, int nblk,
-                                            const unsigned char* __restrict__ lds, int& coinc) {
+                                            const unsigned char* __restrict__ lds,
+                                            const unsigned char* __restrict__ lw, int& coinc) {
     using R = typename P::real;
     using V = typename P::vec2;
     const V* __restrict__ gpos = reinterpret_cast<const V*>(a.pos);
@@ -633,8 +645,10 @@ __device__ __forceinline__ void dense_slice(const SegArgs& a, int i, int nblk,
             o[t] = (__builtin_amdgcn_inverse_ballot_w64(mk[b0 + t]) ? base : sent - t * kStep) +
                    t * kStep;
         R ax, ay, bx, by;
-        offsets_terms<P, Q>(o[0], o[1], o[2], o[3], lds, xv.x, xv.y, ax, ay, mindd, a.rep_q);
-        offsets_terms<P, Q>(o[4], o[5], o[6], o[7], lds, xv.x, xv.y, bx, by, mindd, a.rep_q);
+        offsets_terms<P, WEIGHTED, Q>(o[0], o[1], o[2], o[3], lds, lw, xv.x, xv.y, ax, ay, mindd,
+                                      a.rep_q);
+        offsets_terms<P, WEIGHTED, Q>(o[4], o[5], o[6], o[7], lds, lw, xv.x, xv.y, bx, by, mindd,
+                                      a.rep_q);
         acc.add(ax + bx, ay + by);
     }
     if (mindd <= coincidence_bias<R>()) {
@@ -709,16 +723,17 @@ __global__ __launch_bounds__(seg_block<BIG>(), PREC == GILA_FP64 ? 4 : kSegWaves
     }
     __syncthreads();
     int coinc = 0;
-    if constexpr (PREC != GILA_FP64 && !WEIGHTED) {
+    if constexpr (PREC != GILA_FP64) {
         if (id > ib) {
             const int nblk = (cnt + 63) >> 6;
             const unsigned char* lds = reinterpret_cast<const unsigned char*>(lp);
+            const unsigned char* lwb = reinterpret_cast<const unsigned char*>(lw);
             for (;;) {
                 int i = 0;
                 if (lane64() == 0) i = atomicAdd(&s_dnext, 1);
                 i = __builtin_amdgcn_readfirstlane(i);
                 if (i >= id) break;
-                dense_slice<P, Q>(a, i, nblk, lds, coinc);
+                dense_slice<P, WEIGHTED, Q>(a, i, nblk, lds, lwb, coinc);
             }
         }
     }
@@ -937,7 +952,7 @@ int build_segments(gila_khop* kh, int precision, hipStream_t st) {
     tiling(nseg, tj2, nt2);
     const int64_t H = std::max(nt1 * kLenKeys, nt2 * nseg);
     const size_t ws = (size_t)std::max(scan_workspace_count(H), scan_workspace_count(T));
-    // Dense slices (FP32 positions, unit weights): a k-hop slice with at least
+    // Dense slices (FP32 positions): a k-hop slice with at least
     // dmin ids (GILA_DENSE_MIN per mille of the segment; 0: none) is kept as
     // a bitmap over the segment's slots, one 64-bit mask per block of 64
     // (dblocks, a whole number of the kernel's eight-block steps).
@@ -945,7 +960,7 @@ int build_segments(gila_khop* kh, int precision, hipStream_t st) {
     const int dense_permille = env_int("GILA_DENSE_MIN", 750);
     // (segments of at least 1024 slots: the kernel's select values stay
     // non-negative)
-    const bool dense_ok = precision != GILA_FP64 && !weighted && dense_permille > 0 && S >= 1024;
+    const bool dense_ok = precision != GILA_FP64 && dense_permille > 0 && S >= 1024;
     const int32_t dmin =
         dense_ok ? std::max<int32_t>(64, (int32_t)((int64_t)S * dense_permille / 1000)) : 0;
     const int64_t dense_work = S;

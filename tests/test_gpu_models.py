@@ -29,7 +29,7 @@ def G():
     return gila
 
 
-# segment_dense: every slice of 64 or more ids as a slot bitmap (FP32, unit weights)
+# segment_dense: every slice of 64 or more ids as a slot bitmap (FP32 precisions)
 PATHS = {"segment": {}, "segment_tiny": {"GILA_SEG_BYTES": "2048"},
          "segment_dense": {"GILA_DENSE_MIN": "1"}, "direct": {"GILA_PATH": "direct"}}
 
