@@ -581,26 +581,27 @@ __device__ __forceinline__ void seg_slices(const SegArgs& a, int ib, int ie,
     }
 }
 
-// Repulsion from the four vertices staged at LDS byte offsets o0 .. o3 (with
-// WEIGHTED, their weights at byte offsets o / 2 of lw, as in quad_terms).
+// Repulsion from the four vertices staged at LDS addresses ps[0 .. 3] (with
+// WEIGHTED, each weight at half its position's byte offset in lw, as in
+// quad_terms).
 template <class P, bool WEIGHTED, int Q>
-__device__ __forceinline__ void offsets_terms(uint32_t o0, uint32_t o1, uint32_t o2, uint32_t o3,
-                                              const unsigned char* __restrict__ lds,
-                                              const unsigned char* __restrict__ lw,
-                                              typename P::real xv, typename P::real yv,
-                                              typename P::real& sx, typename P::real& sy,
-                                              typename P::real& mindd, int q) {
+__device__ __forceinline__ void slot_terms(const unsigned char* const* ps,
+                                           const unsigned char* __restrict__ lds,
+                                           const unsigned char* __restrict__ lw,
+                                           typename P::real xv, typename P::real yv,
+                                           typename P::real& sx, typename P::real& sy,
+                                           typename P::real& mindd, int q) {
     using R = typename P::real;
     using V = typename P::vec2;
-    const V p0 = *reinterpret_cast<const V*>(lds + o0);
-    const V p1 = *reinterpret_cast<const V*>(lds + o1);
-    const V p2 = *reinterpret_cast<const V*>(lds + o2);
-    const V p3 = *reinterpret_cast<const V*>(lds + o3);
+    const V p0 = *reinterpret_cast<const V*>(ps[0]);
+    const V p1 = *reinterpret_cast<const V*>(ps[1]);
+    const V p2 = *reinterpret_cast<const V*>(ps[2]);
+    const V p3 = *reinterpret_cast<const V*>(ps[3]);
     if constexpr (WEIGHTED) {
-        const R m[4] = {*reinterpret_cast<const R*>(lw + (o0 >> 1)),
-                        *reinterpret_cast<const R*>(lw + (o1 >> 1)),
-                        *reinterpret_cast<const R*>(lw + (o2 >> 1)),
-                        *reinterpret_cast<const R*>(lw + (o3 >> 1))};
+        const R m[4] = {*reinterpret_cast<const R*>(lw + ((ps[0] - lds) >> 1)),
+                        *reinterpret_cast<const R*>(lw + ((ps[1] - lds) >> 1)),
+                        *reinterpret_cast<const R*>(lw + ((ps[2] - lds) >> 1)),
+                        *reinterpret_cast<const R*>(lw + ((ps[3] - lds) >> 1))};
         repulse4<P, true, Q>(p0, p1, p2, p3, xv, yv, sx, sy, mindd, m, q);
     } else {
         repulse4<P, false, Q>(p0, p1, p2, p3, xv, yv, sx, sy, mindd, nullptr, q);
@@ -629,26 +630,20 @@ __device__ __forceinline__ void dense_slice(const SegArgs& a, int i, int nblk,
     typedef const __attribute__((address_space(4))) uint64_t* MaskPtr;
     const int32_t di = __builtin_amdgcn_readfirstlane((int32_t)a.sl_dn[i]);
     const MaskPtr mk = (MaskPtr)(a.dmask + (int64_t)di * a.dense_blocks);
-    // (both select values below 64 KB, so that the LDS base folds into the reads)
-    const uint32_t sent = ((uint32_t)a.seg * (uint32_t)sizeof(V)) & 0xFFFFu;
+    const unsigned char* lsent = lds + (uint32_t)a.seg * (uint32_t)sizeof(V);
     constexpr uint32_t kStep = 64 * (uint32_t)sizeof(V);
     Acc<R, P::kahan> acc;
     R mindd = R(1);
 #pragma unroll 1
     for (int b0 = 0; b0 < nblk; b0 += 8) {
-        // slot 64 b0 + lane; block b0 + t adds t * kStep (an immediate of the
-        // LDS read), so the sentinel's select value is sent - t * kStep
-        const uint32_t base = ((uint32_t)b0 * kStep + (uint32_t)lane * (uint32_t)sizeof(V)) & 0xFFFFu;
-        uint32_t o[8];
+        const unsigned char* base = lds + (uint32_t)b0 * kStep + (uint32_t)lane * (uint32_t)sizeof(V);
+        const unsigned char* ps[8];  // slots 64 (b0 + t) + lane, or the sentinel
 #pragma unroll
         for (int t = 0; t < 8; ++t)
-            o[t] = (__builtin_amdgcn_inverse_ballot_w64(mk[b0 + t]) ? base : sent - t * kStep) +
-                   t * kStep;
+            ps[t] = __builtin_amdgcn_inverse_ballot_w64(mk[b0 + t]) ? base + t * kStep : lsent;
         R ax, ay, bx, by;
-        offsets_terms<P, WEIGHTED, Q>(o[0], o[1], o[2], o[3], lds, lw, xv.x, xv.y, ax, ay, mindd,
-                                      a.rep_q);
-        offsets_terms<P, WEIGHTED, Q>(o[4], o[5], o[6], o[7], lds, lw, xv.x, xv.y, bx, by, mindd,
-                                      a.rep_q);
+        slot_terms<P, WEIGHTED, Q>(ps, lds, lw, xv.x, xv.y, ax, ay, mindd, a.rep_q);
+        slot_terms<P, WEIGHTED, Q>(ps + 4, lds, lw, xv.x, xv.y, bx, by, mindd, a.rep_q);
         acc.add(ax + bx, ay + by);
     }
     if (mindd <= coincidence_bias<R>()) {
@@ -958,9 +953,7 @@ int build_segments(gila_khop* kh, int precision, hipStream_t st) {
     // (dblocks, a whole number of the kernel's eight-block steps).
     const int32_t dblocks = ((S + 63) / 64 + 7) / 8 * 8;
     const int dense_permille = env_int("GILA_DENSE_MIN", 750);
-    // (segments of at least 1024 slots: the kernel's select values stay
-    // non-negative)
-    const bool dense_ok = precision != GILA_FP64 && dense_permille > 0 && S >= 1024;
+    const bool dense_ok = precision != GILA_FP64 && dense_permille > 0;
     const int32_t dmin =
         dense_ok ? std::max<int32_t>(64, (int32_t)((int64_t)S * dense_permille / 1000)) : 0;
     const int64_t dense_work = S;
