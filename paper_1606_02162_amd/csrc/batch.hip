@@ -196,8 +196,9 @@ __global__ void gather_bounds_kernel(const int64_t* __restrict__ kptr,
 // (visited, this level, next level), deduplicating with LDS atomic ORs.  The
 // count pass writes |N_v(k)|; the fill pass writes the row ascending by
 // scanning the visited bitmap.  Used when every graph of the batch fits.
-constexpr int kBfsBlock = 512;
-constexpr int kBfsWaves = kBfsBlock / 64;
+// Workgroups of 1024 threads (16 wavefronts share one graph, so that the
+// largest graphs, taken first, do not leave a long tail) when the per-wave
+// bitmaps fit beside the graph in LDS, else 512.
 
 struct BatchBfsArgs {
     int32_t count;
@@ -216,10 +217,10 @@ struct BatchBfsArgs {
     int64_t nnzmax;          // ... and adjacency entries
 };
 
-size_t batch_bfs_lds_bytes(int32_t nmax, int64_t nnzmax) {
+size_t batch_bfs_lds_bytes(int32_t nmax, int64_t nnzmax, int waves) {
     const size_t nwords = (size_t)(nmax + 31) / 32;
     return 4 * ((size_t)nmax + 1) + 2 * (((size_t)nnzmax + 1) & ~(size_t)1) +
-           4 * nwords * 3 * kBfsWaves;
+           4 * nwords * 3 * (size_t)waves;
 }
 
 // One pass per source: after its BFS the wavefront knows |N_v(k)|, takes the
@@ -228,7 +229,10 @@ size_t batch_bfs_lds_bytes(int32_t nmax, int64_t nnzmax) {
 // (walk_bound_kernel), so it never overflows -- and writes the row ascending
 // from the visited bitmap, then the padding.  Where a row lands in the block
 // depends on which wavefront finishes first; what it holds does not.
-__global__ __launch_bounds__(kBfsBlock) void batch_khop_kernel(BatchBfsArgs a) {
+template <int BS>
+__global__ __launch_bounds__(BS) void batch_khop_kernel(BatchBfsArgs a) {
+    constexpr int kBfsBlock = BS;
+    constexpr int kBfsWaves = BS / 64;
     extern __shared__ __align__(16) unsigned char s_raw[];
     __shared__ int s_g;
     __shared__ unsigned long long s_cursor;
@@ -331,15 +335,20 @@ __global__ __launch_bounds__(kBfsBlock) void batch_khop_kernel(BatchBfsArgs a) {
     }
 }
 
-static int run_batch_bfs(const BatchBfsArgs& a, size_t lds, int device, hipStream_t s) {
+static int run_batch_bfs(const BatchBfsArgs& a, size_t lds, int bs, int device, hipStream_t s) {
+    const void* kernel = bs == 1024 ? (const void*)batch_khop_kernel<1024>
+                                    : (const void*)batch_khop_kernel<512>;
     if (lds > 48 * 1024)
-        (void)hipFuncSetAttribute((const void*)batch_khop_kernel,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        (void)hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     const DeviceInfo& di = device_info(device);
-    const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(4, (160u * 1024u) / (lds + 1024)));
+    const int per_cu =
+        (int)std::max<size_t>(1, std::min<size_t>(2048 / bs, (160u * 1024u) / (lds + 1024)));
     const int grid = std::min(a.count, di.cus * per_cu);
     GILA_HIP(hipMemsetAsync(a.work, 0, sizeof(int32_t), s));
-    hipLaunchKernelGGL(batch_khop_kernel, dim3(grid), dim3(kBfsBlock), lds, s, a);
+    if (bs == 1024)
+        hipLaunchKernelGGL(batch_khop_kernel<1024>, dim3(grid), dim3(1024), lds, s, a);
+    else
+        hipLaunchKernelGGL(batch_khop_kernel<512>, dim3(grid), dim3(512), lds, s, a);
     GILA_HIP(hipGetLastError());
     return GILA_OK;
 }
@@ -1281,8 +1290,10 @@ int batch_build(const gila_csr* graphs, int32_t count, const int32_t* k, hipStre
     // count then fill
     int64_t nnzmax = 0;
     for (int32_t i = 0; i < count; ++i) nnzmax = std::max(nnzmax, b->ebase[i + 1] - b->ebase[i]);
-    const size_t bfs_lds = batch_bfs_lds_bytes(b->nmax, nnzmax);
-    const bool per_graph = bfs_lds + 1024 <= device_info(dev).max_lds_per_block &&
+    const size_t max_lds = device_info(dev).max_lds_per_block;
+    const int bfs_bs = batch_bfs_lds_bytes(b->nmax, nnzmax, 16) + 1024 <= max_lds ? 1024 : 512;
+    const size_t bfs_lds = batch_bfs_lds_bytes(b->nmax, nnzmax, bfs_bs / 64);
+    const bool per_graph = bfs_lds + 1024 <= max_lds &&
                            !(getenv("GILA_BATCH_BFS") && std::strcmp(getenv("GILA_BATCH_BFS"), "source") == 0);
     const int vg = (int)std::min<int64_t>(4096, (std::max<int64_t>(b->nv, 1) + kBlock - 1) / kBlock);
     if (per_graph) {
@@ -1342,7 +1353,7 @@ int batch_build(const gila_csr* graphs, int32_t count, const int32_t* k, hipStre
         ga.work = d_flag.p + 1;
         ga.nmax = b->nmax;
         ga.nnzmax = nnzmax;
-        GILA_TRY(run_batch_bfs(ga, bfs_lds, dev, s));
+        GILA_TRY(run_batch_bfs(ga, bfs_lds, bfs_bs, dev, s));
         GILA_HIP(hipStreamSynchronize(s));
     } else if (b->nv > 0) {
         BfsArgs a{};
