@@ -581,6 +581,24 @@ __device__ __forceinline__ typename P::vec2 batch_move(const BatchDesc& G, typen
     return nx;
 }
 
+// The attraction term of the batched launch: attract() with p = 2, the FP32
+// distance taken by the hardware square root (within 1 ulp).  The correctly
+// rounded square root costs ~17 more instructions per edge, about a fifth of
+// a vertex's work in these graphs of short rows; in FP64 attract() itself.
+template <class P>
+__device__ __forceinline__ void batch_attract(typename P::real xv, typename P::real yv,
+                                              typename P::vec2 p, typename P::real dparam,
+                                              Acc<typename P::real, P::kahan>& acc) {
+    if constexpr (sizeof(typename P::real) == 4) {
+        const float dx = p.x - xv;
+        const float dy = p.y - yv;
+        const float s = __builtin_amdgcn_sqrtf(dx * dx + dy * dy) * dparam;
+        acc.add(dx * s, dy * s);
+    } else {
+        attract<P>(xv, yv, p, dparam, acc);
+    }
+}
+
 template <class P, int LPV>
 __device__ __forceinline__ void batch_graph_iteration(
     const BatchArgs& a, const BatchDesc& G, const typename P::vec2* __restrict__ cur,
@@ -651,7 +669,7 @@ __device__ __forceinline__ void batch_graph_iteration(
                 }
             }
             const int64_t ab = a.rp[G.vbase + v], ae = a.rp[G.vbase + v + 1];
-            for (int64_t j = ab + gl; j < ae; j += LPV) attract<P>(xv.x, xv.y, cur[a.ci[j]], dpar, acc);
+            for (int64_t j = ab + gl; j < ae; j += LPV) batch_attract<P>(xv.x, xv.y, cur[a.ci[j]], dpar, acc);
         }
         const double fx = group_sum<LPV>(acc.x()) * d2;
         const double fy = group_sum<LPV>(acc.y()) * d2;
@@ -730,10 +748,23 @@ __device__ __forceinline__ void batch_graph_iteration_slices(
                 coinc += (row[e] != G.n && p.x == xv.x && p.y == xv.y) ? 1 : 0;
             }
         }
+        // the slice's adjacency, up to four entries at a time: every id is
+        // loaded before the first term (padding holds the sentinel id n, a
+        // valid slot; the empty asm keeps the loads from being moved into
+        // the per-lane branches), so the loads wait once; terms in edge order
         const uint16_t* __restrict__ aq = a.sa + S.aoff + lane;
-        for (int e = 0; e < S.na; ++e) {
-            const int u = aq[(int64_t)e * 64];
-            if (e < deg) attract<P>(xv.x, xv.y, cur[u], dpar, acc);
+        for (int e = 0; e < S.na; e += 4) {
+            const int r = S.na - e;  // uniform
+            const int u0 = aq[(int64_t)e * 64];
+            const int u1 = r > 1 ? (int)aq[(int64_t)(e + 1) * 64] : G.n;
+            const int u2 = r > 2 ? (int)aq[(int64_t)(e + 2) * 64] : G.n;
+            const int u3 = r > 3 ? (int)aq[(int64_t)(e + 3) * 64] : G.n;
+            const V p0 = cur[u0], p1 = cur[u1], p2 = cur[u2], p3 = cur[u3];
+            asm volatile("" ::"v"(p0.x), "v"(p1.x), "v"(p2.x), "v"(p3.x));
+            if (e < deg) batch_attract<P>(xv.x, xv.y, p0, dpar, acc);
+            if (e + 1 < deg) batch_attract<P>(xv.x, xv.y, p1, dpar, acc);
+            if (e + 2 < deg) batch_attract<P>(xv.x, xv.y, p2, dpar, acc);
+            if (e + 3 < deg) batch_attract<P>(xv.x, xv.y, p3, dpar, acc);
         }
         double energy = 0.0;
         if (live) {

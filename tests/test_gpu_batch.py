@@ -68,6 +68,30 @@ def test_batch_khop_lists_bit_exact(G, bfs, monkeypatch):
     b.free()
 
 
+def test_batch_khop_half_size_workgroups_bit_exact(G):
+    """A batch whose largest graph leaves no room in LDS for the bitmaps of 16
+    wavefronts beside its CSR (11,000 vertices, ~33,000 adjacency entries:
+    ~176 KB) runs the one-pass build in 512-thread workgroups (~143 KB); its
+    lists, and those of the small graphs beside it, equal the oracle's."""
+    gs = [(inputs.random_tree_plus_edges(11000, 5500, seed=81), 2),
+          (inputs.barabasi_albert(400, 2, seed=82), 3),
+          (inputs.random_tree_plus_edges(60, 30, seed=83), 4)]
+    nmax = max(g.n for g, _ in gs)
+    nnzmax = max(int(g.row_ptr[-1]) for g, _ in gs)
+
+    def bfs_lds(waves):  # the build's LDS budget of the one-pass BFS
+        return 4 * (nmax + 1) + 2 * ((nnzmax + 1) & ~1) + 4 * ((nmax + 31) // 32) * 3 * waves
+
+    assert bfs_lds(16) + 1024 > 160 * 1024 >= bfs_lds(8) + 1024
+    b = G.Batch([G.to_device_csr(g) for g, _ in gs], [k for _, k in gs])
+    for i, (g, k) in enumerate(gs):
+        ptr, idx = b.export(i, g.n)
+        optr, oidx = oracle_rows(g, k)
+        assert np.array_equal(ptr, optr), (i, g.name, k)
+        assert np.array_equal(idx, oidx), (i, g.name, k)
+    b.free()
+
+
 def test_concatenated_marshalling_same_bits(G):
     """Batch.concatenated + BatchParams + (positions, offsets) give the same
     bits as the per-graph list form."""
