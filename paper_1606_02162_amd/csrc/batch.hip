@@ -710,9 +710,24 @@ __device__ __forceinline__ void batch_graph_iteration_slices(
         R mindd = R(1);
         const uint2* __restrict__ q = a.sk + S.koff + lane;
         int j = 0;
+        // groups of four quad steps, the next group's loads issued before
+        // this group's terms (rows stream from HBM: a wait per group would
+        // leave each slice waiting on its row length over four latencies)
+        uint2 n0 = make_uint2(0, 0), n1 = n0, n2 = n0, n3 = n0;
+        if (S.nq >= 4) {
+            n0 = q[0];
+            n1 = q[64];
+            n2 = q[128];
+            n3 = q[192];
+        }
         for (; j + 3 < S.nq; j += 4) {
-            const uint2 w0 = q[(int64_t)j * 64], w1 = q[(int64_t)(j + 1) * 64],
-                        w2 = q[(int64_t)(j + 2) * 64], w3 = q[(int64_t)(j + 3) * 64];
+            const uint2 w0 = n0, w1 = n1, w2 = n2, w3 = n3;
+            if (j + 7 < S.nq) {  // uniform
+                n0 = q[(int64_t)(j + 4) * 64];
+                n1 = q[(int64_t)(j + 5) * 64];
+                n2 = q[(int64_t)(j + 6) * 64];
+                n3 = q[(int64_t)(j + 7) * 64];
+            }
             R ax, ay, bx, by;
             repulse4<P>(cur[w0.x & 0xFFFFu], cur[w0.x >> 16], cur[w0.y & 0xFFFFu],
                         cur[w0.y >> 16], xv.x, xv.y, ax, ay, mindd);
