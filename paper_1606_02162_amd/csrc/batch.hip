@@ -339,7 +339,7 @@ static int run_batch_bfs(const BatchBfsArgs& a, size_t lds, int bs, int device, 
     const void* kernel = bs == 1024 ? (const void*)batch_khop_kernel<1024>
                                     : (const void*)batch_khop_kernel<512>;
     if (lds > 48 * 1024)
-        (void)hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        (void)quiet(hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     const DeviceInfo& di = device_info(device);
     const int per_cu =
         (int)std::max<size_t>(1, std::min<size_t>(2048 / bs, (160u * 1024u) / (lds + 1024)));
@@ -501,15 +501,15 @@ __global__ __launch_bounds__(kBlock) void sell_dims_kernel(
     smeta[sl * 64 + lane] = make_uint2((uint32_t)v, (uint32_t)nq | ((uint32_t)deg << 16));
     if (lane == 0) {
         szk[sl] = (int64_t)Q * 64;
-        sza[sl] = (int64_t)D * 64;
+        sza[sl] = (int64_t)((D + 3) & ~3) * 64;
         hdr[sl].nq = Q;
         hdr[sl].na = D;
     }
 }
 
 // One wavefront per slice: the interleaved rows (sentinel quads past a row's
-// end) and adjacency (sentinel ids past a vertex's degree), and the slice's
-// offsets.
+// end) and adjacency (sentinel ids past a vertex's degree, up to a multiple
+// of four), and the slice's offsets.
 __global__ __launch_bounds__(kBlock) void sell_fill_kernel(
     int64_t nslices, const int32_t* __restrict__ sgraph, const int64_t* __restrict__ vbase,
     const int64_t* __restrict__ kstart, const uint16_t* __restrict__ kidx,
@@ -533,7 +533,10 @@ __global__ __launch_bounds__(kBlock) void sell_fill_kernel(
     const uint2 sent = make_uint2(n | (n << 16), n | (n << 16));
     for (int j = 0; j < Q; ++j) sk[ko + (int64_t)j * 64 + lane] = j < nq ? row[j] : sent;
     const uint16_t* arow = ci16 + rp[vb + v];
-    for (int j = 0; j < D; ++j) sa[ao + (int64_t)j * 64 + lane] = j < deg ? arow[j] : (uint16_t)n;
+    // adjacency in groups of four entries per lane (8 contiguous bytes, one
+    // load), group g of lane l at entries 256 g + 4 l
+    for (int j = 0; j < ((D + 3) & ~3); ++j)
+        sa[ao + (int64_t)(j >> 2) * 256 + lane * 4 + (j & 3)] = j < deg ? arow[j] : (uint16_t)n;
     if (lane == 0) {
         hdr[sl].koff = ko;
         hdr[sl].aoff = ao;
@@ -701,8 +704,21 @@ __device__ __forceinline__ void batch_graph_iteration_slices(
         sl = __builtin_amdgcn_readfirstlane(sl);
         if (sl >= ns) break;
         const int64_t si = G.sbase + sl;
-        const SellSlice S = a.sell[si];
+        // the slice's header through the scalar cache (built by an earlier
+        // launch, only read here)
+        typedef const __attribute__((address_space(4))) SellSlice* SellPtr;
+        const SellPtr hp = (SellPtr)(a.sell + si);
+        SellSlice S;
+        S.koff = hp->koff;
+        S.aoff = hp->aoff;
+        S.nq = hp->nq;
+        S.na = hp->na;
         const uint2 m = a.smeta[si * 64 + lane];
+        // the first four adjacency entries, loaded now so that they arrive
+        // during the row's terms
+        const uint2* __restrict__ aq = reinterpret_cast<const uint2*>(a.sa + S.aoff) + lane;
+        uint2 ag = make_uint2(0, 0);
+        if (S.na > 0) ag = aq[0];
         const int v = (int)m.x;  // n (the far sentinel) past the graph's end
         const int nq = (int)(m.y & 0xFFFFu), deg = (int)(m.y >> 16);
         const V xv = cur[v];
@@ -763,17 +779,16 @@ __device__ __forceinline__ void batch_graph_iteration_slices(
                 coinc += (row[e] != G.n && p.x == xv.x && p.y == xv.y) ? 1 : 0;
             }
         }
-        // the slice's adjacency, up to four entries at a time: every id is
-        // loaded before the first term (padding holds the sentinel id n, a
-        // valid slot; the empty asm keeps the loads from being moved into
-        // the per-lane branches), so the loads wait once; terms in edge order
-        const uint16_t* __restrict__ aq = a.sa + S.aoff + lane;
+        // the slice's adjacency, four entries (one load) at a time, the next
+        // group loaded before this one's terms; padding holds the sentinel id
+        // n, a valid slot.  All four positions are read before the first
+        // term (the empty asm keeps the reads from being moved into the
+        // per-lane branches); terms in edge order.
         for (int e = 0; e < S.na; e += 4) {
-            const int r = S.na - e;  // uniform
-            const int u0 = aq[(int64_t)e * 64];
-            const int u1 = r > 1 ? (int)aq[(int64_t)(e + 1) * 64] : G.n;
-            const int u2 = r > 2 ? (int)aq[(int64_t)(e + 2) * 64] : G.n;
-            const int u3 = r > 3 ? (int)aq[(int64_t)(e + 3) * 64] : G.n;
+            const uint2 g = ag;
+            if (e + 4 < S.na) ag = aq[(int64_t)((e >> 2) + 1) * 64];  // uniform
+            const int u0 = (int)(g.x & 0xFFFFu), u1 = (int)(g.x >> 16);
+            const int u2 = (int)(g.y & 0xFFFFu), u3 = (int)(g.y >> 16);
             const V p0 = cur[u0], p1 = cur[u1], p2 = cur[u2], p3 = cur[u3];
             asm volatile("" ::"v"(p0.x), "v"(p1.x), "v"(p2.x), "v"(p3.x));
             if (e < deg) batch_attract<P>(xv.x, xv.y, p0, dpar, acc);
@@ -1000,12 +1015,12 @@ static void launch_batch_kernel(int precision, int grid, size_t lds, hipStream_t
 
 static void set_lds_attr(size_t lds) {
     if (lds <= 48 * 1024) return;
-    (void)hipFuncSetAttribute((const void*)batch_layout_kernel_f64,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    (void)hipFuncSetAttribute((const void*)batch_layout_kernel<GILA_FP32>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    (void)hipFuncSetAttribute((const void*)batch_layout_kernel<GILA_FP32_KAHAN>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    (void)quiet(hipFuncSetAttribute((const void*)batch_layout_kernel_f64,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    (void)quiet(hipFuncSetAttribute((const void*)batch_layout_kernel<GILA_FP32>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    (void)quiet(hipFuncSetAttribute((const void*)batch_layout_kernel<GILA_FP32_KAHAN>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
 }
 
 static int batch_grid(const gila_batch* b, size_t lds) {
@@ -1124,15 +1139,15 @@ static int tune_plan(gila_batch* b, int precision, hipStream_t s, int32_t* table
             const int grid = (int)std::min<int64_t>(std::min<int64_t>(a.count, device_info(b->device).cus),
                                                     b->escratch_grid);
             hipLaunchKernelGGL(reset_work_kernel, dim3(1), dim3(1), 0, s, b->d_work);
-            (void)hipEventRecord(e0, s);
+            (void)quiet(hipEventRecord(e0, s));
             launch_batch_kernel(precision, grid, lds, s, a);
-            (void)hipEventRecord(e1, s);
+            (void)quiet(hipEventRecord(e1, s));
             if (hipStreamSynchronize(s) != hipSuccess) {
                 rc = fail(GILA_EDEVICE, "tuner run failed");
                 break;
             }
             float ms = 0.f;
-            (void)hipEventElapsedTime(&ms, e0, e1);
+            (void)quiet(hipEventElapsedTime(&ms, e0, e1));
             if (ms < best_ms) {
                 best_ms = ms;
                 best = lpv;
@@ -1148,15 +1163,15 @@ static int tune_plan(gila_batch* b, int precision, hipStream_t s, int32_t* table
         for (int32_t i = 0; i < b->count; ++i)
             if (b->cls[i] == c) b->lpv[i] = std::max(best, fill_lanes(b->n[i]));
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    (void)quiet(hipEventDestroy(e0));
+    (void)quiet(hipEventDestroy(e1));
     return rc;
 }
 
 void free_batch(gila_batch* b, Release rel) {
     if (!b) return;
     DeviceGuard g(b->device);
-    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->gexec) (void)quiet(hipGraphExecDestroy(b->gexec));
     rel(b->kstart);
     rel(b->klen);
     rel(b->kidx);
@@ -1548,7 +1563,7 @@ int batch_run(gila_batch* b, const gila_params* params, void* const* pos, hipStr
         GILA_TRY(dalloc_t(&b->d_temps, temps.size()));
         b->temps_cap = (int64_t)temps.size();
         if (b->gexec) {
-            (void)hipGraphExecDestroy(b->gexec);
+            (void)quiet(hipGraphExecDestroy(b->gexec));
             b->gexec = nullptr;
         }
     }
@@ -1586,7 +1601,7 @@ int batch_run(gila_batch* b, const gila_params* params, void* const* pos, hipStr
         GILA_HIP(hipGetLastError());
     } else if (!b->gexec || key != b->gkey) {
         if (b->gexec) {
-            (void)hipGraphExecDestroy(b->gexec);
+            (void)quiet(hipGraphExecDestroy(b->gexec));
             b->gexec = nullptr;
         }
         hipStream_t cs = capture_stream(b->device);
@@ -1599,12 +1614,12 @@ int batch_run(gila_batch* b, const gila_params* params, void* const* pos, hipStr
         const hipError_t le = hipGetLastError();
         const hipError_t ee = hipStreamEndCapture(cs, &graph);
         if (le != hipSuccess || ee != hipSuccess) {
-            if (graph) (void)hipGraphDestroy(graph);
+            if (graph) (void)quiet(hipGraphDestroy(graph));
             return fail(GILA_EDEVICE, "batch graph capture: %s",
                         hipGetErrorString(le != hipSuccess ? le : ee));
         }
         const hipError_t ie = hipGraphInstantiate(&b->gexec, graph, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(graph);
+        (void)quiet(hipGraphDestroy(graph));
         if (ie != hipSuccess) {
             b->gexec = nullptr;
             return fail(GILA_EDEVICE, "batch graph instantiate: %s", hipGetErrorString(ie));

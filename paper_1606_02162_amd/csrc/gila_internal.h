@@ -34,6 +34,15 @@ void clear_error();
             return gila_rc_;      \
     } while (0)
 
+// For a call whose failure is handled otherwise or harmless (teardown, cache
+// trims, a function attribute that the launch after it checks): HIP also
+// keeps a failure as the thread's last error, which the next launch check
+// would report as its own, so it is taken back here.
+inline hipError_t quiet(hipError_t e) {
+    if (e != hipSuccess) (void)hipGetLastError();
+    return e;
+}
+
 // Device allocation that maps failure to GILA_ENOMEM.
 int dalloc(void** p, size_t bytes);
 template <class T>

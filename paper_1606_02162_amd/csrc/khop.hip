@@ -451,8 +451,8 @@ int run_bfs(bool fill, int device, hipStream_t s, BfsArgs a) {
     const size_t shm = lds ? bm_bytes : 0;
     auto launch = [&](auto kernel, int threads) {
         if (shm > 65536)
-            (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      (int)shm);
+            (void)quiet(hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)shm));
         hipLaunchKernelGGL(kernel, dim3(grid), dim3(threads), shm, s, a);
     };
     if (bs == 512) {
@@ -479,9 +479,9 @@ int run_bfs(bool fill, int device, hipStream_t s, BfsArgs a) {
 void free_khop(gila_khop* kh, Release rel) {
     if (!kh) return;
     DeviceGuard g(kh->device);
-    if (kh->gexec) (void)hipGraphExecDestroy(kh->gexec);
-    if (kh->tick_exec) (void)hipGraphExecDestroy(kh->tick_exec);
-    if (kh->chunk_exec) (void)hipGraphExecDestroy(kh->chunk_exec);
+    if (kh->gexec) (void)quiet(hipGraphExecDestroy(kh->gexec));
+    if (kh->tick_exec) (void)quiet(hipGraphExecDestroy(kh->tick_exec));
+    if (kh->chunk_exec) (void)quiet(hipGraphExecDestroy(kh->chunk_exec));
     rel(kh->d_temps);
     rel(kh->perm);
     rel(kh->iperm);

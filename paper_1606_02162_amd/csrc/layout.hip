@@ -273,9 +273,9 @@ int enqueue_run(gila_khop* kh, const gila_params* p, int32_t start_h, int32_t en
 }
 
 void drop_graphs(gila_khop* kh) {
-    if (kh->gexec) (void)hipGraphExecDestroy(kh->gexec);
-    if (kh->tick_exec) (void)hipGraphExecDestroy(kh->tick_exec);
-    if (kh->chunk_exec) (void)hipGraphExecDestroy(kh->chunk_exec);
+    if (kh->gexec) (void)quiet(hipGraphExecDestroy(kh->gexec));
+    if (kh->tick_exec) (void)quiet(hipGraphExecDestroy(kh->tick_exec));
+    if (kh->chunk_exec) (void)quiet(hipGraphExecDestroy(kh->chunk_exec));
     kh->gexec = nullptr;
     kh->tick_exec = nullptr;
     kh->chunk_exec = nullptr;
@@ -327,7 +327,7 @@ int enqueue_tick(gila_khop* kh, const gila_params* p, int32_t h, int32_t count,
                                        (uint64_t)segment_ready_for(kh, p->precision),
                                        (uint64_t)(uintptr_t)kh->d_temps};
     if (!kh->tick_exec || key != kh->tick_key) {
-        if (kh->tick_exec) (void)hipGraphExecDestroy(kh->tick_exec);
+        if (kh->tick_exec) (void)quiet(hipGraphExecDestroy(kh->tick_exec));
         kh->tick_exec = nullptr;
         kh->tick_key.clear();
         hipStream_t cs = capture_stream(kh->device);
@@ -355,7 +355,7 @@ int enqueue_tick(gila_khop* kh, const gila_params* p, int32_t h, int32_t count,
         hipError_t ie = hipErrorUnknown;
         if (rc == GILA_OK && ee == hipSuccess && graph)
             ie = hipGraphInstantiate(&kh->tick_exec, graph, nullptr, nullptr, 0);
-        if (graph) (void)hipGraphDestroy(graph);
+        if (graph) (void)quiet(hipGraphDestroy(graph));
         if (ie != hipSuccess) {
             // a capture another thread's call invalidated, or one the runtime
             // refused: this tick runs eagerly (the same bits); the next tries again
@@ -471,7 +471,7 @@ static int enqueue_chunked_run(gila_khop* kh, const gila_params* p, int32_t star
     a.check_stop = p->stop_fraction > 0.0 ? 1 : 0;
     a.temps = kh->d_temps;
     if (!kh->chunk_exec || key != kh->chunk_key) {
-        if (kh->chunk_exec) (void)hipGraphExecDestroy(kh->chunk_exec);
+        if (kh->chunk_exec) (void)quiet(hipGraphExecDestroy(kh->chunk_exec));
         kh->chunk_exec = nullptr;
         kh->chunk_key.clear();
         hipStream_t cs = capture_stream(kh->device);
@@ -488,12 +488,12 @@ static int enqueue_chunked_run(gila_khop* kh, const gila_params* p, int32_t star
         hipGraph_t graph = nullptr;
         const hipError_t ee = hipStreamEndCapture(cs, &graph);
         if (rc != GILA_OK) {
-            if (graph) (void)hipGraphDestroy(graph);
+            if (graph) (void)quiet(hipGraphDestroy(graph));
             return rc;
         }
         if (ee != hipSuccess) return fail(GILA_EDEVICE, "chunk capture: %s", hipGetErrorString(ee));
         const hipError_t ie = hipGraphInstantiate(&kh->chunk_exec, graph, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(graph);
+        (void)quiet(hipGraphDestroy(graph));
         if (ie != hipSuccess) {
             kh->chunk_exec = nullptr;
             return fail(GILA_EDEVICE, "chunk instantiate: %s", hipGetErrorString(ie));
@@ -534,7 +534,7 @@ int run_iterations(gila_khop* kh, const gila_params* p, int32_t start_h, int32_t
         std::vector<uint64_t> key = graph_key(kh, p, start_h, end_h, pos_dev);
         if (!kh->gexec || key != kh->gkey) {
             if (kh->gexec) {
-                (void)hipGraphExecDestroy(kh->gexec);
+                (void)quiet(hipGraphExecDestroy(kh->gexec));
                 kh->gexec = nullptr;
             }
             hipStream_t cs = capture_stream(kh->device);
@@ -545,13 +545,13 @@ int run_iterations(gila_khop* kh, const gila_params* p, int32_t start_h, int32_t
             hipGraph_t graph = nullptr;
             const hipError_t ee = hipStreamEndCapture(cs, &graph);
             if (rc != GILA_OK) {
-                if (graph) (void)hipGraphDestroy(graph);
+                if (graph) (void)quiet(hipGraphDestroy(graph));
                 return rc;
             }
             if (ee != hipSuccess)
                 return fail(GILA_EDEVICE, "graph capture: %s", hipGetErrorString(ee));
             const hipError_t ie = hipGraphInstantiate(&kh->gexec, graph, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(graph);
+            (void)quiet(hipGraphDestroy(graph));
             if (ie != hipSuccess) {
                 kh->gexec = nullptr;
                 return fail(GILA_EDEVICE, "graph instantiate: %s", hipGetErrorString(ie));
@@ -735,7 +735,7 @@ int gila_time_iterations(const gila_khop* kh_c, const gila_params* params, int32
             const hipError_t ee = hipStreamEndCapture(cs, &graph);
             in_graph = erc == GILA_OK && ee == hipSuccess && graph &&
                        hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
-            if (graph) (void)hipGraphDestroy(graph);
+            if (graph) (void)quiet(hipGraphDestroy(graph));
             if (!in_graph && getenv("GILA_DEBUG"))
                 fprintf(stderr, "[gila] timing capture refused: %d (%s), end %s\n", erc,
                         gila_last_error(), hipGetErrorString(ee));
@@ -768,9 +768,9 @@ int gila_time_iterations(const gila_khop* kh_c, const gila_params* params, int32
     float t = 0.f;
     if (rc == GILA_OK && hipEventElapsedTime(&t, ev[0], ev[1]) != hipSuccess)
         rc = fail(GILA_EDEVICE, "hipEventElapsedTime failed");
-    if (exec) (void)hipGraphExecDestroy(exec);
+    if (exec) (void)quiet(hipGraphExecDestroy(exec));
     for (auto& e : ev)
-        if (e) (void)hipEventDestroy(e);
+        if (e) (void)quiet(hipEventDestroy(e));
     dfree_on(span, s);
     if (rc == GILA_OK) {
         const double iter = (double)t / reps;

@@ -1006,10 +1006,10 @@ int build_segments(gila_khop* kh, int precision, hipStream_t st) {
                              const int32_t* perm, int32_t* out) -> int {
         const size_t lds = sizeof(int32_t) * (size_t)nkeys;
         if (lds > 48 * 1024) {
-            (void)hipFuncSetAttribute((const void*)slice_hist_kernel,
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            (void)hipFuncSetAttribute((const void*)slice_scatter_kernel,
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            (void)quiet(hipFuncSetAttribute((const void*)slice_hist_kernel,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+            (void)quiet(hipFuncSetAttribute((const void*)slice_scatter_kernel,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         }
         hipLaunchKernelGGL(slice_hist_kernel, dim3((unsigned)ntiles), dim3(kBlock), lds, st, T, tj,
                            ntiles, nkeys, key, perm, hist);
@@ -1120,7 +1120,7 @@ int build_segments(gila_khop* kh, int precision, hipStream_t st) {
 #undef GILA_SEG_KERNELS
         };
         for (const void* k : kernels)
-            (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            (void)quiet(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     }
     GILA_HIP(hipStreamSynchronize(st));
     pt.mark("fill+plan");

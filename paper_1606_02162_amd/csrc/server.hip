@@ -312,7 +312,7 @@ static int admit_large(gila_server* s, Job* j) {
 // allow; small jobs go to the small-job worker, large ones are built here and
 // handed to the ticker.
 static void admitter(gila_server* s) {
-    (void)hipSetDevice(s->device);
+    (void)quiet(hipSetDevice(s->device));
     for (;;) {
         std::vector<Job*> fresh;
         {
@@ -372,7 +372,7 @@ static void admitter(gila_server* s) {
 // Builder: graph upload and k-hop lists of admitted large jobs, one at a time
 // in admission order, then the job joins the ticker's resident set.
 static void builder(gila_server* s) {
-    (void)hipSetDevice(s->device);
+    (void)quiet(hipSetDevice(s->device));
     for (;;) {
         Job* j = nullptr;
         {
@@ -400,7 +400,7 @@ static void builder(gila_server* s) {
 // precision); jobs admitted while it runs go to the other worker, so they do
 // not wait for that group to finish.
 static void small_worker(gila_server* s, int w) {
-    (void)hipSetDevice(s->device);
+    (void)quiet(hipSetDevice(s->device));
     for (;;) {
         std::vector<Job*> take;
         {
@@ -423,7 +423,7 @@ static void small_worker(gila_server* s, int w) {
 // stream it shares).  Final positions are copied on a stream of their own, so
 // they do not queue behind other jobs' ticks.
 static void ticker(gila_server* s) {
-    (void)hipSetDevice(s->device);
+    (void)quiet(hipSetDevice(s->device));
     std::vector<Job*> mine;  // resident jobs, owned by this thread
     for (;;) {
         int32_t tick_iters = 1;
@@ -453,8 +453,11 @@ static void ticker(gila_server* s) {
             bool finished = false;
             if (j->in_tick) {
                 const hipError_t q = hipEventQuery(s->slot_ev[j->slot]);
-                if (q == hipErrorNotReady) {
-                    (void)hipGetLastError();  // pending work, not an error
+                // pending work, or a query refused while another thread
+                // captures a stream: not an error, asked again next round
+                if (q == hipErrorNotReady || q == hipErrorStreamCaptureUnsupported ||
+                    q == hipErrorStreamCaptureImplicit) {
+                    (void)hipGetLastError();
                     keep.push_back(j);
                     continue;
                 }
@@ -499,7 +502,7 @@ static void ticker(gila_server* s) {
                     continue;
                 }
                 // a job whose tick could not be queued waits for what it queued
-                (void)hipStreamSynchronize(st);
+                (void)quiet(hipStreamSynchronize(st));
             }
             release_device(j, s->compute[j->lane]);
             std::lock_guard<std::mutex> lk(s->mu);
@@ -568,14 +571,14 @@ int gila_server_create(int32_t device, int64_t hbm_budget_bytes, int32_t max_slo
         ok = hipStreamCreateWithFlags(&s->compute[c], hipStreamNonBlocking) == hipSuccess;
     if (!ok) {
         for (int c = 0; c < gila_server::kComputeStreams; ++c)
-            if (s->compute[c]) (void)hipStreamDestroy(s->compute[c]);
-        if (s->build) (void)hipStreamDestroy(s->build);
+            if (s->compute[c]) (void)quiet(hipStreamDestroy(s->compute[c]));
+        if (s->build) (void)quiet(hipStreamDestroy(s->build));
         for (auto& q : s->small)
-            if (q) (void)hipStreamDestroy(q);
-        if (s->download) (void)hipStreamDestroy(s->download);
+            if (q) (void)quiet(hipStreamDestroy(q));
+        if (s->download) (void)quiet(hipStreamDestroy(s->download));
         for (auto& e : s->slot_ev)
-            if (e) (void)hipEventDestroy(e);
-        (void)hipHostFree(s->host_ctl);
+            if (e) (void)quiet(hipEventDestroy(e));
+        (void)quiet(hipHostFree(s->host_ctl));
         delete s;
         return fail(GILA_EDEVICE, "cannot create streams or events");
     }
@@ -746,19 +749,19 @@ void gila_server_destroy(gila_server* s) {
     if (s->th_build.joinable()) s->th_build.join();
     if (s->th_tick.joinable()) s->th_tick.join();
     DeviceGuard dg(s->device);
-    for (int c = 0; c < gila_server::kComputeStreams; ++c) (void)hipStreamSynchronize(s->compute[c]);
-    (void)hipStreamSynchronize(s->build);
-    for (auto& q : s->small) (void)hipStreamSynchronize(q);
-    (void)hipStreamSynchronize(s->download);
+    for (int c = 0; c < gila_server::kComputeStreams; ++c) (void)quiet(hipStreamSynchronize(s->compute[c]));
+    (void)quiet(hipStreamSynchronize(s->build));
+    for (auto& q : s->small) (void)quiet(hipStreamSynchronize(q));
+    (void)quiet(hipStreamSynchronize(s->download));
     for (Job* j : s->resident) release_device(j, s->build);
     for (Job* j : s->ready) release_device(j, s->build);
     for (auto& kv : s->jobs) delete kv.second;
-    for (int c = 0; c < gila_server::kComputeStreams; ++c) (void)hipStreamDestroy(s->compute[c]);
-    (void)hipStreamDestroy(s->build);
-    for (auto& q : s->small) (void)hipStreamDestroy(q);
-    (void)hipStreamDestroy(s->download);
-    for (auto& e : s->slot_ev) (void)hipEventDestroy(e);
-    (void)hipHostFree(s->host_ctl);
+    for (int c = 0; c < gila_server::kComputeStreams; ++c) (void)quiet(hipStreamDestroy(s->compute[c]));
+    (void)quiet(hipStreamDestroy(s->build));
+    for (auto& q : s->small) (void)quiet(hipStreamDestroy(q));
+    (void)quiet(hipStreamDestroy(s->download));
+    for (auto& e : s->slot_ev) (void)quiet(hipEventDestroy(e));
+    (void)quiet(hipHostFree(s->host_ctl));
     delete s;
 }
 

@@ -116,7 +116,7 @@ void PhaseTimer::mark(const char* phase) {
     snprintf(name, sizeof(name), "%s: %s done", what, phase);
     roctxMarkA(name);
     if (!on) return;
-    (void)hipStreamSynchronize(stream);
+    (void)quiet(hipStreamSynchronize(stream));
     const double t = wall_s();
     char buf[128];
     snprintf(buf, sizeof(buf), " %s=%.2f", phase, (t - last) * 1e3);
@@ -177,14 +177,13 @@ size_t size_class(size_t b) {
     return r;
 }
 
-// hipEventQuery reports pending work as hipErrorNotReady, which HIP also keeps
+// hipEventQuery reports pending work as hipErrorNotReady (and may refuse the
+// query, e.g. while another thread captures a stream), which HIP also keeps
 // as the thread's last error: it is taken back here, so that the next launch
-// check does not report it.
+// check does not report it; a block whose event cannot be queried waits.
 bool block_ready(const CachedBlock& c) {
     if (!c.ev) return true;
-    const hipError_t q = hipEventQuery(c.ev);
-    if (q == hipErrorNotReady) (void)hipGetLastError();
-    return q == hipSuccess;
+    return quiet(hipEventQuery(c.ev)) == hipSuccess;
 }
 
 // Returns ready cached blocks to the device until at most `keep` bytes stay
@@ -198,8 +197,8 @@ void trim_locked(size_t keep) {
         if (g_cached_bytes <= keep) break;
         if (!block_ready(it->second)) continue;
         DeviceGuard dg(it->first.first);
-        if (it->second.ev) (void)hipEventDestroy(it->second.ev);
-        (void)hipFree(it->second.p);
+        if (quiet(hipFree(it->second.p)) != hipSuccess) continue;  // kept for a later trim
+        if (it->second.ev) (void)quiet(hipEventDestroy(it->second.ev));
         g_cached_bytes -= it->second.bytes;
         g_cache.erase(it);
     }
@@ -217,7 +216,7 @@ int dalloc(void** p, size_t bytes) {
         for (auto it = range.first; it != range.second; ++it) {
             if (!block_ready(it->second)) continue;
             *p = it->second.p;
-            if (it->second.ev) (void)hipEventDestroy(it->second.ev);
+            if (it->second.ev) (void)quiet(hipEventDestroy(it->second.ev));
             g_cached_bytes -= rb;
             g_cache.erase(it);
             g_live[*p] = LiveBlock{dev, rb};
@@ -250,7 +249,7 @@ void dfree(void* p) {
         std::lock_guard<std::mutex> lk(g_mem_mu);
         g_live.erase(p);
     }
-    (void)hipFree(p);
+    (void)quiet(hipFree(p));
 }
 
 void dfree_on(void* p, hipStream_t s, bool idle) {
@@ -258,7 +257,7 @@ void dfree_on(void* p, hipStream_t s, bool idle) {
     std::lock_guard<std::mutex> lk(g_mem_mu);
     auto it = g_live.find(p);
     if (it == g_live.end()) {  // not from dalloc: plain free
-        (void)hipFree(p);
+        (void)quiet(hipFree(p));
         return;
     }
     CachedBlock c{p, it->second.bytes, nullptr, ++g_seq};
@@ -266,9 +265,9 @@ void dfree_on(void* p, hipStream_t s, bool idle) {
         if (hipEventCreateWithFlags(&c.ev, hipEventDisableTiming) != hipSuccess ||
             hipEventRecord(c.ev, s) != hipSuccess) {
             // cannot mark the stream: wait for it instead
-            if (c.ev) (void)hipEventDestroy(c.ev);
+            if (c.ev) (void)quiet(hipEventDestroy(c.ev));
             c.ev = nullptr;
-            (void)hipStreamSynchronize(s);
+            (void)quiet(hipStreamSynchronize(s));
         }
     }
     g_cache.insert({{it->second.device, c.bytes}, c});
@@ -298,7 +297,7 @@ DeviceGuard::DeviceGuard(int dev) {
 }
 
 DeviceGuard::~DeviceGuard() {
-    if (prev >= 0) (void)hipSetDevice(prev);
+    if (prev >= 0) (void)quiet(hipSetDevice(prev));
 }
 
 static std::mutex g_mu;
@@ -309,7 +308,7 @@ static std::map<int, DeviceInfo> g_info;
 struct CaptureStreams {
     std::map<int, hipStream_t> by_device;
     ~CaptureStreams() {
-        for (auto& kv : by_device) (void)hipStreamDestroy(kv.second);
+        for (auto& kv : by_device) (void)quiet(hipStreamDestroy(kv.second));
     }
 };
 static thread_local CaptureStreams t_capture;
