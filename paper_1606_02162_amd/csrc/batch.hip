@@ -713,6 +713,19 @@ __device__ __forceinline__ void batch_graph_iteration_slices(
         S.aoff = hp->aoff;
         S.nq = hp->nq;
         S.na = hp->na;
+        // groups of four quad steps, the next group's loads issued before
+        // this group's terms (rows stream from HBM: a wait per group would
+        // leave each slice waiting on its row length over four latencies).
+        // The first group is issued before the lane records, whose wait
+        // then overlaps it.
+        const uint2* __restrict__ q = a.sk + S.koff + lane;
+        uint2 n0 = make_uint2(0, 0), n1 = n0, n2 = n0, n3 = n0;
+        if (S.nq >= 4) {
+            n0 = q[0];
+            n1 = q[64];
+            n2 = q[128];
+            n3 = q[192];
+        }
         const uint2 m = a.smeta[si * 64 + lane];
         // the first four adjacency entries, loaded now so that they arrive
         // during the row's terms
@@ -724,18 +737,7 @@ __device__ __forceinline__ void batch_graph_iteration_slices(
         const V xv = cur[v];
         Acc<R, P::kahan> acc;
         R mindd = R(1);
-        const uint2* __restrict__ q = a.sk + S.koff + lane;
         int j = 0;
-        // groups of four quad steps, the next group's loads issued before
-        // this group's terms (rows stream from HBM: a wait per group would
-        // leave each slice waiting on its row length over four latencies)
-        uint2 n0 = make_uint2(0, 0), n1 = n0, n2 = n0, n3 = n0;
-        if (S.nq >= 4) {
-            n0 = q[0];
-            n1 = q[64];
-            n2 = q[128];
-            n3 = q[192];
-        }
         for (; j + 3 < S.nq; j += 4) {
             const uint2 w0 = n0, w1 = n1, w2 = n2, w3 = n3;
             if (j + 7 < S.nq) {  // uniform
