@@ -439,6 +439,11 @@ __global__ __launch_bounds__(kBlock) void pad_rows_kernel(const int64_t* __restr
 // more than kOrderMax vertices keep the identity order (their slices are then
 // less even, the results are the same).
 constexpr int kOrderMax = 8192;
+// Graphs of fewer than kOffsetLimit vertices store their wave slices' rows
+// as 16-bit offsets of 8-byte slots (id x 8; the sentinel's n x 8 <= 65528):
+// the byte offset of an FP32 position, so its address is one add of a 16-bit
+// half; larger graphs keep ids.
+constexpr int kOffsetLimit = 8192;
 
 __global__ __launch_bounds__(kBlock) void row_order_kernel(const int64_t* __restrict__ vbase,
                                                            const int32_t* __restrict__ klen,
@@ -531,7 +536,12 @@ __global__ __launch_bounds__(kBlock) void sell_fill_kernel(
     // a lane past the graph's end (v = n) reads no row
     const uint2* row = reinterpret_cast<const uint2*>(kidx + (v < (int)n ? kstart[vb + v] : 0));
     const uint2 sent = make_uint2(n | (n << 16), n | (n << 16));
-    for (int j = 0; j < Q; ++j) sk[ko + (int64_t)j * 64 + lane] = j < nq ? row[j] : sent;
+    // both halves below 8192, so one shift scales both
+    const int sh = n < (uint32_t)kOffsetLimit ? 3 : 0;
+    for (int j = 0; j < Q; ++j) {
+        const uint2 w = j < nq ? row[j] : sent;
+        sk[ko + (int64_t)j * 64 + lane] = make_uint2(w.x << sh, w.y << sh);
+    }
     const uint16_t* arow = ci16 + rp[vb + v];
     // adjacency in groups of four entries per lane (8 contiguous bytes, one
     // load), group g of lane l at entries 256 g + 4 l
@@ -687,7 +697,7 @@ __device__ __forceinline__ void batch_graph_iteration(
 // the slice; a lane adds a step's terms only within its own row, in the same
 // grouping as the row layout (pairs of quads, a last odd quad alone), and its
 // adjacency terms only within its degree, so each vertex gets the same bits.
-template <class P>
+template <class P, bool OFF>
 __device__ __forceinline__ void batch_graph_iteration_slices(
     const BatchArgs& a, const BatchDesc& G, const typename P::vec2* __restrict__ cur,
     typename P::vec2* __restrict__ nxt, double t, int* s_next, double* e_slice, double& maxd,
@@ -697,6 +707,15 @@ __device__ __forceinline__ void batch_graph_iteration_slices(
     const double d2 = G.d * G.d;
     const R dpar = sizeof(R) == 4 ? (R)(1.0 / (G.d * d2)) : (R)(G.d * d2);
     const int lane = lane64();
+    // a row entry's position: entries are ids, or (OFF) offsets of 8-byte
+    // slots -- byte offsets of FP32 positions, half those of FP64 ones
+    const auto at = [cur](uint32_t h) -> V {
+        if constexpr (OFF)
+            return *reinterpret_cast<const V*>(reinterpret_cast<const char*>(cur) +
+                                               h * (uint32_t)(sizeof(V) / 8));
+        else
+            return cur[h];
+    };
     const int ns = (G.n + 63) >> 6;
     for (;;) {
         int sl = 0;
@@ -747,26 +766,26 @@ __device__ __forceinline__ void batch_graph_iteration_slices(
                 n3 = q[(int64_t)(j + 7) * 64];
             }
             R ax, ay, bx, by;
-            repulse4<P>(cur[w0.x & 0xFFFFu], cur[w0.x >> 16], cur[w0.y & 0xFFFFu],
-                        cur[w0.y >> 16], xv.x, xv.y, ax, ay, mindd);
-            repulse4<P>(cur[w1.x & 0xFFFFu], cur[w1.x >> 16], cur[w1.y & 0xFFFFu],
-                        cur[w1.y >> 16], xv.x, xv.y, bx, by, mindd);
+            repulse4<P>(at(w0.x & 0xFFFFu), at(w0.x >> 16), at(w0.y & 0xFFFFu),
+                        at(w0.y >> 16), xv.x, xv.y, ax, ay, mindd);
+            repulse4<P>(at(w1.x & 0xFFFFu), at(w1.x >> 16), at(w1.y & 0xFFFFu),
+                        at(w1.y >> 16), xv.x, xv.y, bx, by, mindd);
             if (j + 1 < nq) acc.add(ax + bx, ay + by);
             else if (j < nq) acc.add(ax, ay);
-            repulse4<P>(cur[w2.x & 0xFFFFu], cur[w2.x >> 16], cur[w2.y & 0xFFFFu],
-                        cur[w2.y >> 16], xv.x, xv.y, ax, ay, mindd);
-            repulse4<P>(cur[w3.x & 0xFFFFu], cur[w3.x >> 16], cur[w3.y & 0xFFFFu],
-                        cur[w3.y >> 16], xv.x, xv.y, bx, by, mindd);
+            repulse4<P>(at(w2.x & 0xFFFFu), at(w2.x >> 16), at(w2.y & 0xFFFFu),
+                        at(w2.y >> 16), xv.x, xv.y, ax, ay, mindd);
+            repulse4<P>(at(w3.x & 0xFFFFu), at(w3.x >> 16), at(w3.y & 0xFFFFu),
+                        at(w3.y >> 16), xv.x, xv.y, bx, by, mindd);
             if (j + 3 < nq) acc.add(ax + bx, ay + by);
             else if (j + 2 < nq) acc.add(ax, ay);
         }
         for (; j < S.nq; j += 2) {  // S.nq is even
             const uint2 w0 = q[(int64_t)j * 64], w1 = q[(int64_t)(j + 1) * 64];
             R ax, ay, bx, by;
-            repulse4<P>(cur[w0.x & 0xFFFFu], cur[w0.x >> 16], cur[w0.y & 0xFFFFu],
-                        cur[w0.y >> 16], xv.x, xv.y, ax, ay, mindd);
-            repulse4<P>(cur[w1.x & 0xFFFFu], cur[w1.x >> 16], cur[w1.y & 0xFFFFu],
-                        cur[w1.y >> 16], xv.x, xv.y, bx, by, mindd);
+            repulse4<P>(at(w0.x & 0xFFFFu), at(w0.x >> 16), at(w0.y & 0xFFFFu),
+                        at(w0.y >> 16), xv.x, xv.y, ax, ay, mindd);
+            repulse4<P>(at(w1.x & 0xFFFFu), at(w1.x >> 16), at(w1.y & 0xFFFFu),
+                        at(w1.y >> 16), xv.x, xv.y, bx, by, mindd);
             if (j + 1 < nq) acc.add(ax + bx, ay + by);
             else if (j < nq) acc.add(ax, ay);
         }
@@ -865,8 +884,12 @@ __device__ __forceinline__ void batch_layout_body(const BatchArgs& a) {
             if (threadIdx.x == 0) s_sl[(h + 1) & 1] = 0;
             switch (G.lpv) {
                 case 1:
-                    batch_graph_iteration_slices<P>(a, G, cur, nxt, t, &s_sl[h & 1],
-                                                    e_sl + (h & 1) * ns, maxd, moved, coinc);
+                    if (G.n < kOffsetLimit)
+                        batch_graph_iteration_slices<P, true>(a, G, cur, nxt, t, &s_sl[h & 1],
+                                                              e_sl + (h & 1) * ns, maxd, moved, coinc);
+                    else
+                        batch_graph_iteration_slices<P, false>(a, G, cur, nxt, t, &s_sl[h & 1],
+                                                               e_sl + (h & 1) * ns, maxd, moved, coinc);
                     break;
                 case 2: batch_graph_iteration<P, 2>(a, G, cur, nxt, t, energy, maxd, moved, coinc); break;
                 case 4: batch_graph_iteration<P, 4>(a, G, cur, nxt, t, energy, maxd, moved, coinc); break;
