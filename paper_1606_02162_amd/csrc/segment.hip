@@ -549,12 +549,23 @@ __device__ __forceinline__ void seg_slices(const SegArgs& a, int ib, int ie,
             // pairs in flight exceed the 128 VGPRs of four waves per SIMD.
             constexpr bool kFourQuads = !(sizeof(R) == 8 && Q < 0);
             int q = gl;
+            // the next step's four quads are loaded before this step's terms
+            uint2 n0 = make_uint2(0, 0), n1 = n0, n2 = n0, n3 = n0;
+            if (kFourQuads && q + 3 * LPV < nq) {
+                n0 = q4[q];
+                n1 = q4[q + LPV];
+                n2 = q4[q + 2 * LPV];
+                n3 = q4[q + 3 * LPV];
+            }
             if constexpr (kFourQuads)
             for (; q + 3 * LPV < nq; q += 4 * LPV) {
-                const uint2 w0 = q4[q];
-                const uint2 w1 = q4[q + LPV];
-                const uint2 w2 = q4[q + 2 * LPV];
-                const uint2 w3 = q4[q + 3 * LPV];
+                const uint2 w0 = n0, w1 = n1, w2 = n2, w3 = n3;
+                if (q + 7 * LPV < nq) {
+                    n0 = q4[q + 4 * LPV];
+                    n1 = q4[q + 5 * LPV];
+                    n2 = q4[q + 6 * LPV];
+                    n3 = q4[q + 7 * LPV];
+                }
                 R ax, ay, bx, by;
                 quad_terms<P, WEIGHTED, Q>(w0, lds, lw, xv.x, xv.y, ax, ay, mindd, a.rep_q);
                 quad_terms<P, WEIGHTED, Q>(w1, lds, lw, xv.x, xv.y, bx, by, mindd, a.rep_q);
